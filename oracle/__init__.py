@@ -1,0 +1,108 @@
+"""CPU oracle for grayscale reconstruction by dilation and fill-holes.
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by ``__graft_entry__.smoke()``
+and by the ``cpu_baseline`` leg of ``bench.py``.  The product library never
+imports, links or runs anything in this directory.
+
+The arithmetic lives in ``recon_oracle.c`` (plain C, built with gcc); this
+module only compiles it and marshals numpy arrays through ctypes.  See that
+file's header for the definition followed (the reconstruction the paper's
+Table 1 operations are built on, Sec. V-A) and for the sequential algorithm.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "recon_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the C oracle into ``oracle/liboracle.so`` with gcc."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.run(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-o", tmp, _SRC],
+                       check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB)
+        u8p = ctypes.c_void_p
+        i64 = ctypes.c_int64
+        lib.oracle_recon_dilate.argtypes = [u8p, u8p, u8p, i64, i64, ctypes.c_int]
+        lib.oracle_recon_dilate.restype = ctypes.c_int
+        lib.oracle_fill_holes.argtypes = [u8p, u8p, i64, i64, ctypes.c_int]
+        lib.oracle_fill_holes.restype = ctypes.c_int
+        lib.oracle_recon_dilate_many.argtypes = [u8p, u8p, u8p, i64, i64, i64, ctypes.c_int]
+        lib.oracle_recon_dilate_many.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _u8(a) -> np.ndarray:
+    a = np.ascontiguousarray(a)
+    if a.dtype != np.uint8:
+        raise TypeError("oracle images are uint8, got %s" % a.dtype)
+    return a
+
+
+def recon_dilate(marker, mask, conn: int = 8) -> np.ndarray:
+    """rho_mask(marker): reconstruction by dilation (marker clipped under mask)."""
+    marker, mask = _u8(marker), _u8(mask)
+    if marker.shape != mask.shape or marker.ndim != 2:
+        raise ValueError("marker and mask must be 2-D arrays of one shape")
+    out = np.empty_like(marker)
+    h, w = marker.shape
+    rc = _load().oracle_recon_dilate(marker.ctypes.data, mask.ctypes.data, out.ctypes.data,
+                                     h, w, int(conn))
+    if rc != 0:
+        raise ValueError("oracle_recon_dilate failed with %d" % rc)
+    return out
+
+
+def fill_holes(img, conn: int = 8) -> np.ndarray:
+    """255 - rho_{255-img}(frame marker): fill-holes as reconstruction of the complement."""
+    img = _u8(img)
+    if img.ndim != 2:
+        raise ValueError("image must be 2-D")
+    out = np.empty_like(img)
+    h, w = img.shape
+    rc = _load().oracle_fill_holes(img.ctypes.data, out.ctypes.data, h, w, int(conn))
+    if rc != 0:
+        raise ValueError("oracle_fill_holes failed with %d" % rc)
+    return out
+
+
+def recon_dilate_many(markers, masks, conn: int = 8) -> np.ndarray:
+    """Reconstruction of a stack (n, h, w) of same-shaped images."""
+    markers, masks = _u8(markers), _u8(masks)
+    if markers.shape != masks.shape or markers.ndim != 3:
+        raise ValueError("expected two (n, h, w) stacks of one shape")
+    out = np.empty_like(markers)
+    n, h, w = markers.shape
+    rc = _load().oracle_recon_dilate_many(markers.ctypes.data, masks.ctypes.data,
+                                          out.ctypes.data, n, h, w, int(conn))
+    if rc != 0:
+        raise ValueError("oracle_recon_dilate_many failed with %d" % rc)
+    return out
+
+
+def run_task(task) -> np.ndarray:
+    """Oracle result of one task dict {op, marker/img, mask, conn} (host arrays)."""
+    if task["op"] == "dilate":
+        return recon_dilate(task["marker"], task["mask"], task["conn"])
+    if task["op"] == "fill_holes":
+        return fill_holes(task["img"], task["conn"])
+    raise ValueError("unknown op %r" % (task["op"],))
