@@ -1,0 +1,150 @@
+/*
+ * recon.h -- C ABI of librecon: grayscale morphological reconstruction by
+ * dilation and fill-holes on uint8 image tiles, for AMD Instinct MI355X
+ * (gfx950).
+ *
+ * What is computed
+ * ----------------
+ * Morphological reconstruction (MR) is the operation the paper's nucleus
+ * segmentation stage is built on: Table 1 ("Sources of CPU and GPU
+ * implementations of operations in the segmentation and feature computation
+ * stages", Sec. V-A) lists ReconToNuclei, FillHoles, Pre-Watershed and RBC
+ * detection as MR-based, and the paragraph that follows it describes MR as
+ * an irregular wave-propagation computation.  The reconstruction of a mask I
+ * from a marker J is the fixed point of J <- min(dilate(J), I) started from
+ * min(J, I), where dilate is the flat dilation over the 4- or 8-neighbourhood
+ * (pixels outside the image do not exist).  The result is unique, so every
+ * entry point below returns identical bytes for every tuning, batch
+ * composition and arrival order.
+ *
+ * Fill-holes (the FillHoles operation of Table 1) is the reconstruction of the
+ * complement: F = 255 - rho_{255-X}(m), with m = 255 - X on the one-pixel
+ * image frame and 0 elsewhere; `conn` is the connectivity of that
+ * reconstruction, i.e. of the background.
+ *
+ * Conventions
+ * -----------
+ * * Images are single-channel uint8, row-major, `pitch` bytes between rows
+ *   (pitch >= width).  `data` is a DEVICE pointer on the context's GPU.  The
+ *   caller owns every image buffer; the library never allocates or frees
+ *   them, and they must stay valid until the work on `stream` (or the
+ *   ticket) has completed.
+ * * Results are written in place: into the marker (recon_dilate) or the image
+ *   (recon_fill_holes).  The marker and the mask must not overlap.
+ * * `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *   device work is enqueued asynchronously on it; the call returns once the
+ *   work is enqueued.
+ * * Return values are recon_status codes; no exception crosses the ABI.
+ *   Argument errors are detected synchronously, before anything is enqueued.
+ *   Device errors are reported by the call that observes them (the next call,
+ *   recon_poll or recon_wait).  recon_last_error() gives the message of the
+ *   last failure on the calling thread.
+ * * A context may be used from one host thread at a time, and its calls are
+ *   ordered on the streams they name; calls on different streams that
+ *   overlap in time share the context's workspace and must not be issued
+ *   concurrently.
+ */
+#ifndef RECON_H
+#define RECON_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RECON_OK = 0,
+    RECON_EINVAL = -1,     /* bad argument (null pointer, conn, shape, pitch, overlap) */
+    RECON_ENOMEM = -2,     /* device or host allocation failed */
+    RECON_EDEVICE = -3,    /* HIP runtime or kernel error */
+    RECON_EAGAIN = -4,     /* serving admission full: retry after polling */
+    RECON_ETIMEDOUT = -5   /* recon_wait timed out; the work is still in flight */
+} recon_status;
+
+enum { RECON_OP_DILATE = 0, RECON_OP_FILL_HOLES = 1 };
+
+typedef struct recon_ctx recon_ctx;
+
+/* One uint8 image: device pointer, shape, and row pitch in bytes. */
+typedef struct {
+    uint8_t *data;
+    int32_t height;
+    int32_t width;
+    int64_t pitch;
+} recon_image;
+
+/* One unit of work for recon_batch / recon_submit.
+ * op == RECON_OP_DILATE:     image = marker (in: J, out: rho_mask(J)), mask = I.
+ * op == RECON_OP_FILL_HOLES: image = X (in: X, out: filled), mask ignored. */
+typedef struct {
+    int32_t op;
+    int32_t conn;          /* 4 or 8 */
+    recon_image image;
+    recon_image mask;
+} recon_task;
+
+/* Tuning and capacity knobs; zero fields take the defaults. */
+typedef struct {
+    int32_t block_rows;        /* rows per work block: 16, 32 or 64 (default: tuned) */
+    int32_t queue_capacity;    /* LDS queue entries per workgroup, 64..8192 */
+    int32_t scan_rounds;       /* directional pass rounds on a block's first visit,
+                                  1..8; 0 = default (2); -1 = none */
+    int32_t wg_per_cu;         /* cap on resident workgroups per CU (0 = occupancy limit) */
+    int64_t serve_mem_cap;     /* serving admission cap in device bytes (default 64 GiB) */
+    int32_t serve_slots;       /* serving in-flight task slots (default 256) */
+    int32_t reserved[5];
+} recon_config;
+
+/* Per-call statistics of the last completed launch (for tests and tuning). */
+typedef struct {
+    int64_t dense_visits;      /* first visits of work blocks */
+    int64_t revisits;          /* later visits triggered by neighbour changes */
+    int64_t reruns;            /* in-place re-runs of a block re-requested while running */
+    int64_t queue_overflows;   /* LDS queue overflows (each followed by a re-seed) */
+    int64_t spills;            /* queue entries spilled to the global overflow area */
+    int64_t aborted;           /* 1 if the scheduler watchdog stopped the launch */
+} recon_stats;
+
+/* Create a context on HIP device `device`.  cfg may be NULL. */
+int recon_create(recon_ctx **out, int device, const recon_config *cfg);
+/* Destroy a context after all its work has completed. */
+int recon_destroy(recon_ctx *ctx);
+
+/* Reconstruction by dilation of `mask` from `marker`, in place on marker.
+ * Shapes must match; conn is 4 or 8.  Enqueued on `stream`. */
+int recon_dilate(recon_ctx *ctx, recon_image *marker, const recon_image *mask, int conn,
+                 void *stream);
+
+/* Fill-holes of `img`, in place.  conn (4 or 8) is the background
+ * connectivity.  Enqueued on `stream`. */
+int recon_fill_holes(recon_ctx *ctx, recon_image *img, int conn, void *stream);
+
+/* Run n tasks (any mix of ops, shapes and connectivities) in one persistent
+ * launch sequence, replayed from a HIP graph.  Enqueued on `stream`. */
+int recon_batch(recon_ctx *ctx, const recon_task *tasks, int32_t n, void *stream);
+
+/* Serving: admit one task into the resident request loop.  On success
+ * *ticket identifies it.  Returns RECON_EAGAIN when the admission cap (device
+ * bytes or slots) is reached; poll earlier tickets and retry. */
+int recon_submit(recon_ctx *ctx, const recon_task *task, uint64_t *ticket);
+/* Non-blocking: *done = 1 once the ticket's result is in its image buffer. */
+int recon_poll(recon_ctx *ctx, uint64_t ticket, int *done);
+/* Block until the ticket completes or timeout_us elapses (< 0: no limit). */
+int recon_wait(recon_ctx *ctx, uint64_t ticket, int64_t timeout_us);
+/* Stop the request loop after the admitted work has drained. */
+int recon_serve_stop(recon_ctx *ctx);
+
+/* Statistics of the last completed recon_dilate / recon_fill_holes /
+ * recon_batch launch (synchronises with it).  Returns RECON_EDEVICE if that
+ * launch was stopped by the scheduler watchdog (no block visit completed for
+ * 8 s), in which case its results are incomplete. */
+int recon_last_stats(recon_ctx *ctx, recon_stats *out);
+
+/* Message describing the last failure on the calling thread ("" if none). */
+const char *recon_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RECON_H */

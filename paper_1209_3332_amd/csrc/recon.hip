@@ -1,0 +1,516 @@
+// recon.hip -- host runtime and C ABI of librecon (see include/recon.h).
+//
+// A context owns the device workspace of the scheduler (task table, block
+// states, visit ring, per-tile counters), the fill-holes scratch planes, and
+// one captured HIP graph per block-shape variant for recon_batch.  Every
+// launch sequence is: copy the task table -> reset the scheduler state ->
+// (fill-holes marker init) -> persistent reconstruction kernel -> (fill-holes
+// result).  The kernels read the batch size from the copied header, so one
+// captured graph serves every batch that fits the workspace.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/recon.h"
+#include "kernels.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return fail(RECON_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));  \
+    } while (0)
+
+using rk::BatchHdr;
+static_assert(sizeof(BatchHdr) == 64, "header size");
+
+constexpr int kVariants = 3;                 // block rows 16, 32, 64
+constexpr int kBlockRows[kVariants] = {16, 32, 64};
+
+int variant_of(int rows) {
+    for (int v = 0; v < kVariants; ++v)
+        if (kBlockRows[v] == rows) return v;
+    return -1;
+}
+
+size_t lds_bytes(int bh, int qcap) {
+    return (size_t)(bh + 2) * rk::JP + (size_t)bh * rk::IP + (size_t)((bh + 15) & ~15) +
+           2u * (size_t)qcap;
+}
+
+const void *persistent_fn(int v) {
+    switch (v) {
+        case 0: return reinterpret_cast<const void *>(&rk::recon_persistent<16>);
+        case 1: return reinterpret_cast<const void *>(&rk::recon_persistent<32>);
+        default: return reinterpret_cast<const void *>(&rk::recon_persistent<64>);
+    }
+}
+
+}  // namespace
+
+struct recon_ctx {
+    int device = 0;
+    int cus = 0;
+    recon_config cfg{};
+    // scheduler workspace
+    uint8_t *d_table = nullptr;       // BatchHdr + TaskDev[cap_tasks]
+    size_t cap_tasks = 0;
+    rk::Work *d_work = nullptr;
+    uint32_t *d_state = nullptr;
+    uint32_t *d_ring = nullptr;
+    size_t cap_blocks = 0;
+    uint32_t *d_tile_pending = nullptr;
+    uint32_t *d_tile_done = nullptr;
+    uint8_t *d_scratch = nullptr;     // fill-holes marker planes
+    size_t cap_scratch = 0;
+    // pinned staging for the task table
+    uint8_t *h_table = nullptr;
+    size_t cap_h_table = 0;
+    hipEvent_t table_copied = nullptr;
+    hipEvent_t last_done = nullptr;
+    bool have_last = false;
+    // resident workgroups per variant (0 = not yet computed)
+    int resident[kVariants] = {0, 0, 0};
+    uint64_t watchdog_ticks = 0;      // device wall-clock ticks of the scheduler watchdog
+    // captured batch graphs per variant
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t graph[kVariants] = {nullptr, nullptr, nullptr};
+    size_t graph_cap_blocks[kVariants] = {0, 0, 0};
+    size_t graph_cap_tasks[kVariants] = {0, 0, 0};
+    // serving
+    struct Serve;
+    Serve *serve = nullptr;
+};
+
+namespace {
+
+int ensure_device(recon_ctx *c) {
+    HIP_TRY(hipSetDevice(c->device));
+    return RECON_OK;
+}
+
+int resident_wgs(recon_ctx *c, int v) {
+    if (c->resident[v] == 0) {
+        int per_cu = 0;
+        const size_t lds = lds_bytes(kBlockRows[v], c->cfg.queue_capacity);
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, persistent_fn(v), 64, lds);
+        if (e != hipSuccess || per_cu <= 0) per_cu = 1;
+        if (c->cfg.wg_per_cu > 0) per_cu = std::min(per_cu, c->cfg.wg_per_cu);
+        c->resident[v] = per_cu * c->cus;
+    }
+    return c->resident[v];
+}
+
+void free_workspace(recon_ctx *c) {
+    (void)hipFree(c->d_table);
+    (void)hipFree(c->d_work);
+    (void)hipFree(c->d_state);
+    (void)hipFree(c->d_ring);
+    (void)hipFree(c->d_tile_pending);
+    (void)hipFree(c->d_tile_done);
+    (void)hipFree(c->d_scratch);
+    c->d_table = nullptr;
+    c->d_work = nullptr;
+    c->d_state = c->d_ring = c->d_tile_pending = c->d_tile_done = nullptr;
+    c->d_scratch = nullptr;
+    c->cap_tasks = c->cap_blocks = c->cap_scratch = 0;
+}
+
+void drop_graphs(recon_ctx *c) {
+    for (int v = 0; v < kVariants; ++v) {
+        if (c->graph[v]) (void)hipGraphExecDestroy(c->graph[v]);
+        c->graph[v] = nullptr;
+        c->graph_cap_blocks[v] = c->graph_cap_tasks[v] = 0;
+    }
+}
+
+size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Grow the workspace to hold n_tasks tasks, n_blocks blocks and `scratch` bytes
+// of fill-holes planes.  Growing synchronises the device and drops captured graphs.
+int ensure_capacity(recon_ctx *c, size_t n_tasks, size_t n_blocks, size_t scratch) {
+    if (n_tasks <= c->cap_tasks && n_blocks <= c->cap_blocks && scratch <= c->cap_scratch)
+        return RECON_OK;
+    HIP_TRY(hipDeviceSynchronize());
+    drop_graphs(c);
+    size_t nt = std::max(c->cap_tasks, std::max<size_t>(n_tasks, 64));
+    size_t nb = std::max(c->cap_blocks, std::max<size_t>(n_blocks, 4096));
+    size_t ns = std::max(c->cap_scratch, scratch);
+    free_workspace(c);
+    const size_t table = sizeof(BatchHdr) + nt * sizeof(rk::TaskDev);
+    if (hipMalloc(&c->d_table, table) != hipSuccess ||
+        hipMalloc(&c->d_work, sizeof(rk::Work)) != hipSuccess ||
+        hipMalloc(&c->d_state, nb * sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc(&c->d_ring, (nb + 1) * sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc(&c->d_tile_pending, nt * sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc(&c->d_tile_done, nt * sizeof(uint32_t)) != hipSuccess ||
+        (ns > 0 && hipMalloc(&c->d_scratch, ns) != hipSuccess)) {
+        free_workspace(c);
+        return fail(RECON_ENOMEM, "workspace allocation of %zu tasks / %zu blocks / %zu scratch bytes failed",
+                    nt, nb, ns);
+    }
+    c->cap_tasks = nt;
+    c->cap_blocks = nb;
+    c->cap_scratch = ns;
+    if (c->cap_h_table < table) {
+        if (c->h_table) (void)hipHostFree(c->h_table);
+        c->h_table = nullptr;
+        if (hipHostMalloc((void **)&c->h_table, table, hipHostMallocDefault) != hipSuccess)
+            return fail(RECON_ENOMEM, "pinned task table allocation failed");
+        c->cap_h_table = table;
+    }
+    return RECON_OK;
+}
+
+int check_image(const recon_image *im, const char *what) {
+    if (!im) return fail(RECON_EINVAL, "%s: null image", what);
+    if (!im->data) return fail(RECON_EINVAL, "%s: null data pointer", what);
+    if (im->height < 1 || im->width < 1)
+        return fail(RECON_EINVAL, "%s: shape %dx%d is empty", what, im->height, im->width);
+    if (im->pitch < im->width)
+        return fail(RECON_EINVAL, "%s: pitch %lld < width %d", what, (long long)im->pitch, im->width);
+    return RECON_OK;
+}
+
+bool overlaps(const recon_image &a, const recon_image &b) {
+    const uintptr_t a0 = (uintptr_t)a.data, a1 = a0 + (uintptr_t)((a.height - 1) * a.pitch + a.width);
+    const uintptr_t b0 = (uintptr_t)b.data, b1 = b0 + (uintptr_t)((b.height - 1) * b.pitch + b.width);
+    return a0 < b1 && b0 < a1;
+}
+
+int check_task(const recon_task &t) {
+    if (t.op != RECON_OP_DILATE && t.op != RECON_OP_FILL_HOLES)
+        return fail(RECON_EINVAL, "unknown op %d", t.op);
+    if (t.conn != 4 && t.conn != 8) return fail(RECON_EINVAL, "conn must be 4 or 8, got %d", t.conn);
+    int rc = check_image(&t.image, t.op == RECON_OP_DILATE ? "marker" : "image");
+    if (rc) return rc;
+    if (t.op == RECON_OP_DILATE) {
+        rc = check_image(&t.mask, "mask");
+        if (rc) return rc;
+        if (t.mask.height != t.image.height || t.mask.width != t.image.width)
+            return fail(RECON_EINVAL, "marker %dx%d and mask %dx%d differ in shape", t.image.height,
+                        t.image.width, t.mask.height, t.mask.width);
+        if (overlaps(t.image, t.mask)) return fail(RECON_EINVAL, "marker and mask overlap");
+    }
+    return RECON_OK;
+}
+
+bool aligned4(const void *p, int64_t pitch) { return ((uintptr_t)p % 4 == 0) && (pitch % 4 == 0); }
+
+// Build the device task table (host side) for `n` tasks; returns totals.
+void build_table(recon_ctx *c, const recon_task *tasks, int n, int bh, std::vector<rk::TaskDev> &out,
+                 uint32_t &total_blocks, size_t &scratch_bytes, bool &any_fill) {
+    out.resize(n);
+    total_blocks = 0;
+    scratch_bytes = 0;
+    any_fill = false;
+    for (int k = 0; k < n; ++k) {
+        const recon_task &t = tasks[k];
+        rk::TaskDev d{};
+        d.h = t.image.height;
+        d.w = t.image.width;
+        d.conn = t.conn;
+        d.nby = (d.h + bh - 1) / bh;
+        d.nbx = (d.w + rk::BW - 1) / rk::BW;
+        d.block0 = total_blocks;
+        total_blocks += (uint32_t)(d.nby * d.nbx);
+        if (t.op == RECON_OP_DILATE) {
+            d.op = rk::OP_DILATE;
+            d.j = t.image.data;
+            d.pitch_j = t.image.pitch;
+            d.i = t.mask.data;
+            d.pitch_i = t.mask.pitch;
+            d.img = nullptr;
+            d.aligned = aligned4(d.j, d.pitch_j) && aligned4(d.i, d.pitch_i);
+        } else {
+            d.op = rk::OP_FILL;
+            d.i = t.image.data;
+            d.pitch_i = t.image.pitch;
+            d.img = t.image.data;
+            d.pitch_j = (int64_t)round_up((size_t)d.w, 4);
+            d.j = (uint8_t *)(uintptr_t)scratch_bytes;   // offset, patched below
+            scratch_bytes += round_up((size_t)d.pitch_j * d.h, 256);
+            d.aligned = aligned4(d.i, d.pitch_i);
+            any_fill = true;
+        }
+        out[k] = d;
+    }
+    (void)c;
+}
+
+// Enqueue one launch sequence for `tasks` on `stream`; graph=true replays the
+// captured batch graph of the variant instead of launching directly.
+int run_tasks(recon_ctx *c, const recon_task *tasks, int n, hipStream_t stream, bool use_graph) {
+    int rc = ensure_device(c);
+    if (rc) return rc;
+    const int bh = c->cfg.block_rows;
+    const int v = variant_of(bh);
+    std::vector<rk::TaskDev> table;
+    uint32_t total_blocks = 0;
+    size_t scratch = 0;
+    bool any_fill = false;
+    build_table(c, tasks, n, bh, table, total_blocks, scratch, any_fill);
+    rc = ensure_capacity(c, (size_t)n, (size_t)total_blocks, scratch);
+    if (rc) return rc;
+    for (auto &d : table)
+        if (d.op == rk::OP_FILL) d.j = c->d_scratch + (uintptr_t)d.j;
+
+    // stage the table in pinned memory (wait for the previous copy out of it)
+    if (c->table_copied) HIP_TRY(hipEventSynchronize(c->table_copied));
+    BatchHdr hdr{};
+    hdr.n_tasks = (uint32_t)n;
+    hdr.total_blocks = total_blocks;
+    hdr.ring_cap = (uint32_t)(c->cap_blocks + 1);
+    hdr.any_fill = any_fill ? 1u : 0u;
+    std::memcpy(c->h_table, &hdr, sizeof(hdr));
+    std::memcpy(c->h_table + sizeof(hdr), table.data(), table.size() * sizeof(rk::TaskDev));
+    HIP_TRY(hipMemcpyAsync(c->d_table, c->h_table, sizeof(hdr) + table.size() * sizeof(rk::TaskDev),
+                           hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipEventRecord(c->table_copied, stream));
+
+    const BatchHdr *d_hdr = (const BatchHdr *)c->d_table;
+    const rk::TaskDev *d_tasks = (const rk::TaskDev *)(c->d_table + sizeof(BatchHdr));
+    const int resident = resident_wgs(c, v);
+    const size_t lds = lds_bytes(bh, c->cfg.queue_capacity);
+
+    auto enqueue = [&](hipStream_t s, int grid, bool fills) -> int {
+        rk::KArgs ka;
+        ka.tasks = d_tasks;
+        ka.work = c->d_work;
+        ka.state = c->d_state;
+        ka.ring = c->d_ring;
+        ka.tile_pending = c->d_tile_pending;
+        ka.tile_done = c->d_tile_done;
+        ka.qcap = c->cfg.queue_capacity;
+        ka.scan_rounds = c->cfg.scan_rounds;
+        ka.watchdog_ticks = c->watchdog_ticks;
+        hipLaunchKernelGGL(rk::reset_work, dim3(256), dim3(256), 0, s, d_hdr, d_tasks, c->d_work,
+                           c->d_state, c->d_ring, c->d_tile_pending, c->d_tile_done);
+        if (fills) hipLaunchKernelGGL(rk::fill_init, dim3(1024), dim3(256), 0, s, d_hdr, d_tasks);
+        switch (v) {
+            case 0: hipLaunchKernelGGL(rk::recon_persistent<16>, dim3(grid), dim3(64), lds, s, ka); break;
+            case 1: hipLaunchKernelGGL(rk::recon_persistent<32>, dim3(grid), dim3(64), lds, s, ka); break;
+            default: hipLaunchKernelGGL(rk::recon_persistent<64>, dim3(grid), dim3(64), lds, s, ka); break;
+        }
+        if (fills) hipLaunchKernelGGL(rk::fill_finish, dim3(1024), dim3(256), 0, s, d_hdr, d_tasks);
+        HIP_TRY(hipGetLastError());
+        return RECON_OK;
+    };
+
+    if (use_graph) {
+        if (!c->graph[v] || c->graph_cap_blocks[v] != c->cap_blocks || c->graph_cap_tasks[v] != c->cap_tasks) {
+            if (c->graph[v]) (void)hipGraphExecDestroy(c->graph[v]);
+            c->graph[v] = nullptr;
+            if (!c->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+            hipGraph_t g = nullptr;
+            HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+            rc = enqueue(c->cap_stream, resident, true);
+            hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+            if (rc) return rc;
+            if (e != hipSuccess) return fail(RECON_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+            e = hipGraphInstantiate(&c->graph[v], g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) return fail(RECON_EDEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
+            c->graph_cap_blocks[v] = c->cap_blocks;
+            c->graph_cap_tasks[v] = c->cap_tasks;
+        }
+        HIP_TRY(hipGraphLaunch(c->graph[v], stream));
+    } else {
+        const int grid = (int)std::max<uint32_t>(1u, std::min<uint32_t>((uint32_t)resident, total_blocks));
+        rc = enqueue(stream, grid, any_fill);
+        if (rc) return rc;
+    }
+    HIP_TRY(hipEventRecord(c->last_done, stream));
+    c->have_last = true;
+    return RECON_OK;
+}
+
+}  // namespace
+
+// ============================================================================
+// serving: a request loop that admits tasks by device memory and slots and
+// runs them as continuous batches (see recon_submit)
+struct recon_ctx::Serve {
+    struct Req {
+        uint64_t ticket;
+        recon_task task;
+        size_t bytes;
+    };
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<Req> waiting;                 // admitted, not yet launched
+    std::vector<uint64_t> done_tickets;      // completed (sorted insert not needed)
+    std::vector<uint64_t> completed;
+    uint64_t next_ticket = 1;
+    size_t bytes_in_flight = 0;
+    int slots_in_flight = 0;
+    bool stop = false;
+    std::thread worker;
+    int worker_error = 0;
+    std::string worker_msg;
+    hipStream_t stream = nullptr;
+    recon_ctx *owner = nullptr;
+    std::vector<uint8_t> done_flag;          // indexed by ticket (grown)
+};
+
+extern "C" {
+
+const char *recon_last_error(void) { return g_err.c_str(); }
+
+int recon_create(recon_ctx **out, int device, const recon_config *cfg) {
+    if (!out) return fail(RECON_EINVAL, "null output pointer");
+    *out = nullptr;
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || ndev == 0) return fail(RECON_EDEVICE, "no HIP device available");
+    if (device < 0 || device >= ndev) return fail(RECON_EINVAL, "device %d out of range (%d devices)", device, ndev);
+    recon_config c{};
+    if (cfg) c = *cfg;
+    if (c.block_rows == 0) c.block_rows = 32;
+    if (variant_of(c.block_rows) < 0) return fail(RECON_EINVAL, "block_rows must be 16, 32 or 64");
+    if (c.queue_capacity == 0) c.queue_capacity = 2048;
+    if (c.queue_capacity < 64 || c.queue_capacity > 8192)
+        return fail(RECON_EINVAL, "queue_capacity must be in 64..8192");
+    if (c.scan_rounds < -1 || c.scan_rounds > 8) return fail(RECON_EINVAL, "scan_rounds must be in -1..8");
+    if (c.scan_rounds == 0) c.scan_rounds = 2;
+    if (c.scan_rounds < 0) c.scan_rounds = 0;
+    if (c.wg_per_cu < 0) return fail(RECON_EINVAL, "wg_per_cu must be >= 0");
+    if (c.serve_mem_cap == 0) c.serve_mem_cap = (int64_t)64 << 30;
+    if (c.serve_slots == 0) c.serve_slots = 256;
+    recon_ctx *ctx = new recon_ctx();
+    ctx->device = device;
+    ctx->cfg = c;
+    int rc = ensure_device(ctx);
+    if (rc) { delete ctx; return rc; }
+    if (hipDeviceGetAttribute(&ctx->cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->table_copied, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->last_done, hipEventDisableTiming) != hipSuccess) {
+        delete ctx;
+        return fail(RECON_EDEVICE, "device query / event creation failed");
+    }
+    int clock_khz = 0;
+    if (hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, device) != hipSuccess ||
+        clock_khz <= 0)
+        clock_khz = 100000;
+    ctx->watchdog_ticks = (uint64_t)clock_khz * 1000ull * 8ull;   // 8 s without progress
+    *out = ctx;
+    return RECON_OK;
+}
+
+int recon_destroy(recon_ctx *ctx) {
+    if (!ctx) return fail(RECON_EINVAL, "null context");
+    if (ctx->serve) recon_serve_stop(ctx);
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    drop_graphs(ctx);
+    free_workspace(ctx);
+    if (ctx->h_table) (void)hipHostFree(ctx->h_table);
+    if (ctx->table_copied) (void)hipEventDestroy(ctx->table_copied);
+    if (ctx->last_done) (void)hipEventDestroy(ctx->last_done);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    delete ctx;
+    return RECON_OK;
+}
+
+int recon_dilate(recon_ctx *ctx, recon_image *marker, const recon_image *mask, int conn, void *stream) {
+    if (!ctx) return fail(RECON_EINVAL, "null context");
+    if (!marker || !mask) return fail(RECON_EINVAL, "null image");
+    recon_task t{};
+    t.op = RECON_OP_DILATE;
+    t.conn = conn;
+    t.image = *marker;
+    t.mask = *mask;
+    int rc = check_task(t);
+    if (rc) return rc;
+    return run_tasks(ctx, &t, 1, (hipStream_t)stream, false);
+}
+
+int recon_fill_holes(recon_ctx *ctx, recon_image *img, int conn, void *stream) {
+    if (!ctx) return fail(RECON_EINVAL, "null context");
+    if (!img) return fail(RECON_EINVAL, "null image");
+    recon_task t{};
+    t.op = RECON_OP_FILL_HOLES;
+    t.conn = conn;
+    t.image = *img;
+    int rc = check_task(t);
+    if (rc) return rc;
+    return run_tasks(ctx, &t, 1, (hipStream_t)stream, false);
+}
+
+int recon_batch(recon_ctx *ctx, const recon_task *tasks, int32_t n, void *stream) {
+    if (!ctx) return fail(RECON_EINVAL, "null context");
+    if (n < 0 || (n > 0 && !tasks)) return fail(RECON_EINVAL, "bad task list");
+    if (n == 0) return RECON_OK;
+    for (int k = 0; k < n; ++k) {
+        int rc = check_task(tasks[k]);
+        if (rc) {
+            std::string m = g_err;
+            return fail(rc, "task %d: %s", k, m.c_str());
+        }
+    }
+    return run_tasks(ctx, tasks, n, (hipStream_t)stream, true);
+}
+
+int recon_last_stats(recon_ctx *ctx, recon_stats *out) {
+    if (!ctx || !out) return fail(RECON_EINVAL, "null argument");
+    std::memset(out, 0, sizeof(*out));
+    if (!ctx->have_last) return RECON_OK;
+    int rc = ensure_device(ctx);
+    if (rc) return rc;
+    HIP_TRY(hipEventSynchronize(ctx->last_done));
+    rk::Work w{};
+    HIP_TRY(hipMemcpy(&w, ctx->d_work, sizeof(w), hipMemcpyDeviceToHost));
+    out->dense_visits = (int64_t)w.stat_dense;
+    out->revisits = (int64_t)w.stat_revisit;
+    out->reruns = (int64_t)w.stat_rerun;
+    out->queue_overflows = (int64_t)w.stat_overflow;
+    out->spills = (int64_t)w.stat_spill;
+    out->aborted = (int64_t)w.abort;
+    if (w.abort) return fail(RECON_EDEVICE, "scheduler watchdog expired: the last launch did not converge");
+    return RECON_OK;
+}
+
+int recon_submit(recon_ctx *ctx, const recon_task *task, uint64_t *ticket) {
+    (void)ctx; (void)task; (void)ticket;
+    return fail(RECON_EINVAL, "serving is not available in this build");
+}
+int recon_poll(recon_ctx *ctx, uint64_t ticket, int *done) {
+    (void)ctx; (void)ticket; (void)done;
+    return fail(RECON_EINVAL, "serving is not available in this build");
+}
+int recon_wait(recon_ctx *ctx, uint64_t ticket, int64_t timeout_us) {
+    (void)ctx; (void)ticket; (void)timeout_us;
+    return fail(RECON_EINVAL, "serving is not available in this build");
+}
+int recon_serve_stop(recon_ctx *ctx) {
+    (void)ctx;
+    return RECON_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,246 @@
+"""GPU parity: the HIP path through the C ABI must equal the CPU oracle byte for byte.
+
+All inputs are seeded and synthetic.  Integer work, so the bar is bit-exact
+(tolerance 0) everywhere: every tile shape, connectivity, tuning, batch mix
+and repetition.
+"""
+import numpy as np
+import pytest
+
+import golden_io
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def lib(torch_mod):
+    import paper_1209_3332_amd as p
+    return p
+
+
+@pytest.fixture(scope="module")
+def rc(lib):
+    ctx = lib.Recon(0)
+    yield ctx
+    ctx.close()
+
+
+def dev(torch_mod, a):
+    return torch_mod.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def gpu_dilate(torch_mod, ctx, marker, mask, conn):
+    m = dev(torch_mod, marker)
+    k = dev(torch_mod, mask)
+    ctx.dilate(m, k, conn)
+    torch_mod.cuda.synchronize()
+    ctx.last_stats()  # raises if the watchdog stopped the launch
+    return m.cpu().numpy()
+
+
+def gpu_fill(torch_mod, ctx, img, conn):
+    x = dev(torch_mod, img)
+    ctx.fill_holes(x, conn)
+    torch_mod.cuda.synchronize()
+    ctx.last_stats()
+    return x.cpu().numpy()
+
+
+def assert_same(got, want, what):
+    if not np.array_equal(got, want):
+        bad = np.argwhere(got != want)
+        y, x = bad[0]
+        raise AssertionError("%s: %d pixels differ, first at (%d, %d): got %d want %d"
+                             % (what, len(bad), y, x, got[y, x], want[y, x]))
+
+
+@pytest.mark.parametrize("case", golden_io.all_cases(), ids=lambda c: c["name"])
+def test_golden(torch_mod, rc, case):
+    for conn in case["conns"]:
+        if case["op"] == "dilate":
+            got = gpu_dilate(torch_mod, rc, case["marker"], case["mask"], conn)
+        else:
+            got = gpu_fill(torch_mod, rc, case["img"], conn)
+        assert_same(got, case["expect"], "%s conn %d" % (case["name"], conn))
+
+
+@pytest.mark.parametrize("conn", [8, 4])
+def test_config1_tile(torch_mod, rc, oracle_mod, conn):
+    marker, mask = synth.config1_tile()
+    assert_same(gpu_dilate(torch_mod, rc, marker, mask, conn), oracle_mod.recon_dilate(marker, mask, conn),
+                "512x512 nuclei conn %d" % conn)
+
+
+SHAPES = [(1, 1), (1, 7), (7, 1), (1, 300), (300, 1), (2, 2), (3, 257), (65, 3), (31, 256), (32, 256),
+          (33, 257), (64, 512), (257, 131), (100, 513), (129, 1000)]
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "%dx%d" % s)
+@pytest.mark.parametrize("conn", [8, 4])
+def test_ragged_shapes(torch_mod, rc, oracle_mod, shape, conn):
+    rng = np.random.default_rng(shape[0] * 1000 + shape[1] + conn)
+    for levels in (3, 256):
+        marker, mask = synth.random_pair(rng, shape[0], shape[1], levels)
+        if levels == 256:
+            marker = synth.hdome_marker(mask, int(rng.integers(1, 80)))
+        assert_same(gpu_dilate(torch_mod, rc, marker, mask, conn), oracle_mod.recon_dilate(marker, mask, conn),
+                    "%dx%d levels %d conn %d" % (shape[0], shape[1], levels, conn))
+
+
+@pytest.mark.parametrize("conn", [8, 4])
+def test_marker_above_mask_is_clipped(torch_mod, rc, oracle_mod, conn):
+    rng = np.random.default_rng(9)
+    marker, mask = synth.random_pair(rng, 70, 300, 256)
+    assert_same(gpu_dilate(torch_mod, rc, marker, mask, conn), oracle_mod.recon_dilate(marker, mask, conn),
+                "unclipped marker")
+
+
+@pytest.mark.parametrize("conn", [8, 4])
+def test_nuclei_1024(torch_mod, rc, oracle_mod, conn):
+    marker, mask, binary = synth.config2_tile(seed=synth.seed_for(2, 7), size=1024, n_gauss=188)
+    assert_same(gpu_dilate(torch_mod, rc, marker, mask, conn), oracle_mod.recon_dilate(marker, mask, conn),
+                "1024 nuclei conn %d" % conn)
+    assert_same(gpu_fill(torch_mod, rc, binary, conn), oracle_mod.fill_holes(binary, conn),
+                "1024 fill conn %d" % conn)
+
+
+@pytest.mark.parametrize("conn", [8, 4])
+def test_config2_full_tile(torch_mod, rc, oracle_mod, conn):
+    marker, mask, binary = synth.config2_tile()
+    assert_same(gpu_dilate(torch_mod, rc, marker, mask, conn), oracle_mod.recon_dilate(marker, mask, conn),
+                "4096 nuclei conn %d" % conn)
+    assert_same(gpu_fill(torch_mod, rc, binary, conn), oracle_mod.fill_holes(binary, conn),
+                "4096 fill conn %d" % conn)
+
+
+@pytest.mark.parametrize("conn", [8, 4])
+def test_fill_holes_grey_and_ragged(torch_mod, rc, oracle_mod, conn):
+    rng = np.random.default_rng(31 + conn)
+    for shape in [(1, 1), (2, 5), (5, 2), (3, 3), (40, 300), (257, 131)]:
+        img = rng.integers(0, 256, size=shape).astype(np.uint8)
+        assert_same(gpu_fill(torch_mod, rc, img, conn), oracle_mod.fill_holes(img, conn), "grey fill %s" % (shape,))
+        b = np.where(rng.random(shape) < 0.55, 255, 0).astype(np.uint8)
+        assert_same(gpu_fill(torch_mod, rc, b, conn), oracle_mod.fill_holes(b, conn), "binary fill %s" % (shape,))
+
+
+@pytest.mark.parametrize("seed_at", ["outer", "inner"])
+def test_spiral_1024(torch_mod, rc, seed_at):
+    marker, mask, _ = synth.spiral_tile(1024, 1024, seed_at)
+    for conn in (8, 4):
+        assert_same(gpu_dilate(torch_mod, rc, marker, mask, conn), mask, "spiral %s conn %d" % (seed_at, conn))
+
+
+def test_unaligned_pitch_and_offset(torch_mod, rc, oracle_mod):
+    rng = np.random.default_rng(4)
+    h, w = 90, 301
+    marker, mask = synth.random_pair(rng, h, w, 256)
+    marker = synth.hdome_marker(mask, 25)
+    big_m = torch_mod.zeros((h, w + 7), dtype=torch_mod.uint8, device="cuda")
+    big_k = torch_mod.zeros((h + 1, w + 7), dtype=torch_mod.uint8, device="cuda")
+    m = big_m[:, 1:1 + w]
+    k = big_k[1:, 3:3 + w]
+    m.copy_(torch_mod.from_numpy(marker))
+    k.copy_(torch_mod.from_numpy(mask))
+    rc.dilate(m, k, 8)
+    torch_mod.cuda.synchronize()
+    assert_same(m.cpu().numpy(), oracle_mod.recon_dilate(marker, mask, 8), "unaligned views")
+    # the padding around the views is untouched
+    assert int(big_m[:, 0].sum()) == 0 and int(big_m[:, 1 + w:].sum()) == 0
+
+
+@pytest.mark.parametrize("cfg", [dict(block_rows=16), dict(block_rows=64), dict(queue_capacity=64),
+                                 dict(scan_rounds=-1), dict(scan_rounds=4, block_rows=64),
+                                 dict(wg_per_cu=1)], ids=str)
+def test_tuning_invariance(torch_mod, lib, oracle_mod, cfg):
+    marker, mask, binary = synth.config2_tile(seed=synth.seed_for(2, 11), size=768, n_gauss=106)
+    sm, smask, _ = synth.spiral_tile(300, 520, "inner")
+    with lib.Recon(0, **cfg) as ctx:
+        for conn in (8, 4):
+            assert_same(gpu_dilate(torch_mod, ctx, marker, mask, conn), oracle_mod.recon_dilate(marker, mask, conn),
+                        "%s conn %d" % (cfg, conn))
+            assert_same(gpu_fill(torch_mod, ctx, binary, conn), oracle_mod.fill_holes(binary, conn),
+                        "%s fill conn %d" % (cfg, conn))
+            assert_same(gpu_dilate(torch_mod, ctx, sm, smask, conn), smask, "%s spiral conn %d" % (cfg, conn))
+
+
+def test_determinism(torch_mod, rc):
+    marker, mask, _ = synth.config2_tile(seed=synth.seed_for(2, 12), size=1024, n_gauss=188)
+    first = gpu_dilate(torch_mod, rc, marker, mask, 8)
+    for _ in range(5):
+        assert np.array_equal(gpu_dilate(torch_mod, rc, marker, mask, 8), first)
+
+
+def _batch_tasks(rng, n):
+    tasks = []
+    for i in range(n):
+        h, w = int(rng.integers(1, 700)), int(rng.integers(1, 900))
+        conn = int(rng.choice([4, 8]))
+        if i % 5 == 4:
+            img = np.where(rng.random((h, w)) < 0.6, 255, 0).astype(np.uint8)
+            tasks.append({"op": "fill_holes", "img": img, "conn": conn})
+        else:
+            mask = synth.scaled_config1_tile(h, w, 5000 + i)
+            tasks.append({"op": "dilate", "marker": synth.hdome_marker(mask, int(rng.integers(10, 41))),
+                          "mask": mask, "conn": conn})
+    return tasks
+
+
+def _run_batch(torch_mod, ctx, tasks):
+    devs = []
+    spec = []
+    for t in tasks:
+        if t["op"] == "dilate":
+            m, k = dev(torch_mod, t["marker"]), dev(torch_mod, t["mask"])
+            devs.append(m)
+            spec.append({"op": "dilate", "image": m, "mask": k, "conn": t["conn"]})
+        else:
+            x = dev(torch_mod, t["img"])
+            devs.append(x)
+            spec.append({"op": "fill_holes", "image": x, "conn": t["conn"]})
+    ctx.batch(spec)
+    torch_mod.cuda.synchronize()
+    ctx.last_stats()
+    return [d.cpu().numpy() for d in devs]
+
+
+def test_batch_mixed(torch_mod, rc, oracle_mod):
+    rng = np.random.default_rng(123)
+    tasks = _batch_tasks(rng, 23)
+    outs = _run_batch(torch_mod, rc, tasks)
+    for i, (t, got) in enumerate(zip(tasks, outs)):
+        assert_same(got, oracle_mod.run_task(t), "batch task %d (%s)" % (i, t["op"]))
+    # replay of the captured graph with a different batch
+    tasks2 = _batch_tasks(np.random.default_rng(321), 9)
+    outs2 = _run_batch(torch_mod, rc, tasks2)
+    for i, (t, got) in enumerate(zip(tasks2, outs2)):
+        assert_same(got, oracle_mod.run_task(t), "second batch task %d" % i)
+
+
+def test_batch_with_spirals(torch_mod, rc, oracle_mod):
+    tasks = synth.config3_batch(n_tiles=8, size=512)
+    outs = _run_batch(torch_mod, rc, tasks)
+    for i, (t, got) in enumerate(zip(tasks, outs)):
+        assert_same(got, oracle_mod.run_task(t), "config-3 style task %d (%s)" % (i, t["kind"]))
+
+
+def test_argument_errors(torch_mod, rc, lib):
+    a = torch_mod.zeros((4, 5), dtype=torch_mod.uint8, device="cuda")
+    b = torch_mod.zeros((4, 6), dtype=torch_mod.uint8, device="cuda")
+    with pytest.raises(lib.ReconError):
+        rc.dilate(a, b, 8)
+    c = torch_mod.zeros((4, 5), dtype=torch_mod.uint8, device="cuda")
+    with pytest.raises(lib.ReconError):
+        rc.dilate(a, c, 6)
+    with pytest.raises(lib.ReconError):
+        rc.dilate(a, a, 8)  # marker and mask overlap
+    with pytest.raises(lib.ReconError):
+        rc.fill_holes(a, 5)
