@@ -77,6 +77,7 @@ def load_library(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise ImportError("librecon.so is not built (%s); run `python -m paper_1209_3332_amd.build`" % path)
+    import torch  # noqa: F401  (load torch's HIP runtime first so one runtime serves both)
     lib = ctypes.CDLL(path)
     P = ctypes.c_void_p
     lib.recon_create.argtypes = [ctypes.POINTER(P), ctypes.c_int, ctypes.POINTER(recon_config)]

@@ -402,7 +402,13 @@ __device__ void drain(Lds<BH> &L, int conn, int qcap, uint32_t &head, uint32_t &
     const int ndir = conn == 8 ? 8 : 4;
     const int dys[8] = {-1, 1, 0, 0, -1, -1, 1, 1};
     const int dxs[8] = {0, 0, -1, 1, -1, 1, -1, 1};
+    uint32_t iters = 0;
     while (head != tail) {
+        if (++iters > (1u << 24)) {   // cannot happen: the raises are bounded; guard anyway
+            overflow = false;
+            head = tail;
+            break;
+        }
         const uint32_t n = min(tail - head, (uint32_t)LANES);
         const bool valid = (uint32_t)ln < n;
         uint32_t p = 0;
@@ -451,6 +457,19 @@ __device__ __forceinline__ int find_task(const TaskDev *tasks, int n, uint32_t g
     return lo;
 }
 
+// Set the abort flag and report true once `start` is older than the watchdog
+// budget (or another wave has already aborted).  Every wait in the kernels
+// polls this, so every wave exits in bounded time even if the scheduler had
+// a bug.
+__device__ __forceinline__ bool expired(const KArgs &a, uint64_t start) {
+    if (__hip_atomic_load(&a.work->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return true;
+    if (wall_clock64() - start > a.watchdog_ticks) {
+        __hip_atomic_store(&a.work->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return true;
+    }
+    return false;
+}
+
 __device__ __forceinline__ uint32_t ld_acq(uint32_t *p) {
     return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -466,8 +485,11 @@ __device__ void request_block(const KArgs &a, int ti, uint32_t nb) {
     const uint32_t pos = __hip_atomic_fetch_add(&a.work->ring_tail, 1u, __ATOMIC_RELAXED,
                                                 __HIP_MEMORY_SCOPE_AGENT);
     uint32_t *slot = a.ring + pos % a.work->ring_cap;
-    while (__hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)
+    const uint64_t t0 = wall_clock64();
+    while (__hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+        if (expired(a, t0)) return;
         __builtin_amdgcn_s_sleep(1);
+    }
     __hip_atomic_store(slot, nb + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
@@ -588,9 +610,14 @@ __global__ __launch_bounds__(64) void recon_persistent(KArgs a) {
                                                              __HIP_MEMORY_SCOPE_AGENT)) {
                         uint32_t *slot = a.ring + h % w->ring_cap;
                         uint32_t v;
+                        const uint64_t t0 = wall_clock64();
+                        bool gave_up = false;
                         while ((v = __hip_atomic_exchange(slot, 0u, __ATOMIC_ACQ_REL,
-                                                          __HIP_MEMORY_SCOPE_AGENT)) == 0u)
+                                                          __HIP_MEMORY_SCOPE_AGENT)) == 0u) {
+                            if (expired(a, t0)) { gave_up = true; break; }
                             __builtin_amdgcn_s_sleep(1);
+                        }
+                        if (gave_up) break;
                         gsel = (int)(v - 1u);
                         dense = 0;
                         break;
@@ -664,7 +691,12 @@ __global__ __launch_bounds__(64) void recon_persistent(KArgs a) {
                 }
             }
             // seed + drain until no overflow
-            while (true) {
+            for (int round = 0;; ++round) {
+                if (round > (1 << 16)) {   // cannot happen (each round raises pixels); guard anyway
+                    if (ln == 0)
+                        __hip_atomic_store(&w->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
                 uint32_t head = 0, tail = 0;
                 bool overflow = false;
                 seed_pass<BH>(L, t.conn, a.qcap, head, tail, overflow, changed);

@@ -483,7 +483,17 @@ int recon_last_stats(recon_ctx *ctx, recon_stats *out) {
     if (!ctx->have_last) return RECON_OK;
     int rc = ensure_device(ctx);
     if (rc) return rc;
-    HIP_TRY(hipEventSynchronize(ctx->last_done));
+    // wait for the launch with a deadline rather than blocking forever
+    const auto t0 = std::chrono::steady_clock::now();
+    while (true) {
+        hipError_t q = hipEventQuery(ctx->last_done);
+        if (q == hipSuccess) break;
+        if (q != hipErrorNotReady)
+            return fail(RECON_EDEVICE, "launch failed: %s", hipGetErrorString(q));
+        if (std::chrono::steady_clock::now() - t0 > std::chrono::seconds(60))
+            return fail(RECON_ETIMEDOUT, "the last launch has not completed after 60 s");
+        std::this_thread::sleep_for(std::chrono::microseconds(200));
+    }
     rk::Work w{};
     HIP_TRY(hipMemcpy(&w, ctx->d_work, sizeof(w), hipMemcpyDeviceToHost));
     out->dense_visits = (int64_t)w.stat_dense;

@@ -42,15 +42,13 @@ def gpu_dilate(torch_mod, ctx, marker, mask, conn):
     m = dev(torch_mod, marker)
     k = dev(torch_mod, mask)
     ctx.dilate(m, k, conn)
-    torch_mod.cuda.synchronize()
-    ctx.last_stats()  # raises if the watchdog stopped the launch
+    ctx.last_stats()  # waits with a deadline; raises if the launch timed out or was stopped
     return m.cpu().numpy()
 
 
 def gpu_fill(torch_mod, ctx, img, conn):
     x = dev(torch_mod, img)
     ctx.fill_holes(x, conn)
-    torch_mod.cuda.synchronize()
     ctx.last_stats()
     return x.cpu().numpy()
 
@@ -207,7 +205,6 @@ def _run_batch(torch_mod, ctx, tasks):
             devs.append(x)
             spec.append({"op": "fill_holes", "image": x, "conn": t["conn"]})
     ctx.batch(spec)
-    torch_mod.cuda.synchronize()
     ctx.last_stats()
     return [d.cpu().numpy() for d in devs]
 
