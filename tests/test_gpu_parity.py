@@ -149,7 +149,7 @@ def test_unaligned_pitch_and_offset(torch_mod, rc, oracle_mod):
     m.copy_(torch_mod.from_numpy(marker))
     k.copy_(torch_mod.from_numpy(mask))
     rc.dilate(m, k, 8)
-    torch_mod.cuda.synchronize()
+    rc.last_stats()
     assert_same(m.cpu().numpy(), oracle_mod.recon_dilate(marker, mask, 8), "unaligned views")
     # the padding around the views is untouched
     assert int(big_m[:, 0].sum()) == 0 and int(big_m[:, 1 + w:].sum()) == 0
