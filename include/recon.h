@@ -93,7 +93,10 @@ typedef struct {
     int32_t wg_per_cu;         /* cap on resident workgroups per CU (0 = occupancy limit) */
     int64_t serve_mem_cap;     /* serving admission cap in device bytes (default 64 GiB) */
     int32_t serve_slots;       /* serving in-flight task slots (default 256) */
-    int32_t reserved[5];
+    int32_t stop_after_stage;  /* test hook: 0 = full pipeline; 1 = stop after the dense
+                                  per-block pass (each block reconstructed on its own);
+                                  2 = also seed the border requests, but do not drain them */
+    int32_t reserved[4];
 } recon_config;
 
 /* Per-call statistics of the last completed launch (for tests and tuning). */
@@ -101,12 +104,14 @@ typedef struct {
     int64_t dense_visits;      /* first visits of work blocks */
     int64_t revisits;          /* later visits triggered by neighbour changes */
     int64_t reruns;            /* in-place re-runs of a block re-requested while running */
-    int64_t queue_overflows;   /* LDS queue overflows (each followed by a re-seed) */
-    int64_t spills;            /* queue entries spilled to the global overflow area */
+    int64_t queue_overflows;   /* LDS queue overflows (each followed by a re-seed pass) */
+    int64_t requests;          /* block revisits requested by border checks */
     int64_t aborted;           /* 1 if the scheduler watchdog stopped the launch */
 } recon_stats;
 
-/* Create a context on HIP device `device`.  cfg may be NULL. */
+/* Create a context on HIP device `device`.  cfg may be NULL.  Runs a small
+ * self-test kernel (with a 20 s deadline) and fails with RECON_EDEVICE if the
+ * library's device code does not run on this device. */
 int recon_create(recon_ctx **out, int device, const recon_config *cfg);
 /* Destroy a context after all its work has completed. */
 int recon_destroy(recon_ctx *ctx);

@@ -1,12 +1,15 @@
 // recon.hip -- host runtime and C ABI of librecon (see include/recon.h).
 //
-// A context owns the device workspace of the scheduler (task table, block
-// states, visit ring, per-tile counters), the fill-holes scratch planes, and
-// one captured HIP graph per block-shape variant for recon_batch.  Every
-// launch sequence is: copy the task table -> reset the scheduler state ->
-// (fill-holes marker init) -> persistent reconstruction kernel -> (fill-holes
-// result).  The kernels read the batch size from the copied header, so one
-// captured graph serves every batch that fits the workspace.
+// A context owns the device workspace of the block scheduler (block states,
+// visit ring, counters, per-tile counts), the fill-holes scratch planes, a
+// pinned staging area, and one captured HIP graph per block shape for
+// recon_batch.  A launch sequence is
+//     [copy task table] -> reset -> K1 dense pass -> K2 border seeding
+//     -> K3 revisit drain -> [fill-holes result]
+// Up to MAX_INLINE_TASKS tasks travel by value in the kernel arguments; larger
+// batches are copied into device memory by a kernel that reads the pinned
+// staging buffer.  The library itself issues no hipMemcpy: every transfer is
+// a kernel, so every step of the sequence is ordered on the caller's stream.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -49,7 +52,7 @@ int fail(int code, const char *fmt, ...) {
 using rk::BatchHdr;
 static_assert(sizeof(BatchHdr) == 64, "header size");
 
-constexpr int kVariants = 3;                 // block rows 16, 32, 64
+constexpr int kVariants = 3;   // block rows 16, 32, 64
 constexpr int kBlockRows[kVariants] = {16, 32, 64};
 
 int variant_of(int rows) {
@@ -58,16 +61,34 @@ int variant_of(int rows) {
     return -1;
 }
 
-size_t lds_bytes(int bh, int qcap) {
-    return (size_t)(bh + 2) * rk::JP + (size_t)bh * rk::IP + (size_t)((bh + 15) & ~15) +
-           2u * (size_t)qcap;
+size_t lds_for(int v, int qcap) {
+    switch (v) {
+        case 0: return rk::lds_bytes<16>(qcap);
+        case 1: return rk::lds_bytes<32>(qcap);
+        default: return rk::lds_bytes<64>(qcap);
+    }
 }
 
-const void *persistent_fn(int v) {
+const void *drain_fn(int v) {
     switch (v) {
-        case 0: return reinterpret_cast<const void *>(&rk::recon_persistent<16>);
-        case 1: return reinterpret_cast<const void *>(&rk::recon_persistent<32>);
-        default: return reinterpret_cast<const void *>(&rk::recon_persistent<64>);
+        case 0: return reinterpret_cast<const void *>(&rk::revisit_drain<16>);
+        case 1: return reinterpret_cast<const void *>(&rk::revisit_drain<32>);
+        default: return reinterpret_cast<const void *>(&rk::revisit_drain<64>);
+    }
+}
+
+size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Wait for `ev` with a deadline; RECON_ETIMEDOUT if it does not complete.
+int wait_event(hipEvent_t ev, double seconds, const char *what) {
+    const auto t0 = std::chrono::steady_clock::now();
+    while (true) {
+        hipError_t q = hipEventQuery(ev);
+        if (q == hipSuccess) return RECON_OK;
+        if (q != hipErrorNotReady) return fail(RECON_EDEVICE, "%s failed: %s", what, hipGetErrorString(q));
+        if (std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() > seconds)
+            return fail(RECON_ETIMEDOUT, "%s has not completed after %.0f s", what, seconds);
+        std::this_thread::sleep_for(std::chrono::microseconds(100));
     }
 }
 
@@ -77,6 +98,7 @@ struct recon_ctx {
     int device = 0;
     int cus = 0;
     recon_config cfg{};
+    uint64_t watchdog_ticks = 0;
     // scheduler workspace
     uint8_t *d_table = nullptr;       // BatchHdr + TaskDev[cap_tasks]
     size_t cap_tasks = 0;
@@ -88,23 +110,20 @@ struct recon_ctx {
     uint32_t *d_tile_done = nullptr;
     uint8_t *d_scratch = nullptr;     // fill-holes marker planes
     size_t cap_scratch = 0;
-    // pinned staging for the task table
+    // pinned staging (task table in, statistics out)
     uint8_t *h_table = nullptr;
     size_t cap_h_table = 0;
-    hipEvent_t table_copied = nullptr;
+    rk::Work *h_work = nullptr;
+    hipEvent_t table_used = nullptr;  // the last copy out of h_table has finished
     hipEvent_t last_done = nullptr;
     bool have_last = false;
-    // resident workgroups per variant (0 = not yet computed)
     int resident[kVariants] = {0, 0, 0};
-    uint64_t watchdog_ticks = 0;      // device wall-clock ticks of the scheduler watchdog
     // captured batch graphs per variant
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t graph[kVariants] = {nullptr, nullptr, nullptr};
     size_t graph_cap_blocks[kVariants] = {0, 0, 0};
     size_t graph_cap_tasks[kVariants] = {0, 0, 0};
-    // serving
-    struct Serve;
-    Serve *serve = nullptr;
+    size_t graph_cap_scratch[kVariants] = {0, 0, 0};
 };
 
 namespace {
@@ -117,9 +136,8 @@ int ensure_device(recon_ctx *c) {
 int resident_wgs(recon_ctx *c, int v) {
     if (c->resident[v] == 0) {
         int per_cu = 0;
-        const size_t lds = lds_bytes(kBlockRows[v], c->cfg.queue_capacity);
-        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, persistent_fn(v), 64, lds);
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, drain_fn(v), 64,
+                                                                    lds_for(v, c->cfg.queue_capacity));
         if (e != hipSuccess || per_cu <= 0) per_cu = 1;
         if (c->cfg.wg_per_cu > 0) per_cu = std::min(per_cu, c->cfg.wg_per_cu);
         c->resident[v] = per_cu * c->cus;
@@ -146,22 +164,21 @@ void drop_graphs(recon_ctx *c) {
     for (int v = 0; v < kVariants; ++v) {
         if (c->graph[v]) (void)hipGraphExecDestroy(c->graph[v]);
         c->graph[v] = nullptr;
-        c->graph_cap_blocks[v] = c->graph_cap_tasks[v] = 0;
+        c->graph_cap_blocks[v] = c->graph_cap_tasks[v] = c->graph_cap_scratch[v] = 0;
     }
 }
 
-size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
-
-// Grow the workspace to hold n_tasks tasks, n_blocks blocks and `scratch` bytes
-// of fill-holes planes.  Growing synchronises the device and drops captured graphs.
+// Grow the workspace to hold n_tasks tasks, n_blocks blocks and `scratch`
+// bytes of fill-holes planes.  Growing synchronises the device and drops the
+// captured graphs (they hold the old pointers).
 int ensure_capacity(recon_ctx *c, size_t n_tasks, size_t n_blocks, size_t scratch) {
     if (n_tasks <= c->cap_tasks && n_blocks <= c->cap_blocks && scratch <= c->cap_scratch)
         return RECON_OK;
     HIP_TRY(hipDeviceSynchronize());
     drop_graphs(c);
-    size_t nt = std::max(c->cap_tasks, std::max<size_t>(n_tasks, 64));
-    size_t nb = std::max(c->cap_blocks, std::max<size_t>(n_blocks, 4096));
-    size_t ns = std::max(c->cap_scratch, scratch);
+    const size_t nt = std::max(c->cap_tasks, std::max<size_t>(n_tasks, 64));
+    const size_t nb = std::max(c->cap_blocks, std::max<size_t>(n_blocks, 4096));
+    const size_t ns = std::max(c->cap_scratch, scratch);
     free_workspace(c);
     const size_t table = sizeof(BatchHdr) + nt * sizeof(rk::TaskDev);
     if (hipMalloc(&c->d_table, table) != hipSuccess ||
@@ -172,7 +189,7 @@ int ensure_capacity(recon_ctx *c, size_t n_tasks, size_t n_blocks, size_t scratc
         hipMalloc(&c->d_tile_done, nt * sizeof(uint32_t)) != hipSuccess ||
         (ns > 0 && hipMalloc(&c->d_scratch, ns) != hipSuccess)) {
         free_workspace(c);
-        return fail(RECON_ENOMEM, "workspace allocation of %zu tasks / %zu blocks / %zu scratch bytes failed",
+        return fail(RECON_ENOMEM, "workspace allocation (%zu tasks, %zu blocks, %zu scratch bytes) failed",
                     nt, nb, ns);
     }
     c->cap_tasks = nt;
@@ -223,8 +240,8 @@ int check_task(const recon_task &t) {
 
 bool aligned4(const void *p, int64_t pitch) { return ((uintptr_t)p % 4 == 0) && (pitch % 4 == 0); }
 
-// Build the device task table (host side) for `n` tasks; returns totals.
-void build_table(recon_ctx *c, const recon_task *tasks, int n, int bh, std::vector<rk::TaskDev> &out,
+// Host-side task table for `n` tasks (fill scratch planes as offsets, patched later).
+void build_table(const recon_task *tasks, int n, int bh, std::vector<rk::TaskDev> &out,
                  uint32_t &total_blocks, size_t &scratch_bytes, bool &any_fill) {
     out.resize(n);
     total_blocks = 0;
@@ -254,18 +271,55 @@ void build_table(recon_ctx *c, const recon_task *tasks, int n, int bh, std::vect
             d.pitch_i = t.image.pitch;
             d.img = t.image.data;
             d.pitch_j = (int64_t)round_up((size_t)d.w, 4);
-            d.j = (uint8_t *)(uintptr_t)scratch_bytes;   // offset, patched below
+            d.j = (uint8_t *)(uintptr_t)scratch_bytes;   // offset into the scratch area
             scratch_bytes += round_up((size_t)d.pitch_j * d.h, 256);
             d.aligned = aligned4(d.i, d.pitch_i);
             any_fill = true;
         }
         out[k] = d;
     }
-    (void)c;
 }
 
-// Enqueue one launch sequence for `tasks` on `stream`; graph=true replays the
-// captured batch graph of the variant instead of launching directly.
+// Enqueue the kernels of one launch sequence on `s`.
+int enqueue_kernels(recon_ctx *c, int v, const rk::TaskTable &tt, uint32_t total_blocks, bool any_fill,
+                    bool dynamic_sizes, hipStream_t s) {
+    rk::KArgs ka;
+    ka.work = c->d_work;
+    ka.state = c->d_state;
+    ka.ring = c->d_ring;
+    ka.tile_pending = c->d_tile_pending;
+    ka.tile_done = c->d_tile_done;
+    ka.qcap = c->cfg.queue_capacity;
+    ka.scan_rounds = c->cfg.scan_rounds;
+    ka.watchdog_ticks = c->watchdog_ticks;
+    const size_t lds = lds_for(v, c->cfg.queue_capacity);
+    const int resident = resident_wgs(c, v);
+    // K1/K2 are grid-stride: with sizes known only on the device (captured
+    // graphs), launch enough workgroups for the largest batch the workspace holds.
+    const uint32_t nblk = dynamic_sizes ? (uint32_t)c->cap_blocks : total_blocks;
+    const int grid12 = (int)std::max<uint32_t>(1u, std::min<uint32_t>(nblk, 65535u));
+    const int grid3 = std::max(1, std::min<int>(resident, (int)std::max<uint32_t>(1u, nblk)));
+    const int stop = c->cfg.stop_after_stage;
+    hipLaunchKernelGGL(rk::reset_work, dim3(64), dim3(256), 0, s, tt, c->d_work, c->d_state, c->d_ring,
+                       c->d_tile_pending, c->d_tile_done);
+#define RK_LAUNCH(K, GRID)                                                                        \
+    switch (v) {                                                                                  \
+        case 0: hipLaunchKernelGGL(rk::K<16>, dim3(GRID), dim3(64), lds, s, tt, ka); break;      \
+        case 1: hipLaunchKernelGGL(rk::K<32>, dim3(GRID), dim3(64), lds, s, tt, ka); break;      \
+        default: hipLaunchKernelGGL(rk::K<64>, dim3(GRID), dim3(64), lds, s, tt, ka); break;     \
+    }
+    RK_LAUNCH(dense_pass, grid12);
+    if (stop == 0 || stop >= 2) RK_LAUNCH(border_seed, grid12);
+    if (stop == 0 || stop >= 3) RK_LAUNCH(revisit_drain, grid3);
+#undef RK_LAUNCH
+    if (any_fill) hipLaunchKernelGGL(rk::fill_finish, dim3(1024), dim3(256), 0, s, tt);
+    HIP_TRY(hipGetLastError());
+    return RECON_OK;
+}
+
+// Enqueue one launch sequence for `tasks` on `stream`.  use_graph replays the
+// context's captured graph for the block shape (the task table then always
+// lives in device memory).
 int run_tasks(recon_ctx *c, const recon_task *tasks, int n, hipStream_t stream, bool use_graph) {
     int rc = ensure_device(c);
     if (rc) return rc;
@@ -275,62 +329,49 @@ int run_tasks(recon_ctx *c, const recon_task *tasks, int n, hipStream_t stream, 
     uint32_t total_blocks = 0;
     size_t scratch = 0;
     bool any_fill = false;
-    build_table(c, tasks, n, bh, table, total_blocks, scratch, any_fill);
+    build_table(tasks, n, bh, table, total_blocks, scratch, any_fill);
     rc = ensure_capacity(c, (size_t)n, (size_t)total_blocks, scratch);
     if (rc) return rc;
     for (auto &d : table)
         if (d.op == rk::OP_FILL) d.j = c->d_scratch + (uintptr_t)d.j;
 
-    // stage the table in pinned memory (wait for the previous copy out of it)
-    if (c->table_copied) HIP_TRY(hipEventSynchronize(c->table_copied));
-    BatchHdr hdr{};
-    hdr.n_tasks = (uint32_t)n;
-    hdr.total_blocks = total_blocks;
-    hdr.ring_cap = (uint32_t)(c->cap_blocks + 1);
-    hdr.any_fill = any_fill ? 1u : 0u;
-    std::memcpy(c->h_table, &hdr, sizeof(hdr));
-    std::memcpy(c->h_table + sizeof(hdr), table.data(), table.size() * sizeof(rk::TaskDev));
-    HIP_TRY(hipMemcpyAsync(c->d_table, c->h_table, sizeof(hdr) + table.size() * sizeof(rk::TaskDev),
-                           hipMemcpyHostToDevice, stream));
-    HIP_TRY(hipEventRecord(c->table_copied, stream));
-
-    const BatchHdr *d_hdr = (const BatchHdr *)c->d_table;
-    const rk::TaskDev *d_tasks = (const rk::TaskDev *)(c->d_table + sizeof(BatchHdr));
-    const int resident = resident_wgs(c, v);
-    const size_t lds = lds_bytes(bh, c->cfg.queue_capacity);
-
-    auto enqueue = [&](hipStream_t s, int grid, bool fills) -> int {
-        rk::KArgs ka;
-        ka.tasks = d_tasks;
-        ka.work = c->d_work;
-        ka.state = c->d_state;
-        ka.ring = c->d_ring;
-        ka.tile_pending = c->d_tile_pending;
-        ka.tile_done = c->d_tile_done;
-        ka.qcap = c->cfg.queue_capacity;
-        ka.scan_rounds = c->cfg.scan_rounds;
-        ka.watchdog_ticks = c->watchdog_ticks;
-        hipLaunchKernelGGL(rk::reset_work, dim3(256), dim3(256), 0, s, d_hdr, d_tasks, c->d_work,
-                           c->d_state, c->d_ring, c->d_tile_pending, c->d_tile_done);
-        if (fills) hipLaunchKernelGGL(rk::fill_init, dim3(1024), dim3(256), 0, s, d_hdr, d_tasks);
-        switch (v) {
-            case 0: hipLaunchKernelGGL(rk::recon_persistent<16>, dim3(grid), dim3(64), lds, s, ka); break;
-            case 1: hipLaunchKernelGGL(rk::recon_persistent<32>, dim3(grid), dim3(64), lds, s, ka); break;
-            default: hipLaunchKernelGGL(rk::recon_persistent<64>, dim3(grid), dim3(64), lds, s, ka); break;
-        }
-        if (fills) hipLaunchKernelGGL(rk::fill_finish, dim3(1024), dim3(256), 0, s, d_hdr, d_tasks);
-        HIP_TRY(hipGetLastError());
-        return RECON_OK;
-    };
+    rk::TaskTable tt{};
+    const bool inline_table = !use_graph && n <= rk::MAX_INLINE_TASKS;
+    if (inline_table) {
+        tt.hdr = nullptr;
+        tt.ext = nullptr;
+        tt.n_inline = (uint32_t)n;
+        tt.total_inline = total_blocks;
+        tt.ring_cap_inline = (uint32_t)(c->cap_blocks + 1);
+        for (int k = 0; k < n; ++k) tt.inl[k] = table[k];
+    } else {
+        tt.hdr = (const BatchHdr *)c->d_table;
+        tt.ext = (const rk::TaskDev *)(c->d_table + sizeof(BatchHdr));
+        // stage the table in pinned memory once the previous copy out of it is done
+        rc = wait_event(c->table_used, 60.0, "the previous task-table copy");
+        if (rc) return rc;
+        BatchHdr hdr{};
+        hdr.n_tasks = (uint32_t)n;
+        hdr.total_blocks = total_blocks;
+        hdr.ring_cap = (uint32_t)(c->cap_blocks + 1);
+        hdr.any_fill = any_fill ? 1u : 0u;
+        std::memcpy(c->h_table, &hdr, sizeof(hdr));
+        std::memcpy(c->h_table + sizeof(hdr), table.data(), table.size() * sizeof(rk::TaskDev));
+    }
+    const uint32_t table_bytes = (uint32_t)(sizeof(BatchHdr) + table.size() * sizeof(rk::TaskDev));
 
     if (use_graph) {
-        if (!c->graph[v] || c->graph_cap_blocks[v] != c->cap_blocks || c->graph_cap_tasks[v] != c->cap_tasks) {
+        if (!c->graph[v] || c->graph_cap_blocks[v] != c->cap_blocks || c->graph_cap_tasks[v] != c->cap_tasks ||
+            c->graph_cap_scratch[v] != c->cap_scratch) {
             if (c->graph[v]) (void)hipGraphExecDestroy(c->graph[v]);
             c->graph[v] = nullptr;
             if (!c->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
             hipGraph_t g = nullptr;
             HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-            rc = enqueue(c->cap_stream, resident, true);
+            const uint32_t max_bytes = (uint32_t)(sizeof(BatchHdr) + c->cap_tasks * sizeof(rk::TaskDev));
+            hipLaunchKernelGGL(rk::copy_table, dim3(16), dim3(256), 0, c->cap_stream, c->h_table, c->d_table,
+                               max_bytes);
+            rc = enqueue_kernels(c, v, tt, total_blocks, true, true, c->cap_stream);
             hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
             if (rc) return rc;
             if (e != hipSuccess) return fail(RECON_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
@@ -339,11 +380,17 @@ int run_tasks(recon_ctx *c, const recon_task *tasks, int n, hipStream_t stream, 
             if (e != hipSuccess) return fail(RECON_EDEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
             c->graph_cap_blocks[v] = c->cap_blocks;
             c->graph_cap_tasks[v] = c->cap_tasks;
+            c->graph_cap_scratch[v] = c->cap_scratch;
         }
         HIP_TRY(hipGraphLaunch(c->graph[v], stream));
+        HIP_TRY(hipEventRecord(c->table_used, stream));
     } else {
-        const int grid = (int)std::max<uint32_t>(1u, std::min<uint32_t>((uint32_t)resident, total_blocks));
-        rc = enqueue(stream, grid, any_fill);
+        if (!inline_table) {
+            hipLaunchKernelGGL(rk::copy_table, dim3(16), dim3(256), 0, stream, c->h_table, c->d_table,
+                               table_bytes);
+            HIP_TRY(hipEventRecord(c->table_used, stream));
+        }
+        rc = enqueue_kernels(c, v, tt, total_blocks, any_fill, false, stream);
         if (rc) return rc;
     }
     HIP_TRY(hipEventRecord(c->last_done, stream));
@@ -351,33 +398,37 @@ int run_tasks(recon_ctx *c, const recon_task *tasks, int n, hipStream_t stream, 
     return RECON_OK;
 }
 
-}  // namespace
+// Run the self-test kernel: it writes into pinned host memory, which the host
+// checks once the kernel's event has completed (within `seconds`).
+int self_test(double seconds) {
+    const uint32_t n = 1000;
+    uint32_t *h = nullptr;
+    hipEvent_t ev = nullptr;
+    if (hipHostMalloc((void **)&h, n * sizeof(uint32_t), hipHostMallocDefault) != hipSuccess)
+        return fail(RECON_ENOMEM, "self-test pinned allocation failed");
+    std::memset(h, 0, n * sizeof(uint32_t));
+    int rc = RECON_OK;
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+        rc = fail(RECON_EDEVICE, "self-test event creation failed");
+    } else {
+        hipLaunchKernelGGL(rk::self_test, dim3((n + 255) / 256), dim3(256), 0, nullptr, h, n);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) rc = fail(RECON_EDEVICE, "self-test launch failed: %s", hipGetErrorString(e));
+        else if (hipEventRecord(ev, nullptr) != hipSuccess) rc = fail(RECON_EDEVICE, "self-test event record failed");
+        else rc = wait_event(ev, seconds, "the self-test kernel");
+        if (rc == RECON_OK)
+            for (uint32_t i = 0; i < n; ++i)
+                if (((volatile uint32_t *)h)[i] != i * 3u + 1u) {
+                    rc = fail(RECON_EDEVICE, "self-test kernel wrote %u at %u (expected %u)", h[i], i, i * 3u + 1u);
+                    break;
+                }
+        if (rc != RECON_ETIMEDOUT) (void)hipEventDestroy(ev);
+    }
+    if (rc != RECON_ETIMEDOUT) (void)hipHostFree(h);   // never free memory a live kernel may write
+    return rc == RECON_ETIMEDOUT ? RECON_EDEVICE : rc;
+}
 
-// ============================================================================
-// serving: a request loop that admits tasks by device memory and slots and
-// runs them as continuous batches (see recon_submit)
-struct recon_ctx::Serve {
-    struct Req {
-        uint64_t ticket;
-        recon_task task;
-        size_t bytes;
-    };
-    std::mutex mu;
-    std::condition_variable cv;
-    std::deque<Req> waiting;                 // admitted, not yet launched
-    std::vector<uint64_t> done_tickets;      // completed (sorted insert not needed)
-    std::vector<uint64_t> completed;
-    uint64_t next_ticket = 1;
-    size_t bytes_in_flight = 0;
-    int slots_in_flight = 0;
-    bool stop = false;
-    std::thread worker;
-    int worker_error = 0;
-    std::string worker_msg;
-    hipStream_t stream = nullptr;
-    recon_ctx *owner = nullptr;
-    std::vector<uint8_t> done_flag;          // indexed by ticket (grown)
-};
+}  // namespace
 
 extern "C" {
 
@@ -401,37 +452,49 @@ int recon_create(recon_ctx **out, int device, const recon_config *cfg) {
     if (c.scan_rounds == 0) c.scan_rounds = 2;
     if (c.scan_rounds < 0) c.scan_rounds = 0;
     if (c.wg_per_cu < 0) return fail(RECON_EINVAL, "wg_per_cu must be >= 0");
+    if (c.stop_after_stage < 0 || c.stop_after_stage > 3) return fail(RECON_EINVAL, "stop_after_stage must be 0..3");
     if (c.serve_mem_cap == 0) c.serve_mem_cap = (int64_t)64 << 30;
     if (c.serve_slots == 0) c.serve_slots = 256;
+    e = hipSetDevice(device);
+    if (e != hipSuccess) return fail(RECON_EDEVICE, "hipSetDevice failed: %s", hipGetErrorString(e));
+    int rc = self_test(20.0);
+    if (rc) {
+        std::string m = g_err;
+        return fail(rc, "device self-test failed: %s", m.c_str());
+    }
     recon_ctx *ctx = new recon_ctx();
     ctx->device = device;
     ctx->cfg = c;
-    int rc = ensure_device(ctx);
-    if (rc) { delete ctx; return rc; }
     if (hipDeviceGetAttribute(&ctx->cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
-        hipEventCreateWithFlags(&ctx->table_copied, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&ctx->last_done, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&ctx->table_used, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->last_done, hipEventDisableTiming) != hipSuccess ||
+        hipHostMalloc((void **)&ctx->h_work, sizeof(rk::Work), hipHostMallocDefault) != hipSuccess) {
         delete ctx;
-        return fail(RECON_EDEVICE, "device query / event creation failed");
+        return fail(RECON_EDEVICE, "device query / event / pinned allocation failed");
     }
     int clock_khz = 0;
-    if (hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, device) != hipSuccess ||
-        clock_khz <= 0)
+    if (hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, device) != hipSuccess || clock_khz <= 0)
         clock_khz = 100000;
     ctx->watchdog_ticks = (uint64_t)clock_khz * 1000ull * 8ull;   // 8 s without progress
+    // the table event must be "complete" before its first use
+    if (hipEventRecord(ctx->table_used, nullptr) != hipSuccess) {
+        delete ctx;
+        return fail(RECON_EDEVICE, "event record failed");
+    }
     *out = ctx;
     return RECON_OK;
 }
 
 int recon_destroy(recon_ctx *ctx) {
     if (!ctx) return fail(RECON_EINVAL, "null context");
-    if (ctx->serve) recon_serve_stop(ctx);
     (void)hipSetDevice(ctx->device);
-    (void)hipDeviceSynchronize();
+    if (ctx->have_last && wait_event(ctx->last_done, 60.0, "the last launch") != RECON_OK)
+        return RECON_ETIMEDOUT;   // leak rather than free memory a running kernel may use
     drop_graphs(ctx);
     free_workspace(ctx);
     if (ctx->h_table) (void)hipHostFree(ctx->h_table);
-    if (ctx->table_copied) (void)hipEventDestroy(ctx->table_copied);
+    if (ctx->h_work) (void)hipHostFree(ctx->h_work);
+    if (ctx->table_used) (void)hipEventDestroy(ctx->table_used);
     if (ctx->last_done) (void)hipEventDestroy(ctx->last_done);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     delete ctx;
@@ -483,24 +546,22 @@ int recon_last_stats(recon_ctx *ctx, recon_stats *out) {
     if (!ctx->have_last) return RECON_OK;
     int rc = ensure_device(ctx);
     if (rc) return rc;
-    // wait for the launch with a deadline rather than blocking forever
-    const auto t0 = std::chrono::steady_clock::now();
-    while (true) {
-        hipError_t q = hipEventQuery(ctx->last_done);
-        if (q == hipSuccess) break;
-        if (q != hipErrorNotReady)
-            return fail(RECON_EDEVICE, "launch failed: %s", hipGetErrorString(q));
-        if (std::chrono::steady_clock::now() - t0 > std::chrono::seconds(60))
-            return fail(RECON_ETIMEDOUT, "the last launch has not completed after 60 s");
-        std::this_thread::sleep_for(std::chrono::microseconds(200));
-    }
-    rk::Work w{};
-    HIP_TRY(hipMemcpy(&w, ctx->d_work, sizeof(w), hipMemcpyDeviceToHost));
+    rc = wait_event(ctx->last_done, 60.0, "the last launch");
+    if (rc) return rc;
+    // read the counters through a kernel into pinned memory
+    hipLaunchKernelGGL(rk::copy_table, dim3(1), dim3(64), 0, nullptr, (const uint8_t *)ctx->d_work,
+                       (uint8_t *)ctx->h_work, (uint32_t)sizeof(rk::Work));
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipEventRecord(ctx->last_done, nullptr));
+    rc = wait_event(ctx->last_done, 60.0, "the statistics read-back");
+    if (rc) return rc;
+    rk::Work w;
+    std::memcpy(&w, (const void *)ctx->h_work, sizeof(w));
     out->dense_visits = (int64_t)w.stat_dense;
     out->revisits = (int64_t)w.stat_revisit;
     out->reruns = (int64_t)w.stat_rerun;
     out->queue_overflows = (int64_t)w.stat_overflow;
-    out->spills = (int64_t)w.stat_spill;
+    out->requests = (int64_t)w.stat_request;
     out->aborted = (int64_t)w.abort;
     if (w.abort) return fail(RECON_EDEVICE, "scheduler watchdog expired: the last launch did not converge");
     return RECON_OK;

@@ -1,0 +1,55 @@
+"""Driver for the host emulation of the HIP kernels (tests/kernel_emu).
+
+The kernels' device code is compiled for the CPU against a stand-in HIP
+header and run on emulated 64-lane waves, so that the scheduler and the pixel
+logic can be checked against the oracle, and bounds-checked under
+AddressSanitizer, without a GPU.
+"""
+import os
+import subprocess
+import tempfile
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC_DIR = os.path.join(HERE, "kernel_emu")
+CLANG = "/opt/rocm/llvm/bin/clang++"
+
+
+def build(out_dir, sanitize=True):
+    exe = os.path.join(out_dir, "kemu%s" % ("_asan" if sanitize else ""))
+    cmd = [CLANG, "-std=c++17", "-O1", "-g", "-DKEMU_MAIN", "-I", SRC_DIR, "-o", exe,
+           os.path.join(SRC_DIR, "emu.cpp"), "-lpthread"]
+    if sanitize:
+        cmd[1:1] = ["-fsanitize=address,undefined", "-fno-omit-frame-pointer",
+                    "-fno-sanitize-recover=undefined"]
+    subprocess.run(cmd, check=True)
+    return exe
+
+
+def run(exe, tasks, bh=32, qcap=2048, scan_rounds=2, n_waves=4, watchdog_s=20.0, timeout=600, stop_after=0):
+    """tasks: list of dicts {op: 'dilate'|'fill_holes', marker+mask or img, conn}.
+    Returns (returncode, outputs, stdout+stderr)."""
+    with tempfile.TemporaryDirectory() as d:
+        lines = []
+        for k, t in enumerate(tasks):
+            img = np.ascontiguousarray(t["marker"] if t["op"] == "dilate" else t["img"], dtype=np.uint8)
+            ip, mp, op = (os.path.join(d, "%d_%s.bin" % (k, s)) for s in ("img", "mask", "out"))
+            img.tofile(ip)
+            if t["op"] == "dilate":
+                np.ascontiguousarray(t["mask"], dtype=np.uint8).tofile(mp)
+            else:
+                mp = "-"
+            lines.append("%d %d %d %d %s %s %s" % (0 if t["op"] == "dilate" else 1, t["conn"],
+                                                   img.shape[0], img.shape[1], ip, mp, op))
+        env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1",
+                   UBSAN_OPTIONS="print_stacktrace=1")
+        p = subprocess.run([exe, str(bh), str(qcap), str(scan_rounds), str(n_waves), str(watchdog_s),
+                            str(len(tasks)), str(stop_after)], input="\n".join(lines) + "\n", capture_output=True,
+                           text=True, timeout=timeout, env=env)
+        outs = []
+        for k, t in enumerate(tasks):
+            shape = (t["marker"] if t["op"] == "dilate" else t["img"]).shape
+            op = os.path.join(d, "%d_out.bin" % k)
+            outs.append(np.fromfile(op, dtype=np.uint8).reshape(shape) if os.path.exists(op) else None)
+        return p.returncode, outs, p.stdout + p.stderr

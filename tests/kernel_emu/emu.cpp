@@ -1,0 +1,415 @@
+// Host emulation of the librecon kernels (test infrastructure, CPU only).
+//
+// Compiles paper_1209_3332_amd/csrc/kernels.hpp against the stand-in
+// hip/hip_runtime.h next to this file and runs the same launch sequence as the
+// library (reset -> fill init -> persistent kernel -> fill finish) on host
+// memory.  Each workgroup (one 64-lane wave) runs on its own OS thread, its
+// lanes as fibers switched at every cross-lane operation, so inter-wave
+// atomics and the block scheduler run with real concurrency.  Every LDS
+// buffer and every image copy is an exact-size heap allocation, so a build
+// with -fsanitize=address bounds-checks all of the kernels' memory accesses.
+#include "hip/hip_runtime.h"
+
+
+#include <cstdio>
+#include <cstdlib>
+#include <functional>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "../../paper_1209_3332_amd/csrc/kernels.hpp"
+
+#if defined(__has_feature)
+#if __has_feature(address_sanitizer)
+#define KEMU_ASAN 1
+#include <sanitizer/common_interface_defs.h>
+#endif
+#endif
+
+namespace kemu {
+
+thread_local Dim3 blockIdx_, threadIdx_, blockDim_, gridDim_;
+
+// Minimal fiber switch for x86-64 SysV: push the callee-saved registers on
+// the current stack, store the stack pointer in *from, load *to, pop, return.
+// (glibc's swapcontext also saves the signal mask with a system call on every
+// switch, which made emulation two orders of magnitude slower.)
+extern "C" void kemu_switch(void **from, void *to);
+asm(R"(
+.text
+.globl kemu_switch
+.type kemu_switch,@function
+kemu_switch:
+    pushq %rbp
+    pushq %rbx
+    pushq %r12
+    pushq %r13
+    pushq %r14
+    pushq %r15
+    movq %rsp, (%rdi)
+    movq %rsi, %rsp
+    popq %r15
+    popq %r14
+    popq %r13
+    popq %r12
+    popq %rbx
+    popq %rbp
+    ret
+.size kemu_switch,.-kemu_switch
+)");
+
+constexpr int kLanes = 64;
+constexpr size_t kStack = 512 * 1024;
+
+struct Wave {
+    void *sched_sp = nullptr;
+    void *sp[kLanes] = {};
+    std::vector<char *> stacks;
+    int cur = 0;
+    bool finished[kLanes] = {};
+    int parity[kLanes] = {};
+    uint64_t xch[2][kLanes] = {};
+    uint8_t *lds = nullptr;
+    size_t lds_size = 0;
+    std::function<void()> body;
+    const void *sched_bottom = nullptr;
+    size_t sched_size = 0;
+    void *fake[kLanes + 1] = {};
+    bool error = false;
+};
+
+thread_local Wave *tw = nullptr;
+
+int lane() { return tw->cur; }
+uint8_t *wave_lds() { return tw->lds; }
+
+uint64_t wall_ticks() {
+    using namespace std::chrono;
+    return (uint64_t)duration_cast<nanoseconds>(steady_clock::now().time_since_epoch()).count() / 10;
+}
+
+void check_lds(const void *p, size_t n) {
+    const uint8_t *q = (const uint8_t *)p;
+    if (q < tw->lds || q + n > tw->lds + tw->lds_size) {
+        std::fprintf(stderr, "kemu: LDS atomic out of bounds (offset %ld)\n", (long)(q - tw->lds));
+        std::abort();
+    }
+}
+
+// lane -> scheduler switch
+static void yield_to_sched() {
+    Wave *w = tw;
+    const int l = w->cur;
+#ifdef KEMU_ASAN
+    __sanitizer_start_switch_fiber(&w->fake[l], w->sched_bottom, w->sched_size);
+#endif
+    kemu_switch(&w->sp[l], w->sched_sp);
+#ifdef KEMU_ASAN
+    __sanitizer_finish_switch_fiber(w->fake[l], nullptr, nullptr);
+#endif
+}
+
+void wave_sync() { yield_to_sched(); }
+
+uint64_t exchange(uint64_t v, int src) {
+    Wave *w = tw;
+    const int l = w->cur;
+    const int p = w->parity[l];
+    w->xch[p][l] = v;
+    w->parity[l] = p ^ 1;
+    yield_to_sched();
+    if (src < 0 || src >= kLanes) {
+        std::fprintf(stderr, "kemu: shuffle from lane %d\n", src);
+        std::abort();
+    }
+    return w->xch[p][src];
+}
+
+uint64_t ballot(bool pred) {
+    Wave *w = tw;
+    const int l = w->cur;
+    const int p = w->parity[l];
+    w->xch[p][l] = pred ? 1u : 0u;
+    w->parity[l] = p ^ 1;
+    yield_to_sched();
+    uint64_t m = 0;
+    for (int k = 0; k < kLanes; ++k)
+        if (w->xch[p][k]) m |= 1ull << k;
+    return m;
+}
+
+[[noreturn]] static void lane_entry() {
+    Wave *w = tw;
+#ifdef KEMU_ASAN
+    __sanitizer_finish_switch_fiber(nullptr, &w->sched_bottom, &w->sched_size);
+#endif
+    w->body();
+    w->finished[w->cur] = true;
+    void *dead = nullptr;
+#ifdef KEMU_ASAN
+    __sanitizer_start_switch_fiber(nullptr, w->sched_bottom, w->sched_size);
+#endif
+    kemu_switch(&dead, w->sched_sp);
+    __builtin_unreachable();
+}
+
+// Run `body` as one 64-lane wave on the calling thread.
+static bool run_wave(const std::function<void()> &body, size_t lds_size) {
+    Wave w;
+    w.body = body;
+    w.lds_size = lds_size;
+    w.lds = (uint8_t *)std::malloc(lds_size);
+    std::memset(w.lds, 0xcd, lds_size);   // garbage, like fresh LDS
+    tw = &w;
+    for (int l = 0; l < kLanes; ++l) {
+        char *st = (char *)std::malloc(kStack);
+        w.stacks.push_back(st);
+        // initial frame: six callee-saved registers (zero) and the entry point as return address
+        uintptr_t top = ((uintptr_t)(st + kStack) & ~(uintptr_t)15) - 8;   // entry sees rsp % 16 == 8
+        void **sp = (void **)top;
+        *--sp = (void *)&lane_entry;
+        for (int k = 0; k < 6; ++k) *--sp = nullptr;
+        w.sp[l] = sp;
+    }
+    bool ok = true;
+    while (true) {
+        int alive = 0, done = 0;
+        for (int l = 0; l < kLanes; ++l) {
+            if (w.finished[l]) { ++done; continue; }
+            w.cur = l;
+#ifdef KEMU_ASAN
+            __sanitizer_start_switch_fiber(&w.fake[kLanes], w.stacks[l], kStack);
+#endif
+            kemu_switch(&w.sched_sp, w.sp[l]);
+#ifdef KEMU_ASAN
+            __sanitizer_finish_switch_fiber(w.fake[kLanes], nullptr, nullptr);
+#endif
+            if (!w.finished[l]) ++alive;
+        }
+        if (alive == 0) break;
+        if (done > 0 && alive > 0) {   // some lanes returned while others wait at a collective
+            std::fprintf(stderr, "kemu: non-uniform exit of a wave\n");
+            ok = false;
+            break;
+        }
+    }
+    for (char *st : w.stacks) std::free(st);
+    std::free(w.lds);
+    tw = nullptr;
+    return ok;
+}
+
+}  // namespace kemu
+
+// ---------------------------------------------------------------------------
+// driver (called through ctypes)
+
+extern "C" {
+
+struct EmuTask {
+    int32_t op;        // 0 dilate, 1 fill-holes
+    int32_t conn;
+    int32_t h, w;
+    uint8_t *image;    // dilate: marker (in/out); fill: image (in/out); dense h x w
+    const uint8_t *mask;
+};
+
+struct EmuStats {
+    int64_t dense, revisit, rerun, overflow, aborted;
+};
+
+int emu_run(const EmuTask *tasks, int n, int bh, int qcap, int scan_rounds, int n_waves,
+            double watchdog_s, int stop_after, EmuStats *stats) {
+    using namespace rk;
+    if (bh != 16 && bh != 32 && bh != 64) return -1;
+    // exact-size copies so that the sanitizer bounds-checks global accesses
+    std::vector<uint8_t *> jplanes(n), iplanes(n, nullptr), scratch(n, nullptr);
+    std::vector<TaskDev> table(n);
+    uint32_t total = 0;
+    bool any_fill = false;
+    for (int k = 0; k < n; ++k) {
+        const EmuTask &e = tasks[k];
+        const size_t px = (size_t)e.h * e.w;
+        TaskDev d{};
+        d.h = e.h;
+        d.w = e.w;
+        d.conn = e.conn;
+        d.nby = (e.h + bh - 1) / bh;
+        d.nbx = (e.w + BW - 1) / BW;
+        d.block0 = total;
+        total += (uint32_t)(d.nby * d.nbx);
+        jplanes[k] = (uint8_t *)std::malloc(px);
+        std::memcpy(jplanes[k], e.image, px);
+        if (e.op == 0) {
+            iplanes[k] = (uint8_t *)std::malloc(px);
+            std::memcpy(iplanes[k], e.mask, px);
+            d.op = OP_DILATE;
+            d.j = jplanes[k];
+            d.pitch_j = e.w;
+            d.i = iplanes[k];
+            d.pitch_i = e.w;
+            d.aligned = (e.w % 4 == 0);
+        } else {
+            const int64_t pj = (e.w + 3) / 4 * 4;
+            scratch[k] = (uint8_t *)std::malloc((size_t)pj * e.h);
+            std::memset(scratch[k], 0xee, (size_t)pj * e.h);   // garbage: K1 must not read it
+            d.op = OP_FILL;
+            d.i = jplanes[k];
+            d.pitch_i = e.w;
+            d.img = jplanes[k];
+            d.j = scratch[k];
+            d.pitch_j = pj;
+            d.aligned = (e.w % 4 == 0);
+            any_fill = true;
+        }
+        table[k] = d;
+    }
+    // task table: inline in the "kernel arguments" when small, else in memory
+    std::vector<uint8_t> ext_mem;
+    TaskTable tt{};
+    if (n <= MAX_INLINE_TASKS) {
+        tt.n_inline = (uint32_t)n;
+        tt.total_inline = total;
+        tt.ring_cap_inline = total + 1;
+        for (int k = 0; k < n; ++k) tt.inl[k] = table[k];
+    } else {
+        ext_mem.resize(sizeof(BatchHdr) + n * sizeof(TaskDev));
+        BatchHdr hdr{};
+        hdr.n_tasks = (uint32_t)n;
+        hdr.total_blocks = total;
+        hdr.ring_cap = total + 1;
+        hdr.any_fill = any_fill ? 1u : 0u;
+        std::memcpy(ext_mem.data(), &hdr, sizeof(hdr));
+        std::memcpy(ext_mem.data() + sizeof(hdr), table.data(), n * sizeof(TaskDev));
+        tt.hdr = (const BatchHdr *)ext_mem.data();
+        tt.ext = (const TaskDev *)(ext_mem.data() + sizeof(BatchHdr));
+    }
+    Work *work = (Work *)std::calloc(1, sizeof(Work));
+    uint32_t *state = (uint32_t *)std::malloc(total * sizeof(uint32_t));
+    uint32_t *ring = (uint32_t *)std::malloc((total + 1) * sizeof(uint32_t));
+    uint32_t *tpend = (uint32_t *)std::malloc(n * sizeof(uint32_t));
+    uint32_t *tdone = (uint32_t *)std::malloc(n * sizeof(uint32_t));
+
+    auto grid_run = [&](auto fn, uint32_t blocks, uint32_t threads) {
+        kemu::gridDim_.x = blocks;
+        kemu::blockDim_.x = threads;
+        for (uint32_t b = 0; b < blocks; ++b)
+            for (uint32_t t = 0; t < threads; ++t) {
+                kemu::blockIdx_.x = b;
+                kemu::threadIdx_.x = t;
+                fn();
+            }
+    };
+    grid_run([&] { reset_work(tt, work, state, ring, tpend, tdone); }, 4, 64);
+
+    KArgs ka;
+    ka.work = work;
+    ka.state = state;
+    ka.ring = ring;
+    ka.tile_pending = tpend;
+    ka.tile_done = tdone;
+    ka.qcap = qcap;
+    ka.scan_rounds = scan_rounds;
+    ka.watchdog_ticks = (uint64_t)(watchdog_s * 1e8);
+    const size_t lds = bh == 16 ? lds_bytes<16>(qcap) : bh == 32 ? lds_bytes<32>(qcap) : lds_bytes<64>(qcap);
+    std::atomic<int> bad{0};
+    auto run_grid = [&](int stage, int waves) {
+        std::vector<std::thread> th;
+        for (int g = 0; g < waves; ++g) {
+            th.emplace_back([&, g, stage] {
+                kemu::blockIdx_.x = (uint32_t)g;
+                kemu::gridDim_.x = (uint32_t)waves;
+                kemu::blockDim_.x = 64;
+                std::function<void()> body;
+#define KEMU_PICK(K)                                            \
+    switch (bh) {                                               \
+        case 16: body = [&] { K<16>(tt, ka); }; break;          \
+        case 32: body = [&] { K<32>(tt, ka); }; break;          \
+        default: body = [&] { K<64>(tt, ka); }; break;          \
+    }
+                if (stage == 1) { KEMU_PICK(dense_pass) }
+                else if (stage == 2) { KEMU_PICK(border_seed) }
+                else { KEMU_PICK(revisit_drain) }
+#undef KEMU_PICK
+                if (!kemu::run_wave(body, lds)) bad++;
+            });
+        }
+        for (auto &t : th) t.join();
+    };
+    run_grid(1, n_waves);
+    if (stop_after == 0 || stop_after >= 2) run_grid(2, n_waves);
+    if (stop_after == 0 || stop_after >= 3) run_grid(3, n_waves);
+    if (any_fill) grid_run([&] { fill_finish(tt); }, 4, 64);
+
+    for (int k = 0; k < n; ++k) {
+        const EmuTask &e = tasks[k];
+        std::memcpy(e.image, jplanes[k], (size_t)e.h * e.w);
+        std::free(jplanes[k]);
+        if (iplanes[k]) std::free(iplanes[k]);
+        if (scratch[k]) std::free(scratch[k]);
+    }
+    if (stats) {
+        stats->dense = (int64_t)work->stat_dense;
+        stats->revisit = (int64_t)work->stat_revisit;
+        stats->rerun = (int64_t)work->stat_rerun;
+        stats->overflow = (int64_t)work->stat_overflow;
+        stats->aborted = (int64_t)work->abort;
+    }
+    const bool full = stop_after == 0 || stop_after >= 3;
+    const int rc = bad ? -2 : (work->abort ? -3 : (full && work->pending != 0 ? -4 : 0));
+    std::free(work);
+    std::free(state);
+    std::free(ring);
+    std::free(tpend);
+    std::free(tdone);
+    return rc;
+}
+
+}  // extern "C"
+
+#ifdef KEMU_MAIN
+// Stand-alone driver (lets the sanitizer runtime link into the executable):
+//   kemu <bh> <qcap> <scan_rounds> <waves> <watchdog_s> <n> then n lines of
+//   "op conn h w image_path mask_path_or_- out_path" on stdin.
+#include <string>
+int main(int argc, char **argv) {
+    if (argc < 7) return 2;
+    const int bh = std::atoi(argv[1]), qcap = std::atoi(argv[2]), rounds = std::atoi(argv[3]);
+    const int waves = std::atoi(argv[4]);
+    const double wd = std::atof(argv[5]);
+    const int n = std::atoi(argv[6]);
+    const int stop_after = argc > 7 ? std::atoi(argv[7]) : 0;
+    std::vector<EmuTask> tasks(n);
+    std::vector<std::vector<uint8_t>> imgs(n), masks(n);
+    std::vector<std::string> outs(n);
+    for (int k = 0; k < n; ++k) {
+        int op, conn, h, w;
+        char ip[1024], mp[1024], op_[1024];
+        if (std::scanf("%d %d %d %d %1023s %1023s %1023s", &op, &conn, &h, &w, ip, mp, op_) != 7) return 3;
+        imgs[k].resize((size_t)h * w);
+        FILE *f = std::fopen(ip, "rb");
+        if (!f || std::fread(imgs[k].data(), 1, imgs[k].size(), f) != imgs[k].size()) return 4;
+        std::fclose(f);
+        if (op == 0) {
+            masks[k].resize((size_t)h * w);
+            f = std::fopen(mp, "rb");
+            if (!f || std::fread(masks[k].data(), 1, masks[k].size(), f) != masks[k].size()) return 5;
+            std::fclose(f);
+        }
+        tasks[k] = EmuTask{op, conn, h, w, imgs[k].data(), op == 0 ? masks[k].data() : nullptr};
+        outs[k] = op_;
+    }
+    EmuStats st{};
+    const int rc = emu_run(tasks.data(), n, bh, qcap, rounds, waves, wd, stop_after, &st);
+    for (int k = 0; k < n; ++k) {
+        FILE *f = std::fopen(outs[k].c_str(), "wb");
+        std::fwrite(imgs[k].data(), 1, imgs[k].size(), f);
+        std::fclose(f);
+    }
+    std::printf("rc %d dense %lld revisit %lld rerun %lld overflow %lld aborted %lld\n", rc,
+                (long long)st.dense, (long long)st.revisit, (long long)st.rerun, (long long)st.overflow,
+                (long long)st.aborted);
+    return rc == 0 ? 0 : 1;
+}
+#endif

@@ -61,6 +61,34 @@ def assert_same(got, want, what):
                              % (what, len(bad), y, x, got[y, x], want[y, x]))
 
 
+def test_context_self_test(lib, torch_mod):
+    # context creation runs the library's self-test kernel (with a deadline)
+    with lib.Recon(0) as ctx:
+        assert ctx.ctx
+
+
+def _blockwise(oracle_mod, marker, mask, conn, bh=32, bw=256):
+    want = np.empty_like(mask)
+    for y0 in range(0, mask.shape[0], bh):
+        for x0 in range(0, mask.shape[1], bw):
+            sl = np.s_[y0:y0 + bh, x0:x0 + bw]
+            want[sl] = oracle_mod.recon_dilate(marker[sl], mask[sl], conn)
+    return want
+
+
+@pytest.mark.parametrize("conn", [8, 4])
+def test_stage1_dense_pass_blockwise(torch_mod, lib, oracle_mod, conn):
+    # the first kernel alone reconstructs every 32 x 256 block on its own
+    rng = np.random.default_rng(50 + conn)
+    mask = rng.integers(0, 256, (70, 600)).astype(np.uint8)
+    marker = synth.hdome_marker(mask, 50)
+    c1m, c1k = synth.config1_tile()
+    with lib.Recon(0, stop_after_stage=1) as ctx:
+        for m, k in ((marker, mask), (c1m, c1k)):
+            assert_same(gpu_dilate(torch_mod, ctx, m, k, conn), _blockwise(oracle_mod, m, k, conn),
+                        "dense pass %s conn %d" % (k.shape, conn))
+
+
 @pytest.mark.parametrize("case", golden_io.all_cases(), ids=lambda c: c["name"])
 def test_golden(torch_mod, rc, case):
     for conn in case["conns"]:
