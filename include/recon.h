@@ -96,7 +96,9 @@ typedef struct {
     int32_t stop_after_stage;  /* test hook: 0 = full pipeline; 1 = stop after the dense
                                   per-block pass (each block reconstructed on its own);
                                   2 = also seed the border requests, but do not drain them */
-    int32_t reserved[4];
+    int32_t timing;            /* 1: record HIP events between the kernels of each launch so
+                                  that recon_last_stats reports per-kernel durations */
+    int32_t reserved[3];
 } recon_config;
 
 /* Per-call statistics of the last completed launch (for tests and tuning). */
@@ -107,6 +109,9 @@ typedef struct {
     int64_t queue_overflows;   /* LDS queue overflows (each followed by a re-seed pass) */
     int64_t requests;          /* block revisits requested by border checks */
     int64_t aborted;           /* 1 if the scheduler watchdog stopped the launch */
+    /* with recon_config.timing: durations in ms of the dense pass (K1), the border
+       seeding (K2), the revisit drain (K3) and the whole launch; else 0 */
+    float dense_ms, seed_ms, drain_ms, total_ms;
 } recon_stats;
 
 /* Create a context on HIP device `device`.  cfg may be NULL.  Runs a small

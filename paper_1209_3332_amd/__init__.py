@@ -58,13 +58,16 @@ class recon_config(ctypes.Structure):
     _fields_ = [("block_rows", ctypes.c_int32), ("queue_capacity", ctypes.c_int32),
                 ("scan_rounds", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32),
                 ("serve_mem_cap", ctypes.c_int64), ("serve_slots", ctypes.c_int32),
-                ("stop_after_stage", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+                ("stop_after_stage", ctypes.c_int32), ("timing", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 3)]
 
 
 class recon_stats(ctypes.Structure):
     _fields_ = [("dense_visits", ctypes.c_int64), ("revisits", ctypes.c_int64),
                 ("reruns", ctypes.c_int64), ("queue_overflows", ctypes.c_int64),
-                ("requests", ctypes.c_int64), ("aborted", ctypes.c_int64)]
+                ("requests", ctypes.c_int64), ("aborted", ctypes.c_int64),
+                ("dense_ms", ctypes.c_float), ("seed_ms", ctypes.c_float), ("drain_ms", ctypes.c_float),
+                ("total_ms", ctypes.c_float)]
 
 
 _lib = None

@@ -116,6 +116,7 @@ struct recon_ctx {
     rk::Work *h_work = nullptr;
     hipEvent_t table_used = nullptr;  // the last copy out of h_table has finished
     hipEvent_t last_done = nullptr;
+    hipEvent_t tev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};   // timing marks
     bool have_last = false;
     int resident[kVariants] = {0, 0, 0};
     // captured batch graphs per variant
@@ -300,8 +301,10 @@ int enqueue_kernels(recon_ctx *c, int v, const rk::TaskTable &tt, uint32_t total
     const int grid12 = (int)std::max<uint32_t>(1u, std::min<uint32_t>(nblk, 65535u));
     const int grid3 = std::max(1, std::min<int>(resident, (int)std::max<uint32_t>(1u, nblk)));
     const int stop = c->cfg.stop_after_stage;
+    const bool timing = c->cfg.timing != 0;
     hipLaunchKernelGGL(rk::reset_work, dim3(64), dim3(256), 0, s, tt, c->d_work, c->d_state, c->d_ring,
                        c->d_tile_pending, c->d_tile_done);
+    if (timing) HIP_TRY(hipEventRecord(c->tev[0], s));
 #define RK_LAUNCH(K, GRID)                                                                        \
     switch (v) {                                                                                  \
         case 0: hipLaunchKernelGGL(rk::K<16>, dim3(GRID), dim3(64), lds, s, tt, ka); break;      \
@@ -309,10 +312,14 @@ int enqueue_kernels(recon_ctx *c, int v, const rk::TaskTable &tt, uint32_t total
         default: hipLaunchKernelGGL(rk::K<64>, dim3(GRID), dim3(64), lds, s, tt, ka); break;     \
     }
     RK_LAUNCH(dense_pass, grid12);
+    if (timing) HIP_TRY(hipEventRecord(c->tev[1], s));
     if (stop == 0 || stop >= 2) RK_LAUNCH(border_seed, grid12);
+    if (timing) HIP_TRY(hipEventRecord(c->tev[2], s));
     if (stop == 0 || stop >= 3) RK_LAUNCH(revisit_drain, grid3);
+    if (timing) HIP_TRY(hipEventRecord(c->tev[3], s));
 #undef RK_LAUNCH
     if (any_fill) hipLaunchKernelGGL(rk::fill_finish, dim3(1024), dim3(256), 0, s, tt);
+    if (timing) HIP_TRY(hipEventRecord(c->tev[4], s));
     HIP_TRY(hipGetLastError());
     return RECON_OK;
 }
@@ -472,6 +479,12 @@ int recon_create(recon_ctx **out, int device, const recon_config *cfg) {
         delete ctx;
         return fail(RECON_EDEVICE, "device query / event / pinned allocation failed");
     }
+    if (c.timing)
+        for (auto &ev : ctx->tev)
+            if (hipEventCreate(&ev) != hipSuccess) {
+                delete ctx;
+                return fail(RECON_EDEVICE, "timing event creation failed");
+            }
     int clock_khz = 0;
     if (hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, device) != hipSuccess || clock_khz <= 0)
         clock_khz = 100000;
@@ -496,6 +509,8 @@ int recon_destroy(recon_ctx *ctx) {
     if (ctx->h_work) (void)hipHostFree(ctx->h_work);
     if (ctx->table_used) (void)hipEventDestroy(ctx->table_used);
     if (ctx->last_done) (void)hipEventDestroy(ctx->last_done);
+    for (auto &ev : ctx->tev)
+        if (ev) (void)hipEventDestroy(ev);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     delete ctx;
     return RECON_OK;
@@ -563,6 +578,13 @@ int recon_last_stats(recon_ctx *ctx, recon_stats *out) {
     out->queue_overflows = (int64_t)w.stat_overflow;
     out->requests = (int64_t)w.stat_request;
     out->aborted = (int64_t)w.abort;
+    if (ctx->cfg.timing) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, ctx->tev[0], ctx->tev[1]) == hipSuccess) out->dense_ms = ms;
+        if (hipEventElapsedTime(&ms, ctx->tev[1], ctx->tev[2]) == hipSuccess) out->seed_ms = ms;
+        if (hipEventElapsedTime(&ms, ctx->tev[2], ctx->tev[3]) == hipSuccess) out->drain_ms = ms;
+        if (hipEventElapsedTime(&ms, ctx->tev[0], ctx->tev[4]) == hipSuccess) out->total_ms = ms;
+    }
     if (w.abort) return fail(RECON_EDEVICE, "scheduler watchdog expired: the last launch did not converge");
     return RECON_OK;
 }
