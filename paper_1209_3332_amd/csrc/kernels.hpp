@@ -191,6 +191,18 @@ __device__ __forceinline__ uint32_t diff_bytes(uint32_t a, uint32_t b) {
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
+// Whole-wave shifts by one lane through DPP (a single VALU operation):
+// from_lower(v) gives lane i the value of lane i-1 (lane 0 gets 0);
+// from_upper(v) gives lane i the value of lane i+1 (lane 63 gets 0).
+constexpr int DPP_WAVE_SHL1 = 0x130;
+constexpr int DPP_WAVE_SHR1 = 0x138;
+__device__ __forceinline__ uint32_t from_lower(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, DPP_WAVE_SHR1, 0xf, 0xf, true);
+}
+__device__ __forceinline__ uint32_t from_upper(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, DPP_WAVE_SHL1, 0xf, 0xf, true);
+}
+
 __device__ __forceinline__ uint32_t prefix_count(unsigned long long mask) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
                                      __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
@@ -375,8 +387,8 @@ template <int BH>
 __device__ __forceinline__ void side_bytes(Lds<BH> &L, int y, uint32_t v, uint32_t &left,
                                            uint32_t &right) {
     const int ln = lane_id();
-    const uint32_t up = __shfl_up(v, 1);
-    const uint32_t dn = __shfl_down(v, 1);
+    const uint32_t up = from_lower(v);
+    const uint32_t dn = from_upper(v);
     left = ln == 0 ? (uint32_t)L.Jb(y, -1) : (up >> 24);
     right = ln == LANES - 1 ? (uint32_t)L.Jb(y, BW) : (dn & 0xffu);
 }
@@ -428,8 +440,8 @@ __device__ bool hpass(Lds<BH> &L, int conn, int dir) {
             const int x = 4 * d + j;
             uint32_t m = max(byte_of(cur, j), prev);
             if (conn == 8) {
-                uint32_t up = __shfl_up(prev, 1);
-                uint32_t dn = __shfl_down(prev, 1);
+                uint32_t up = from_lower(prev);
+                uint32_t dn = from_upper(prev);
                 const int xs = x - dir;   // column the diagonal neighbours sit in
                 if (ln == 0) up = L.Jb(-1, xs);
                 if (ln == BH - 1) dn = L.Jb(BH, xs);
@@ -634,7 +646,7 @@ __device__ bool check_neighbours(const KArgs &a, uint32_t ring_cap, int ti, cons
             const uint32_t c = *L.Jw(r, ln);
             uint32_t out = c;
             if (conn == 8) {
-                const uint32_t up = __shfl_up(c, 1), dn = __shfl_down(c, 1);
+                const uint32_t up = from_lower(c), dn = from_upper(c);
                 const uint32_t l = ln == 0 ? 0u : (up >> 24);          // our pixel x-1 (none at x=0)
                 const uint32_t rr = ln == LANES - 1 ? 0u : (dn & 0xffu);
                 out = bmax4(out, bmax4((c << 8) | l, (c >> 8) | (rr << 24)));
@@ -948,10 +960,18 @@ __global__ void fill_finish(TaskTable tt) {
     }
 }
 
-// Self-test: out[i] = 3 i + 1 for i < n (checks that this code object runs).
+// Self-test (checks that this code object runs and that the one-lane DPP
+// shifts move data the way the kernels assume):
+//   out[i] = 3 i + 1,  out[n + i] = from_lower(i + 100),  out[2n + i] = from_upper(i + 100)
+// for i < n, with n a multiple of the block size (all lanes active).
 __global__ void self_test(uint32_t *out, uint32_t n) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) out[i] = i * 3u + 1u;
+    const uint32_t lo = from_lower(i + 100u), hi = from_upper(i + 100u);
+    if (i < n) {
+        out[i] = i * 3u + 1u;
+        out[n + i] = lo;
+        out[2 * n + i] = hi;
+    }
 }
 
 }  // namespace rk

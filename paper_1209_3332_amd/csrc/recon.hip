@@ -408,12 +408,12 @@ int run_tasks(recon_ctx *c, const recon_task *tasks, int n, hipStream_t stream, 
 // Run the self-test kernel: it writes into pinned host memory, which the host
 // checks once the kernel's event has completed (within `seconds`).
 int self_test(double seconds) {
-    const uint32_t n = 1000;
+    const uint32_t n = 1024;
     uint32_t *h = nullptr;
     hipEvent_t ev = nullptr;
-    if (hipHostMalloc((void **)&h, n * sizeof(uint32_t), hipHostMallocDefault) != hipSuccess)
+    if (hipHostMalloc((void **)&h, 3 * n * sizeof(uint32_t), hipHostMallocDefault) != hipSuccess)
         return fail(RECON_ENOMEM, "self-test pinned allocation failed");
-    std::memset(h, 0, n * sizeof(uint32_t));
+    std::memset(h, 0, 3 * n * sizeof(uint32_t));
     int rc = RECON_OK;
     if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
         rc = fail(RECON_EDEVICE, "self-test event creation failed");
@@ -424,11 +424,18 @@ int self_test(double seconds) {
         else if (hipEventRecord(ev, nullptr) != hipSuccess) rc = fail(RECON_EDEVICE, "self-test event record failed");
         else rc = wait_event(ev, seconds, "the self-test kernel");
         if (rc == RECON_OK)
-            for (uint32_t i = 0; i < n; ++i)
-                if (((volatile uint32_t *)h)[i] != i * 3u + 1u) {
-                    rc = fail(RECON_EDEVICE, "self-test kernel wrote %u at %u (expected %u)", h[i], i, i * 3u + 1u);
+            for (uint32_t i = 0; i < n; ++i) {
+                const volatile uint32_t *v = h;
+                const uint32_t lane = i % 64u;
+                const uint32_t want_lo = lane > 0 ? i - 1u + 100u : 0u;
+                const uint32_t want_hi = lane < 63 ? i + 1u + 100u : 0u;
+                if (v[i] != i * 3u + 1u || v[n + i] != want_lo || v[2 * n + i] != want_hi) {
+                    rc = fail(RECON_EDEVICE,
+                              "self-test mismatch at %u: wrote %u/%u/%u, expected %u/%u/%u (lane shifts)", i,
+                              v[i], v[n + i], v[2 * n + i], i * 3u + 1u, want_lo, want_hi);
                     break;
                 }
+            }
         if (rc != RECON_ETIMEDOUT) (void)hipEventDestroy(ev);
     }
     if (rc != RECON_ETIMEDOUT) (void)hipHostFree(h);   // never free memory a live kernel may write

@@ -84,6 +84,15 @@ inline uint32_t __builtin_amdgcn_mbcnt_hi(uint32_t m, uint32_t acc) {
 }
 inline void __builtin_amdgcn_s_sleep(int) { std::this_thread::yield(); }
 inline int __builtin_amdgcn_readfirstlane(int v) { return (int)(uint32_t)kemu::exchange((uint32_t)v, 0); }
+// DPP: only the whole-wave shifts by one lane are emulated (bound_ctrl: 0 where no source lane)
+inline int __builtin_amdgcn_update_dpp(int old, int src, int ctrl, int row_mask, int bank_mask, bool bound_ctrl) {
+    (void)old; (void)row_mask; (void)bank_mask; (void)bound_ctrl;
+    const int l = kemu::lane();
+    const int from = ctrl == 0x138 ? l - 1 : (ctrl == 0x130 ? l + 1 : -100);
+    if (from == -100) { __builtin_trap(); }
+    const uint32_t v = (uint32_t)kemu::exchange((uint32_t)src, from >= 0 && from < 64 ? from : l);
+    return (from >= 0 && from < 64) ? (int)v : 0;
+}
 
 inline uint32_t atomicCAS(uint32_t *p, uint32_t expected, uint32_t desired) {
     kemu::check_lds(p, 4);
