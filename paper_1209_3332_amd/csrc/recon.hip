@@ -23,6 +23,7 @@
 #include <mutex>
 #include <string>
 #include <thread>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/recon.h"
@@ -125,6 +126,10 @@ struct recon_ctx {
     size_t graph_cap_blocks[kVariants] = {0, 0, 0};
     size_t graph_cap_tasks[kVariants] = {0, 0, 0};
     size_t graph_cap_scratch[kVariants] = {0, 0, 0};
+    // serving (created on the first recon_submit)
+    struct Serve;
+    Serve *serve = nullptr;
+    bool is_lane = false;   // a serving lane's private context
 };
 
 namespace {
@@ -442,40 +447,8 @@ int self_test(double seconds) {
     return rc == RECON_ETIMEDOUT ? RECON_EDEVICE : rc;
 }
 
-}  // namespace
-
-extern "C" {
-
-const char *recon_last_error(void) { return g_err.c_str(); }
-
-int recon_create(recon_ctx **out, int device, const recon_config *cfg) {
-    if (!out) return fail(RECON_EINVAL, "null output pointer");
-    *out = nullptr;
-    int ndev = 0;
-    hipError_t e = hipGetDeviceCount(&ndev);
-    if (e != hipSuccess || ndev == 0) return fail(RECON_EDEVICE, "no HIP device available");
-    if (device < 0 || device >= ndev) return fail(RECON_EINVAL, "device %d out of range (%d devices)", device, ndev);
-    recon_config c{};
-    if (cfg) c = *cfg;
-    if (c.block_rows == 0) c.block_rows = 32;
-    if (variant_of(c.block_rows) < 0) return fail(RECON_EINVAL, "block_rows must be 16, 32 or 64");
-    if (c.queue_capacity == 0) c.queue_capacity = 2048;
-    if (c.queue_capacity < 64 || c.queue_capacity > 8192)
-        return fail(RECON_EINVAL, "queue_capacity must be in 64..8192");
-    if (c.scan_rounds < -1 || c.scan_rounds > 8) return fail(RECON_EINVAL, "scan_rounds must be in -1..8");
-    if (c.scan_rounds == 0) c.scan_rounds = 2;
-    if (c.scan_rounds < 0) c.scan_rounds = 0;
-    if (c.wg_per_cu < 0) return fail(RECON_EINVAL, "wg_per_cu must be >= 0");
-    if (c.stop_after_stage < 0 || c.stop_after_stage > 3) return fail(RECON_EINVAL, "stop_after_stage must be 0..3");
-    if (c.serve_mem_cap == 0) c.serve_mem_cap = (int64_t)64 << 30;
-    if (c.serve_slots == 0) c.serve_slots = 256;
-    e = hipSetDevice(device);
-    if (e != hipSuccess) return fail(RECON_EDEVICE, "hipSetDevice failed: %s", hipGetErrorString(e));
-    int rc = self_test(20.0);
-    if (rc) {
-        std::string m = g_err;
-        return fail(rc, "device self-test failed: %s", m.c_str());
-    }
+// Allocate a context (no self-test): events, pinned statistics buffer, watchdog.
+int make_ctx(recon_ctx **out, int device, const recon_config &c) {
     recon_ctx *ctx = new recon_ctx();
     ctx->device = device;
     ctx->cfg = c;
@@ -505,8 +478,198 @@ int recon_create(recon_ctx **out, int device, const recon_config *cfg) {
     return RECON_OK;
 }
 
+size_t task_bytes(const recon_task &t) {
+    size_t b = (size_t)t.image.height * (size_t)t.image.pitch;
+    if (t.op == RECON_OP_DILATE) b += (size_t)t.mask.height * (size_t)t.mask.pitch;
+    else b += round_up((size_t)round_up((size_t)t.image.width, 4) * t.image.height, 256);
+    return b;
+}
+
+}  // namespace
+
+// ============================================================================
+// Serving: a request loop that admits tasks by device memory and slots and runs
+// them as continuous batches.  A worker thread owns `kLanes` lanes, each a
+// private context (its own scheduler workspace, kept resident) with its own
+// stream.  Whenever a lane is free and requests are waiting, the lane takes
+// every waiting request (up to its batch limit) and launches the pipeline on
+// them; lanes run concurrently, so requests admitted while others are on the
+// GPU start as soon as a lane frees up and overlap with the work in flight.
+struct recon_ctx::Serve {
+    static constexpr int kLanes = 3;
+    static constexpr int kMaxPerLaunch = 64;
+    struct Req {
+        uint64_t ticket;
+        recon_task task;
+        size_t bytes;
+    };
+    struct Lane {
+        recon_ctx *sub = nullptr;
+        hipStream_t stream = nullptr;
+        hipEvent_t done = nullptr;
+        std::vector<Req> reqs;
+        bool busy = false;
+    };
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Req> waiting;
+    std::unordered_map<uint64_t, int> status;   // 0 waiting, 1 running, 2 done, -1 failed
+    uint64_t next_ticket = 1;
+    size_t bytes_admitted = 0;
+    int slots_admitted = 0;
+    bool stop = false;
+    int error = RECON_OK;
+    std::string error_msg;
+    Lane lanes[kLanes];
+    std::thread worker;
+    int device = 0;
+};
+
+namespace {
+
+void serve_loop(recon_ctx *ctx) {
+    recon_ctx::Serve *S = ctx->serve;
+    (void)hipSetDevice(S->device);
+    std::unique_lock<std::mutex> lk(S->mu);
+    while (true) {
+        bool any_busy = false;
+        // harvest finished lanes
+        for (auto &L : S->lanes) {
+            if (!L.busy) continue;
+            const hipError_t q = hipEventQuery(L.done);
+            if (q == hipErrorNotReady) {
+                any_busy = true;
+                continue;
+            }
+            const int st = q == hipSuccess ? 2 : -1;
+            if (q != hipSuccess) {
+                S->error = RECON_EDEVICE;
+                S->error_msg = std::string("serving launch failed: ") + hipGetErrorString(q);
+            }
+            for (auto &r : L.reqs) {
+                S->status[r.ticket] = st;
+                S->bytes_admitted -= r.bytes;
+                S->slots_admitted -= 1;
+            }
+            L.reqs.clear();
+            L.busy = false;
+            S->cv_done.notify_all();
+        }
+        // launch waiting requests on free lanes
+        for (auto &L : S->lanes) {
+            if (L.busy || S->waiting.empty()) continue;
+            std::vector<recon_task> tasks;
+            while (!S->waiting.empty() && (int)L.reqs.size() < recon_ctx::Serve::kMaxPerLaunch) {
+                L.reqs.push_back(S->waiting.front());
+                S->waiting.pop_front();
+            }
+            for (auto &r : L.reqs) {
+                tasks.push_back(r.task);
+                S->status[r.ticket] = 1;
+            }
+            int rc = run_tasks(L.sub, tasks.data(), (int)tasks.size(), L.stream, false);
+            if (rc == RECON_OK && hipEventRecord(L.done, L.stream) != hipSuccess) rc = RECON_EDEVICE;
+            if (rc != RECON_OK) {
+                S->error = rc;
+                S->error_msg = g_err;
+                for (auto &r : L.reqs) {
+                    S->status[r.ticket] = -1;
+                    S->bytes_admitted -= r.bytes;
+                    S->slots_admitted -= 1;
+                }
+                L.reqs.clear();
+                S->cv_done.notify_all();
+                continue;
+            }
+            L.busy = true;
+            any_busy = true;
+        }
+        if (S->stop && S->waiting.empty() && !any_busy) break;
+        if (any_busy)
+            S->cv_work.wait_for(lk, std::chrono::microseconds(20));
+        else
+            S->cv_work.wait_for(lk, std::chrono::milliseconds(5));
+    }
+}
+
+int serve_start(recon_ctx *ctx) {
+    if (ctx->serve) return RECON_OK;
+    auto *S = new recon_ctx::Serve();
+    S->device = ctx->device;
+    recon_config c = ctx->cfg;
+    c.timing = 0;
+    for (auto &L : S->lanes) {
+        int rc = make_ctx(&L.sub, ctx->device, c);
+        if (rc == RECON_OK) {
+            L.sub->is_lane = true;
+            if (hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking) != hipSuccess ||
+                hipEventCreateWithFlags(&L.done, hipEventDisableTiming) != hipSuccess)
+                rc = fail(RECON_EDEVICE, "serving lane stream/event creation failed");
+        }
+        if (rc != RECON_OK) {
+            for (auto &M : S->lanes) {
+                if (M.sub) recon_destroy(M.sub);
+                if (M.stream) (void)hipStreamDestroy(M.stream);
+                if (M.done) (void)hipEventDestroy(M.done);
+            }
+            delete S;
+            return rc;
+        }
+    }
+    ctx->serve = S;
+    S->worker = std::thread(serve_loop, ctx);
+    return RECON_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *recon_last_error(void) { return g_err.c_str(); }
+
+int recon_create(recon_ctx **out, int device, const recon_config *cfg) {
+    if (!out) return fail(RECON_EINVAL, "null output pointer");
+    *out = nullptr;
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || ndev == 0) return fail(RECON_EDEVICE, "no HIP device available");
+    if (device < 0 || device >= ndev) return fail(RECON_EINVAL, "device %d out of range (%d devices)", device, ndev);
+    recon_config c{};
+    if (cfg) c = *cfg;
+    if (c.block_rows == 0) c.block_rows = 32;
+    if (variant_of(c.block_rows) < 0) return fail(RECON_EINVAL, "block_rows must be 16, 32 or 64");
+    if (c.queue_capacity == 0) c.queue_capacity = 2048;
+    if (c.queue_capacity < 64 || c.queue_capacity > 8192)
+        return fail(RECON_EINVAL, "queue_capacity must be in 64..8192");
+    if (c.scan_rounds < -1 || c.scan_rounds > 8) return fail(RECON_EINVAL, "scan_rounds must be in -1..8");
+    if (c.scan_rounds == 0) c.scan_rounds = 2;
+    if (c.scan_rounds < 0) c.scan_rounds = 0;
+    if (c.wg_per_cu < 0) return fail(RECON_EINVAL, "wg_per_cu must be >= 0");
+    if (c.stop_after_stage < 0 || c.stop_after_stage > 3) return fail(RECON_EINVAL, "stop_after_stage must be 0..3");
+    if (c.serve_mem_cap < 0 || c.serve_slots < 0) return fail(RECON_EINVAL, "serving limits must be >= 0");
+    if (c.serve_mem_cap == 0) c.serve_mem_cap = (int64_t)64 << 30;
+    if (c.serve_slots == 0) c.serve_slots = 256;
+    e = hipSetDevice(device);
+    if (e != hipSuccess) return fail(RECON_EDEVICE, "hipSetDevice failed: %s", hipGetErrorString(e));
+    static std::mutex tested_mu;
+    static std::vector<int> tested;
+    {
+        std::lock_guard<std::mutex> lk(tested_mu);
+        if (std::find(tested.begin(), tested.end(), device) == tested.end()) {
+            int rc = self_test(20.0);
+            if (rc) {
+                std::string m = g_err;
+                return fail(rc, "device self-test failed: %s", m.c_str());
+            }
+            tested.push_back(device);
+        }
+    }
+    return make_ctx(out, device, c);
+}
+
 int recon_destroy(recon_ctx *ctx) {
     if (!ctx) return fail(RECON_EINVAL, "null context");
+    if (ctx->serve) (void)recon_serve_stop(ctx);
     (void)hipSetDevice(ctx->device);
     if (ctx->have_last && wait_event(ctx->last_done, 60.0, "the last launch") != RECON_OK)
         return RECON_ETIMEDOUT;   // leak rather than free memory a running kernel may use
@@ -597,20 +760,102 @@ int recon_last_stats(recon_ctx *ctx, recon_stats *out) {
 }
 
 int recon_submit(recon_ctx *ctx, const recon_task *task, uint64_t *ticket) {
-    (void)ctx; (void)task; (void)ticket;
-    return fail(RECON_EINVAL, "serving is not available in this build");
-}
-int recon_poll(recon_ctx *ctx, uint64_t ticket, int *done) {
-    (void)ctx; (void)ticket; (void)done;
-    return fail(RECON_EINVAL, "serving is not available in this build");
-}
-int recon_wait(recon_ctx *ctx, uint64_t ticket, int64_t timeout_us) {
-    (void)ctx; (void)ticket; (void)timeout_us;
-    return fail(RECON_EINVAL, "serving is not available in this build");
-}
-int recon_serve_stop(recon_ctx *ctx) {
-    (void)ctx;
+    if (!ctx || !task || !ticket) return fail(RECON_EINVAL, "null argument");
+    int rc = check_task(*task);
+    if (rc) return rc;
+    rc = ensure_device(ctx);
+    if (rc) return rc;
+    if (!ctx->serve) {
+        rc = serve_start(ctx);
+        if (rc) return rc;
+    }
+    recon_ctx::Serve *S = ctx->serve;
+    const size_t bytes = task_bytes(*task);
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        if (S->stop) return fail(RECON_EINVAL, "serving has been stopped");
+        if ((int64_t)bytes > ctx->cfg.serve_mem_cap)
+            return fail(RECON_EINVAL, "task needs %zu bytes, above the admission cap", bytes);
+        if ((int64_t)(S->bytes_admitted + bytes) > ctx->cfg.serve_mem_cap || S->slots_admitted >= ctx->cfg.serve_slots)
+            return fail(RECON_EAGAIN, "admission full (%zu bytes, %d slots in flight)", S->bytes_admitted,
+                        S->slots_admitted);
+        const uint64_t tk = S->next_ticket++;
+        S->waiting.push_back({tk, *task, bytes});
+        S->status[tk] = 0;
+        S->bytes_admitted += bytes;
+        S->slots_admitted += 1;
+        *ticket = tk;
+    }
+    S->cv_work.notify_one();
     return RECON_OK;
+}
+
+int recon_poll(recon_ctx *ctx, uint64_t ticket, int *done) {
+    if (!ctx || !done) return fail(RECON_EINVAL, "null argument");
+    *done = 0;
+    if (!ctx->serve) return fail(RECON_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+    recon_ctx::Serve *S = ctx->serve;
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->status.find(ticket);
+    if (it == S->status.end()) return fail(RECON_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+    if (it->second == -1) {
+        S->status.erase(it);
+        return fail(S->error ? S->error : RECON_EDEVICE, "%s", S->error_msg.c_str());
+    }
+    if (it->second == 2) {
+        *done = 1;
+        S->status.erase(it);
+    }
+    return RECON_OK;
+}
+
+int recon_wait(recon_ctx *ctx, uint64_t ticket, int64_t timeout_us) {
+    if (!ctx) return fail(RECON_EINVAL, "null context");
+    if (!ctx->serve) return fail(RECON_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+    recon_ctx::Serve *S = ctx->serve;
+    std::unique_lock<std::mutex> lk(S->mu);
+    const auto deadline = std::chrono::steady_clock::now() + std::chrono::microseconds(timeout_us < 0 ? 0 : timeout_us);
+    while (true) {
+        auto it = S->status.find(ticket);
+        if (it == S->status.end()) return fail(RECON_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+        if (it->second == 2) {
+            S->status.erase(it);
+            return RECON_OK;
+        }
+        if (it->second == -1) {
+            S->status.erase(it);
+            return fail(S->error ? S->error : RECON_EDEVICE, "%s", S->error_msg.c_str());
+        }
+        if (timeout_us < 0) {
+            S->cv_done.wait_for(lk, std::chrono::milliseconds(10));
+        } else {
+            if (std::chrono::steady_clock::now() >= deadline)
+                return fail(RECON_ETIMEDOUT, "ticket %llu not done after %lld us", (unsigned long long)ticket,
+                            (long long)timeout_us);
+            S->cv_done.wait_until(lk, std::min(deadline, std::chrono::steady_clock::now() + std::chrono::milliseconds(10)));
+        }
+    }
+}
+
+int recon_serve_stop(recon_ctx *ctx) {
+    if (!ctx) return fail(RECON_EINVAL, "null context");
+    recon_ctx::Serve *S = ctx->serve;
+    if (!S) return RECON_OK;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->stop = true;
+    }
+    S->cv_work.notify_all();
+    if (S->worker.joinable()) S->worker.join();
+    int rc = RECON_OK;
+    for (auto &L : S->lanes) {
+        if (L.sub && recon_destroy(L.sub) != RECON_OK) rc = RECON_ETIMEDOUT;
+        if (L.stream) (void)hipStreamDestroy(L.stream);
+        if (L.done) (void)hipEventDestroy(L.done);
+    }
+    delete S;
+    ctx->serve = nullptr;
+    return rc;
 }
 
 }  // extern "C"

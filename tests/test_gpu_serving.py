@@ -1,0 +1,117 @@
+"""Serving loop (recon_submit / recon_poll / recon_wait) on the GPU.
+
+Each request's result must be the same bytes alone and inside a mix of
+concurrent requests (the reconstruction is unique, so the tolerance is 0), and
+equal to the oracle; admission must push back (RECON_EAGAIN) instead of
+over-committing when the slot or memory cap is reached.
+"""
+import time
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def lib(torch_mod):
+    import paper_1209_3332_amd as p
+    return p
+
+
+def _task(rng, i):
+    h, w = int(rng.integers(64, 900)), int(rng.integers(64, 900))
+    conn = int(rng.choice([4, 8]))
+    mask = synth.scaled_config1_tile(h, w, 9000 + i)
+    return {"op": "dilate", "marker": synth.hdome_marker(mask, int(rng.integers(10, 41))), "mask": mask,
+            "conn": conn}
+
+
+def _submit_all(torch_mod, ctx, tasks, lib, timeout_s=60.0):
+    bufs, tickets = [], []
+    for t in tasks:
+        m = torch_mod.from_numpy(t["marker"]).cuda()
+        k = torch_mod.from_numpy(t["mask"]).cuda()
+        torch_mod.cuda.synchronize()
+        bufs.append((m, k))
+        deadline = time.time() + timeout_s
+        while True:
+            try:
+                tickets.append(ctx.submit("dilate", m, k, t["conn"]))
+                break
+            except lib.ReconAgain:
+                assert time.time() < deadline, "admission never freed up"
+                time.sleep(0.001)   # earlier requests complete in the background
+    for tk in tickets:
+        ctx.wait(tk, int(timeout_s * 1e6))
+    return [m.cpu().numpy() for m, _ in bufs]
+
+
+def test_alone_and_in_the_mix(torch_mod, lib, oracle_mod):
+    rng = np.random.default_rng(2024)
+    probe = _task(rng, 0)
+    want = oracle_mod.run_task(probe)
+    with lib.Recon(0) as ctx:
+        alone = _submit_all(torch_mod, ctx, [probe], lib)[0]
+        assert np.array_equal(alone, want)
+        mix = [_task(rng, i) for i in range(1, 30)]
+        mix.insert(11, probe)
+        outs = _submit_all(torch_mod, ctx, mix, lib)
+        assert np.array_equal(outs[11], alone)
+        for i, (t, got) in enumerate(zip(mix, outs)):
+            assert np.array_equal(got, oracle_mod.run_task(t)), "request %d" % i
+        ctx.serve_stop()
+
+
+def test_admission_backpressure(torch_mod, lib, oracle_mod):
+    rng = np.random.default_rng(7)
+    tasks = [_task(rng, 100 + i) for i in range(12)]
+    with lib.Recon(0, serve_slots=3) as ctx:
+        bufs, tickets, again = [], [], 0
+        for t in tasks:
+            m = torch_mod.from_numpy(t["marker"]).cuda()
+            k = torch_mod.from_numpy(t["mask"]).cuda()
+            torch_mod.cuda.synchronize()
+            bufs.append(m)
+            while True:
+                try:
+                    tickets.append(ctx.submit("dilate", m, k, t["conn"]))
+                    break
+                except lib.ReconAgain:
+                    again += 1
+                    # poll the oldest outstanding ticket until it completes
+                    pending = [tk for tk in tickets if tk is not None]
+                    ctx.wait(pending[0], 60_000_000)
+                    tickets[tickets.index(pending[0])] = None
+        for tk in tickets:
+            if tk is not None:
+                ctx.wait(tk, 60_000_000)
+        assert again > 0   # the slot cap of 3 was hit
+        for t, m in zip(tasks, bufs):
+            assert np.array_equal(m.cpu().numpy(), oracle_mod.run_task(t))
+        # stop, then serving restarts on the next submit
+        ctx.serve_stop()
+        t = tasks[0]
+        m = torch_mod.from_numpy(t["marker"]).cuda()
+        k = torch_mod.from_numpy(t["mask"]).cuda()
+        torch_mod.cuda.synchronize()
+        tk = ctx.submit("dilate", m, k, t["conn"])
+        assert not isinstance(tk, bool)
+        ctx.wait(tk, 60_000_000)
+        assert np.array_equal(m.cpu().numpy(), oracle_mod.run_task(t))
+
+
+def test_unknown_ticket(torch_mod, lib):
+    with lib.Recon(0) as ctx:
+        with pytest.raises(lib.ReconError):
+            ctx.poll(12345)
