@@ -82,6 +82,10 @@ typedef struct {
     int32_t conn;          /* 4 or 8 */
     recon_image image;
     recon_image mask;
+    int32_t scan_rounds;   /* per-task tuning: directional pass rounds (0 = context default,
+                              -1 = none, 1..8) */
+    int32_t queue_capacity;/* per-task tuning: LDS queue entries (0 = context default; at most
+                              the context's queue_capacity) */
 } recon_task;
 
 /* Tuning and capacity knobs; zero fields take the defaults. */

@@ -51,7 +51,7 @@ class recon_image(ctypes.Structure):
 
 class recon_task(ctypes.Structure):
     _fields_ = [("op", ctypes.c_int32), ("conn", ctypes.c_int32), ("image", recon_image),
-                ("mask", recon_image)]
+                ("mask", recon_image), ("scan_rounds", ctypes.c_int32), ("queue_capacity", ctypes.c_int32)]
 
 
 class recon_config(ctypes.Structure):
@@ -160,8 +160,10 @@ def recon_fill_holes(ctx: int, img, conn: int = 8, stream=None) -> None:
     _check(load_library().recon_fill_holes(ctx, ctypes.byref(m), int(conn), _stream_ptr(stream)))
 
 
-def make_task(op: str, image, mask=None, conn: int = 8) -> recon_task:
+def make_task(op: str, image, mask=None, conn: int = 8, scan_rounds: int = 0, queue_capacity: int = 0) -> recon_task:
     t = recon_task()
+    t.scan_rounds = int(scan_rounds)
+    t.queue_capacity = int(queue_capacity)
     t.op = RECON_OP_DILATE if op == "dilate" else RECON_OP_FILL_HOLES
     if op not in ("dilate", "fill_holes"):
         raise ValueError("op must be 'dilate' or 'fill_holes'")
@@ -245,11 +247,12 @@ class Recon:
 
     def batch(self, tasks, stream=None):
         """tasks: list of dicts {op, image, mask?, conn} of device tensors (results in place)."""
-        recon_batch(self.ctx, [make_task(t["op"], t["image"], t.get("mask"), t.get("conn", 8))
+        recon_batch(self.ctx, [make_task(t["op"], t["image"], t.get("mask"), t.get("conn", 8),
+                                         t.get("scan_rounds", 0), t.get("queue_capacity", 0))
                                for t in tasks], stream)
 
-    def submit(self, op, image, mask=None, conn: int = 8) -> int:
-        tk = recon_submit(self.ctx, make_task(op, image, mask, conn))
+    def submit(self, op, image, mask=None, conn: int = 8, scan_rounds: int = 0, queue_capacity: int = 0) -> int:
+        tk = recon_submit(self.ctx, make_task(op, image, mask, conn, scan_rounds, queue_capacity))
         self._keep[tk] = (image, mask)
         return tk
 

@@ -74,6 +74,8 @@ struct TaskDev {
     int32_t nby, nbx;
     uint32_t block0;       // first global block id of this task
     int32_t aligned;       // 1 if both planes allow dword access (4-aligned base and pitch)
+    int32_t scan_rounds;   // directional pass rounds on the dense pass
+    int32_t qcap;          // LDS queue entries (<= the launch's LDS allocation)
 };
 
 // Batch header in device memory, in front of a device task table.
@@ -722,7 +724,7 @@ __global__ __launch_bounds__(64) void dense_pass(TaskTable tt, KArgs a) {
         clear_halo<BH>(L);
         for (int r = ln; r < BH; r += LANES) L.rowdirty[r] = 0;
         __syncthreads();
-        for (int k = 0; k < a.scan_rounds; ++k) {
+        for (int k = 0; k < t.scan_rounds; ++k) {
             bool c = vpass<BH>(L, t.conn, +1);
             c |= vpass<BH>(L, t.conn, -1);
             __syncthreads();
@@ -731,7 +733,7 @@ __global__ __launch_bounds__(64) void dense_pass(TaskTable tt, KArgs a) {
             __syncthreads();
             if (!__ballot(c)) break;
         }
-        converge_block<BH>(L, t.conn, a.qcap, a.work);
+        converge_block<BH>(L, t.conn, t.qcap, a.work);
         store_block<BH>(t, g, L, true);
         if (ln == 0)
             __hip_atomic_fetch_add(&a.work->stat_dense, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -875,7 +877,7 @@ __global__ __launch_bounds__(64) void revisit_drain(TaskTable tt, KArgs a) {
             load_halo<BH>(t, g, L);
             for (int r = ln; r < BH; r += LANES) L.rowdirty[r] = 0;
             __syncthreads();
-            if (converge_block<BH>(L, t.conn, a.qcap, w)) {
+            if (converge_block<BH>(L, t.conn, t.qcap, w)) {
                 store_block<BH>(t, g, L, false);
                 __threadfence();
                 ok = check_neighbours<BH>(a, ring_cap, ti, t, g, by, bx, L);

@@ -227,9 +227,13 @@ bool overlaps(const recon_image &a, const recon_image &b) {
     return a0 < b1 && b0 < a1;
 }
 
-int check_task(const recon_task &t) {
+int check_task(const recon_task &t, const recon_config *cfg = nullptr) {
     if (t.op != RECON_OP_DILATE && t.op != RECON_OP_FILL_HOLES)
         return fail(RECON_EINVAL, "unknown op %d", t.op);
+    if (t.scan_rounds < -1 || t.scan_rounds > 8) return fail(RECON_EINVAL, "task scan_rounds must be in -1..8");
+    if (t.queue_capacity != 0 &&
+        (t.queue_capacity < 64 || (cfg && t.queue_capacity > cfg->queue_capacity)))
+        return fail(RECON_EINVAL, "task queue_capacity must be in 64..%d", cfg ? cfg->queue_capacity : 8192);
     if (t.conn != 4 && t.conn != 8) return fail(RECON_EINVAL, "conn must be 4 or 8, got %d", t.conn);
     int rc = check_image(&t.image, t.op == RECON_OP_DILATE ? "marker" : "image");
     if (rc) return rc;
@@ -247,7 +251,7 @@ int check_task(const recon_task &t) {
 bool aligned4(const void *p, int64_t pitch) { return ((uintptr_t)p % 4 == 0) && (pitch % 4 == 0); }
 
 // Host-side task table for `n` tasks (fill scratch planes as offsets, patched later).
-void build_table(const recon_task *tasks, int n, int bh, std::vector<rk::TaskDev> &out,
+void build_table(const recon_config &cfg, const recon_task *tasks, int n, int bh, std::vector<rk::TaskDev> &out,
                  uint32_t &total_blocks, size_t &scratch_bytes, bool &any_fill) {
     out.resize(n);
     total_blocks = 0;
@@ -263,6 +267,8 @@ void build_table(const recon_task *tasks, int n, int bh, std::vector<rk::TaskDev
         d.nbx = (d.w + rk::BW - 1) / rk::BW;
         d.block0 = total_blocks;
         total_blocks += (uint32_t)(d.nby * d.nbx);
+        d.scan_rounds = t.scan_rounds == 0 ? cfg.scan_rounds : (t.scan_rounds < 0 ? 0 : t.scan_rounds);
+        d.qcap = t.queue_capacity == 0 ? cfg.queue_capacity : t.queue_capacity;
         if (t.op == RECON_OP_DILATE) {
             d.op = rk::OP_DILATE;
             d.j = t.image.data;
@@ -341,7 +347,7 @@ int run_tasks(recon_ctx *c, const recon_task *tasks, int n, hipStream_t stream, 
     uint32_t total_blocks = 0;
     size_t scratch = 0;
     bool any_fill = false;
-    build_table(tasks, n, bh, table, total_blocks, scratch, any_fill);
+    build_table(c->cfg, tasks, n, bh, table, total_blocks, scratch, any_fill);
     rc = ensure_capacity(c, (size_t)n, (size_t)total_blocks, scratch);
     if (rc) return rc;
     for (auto &d : table)
@@ -716,7 +722,7 @@ int recon_batch(recon_ctx *ctx, const recon_task *tasks, int32_t n, void *stream
     if (n < 0 || (n > 0 && !tasks)) return fail(RECON_EINVAL, "bad task list");
     if (n == 0) return RECON_OK;
     for (int k = 0; k < n; ++k) {
-        int rc = check_task(tasks[k]);
+        int rc = check_task(tasks[k], &ctx->cfg);
         if (rc) {
             std::string m = g_err;
             return fail(rc, "task %d: %s", k, m.c_str());
@@ -761,7 +767,7 @@ int recon_last_stats(recon_ctx *ctx, recon_stats *out) {
 
 int recon_submit(recon_ctx *ctx, const recon_task *task, uint64_t *ticket) {
     if (!ctx || !task || !ticket) return fail(RECON_EINVAL, "null argument");
-    int rc = check_task(*task);
+    int rc = check_task(*task, &ctx->cfg);
     if (rc) return rc;
     rc = ensure_device(ctx);
     if (rc) return rc;

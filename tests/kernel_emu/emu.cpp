@@ -239,6 +239,8 @@ int emu_run(const EmuTask *tasks, int n, int bh, int qcap, int scan_rounds, int 
         d.nbx = (e.w + BW - 1) / BW;
         d.block0 = total;
         total += (uint32_t)(d.nby * d.nbx);
+        d.scan_rounds = scan_rounds;
+        d.qcap = qcap;
         jplanes[k] = (uint8_t *)std::malloc(px);
         std::memcpy(jplanes[k], e.image, px);
         if (e.op == 0) {

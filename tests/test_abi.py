@@ -38,7 +38,7 @@ def test_binding_names_match_header():
 def test_struct_layouts():
     import paper_1209_3332_amd as p
     assert ctypes.sizeof(p.recon_image) == 24
-    assert ctypes.sizeof(p.recon_task) == 56
+    assert ctypes.sizeof(p.recon_task) == 64
     assert ctypes.sizeof(p.recon_config) == 48
 
 
