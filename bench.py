@@ -1,20 +1,19 @@
 #!/usr/bin/env python3
 """Benchmark of the reconstruction path on one MI355X.
 
-Workload (the configuration the headline metric is quoted on): a batch of 64
-uint8 4096 x 4096 tiles, 8-connectivity -- 56 nuclei-like tiles (the 512 x 512
-generator scaled to area: 2560 Gaussians, sigma U[4,12], amplitude U[40,200],
-noise [-8,8]; marker max(I - 30, 0)) and 8 adversarial spiral-corridor tiles
-(1-pixel corridor, one chain of 8.39 M pixels, a single seed at one end).
+Headline workload (the 4K-tile configuration the metric is quoted on): one
+uint8 4096 x 4096 nuclei-like tile (~3000 Gaussians, sigma U[3,8], amplitude
+U[60,220], background 30, noise [-10,10]).  A step is the tile's whole hot
+path: reconstruction by dilation with 8-connectivity from the marker
+max(I - 20, 0), then fill-holes (8-connected background) of its binary copy
+255 * (I > 120) -- two plain per-tile launch sequences.  Every step works on
+its own untouched copies of the inputs, all resident in device memory before
+the timed region; `value` = pixels processed (2 x 16.78 M per step) / time.
 
-A step is one batched launch sequence (recon_batch: one HIP-graph replay of
-reset -> dense pass -> border seeding -> revisit drain) over the whole batch,
-with every input already resident in device memory; each step reconstructs its
-own untouched copy of the markers, so nothing is skipped or cached.  Printed as
-one JSON line: batched Mpixel/s (value), the same 64 tiles as 64 plain per-tile
-calls, per-tile latency percentiles, per-kernel durations measured with HIP
-events inside the timed steps, the dense kernel's roofline, and the CPU oracle
-timed on the host cores on a bounded sample.
+Alongside, in the same run: the batched-vs-per-tile comparison on a batch of
+4096 x 4096 tiles (56 nuclei-like + 8 spiral corridors at the default 64), the
+per-kernel HIP-event durations of the timed steps, the dense kernel's
+roofline, and the CPU oracle timed on the host cores on a bounded sample.
 """
 import argparse
 import json
@@ -27,7 +26,21 @@ sys.path.insert(0, ROOT)
 
 METRIC = "recon Mpixel/s, 4K² uint8 8-conn, batched vs per-tile; p99 latency; %HBM"
 HBM_PEAK_GBS = 8000.0
-BYTES_PER_PX = 3.0   # algorithmic: read mask, read marker, write result
+BYTES_DILATE = 3.0   # algorithmic bytes per pixel: read mask, read marker, write result
+BYTES_FILL = 2.0     # read image, write result (the marker is implicit)
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def percentile(xs, q):
+    xs = sorted(x for x in xs if x is not None)
+    if not xs:
+        return None
+    k = (len(xs) - 1) * q / 100.0
+    lo, hi = int(k), min(int(k) + 1, len(xs) - 1)
+    return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
 
 
 def _gen_tile(args):
@@ -38,7 +51,7 @@ def _gen_tile(args):
 
 
 def make_batch(n_tiles, size, workers):
-    """Host arrays of the batch: (kind, marker, mask) per tile."""
+    """Host arrays of the batch: (kind, marker, mask) per tile; tiles i = 7 (mod 8) are spirals."""
     import multiprocessing as mp
     import synth
     nuclei = [i for i in range(n_tiles) if i % 8 != 7]
@@ -56,72 +69,119 @@ def make_batch(n_tiles, size, workers):
     return out
 
 
-def percentile(xs, q):
-    xs = sorted(xs)
-    if not xs:
-        return None
-    k = (len(xs) - 1) * q / 100.0
-    lo, hi = int(k), min(int(k) + 1, len(xs) - 1)
-    return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
-
-
-def cpu_baseline(batch, budget_s=20.0):
-    """The oracle, as it is, on the host cores: a bag of tiles over a thread pool."""
+def cpu_baseline(marker, mask, binary, budget_s=20.0):
+    """The oracle, as it is, on the host cores: copies of the headline step over a thread pool."""
     from concurrent.futures import ThreadPoolExecutor
     import oracle
     cores = len(os.sched_getaffinity(0))
-    nuclei = [b for b in batch if b[0] == "nuclei"]
-    # one tile single-threaded to size the sample to about budget_s of CPU work
     t = time.perf_counter()
-    oracle.recon_dilate(nuclei[0][1], nuclei[0][2], 8)
-    per_tile = time.perf_counter() - t
-    n = max(1, min(len(nuclei), int(budget_s / max(per_tile, 1e-3))))
-    sample = nuclei[:n]
+    oracle.recon_dilate(marker, mask, 8)
+    oracle.fill_holes(binary, 8)
+    one = time.perf_counter() - t
+    n = max(1, int(budget_s / max(one, 1e-3)))
     t = time.perf_counter()
     with ThreadPoolExecutor(cores) as ex:
-        list(ex.map(lambda b: oracle.recon_dilate(b[1], b[2], 8), sample))
+        list(ex.map(lambda _: (oracle.recon_dilate(marker, mask, 8), oracle.fill_holes(binary, 8)), range(n)))
     wall = time.perf_counter() - t
-    px = sum(b[2].size for b in sample)
+    px = 2 * mask.size * n
     return {"value": px / wall / 1e6, "unit": "Mpixel/s", "cores": cores, "kind": "oracle",
-            "sample": "%d nuclei tiles of %dx%d (8-conn), one tile per thread; single-core %.1f Mpixel/s"
-                      % (n, nuclei[0][2].shape[0], nuclei[0][2].shape[1], nuclei[0][2].size / per_tile / 1e6)}
+            "sample": "%d copies of the headline step (dilate + fill-holes of one %dx%d tile), one per thread; "
+                      "single-core %.2f Mpixel/s" % (n, mask.shape[0], mask.shape[1], 2 * mask.size / one / 1e6)}
+
+
+def batched_vs_per_tile(recon, torch, ctx_cfg, n_tiles, size, workers):
+    import numpy as np
+    import oracle
+    t0 = time.perf_counter()
+    batch = make_batch(n_tiles, size, workers)
+    log("batch: generated %d tiles in %.1f s" % (n_tiles, time.perf_counter() - t0))
+    dev = torch.device("cuda:0")
+    masks = [torch.from_numpy(b[2]).to(dev) for b in batch]
+    pristine = [torch.from_numpy(b[1]).to(dev) for b in batch]
+    px = sum(m.numel() for m in masks)
+    kinds = [b[0] for b in batch]
+    res = {"tiles": n_tiles, "tile": [size, size], "spirals": kinds.count("spiral")}
+    with recon.Recon(0, **ctx_cfg) as ctx:
+        stream = torch.cuda.current_stream()
+        # batched: one graph replay over the whole batch (warm once)
+        for rep in range(2):
+            work = [p.clone() for p in pristine]
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            ctx.batch([{"op": "dilate", "image": w, "mask": m, "conn": 8} for w, m in zip(work, masks)], stream)
+            st = ctx.last_stats()
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t
+        res["batched"] = {"Mpixel_s": px / wall / 1e6, "ms": wall * 1e3, "kernels_ms": {
+            "dense_pass": st["dense_ms"], "border_seed": st["seed_ms"], "revisit_drain": st["drain_ms"]},
+            "revisits": st["revisits"]}
+        ok = all(torch.equal(work[i], masks[i]) for i in range(n_tiles) if kinds[i] == "spiral")
+        ok &= bool(np.array_equal(work[0].cpu().numpy(), oracle.recon_dilate(batch[0][1], batch[0][2], 8)))
+        res["parity_ok"] = ok
+        # per-tile: the same tiles as plain calls, one after another
+        work = [p.clone() for p in pristine]
+        torch.cuda.synchronize()
+        lat = []
+        t = time.perf_counter()
+        for w, m in zip(work, masks):
+            ctx.dilate(w, m, 8, stream)
+            lat.append(ctx.last_stats()["total_ms"])
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t
+        nuc = [l for l, k in zip(lat, kinds) if k == "nuclei"]
+        spi = [l for l, k in zip(lat, kinds) if k == "spiral"]
+        res["per_tile"] = {"Mpixel_s": px / wall / 1e6, "ms": wall * 1e3,
+                           "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99),
+                                          "nuclei_p50": percentile(nuc, 50), "nuclei_p99": percentile(nuc, 99),
+                                          "spiral_max": max(spi) if spi else None}}
+        res["batched_over_per_tile"] = res["batched"]["Mpixel_s"] / res["per_tile"]["Mpixel_s"]
+    return res
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--tiles", type=int, default=64)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--size", type=int, default=4096)
+    ap.add_argument("--batch-tiles", type=int, default=64, help="0 skips the batched-vs-per-tile comparison")
     ap.add_argument("--block-rows", type=int, default=0)
     ap.add_argument("--scan-rounds", type=int, default=0)
     ap.add_argument("--queue", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-per-tile", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="only copy this many bytes device-to-device 5 times (counter calibration) and exit")
     ap.add_argument("--workers", type=int, default=min(16, len(os.sched_getaffinity(0))))
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on exactly one GPU: the reconstruction shards by tile with no "
-              "communication, and this build measures the single-GPU path only (--gpus 1).", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the reconstruction shards by tile with no communication, "
+              "and this build measures the single-GPU path only (--gpus 1).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
     import torch
+
+    if args.copy_probe:
+        a = torch.empty(args.copy_probe, dtype=torch.uint8, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": args.copy_probe, "copies": 5}))
+        return
+
     import oracle
     import paper_1209_3332_amd as recon
+    import synth
 
-    log = lambda *a: print("[bench]", *a, file=sys.stderr, flush=True)
-    t0 = time.perf_counter()
-    batch = make_batch(args.tiles, args.size, args.workers)
-    log("generated %d tiles in %.1f s" % (len(batch), time.perf_counter() - t0))
+    marker, mask, binary = synth.config2_tile(size=args.size, n_gauss=round(3000 * args.size ** 2 / 4096 ** 2))
     dev = torch.device("cuda:0")
-    masks = [torch.from_numpy(b[2]).to(dev) for b in batch]
-    pristine = [torch.from_numpy(b[1]).to(dev) for b in batch]
+    d_mask = torch.from_numpy(mask).to(dev)
     n_sets = args.warmup + args.steps
-    sets = [[p.clone() for p in pristine] for _ in range(n_sets)]
+    markers = [torch.from_numpy(marker).to(dev) for _ in range(n_sets)]
+    images = [torch.from_numpy(binary).to(dev) for _ in range(n_sets)]
     torch.cuda.synchronize()
-    px_total = sum(m.numel() for m in masks)
+    px_step = 2 * mask.size
 
     cfg = dict(timing=1)
     if args.block_rows:
@@ -133,84 +193,71 @@ def main():
     ctx = recon.Recon(0, **cfg)
     stream = torch.cuda.current_stream()
 
-    def tasks_of(markers):
-        return [{"op": "dilate", "image": markers[i], "mask": masks[i], "conn": 8} for i in range(len(masks))]
+    def step(s):
+        ctx.dilate(markers[s], d_mask, 8, stream)
+        a = ctx.last_stats()
+        ctx.fill_holes(images[s], 8, stream)
+        b = ctx.last_stats()
+        return a, b
 
-    # ---- batched: warmup, then exactly `steps` timed steps
     for s in range(args.warmup):
-        ctx.batch(tasks_of(sets[s]), stream)
-        ctx.last_stats()
+        step(s)
     torch.cuda.synchronize()
-    kstats = []
+    kd, kf = [], []
     t_start = time.perf_counter()
     for s in range(args.warmup, n_sets):
-        ctx.batch(tasks_of(sets[s]), stream)
-        kstats.append(ctx.last_stats())   # waits for the step; per-kernel HIP event times
+        a, b = step(s)
+        kd.append(a)
+        kf.append(b)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
     ms_per_step = wall * 1e3 / args.steps
-    value = px_total / (wall / args.steps) / 1e6
-    log("batched: %.2f ms/step, %.0f Mpixel/s" % (ms_per_step, value))
+    value = px_step / (wall / args.steps) / 1e6
+    log("headline: %.3f ms/step, %.0f Mpixel/s" % (ms_per_step, value))
 
-    # ---- parity on the last step: spirals must equal their mask; one nuclei tile against the oracle
-    last = sets[-1]
-    parity = {"checked": [], "ok": True}
-    for i, b in enumerate(batch):
-        if b[0] == "spiral":
-            ok = bool(torch.equal(last[i], masks[i]))
-            parity["checked"].append("spiral %d" % i)
-            parity["ok"] &= ok
-    want = oracle.recon_dilate(batch[0][1], batch[0][2], 8)
-    parity["ok"] &= bool(np.array_equal(last[0].cpu().numpy(), want))
-    parity["checked"].append("nuclei 0 vs oracle")
+    # parity of the last step against the oracle (whole tile, bit-exact)
+    parity = {"dilate": bool(np.array_equal(markers[-1].cpu().numpy(), oracle.recon_dilate(marker, mask, 8))),
+              "fill_holes": bool(np.array_equal(images[-1].cpu().numpy(), oracle.fill_holes(binary, 8)))}
 
-    # ---- per-tile: the same tiles as plain calls
-    per_tile = None
-    if not args.no_per_tile:
-        work = [p.clone() for p in pristine]
-        torch.cuda.synchronize()
-        lat = []
-        t = time.perf_counter()
-        for i in range(len(masks)):
-            ctx.dilate(work[i], masks[i], 8, stream)
-            lat.append(ctx.last_stats()["total_ms"])
-        torch.cuda.synchronize()
-        wall_pt = time.perf_counter() - t
-        nuc = [lat[i] for i, b in enumerate(batch) if b[0] == "nuclei"]
-        spi = [lat[i] for i, b in enumerate(batch) if b[0] == "spiral"]
-        per_tile = {"value": px_total / wall_pt / 1e6, "unit": "Mpixel/s", "ms_total": wall_pt * 1e3,
-                    "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99),
-                                   "nuclei_p50": percentile(nuc, 50), "nuclei_p99": percentile(nuc, 99),
-                                   "spiral_p50": percentile(spi, 50), "spiral_max": max(spi) if spi else None}}
-        log("per-tile: %.0f Mpixel/s, p50 %.2f ms, p99 %.2f ms" % (per_tile["value"], per_tile["latency_ms"]["p50"],
-                                                                   per_tile["latency_ms"]["p99"]))
-
-    # ---- per-kernel durations (HIP events on the launch stream, averaged over the timed steps)
-    avg = lambda k: sum(s[k] for s in kstats) / len(kstats)
-    kernels = {"dense_pass_ms": avg("dense_ms"), "border_seed_ms": avg("seed_ms"),
-               "revisit_drain_ms": avg("drain_ms"), "launch_ms": avg("total_ms"),
-               "revisits": avg("revisits"), "queue_overflows": avg("queue_overflows")}
-    dense_gbs = BYTES_PER_PX * px_total / (kernels["dense_pass_ms"] * 1e-3) / 1e9
-    roofline = {"kernel": "dense_pass", "bound": "hbm", "achieved": dense_gbs, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": dense_gbs / HBM_PEAK_GBS, "traffic": None,
-                "bytes_per_px": BYTES_PER_PX,
-                "whole_launch_GBs": BYTES_PER_PX * px_total / (kernels["launch_ms"] * 1e-3) / 1e9}
+    avg = lambda xs, k: sum(x[k] for x in xs) / len(xs)
+    kernels = {"dilate": {"dense_pass_ms": avg(kd, "dense_ms"), "border_seed_ms": avg(kd, "seed_ms"),
+                          "revisit_drain_ms": avg(kd, "drain_ms"), "launch_ms": avg(kd, "total_ms"),
+                          "revisits": avg(kd, "revisits"), "queue_overflows": avg(kd, "queue_overflows")},
+               "fill_holes": {"dense_pass_ms": avg(kf, "dense_ms"), "border_seed_ms": avg(kf, "seed_ms"),
+                              "revisit_drain_ms": avg(kf, "drain_ms"), "launch_ms": avg(kf, "total_ms"),
+                              "revisits": avg(kf, "revisits")}}
+    # dominant kernel of the step (by average duration) and its roofline
+    cand = [("dense_pass (dilate)", kernels["dilate"]["dense_pass_ms"], BYTES_DILATE * mask.size),
+            ("revisit_drain (dilate)", kernels["dilate"]["revisit_drain_ms"], None),
+            ("dense_pass (fill_holes)", kernels["fill_holes"]["dense_pass_ms"], BYTES_FILL * mask.size),
+            ("revisit_drain (fill_holes)", kernels["fill_holes"]["revisit_drain_ms"], None)]
+    dom = max(cand, key=lambda c: c[1])
+    dense = cand[0]
+    achieved = dense[2] / (dense[1] * 1e-3) / 1e9
+    roofline = {"kernel": dense[0], "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "bytes_per_px": BYTES_DILATE,
+                "dominant_kernel": dom[0], "dominant_ms": dom[1],
+                "step_GBs": (BYTES_DILATE + BYTES_FILL) * mask.size / (ms_per_step * 1e-3) / 1e9}
 
     out = {"metric": METRIC, "value": value, "unit": "Mpixel/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "u8", "data": "synthetic",
-           "config": {"workload": "batch of %d uint8 %dx%d tiles, 8-conn: %d nuclei-like (h=30) + %d spiral corridors"
-                                  % (args.tiles, args.size, args.size,
-                                     sum(b[0] == "nuclei" for b in batch), sum(b[0] == "spiral" for b in batch)),
-                      "tiles": args.tiles, "tile": [args.size, args.size], "conn": 8, "mode": "batched hipGraph",
-                      "block_rows": ctx.cfg.get("block_rows", 32)},
-           "per_tile": per_tile, "kernels": kernels, "roofline": roofline, "parity": parity}
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(batch)
-        log("cpu baseline: %.1f Mpixel/s on %d cores" % (out["cpu_baseline"]["value"], out["cpu_baseline"]["cores"]))
+           "config": {"workload": "one uint8 %dx%d nuclei-like tile: 8-conn reconstruction (marker I-20) + "
+                                  "8-conn fill-holes of I>120; plain per-tile launches" % (args.size, args.size),
+                      "pixels_per_step": px_step, "block_rows": cfg.get("block_rows", 32)},
+           "kernels": kernels, "roofline": roofline, "parity": parity}
     ctx.close()
+    if args.batch_tiles:
+        out["batched_vs_per_tile"] = batched_vs_per_tile(recon, torch, {k: v for k, v in cfg.items()},
+                                                         args.batch_tiles, args.size, args.workers)
+        b = out["batched_vs_per_tile"]
+        log("batch of %d: batched %.0f Mpixel/s vs per-tile %.0f Mpixel/s" % (
+            args.batch_tiles, b["batched"]["Mpixel_s"], b["per_tile"]["Mpixel_s"]))
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(marker, mask, binary)
+        log("cpu baseline: %.1f Mpixel/s on %d cores" % (out["cpu_baseline"]["value"], out["cpu_baseline"]["cores"]))
     print(json.dumps(out), flush=True)
-    if not parity["ok"]:
+    if not (parity["dilate"] and parity["fill_holes"]):
         sys.exit(1)
 
 

@@ -595,6 +595,13 @@ __device__ __forceinline__ bool expired(const KArgs &a, uint64_t start) {
     return wall_clock64() - start > a.watchdog_ticks;
 }
 
+// Idle back-off: about 2^min(k, 6) x 256 cycles, so that hundreds of idle waves
+// do not hammer the scheduler's counters while a few waves work.
+__device__ __forceinline__ void backoff(int k) {
+    const int n = 1 << (k < 6 ? k : 6);
+    for (int i = 0; i < n; ++i) __builtin_amdgcn_s_sleep(4);
+}
+
 // Request a visit of global block `nb` of task `ti`.  Called by all lanes with
 // wave-uniform arguments; lane 0 performs the atomics.  Returns false if the
 // watchdog expired while waiting for a ring slot.
@@ -790,7 +797,7 @@ __global__ __launch_bounds__(64) void revisit_drain(TaskTable tt, KArgs a) {
             if (ln == 0) seen = __hip_atomic_load(&w->progress, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             seen = uniform(seen);
             uint64_t since = wall_clock64();
-            while (true) {
+            for (int spin = 0;; ++spin) {
                 int r = -1;
                 uint32_t pr = 0;
                 if (ln == 0) {
@@ -824,7 +831,7 @@ __global__ __launch_bounds__(64) void revisit_drain(TaskTable tt, KArgs a) {
                     pos = -2;
                     break;
                 }
-                __builtin_amdgcn_s_sleep(2);
+                backoff(spin);
             }
         }
         if (pos == -2) break;
