@@ -523,6 +523,67 @@ __device__ __forceinline__ bool raise_px(Lds<BH> &L, int y, int x, uint32_t targ
     }
 }
 
+// Border seed: after the halo has been refreshed, only pixels on the block's
+// border can be raised by a neighbour (the interior was left converged by the
+// previous visit, and only the owner writes it).  Raise and push exactly those.
+template <int BH>
+__device__ void seed_border(Lds<BH> &L, int conn, int bh, int bw, int qcap, uint32_t head, uint32_t &tail,
+                            bool &overflow, bool &changed) {
+    const int ln = lane_id();
+    // rows 0 and bh-1 (each once): lanes across columns, like the dense seed pass
+    for (int pass = 0; pass < 2; ++pass) {
+        const int r = pass == 0 ? 0 : bh - 1;
+        if (pass == 1 && r == 0) break;
+        const uint32_t a = *L.Jw(r - 1, ln);
+        const uint32_t c = *L.Jw(r, ln);
+        const uint32_t b = *L.Jw(r + 1, ln);
+        uint32_t al, ar, cl, cr, bl, br;
+        side_bytes(L, r - 1, a, al, ar);
+        side_bytes(L, r, c, cl, cr);
+        side_bytes(L, r + 1, b, bl, br);
+        uint32_t m = bmax4(c, bmax4(a, b));
+        m = bmax4(m, bmax4((c << 8) | cl, (c >> 8) | (cr << 24)));
+        if (conn == 8) {
+            m = bmax4(m, bmax4((a << 8) | al, (a >> 8) | (ar << 24)));
+            m = bmax4(m, bmax4((b << 8) | bl, (b >> 8) | (br << 24)));
+        }
+        const uint32_t nv = bmin4(m, *L.Iw(r, ln));
+        const uint32_t dm = diff_bytes(nv, c);
+        if (dm) {
+            *L.Jw(r, ln) = nv;
+            L.rowdirty[r] = 1;
+        }
+        if (__ballot(dm != 0)) changed = true;
+        for (int j = 0; j < 4; ++j) {
+            const bool p = (dm >> j) & 1u;
+            if (!push_bits(L.Q, qcap, head, tail, p, (uint32_t)(r * BW + 4 * ln + j))) overflow = true;
+        }
+    }
+    __syncthreads();
+    // columns 0 and bw-1, rows 1..bh-2: lane r handles row r
+    for (int side = 0; side < 2; ++side) {
+        const int x = side == 0 ? 0 : bw - 1;
+        if (side == 1 && x == 0) break;
+        bool raised = false;
+        const int r = ln;
+        if (r >= 1 && r < bh - 1) {
+            uint32_t m = L.Jb(r, x);
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    if (dx == 0 && dy == 0) continue;
+                    if (conn == 4 && dx != 0 && dy != 0) continue;
+                    m = max(m, (uint32_t)L.Jb(r + dy, x + dx));
+                }
+            const uint32_t nv = min(m, (uint32_t)L.Ib(r, x));
+            if (nv > (uint32_t)L.Jb(r, x)) raised = raise_px(L, r, x, nv);
+            if (raised) L.rowdirty[r] = 1;
+        }
+        if (__ballot(raised)) changed = true;
+        if (!push_bits(L.Q, qcap, head, tail, raised, (uint32_t)(r * BW + x))) overflow = true;
+        __syncthreads();
+    }
+}
+
 // Drain the LDS ring to empty; *overflow set if pushes had to be dropped.
 template <int BH>
 __device__ void drain(Lds<BH> &L, int conn, int qcap, uint32_t &head, uint32_t &tail,
@@ -557,13 +618,19 @@ __device__ void drain(Lds<BH> &L, int conn, int qcap, uint32_t &head, uint32_t &
 }
 
 // Seed and drain until no queue overflow is left; returns true if anything changed.
+// border_only: the first seed looks at the block's border only (valid when the
+// interior is already converged and only the halo changed); re-seeds after a
+// queue overflow are always dense.
 template <int BH>
-__device__ bool converge_block(Lds<BH> &L, int conn, int qcap, Work *w) {
+__device__ bool converge_block(Lds<BH> &L, int conn, int qcap, Work *w, bool border_only, int bh, int bw) {
     bool changed = false;
     for (int round = 0; round <= (1 << 16); ++round) {   // each round raises pixels; bounded anyway
         uint32_t head = 0, tail = 0;
         bool overflow = false;
-        seed_pass<BH>(L, conn, qcap, head, tail, overflow, changed);
+        if (border_only && round == 0)
+            seed_border<BH>(L, conn, bh, bw, qcap, head, tail, overflow, changed);
+        else
+            seed_pass<BH>(L, conn, qcap, head, tail, overflow, changed);
         __syncthreads();
         drain<BH>(L, conn, qcap, head, tail, overflow);
         __syncthreads();
@@ -740,7 +807,7 @@ __global__ __launch_bounds__(64) void dense_pass(TaskTable tt, KArgs a) {
             __syncthreads();
             if (!__ballot(c)) break;
         }
-        converge_block<BH>(L, t.conn, t.qcap, a.work);
+        converge_block<BH>(L, t.conn, t.qcap, a.work, false, g.bh, g.bw);
         store_block<BH>(t, g, L, true);
         if (ln == 0)
             __hip_atomic_fetch_add(&a.work->stat_dense, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -884,7 +951,7 @@ __global__ __launch_bounds__(64) void revisit_drain(TaskTable tt, KArgs a) {
             load_halo<BH>(t, g, L);
             for (int r = ln; r < BH; r += LANES) L.rowdirty[r] = 0;
             __syncthreads();
-            if (converge_block<BH>(L, t.conn, t.qcap, w)) {
+            if (converge_block<BH>(L, t.conn, t.qcap, w, true, g.bh, g.bw)) {
                 store_block<BH>(t, g, L, false);
                 __threadfence();
                 ok = check_neighbours<BH>(a, ring_cap, ti, t, g, by, bx, L);
