@@ -75,21 +75,23 @@ def test_alone_and_in_the_mix(torch_mod, lib, oracle_mod):
 
 def test_admission_backpressure(torch_mod, lib, oracle_mod):
     rng = np.random.default_rng(7)
-    tasks = [_task(rng, 100 + i) for i in range(12)]
+    # a long-running request first (a spiral corridor: one long propagation chain)
+    # keeps its slot busy while the quick ones are submitted back to back
+    s_marker, s_mask, _ = synth.spiral_tile(1024, 1024, "outer")
+    tasks = [{"op": "dilate", "marker": s_marker, "mask": s_mask, "conn": 8}]
+    tasks += [_task(rng, 100 + i) for i in range(12)]
     with lib.Recon(0, serve_slots=3) as ctx:
-        bufs, tickets, again = [], [], 0
-        for t in tasks:
-            m = torch_mod.from_numpy(t["marker"]).cuda()
-            k = torch_mod.from_numpy(t["mask"]).cuda()
-            torch_mod.cuda.synchronize()
-            bufs.append(m)
+        bufs = [(torch_mod.from_numpy(t["marker"]).cuda(), torch_mod.from_numpy(t["mask"]).cuda()) for t in tasks]
+        torch_mod.cuda.synchronize()
+        tickets, again = [], 0
+        for t, (m, k) in zip(tasks, bufs):
             while True:
                 try:
                     tickets.append(ctx.submit("dilate", m, k, t["conn"]))
                     break
                 except lib.ReconAgain:
                     again += 1
-                    # poll the oldest outstanding ticket until it completes
+                    # wait for the oldest outstanding ticket, then try again
                     pending = [tk for tk in tickets if tk is not None]
                     ctx.wait(pending[0], 60_000_000)
                     tickets[tickets.index(pending[0])] = None
@@ -97,11 +99,11 @@ def test_admission_backpressure(torch_mod, lib, oracle_mod):
             if tk is not None:
                 ctx.wait(tk, 60_000_000)
         assert again > 0   # the slot cap of 3 was hit
-        for t, m in zip(tasks, bufs):
+        for t, (m, _) in zip(tasks, bufs):
             assert np.array_equal(m.cpu().numpy(), oracle_mod.run_task(t))
         # stop, then serving restarts on the next submit
         ctx.serve_stop()
-        t = tasks[0]
+        t = tasks[1]
         m = torch_mod.from_numpy(t["marker"]).cuda()
         k = torch_mod.from_numpy(t["mask"]).cuda()
         torch_mod.cuda.synchronize()
