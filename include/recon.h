@@ -84,14 +84,14 @@ typedef struct {
     recon_image mask;
     int32_t scan_rounds;   /* per-task tuning: directional pass rounds (0 = context default,
                               -1 = none, 1..8) */
-    int32_t queue_capacity;/* per-task tuning: LDS queue entries (0 = context default; at most
-                              the context's queue_capacity) */
+    int32_t queue_capacity;/* per-task tuning: LDS queue entries, a power of two (0 = context
+                              default; at most the context's queue_capacity) */
 } recon_task;
 
 /* Tuning and capacity knobs; zero fields take the defaults. */
 typedef struct {
     int32_t block_rows;        /* rows per work block: 16, 32 or 64 (default: tuned) */
-    int32_t queue_capacity;    /* LDS queue entries per workgroup, 64..8192 */
+    int32_t queue_capacity;    /* LDS queue entries per workgroup: a power of two in 64..8192 */
     int32_t scan_rounds;       /* directional pass rounds on a block's first visit,
                                   1..8; 0 = default (2); -1 = none */
     int32_t wg_per_cu;         /* cap on resident workgroups per CU (0 = occupancy limit) */

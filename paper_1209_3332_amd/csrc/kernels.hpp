@@ -53,8 +53,9 @@ constexpr int LANES = 64;
 constexpr int BW = 256;      // block width: 64 lanes x 4 pixels
 constexpr int JP = 268;      // LDS row pitch of J incl. halo columns (67 dwords: odd)
 constexpr int JOFF = 4;      // byte offset of column 0 inside a J row (column -1 at 3)
-constexpr int IP = 260;      // LDS row pitch of I (65 dwords: odd)
 constexpr int MAX_INLINE_TASKS = 12;
+constexpr int RING_STRIDE = 16;       // ring slots are 64 bytes apart (one waiter per slot line)
+constexpr int MAX_DRAIN_GRID = 4096;  // upper bound of the revisit kernel's grid
 
 // block state bits (revisit scheduler)
 constexpr uint32_t ST_R = 2u;  // a wave owns the block
@@ -99,19 +100,24 @@ struct TaskTable {
     TaskDev inl[MAX_INLINE_TASKS];
 };
 
+// Scheduler counters.  Each group sits in a 128-byte line of its own so that
+// waiters polling one of them do not delay updates of the others.
 struct Work {
     uint32_t pending;        // outstanding revisits (queued + running)
-    uint32_t ring_head;
-    uint32_t ring_tail;
     uint32_t abort;          // set by the watchdog: the launch gave up (results incomplete)
+    uint32_t pad0[30];
+    uint32_t ring_head;      // next ticket handed to a waiting wave
+    uint32_t pad1[31];
+    uint32_t ring_tail;      // next ring position a request is written to
+    uint32_t pad2[31];
     uint32_t progress;       // completed revisits (watchdog heartbeat)
-    uint32_t pad0[3];
+    uint32_t pad3[31];
     unsigned long long stat_dense;
     unsigned long long stat_revisit;
     unsigned long long stat_rerun;
     unsigned long long stat_overflow;
     unsigned long long stat_request;
-    unsigned long long pad1[3];
+    unsigned long long pad4[11];
 };
 
 struct KArgs {
@@ -265,25 +271,36 @@ __device__ __forceinline__ uint32_t fill_init4(const TaskDev &t, int gy, int gx,
     return v;
 }
 
+// Per-wave statistics (meaningful in lane 0), added to the global counters
+// once when the wave leaves a kernel.
+struct WaveStats {
+    unsigned long long dense = 0, revisit = 0, rerun = 0, overflow = 0, request = 0;
+};
+
 // ---------------------------------------------------------------------------
 // per-visit LDS layout
+// J and I share one geometry: (BH + 2) rows of JP bytes, pixel (y, x) at
+// (y + 1) * JP + JOFF + x for y in -1..BH and x in -1..BW (the halo ring holds
+// the neighbours' marker, clipped, and mask).
 template <int BH>
 struct Lds {
-    uint8_t *J;          // (BH + 2) rows of JP bytes; pixel (y, x) at (y + 1) * JP + JOFF + x
-    uint8_t *I;          // BH rows of IP bytes
+    uint8_t *J;
+    uint8_t *I;
     uint8_t *rowdirty;   // BH bytes
-    uint16_t *Q;         // queue ring
+    uint16_t *Q;         // queue ring (power-of-two entries)
     __device__ __forceinline__ uint32_t *Jw(int y, int d) {  // dword d of row y (y in -1..BH)
         return (uint32_t *)(J + (y + 1) * JP + JOFF + 4 * d);
     }
-    __device__ __forceinline__ uint32_t *Iw(int y, int d) { return (uint32_t *)(I + y * IP + 4 * d); }
+    __device__ __forceinline__ uint32_t *Iw(int y, int d) {
+        return (uint32_t *)(I + (y + 1) * JP + JOFF + 4 * d);
+    }
     __device__ __forceinline__ uint8_t &Jb(int y, int x) { return J[(y + 1) * JP + JOFF + x]; }
-    __device__ __forceinline__ uint8_t &Ib(int y, int x) { return I[y * IP + x]; }
+    __device__ __forceinline__ uint8_t &Ib(int y, int x) { return I[(y + 1) * JP + JOFF + x]; }
 };
 
 template <int BH>
 __host__ __device__ constexpr size_t lds_bytes(int qcap) {
-    return (size_t)(BH + 2) * JP + (size_t)BH * IP + (size_t)((BH + 15) & ~15) + 2u * (size_t)qcap;
+    return 2 * (size_t)(BH + 2) * JP + (size_t)((BH + 15) & ~15) + 2u * (size_t)qcap;
 }
 
 // Base of the workgroup's dynamic LDS.  (A host build of these kernels for
@@ -300,7 +317,7 @@ __device__ __forceinline__ Lds<BH> lds_layout() {
     Lds<BH> L;
     L.J = dyn_lds();
     L.I = L.J + (BH + 2) * JP;
-    L.rowdirty = L.I + BH * IP;
+    L.rowdirty = L.I + (BH + 2) * JP;
     L.Q = (uint16_t *)(L.rowdirty + ((BH + 15) & ~15));
     return L;
 }
@@ -352,35 +369,59 @@ __device__ void clear_halo(Lds<BH> &L) {
     const int ln = lane_id();
     *L.Jw(-1, ln) = 0u;
     *L.Jw(BH, ln) = 0u;
+    *L.Iw(-1, ln) = 0u;
+    *L.Iw(BH, ln) = 0u;
     for (int r = ln - 1; r <= BH; r += LANES) {
         L.Jb(r, -1) = 0;
         L.Jb(r, BW) = 0;
+        L.Ib(r, -1) = 0;
+        L.Ib(r, BW) = 0;
     }
 }
 
-// Load the one-pixel ring of neighbour marker values, each clipped under its
-// own mask (0 outside the image).
+// Load the one-pixel ring of neighbour pixels: mask, and marker clipped under
+// it (both 0 outside the image).
 template <int BH>
 __device__ void load_halo(const TaskDev &t, const BlockGeom &g, Lds<BH> &L) {
     const int ln = lane_id();
     const int x = 4 * ln;
     const int valid = min(4, g.bw - x);
-    uint32_t top = 0, bot = 0;
-    if (g.has_n) top = marker4(t, g.y0 - 1, g.x0 + x, valid);
-    if (g.has_s) bot = marker4(t, g.y0 + BH, g.x0 + x, valid);
-    *L.Jw(-1, ln) = top;
-    *L.Jw(BH, ln) = bot;
+    uint32_t ti = 0, tj = 0, bi = 0, bj = 0;
+    if (g.has_n && valid > 0) {
+        ti = mask4(t, g.y0 - 1, g.x0 + x, valid);
+        tj = gload4(t.j + (int64_t)(g.y0 - 1) * t.pitch_j, g.x0 + x, valid, t.aligned);
+    }
+    if (g.has_s && valid > 0) {
+        bi = mask4(t, g.y0 + BH, g.x0 + x, valid);
+        bj = gload4(t.j + (int64_t)(g.y0 + BH) * t.pitch_j, g.x0 + x, valid, t.aligned);
+    }
     // columns -1 and 256 for rows -1..BH (lane k handles row k-1)
-    const bool west = g.has_w;
-    const bool east = g.has_e;
-    for (int r = ln - 1; r <= BH; r += LANES) {
+    uint32_t wi[2] = {0, 0}, wj[2] = {0, 0}, ei[2] = {0, 0}, ej[2] = {0, 0};
+    for (int k = 0; k < 2; ++k) {
+        const int r = ln - 1 + k * LANES;
+        if (r > BH) break;
         const bool row_in = (r >= 0 && r < g.bh) || (r == -1 && g.has_n) || (r == BH && g.has_s);
         const int gy = g.y0 + r;
-        uint32_t wv = 0, ev = 0;
-        if (row_in && west) wv = marker1(t, gy, g.x0 - 1);
-        if (row_in && east) ev = marker1(t, gy, g.x0 + BW);
-        L.Jb(r, -1) = (uint8_t)wv;
-        L.Jb(r, BW) = (uint8_t)ev;
+        if (row_in && g.has_w) {
+            wi[k] = mask1(t, gy, g.x0 - 1);
+            wj[k] = t.j[(int64_t)gy * t.pitch_j + g.x0 - 1];
+        }
+        if (row_in && g.has_e) {
+            ei[k] = mask1(t, gy, g.x0 + BW);
+            ej[k] = t.j[(int64_t)gy * t.pitch_j + g.x0 + BW];
+        }
+    }
+    *L.Iw(-1, ln) = ti;
+    *L.Jw(-1, ln) = bmin4(tj, ti);
+    *L.Iw(BH, ln) = bi;
+    *L.Jw(BH, ln) = bmin4(bj, bi);
+    for (int k = 0; k < 2; ++k) {
+        const int r = ln - 1 + k * LANES;
+        if (r > BH) break;
+        L.Ib(r, -1) = (uint8_t)wi[k];
+        L.Jb(r, -1) = (uint8_t)min(wj[k], wi[k]);
+        L.Ib(r, BW) = (uint8_t)ei[k];
+        L.Jb(r, BW) = (uint8_t)min(ej[k], ei[k]);
     }
 }
 
@@ -461,17 +502,26 @@ __device__ bool hpass(Lds<BH> &L, int conn, int dir) {
     return changed;
 }
 
-// push the pixels flagged by `pred` (one per lane) onto the LDS ring;
-// returns false (and pushes nothing) if they do not fit.
+// push the pixels flagged by `pred` (one per lane) onto the LDS ring of qcap
+// (a power of two) entries; returns false (and pushes nothing) if they do not fit.
 __device__ __forceinline__ bool push_bits(uint16_t *Q, int qcap, uint32_t head, uint32_t &tail,
                                           bool pred, uint32_t pix) {
     const unsigned long long m = __ballot(pred);
     if (m == 0) return true;
     const uint32_t cnt = (uint32_t)__popcll(m);
     if (tail - head + cnt > (uint32_t)qcap) return false;
-    if (pred) Q[(tail + prefix_count(m)) % (uint32_t)qcap] = (uint16_t)pix;
+    if (pred) Q[(tail + prefix_count(m)) & (uint32_t)(qcap - 1)] = (uint16_t)pix;
     tail += cnt;
     return true;
+}
+
+// Ordering point for LDS accesses between the lanes of one wave.  A wave's LDS
+// operations execute in issue order, so keeping the compiler from moving
+// accesses across this point is all that is needed for one lane to see what
+// another lane of the same wave stored before it.
+__device__ __forceinline__ void lds_order() {
+    __builtin_amdgcn_wave_barrier();
+    __asm__ __volatile__("" ::: "memory");
 }
 
 // Seed pass: raise every pixel that a neighbour (block or halo) can raise and push it.
@@ -508,19 +558,15 @@ __device__ void seed_pass(Lds<BH> &L, int conn, int qcap, uint32_t head, uint32_
 }
 
 // Raise J(y, x) to `target` if lower; returns true if this lane raised it.
+// A byte store: within one call site the lanes of the wave write distinct
+// pixels (or the same pixel with the same value), and calls are separated by
+// lds_order(), so no raise is ever lost.
 template <int BH>
 __device__ __forceinline__ bool raise_px(Lds<BH> &L, int y, int x, uint32_t target) {
-    const int off = (y + 1) * JP + JOFF + x;
-    uint32_t *wp = (uint32_t *)(L.J + (off & ~3));
-    const int sh = 8 * (off & 3);
-    uint32_t old = *wp;
-    while (true) {
-        if (((old >> sh) & 0xffu) >= target) return false;
-        const uint32_t nw = (old & ~(0xffu << sh)) | (target << sh);
-        const uint32_t prev = atomicCAS(wp, old, nw);
-        if (prev == old) return true;
-        old = prev;
-    }
+    uint8_t &b = L.Jb(y, x);
+    if ((uint32_t)b >= target) return false;
+    b = (uint8_t)target;
+    return true;
 }
 
 // Border seed: after the halo has been refreshed, only pixels on the block's
@@ -596,24 +642,26 @@ __device__ void drain(Lds<BH> &L, int conn, int qcap, uint32_t &head, uint32_t &
         const uint32_t n = min(tail - head, (uint32_t)LANES);
         const bool valid = (uint32_t)ln < n;
         uint32_t p = 0;
-        if (valid) p = L.Q[(head + ln) % (uint32_t)qcap];
+        if (valid) p = L.Q[(head + ln) & (uint32_t)(qcap - 1)];
         head += n;
-        __syncthreads();
         const int y = (int)(p >> 8), x = (int)(p & 255u);
         const uint32_t v = valid ? (uint32_t)L.Jb(y, x) : 0u;
+        // the mask never changes: all neighbours' mask values up front (a
+        // block pixel's neighbours lie in the LDS planes, the halo ring at worst)
+        uint32_t iv[8];
+        for (int k = 0; k < ndir; ++k) iv[k] = valid ? (uint32_t)L.Ib(y + dys[k], x + dxs[k]) : 0u;
         for (int k = 0; k < ndir; ++k) {
             const int ny = y + dys[k], nx = x + dxs[k];
             bool raised = false;
-            if (valid && ny >= 0 && ny < BH && nx >= 0 && nx < BW) {
-                const uint32_t tgt = min(v, (uint32_t)L.Ib(ny, nx));
-                if ((uint32_t)L.Jb(ny, nx) < tgt) {
-                    raised = raise_px(L, ny, nx, tgt);
-                    if (raised) L.rowdirty[ny] = 1;
-                }
+            const bool inside = ny >= 0 && ny < BH && nx >= 0 && nx < BW;
+            if (valid && inside) {
+                const uint32_t tgt = min(v, iv[k]);
+                raised = raise_px(L, ny, nx, tgt);
+                if (raised) L.rowdirty[ny] = 1;
             }
             if (!push_bits(L.Q, qcap, head, tail, raised, (uint32_t)(ny * BW + nx))) overflow = true;
+            lds_order();
         }
-        __syncthreads();
     }
 }
 
@@ -622,7 +670,7 @@ __device__ void drain(Lds<BH> &L, int conn, int qcap, uint32_t &head, uint32_t &
 // interior is already converged and only the halo changed); re-seeds after a
 // queue overflow are always dense.
 template <int BH>
-__device__ bool converge_block(Lds<BH> &L, int conn, int qcap, Work *w, bool border_only, int bh, int bw) {
+__device__ bool converge_block(Lds<BH> &L, int conn, int qcap, WaveStats &st, bool border_only, int bh, int bw) {
     bool changed = false;
     for (int round = 0; round <= (1 << 16); ++round) {   // each round raises pixels; bounded anyway
         uint32_t head = 0, tail = 0;
@@ -635,8 +683,7 @@ __device__ bool converge_block(Lds<BH> &L, int conn, int qcap, Work *w, bool bor
         drain<BH>(L, conn, qcap, head, tail, overflow);
         __syncthreads();
         if (!__ballot(overflow)) break;
-        if (lane_id() == 0)
-            __hip_atomic_fetch_add(&w->stat_overflow, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        st.overflow += 1;
     }
     for (int r = 0; r < BH; ++r)
         if (L.rowdirty[r]) changed = true;
@@ -662,63 +709,88 @@ __device__ __forceinline__ bool expired(const KArgs &a, uint64_t start) {
     return wall_clock64() - start > a.watchdog_ticks;
 }
 
-// Idle back-off: about 2^min(k, 6) x 256 cycles, so that hundreds of idle waves
-// do not hammer the scheduler's counters while a few waves work.
+// Idle back-off: about 2^min(k, 7) x 512 cycles (up to ~27 us), so that
+// thousands of idle waves do not hammer the memory system while a few work.
 __device__ __forceinline__ void backoff(int k) {
-    const int n = 1 << (k < 6 ? k : 6);
-    for (int i = 0; i < n; ++i) __builtin_amdgcn_s_sleep(4);
+    const int n = 1 << (k < 7 ? k : 7);
+    for (int i = 0; i < n; ++i) __builtin_amdgcn_s_sleep(8);
+}
+
+__device__ __forceinline__ void flush_stats(Work *w, const WaveStats &st) {
+    if (lane_id() != 0) return;
+    if (st.dense) __hip_atomic_fetch_add(&w->stat_dense, st.dense, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (st.revisit) __hip_atomic_fetch_add(&w->stat_revisit, st.revisit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (st.rerun) __hip_atomic_fetch_add(&w->stat_rerun, st.rerun, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (st.overflow)
+        __hip_atomic_fetch_add(&w->stat_overflow, st.overflow, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (st.request)
+        __hip_atomic_fetch_add(&w->stat_request, st.request, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Request a visit of global block `nb` of task `ti`.  Called by all lanes with
-// wave-uniform arguments; lane 0 performs the atomics.  Returns false if the
-// watchdog expired while waiting for a ring slot.
-__device__ bool request_block(const KArgs &a, uint32_t ring_cap, int ti, uint32_t nb) {
+// wave-uniform arguments; lane 0 performs the atomics.  If the block was idle
+// it is queued: kept by the calling wave for its next visit when `keep` points
+// to -1 (the wave's own continuation, no ring round trip), otherwise written to
+// the ring.  Returns false if the watchdog expired while waiting for a ring slot.
+__device__ bool request_block(const KArgs &a, uint32_t ring_cap, int ti, uint32_t nb, int *keep,
+                              WaveStats &st) {
     const int ln = lane_id();
-    int pos = -1;
+    const bool may_keep = keep != nullptr && *keep < 0;
+    int pos = -1;   // >= 0 ring position; -2 kept; -1 nothing to do
     if (ln == 0) {
         const uint32_t old = __hip_atomic_fetch_or(a.state + nb, ST_D, __ATOMIC_ACQ_REL,
                                                    __HIP_MEMORY_SCOPE_AGENT);
         if (!(old & (ST_R | ST_D))) {   // the block was idle: queue it
             __hip_atomic_fetch_add(a.tile_pending + ti, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_fetch_add(&a.work->pending, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_add(&a.work->stat_request, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            pos = (int)(__hip_atomic_fetch_add(&a.work->ring_tail, 1u, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT) % ring_cap);
+            st.request += 1;
+            if (may_keep)
+                pos = -2;
+            else
+                pos = (int)(__hip_atomic_fetch_add(&a.work->ring_tail, 1u, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT) % ring_cap);
         }
     }
     pos = uniform(pos);
+    if (pos == -2) {
+        *keep = (int)nb;
+        return true;
+    }
     if (pos < 0) return true;
+    uint32_t *slot = a.ring + (size_t)pos * RING_STRIDE;
     // the slot is free unless its previous occupant has not been taken out yet
     const uint64_t t0 = wall_clock64();
     while (true) {
         int busy = 0;
-        if (ln == 0) busy = __hip_atomic_load(a.ring + pos, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
+        if (ln == 0) busy = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
         if (!uniform(busy)) break;
         if (expired(a, t0)) return false;
         __builtin_amdgcn_s_sleep(1);
     }
-    if (ln == 0) __hip_atomic_store(a.ring + pos, nb + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (ln == 0) __hip_atomic_store(slot, nb + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     return true;
 }
 
-// Border checks: request every neighbouring block whose pixels the block's
-// border (in LDS rows 0 / bh-1 and columns 0 / bw-1) can still raise.
-// Neighbour pixels are read from global memory, clipped under their mask.
+// Border checks from LDS: request every neighbouring block that a pixel of
+// this block's border (rows 0 / bh-1, columns 0 / bw-1) can still raise,
+// judged against the halo ring (neighbour marker clipped under its mask, as
+// loaded).  A halo value may be older than the neighbour's current one, but
+// never higher, so a needed request is never missed; a stale one only costs a
+// visit that finds nothing to do.
 template <int BH>
 __device__ bool check_neighbours(const KArgs &a, uint32_t ring_cap, int ti, const TaskDev &t,
-                                 const BlockGeom &g, int by, int bx, Lds<BH> &L) {
+                                 const BlockGeom &g, int by, int bx, Lds<BH> &L, int *keep,
+                                 WaveStats &st) {
     const int ln = lane_id();
     const int conn = t.conn;
     const uint32_t gb = t.block0 + (uint32_t)(by * t.nbx + bx);
     uint32_t want = 0;   // bit k: request neighbour k (N, S, W, E, NW, NE, SW, SE)
     {   // N and S edges: lane handles columns 4ln..4ln+3
-        const int x = 4 * ln;
-        const int valid = min(4, g.bw - x);
         for (int side = 0; side < 2; ++side) {
             const bool exists = side == 0 ? g.has_n : g.has_s;
             if (!exists) continue;
             const int r = side == 0 ? 0 : g.bh - 1;
-            const int gy = side == 0 ? g.y0 - 1 : g.y0 + BH;
+            const int hr = side == 0 ? -1 : BH;
             const uint32_t c = *L.Jw(r, ln);
             uint32_t out = c;
             if (conn == 8) {
@@ -727,12 +799,8 @@ __device__ bool check_neighbours(const KArgs &a, uint32_t ring_cap, int ti, cons
                 const uint32_t rr = ln == LANES - 1 ? 0u : (dn & 0xffu);
                 out = bmax4(out, bmax4((c << 8) | l, (c >> 8) | (rr << 24)));
             }
-            bool viol = false;
-            if (valid > 0) {
-                const uint32_t ni = mask4(t, gy, g.x0 + x, valid);
-                const uint32_t nj = bmin4(gload4(t.j + (int64_t)gy * t.pitch_j, g.x0 + x, valid, t.aligned), ni);
-                viol = bmax4(nj, bmin4(out, ni)) != nj;
-            }
+            const uint32_t nj = *L.Jw(hr, ln);
+            const bool viol = bmax4(nj, bmin4(out, *L.Iw(hr, ln))) != nj;
             if (__ballot(viol)) want |= 1u << side;
         }
     }
@@ -742,7 +810,7 @@ __device__ bool check_neighbours(const KArgs &a, uint32_t ring_cap, int ti, cons
             const bool exists = side == 0 ? g.has_w : g.has_e;
             if (!exists) continue;
             const int cx = side == 0 ? 0 : g.bw - 1;
-            const int gx = side == 0 ? g.x0 - 1 : g.x0 + BW;
+            const int hx = side == 0 ? -1 : BW;
             bool viol = false;
             if (r < g.bh) {
                 uint32_t out = L.Jb(r, cx);
@@ -750,8 +818,7 @@ __device__ bool check_neighbours(const KArgs &a, uint32_t ring_cap, int ti, cons
                     if (r > 0) out = max(out, (uint32_t)L.Jb(r - 1, cx));
                     if (r + 1 < g.bh) out = max(out, (uint32_t)L.Jb(r + 1, cx));
                 }
-                const int gy = g.y0 + r;
-                viol = marker1(t, gy, gx) < min(out, mask1(t, gy, gx));
+                viol = (uint32_t)L.Jb(r, hx) < min(out, (uint32_t)L.Ib(r, hx));
             }
             if (__ballot(viol)) want |= 4u << side;
         }
@@ -764,9 +831,9 @@ __device__ bool check_neighbours(const KArgs &a, uint32_t ring_cap, int ti, cons
             if (ex) {
                 const int r = north ? 0 : g.bh - 1;
                 const int cx = west ? 0 : g.bw - 1;
-                const int gy = north ? g.y0 - 1 : g.y0 + BH;
-                const int gx = west ? g.x0 - 1 : g.x0 + BW;
-                viol = marker1(t, gy, gx) < min((uint32_t)L.Jb(r, cx), mask1(t, gy, gx));
+                const int hr = north ? -1 : BH;
+                const int hx = west ? -1 : BW;
+                viol = (uint32_t)L.Jb(hr, hx) < min((uint32_t)L.Jb(r, cx), (uint32_t)L.Ib(hr, hx));
             }
         }
         want |= (uint32_t)(__ballot(viol) & 0xfull) << 4;
@@ -776,7 +843,7 @@ __device__ bool check_neighbours(const KArgs &a, uint32_t ring_cap, int ti, cons
     const int offs[8] = {-nbx, nbx, -1, 1, -nbx - 1, -nbx + 1, nbx - 1, nbx + 1};
     for (int k = 0; k < 8; ++k)
         if (want & (1u << k))
-            if (!request_block(a, ring_cap, ti, (uint32_t)((int)gb + offs[k]))) return false;
+            if (!request_block(a, ring_cap, ti, (uint32_t)((int)gb + offs[k]), keep, st)) return false;
     return true;
 }
 
@@ -788,6 +855,7 @@ __global__ __launch_bounds__(64) void dense_pass(TaskTable tt, KArgs a) {
     Lds<BH> L = lds_layout<BH>();
     const int ln = lane_id();
     const uint32_t total = total_blocks_of(tt);
+    WaveStats st;
     for (uint32_t gb = blockIdx.x; gb < total; gb += gridDim.x) {
         const int ti = uniform(find_task(tt, gb));
         const TaskDev t = task_of(tt, ti);
@@ -807,12 +875,12 @@ __global__ __launch_bounds__(64) void dense_pass(TaskTable tt, KArgs a) {
             __syncthreads();
             if (!__ballot(c)) break;
         }
-        converge_block<BH>(L, t.conn, t.qcap, a.work, false, g.bh, g.bw);
+        converge_block<BH>(L, t.conn, t.qcap, st, false, g.bh, g.bw);
         store_block<BH>(t, g, L, true);
-        if (ln == 0)
-            __hip_atomic_fetch_add(&a.work->stat_dense, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        st.dense += 1;
         __syncthreads();
     }
+    flush_stats(a.work, st);
 }
 
 // K2: border seeding.  Each block's border against its neighbours.
@@ -823,31 +891,96 @@ __global__ __launch_bounds__(64) void border_seed(TaskTable tt, KArgs a) {
     const int ln = lane_id();
     const uint32_t total = total_blocks_of(tt);
     const uint32_t ring_cap = ring_cap_of(tt);
+    WaveStats st;
     for (uint32_t gb = blockIdx.x; gb < total; gb += gridDim.x) {
         const int ti = uniform(find_task(tt, gb));
         const TaskDev t = task_of(tt, ti);
         const int lb = (int)(gb - t.block0);
         const int by = lb / t.nbx, bx = lb % t.nbx;
         const BlockGeom g = geom<BH>(t, by, bx);
-        // border rows and columns of the block's current marker into LDS
+        // border rows and columns of the block's current marker, and the halo
         const int x = 4 * ln;
         const int valid = min(4, g.bw - x);
-        *L.Jw(0, ln) = marker4(t, g.y0, g.x0 + x, valid);
-        *L.Jw(g.bh - 1, ln) = marker4(t, g.y0 + g.bh - 1, g.x0 + x, valid);
-        for (int r = ln; r < g.bh; r += LANES) {
-            L.Jb(r, 0) = (uint8_t)marker1(t, g.y0 + r, g.x0);
-            L.Jb(r, g.bw - 1) = (uint8_t)marker1(t, g.y0 + r, g.x0 + g.bw - 1);
+        const uint32_t top = marker4(t, g.y0, g.x0 + x, valid);
+        const uint32_t bot = marker4(t, g.y0 + g.bh - 1, g.x0 + x, valid);
+        uint32_t lft[2] = {0, 0}, rgt[2] = {0, 0};
+        for (int k = 0; k < 2; ++k) {
+            const int r = ln + k * LANES;
+            if (r < g.bh) {
+                lft[k] = marker1(t, g.y0 + r, g.x0);
+                rgt[k] = marker1(t, g.y0 + r, g.x0 + g.bw - 1);
+            }
+        }
+        load_halo<BH>(t, g, L);
+        *L.Jw(0, ln) = top;
+        *L.Jw(g.bh - 1, ln) = bot;
+        for (int k = 0; k < 2; ++k) {
+            const int r = ln + k * LANES;
+            if (r < g.bh) {
+                L.Jb(r, 0) = (uint8_t)lft[k];
+                L.Jb(r, g.bw - 1) = (uint8_t)rgt[k];
+            }
         }
         __syncthreads();
-        if (!check_neighbours<BH>(a, ring_cap, ti, t, g, by, bx, L)) {
+        if (!check_neighbours<BH>(a, ring_cap, ti, t, g, by, bx, L, nullptr, st)) {
             if (ln == 0) __hip_atomic_store(&a.work->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            return;
+            break;
         }
         __syncthreads();
     }
+    flush_stats(a.work, st);
 }
 
 // K3: revisit scheduler.
+//
+// A wave without a block of its own takes a ticket (the next ring position)
+// and waits on that position's slot alone, so idle waves spread their polling
+// over separate lines.  It leaves when the count of outstanding visits is zero
+// (no visit is running or queued, so no request can come any more).
+
+// Wait for the block id at ticket `pos`.  Returns the global block id, -1 when
+// all work is done, -2 on abort (watchdog).
+__device__ int wait_ticket(const KArgs &a, uint32_t pos) {
+    const int ln = lane_id();
+    Work *w = a.work;
+    uint32_t *slot = a.ring + (size_t)pos * RING_STRIDE;
+    uint32_t seen = 0;
+    if (ln == 0) seen = __hip_atomic_load(&w->progress, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    seen = uniform(seen);
+    uint64_t since = wall_clock64();
+    for (int spin = 0;; ++spin) {
+        int v = 0, done = 0;
+        if (ln == 0) {
+            v = (int)__hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (v != 0) {
+                __hip_atomic_store(slot, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            } else if ((spin & 3) == 0) {
+                if (__hip_atomic_load(&w->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                    done = 2;
+                else if (__hip_atomic_load(&w->pending, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u)
+                    done = 1;
+            }
+        }
+        v = uniform(v);
+        done = uniform(done);
+        if (v != 0) return v - 1;
+        if (done) return -done;
+        if ((spin & 15) == 15) {   // watchdog: no visit completed for too long
+            uint32_t pr = 0;
+            if (ln == 0) pr = __hip_atomic_load(&w->progress, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            pr = uniform(pr);
+            const uint64_t now = wall_clock64();
+            if (pr != seen) {
+                seen = pr;
+                since = now;
+            } else if (now - since > a.watchdog_ticks) {
+                if (ln == 0) __hip_atomic_store(&w->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                return -2;
+            }
+        }
+        backoff(spin);
+    }
+}
 
 template <int BH>
 __global__ __launch_bounds__(64) void revisit_drain(TaskTable tt, KArgs a) {
@@ -855,73 +988,19 @@ __global__ __launch_bounds__(64) void revisit_drain(TaskTable tt, KArgs a) {
     const int ln = lane_id();
     Work *w = a.work;
     const uint32_t ring_cap = ring_cap_of(tt);
+    WaveStats st;
+    int keep = -1;   // block this wave requested and keeps for its next visit
 
     while (true) {
-        // ---- acquire a ring position (or learn that everything is done)
-        int pos = -1;   // >= 0: ring position we own; -2: exit
-        {
-            uint32_t seen = 0;
-            if (ln == 0) seen = __hip_atomic_load(&w->progress, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            seen = uniform(seen);
-            uint64_t since = wall_clock64();
-            for (int spin = 0;; ++spin) {
-                int r = -1;
-                uint32_t pr = 0;
-                if (ln == 0) {
-                    if (__hip_atomic_load(&w->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                        r = -2;
-                    } else {
-                        uint32_t h = __hip_atomic_load(&w->ring_head, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-                        const uint32_t tl = __hip_atomic_load(&w->ring_tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-                        if (h != tl) {
-                            if (__hip_atomic_compare_exchange_strong(&w->ring_head, &h, h + 1u, __ATOMIC_ACQ_REL,
-                                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-                                r = (int)(h % ring_cap);
-                        } else if (__hip_atomic_load(&w->pending, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
-                            r = -2;
-                        }
-                    }
-                    pr = __hip_atomic_load(&w->progress, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                }
-                r = uniform(r);
-                pr = uniform(pr);
-                if (r != -1) {
-                    pos = r;
-                    break;
-                }
-                const uint64_t now = wall_clock64();
-                if (pr != seen) {
-                    seen = pr;
-                    since = now;
-                } else if (now - since > a.watchdog_ticks) {
-                    if (ln == 0) __hip_atomic_store(&w->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    pos = -2;
-                    break;
-                }
-                backoff(spin);
-            }
-        }
-        if (pos == -2) break;
-        // ---- take the block id out of the slot (its producer may still be writing it)
-        int gsel = -1;
-        {
-            const uint64_t t0 = wall_clock64();
-            while (true) {
-                int v = 0;
-                if (ln == 0)
-                    v = (int)__hip_atomic_exchange(a.ring + pos, 0u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-                v = uniform(v);
-                if (v != 0) {
-                    gsel = v - 1;
-                    break;
-                }
-                if (expired(a, t0)) break;
-                __builtin_amdgcn_s_sleep(1);
-            }
-        }
+        int gsel = keep;
+        keep = -1;
         if (gsel < 0) {
-            if (ln == 0) __hip_atomic_store(&w->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            break;
+            uint32_t ticket = 0;
+            if (ln == 0)
+                ticket = __hip_atomic_fetch_add(&w->ring_head, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            ticket = uniform(ticket);
+            gsel = wait_ticket(a, ticket % ring_cap);
+            if (gsel < 0) break;
         }
 
         const uint32_t gb = (uint32_t)gsel;
@@ -931,7 +1010,8 @@ __global__ __launch_bounds__(64) void revisit_drain(TaskTable tt, KArgs a) {
         const int by = lb / t.nbx, bx = lb % t.nbx;
         const BlockGeom g = geom<BH>(t, by, bx);
 
-        // ---- claim: clear D, set R
+        // ---- claim: clear D, set R (acquire: the previous owner's stores and
+        // the requester's are visible from here on)
         if (ln == 0) {
             uint32_t s = __hip_atomic_load(a.state + gb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             for (int k = 0; k < 1024; ++k) {
@@ -940,7 +1020,7 @@ __global__ __launch_bounds__(64) void revisit_drain(TaskTable tt, KArgs a) {
                                                          __HIP_MEMORY_SCOPE_AGENT))
                     break;
             }
-            __hip_atomic_fetch_add(&w->stat_revisit, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            st.revisit += 1;
         }
         __threadfence();
         __syncthreads();
@@ -951,10 +1031,10 @@ __global__ __launch_bounds__(64) void revisit_drain(TaskTable tt, KArgs a) {
             load_halo<BH>(t, g, L);
             for (int r = ln; r < BH; r += LANES) L.rowdirty[r] = 0;
             __syncthreads();
-            if (converge_block<BH>(L, t.conn, t.qcap, w, true, g.bh, g.bw)) {
+            if (converge_block<BH>(L, t.conn, t.qcap, st, true, g.bh, g.bw)) {
                 store_block<BH>(t, g, L, false);
                 __threadfence();
-                ok = check_neighbours<BH>(a, ring_cap, ti, t, g, by, bx, L);
+                ok = check_neighbours<BH>(a, ring_cap, ti, t, g, by, bx, L, &keep, st);
             }
             // ---- finish: re-run if requested meanwhile, else release
             int rerun = 0;
@@ -968,8 +1048,7 @@ __global__ __launch_bounds__(64) void revisit_drain(TaskTable tt, KArgs a) {
                         break;
                     }
                 }
-                if (rerun)
-                    __hip_atomic_fetch_add(&w->stat_rerun, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (rerun) st.rerun += 1;
             }
             rerun = uniform(rerun);
             __threadfence();
@@ -988,6 +1067,7 @@ __global__ __launch_bounds__(64) void revisit_drain(TaskTable tt, KArgs a) {
         }
         if (!ok) break;
     }
+    flush_stats(w, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -1014,7 +1094,7 @@ __global__ void reset_work(TaskTable tt, Work *w, uint32_t *state, uint32_t *rin
         w->stat_dense = w->stat_revisit = w->stat_rerun = w->stat_overflow = w->stat_request = 0;
     }
     for (uint32_t i = tid; i < total; i += nth) state[i] = 0;
-    for (uint32_t i = tid; i < ring_cap; i += nth) ring[i] = 0;
+    for (uint32_t i = tid; i < ring_cap; i += nth) ring[(size_t)i * RING_STRIDE] = 0;
     for (uint32_t i = tid; i < n_tasks; i += nth) {
         tile_pending[i] = 0;
         tile_done[i] = 0;

@@ -139,6 +139,10 @@ int ensure_device(recon_ctx *c) {
     return RECON_OK;
 }
 
+// Ring positions for a workspace of n_blocks blocks: every block is in the ring
+// at most once, and each wave of the revisit grid may hold one ticket ahead.
+size_t ring_slots(size_t n_blocks) { return n_blocks + rk::MAX_DRAIN_GRID + 1; }
+
 int resident_wgs(recon_ctx *c, int v) {
     if (c->resident[v] == 0) {
         int per_cu = 0;
@@ -190,7 +194,7 @@ int ensure_capacity(recon_ctx *c, size_t n_tasks, size_t n_blocks, size_t scratc
     if (hipMalloc(&c->d_table, table) != hipSuccess ||
         hipMalloc(&c->d_work, sizeof(rk::Work)) != hipSuccess ||
         hipMalloc(&c->d_state, nb * sizeof(uint32_t)) != hipSuccess ||
-        hipMalloc(&c->d_ring, (nb + 1) * sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc(&c->d_ring, ring_slots(nb) * rk::RING_STRIDE * sizeof(uint32_t)) != hipSuccess ||
         hipMalloc(&c->d_tile_pending, nt * sizeof(uint32_t)) != hipSuccess ||
         hipMalloc(&c->d_tile_done, nt * sizeof(uint32_t)) != hipSuccess ||
         (ns > 0 && hipMalloc(&c->d_scratch, ns) != hipSuccess)) {
@@ -232,8 +236,10 @@ int check_task(const recon_task &t, const recon_config *cfg = nullptr) {
         return fail(RECON_EINVAL, "unknown op %d", t.op);
     if (t.scan_rounds < -1 || t.scan_rounds > 8) return fail(RECON_EINVAL, "task scan_rounds must be in -1..8");
     if (t.queue_capacity != 0 &&
-        (t.queue_capacity < 64 || (cfg && t.queue_capacity > cfg->queue_capacity)))
-        return fail(RECON_EINVAL, "task queue_capacity must be in 64..%d", cfg ? cfg->queue_capacity : 8192);
+        (t.queue_capacity < 64 || (cfg && t.queue_capacity > cfg->queue_capacity) ||
+         (t.queue_capacity & (t.queue_capacity - 1)) != 0))
+        return fail(RECON_EINVAL, "task queue_capacity must be a power of two in 64..%d",
+                    cfg ? cfg->queue_capacity : 8192);
     if (t.conn != 4 && t.conn != 8) return fail(RECON_EINVAL, "conn must be 4 or 8, got %d", t.conn);
     int rc = check_image(&t.image, t.op == RECON_OP_DILATE ? "marker" : "image");
     if (rc) return rc;
@@ -310,7 +316,8 @@ int enqueue_kernels(recon_ctx *c, int v, const rk::TaskTable &tt, uint32_t total
     // graphs), launch enough workgroups for the largest batch the workspace holds.
     const uint32_t nblk = dynamic_sizes ? (uint32_t)c->cap_blocks : total_blocks;
     const int grid12 = (int)std::max<uint32_t>(1u, std::min<uint32_t>(nblk, 65535u));
-    const int grid3 = std::max(1, std::min<int>(resident, (int)std::max<uint32_t>(1u, nblk)));
+    const int grid3 = std::max(1, std::min<int>(std::min(resident, rk::MAX_DRAIN_GRID),
+                                                (int)std::max<uint32_t>(1u, nblk)));
     const int stop = c->cfg.stop_after_stage;
     const bool timing = c->cfg.timing != 0;
     hipLaunchKernelGGL(rk::reset_work, dim3(64), dim3(256), 0, s, tt, c->d_work, c->d_state, c->d_ring,
@@ -360,7 +367,7 @@ int run_tasks(recon_ctx *c, const recon_task *tasks, int n, hipStream_t stream, 
         tt.ext = nullptr;
         tt.n_inline = (uint32_t)n;
         tt.total_inline = total_blocks;
-        tt.ring_cap_inline = (uint32_t)(c->cap_blocks + 1);
+        tt.ring_cap_inline = (uint32_t)ring_slots(c->cap_blocks);
         for (int k = 0; k < n; ++k) tt.inl[k] = table[k];
     } else {
         tt.hdr = (const BatchHdr *)c->d_table;
@@ -371,7 +378,7 @@ int run_tasks(recon_ctx *c, const recon_task *tasks, int n, hipStream_t stream, 
         BatchHdr hdr{};
         hdr.n_tasks = (uint32_t)n;
         hdr.total_blocks = total_blocks;
-        hdr.ring_cap = (uint32_t)(c->cap_blocks + 1);
+        hdr.ring_cap = (uint32_t)ring_slots(c->cap_blocks);
         hdr.any_fill = any_fill ? 1u : 0u;
         std::memcpy(c->h_table, &hdr, sizeof(hdr));
         std::memcpy(c->h_table + sizeof(hdr), table.data(), table.size() * sizeof(rk::TaskDev));
@@ -645,8 +652,8 @@ int recon_create(recon_ctx **out, int device, const recon_config *cfg) {
     if (c.block_rows == 0) c.block_rows = 32;
     if (variant_of(c.block_rows) < 0) return fail(RECON_EINVAL, "block_rows must be 16, 32 or 64");
     if (c.queue_capacity == 0) c.queue_capacity = 2048;
-    if (c.queue_capacity < 64 || c.queue_capacity > 8192)
-        return fail(RECON_EINVAL, "queue_capacity must be in 64..8192");
+    if (c.queue_capacity < 64 || c.queue_capacity > 8192 || (c.queue_capacity & (c.queue_capacity - 1)) != 0)
+        return fail(RECON_EINVAL, "queue_capacity must be a power of two in 64..8192");
     if (c.scan_rounds < -1 || c.scan_rounds > 8) return fail(RECON_EINVAL, "scan_rounds must be in -1..8");
     if (c.scan_rounds == 0) c.scan_rounds = 2;
     if (c.scan_rounds < 0) c.scan_rounds = 0;

@@ -273,14 +273,14 @@ int emu_run(const EmuTask *tasks, int n, int bh, int qcap, int scan_rounds, int 
     if (n <= MAX_INLINE_TASKS) {
         tt.n_inline = (uint32_t)n;
         tt.total_inline = total;
-        tt.ring_cap_inline = total + 1;
+        tt.ring_cap_inline = total + (uint32_t)n_waves + 1;
         for (int k = 0; k < n; ++k) tt.inl[k] = table[k];
     } else {
         ext_mem.resize(sizeof(BatchHdr) + n * sizeof(TaskDev));
         BatchHdr hdr{};
         hdr.n_tasks = (uint32_t)n;
         hdr.total_blocks = total;
-        hdr.ring_cap = total + 1;
+        hdr.ring_cap = total + (uint32_t)n_waves + 1;
         hdr.any_fill = any_fill ? 1u : 0u;
         std::memcpy(ext_mem.data(), &hdr, sizeof(hdr));
         std::memcpy(ext_mem.data() + sizeof(hdr), table.data(), n * sizeof(TaskDev));
@@ -289,7 +289,7 @@ int emu_run(const EmuTask *tasks, int n, int bh, int qcap, int scan_rounds, int 
     }
     Work *work = (Work *)std::calloc(1, sizeof(Work));
     uint32_t *state = (uint32_t *)std::malloc(total * sizeof(uint32_t));
-    uint32_t *ring = (uint32_t *)std::malloc((total + 1) * sizeof(uint32_t));
+    uint32_t *ring = (uint32_t *)std::malloc((size_t)(total + n_waves + 1) * RING_STRIDE * sizeof(uint32_t));
     uint32_t *tpend = (uint32_t *)std::malloc(n * sizeof(uint32_t));
     uint32_t *tdone = (uint32_t *)std::malloc(n * sizeof(uint32_t));
 

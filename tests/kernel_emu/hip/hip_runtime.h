@@ -55,6 +55,9 @@ void check_lds(const void *p, size_t n);       // bounds check of an LDS access
 
 inline int __lane_id() { return kemu::lane(); }
 inline void __syncthreads() { kemu::wave_sync(); }
+// The wave barrier orders memory accesses across the lanes of one wave (the
+// hardware runs them in lockstep); here it is a switch point like a barrier.
+inline void __builtin_amdgcn_wave_barrier() { kemu::wave_sync(); }
 inline void __threadfence() { std::atomic_thread_fence(std::memory_order_seq_cst); }
 inline unsigned long long __ballot(int p) { return kemu::ballot(p != 0); }
 inline int __popcll(unsigned long long v) { return __builtin_popcountll(v); }
