@@ -436,9 +436,125 @@ __device__ __forceinline__ void side_bytes(Lds<BH> &L, int y, uint32_t v, uint32
     right = ln == LANES - 1 ? (uint32_t)L.Jb(y, BW) : (dn & 0xffu);
 }
 
-// vertical pass (down if dir > 0, up otherwise); returns true if anything changed
+// ---------------------------------------------------------------------------
+// Directional sweeps with row closure.
+//
+// In a raster pass a pixel takes v = clamp(u, lo, hi): u is the value reaching
+// it from its predecessor along the row, lo = min(J', I) with J' the pixel and
+// its neighbours in the row already swept, hi = I.  A map v -> clamp(v, lo, hi)
+// (lo <= hi) composed with another such map is again one (the clamp of the
+// inner bounds into the outer interval), so a whole row is a prefix scan of
+// maps: across the 4 pixels of a lane, then across the lanes of a 16-lane DPP
+// row, then across the 4 DPP rows through readlane.  Running it from both ends
+// and taking the larger value closes the row: everything that reaches a pixel
+// along the row from either side arrives in the same step.
+
+constexpr int DPP_ROW_SHL = 0x100;   // + n: lane i reads lane i + n of its 16-lane row
+constexpr int DPP_ROW_SHR = 0x110;   // + n: lane i reads lane i - n of its 16-lane row
+
+__device__ __forceinline__ uint32_t clampu(uint32_t v, uint32_t lo, uint32_t hi) { return min(max(v, lo), hi); }
+
+// lane i gets `v` of the lane selected by CTRL, or keeps `old` where there is none
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_or(uint32_t old, uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)v, CTRL, 0xf, 0xf, false);
+}
+
+// one step of an inclusive scan of maps (a, b) within 16-lane rows: compose
+// this lane's map after the one of the lane CTRL selects (identity (0, 255)
+// where there is none)
+template <int CTRL>
+__device__ __forceinline__ void map_scan_step(uint32_t &a, uint32_t &b) {
+    const uint32_t ta = dpp_or<CTRL>(0u, a), tb = dpp_or<CTRL>(255u, b);
+    const uint32_t na = clampu(ta, a, b), nb = clampu(tb, a, b);
+    a = na;
+    b = nb;
+}
+
+__device__ __forceinline__ uint32_t sel_row(int row, uint32_t e0, uint32_t e1, uint32_t e2, uint32_t e3) {
+    return row == 0 ? e0 : row == 1 ? e1 : row == 2 ? e2 : e3;
+}
+
+// Row closure of the 256 pixels held 4 per lane (byte j of lane l = pixel 4l+j):
+// per pixel maps (byte j of lo4, hi4, lo <= hi), `vl` entering pixel 0 from the
+// left and `vr` entering pixel 255 from the right (both wave-uniform).  Returns
+// the pixels' values: max of the left-to-right and right-to-left scans.
+__device__ uint32_t row_closure(uint32_t lo4, uint32_t hi4, uint32_t vl, uint32_t vr) {
+    const int ln = lane_id();
+    const int row = ln >> 4;
+    uint32_t lo[4], hi[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        lo[j] = byte_of(lo4, j);
+        hi[j] = byte_of(hi4, j);
+    }
+    vl = uniform(vl);
+    vr = uniform(vr);
+    uint32_t out[4];
+    {   // left to right
+        uint32_t a = lo[0], b = hi[0];
+#pragma unroll
+        for (int j = 1; j < 4; ++j) {
+            a = clampu(a, lo[j], hi[j]);
+            b = clampu(b, lo[j], hi[j]);
+        }
+        map_scan_step<DPP_ROW_SHR + 1>(a, b);
+        map_scan_step<DPP_ROW_SHR + 2>(a, b);
+        map_scan_step<DPP_ROW_SHR + 4>(a, b);
+        map_scan_step<DPP_ROW_SHR + 8>(a, b);
+        // value entering each DPP row: through the totals of the rows before it
+        const uint32_t e0 = vl;
+        const uint32_t e1 = clampu(e0, (uint32_t)__builtin_amdgcn_readlane((int)a, 15),
+                                   (uint32_t)__builtin_amdgcn_readlane((int)b, 15));
+        const uint32_t e2 = clampu(e1, (uint32_t)__builtin_amdgcn_readlane((int)a, 31),
+                                   (uint32_t)__builtin_amdgcn_readlane((int)b, 31));
+        const uint32_t e3 = clampu(e2, (uint32_t)__builtin_amdgcn_readlane((int)a, 47),
+                                   (uint32_t)__builtin_amdgcn_readlane((int)b, 47));
+        // through the lanes before this one in its row
+        const uint32_t xa = dpp_or<DPP_ROW_SHR + 1>(0u, a), xb = dpp_or<DPP_ROW_SHR + 1>(255u, b);
+        uint32_t v = clampu(sel_row(row, e0, e1, e2, e3), xa, xb);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            v = clampu(v, lo[j], hi[j]);
+            out[j] = v;
+        }
+    }
+    {   // right to left
+        uint32_t a = lo[3], b = hi[3];
+#pragma unroll
+        for (int j = 2; j >= 0; --j) {
+            a = clampu(a, lo[j], hi[j]);
+            b = clampu(b, lo[j], hi[j]);
+        }
+        map_scan_step<DPP_ROW_SHL + 1>(a, b);
+        map_scan_step<DPP_ROW_SHL + 2>(a, b);
+        map_scan_step<DPP_ROW_SHL + 4>(a, b);
+        map_scan_step<DPP_ROW_SHL + 8>(a, b);
+        const uint32_t e3 = vr;
+        const uint32_t e2 = clampu(e3, (uint32_t)__builtin_amdgcn_readlane((int)a, 48),
+                                   (uint32_t)__builtin_amdgcn_readlane((int)b, 48));
+        const uint32_t e1 = clampu(e2, (uint32_t)__builtin_amdgcn_readlane((int)a, 32),
+                                   (uint32_t)__builtin_amdgcn_readlane((int)b, 32));
+        const uint32_t e0 = clampu(e1, (uint32_t)__builtin_amdgcn_readlane((int)a, 16),
+                                   (uint32_t)__builtin_amdgcn_readlane((int)b, 16));
+        const uint32_t xa = dpp_or<DPP_ROW_SHL + 1>(0u, a), xb = dpp_or<DPP_ROW_SHL + 1>(255u, b);
+        uint32_t v = clampu(sel_row(row, e0, e1, e2, e3), xa, xb);
+#pragma unroll
+        for (int j = 3; j >= 0; --j) {
+            v = clampu(v, lo[j], hi[j]);
+            out[j] = max(out[j], v);
+        }
+    }
+    return out[0] | (out[1] << 8) | (out[2] << 16) | (out[3] << 24);
+}
+
+// Sweep down (dir > 0) or up over the block's rows: each row takes the swept
+// row before it (and, for 8-connectivity, its diagonal neighbours there) and is
+// then closed along its length, with the halo pixels at both ends as inputs.
+// This is a raster (or anti-raster) pass in which every row run is complete.
+// Returns true if anything changed.
 template <int BH>
-__device__ bool vpass(Lds<BH> &L, int conn, int dir) {
+__device__ bool sweep(Lds<BH> &L, int conn, int dir) {
     const int ln = lane_id();
     const int r0 = dir > 0 ? 0 : BH - 1;
     const int rprev = dir > 0 ? -1 : BH;
@@ -449,55 +565,19 @@ __device__ bool vpass(Lds<BH> &L, int conn, int dir) {
     for (int k = 0; k < BH; ++k) {
         const int r = r0 + dir * k;
         const uint32_t cur = *L.Jw(r, ln);
+        const uint32_t hi = *L.Iw(r, ln);
         uint32_t m = bmax4(cur, prev);
         if (conn == 8) {
             m = bmax4(m, (prev << 8) | pl);
             m = bmax4(m, (prev >> 8) | (pr << 24));
         }
-        const uint32_t nv = bmin4(m, *L.Iw(r, ln));
+        const uint32_t nv = row_closure(bmin4(m, hi), hi, L.Jb(r, -1), L.Jb(r, BW));
         if (nv != cur) {
             *L.Jw(r, ln) = nv;
             changed = true;
         }
         prev = nv;
         side_bytes(L, r, prev, pl, pr);
-    }
-    return changed;
-}
-
-// horizontal pass (right if dir > 0, left otherwise): lane y walks row y
-template <int BH>
-__device__ bool hpass(Lds<BH> &L, int conn, int dir) {
-    const int ln = lane_id();
-    const int y = ln < BH ? ln : BH - 1;   // idle lanes shadow the last row (never store)
-    const bool active = ln < BH;
-    uint32_t prev = dir > 0 ? (uint32_t)L.Jb(y, -1) : (uint32_t)L.Jb(y, BW);
-    bool changed = false;
-    for (int k = 0; k < BW / 4; ++k) {
-        const int d = dir > 0 ? k : BW / 4 - 1 - k;
-        uint32_t cur = *L.Jw(y, d);
-        const uint32_t iv = *L.Iw(y, d);
-        const uint32_t cur0 = cur;
-        for (int s = 0; s < 4; ++s) {
-            const int j = dir > 0 ? s : 3 - s;
-            const int x = 4 * d + j;
-            uint32_t m = max(byte_of(cur, j), prev);
-            if (conn == 8) {
-                uint32_t up = from_lower(prev);
-                uint32_t dn = from_upper(prev);
-                const int xs = x - dir;   // column the diagonal neighbours sit in
-                if (ln == 0) up = L.Jb(-1, xs);
-                if (ln == BH - 1) dn = L.Jb(BH, xs);
-                m = max(m, max(up, dn));
-            }
-            const uint32_t v = min(m, byte_of(iv, j));
-            cur = set_byte(cur, j, v);
-            prev = v;
-        }
-        if (active && cur != cur0) {
-            *L.Jw(y, d) = cur;
-            changed = true;
-        }
     }
     return changed;
 }
@@ -867,11 +947,9 @@ __global__ __launch_bounds__(64) void dense_pass(TaskTable tt, KArgs a) {
         for (int r = ln; r < BH; r += LANES) L.rowdirty[r] = 0;
         __syncthreads();
         for (int k = 0; k < t.scan_rounds; ++k) {
-            bool c = vpass<BH>(L, t.conn, +1);
-            c |= vpass<BH>(L, t.conn, -1);
+            bool c = sweep<BH>(L, t.conn, +1);
             __syncthreads();
-            c |= hpass<BH>(L, t.conn, +1);
-            c |= hpass<BH>(L, t.conn, -1);
+            c |= sweep<BH>(L, t.conn, -1);
             __syncthreads();
             if (!__ballot(c)) break;
         }
@@ -1116,17 +1194,38 @@ __global__ void fill_finish(TaskTable tt) {
     }
 }
 
-// Self-test (checks that this code object runs and that the one-lane DPP
-// shifts move data the way the kernels assume):
+// Self-test input pattern for the row closure (shared with the host check).
+__host__ __device__ inline uint32_t self_test_mask(uint32_t p) {
+    const uint32_t h = p * 2654435761u;
+    return (h >> 13) % 5u == 0u ? (h >> 20) % 40u : 120u + (h >> 8) % 136u;   // dips cut runs
+}
+__host__ __device__ inline uint32_t self_test_low(uint32_t p, uint32_t mask) {
+    const uint32_t h = (p + 977u) * 2246822519u;
+    const uint32_t v = (h >> 17) % 64u;
+    return (h >> 11) % 61u == 0u || v > mask ? mask : v;    // a few sources at the mask
+}
+
+// Self-test (checks that this code object runs and that the DPP lane moves
+// and the row closure work the way the kernels assume):
 //   out[i] = 3 i + 1,  out[n + i] = from_lower(i + 100),  out[2n + i] = from_upper(i + 100)
 // for i < n, with n a multiple of the block size (all lanes active).
 __global__ void self_test(uint32_t *out, uint32_t n) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t lo = from_lower(i + 100u), hi = from_upper(i + 100u);
+    uint32_t m4 = 0, l4 = 0;
+    for (int j = 0; j < 4; ++j) {
+        const uint32_t p = 4u * i + (uint32_t)j;
+        const uint32_t mh = self_test_mask(p), ml = self_test_low(p, mh);
+        m4 |= mh << (8 * j);
+        l4 |= ml << (8 * j);
+    }
+    const uint32_t wave = i / 64u;
+    const uint32_t rc = row_closure(l4, m4, (wave * 37u) & 255u, (wave * 91u + 7u) & 255u);
     if (i < n) {
         out[i] = i * 3u + 1u;
         out[n + i] = lo;
         out[2 * n + i] = hi;
+        out[3 * n + i] = rc;
     }
 }
 

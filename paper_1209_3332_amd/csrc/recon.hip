@@ -429,9 +429,9 @@ int self_test(double seconds) {
     const uint32_t n = 1024;
     uint32_t *h = nullptr;
     hipEvent_t ev = nullptr;
-    if (hipHostMalloc((void **)&h, 3 * n * sizeof(uint32_t), hipHostMallocDefault) != hipSuccess)
+    if (hipHostMalloc((void **)&h, 4 * n * sizeof(uint32_t), hipHostMallocDefault) != hipSuccess)
         return fail(RECON_ENOMEM, "self-test pinned allocation failed");
-    std::memset(h, 0, 3 * n * sizeof(uint32_t));
+    std::memset(h, 0, 4 * n * sizeof(uint32_t));
     int rc = RECON_OK;
     if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
         rc = fail(RECON_EDEVICE, "self-test event creation failed");
@@ -441,9 +441,9 @@ int self_test(double seconds) {
         if (e != hipSuccess) rc = fail(RECON_EDEVICE, "self-test launch failed: %s", hipGetErrorString(e));
         else if (hipEventRecord(ev, nullptr) != hipSuccess) rc = fail(RECON_EDEVICE, "self-test event record failed");
         else rc = wait_event(ev, seconds, "the self-test kernel");
+        const volatile uint32_t *v = h;
         if (rc == RECON_OK)
             for (uint32_t i = 0; i < n; ++i) {
-                const volatile uint32_t *v = h;
                 const uint32_t lane = i % 64u;
                 const uint32_t want_lo = lane > 0 ? i - 1u + 100u : 0u;
                 const uint32_t want_hi = lane < 63 ? i + 1u + 100u : 0u;
@@ -454,6 +454,28 @@ int self_test(double seconds) {
                     break;
                 }
             }
+        // row closure: each wave closes one row of 256 pixels; check it pixel by
+        // pixel against the two sequential scans
+        for (uint32_t w = 0; rc == RECON_OK && w < n / 64u; ++w) {
+            uint32_t lo[256], hi[256], lr[256];
+            for (uint32_t x = 0; x < 256; ++x) {
+                hi[x] = rk::self_test_mask(256u * w + x);
+                lo[x] = rk::self_test_low(256u * w + x, hi[x]);
+            }
+            uint32_t u = (w * 37u) & 255u;
+            for (uint32_t x = 0; x < 256; ++x) lr[x] = u = std::min(std::max(u, lo[x]), hi[x]);
+            u = (w * 91u + 7u) & 255u;
+            for (int x = 255; x >= 0; --x) {
+                u = std::min(std::max(u, lo[x]), hi[x]);
+                const uint32_t want = std::max(lr[x], u);
+                const uint32_t got = (v[3 * n + 64u * w + (uint32_t)x / 4u] >> (8 * (x % 4))) & 0xffu;
+                if (got != want) {
+                    rc = fail(RECON_EDEVICE, "self-test mismatch in the row closure: row %u pixel %d is %u, "
+                              "expected %u (DPP row moves)", w, x, got, want);
+                    break;
+                }
+            }
+        }
         if (rc != RECON_ETIMEDOUT) (void)hipEventDestroy(ev);
     }
     if (rc != RECON_ETIMEDOUT) (void)hipHostFree(h);   // never free memory a live kernel may write

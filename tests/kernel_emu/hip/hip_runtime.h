@@ -87,15 +87,28 @@ inline uint32_t __builtin_amdgcn_mbcnt_hi(uint32_t m, uint32_t acc) {
 }
 inline void __builtin_amdgcn_s_sleep(int) { std::this_thread::yield(); }
 inline int __builtin_amdgcn_readfirstlane(int v) { return (int)(uint32_t)kemu::exchange((uint32_t)v, 0); }
-// DPP: only the whole-wave shifts by one lane are emulated (bound_ctrl: 0 where no source lane)
+// DPP data movement as used by the kernels: row shifts (within 16-lane rows),
+// whole-wave shifts by one lane, and the row broadcasts.  A lane whose source
+// is invalid reads 0 with bound_ctrl, else keeps `old`; rows outside row_mask
+// keep `old`.
 inline int __builtin_amdgcn_update_dpp(int old, int src, int ctrl, int row_mask, int bank_mask, bool bound_ctrl) {
-    (void)old; (void)row_mask; (void)bank_mask; (void)bound_ctrl;
+    if (bank_mask != 0xf) __builtin_trap();
     const int l = kemu::lane();
-    const int from = ctrl == 0x138 ? l - 1 : (ctrl == 0x130 ? l + 1 : -100);
-    if (from == -100) { __builtin_trap(); }
-    const uint32_t v = (uint32_t)kemu::exchange((uint32_t)src, from >= 0 && from < 64 ? from : l);
-    return (from >= 0 && from < 64) ? (int)v : 0;
+    const int row = l >> 4, pos = l & 15;
+    int from = -1;
+    if (ctrl >= 0x101 && ctrl <= 0x10f) from = pos + (ctrl - 0x100) <= 15 ? l + (ctrl - 0x100) : -1;   // row_shl
+    else if (ctrl >= 0x111 && ctrl <= 0x11f) from = pos - (ctrl - 0x110) >= 0 ? l - (ctrl - 0x110) : -1;  // row_shr
+    else if (ctrl == 0x130) from = l + 1 < 64 ? l + 1 : -1;   // wave_shl:1
+    else if (ctrl == 0x138) from = l - 1;                       // wave_shr:1
+    else if (ctrl == 0x142) from = row > 0 ? 16 * row - 1 : -1;  // row_bcast:15
+    else if (ctrl == 0x143) from = row > 1 ? 31 : -1;            // row_bcast:31
+    else __builtin_trap();
+    const uint32_t v = (uint32_t)kemu::exchange((uint32_t)src, from >= 0 ? from : l);
+    if (!((row_mask >> row) & 1)) return old;
+    if (from < 0) return bound_ctrl ? 0 : old;
+    return (int)v;
 }
+inline int __builtin_amdgcn_readlane(int v, int lane) { return (int)(uint32_t)kemu::exchange((uint32_t)v, lane); }
 
 inline uint32_t atomicCAS(uint32_t *p, uint32_t expected, uint32_t desired) {
     kemu::check_lds(p, 4);
