@@ -47,6 +47,15 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+// Address spaces of LDS and global pointers (the host emulation of these
+// kernels defines both empty).  Image planes reach the kernels as plain
+// pointers; accesses go through gp(), so that they are global (not flat)
+// instructions and never wait on, or delay, LDS traffic.
+#ifndef RK_LDS
+#define RK_LDS __attribute__((address_space(3)))
+#define RK_GLOBAL __attribute__((address_space(1)))
+#endif
+
 namespace rk {
 
 constexpr int LANES = 64;
@@ -217,20 +226,25 @@ __device__ __forceinline__ uint32_t prefix_count(unsigned long long mask) {
 }
 
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ const RK_GLOBAL uint8_t *gp(const uint8_t *p) { return (const RK_GLOBAL uint8_t *)p; }
+__device__ __forceinline__ RK_GLOBAL uint8_t *gp(uint8_t *p) { return (RK_GLOBAL uint8_t *)p; }
+
 // global memory access of the 4 pixels at columns x..x+3 of a row with
 // `valid` (0..4) of them inside the image; bytes past the image read 0.
-__device__ __forceinline__ uint32_t gload4(const uint8_t *row, int x, int valid, int aligned) {
+__device__ __forceinline__ uint32_t gload4(const uint8_t *row_, int x, int valid, int aligned) {
+    const RK_GLOBAL uint8_t *row = gp(row_);
     if (valid <= 0) return 0u;
-    if (aligned && valid == 4) return *(const uint32_t *)(row + x);
+    if (aligned && valid == 4) return *(const RK_GLOBAL uint32_t *)(row + x);
     uint32_t v = 0;
     for (int k = 0; k < valid && k < 4; ++k) v |= (uint32_t)row[x + k] << (8 * k);
     return v;
 }
 
-__device__ __forceinline__ void gstore4(uint8_t *row, int x, int valid, int aligned, uint32_t v) {
+__device__ __forceinline__ void gstore4(uint8_t *row_, int x, int valid, int aligned, uint32_t v) {
+    RK_GLOBAL uint8_t *row = gp(row_);
     if (valid <= 0) return;
     if (aligned && valid == 4) {
-        *(uint32_t *)(row + x) = v;
+        *(RK_GLOBAL uint32_t *)(row + x) = v;
         return;
     }
     for (int k = 0; k < valid && k < 4; ++k) row[x + k] = (uint8_t)(v >> (8 * k));
@@ -247,13 +261,13 @@ __device__ __forceinline__ uint32_t mask4(const TaskDev &t, int gy, int gx, int 
 }
 
 __device__ __forceinline__ uint32_t mask1(const TaskDev &t, int gy, int gx) {
-    const uint32_t v = t.i[(int64_t)gy * t.pitch_i + gx];
+    const uint32_t v = gp(t.i)[(int64_t)gy * t.pitch_i + gx];
     return t.op == OP_FILL ? 255u - v : v;
 }
 
 // current marker value of one pixel, clipped under its mask
 __device__ __forceinline__ uint32_t marker1(const TaskDev &t, int gy, int gx) {
-    return min((uint32_t)t.j[(int64_t)gy * t.pitch_j + gx], mask1(t, gy, gx));
+    return min((uint32_t)gp(t.j)[(int64_t)gy * t.pitch_j + gx], mask1(t, gy, gx));
 }
 
 // current marker of 4 pixels, clipped under their mask
@@ -282,20 +296,22 @@ struct WaveStats {
 // J and I share one geometry: (BH + 2) rows of JP bytes, pixel (y, x) at
 // (y + 1) * JP + JOFF + x for y in -1..BH and x in -1..BW (the halo ring holds
 // the neighbours' marker, clipped, and mask).
+// The pointers carry the LDS address space, so that every access (volatile
+// ones included) is a DS instruction.
 template <int BH>
 struct Lds {
-    uint8_t *J;
-    uint8_t *I;
-    uint8_t *rowdirty;   // BH bytes
-    uint16_t *Q;         // queue ring (power-of-two entries)
-    __device__ __forceinline__ uint32_t *Jw(int y, int d) {  // dword d of row y (y in -1..BH)
-        return (uint32_t *)(J + (y + 1) * JP + JOFF + 4 * d);
+    RK_LDS uint8_t *J;
+    RK_LDS uint8_t *I;
+    RK_LDS uint8_t *rowdirty;   // BH bytes
+    RK_LDS uint16_t *Q;         // queue ring (power-of-two entries)
+    __device__ __forceinline__ RK_LDS uint32_t *Jw(int y, int d) {  // dword d of row y (y in -1..BH)
+        return (RK_LDS uint32_t *)(J + (y + 1) * JP + JOFF + 4 * d);
     }
-    __device__ __forceinline__ uint32_t *Iw(int y, int d) {
-        return (uint32_t *)(I + (y + 1) * JP + JOFF + 4 * d);
+    __device__ __forceinline__ RK_LDS uint32_t *Iw(int y, int d) {
+        return (RK_LDS uint32_t *)(I + (y + 1) * JP + JOFF + 4 * d);
     }
-    __device__ __forceinline__ uint8_t &Jb(int y, int x) { return J[(y + 1) * JP + JOFF + x]; }
-    __device__ __forceinline__ uint8_t &Ib(int y, int x) { return I[(y + 1) * JP + JOFF + x]; }
+    __device__ __forceinline__ RK_LDS uint8_t &Jb(int y, int x) { return J[(y + 1) * JP + JOFF + x]; }
+    __device__ __forceinline__ RK_LDS uint8_t &Ib(int y, int x) { return I[(y + 1) * JP + JOFF + x]; }
 };
 
 template <int BH>
@@ -303,12 +319,19 @@ __host__ __device__ constexpr size_t lds_bytes(int qcap) {
     return 2 * (size_t)(BH + 2) * JP + (size_t)((BH + 15) & ~15) + 2u * (size_t)qcap;
 }
 
+// Lockstep point: the lanes of a wave execute in lockstep on the GPU, so this
+// is empty there; the host emulation of these kernels (which runs lanes one
+// after another between cross-lane operations) switches lanes here.
+#ifndef RK_LANE_SYNC
+#define RK_LANE_SYNC() ((void)0)
+#endif
+
 // Base of the workgroup's dynamic LDS.  (A host build of these kernels for
 // emulated testing supplies its own definition.)
 #ifndef RK_DYN_LDS_PROVIDED
-__device__ __forceinline__ uint8_t *dyn_lds() {
+__device__ __forceinline__ RK_LDS uint8_t *dyn_lds() {
     extern __shared__ __align__(16) uint8_t rk_smem[];
-    return rk_smem;
+    return (RK_LDS uint8_t *)rk_smem;
 }
 #endif
 
@@ -318,7 +341,7 @@ __device__ __forceinline__ Lds<BH> lds_layout() {
     L.J = dyn_lds();
     L.I = L.J + (BH + 2) * JP;
     L.rowdirty = L.I + (BH + 2) * JP;
-    L.Q = (uint16_t *)(L.rowdirty + ((BH + 15) & ~15));
+    L.Q = (RK_LDS uint16_t *)(L.rowdirty + ((BH + 15) & ~15));
     return L;
 }
 
@@ -404,11 +427,11 @@ __device__ void load_halo(const TaskDev &t, const BlockGeom &g, Lds<BH> &L) {
         const int gy = g.y0 + r;
         if (row_in && g.has_w) {
             wi[k] = mask1(t, gy, g.x0 - 1);
-            wj[k] = t.j[(int64_t)gy * t.pitch_j + g.x0 - 1];
+            wj[k] = gp(t.j)[(int64_t)gy * t.pitch_j + g.x0 - 1];
         }
         if (row_in && g.has_e) {
             ei[k] = mask1(t, gy, g.x0 + BW);
-            ej[k] = t.j[(int64_t)gy * t.pitch_j + g.x0 + BW];
+            ej[k] = gp(t.j)[(int64_t)gy * t.pitch_j + g.x0 + BW];
         }
     }
     *L.Iw(-1, ln) = ti;
@@ -584,24 +607,24 @@ __device__ bool sweep(Lds<BH> &L, int conn, int dir) {
 
 // push the pixels flagged by `pred` (one per lane) onto the LDS ring of qcap
 // (a power of two) entries; returns false (and pushes nothing) if they do not fit.
-__device__ __forceinline__ bool push_bits(uint16_t *Q, int qcap, uint32_t head, uint32_t &tail,
+__device__ __forceinline__ bool push_bits(RK_LDS uint16_t *Q, int qcap, uint32_t head, uint32_t &tail,
                                           bool pred, uint32_t pix) {
     const unsigned long long m = __ballot(pred);
     if (m == 0) return true;
     const uint32_t cnt = (uint32_t)__popcll(m);
     if (tail - head + cnt > (uint32_t)qcap) return false;
-    if (pred) Q[(tail + prefix_count(m)) & (uint32_t)(qcap - 1)] = (uint16_t)pix;
+    if (pred) ((volatile RK_LDS uint16_t *)Q)[(tail + prefix_count(m)) & (uint32_t)(qcap - 1)] = (uint16_t)pix;
     tail += cnt;
     return true;
 }
 
-// Ordering point for LDS accesses between the lanes of one wave.  A wave's LDS
-// operations execute in issue order, so keeping the compiler from moving
-// accesses across this point is all that is needed for one lane to see what
-// another lane of the same wave stored before it.
-__device__ __forceinline__ void lds_order() {
-    __builtin_amdgcn_wave_barrier();
-    __asm__ __volatile__("" ::: "memory");
+// Marker byte of LDS pixel (y, x) for the queue phase.  A wave's LDS operations
+// execute in issue order; volatile keeps the compiler from reordering these
+// accesses among themselves, so a load issued after another lane's store of
+// the same byte (in an earlier statement) sees that store, with no wait.
+template <int BH>
+__device__ __forceinline__ volatile RK_LDS uint8_t &jv(Lds<BH> &L, int y, int x) {
+    return *(volatile RK_LDS uint8_t *)&L.Jb(y, x);
 }
 
 // Seed pass: raise every pixel that a neighbour (block or halo) can raise and push it.
@@ -639,11 +662,11 @@ __device__ void seed_pass(Lds<BH> &L, int conn, int qcap, uint32_t head, uint32_
 
 // Raise J(y, x) to `target` if lower; returns true if this lane raised it.
 // A byte store: within one call site the lanes of the wave write distinct
-// pixels (or the same pixel with the same value), and calls are separated by
-// lds_order(), so no raise is ever lost.
+// pixels (or the same pixel with the same value), and successive call sites
+// are ordered through jv(), so no raise is ever lost.
 template <int BH>
 __device__ __forceinline__ bool raise_px(Lds<BH> &L, int y, int x, uint32_t target) {
-    uint8_t &b = L.Jb(y, x);
+    volatile RK_LDS uint8_t &b = jv(L, y, x);
     if ((uint32_t)b >= target) return false;
     b = (uint8_t)target;
     return true;
@@ -719,28 +742,28 @@ __device__ void drain(Lds<BH> &L, int conn, int qcap, uint32_t &head, uint32_t &
     const int dys[8] = {-1, 1, 0, 0, -1, -1, 1, 1};
     const int dxs[8] = {0, 0, -1, 1, -1, 1, -1, 1};
     while (head != tail) {
+        RK_LANE_SYNC();
         const uint32_t n = min(tail - head, (uint32_t)LANES);
         const bool valid = (uint32_t)ln < n;
-        uint32_t p = 0;
-        if (valid) p = L.Q[(head + ln) & (uint32_t)(qcap - 1)];
+        const volatile RK_LDS uint16_t *Qv = L.Q;
+        const uint32_t p = valid ? (uint32_t)Qv[(head + ln) & (uint32_t)(qcap - 1)] : 0u;
         head += n;
         const int y = (int)(p >> 8), x = (int)(p & 255u);
-        const uint32_t v = valid ? (uint32_t)L.Jb(y, x) : 0u;
+        const uint32_t v = jv(L, y, x);
         // the mask never changes: all neighbours' mask values up front (a
         // block pixel's neighbours lie in the LDS planes, the halo ring at worst)
         uint32_t iv[8];
-        for (int k = 0; k < ndir; ++k) iv[k] = valid ? (uint32_t)L.Ib(y + dys[k], x + dxs[k]) : 0u;
+        for (int k = 0; k < ndir; ++k) iv[k] = L.Ib(y + dys[k], x + dxs[k]);
         for (int k = 0; k < ndir; ++k) {
             const int ny = y + dys[k], nx = x + dxs[k];
-            bool raised = false;
-            const bool inside = ny >= 0 && ny < BH && nx >= 0 && nx < BW;
-            if (valid && inside) {
-                const uint32_t tgt = min(v, iv[k]);
-                raised = raise_px(L, ny, nx, tgt);
-                if (raised) L.rowdirty[ny] = 1;
+            const bool inside = valid && ny >= 0 && ny < BH && nx >= 0 && nx < BW;
+            const uint32_t tgt = min(v, iv[k]);
+            const bool raised = inside && (uint32_t)jv(L, ny, nx) < tgt;
+            if (raised) {
+                jv(L, ny, nx) = (uint8_t)tgt;
+                L.rowdirty[ny] = 1;
             }
             if (!push_bits(L.Q, qcap, head, tail, raised, (uint32_t)(ny * BW + nx))) overflow = true;
-            lds_order();
         }
     }
 }
@@ -1189,7 +1212,7 @@ __global__ void fill_finish(TaskTable tt) {
         for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < npx;
              p += (int64_t)gridDim.x * blockDim.x) {
             const int y = (int)(p / t.w), x = (int)(p % t.w);
-            t.img[(int64_t)y * t.pitch_i + x] = (uint8_t)(255u - t.j[(int64_t)y * t.pitch_j + x]);
+            gp(t.img)[(int64_t)y * t.pitch_i + x] = (uint8_t)(255u - gp(t.j)[(int64_t)y * t.pitch_j + x]);
         }
     }
 }

@@ -122,6 +122,9 @@ inline uint32_t min(uint32_t a, uint32_t b) { return a < b ? a : b; }
 inline uint32_t max(uint32_t a, uint32_t b) { return a > b ? a : b; }
 
 #define RK_DYN_LDS_PROVIDED 1
+#define RK_LDS
+#define RK_GLOBAL
+#define RK_LANE_SYNC() kemu::wave_sync()
 namespace rk {
 inline uint8_t *dyn_lds() { return kemu::wave_lds(); }
 }
