@@ -114,7 +114,8 @@ struct TaskTable {
 struct Work {
     uint32_t pending;        // outstanding revisits (queued + running)
     uint32_t abort;          // set by the watchdog: the launch gave up (results incomplete)
-    uint32_t pad0[30];
+    uint32_t done;           // set when the last outstanding visit completes
+    uint32_t pad0[29];
     uint32_t ring_head;      // next ticket handed to a waiting wave
     uint32_t pad1[31];
     uint32_t ring_tail;      // next ring position a request is written to
@@ -371,18 +372,26 @@ __device__ void load_block(const TaskDev &t, const BlockGeom &g, Lds<BH> &L, boo
     const int ln = lane_id();
     const int x = 4 * ln;
     const int valid = min(4, g.bw - x);
-    for (int r = 0; r < BH; ++r) {
-        uint32_t iv = 0, jv = 0;
-        if (r < g.bh && valid > 0) {
-            const int gy = g.y0 + r;
-            iv = mask4(t, gy, g.x0 + x, valid);
-            if (fill_initial)
-                jv = fill_init4(t, gy, g.x0 + x, valid, iv);
-            else
-                jv = bmin4(gload4(t.j + (int64_t)gy * t.pitch_j, g.x0 + x, valid, t.aligned), iv);
+    constexpr int CH = BH < 16 ? BH : 16;   // rows whose loads are in flight together
+    for (int r0 = 0; r0 < BH; r0 += CH) {
+        uint32_t iv[CH], jr[CH];
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+            const int r = r0 + k;
+            iv[k] = 0;
+            jr[k] = 0;
+            if (r < g.bh && valid > 0) {
+                const int gy = g.y0 + r;
+                iv[k] = mask4(t, gy, g.x0 + x, valid);
+                if (!fill_initial) jr[k] = gload4(t.j + (int64_t)gy * t.pitch_j, g.x0 + x, valid, t.aligned);
+            }
         }
-        *L.Iw(r, ln) = iv;
-        *L.Jw(r, ln) = jv;
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+            const int r = r0 + k;
+            *L.Iw(r, ln) = iv[k];
+            *L.Jw(r, ln) = fill_initial ? fill_init4(t, g.y0 + r, g.x0 + x, valid, iv[k]) : bmin4(jr[k], iv[k]);
+        }
     }
 }
 
@@ -576,8 +585,9 @@ __device__ uint32_t row_closure(uint32_t lo4, uint32_t hi4, uint32_t vl, uint32_
 // then closed along its length, with the halo pixels at both ends as inputs.
 // This is a raster (or anti-raster) pass in which every row run is complete.
 // Returns true if anything changed.
-template <int BH>
-__device__ bool sweep(Lds<BH> &L, int conn, int dir) {
+template <int BH, int CONN>
+__device__ bool sweep(Lds<BH> &L, int dir) {
+    constexpr int conn = CONN;
     const int ln = lane_id();
     const int r0 = dir > 0 ? 0 : BH - 1;
     const int rprev = dir > 0 ? -1 : BH;
@@ -628,9 +638,10 @@ __device__ __forceinline__ volatile RK_LDS uint8_t &jv(Lds<BH> &L, int y, int x)
 }
 
 // Seed pass: raise every pixel that a neighbour (block or halo) can raise and push it.
-template <int BH>
-__device__ void seed_pass(Lds<BH> &L, int conn, int qcap, uint32_t head, uint32_t &tail,
+template <int BH, int CONN>
+__device__ void seed_pass(Lds<BH> &L, int qcap, uint32_t head, uint32_t &tail,
                           bool &overflow, bool &changed) {
+    constexpr int conn = CONN;
     const int ln = lane_id();
     for (int r = 0; r < BH; ++r) {
         const uint32_t a = *L.Jw(r - 1, ln);
@@ -652,10 +663,12 @@ __device__ void seed_pass(Lds<BH> &L, int conn, int qcap, uint32_t head, uint32_
             *L.Jw(r, ln) = nv;
             L.rowdirty[r] = 1;
         }
-        if (__ballot(dm != 0)) changed = true;
-        for (int j = 0; j < 4; ++j) {
-            const bool p = (dm >> j) & 1u;
-            if (!push_bits(L.Q, qcap, head, tail, p, (uint32_t)(r * BW + 4 * ln + j))) overflow = true;
+        if (__ballot(dm != 0)) {
+            changed = true;
+            for (int j = 0; j < 4; ++j) {
+                const bool p = (dm >> j) & 1u;
+                if (!push_bits(L.Q, qcap, head, tail, p, (uint32_t)(r * BW + 4 * ln + j))) overflow = true;
+            }
         }
     }
 }
@@ -675,9 +688,10 @@ __device__ __forceinline__ bool raise_px(Lds<BH> &L, int y, int x, uint32_t targ
 // Border seed: after the halo has been refreshed, only pixels on the block's
 // border can be raised by a neighbour (the interior was left converged by the
 // previous visit, and only the owner writes it).  Raise and push exactly those.
-template <int BH>
-__device__ void seed_border(Lds<BH> &L, int conn, int bh, int bw, int qcap, uint32_t head, uint32_t &tail,
+template <int BH, int CONN>
+__device__ void seed_border(Lds<BH> &L, int bh, int bw, int qcap, uint32_t head, uint32_t &tail,
                             bool &overflow, bool &changed) {
+    constexpr int conn = CONN;
     const int ln = lane_id();
     // rows 0 and bh-1 (each once): lanes across columns, like the dense seed pass
     for (int pass = 0; pass < 2; ++pass) {
@@ -702,10 +716,12 @@ __device__ void seed_border(Lds<BH> &L, int conn, int bh, int bw, int qcap, uint
             *L.Jw(r, ln) = nv;
             L.rowdirty[r] = 1;
         }
-        if (__ballot(dm != 0)) changed = true;
-        for (int j = 0; j < 4; ++j) {
-            const bool p = (dm >> j) & 1u;
-            if (!push_bits(L.Q, qcap, head, tail, p, (uint32_t)(r * BW + 4 * ln + j))) overflow = true;
+        if (__ballot(dm != 0)) {
+            changed = true;
+            for (int j = 0; j < 4; ++j) {
+                const bool p = (dm >> j) & 1u;
+                if (!push_bits(L.Q, qcap, head, tail, p, (uint32_t)(r * BW + 4 * ln + j))) overflow = true;
+            }
         }
     }
     __syncthreads();
@@ -733,37 +749,46 @@ __device__ void seed_border(Lds<BH> &L, int conn, int bh, int bw, int qcap, uint
     }
 }
 
+// neighbour k of a pixel (N, S, W, E, then NW, NE, SW, SE): row and column step
+__host__ __device__ constexpr int nb_dy(int k) { return k == 0 || k == 4 || k == 5 ? -1 : (k == 1 || k >= 6 ? 1 : 0); }
+__host__ __device__ constexpr int nb_dx(int k) { return k == 2 || k == 4 || k == 6 ? -1 : (k == 3 || k == 5 || k == 7 ? 1 : 0); }
+
 // Drain the LDS ring to empty; *overflow set if pushes had to be dropped.
-template <int BH>
-__device__ void drain(Lds<BH> &L, int conn, int qcap, uint32_t &head, uint32_t &tail,
-                      bool &overflow) {
+// Each round pops up to 64 pixels (one per lane) and offers every popped
+// pixel's value to its neighbours, one direction at a time.
+template <int BH, int CONN>
+__device__ void drain(Lds<BH> &L, int qcap, uint32_t &head, uint32_t &tail, bool &overflow) {
     const int ln = lane_id();
-    const int ndir = conn == 8 ? 8 : 4;
-    const int dys[8] = {-1, 1, 0, 0, -1, -1, 1, 1};
-    const int dxs[8] = {0, 0, -1, 1, -1, 1, -1, 1};
+    const volatile RK_LDS uint16_t *Qv = L.Q;
+    volatile RK_LDS uint8_t *Jv = L.J;
     while (head != tail) {
         RK_LANE_SYNC();
         const uint32_t n = min(tail - head, (uint32_t)LANES);
         const bool valid = (uint32_t)ln < n;
-        const volatile RK_LDS uint16_t *Qv = L.Q;
         const uint32_t p = valid ? (uint32_t)Qv[(head + ln) & (uint32_t)(qcap - 1)] : 0u;
         head += n;
         const int y = (int)(p >> 8), x = (int)(p & 255u);
-        const uint32_t v = jv(L, y, x);
+        const int a = (y + 1) * JP + JOFF + x;   // offset of pixel (y, x) in the J and I planes
+        const uint32_t v = Jv[a];
+        const bool ok_n = valid && y > 0, ok_s = valid && y < BH - 1;
+        const bool ok_w = valid && x > 0, ok_e = valid && x < BW - 1;
         // the mask never changes: all neighbours' mask values up front (a
         // block pixel's neighbours lie in the LDS planes, the halo ring at worst)
-        uint32_t iv[8];
-        for (int k = 0; k < ndir; ++k) iv[k] = L.Ib(y + dys[k], x + dxs[k]);
-        for (int k = 0; k < ndir; ++k) {
-            const int ny = y + dys[k], nx = x + dxs[k];
-            const bool inside = valid && ny >= 0 && ny < BH && nx >= 0 && nx < BW;
+        uint32_t iv[CONN];
+#pragma unroll
+        for (int k = 0; k < CONN; ++k) iv[k] = L.I[a + nb_dy(k) * JP + nb_dx(k)];
+#pragma unroll
+        for (int k = 0; k < CONN; ++k) {
+            const int off = nb_dy(k) * JP + nb_dx(k);
+            const bool in = (nb_dy(k) < 0 ? ok_n : nb_dy(k) > 0 ? ok_s : valid) &&
+                            (nb_dx(k) < 0 ? ok_w : nb_dx(k) > 0 ? ok_e : true);
             const uint32_t tgt = min(v, iv[k]);
-            const bool raised = inside && (uint32_t)jv(L, ny, nx) < tgt;
+            const bool raised = in && (uint32_t)Jv[a + off] < tgt;
             if (raised) {
-                jv(L, ny, nx) = (uint8_t)tgt;
-                L.rowdirty[ny] = 1;
+                Jv[a + off] = (uint8_t)tgt;
+                L.rowdirty[y + nb_dy(k)] = 1;
             }
-            if (!push_bits(L.Q, qcap, head, tail, raised, (uint32_t)(ny * BW + nx))) overflow = true;
+            if (!push_bits(L.Q, qcap, head, tail, raised, p + (uint32_t)(nb_dy(k) * BW + nb_dx(k)))) overflow = true;
         }
     }
 }
@@ -772,18 +797,18 @@ __device__ void drain(Lds<BH> &L, int conn, int qcap, uint32_t &head, uint32_t &
 // border_only: the first seed looks at the block's border only (valid when the
 // interior is already converged and only the halo changed); re-seeds after a
 // queue overflow are always dense.
-template <int BH>
-__device__ bool converge_block(Lds<BH> &L, int conn, int qcap, WaveStats &st, bool border_only, int bh, int bw) {
+template <int BH, int CONN>
+__device__ bool converge_block(Lds<BH> &L, int qcap, WaveStats &st, bool border_only, int bh, int bw) {
     bool changed = false;
     for (int round = 0; round <= (1 << 16); ++round) {   // each round raises pixels; bounded anyway
         uint32_t head = 0, tail = 0;
         bool overflow = false;
         if (border_only && round == 0)
-            seed_border<BH>(L, conn, bh, bw, qcap, head, tail, overflow, changed);
+            seed_border<BH, CONN>(L, bh, bw, qcap, head, tail, overflow, changed);
         else
-            seed_pass<BH>(L, conn, qcap, head, tail, overflow, changed);
+            seed_pass<BH, CONN>(L, qcap, head, tail, overflow, changed);
         __syncthreads();
-        drain<BH>(L, conn, qcap, head, tail, overflow);
+        drain<BH, CONN>(L, qcap, head, tail, overflow);
         __syncthreads();
         if (!__ballot(overflow)) break;
         st.overflow += 1;
@@ -812,12 +837,14 @@ __device__ __forceinline__ bool expired(const KArgs &a, uint64_t start) {
     return wall_clock64() - start > a.watchdog_ticks;
 }
 
-// Idle back-off: about 2^min(k, 7) x 512 cycles (up to ~27 us), so that
-// thousands of idle waves do not hammer the memory system while a few work.
+// Idle back-off of a waiter polling its own ring slot: about 2^min(k, 3) x 512
+// cycles (under 2 us), so a block handed to it is picked up quickly.
 __device__ __forceinline__ void backoff(int k) {
-    const int n = 1 << (k < 7 ? k : 7);
+    const int n = 1 << (k < 3 ? k : 3);
     for (int i = 0; i < n; ++i) __builtin_amdgcn_s_sleep(8);
 }
+
+constexpr uint32_t SLOT_EXIT = 0xffffffffu;   // ring slot value: no more work will come
 
 __device__ __forceinline__ void flush_stats(Work *w, const WaveStats &st) {
     if (lane_id() != 0) return;
@@ -953,6 +980,19 @@ __device__ bool check_neighbours(const KArgs &a, uint32_t ring_cap, int ti, cons
 // ---------------------------------------------------------------------------
 // K1: dense pass.  Every block once, independently (empty halo).
 
+// A block loaded with an empty halo: sweep rounds, then seed and drain.
+template <int BH, int CONN>
+__device__ void dense_block(const TaskDev &t, const BlockGeom &g, Lds<BH> &L, WaveStats &st) {
+    for (int k = 0; k < t.scan_rounds; ++k) {
+        bool c = sweep<BH, CONN>(L, +1);
+        __syncthreads();
+        c |= sweep<BH, CONN>(L, -1);
+        __syncthreads();
+        if (!__ballot(c)) break;
+    }
+    converge_block<BH, CONN>(L, t.qcap, st, false, g.bh, g.bw);
+}
+
 template <int BH>
 __global__ __launch_bounds__(64) void dense_pass(TaskTable tt, KArgs a) {
     Lds<BH> L = lds_layout<BH>();
@@ -969,14 +1009,10 @@ __global__ __launch_bounds__(64) void dense_pass(TaskTable tt, KArgs a) {
         clear_halo<BH>(L);
         for (int r = ln; r < BH; r += LANES) L.rowdirty[r] = 0;
         __syncthreads();
-        for (int k = 0; k < t.scan_rounds; ++k) {
-            bool c = sweep<BH>(L, t.conn, +1);
-            __syncthreads();
-            c |= sweep<BH>(L, t.conn, -1);
-            __syncthreads();
-            if (!__ballot(c)) break;
-        }
-        converge_block<BH>(L, t.conn, t.qcap, st, false, g.bh, g.bw);
+        if (t.conn == 8)
+            dense_block<BH, 8>(t, g, L, st);
+        else
+            dense_block<BH, 4>(t, g, L, st);
         store_block<BH>(t, g, L, true);
         st.dense += 1;
         __syncthreads();
@@ -1036,40 +1072,41 @@ __global__ __launch_bounds__(64) void border_seed(TaskTable tt, KArgs a) {
 //
 // A wave without a block of its own takes a ticket (the next ring position)
 // and waits on that position's slot alone, so idle waves spread their polling
-// over separate lines.  It leaves when the count of outstanding visits is zero
-// (no visit is running or queued, so no request can come any more).
+// over separate lines.  The wave that completes the last outstanding visit
+// sets `done` and writes SLOT_EXIT into the slot of every ticket handed out so
+// far; a wave that takes a ticket later sees `done` right after taking it (the
+// two updates of ring_head are ordered, and `done` is written before).
 
-// Wait for the block id at ticket `pos`.  Returns the global block id, -1 when
-// all work is done, -2 on abort (watchdog).
-__device__ int wait_ticket(const KArgs &a, uint32_t pos) {
+// Wait for the block id at ticket `ticket`.  Returns the global block id, -1
+// when all work is done, -2 on abort (watchdog).
+__device__ int wait_ticket(const KArgs &a, uint32_t ring_cap, uint32_t ticket) {
     const int ln = lane_id();
     Work *w = a.work;
-    uint32_t *slot = a.ring + (size_t)pos * RING_STRIDE;
+    uint32_t *slot = a.ring + (size_t)(ticket % ring_cap) * RING_STRIDE;
+    int state = 0;
+    if (ln == 0 && __hip_atomic_load(&w->done, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) state = 1;
+    if (uniform(state)) return -1;
     uint32_t seen = 0;
     if (ln == 0) seen = __hip_atomic_load(&w->progress, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     seen = uniform(seen);
     uint64_t since = wall_clock64();
     for (int spin = 0;; ++spin) {
-        int v = 0, done = 0;
+        uint32_t v = 0;
         if (ln == 0) {
-            v = (int)__hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (v != 0) {
-                __hip_atomic_store(slot, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            } else if ((spin & 3) == 0) {
-                if (__hip_atomic_load(&w->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-                    done = 2;
-                else if (__hip_atomic_load(&w->pending, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u)
-                    done = 1;
-            }
+            v = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (v != 0u && v != SLOT_EXIT) __hip_atomic_store(slot, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         v = uniform(v);
-        done = uniform(done);
-        if (v != 0) return v - 1;
-        if (done) return -done;
-        if ((spin & 15) == 15) {   // watchdog: no visit completed for too long
-            uint32_t pr = 0;
-            if (ln == 0) pr = __hip_atomic_load(&w->progress, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (v == SLOT_EXIT) return -1;
+        if (v != 0u) return (int)(v - 1u);
+        if ((spin & 63) == 63) {   // abort flag and watchdog: no visit completed for too long
+            uint32_t pr = 0, ab = 0;
+            if (ln == 0) {
+                pr = __hip_atomic_load(&w->progress, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ab = __hip_atomic_load(&w->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
             pr = uniform(pr);
+            if (uniform(ab)) return -2;
             const uint64_t now = wall_clock64();
             if (pr != seen) {
                 seen = pr;
@@ -1083,6 +1120,24 @@ __device__ int wait_ticket(const KArgs &a, uint32_t pos) {
     }
 }
 
+// The last outstanding visit is complete: release every waiting ticket holder.
+__device__ void release_waiters(const KArgs &a, uint32_t ring_cap) {
+    const int ln = lane_id();
+    Work *w = a.work;
+    uint32_t h = 0, tl = 0;
+    if (ln == 0) {
+        __hip_atomic_store(&w->done, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        h = __hip_atomic_fetch_add(&w->ring_head, 0u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        tl = __hip_atomic_load(&w->ring_tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    h = uniform(h);
+    tl = uniform(tl);
+    // tickets below ring_tail were all served; the others wait for a block
+    for (uint32_t pos = tl + (uint32_t)ln; (int32_t)(h - pos) > 0; pos += LANES)
+        __hip_atomic_store(a.ring + (size_t)(pos % ring_cap) * RING_STRIDE, SLOT_EXIT, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+}
+
 template <int BH>
 __global__ __launch_bounds__(64) void revisit_drain(TaskTable tt, KArgs a) {
     Lds<BH> L = lds_layout<BH>();
@@ -1091,6 +1146,11 @@ __global__ __launch_bounds__(64) void revisit_drain(TaskTable tt, KArgs a) {
     const uint32_t ring_cap = ring_cap_of(tt);
     WaveStats st;
     int keep = -1;   // block this wave requested and keeps for its next visit
+    {   // nothing was requested at all: no visit will ever complete, leave now
+        uint32_t pend = 0;
+        if (ln == 0) pend = __hip_atomic_load(&w->pending, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        if (uniform(pend) == 0u) return;
+    }
 
     while (true) {
         int gsel = keep;
@@ -1098,9 +1158,9 @@ __global__ __launch_bounds__(64) void revisit_drain(TaskTable tt, KArgs a) {
         if (gsel < 0) {
             uint32_t ticket = 0;
             if (ln == 0)
-                ticket = __hip_atomic_fetch_add(&w->ring_head, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ticket = __hip_atomic_fetch_add(&w->ring_head, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
             ticket = uniform(ticket);
-            gsel = wait_ticket(a, ticket % ring_cap);
+            gsel = wait_ticket(a, ring_cap, ticket);
             if (gsel < 0) break;
         }
 
@@ -1132,7 +1192,9 @@ __global__ __launch_bounds__(64) void revisit_drain(TaskTable tt, KArgs a) {
             load_halo<BH>(t, g, L);
             for (int r = ln; r < BH; r += LANES) L.rowdirty[r] = 0;
             __syncthreads();
-            if (converge_block<BH>(L, t.conn, t.qcap, st, true, g.bh, g.bw)) {
+            const bool changed = t.conn == 8 ? converge_block<BH, 8>(L, t.qcap, st, true, g.bh, g.bw)
+                                             : converge_block<BH, 4>(L, t.qcap, st, true, g.bh, g.bw);
+            if (changed) {
                 store_block<BH>(t, g, L, false);
                 __threadfence();
                 ok = check_neighbours<BH>(a, ring_cap, ti, t, g, by, bx, L, &keep, st);
@@ -1157,15 +1219,17 @@ __global__ __launch_bounds__(64) void revisit_drain(TaskTable tt, KArgs a) {
             if (!rerun || !ok) break;
         }
         // ---- the visit is complete
+        int last = 0;
         if (ln == 0) {
             const uint32_t left = __hip_atomic_fetch_sub(a.tile_pending + ti, 1u, __ATOMIC_ACQ_REL,
                                                          __HIP_MEMORY_SCOPE_AGENT);
             if (left == 1u)
                 __hip_atomic_store(a.tile_done + ti, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_sub(&w->pending, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_fetch_add(&w->progress, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (!ok) __hip_atomic_store(&w->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            last = __hip_atomic_fetch_sub(&w->pending, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == 1u;
         }
+        if (uniform(last)) release_waiters(a, ring_cap);
         if (!ok) break;
     }
     flush_stats(w, st);
@@ -1188,6 +1252,7 @@ __global__ void reset_work(TaskTable tt, Work *w, uint32_t *state, uint32_t *rin
     const uint32_t n_tasks = n_tasks_of(tt), total = total_blocks_of(tt), ring_cap = ring_cap_of(tt);
     if (tid == 0) {
         w->pending = 0;
+        w->done = 0;
         w->ring_head = 0;
         w->ring_tail = 0;
         w->abort = 0;
