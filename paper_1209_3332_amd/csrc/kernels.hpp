@@ -373,6 +373,31 @@ __device__ void load_block(const TaskDev &t, const BlockGeom &g, Lds<BH> &L, boo
     const int x = 4 * ln;
     const int valid = min(4, g.bw - x);
     constexpr int CH = BH < 16 ? BH : 16;   // rows whose loads are in flight together
+    if (t.aligned && g.bw == BW) {
+        // whole-width block of a dword-aligned tile: one dword per lane and row,
+        // issued without branches (rows past the image re-read the last row
+        // and are zeroed afterwards)
+        const RK_GLOBAL uint8_t *ip = gp(t.i) + g.x0 + x;
+        const RK_GLOBAL uint8_t *jp = gp(t.j) + g.x0 + x;
+        for (int r0 = 0; r0 < BH; r0 += CH) {
+            uint32_t iv[CH], jr[CH];
+#pragma unroll
+            for (int k = 0; k < CH; ++k) {
+                const int64_t gy = g.y0 + min(r0 + k, g.bh - 1);
+                iv[k] = *(const RK_GLOBAL uint32_t *)(ip + gy * t.pitch_i);
+                jr[k] = fill_initial ? 0u : *(const RK_GLOBAL uint32_t *)(jp + gy * t.pitch_j);
+            }
+#pragma unroll
+            for (int k = 0; k < CH; ++k) {
+                const int r = r0 + k;
+                const bool in = r < g.bh;
+                const uint32_t m = in ? (t.op == OP_FILL ? ~iv[k] : iv[k]) : 0u;
+                *L.Iw(r, ln) = m;
+                *L.Jw(r, ln) = fill_initial ? fill_init4(t, g.y0 + r, g.x0 + x, in ? 4 : 0, m) : bmin4(jr[k], m);
+            }
+        }
+        return;
+    }
     for (int r0 = 0; r0 < BH; r0 += CH) {
         uint32_t iv[CH], jr[CH];
 #pragma unroll
@@ -503,8 +528,11 @@ __device__ __forceinline__ void map_scan_step(uint32_t &a, uint32_t &b) {
     b = nb;
 }
 
+// e_row for the lane's DPP row (row = lane / 16), without branches
 __device__ __forceinline__ uint32_t sel_row(int row, uint32_t e0, uint32_t e1, uint32_t e2, uint32_t e3) {
-    return row == 0 ? e0 : row == 1 ? e1 : row == 2 ? e2 : e3;
+    const uint32_t m1 = 0u - (uint32_t)(row & 1), m2 = 0u - (uint32_t)(row >> 1);
+    const uint32_t lo = e0 ^ ((e0 ^ e1) & m1), hi = e2 ^ ((e2 ^ e3) & m1);
+    return lo ^ ((lo ^ hi) & m2);
 }
 
 // Row closure of the 256 pixels held 4 per lane (byte j of lane l = pixel 4l+j):
