@@ -635,6 +635,7 @@ __device__ bool sweep(Lds<BH> &L, int dir) {
         const uint32_t nv = row_closure(bmin4(m, hi), hi, L.Jb(r, -1), L.Jb(r, BW));
         if (nv != cur) {
             *L.Jw(r, ln) = nv;
+            L.rowdirty[r] = 1;
             changed = true;
         }
         prev = nv;
@@ -784,12 +785,15 @@ __host__ __device__ constexpr int nb_dx(int k) { return k == 2 || k == 4 || k ==
 // Drain the LDS ring to empty; *overflow set if pushes had to be dropped.
 // Each round pops up to 64 pixels (one per lane) and offers every popped
 // pixel's value to its neighbours, one direction at a time.
+// At most `budget` rounds (no limit if negative); returns false if the ring was
+// not empty when the budget ran out.
 template <int BH, int CONN>
-__device__ void drain(Lds<BH> &L, int qcap, uint32_t &head, uint32_t &tail, bool &overflow) {
+__device__ bool drain(Lds<BH> &L, int qcap, uint32_t &head, uint32_t &tail, bool &overflow, int budget) {
     const int ln = lane_id();
     const volatile RK_LDS uint16_t *Qv = L.Q;
     volatile RK_LDS uint8_t *Jv = L.J;
     while (head != tail) {
+        if (budget-- == 0) return false;
         RK_LANE_SYNC();
         const uint32_t n = min(tail - head, (uint32_t)LANES);
         const bool valid = (uint32_t)ln < n;
@@ -819,15 +823,24 @@ __device__ void drain(Lds<BH> &L, int qcap, uint32_t &head, uint32_t &tail, bool
             if (!push_bits(L.Q, qcap, head, tail, raised, p + (uint32_t)(nb_dy(k) * BW + nb_dx(k)))) overflow = true;
         }
     }
+    return true;
 }
 
 // Seed and drain until no queue overflow is left; returns true if anything changed.
 // border_only: the first seed looks at the block's border only (valid when the
 // interior is already converged and only the halo changed); re-seeds after a
 // queue overflow are always dense.
+// A drain that is still running after DRAIN_BUDGET rounds is following long
+// paths one pixel per round; it is cut short and a round of sweeps (which
+// move whole row runs at once) takes over, followed by a dense seed.  After
+// SWEEP_FALLBACKS such rounds the drain runs to the end.
+constexpr int DRAIN_BUDGET = 32;
+constexpr int SWEEP_FALLBACKS = 4;
+
 template <int BH, int CONN>
 __device__ bool converge_block(Lds<BH> &L, int qcap, WaveStats &st, bool border_only, int bh, int bw) {
     bool changed = false;
+    int fallbacks = SWEEP_FALLBACKS;
     for (int round = 0; round <= (1 << 16); ++round) {   // each round raises pixels; bounded anyway
         uint32_t head = 0, tail = 0;
         bool overflow = false;
@@ -836,8 +849,16 @@ __device__ bool converge_block(Lds<BH> &L, int qcap, WaveStats &st, bool border_
         else
             seed_pass<BH, CONN>(L, qcap, head, tail, overflow, changed);
         __syncthreads();
-        drain<BH, CONN>(L, qcap, head, tail, overflow);
+        const bool drained = drain<BH, CONN>(L, qcap, head, tail, overflow, fallbacks > 0 ? DRAIN_BUDGET : -1);
         __syncthreads();
+        if (!drained) {
+            --fallbacks;
+            sweep<BH, CONN>(L, +1);
+            __syncthreads();
+            sweep<BH, CONN>(L, -1);
+            __syncthreads();
+            continue;
+        }
         if (!__ballot(overflow)) break;
         st.overflow += 1;
     }
