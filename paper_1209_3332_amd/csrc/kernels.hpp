@@ -909,25 +909,29 @@ __device__ __forceinline__ void flush_stats(Work *w, const WaveStats &st) {
 // Request a visit of global block `nb` of task `ti`.  Called by all lanes with
 // wave-uniform arguments; lane 0 performs the atomics.  If the block was idle
 // it is queued: kept by the calling wave for its next visit when `keep` points
-// to -1 (the wave's own continuation, no ring round trip), otherwise written to
-// the ring.  Returns false if the watchdog expired while waiting for a ring slot.
+// to -1 (the wave's own continuation: no ring round trip, and the calling
+// visit's count of outstanding work passes to it unchanged), otherwise counted
+// and written to the ring.  The caller has made its stores visible (release
+// fence) before, so all atomics here are relaxed.  Returns false if the
+// watchdog expired while waiting for a ring slot.
 __device__ bool request_block(const KArgs &a, uint32_t ring_cap, int ti, uint32_t nb, int *keep,
                               WaveStats &st) {
     const int ln = lane_id();
     const bool may_keep = keep != nullptr && *keep < 0;
     int pos = -1;   // >= 0 ring position; -2 kept; -1 nothing to do
     if (ln == 0) {
-        const uint32_t old = __hip_atomic_fetch_or(a.state + nb, ST_D, __ATOMIC_ACQ_REL,
+        const uint32_t old = __hip_atomic_fetch_or(a.state + nb, ST_D, __ATOMIC_RELAXED,
                                                    __HIP_MEMORY_SCOPE_AGENT);
         if (!(old & (ST_R | ST_D))) {   // the block was idle: queue it
-            __hip_atomic_fetch_add(a.tile_pending + ti, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_add(&a.work->pending, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             st.request += 1;
-            if (may_keep)
+            if (may_keep) {
                 pos = -2;
-            else
+            } else {
+                __hip_atomic_fetch_add(a.tile_pending + ti, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_add(&a.work->pending, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 pos = (int)(__hip_atomic_fetch_add(&a.work->ring_tail, 1u, __ATOMIC_RELAXED,
                                                    __HIP_MEMORY_SCOPE_AGENT) % ring_cap);
+            }
         }
     }
     pos = uniform(pos);
@@ -946,7 +950,7 @@ __device__ bool request_block(const KArgs &a, uint32_t ring_cap, int ti, uint32_
         if (expired(a, t0)) return false;
         __builtin_amdgcn_s_sleep(1);
     }
-    if (ln == 0) __hip_atomic_store(slot, nb + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (ln == 0) __hip_atomic_store(slot, nb + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return true;
 }
 
@@ -1220,20 +1224,21 @@ __global__ __launch_bounds__(64) void revisit_drain(TaskTable tt, KArgs a) {
         const int by = lb / t.nbx, bx = lb % t.nbx;
         const BlockGeom g = geom<BH>(t, by, bx);
 
-        // ---- claim: clear D, set R (acquire: the previous owner's stores and
-        // the requester's are visible from here on)
+        // ---- claim: clear D, set R.  The acquire fence after it makes the
+        // previous owner's stores and those of every requester visible (each
+        // of them fenced with release before its update of the state word).
         if (ln == 0) {
             uint32_t s = __hip_atomic_load(a.state + gb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             for (int k = 0; k < 1024; ++k) {
                 if (__hip_atomic_compare_exchange_strong(a.state + gb, &s, (s & ~ST_D) | ST_R,
-                                                         __ATOMIC_ACQ_REL, __ATOMIC_RELAXED,
+                                                         __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                                          __HIP_MEMORY_SCOPE_AGENT))
                     break;
             }
             st.revisit += 1;
         }
-        __threadfence();
         __syncthreads();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 
         load_block<BH>(t, g, L, false);
         bool ok = true;
@@ -1245,7 +1250,7 @@ __global__ __launch_bounds__(64) void revisit_drain(TaskTable tt, KArgs a) {
                                              : converge_block<BH, 4>(L, t.qcap, st, true, g.bh, g.bw);
             if (changed) {
                 store_block<BH>(t, g, L, false);
-                __threadfence();
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
                 ok = check_neighbours<BH>(a, ring_cap, ti, t, g, by, bx, L, &keep, st);
             }
             // ---- finish: re-run if requested meanwhile, else release
@@ -1254,7 +1259,7 @@ __global__ __launch_bounds__(64) void revisit_drain(TaskTable tt, KArgs a) {
                 uint32_t s = __hip_atomic_load(a.state + gb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 for (int k = 0; k < 1024; ++k) {
                     const uint32_t ns = (s & ST_D) ? (s & ~ST_D) : (s & ~ST_R);
-                    if (__hip_atomic_compare_exchange_strong(a.state + gb, &s, ns, __ATOMIC_ACQ_REL,
+                    if (__hip_atomic_compare_exchange_strong(a.state + gb, &s, ns, __ATOMIC_RELAXED,
                                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
                         rerun = (s & ST_D) ? 1 : 0;
                         break;
@@ -1263,20 +1268,25 @@ __global__ __launch_bounds__(64) void revisit_drain(TaskTable tt, KArgs a) {
                 if (rerun) st.rerun += 1;
             }
             rerun = uniform(rerun);
-            __threadfence();
             __syncthreads();
             if (!rerun || !ok) break;
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // the requesters' stores
         }
-        // ---- the visit is complete
+        // ---- the visit is complete.  A kept block inherits this visit's count
+        // of outstanding work; otherwise the counts go down.  The watchdog
+        // heartbeat is bumped on every eighth visit of a wave.
         int last = 0;
         if (ln == 0) {
-            const uint32_t left = __hip_atomic_fetch_sub(a.tile_pending + ti, 1u, __ATOMIC_ACQ_REL,
-                                                         __HIP_MEMORY_SCOPE_AGENT);
-            if (left == 1u)
-                __hip_atomic_store(a.tile_done + ti, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_add(&w->progress, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if ((st.revisit & 7u) == 0u)
+                __hip_atomic_fetch_add(&w->progress, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (!ok) __hip_atomic_store(&w->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            last = __hip_atomic_fetch_sub(&w->pending, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == 1u;
+            if (keep < 0) {
+                const uint32_t left = __hip_atomic_fetch_sub(a.tile_pending + ti, 1u, __ATOMIC_RELAXED,
+                                                             __HIP_MEMORY_SCOPE_AGENT);
+                if (left == 1u)
+                    __hip_atomic_store(a.tile_done + ti, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                last = __hip_atomic_fetch_sub(&w->pending, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 1u;
+            }
         }
         if (uniform(last)) release_waiters(a, ring_cap);
         if (!ok) break;
