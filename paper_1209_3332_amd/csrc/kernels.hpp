@@ -251,6 +251,48 @@ __device__ __forceinline__ void gstore4(uint8_t *row_, int x, int valid, int ali
     for (int k = 0; k < valid && k < 4; ++k) row[x + k] = (uint8_t)(v >> (8 * k));
 }
 
+// Marker-plane accesses of the revisit kernel go to the device-coherent level
+// (agent-scope atomic loads and stores): a wave on one XCD then reads what a
+// wave on another wrote, with no L2 write-back or invalidation.  A writer
+// waits for its stores to complete (vm_sync) before the scheduler atomics that
+// let another wave read them; a reader issues its loads only after the atomic
+// that handed it the block has returned.
+__device__ __forceinline__ uint32_t cload32(const uint8_t *p) {
+    return __hip_atomic_load((RK_GLOBAL uint32_t *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t cload8(const uint8_t *p) {
+    return __hip_atomic_load((RK_GLOBAL uint8_t *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void cstore32(uint8_t *p, uint32_t v) {
+    __hip_atomic_store((RK_GLOBAL uint32_t *)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void cstore8(uint8_t *p, uint32_t v) {
+    __hip_atomic_store((RK_GLOBAL uint8_t *)p, (uint8_t)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// wait until every memory operation this wave issued has completed
+__device__ __forceinline__ void vm_sync() {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+__device__ __forceinline__ uint32_t cload4(const uint8_t *row, int x, int valid, int aligned) {
+    if (valid <= 0) return 0u;
+    if (aligned && valid == 4) return cload32(row + x);
+    uint32_t v = 0;
+    for (int k = 0; k < valid && k < 4; ++k) v |= cload8(row + x + k) << (8 * k);
+    return v;
+}
+
+__device__ __forceinline__ void cstore4(uint8_t *row, int x, int valid, int aligned, uint32_t v) {
+    if (valid <= 0) return;
+    if (aligned && valid == 4) {
+        cstore32(row + x, v);
+        return;
+    }
+    for (int k = 0; k < valid && k < 4; ++k) cstore8(row + x + k, v >> (8 * k));
+}
+
 // mask value of 4 pixels: I, or 255 - X for fill-holes (0 outside the image)
 __device__ __forceinline__ uint32_t mask4(const TaskDev &t, int gy, int gx, int valid) {
     uint32_t v = gload4(t.i + (int64_t)gy * t.pitch_i, gx, valid, t.aligned);
@@ -367,7 +409,8 @@ __device__ __forceinline__ BlockGeom geom(const TaskDev &t, int by, int bx) {
 
 // Load I and J of the block into LDS (J clipped under I; for the first visit
 // of a fill-holes block, J is the initial frame marker).  Outside the image: 0.
-template <int BH>
+// COH: marker read from the device-coherent level (revisits).
+template <int BH, bool COH>
 __device__ void load_block(const TaskDev &t, const BlockGeom &g, Lds<BH> &L, bool fill_initial) {
     const int ln = lane_id();
     const int x = 4 * ln;
@@ -385,7 +428,12 @@ __device__ void load_block(const TaskDev &t, const BlockGeom &g, Lds<BH> &L, boo
             for (int k = 0; k < CH; ++k) {
                 const int64_t gy = g.y0 + min(r0 + k, g.bh - 1);
                 iv[k] = *(const RK_GLOBAL uint32_t *)(ip + gy * t.pitch_i);
-                jr[k] = fill_initial ? 0u : *(const RK_GLOBAL uint32_t *)(jp + gy * t.pitch_j);
+                if (fill_initial)
+                    jr[k] = 0u;
+                else if (COH)
+                    jr[k] = cload32(t.j + g.x0 + x + gy * t.pitch_j);
+                else
+                    jr[k] = *(const RK_GLOBAL uint32_t *)(jp + gy * t.pitch_j);
             }
 #pragma unroll
             for (int k = 0; k < CH; ++k) {
@@ -408,7 +456,9 @@ __device__ void load_block(const TaskDev &t, const BlockGeom &g, Lds<BH> &L, boo
             if (r < g.bh && valid > 0) {
                 const int gy = g.y0 + r;
                 iv[k] = mask4(t, gy, g.x0 + x, valid);
-                if (!fill_initial) jr[k] = gload4(t.j + (int64_t)gy * t.pitch_j, g.x0 + x, valid, t.aligned);
+                if (!fill_initial)
+                    jr[k] = COH ? cload4(t.j + (int64_t)gy * t.pitch_j, g.x0 + x, valid, t.aligned)
+                                : gload4(t.j + (int64_t)gy * t.pitch_j, g.x0 + x, valid, t.aligned);
             }
         }
 #pragma unroll
@@ -437,7 +487,7 @@ __device__ void clear_halo(Lds<BH> &L) {
 }
 
 // Load the one-pixel ring of neighbour pixels: mask, and marker clipped under
-// it (both 0 outside the image).
+// it (both 0 outside the image; the marker from the device-coherent level).
 template <int BH>
 __device__ void load_halo(const TaskDev &t, const BlockGeom &g, Lds<BH> &L) {
     const int ln = lane_id();
@@ -446,11 +496,11 @@ __device__ void load_halo(const TaskDev &t, const BlockGeom &g, Lds<BH> &L) {
     uint32_t ti = 0, tj = 0, bi = 0, bj = 0;
     if (g.has_n && valid > 0) {
         ti = mask4(t, g.y0 - 1, g.x0 + x, valid);
-        tj = gload4(t.j + (int64_t)(g.y0 - 1) * t.pitch_j, g.x0 + x, valid, t.aligned);
+        tj = cload4(t.j + (int64_t)(g.y0 - 1) * t.pitch_j, g.x0 + x, valid, t.aligned);
     }
     if (g.has_s && valid > 0) {
         bi = mask4(t, g.y0 + BH, g.x0 + x, valid);
-        bj = gload4(t.j + (int64_t)(g.y0 + BH) * t.pitch_j, g.x0 + x, valid, t.aligned);
+        bj = cload4(t.j + (int64_t)(g.y0 + BH) * t.pitch_j, g.x0 + x, valid, t.aligned);
     }
     // columns -1 and 256 for rows -1..BH (lane k handles row k-1)
     uint32_t wi[2] = {0, 0}, wj[2] = {0, 0}, ei[2] = {0, 0}, ej[2] = {0, 0};
@@ -461,11 +511,11 @@ __device__ void load_halo(const TaskDev &t, const BlockGeom &g, Lds<BH> &L) {
         const int gy = g.y0 + r;
         if (row_in && g.has_w) {
             wi[k] = mask1(t, gy, g.x0 - 1);
-            wj[k] = gp(t.j)[(int64_t)gy * t.pitch_j + g.x0 - 1];
+            wj[k] = cload8(t.j + (int64_t)gy * t.pitch_j + g.x0 - 1);
         }
         if (row_in && g.has_e) {
             ei[k] = mask1(t, gy, g.x0 + BW);
-            ej[k] = gp(t.j)[(int64_t)gy * t.pitch_j + g.x0 + BW];
+            ej[k] = cload8(t.j + (int64_t)gy * t.pitch_j + g.x0 + BW);
         }
     }
     *L.Iw(-1, ln) = ti;
@@ -868,14 +918,18 @@ __device__ bool converge_block(Lds<BH> &L, int qcap, WaveStats &st, bool border_
 }
 
 // Write back the rows flagged dirty (all rows if `all`).
-template <int BH>
+// COH: to the device-coherent level (revisits).
+template <int BH, bool COH>
 __device__ void store_block(const TaskDev &t, const BlockGeom &g, Lds<BH> &L, bool all) {
     const int ln = lane_id();
     const int x = 4 * ln;
     const int valid = min(4, g.bw - x);
     for (int r = 0; r < g.bh; ++r) {
         if (!all && !L.rowdirty[r]) continue;
-        gstore4(t.j + (int64_t)(g.y0 + r) * t.pitch_j, g.x0 + x, valid, t.aligned, *L.Jw(r, ln));
+        if (COH)
+            cstore4(t.j + (int64_t)(g.y0 + r) * t.pitch_j, g.x0 + x, valid, t.aligned, *L.Jw(r, ln));
+        else
+            gstore4(t.j + (int64_t)(g.y0 + r) * t.pitch_j, g.x0 + x, valid, t.aligned, *L.Jw(r, ln));
     }
 }
 
@@ -911,9 +965,9 @@ __device__ __forceinline__ void flush_stats(Work *w, const WaveStats &st) {
 // it is queued: kept by the calling wave for its next visit when `keep` points
 // to -1 (the wave's own continuation: no ring round trip, and the calling
 // visit's count of outstanding work passes to it unchanged), otherwise counted
-// and written to the ring.  The caller has made its stores visible (release
-// fence) before, so all atomics here are relaxed.  Returns false if the
-// watchdog expired while waiting for a ring slot.
+// and written to the ring.  The caller's marker stores have completed before
+// (vm_sync), so all atomics here are relaxed.  Returns false if the watchdog
+// expired while waiting for a ring slot.
 __device__ bool request_block(const KArgs &a, uint32_t ring_cap, int ti, uint32_t nb, int *keep,
                               WaveStats &st) {
     const int ln = lane_id();
@@ -1058,7 +1112,7 @@ __global__ __launch_bounds__(64) void dense_pass(TaskTable tt, KArgs a) {
         const int lb = (int)(gb - t.block0);
         const int by = lb / t.nbx, bx = lb % t.nbx;
         const BlockGeom g = geom<BH>(t, by, bx);
-        load_block<BH>(t, g, L, t.op == OP_FILL);
+        load_block<BH, false>(t, g, L, t.op == OP_FILL);
         clear_halo<BH>(L);
         for (int r = ln; r < BH; r += LANES) L.rowdirty[r] = 0;
         __syncthreads();
@@ -1066,7 +1120,7 @@ __global__ __launch_bounds__(64) void dense_pass(TaskTable tt, KArgs a) {
             dense_block<BH, 8>(t, g, L, st);
         else
             dense_block<BH, 4>(t, g, L, st);
-        store_block<BH>(t, g, L, true);
+        store_block<BH, false>(t, g, L, true);
         st.dense += 1;
         __syncthreads();
     }
@@ -1224,9 +1278,9 @@ __global__ __launch_bounds__(64) void revisit_drain(TaskTable tt, KArgs a) {
         const int by = lb / t.nbx, bx = lb % t.nbx;
         const BlockGeom g = geom<BH>(t, by, bx);
 
-        // ---- claim: clear D, set R.  The acquire fence after it makes the
-        // previous owner's stores and those of every requester visible (each
-        // of them fenced with release before its update of the state word).
+        // ---- claim: clear D, set R.  The previous owner and every requester
+        // completed their (coherent) stores before updating the state word, so
+        // loads issued after the claim returned see them.
         if (ln == 0) {
             uint32_t s = __hip_atomic_load(a.state + gb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             for (int k = 0; k < 1024; ++k) {
@@ -1238,9 +1292,9 @@ __global__ __launch_bounds__(64) void revisit_drain(TaskTable tt, KArgs a) {
             st.revisit += 1;
         }
         __syncthreads();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
 
-        load_block<BH>(t, g, L, false);
+        load_block<BH, true>(t, g, L, false);
         bool ok = true;
         while (true) {
             load_halo<BH>(t, g, L);
@@ -1249,8 +1303,8 @@ __global__ __launch_bounds__(64) void revisit_drain(TaskTable tt, KArgs a) {
             const bool changed = t.conn == 8 ? converge_block<BH, 8>(L, t.qcap, st, true, g.bh, g.bw)
                                              : converge_block<BH, 4>(L, t.qcap, st, true, g.bh, g.bw);
             if (changed) {
-                store_block<BH>(t, g, L, false);
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                store_block<BH, true>(t, g, L, false);
+                vm_sync();   // the stores are complete before any request below
                 ok = check_neighbours<BH>(a, ring_cap, ti, t, g, by, bx, L, &keep, st);
             }
             // ---- finish: re-run if requested meanwhile, else release
@@ -1270,7 +1324,7 @@ __global__ __launch_bounds__(64) void revisit_drain(TaskTable tt, KArgs a) {
             rerun = uniform(rerun);
             __syncthreads();
             if (!rerun || !ok) break;
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // the requesters' stores
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
         }
         // ---- the visit is complete.  A kept block inherits this visit's count
         // of outstanding work; otherwise the counts go down.  The watchdog

@@ -111,6 +111,8 @@ inline int __builtin_amdgcn_update_dpp(int old, int src, int ctrl, int row_mask,
 inline int __builtin_amdgcn_readlane(int v, int lane) { return (int)(uint32_t)kemu::exchange((uint32_t)v, lane); }
 // Memory fence of a given order at a named scope: a full fence on the host.
 inline void __builtin_amdgcn_fence(int, const char *) { std::atomic_thread_fence(std::memory_order_seq_cst); }
+// Waiting for this wave's memory operations: a full fence on the host.
+inline void __builtin_amdgcn_s_waitcnt(int) { std::atomic_thread_fence(std::memory_order_seq_cst); }
 
 inline uint32_t atomicCAS(uint32_t *p, uint32_t expected, uint32_t desired) {
     kemu::check_lds(p, 4);
