@@ -11,13 +11,20 @@ its own untouched copies of the inputs, all resident in device memory before
 the timed region; `value` = pixels processed (2 x 16.78 M per step) / time.
 
 Alongside, in the same run: the batched-vs-per-tile comparison on a batch of
-4096 x 4096 tiles (56 nuclei-like + 8 spiral corridors at the default 64), the
-per-kernel HIP-event durations of the timed steps, the dense kernel's
-roofline, and the CPU oracle timed on the host cores on a bounded sample.
+4096 x 4096 nuclei-like tiles with every eighth tile replaced by a spiral
+corridor (1024 x 1024 by default: a corridor is one sequential chain of
+pixels, and a 4096 x 4096 one crosses about 590 thousand blocks, which takes
+tens of seconds; --spiral-size 4096 runs them at full size), the per-kernel
+HIP-event durations of the timed steps, the dominant kernel's roofline (with
+the HBM traffic of the committed counter summary when it was taken on the
+current kernel source), and the CPU oracle timed on the host cores on a
+bounded sample.
 """
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -43,6 +50,32 @@ def percentile(xs, q):
     return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
 
 
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1209_3332_amd", "csrc", "kernels.hpp")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "revisit_drain_4k_nuclei_traffic.md")
+
+
+def kernel_sha():
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def committed_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration), or None if
+    there is none or it was taken on other kernel source."""
+    try:
+        text = open(TRAFFIC_SUMMARY).read()
+    except OSError:
+        return None
+    m = re.search(r"^TRAFFIC_JSON (\{.*\})$", text, re.M)
+    if not m:
+        return None
+    d = json.loads(m.group(1))
+    if d.get("kernel_sha") != kernel_sha() or kernel not in d.get("bytes_per_launch", {}):
+        return None
+    return d["bytes_per_launch"][kernel]
+
+
 def _gen_tile(args):
     import synth
     i, size = args
@@ -50,7 +83,7 @@ def _gen_tile(args):
     return i, synth.hdome_marker(mask, 30), mask
 
 
-def make_batch(n_tiles, size, workers):
+def make_batch(n_tiles, size, workers, spiral_size):
     """Host arrays of the batch: (kind, marker, mask) per tile; tiles i = 7 (mod 8) are spirals."""
     import multiprocessing as mp
     import synth
@@ -64,7 +97,7 @@ def make_batch(n_tiles, size, workers):
         if i % 8 == 7:
             where = "outer" if i % 16 == 7 else "inner"
             if where not in spirals:
-                spirals[where] = synth.spiral_tile(size, size, where)[:2]
+                spirals[where] = synth.spiral_tile(spiral_size, spiral_size, where)[:2]
             out[i] = ("spiral", spirals[where][0], spirals[where][1])
     return out
 
@@ -89,18 +122,19 @@ def cpu_baseline(marker, mask, binary, budget_s=20.0):
                       "single-core %.2f Mpixel/s" % (n, mask.shape[0], mask.shape[1], 2 * mask.size / one / 1e6)}
 
 
-def batched_vs_per_tile(recon, torch, ctx_cfg, n_tiles, size, workers):
+def batched_vs_per_tile(recon, torch, ctx_cfg, n_tiles, size, workers, spiral_size):
     import numpy as np
     import oracle
     t0 = time.perf_counter()
-    batch = make_batch(n_tiles, size, workers)
+    batch = make_batch(n_tiles, size, workers, spiral_size)
     log("batch: generated %d tiles in %.1f s" % (n_tiles, time.perf_counter() - t0))
     dev = torch.device("cuda:0")
     masks = [torch.from_numpy(b[2]).to(dev) for b in batch]
     pristine = [torch.from_numpy(b[1]).to(dev) for b in batch]
     px = sum(m.numel() for m in masks)
     kinds = [b[0] for b in batch]
-    res = {"tiles": n_tiles, "tile": [size, size], "spirals": kinds.count("spiral")}
+    res = {"tiles": n_tiles, "tile": [size, size], "spirals": kinds.count("spiral"),
+           "spiral_tile": [spiral_size, spiral_size], "pixels": px}
     with recon.Recon(0, **ctx_cfg) as ctx:
         stream = torch.cuda.current_stream()
         # batched: one graph replay over the whole batch (warm once)
@@ -145,6 +179,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--size", type=int, default=4096)
     ap.add_argument("--batch-tiles", type=int, default=64, help="0 skips the batched-vs-per-tile comparison")
+    ap.add_argument("--spiral-size", type=int, default=1024, help="side of the spiral-corridor tiles of the batch")
     ap.add_argument("--block-rows", type=int, default=0)
     ap.add_argument("--scan-rounds", type=int, default=0)
     ap.add_argument("--queue", type=int, default=0)
@@ -225,20 +260,27 @@ def main():
                           "revisits": avg(kd, "revisits"), "queue_overflows": avg(kd, "queue_overflows")},
                "fill_holes": {"dense_pass_ms": avg(kf, "dense_ms"), "border_seed_ms": avg(kf, "seed_ms"),
                               "revisit_drain_ms": avg(kf, "drain_ms"), "launch_ms": avg(kf, "total_ms"),
-                              "revisits": avg(kf, "revisits")}}
-    # dominant kernel of the step (by average duration) and its roofline
+                              "revisits": avg(kf, "revisits"), "queue_overflows": avg(kf, "queue_overflows")}}
+    # dominant kernel of the step (by average duration) and its roofline.  The
+    # algorithmic bytes of a kernel: dense_pass reads mask and marker and writes
+    # the marker once per pixel (3 B/px; fill-holes 2 B/px, its marker is
+    # implicit); a revisit reads a block's mask and marker and writes it back
+    # (3 B/px of the block per visit).
+    bh = cfg.get("block_rows", 32)
     cand = [("dense_pass (dilate)", kernels["dilate"]["dense_pass_ms"], BYTES_DILATE * mask.size),
-            ("revisit_drain (dilate)", kernels["dilate"]["revisit_drain_ms"], None),
+            ("revisit_drain (dilate)", kernels["dilate"]["revisit_drain_ms"],
+             3.0 * bh * 256 * kernels["dilate"]["revisits"]),
             ("dense_pass (fill_holes)", kernels["fill_holes"]["dense_pass_ms"], BYTES_FILL * mask.size),
-            ("revisit_drain (fill_holes)", kernels["fill_holes"]["revisit_drain_ms"], None)]
+            ("revisit_drain (fill_holes)", kernels["fill_holes"]["revisit_drain_ms"],
+             3.0 * bh * 256 * kernels["fill_holes"]["revisits"])]
     dom = max(cand, key=lambda c: c[1])
-    dense = cand[0]
-    achieved = dense[2] / (dense[1] * 1e-3) / 1e9
-    roofline = {"kernel": dense[0], "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "bytes_per_px": BYTES_DILATE,
-                "dominant_kernel": dom[0], "dominant_ms": dom[1],
-                "step_GBs": (BYTES_DILATE + BYTES_FILL) * mask.size / (ms_per_step * 1e-3) / 1e9}
-
+    achieved = dom[2] / (dom[1] * 1e-3) / 1e9
+    traffic = committed_traffic(dom[0])
+    roofline = {"kernel": dom[0], "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "algorithmic_bytes": dom[2],
+                "kernel_ms": dom[1],
+                "step_GBs": (BYTES_DILATE + BYTES_FILL) * mask.size / (ms_per_step * 1e-3) / 1e9,
+                "kernel_source": kernel_sha()}
     out = {"metric": METRIC, "value": value, "unit": "Mpixel/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "u8", "data": "synthetic",
@@ -249,7 +291,8 @@ def main():
     ctx.close()
     if args.batch_tiles:
         out["batched_vs_per_tile"] = batched_vs_per_tile(recon, torch, {k: v for k, v in cfg.items()},
-                                                         args.batch_tiles, args.size, args.workers)
+                                                         args.batch_tiles, args.size, args.workers,
+                                                         args.spiral_size)
         b = out["batched_vs_per_tile"]
         log("batch of %d: batched %.0f Mpixel/s vs per-tile %.0f Mpixel/s" % (
             args.batch_tiles, b["batched"]["Mpixel_s"], b["per_tile"]["Mpixel_s"]))
