@@ -114,7 +114,9 @@ typedef struct {
     int64_t requests;          /* block revisits requested by border checks */
     int64_t aborted;           /* 1 if the scheduler watchdog stopped the launch */
     /* with recon_config.timing: durations in ms of the dense pass (K1), the border
-       seeding (K2), the revisit drain (K3) and the whole launch; else 0 */
+       seeding (K2), the revisit drain (K3) and the whole launch; else 0.  A
+       batch replayed from a captured graph is timed as a whole: the three
+       kernel durations are then -1 */
     float dense_ms, seed_ms, drain_ms, total_ms;
 } recon_stats;
 

@@ -119,6 +119,7 @@ struct recon_ctx {
     hipEvent_t last_done = nullptr;
     hipEvent_t tev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};   // timing marks
     bool have_last = false;
+    bool last_was_graph = false;   // the last launch replayed a graph (only its total is timed)
     int resident[kVariants] = {0, 0, 0};
     // captured batch graphs per variant
     hipStream_t cap_stream = nullptr;
@@ -319,7 +320,9 @@ int enqueue_kernels(recon_ctx *c, int v, const rk::TaskTable &tt, uint32_t total
     const int grid3 = std::max(1, std::min<int>(std::min(resident, rk::MAX_DRAIN_GRID),
                                                 (int)std::max<uint32_t>(1u, nblk)));
     const int stop = c->cfg.stop_after_stage;
-    const bool timing = c->cfg.timing != 0;
+    // per-kernel timing marks on plain launches only: events recorded inside a
+    // captured graph cannot be timed (a graph launch is timed as a whole)
+    const bool timing = c->cfg.timing != 0 && !dynamic_sizes;
     hipLaunchKernelGGL(rk::reset_work, dim3(64), dim3(256), 0, s, tt, c->d_work, c->d_state, c->d_ring,
                        c->d_tile_pending, c->d_tile_done);
     if (timing) HIP_TRY(hipEventRecord(c->tev[0], s));
@@ -407,7 +410,9 @@ int run_tasks(recon_ctx *c, const recon_task *tasks, int n, hipStream_t stream, 
             c->graph_cap_tasks[v] = c->cap_tasks;
             c->graph_cap_scratch[v] = c->cap_scratch;
         }
+        if (c->cfg.timing) HIP_TRY(hipEventRecord(c->tev[0], stream));
         HIP_TRY(hipGraphLaunch(c->graph[v], stream));
+        if (c->cfg.timing) HIP_TRY(hipEventRecord(c->tev[4], stream));
         HIP_TRY(hipEventRecord(c->table_used, stream));
     } else {
         if (!inline_table) {
@@ -420,6 +425,7 @@ int run_tasks(recon_ctx *c, const recon_task *tasks, int n, hipStream_t stream, 
     }
     HIP_TRY(hipEventRecord(c->last_done, stream));
     c->have_last = true;
+    c->last_was_graph = use_graph;
     return RECON_OK;
 }
 
@@ -785,10 +791,15 @@ int recon_last_stats(recon_ctx *ctx, recon_stats *out) {
     out->aborted = (int64_t)w.abort;
     if (ctx->cfg.timing) {
         float ms = 0.f;
-        if (hipEventElapsedTime(&ms, ctx->tev[0], ctx->tev[1]) == hipSuccess) out->dense_ms = ms;
-        if (hipEventElapsedTime(&ms, ctx->tev[1], ctx->tev[2]) == hipSuccess) out->seed_ms = ms;
-        if (hipEventElapsedTime(&ms, ctx->tev[2], ctx->tev[3]) == hipSuccess) out->drain_ms = ms;
+        if (ctx->last_was_graph) {
+            out->dense_ms = out->seed_ms = out->drain_ms = -1.f;   // not timed per kernel
+        } else {
+            if (hipEventElapsedTime(&ms, ctx->tev[0], ctx->tev[1]) == hipSuccess) out->dense_ms = ms;
+            if (hipEventElapsedTime(&ms, ctx->tev[1], ctx->tev[2]) == hipSuccess) out->seed_ms = ms;
+            if (hipEventElapsedTime(&ms, ctx->tev[2], ctx->tev[3]) == hipSuccess) out->drain_ms = ms;
+        }
         if (hipEventElapsedTime(&ms, ctx->tev[0], ctx->tev[4]) == hipSuccess) out->total_ms = ms;
+        (void)hipGetLastError();   // a stage that was not recorded must not leave an error behind
     }
     if (w.abort) return fail(RECON_EDEVICE, "scheduler watchdog expired: the last launch did not converge");
     return RECON_OK;

@@ -257,6 +257,33 @@ def test_batch_with_spirals(torch_mod, rc, oracle_mod):
         assert_same(got, oracle_mod.run_task(t), "config-3 style task %d (%s)" % (i, t["kind"]))
 
 
+def test_graph_replays_with_timing(torch_mod, lib, oracle_mod):
+    """The same batch replayed from the captured graph three times, with eager
+    work and synchronisation in between, equals the plain per-task calls each
+    time; timing a graph replay reports the launch total only and leaves no HIP
+    error behind for the next torch call."""
+    rng = np.random.default_rng(77)
+    tasks = _batch_tasks(rng, 14)
+    with lib.Recon(0, timing=1) as ctx:
+        eager = []
+        for t in tasks:
+            if t["op"] == "dilate":
+                eager.append(gpu_dilate(torch_mod, ctx, t["marker"], t["mask"], t["conn"]))
+            else:
+                eager.append(gpu_fill(torch_mod, ctx, t["img"], t["conn"]))
+        for rep in range(3):
+            outs = _run_batch(torch_mod, ctx, tasks)
+            st = ctx.last_stats()
+            assert st["total_ms"] > 0 and st["dense_ms"] == -1.0
+            probe = torch_mod.arange(1000, device="cuda").sum().item()   # eager work in between
+            assert probe == 499500
+            torch_mod.cuda.synchronize()
+            for i, (want, got) in enumerate(zip(eager, outs)):
+                assert_same(got, want, "replay %d task %d" % (rep, i))
+    for i, (t, got) in enumerate(zip(tasks, eager)):
+        assert_same(got, oracle_mod.run_task(t), "eager task %d" % i)
+
+
 def test_argument_errors(torch_mod, rc, lib):
     a = torch_mod.zeros((4, 5), dtype=torch_mod.uint8, device="cuda")
     b = torch_mod.zeros((4, 6), dtype=torch_mod.uint8, device="cuda")
