@@ -486,50 +486,99 @@ __device__ void clear_halo(Lds<BH> &L) {
     }
 }
 
-// Load the one-pixel ring of neighbour pixels: mask, and marker clipped under
-// it (both 0 outside the image; the marker from the device-coherent level).
+// The one-pixel ring of neighbour pixels: mask, and marker clipped under it
+// (both 0 outside the image; the marker from the device-coherent level).
+// Loads into registers first (halo_issue), LDS stores after (halo_store), so a
+// caller can have other loads in flight meanwhile.
+struct HaloRegs {
+    uint32_t ti, tj, bi, bj;
+    uint32_t wi[2], wj[2], ei[2], ej[2];
+};
+
 template <int BH>
-__device__ void load_halo(const TaskDev &t, const BlockGeom &g, Lds<BH> &L) {
+__device__ __forceinline__ void halo_issue(const TaskDev &t, const BlockGeom &g, HaloRegs &h) {
     const int ln = lane_id();
     const int x = 4 * ln;
     const int valid = min(4, g.bw - x);
-    uint32_t ti = 0, tj = 0, bi = 0, bj = 0;
+    h.ti = h.tj = h.bi = h.bj = 0;
     if (g.has_n && valid > 0) {
-        ti = mask4(t, g.y0 - 1, g.x0 + x, valid);
-        tj = cload4(t.j + (int64_t)(g.y0 - 1) * t.pitch_j, g.x0 + x, valid, t.aligned);
+        h.ti = mask4(t, g.y0 - 1, g.x0 + x, valid);
+        h.tj = cload4(t.j + (int64_t)(g.y0 - 1) * t.pitch_j, g.x0 + x, valid, t.aligned);
     }
     if (g.has_s && valid > 0) {
-        bi = mask4(t, g.y0 + BH, g.x0 + x, valid);
-        bj = cload4(t.j + (int64_t)(g.y0 + BH) * t.pitch_j, g.x0 + x, valid, t.aligned);
+        h.bi = mask4(t, g.y0 + BH, g.x0 + x, valid);
+        h.bj = cload4(t.j + (int64_t)(g.y0 + BH) * t.pitch_j, g.x0 + x, valid, t.aligned);
     }
     // columns -1 and 256 for rows -1..BH (lane k handles row k-1)
-    uint32_t wi[2] = {0, 0}, wj[2] = {0, 0}, ei[2] = {0, 0}, ej[2] = {0, 0};
     for (int k = 0; k < 2; ++k) {
+        h.wi[k] = h.wj[k] = h.ei[k] = h.ej[k] = 0;
         const int r = ln - 1 + k * LANES;
-        if (r > BH) break;
         const bool row_in = (r >= 0 && r < g.bh) || (r == -1 && g.has_n) || (r == BH && g.has_s);
         const int gy = g.y0 + r;
         if (row_in && g.has_w) {
-            wi[k] = mask1(t, gy, g.x0 - 1);
-            wj[k] = cload8(t.j + (int64_t)gy * t.pitch_j + g.x0 - 1);
+            h.wi[k] = mask1(t, gy, g.x0 - 1);
+            h.wj[k] = cload8(t.j + (int64_t)gy * t.pitch_j + g.x0 - 1);
         }
         if (row_in && g.has_e) {
-            ei[k] = mask1(t, gy, g.x0 + BW);
-            ej[k] = cload8(t.j + (int64_t)gy * t.pitch_j + g.x0 + BW);
+            h.ei[k] = mask1(t, gy, g.x0 + BW);
+            h.ej[k] = cload8(t.j + (int64_t)gy * t.pitch_j + g.x0 + BW);
         }
     }
-    *L.Iw(-1, ln) = ti;
-    *L.Jw(-1, ln) = bmin4(tj, ti);
-    *L.Iw(BH, ln) = bi;
-    *L.Jw(BH, ln) = bmin4(bj, bi);
+}
+
+template <int BH>
+__device__ __forceinline__ void halo_store(const HaloRegs &h, Lds<BH> &L) {
+    const int ln = lane_id();
+    *L.Iw(-1, ln) = h.ti;
+    *L.Jw(-1, ln) = bmin4(h.tj, h.ti);
+    *L.Iw(BH, ln) = h.bi;
+    *L.Jw(BH, ln) = bmin4(h.bj, h.bi);
     for (int k = 0; k < 2; ++k) {
         const int r = ln - 1 + k * LANES;
         if (r > BH) break;
-        L.Ib(r, -1) = (uint8_t)wi[k];
-        L.Jb(r, -1) = (uint8_t)min(wj[k], wi[k]);
-        L.Ib(r, BW) = (uint8_t)ei[k];
-        L.Jb(r, BW) = (uint8_t)min(ej[k], ei[k]);
+        L.Ib(r, -1) = (uint8_t)h.wi[k];
+        L.Jb(r, -1) = (uint8_t)min(h.wj[k], h.wi[k]);
+        L.Ib(r, BW) = (uint8_t)h.ei[k];
+        L.Jb(r, BW) = (uint8_t)min(h.ej[k], h.ei[k]);
     }
+}
+
+template <int BH>
+__device__ void load_halo(const TaskDev &t, const BlockGeom &g, Lds<BH> &L) {
+    HaloRegs h;
+    halo_issue<BH>(t, g, h);
+    halo_store<BH>(h, L);
+}
+
+// A revisit's load: the block (mask, and marker from the device-coherent
+// level) and its halo, with all loads of a whole-width aligned block of up to
+// 32 rows in flight together.
+template <int BH>
+__device__ void load_visit(const TaskDev &t, const BlockGeom &g, Lds<BH> &L) {
+    if (!(t.aligned && g.bw == BW && BH <= 32)) {
+        load_block<BH, true>(t, g, L, false);
+        load_halo<BH>(t, g, L);
+        return;
+    }
+    const int ln = lane_id();
+    const int x = 4 * ln;
+    HaloRegs h;
+    halo_issue<BH>(t, g, h);
+    uint32_t iv[BH], jr[BH];
+#pragma unroll
+    for (int k = 0; k < BH; ++k) {
+        const int64_t gy = g.y0 + min(k, g.bh - 1);
+        iv[k] = *(const RK_GLOBAL uint32_t *)(gp(t.i) + g.x0 + x + gy * t.pitch_i);
+        jr[k] = cload32(t.j + g.x0 + x + gy * t.pitch_j);
+    }
+#pragma unroll
+    for (int k = 0; k < BH; ++k) {
+        const bool in = k < g.bh;
+        const uint32_t m = in ? (t.op == OP_FILL ? ~iv[k] : iv[k]) : 0u;
+        *L.Iw(k, ln) = m;
+        *L.Jw(k, ln) = bmin4(jr[k], m);
+    }
+    halo_store<BH>(h, L);
 }
 
 // neighbour bytes of a dword row across lanes: left = pixel x-1, right = pixel x+4
@@ -960,51 +1009,65 @@ __device__ __forceinline__ void flush_stats(Work *w, const WaveStats &st) {
         __hip_atomic_fetch_add(&w->stat_request, st.request, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Request a visit of global block `nb` of task `ti`.  Called by all lanes with
-// wave-uniform arguments; lane 0 performs the atomics.  If the block was idle
-// it is queued: kept by the calling wave for its next visit when `keep` points
-// to -1 (the wave's own continuation: no ring round trip, and the calling
-// visit's count of outstanding work passes to it unchanged), otherwise counted
-// and written to the ring.  The caller's marker stores have completed before
-// (vm_sync), so all atomics here are relaxed.  Returns false if the watchdog
-// expired while waiting for a ring slot.
-__device__ bool request_block(const KArgs &a, uint32_t ring_cap, int ti, uint32_t nb, int *keep,
-                              WaveStats &st) {
+// Request visits of the neighbouring blocks flagged in `want` (bit k:
+// neighbour k of N, S, W, E, NW, NE, SW, SE) of block `gb` of task `ti`.
+// Called by all lanes with wave-uniform arguments; lane k handles neighbour k,
+// so the requests go out together.  When `keep` points to -1, the first
+// flagged neighbour is claimed for the calling wave's next visit if it is idle
+// (compare-and-swap idle -> owned): no ring round trip, and the calling visit's
+// count of outstanding work passes to it unchanged.  Every other neighbour gets
+// its requested bit; one that was idle is counted and written to the ring.  The
+// caller's marker stores have completed before (vm_sync), so all atomics here
+// are relaxed.  Returns false if the watchdog expired while waiting for a ring
+// slot.
+__device__ bool request_neighbours(const KArgs &a, uint32_t ring_cap, int ti, uint32_t gb, int nbx, uint32_t want,
+                                   int *keep, WaveStats &st) {
     const int ln = lane_id();
-    const bool may_keep = keep != nullptr && *keep < 0;
-    int pos = -1;   // >= 0 ring position; -2 kept; -1 nothing to do
-    if (ln == 0) {
-        const uint32_t old = __hip_atomic_fetch_or(a.state + nb, ST_D, __ATOMIC_RELAXED,
-                                                   __HIP_MEMORY_SCOPE_AGENT);
-        if (!(old & (ST_R | ST_D))) {   // the block was idle: queue it
-            st.request += 1;
-            if (may_keep) {
-                pos = -2;
-            } else {
-                __hip_atomic_fetch_add(a.tile_pending + ti, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __hip_atomic_fetch_add(&a.work->pending, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                pos = (int)(__hip_atomic_fetch_add(&a.work->ring_tail, 1u, __ATOMIC_RELAXED,
-                                                   __HIP_MEMORY_SCOPE_AGENT) % ring_cap);
-            }
+    const int k = ln & 7;
+    const int off = k == 0 ? -nbx : k == 1 ? nbx : k == 2 ? -1 : k == 3 ? 1 : k == 4 ? -nbx - 1
+                  : k == 5 ? -nbx + 1 : k == 6 ? nbx - 1 : nbx + 1;
+    const uint32_t nb = (uint32_t)((int)gb + off);
+    const bool mine = ln < 8 && ((want >> ln) & 1u);
+    const int cand = (keep != nullptr && *keep < 0 && want != 0u) ? (int)__builtin_ctz(want) : -1;
+    bool kept = false, queue = false;
+    if (mine) {
+        uint32_t old;
+        if (ln == cand) {
+            uint32_t expected = 0u;
+            kept = __hip_atomic_compare_exchange_strong(a.state + nb, &expected, ST_R, __ATOMIC_RELAXED,
+                                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            old = kept ? 0u : __hip_atomic_fetch_or(a.state + nb, ST_D, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            old = __hip_atomic_fetch_or(a.state + nb, ST_D, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
+        queue = !kept && !(old & (ST_R | ST_D));   // this request made an idle block pending
     }
-    pos = uniform(pos);
-    if (pos == -2) {
-        *keep = (int)nb;
-        return true;
+    if (__ballot(kept)) {
+        *keep = (int)((int)gb + (cand == 0 ? -nbx : cand == 1 ? nbx : cand == 2 ? -1 : cand == 3 ? 1
+                      : cand == 4 ? -nbx - 1 : cand == 5 ? -nbx + 1 : cand == 6 ? nbx - 1 : nbx + 1));
+        if (ln == 0) st.request += 1;
     }
-    if (pos < 0) return true;
-    uint32_t *slot = a.ring + (size_t)pos * RING_STRIDE;
-    // the slot is free unless its previous occupant has not been taken out yet
+    const unsigned long long qm = __ballot(queue);
+    if (qm == 0) return true;
+    const uint32_t nq = (uint32_t)__popcll(qm);
+    uint32_t base = 0;
+    if (ln == 0) {
+        __hip_atomic_fetch_add(a.tile_pending + ti, nq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(&a.work->pending, nq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        base = __hip_atomic_fetch_add(&a.work->ring_tail, nq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        st.request += nq;
+    }
+    base = uniform(base);
+    uint32_t *slot = a.ring + (size_t)((base + prefix_count(qm)) % ring_cap) * RING_STRIDE;
+    // a slot is free unless its previous occupant has not been taken out yet
     const uint64_t t0 = wall_clock64();
     while (true) {
-        int busy = 0;
-        if (ln == 0) busy = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
-        if (!uniform(busy)) break;
+        const bool busy = queue && __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
+        if (!__ballot(busy)) break;
         if (expired(a, t0)) return false;
         __builtin_amdgcn_s_sleep(1);
     }
-    if (ln == 0) __hip_atomic_store(slot, nb + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (queue) __hip_atomic_store(slot, nb + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return true;
 }
 
@@ -1076,12 +1139,8 @@ __device__ bool check_neighbours(const KArgs &a, uint32_t ring_cap, int ti, cons
         want |= (uint32_t)(__ballot(viol) & 0xfull) << 4;
     }
     want = uniform(want);
-    const int nbx = t.nbx;
-    const int offs[8] = {-nbx, nbx, -1, 1, -nbx - 1, -nbx + 1, nbx - 1, nbx + 1};
-    for (int k = 0; k < 8; ++k)
-        if (want & (1u << k))
-            if (!request_block(a, ring_cap, ti, (uint32_t)((int)gb + offs[k]), keep, st)) return false;
-    return true;
+    if (want == 0u) return true;
+    return request_neighbours(a, ring_cap, ti, gb, t.nbx, want, keep, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -1259,9 +1318,13 @@ __global__ __launch_bounds__(64) void revisit_drain(TaskTable tt, KArgs a) {
         if (uniform(pend) == 0u) return;
     }
 
+    int cur_ti = -1;      // task of the last visit and its descriptor (most visits stay in one task)
+    TaskDev t{};
+    uint32_t t_end = 0;
     while (true) {
         int gsel = keep;
         keep = -1;
+        const bool claimed = gsel >= 0;   // a kept block was claimed when it was requested
         if (gsel < 0) {
             uint32_t ticket = 0;
             if (ln == 0)
@@ -1272,32 +1335,38 @@ __global__ __launch_bounds__(64) void revisit_drain(TaskTable tt, KArgs a) {
         }
 
         const uint32_t gb = (uint32_t)gsel;
-        const int ti = uniform(find_task(tt, gb));
-        const TaskDev t = task_of(tt, ti);
+        if (cur_ti < 0 || gb < t.block0 || gb >= t_end) {
+            cur_ti = uniform(find_task(tt, gb));
+            t = task_of(tt, cur_ti);
+            t_end = t.block0 + (uint32_t)(t.nby * t.nbx);
+        }
+        const int ti = cur_ti;
         const int lb = (int)(gb - t.block0);
         const int by = lb / t.nbx, bx = lb % t.nbx;
         const BlockGeom g = geom<BH>(t, by, bx);
 
-        // ---- claim: clear D, set R.  The previous owner and every requester
+        // ---- claim: clear D, set R (a kept block is owned already).  The previous owner and every requester
         // completed their (coherent) stores before updating the state word, so
         // loads issued after the claim returned see them.
         if (ln == 0) {
-            uint32_t s = __hip_atomic_load(a.state + gb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            for (int k = 0; k < 1024; ++k) {
-                if (__hip_atomic_compare_exchange_strong(a.state + gb, &s, (s & ~ST_D) | ST_R,
-                                                         __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                                         __HIP_MEMORY_SCOPE_AGENT))
-                    break;
+            if (!claimed) {
+                uint32_t s = __hip_atomic_load(a.state + gb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                for (int k = 0; k < 1024; ++k) {
+                    if (__hip_atomic_compare_exchange_strong(a.state + gb, &s, (s & ~ST_D) | ST_R,
+                                                             __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                             __HIP_MEMORY_SCOPE_AGENT))
+                        break;
+                }
             }
             st.revisit += 1;
         }
         __syncthreads();
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
 
-        load_block<BH, true>(t, g, L, false);
+        load_visit<BH>(t, g, L);
         bool ok = true;
-        while (true) {
-            load_halo<BH>(t, g, L);
+        for (int pass = 0;; ++pass) {
+            if (pass > 0) load_halo<BH>(t, g, L);   // a re-run: neighbours changed meanwhile
             for (int r = ln; r < BH; r += LANES) L.rowdirty[r] = 0;
             __syncthreads();
             const bool changed = t.conn == 8 ? converge_block<BH, 8>(L, t.qcap, st, true, g.bh, g.bw)
@@ -1337,9 +1406,11 @@ __global__ __launch_bounds__(64) void revisit_drain(TaskTable tt, KArgs a) {
             if (keep < 0) {
                 const uint32_t left = __hip_atomic_fetch_sub(a.tile_pending + ti, 1u, __ATOMIC_RELAXED,
                                                              __HIP_MEMORY_SCOPE_AGENT);
+                const uint32_t all = __hip_atomic_fetch_sub(&w->pending, 1u, __ATOMIC_RELAXED,
+                                                            __HIP_MEMORY_SCOPE_AGENT);
                 if (left == 1u)
                     __hip_atomic_store(a.tile_done + ti, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                last = __hip_atomic_fetch_sub(&w->pending, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 1u;
+                last = all == 1u;
             }
         }
         if (uniform(last)) release_waiters(a, ring_cap);
