@@ -909,17 +909,20 @@ __device__ bool drain(Lds<BH> &L, int qcap, uint32_t &head, uint32_t &tail, bool
         const bool ok_w = valid && x > 0, ok_e = valid && x < BW - 1;
         // reads: the popped value, its neighbours' marker and mask (a block
         // pixel's neighbours lie in the LDS planes, the halo ring at worst)
+        // (unconditional, so that they all go out before the first wait)
         const uint32_t v = Jv[a];
-        uint32_t tgt[CONN];
+        uint32_t cur[CONN], tgt[CONN];
+#pragma unroll
+        for (int k = 0; k < CONN; ++k) cur[k] = Jv[a + nb_dy(k) * JP + nb_dx(k)];
+#pragma unroll
+        for (int k = 0; k < CONN; ++k) tgt[k] = L.I[a + nb_dy(k) * JP + nb_dx(k)];
         uint32_t raise = 0u;
 #pragma unroll
         for (int k = 0; k < CONN; ++k) {
-            const int off = nb_dy(k) * JP + nb_dx(k);
-            const uint32_t cur = Jv[a + off];
-            tgt[k] = min(v, (uint32_t)L.I[a + off]);
+            tgt[k] = min(v, tgt[k]);
             const bool in = (nb_dy(k) < 0 ? ok_n : nb_dy(k) > 0 ? ok_s : valid) &&
                             (nb_dx(k) < 0 ? ok_w : nb_dx(k) > 0 ? ok_e : true);
-            if (in && cur < tgt[k]) raise |= 1u << k;
+            if (in && cur[k] < tgt[k]) raise |= 1u << k;
         }
         RK_LANE_SYNC();
         // stores, read back until every raise holds
@@ -929,10 +932,12 @@ __device__ bool drain(Lds<BH> &L, int qcap, uint32_t &head, uint32_t &tail, bool
             for (int k = 0; k < CONN; ++k)
                 if ((pend >> k) & 1u) Jv[a + nb_dy(k) * JP + nb_dx(k)] = (uint8_t)tgt[k];
             RK_LANE_SYNC();
+#pragma unroll
+            for (int k = 0; k < CONN; ++k) cur[k] = Jv[a + nb_dy(k) * JP + nb_dx(k)];   // read back
             uint32_t again = 0u;
 #pragma unroll
             for (int k = 0; k < CONN; ++k)
-                if (((pend >> k) & 1u) && (uint32_t)Jv[a + nb_dy(k) * JP + nb_dx(k)] < tgt[k]) again |= 1u << k;
+                if (((pend >> k) & 1u) && cur[k] < tgt[k]) again |= 1u << k;
             pend = again;
             if (!__ballot(pend != 0u)) break;
         }
