@@ -883,12 +883,7 @@ __host__ __device__ constexpr int nb_dx(int k) { return k == 2 || k == 4 || k ==
 
 // Drain the LDS ring to empty; *overflow set if pushes had to be dropped.
 // Each round pops up to 64 pixels (one per lane) and offers every popped
-// pixel's value to its neighbours.  All reads of a round go out together; the
-// raises are byte stores.  Two lanes can store the same byte in one round
-// (their popped pixels lie within two of each other) and the smaller value may
-// land last, so every raise is read back and stored again until each raised
-// byte holds at least its lane's value.  Pixels not yet popped are only read
-// after the round, so none ever sees a lowered value.
+// pixel's value to its neighbours, one direction at a time.
 // At most `budget` rounds (no limit if negative); returns false if the ring was
 // not empty when the budget ran out.
 template <int BH, int CONN>
@@ -905,52 +900,35 @@ __device__ bool drain(Lds<BH> &L, int qcap, uint32_t &head, uint32_t &tail, bool
         head += n;
         const int y = (int)(p >> 8), x = (int)(p & 255u);
         const int a = (y + 1) * JP + JOFF + x;   // offset of pixel (y, x) in the J and I planes
+        const uint32_t v = Jv[a];
         const bool ok_n = valid && y > 0, ok_s = valid && y < BH - 1;
         const bool ok_w = valid && x > 0, ok_e = valid && x < BW - 1;
-        // reads: the popped value, its neighbours' marker and mask (a block
-        // pixel's neighbours lie in the LDS planes, the halo ring at worst)
-        // (unconditional, so that they all go out before the first wait)
-        const uint32_t v = Jv[a];
-        uint32_t cur[CONN], tgt[CONN];
+        // the mask never changes: all neighbours' mask values up front (a
+        // block pixel's neighbours lie in the LDS planes, the halo ring at worst)
+        uint32_t iv[CONN];
 #pragma unroll
-        for (int k = 0; k < CONN; ++k) cur[k] = Jv[a + nb_dy(k) * JP + nb_dx(k)];
-#pragma unroll
-        for (int k = 0; k < CONN; ++k) tgt[k] = L.I[a + nb_dy(k) * JP + nb_dx(k)];
-        uint32_t raise = 0u;
+        for (int k = 0; k < CONN; ++k) iv[k] = L.I[a + nb_dy(k) * JP + nb_dx(k)];
 #pragma unroll
         for (int k = 0; k < CONN; ++k) {
-            tgt[k] = min(v, tgt[k]);
+            const int off = nb_dy(k) * JP + nb_dx(k);
             const bool in = (nb_dy(k) < 0 ? ok_n : nb_dy(k) > 0 ? ok_s : valid) &&
                             (nb_dx(k) < 0 ? ok_w : nb_dx(k) > 0 ? ok_e : true);
-            if (in && cur[k] < tgt[k]) raise |= 1u << k;
-        }
-        RK_LANE_SYNC();
-        // stores, read back until every raise holds
-        uint32_t pend = raise;
-        for (int rep = 0; rep <= 8 * LANES; ++rep) {
-#pragma unroll
-            for (int k = 0; k < CONN; ++k)
-                if ((pend >> k) & 1u) Jv[a + nb_dy(k) * JP + nb_dx(k)] = (uint8_t)tgt[k];
-            RK_LANE_SYNC();
-#pragma unroll
-            for (int k = 0; k < CONN; ++k) cur[k] = Jv[a + nb_dy(k) * JP + nb_dx(k)];   // read back
-            uint32_t again = 0u;
-#pragma unroll
-            for (int k = 0; k < CONN; ++k)
-                if (((pend >> k) & 1u) && cur[k] < tgt[k]) again |= 1u << k;
-            pend = again;
-            if (!__ballot(pend != 0u)) break;
-        }
-#pragma unroll
-        for (int k = 0; k < CONN; ++k) {
-            const bool r = (raise >> k) & 1u;
-            if (r) L.rowdirty[y + nb_dy(k)] = 1;
-            if (!push_bits(L.Q, qcap, head, tail, r, p + (uint32_t)(nb_dy(k) * BW + nb_dx(k)))) overflow = true;
+            const uint32_t tgt = min(v, iv[k]);
+            const bool raised = in && (uint32_t)Jv[a + off] < tgt;
+            if (raised) {
+                Jv[a + off] = (uint8_t)tgt;
+                L.rowdirty[y + nb_dy(k)] = 1;
+            }
+            if (!push_bits(L.Q, qcap, head, tail, raised, p + (uint32_t)(nb_dy(k) * BW + nb_dx(k)))) overflow = true;
         }
     }
     return true;
 }
 
+// Seed and drain until no queue overflow is left; returns true if anything changed.
+// border_only: the first seed looks at the block's border only (valid when the
+// interior is already converged and only the halo changed); re-seeds after a
+// queue overflow are always dense.
 // A drain that is still running after DRAIN_BUDGET rounds is following long
 // paths one pixel per round; it is cut short and a round of sweeps (which
 // move whole row runs at once) takes over, followed by a dense seed.  After
