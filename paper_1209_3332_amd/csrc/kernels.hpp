@@ -929,17 +929,18 @@ __device__ bool drain(Lds<BH> &L, int qcap, uint32_t &head, uint32_t &tail, bool
 // border_only: the first seed looks at the block's border only (valid when the
 // interior is already converged and only the halo changed); re-seeds after a
 // queue overflow are always dense.
-// A drain that is still running after DRAIN_BUDGET rounds is following long
-// paths one pixel per round; it is cut short and a round of sweeps (which
-// move whole row runs at once) takes over, followed by a dense seed.  After
-// SWEEP_FALLBACKS such rounds the drain runs to the end.
+// On a revisit, a drain that is still running after DRAIN_BUDGET rounds is
+// following long paths (a flood entering the block) one pixel per round; it
+// is cut short and a round of sweeps (which move whole row runs at once) takes
+// over, followed by a dense seed, at most SWEEP_FALLBACKS times.  A first
+// visit has had its sweep rounds already and drains to the end.
 constexpr int DRAIN_BUDGET = 32;
 constexpr int SWEEP_FALLBACKS = 4;
 
 template <int BH, int CONN>
 __device__ bool converge_block(Lds<BH> &L, int qcap, WaveStats &st, bool border_only, int bh, int bw) {
     bool changed = false;
-    int fallbacks = SWEEP_FALLBACKS;
+    int fallbacks = border_only ? SWEEP_FALLBACKS : 0;
     for (int round = 0; round <= (1 << 16); ++round) {   // each round raises pixels; bounded anyway
         uint32_t head = 0, tail = 0;
         bool overflow = false;
