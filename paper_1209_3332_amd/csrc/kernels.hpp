@@ -64,6 +64,7 @@ constexpr int JP = 268;      // LDS row pitch of J incl. halo columns (67 dwords
 constexpr int JOFF = 4;      // byte offset of column 0 inside a J row (column -1 at 3)
 constexpr int MAX_INLINE_TASKS = 12;
 constexpr int RING_STRIDE = 16;       // ring slots are 64 bytes apart (one waiter per slot line)
+constexpr int STATE_STRIDE = 32;      // block state words are 128 bytes apart (no shared atomic lines)
 constexpr int MAX_DRAIN_GRID = 4096;  // upper bound of the revisit kernel's grid
 
 // block state bits (revisit scheduler)
@@ -986,6 +987,10 @@ __device__ void store_block(const TaskDev &t, const BlockGeom &g, Lds<BH> &L, bo
 // ---------------------------------------------------------------------------
 // scheduling (revisits)
 
+__device__ __forceinline__ uint32_t *state_word(const KArgs &a, uint32_t block) {
+    return a.state + (size_t)block * STATE_STRIDE;
+}
+
 __device__ __forceinline__ bool expired(const KArgs &a, uint64_t start) {
     return wall_clock64() - start > a.watchdog_ticks;
 }
@@ -1035,11 +1040,11 @@ __device__ bool request_neighbours(const KArgs &a, uint32_t ring_cap, int ti, ui
         uint32_t old;
         if (ln == cand) {
             uint32_t expected = 0u;
-            kept = __hip_atomic_compare_exchange_strong(a.state + nb, &expected, ST_R, __ATOMIC_RELAXED,
+            kept = __hip_atomic_compare_exchange_strong(state_word(a, nb), &expected, ST_R, __ATOMIC_RELAXED,
                                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            old = kept ? 0u : __hip_atomic_fetch_or(a.state + nb, ST_D, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            old = kept ? 0u : __hip_atomic_fetch_or(state_word(a, nb), ST_D, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         } else {
-            old = __hip_atomic_fetch_or(a.state + nb, ST_D, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            old = __hip_atomic_fetch_or(state_word(a, nb), ST_D, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         queue = !kept && !(old & (ST_R | ST_D));   // this request made an idle block pending
     }
@@ -1351,9 +1356,9 @@ __global__ __launch_bounds__(64) void revisit_drain(TaskTable tt, KArgs a) {
         // loads issued after the claim returned see them.
         if (ln == 0) {
             if (!claimed) {
-                uint32_t s = __hip_atomic_load(a.state + gb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                uint32_t s = __hip_atomic_load(state_word(a, gb), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 for (int k = 0; k < 1024; ++k) {
-                    if (__hip_atomic_compare_exchange_strong(a.state + gb, &s, (s & ~ST_D) | ST_R,
+                    if (__hip_atomic_compare_exchange_strong(state_word(a, gb), &s, (s & ~ST_D) | ST_R,
                                                              __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                                              __HIP_MEMORY_SCOPE_AGENT))
                         break;
@@ -1380,10 +1385,10 @@ __global__ __launch_bounds__(64) void revisit_drain(TaskTable tt, KArgs a) {
             // ---- finish: re-run if requested meanwhile, else release
             int rerun = 0;
             if (ln == 0) {
-                uint32_t s = __hip_atomic_load(a.state + gb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                uint32_t s = __hip_atomic_load(state_word(a, gb), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 for (int k = 0; k < 1024; ++k) {
                     const uint32_t ns = (s & ST_D) ? (s & ~ST_D) : (s & ~ST_R);
-                    if (__hip_atomic_compare_exchange_strong(a.state + gb, &s, ns, __ATOMIC_RELAXED,
+                    if (__hip_atomic_compare_exchange_strong(state_word(a, gb), &s, ns, __ATOMIC_RELAXED,
                                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
                         rerun = (s & ST_D) ? 1 : 0;
                         break;
@@ -1444,7 +1449,7 @@ __global__ void reset_work(TaskTable tt, Work *w, uint32_t *state, uint32_t *rin
         w->progress = 0;
         w->stat_dense = w->stat_revisit = w->stat_rerun = w->stat_overflow = w->stat_request = 0;
     }
-    for (uint32_t i = tid; i < total; i += nth) state[i] = 0;
+    for (uint32_t i = tid; i < total; i += nth) state[(size_t)i * STATE_STRIDE] = 0;
     for (uint32_t i = tid; i < ring_cap; i += nth) ring[(size_t)i * RING_STRIDE] = 0;
     for (uint32_t i = tid; i < n_tasks; i += nth) {
         tile_pending[i] = 0;

@@ -194,7 +194,7 @@ int ensure_capacity(recon_ctx *c, size_t n_tasks, size_t n_blocks, size_t scratc
     const size_t table = sizeof(BatchHdr) + nt * sizeof(rk::TaskDev);
     if (hipMalloc(&c->d_table, table) != hipSuccess ||
         hipMalloc(&c->d_work, sizeof(rk::Work)) != hipSuccess ||
-        hipMalloc(&c->d_state, nb * sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc(&c->d_state, nb * rk::STATE_STRIDE * sizeof(uint32_t)) != hipSuccess ||
         hipMalloc(&c->d_ring, ring_slots(nb) * rk::RING_STRIDE * sizeof(uint32_t)) != hipSuccess ||
         hipMalloc(&c->d_tile_pending, nt * sizeof(uint32_t)) != hipSuccess ||
         hipMalloc(&c->d_tile_done, nt * sizeof(uint32_t)) != hipSuccess ||

@@ -288,7 +288,7 @@ int emu_run(const EmuTask *tasks, int n, int bh, int qcap, int scan_rounds, int 
         tt.ext = (const TaskDev *)(ext_mem.data() + sizeof(BatchHdr));
     }
     Work *work = (Work *)std::calloc(1, sizeof(Work));
-    uint32_t *state = (uint32_t *)std::malloc(total * sizeof(uint32_t));
+    uint32_t *state = (uint32_t *)std::malloc((size_t)total * STATE_STRIDE * sizeof(uint32_t));
     uint32_t *ring = (uint32_t *)std::malloc((size_t)(total + n_waves + 1) * RING_STRIDE * sizeof(uint32_t));
     uint32_t *tpend = (uint32_t *)std::malloc(n * sizeof(uint32_t));
     uint32_t *tdone = (uint32_t *)std::malloc(n * sizeof(uint32_t));
