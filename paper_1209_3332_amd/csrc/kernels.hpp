@@ -1015,26 +1015,6 @@ __device__ __forceinline__ void flush_stats(Work *w, const WaveStats &st) {
         __hip_atomic_fetch_add(&w->stat_request, st.request, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Write block `nb` (already counted and marked requested) to the next ring
-// position.  Returns false if the watchdog expired waiting for the slot.
-__device__ bool ring_push(const KArgs &a, uint32_t ring_cap, uint32_t nb) {
-    const int ln = lane_id();
-    uint32_t pos = 0;
-    if (ln == 0) pos = __hip_atomic_fetch_add(&a.work->ring_tail, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    pos = uniform(pos);
-    uint32_t *slot = a.ring + (size_t)(pos % ring_cap) * RING_STRIDE;
-    const uint64_t t0 = wall_clock64();
-    while (true) {
-        int busy = 0;
-        if (ln == 0) busy = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
-        if (!uniform(busy)) break;
-        if (expired(a, t0)) return false;
-        __builtin_amdgcn_s_sleep(1);
-    }
-    if (ln == 0) __hip_atomic_store(slot, nb + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return true;
-}
-
 // Request visits of the neighbouring blocks flagged in `want` (bit k:
 // neighbour k of N, S, W, E, NW, NE, SW, SE) of block `gb` of task `ti`.
 // Called by all lanes with wave-uniform arguments; lane k handles neighbour k,
@@ -1391,7 +1371,6 @@ __global__ __launch_bounds__(64) void revisit_drain(TaskTable tt, KArgs a) {
 
         load_visit<BH>(t, g, L);
         bool ok = true;
-        int requeue = 0;
         for (int pass = 0;; ++pass) {
             if (pass > 0) load_halo<BH>(t, g, L);   // a re-run: neighbours changed meanwhile
             for (int r = ln; r < BH; r += LANES) L.rowdirty[r] = 0;
@@ -1403,38 +1382,34 @@ __global__ __launch_bounds__(64) void revisit_drain(TaskTable tt, KArgs a) {
                 vm_sync();   // the stores are complete before any request below
                 ok = check_neighbours<BH>(a, ring_cap, ti, t, g, by, bx, L, &keep, st);
             }
-            // ---- finish: release the block.  If it was requested meanwhile it
-            // stays requested and goes back to the ring, so that its next
-            // visit takes in everything its neighbours have done by then.
+            // ---- finish: re-run if requested meanwhile, else release
+            int rerun = 0;
             if (ln == 0) {
                 uint32_t s = __hip_atomic_load(state_word(a, gb), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 for (int k = 0; k < 1024; ++k) {
-                    if (__hip_atomic_compare_exchange_strong(state_word(a, gb), &s, s & ~ST_R, __ATOMIC_RELAXED,
+                    const uint32_t ns = (s & ST_D) ? (s & ~ST_D) : (s & ~ST_R);
+                    if (__hip_atomic_compare_exchange_strong(state_word(a, gb), &s, ns, __ATOMIC_RELAXED,
                                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                        requeue = (s & ST_D) ? 1 : 0;
+                        rerun = (s & ST_D) ? 1 : 0;
                         break;
                     }
                 }
-                if (requeue) st.rerun += 1;
+                if (rerun) st.rerun += 1;
             }
-            requeue = uniform(requeue);
+            rerun = uniform(rerun);
             __syncthreads();
-            break;
+            if (!rerun || !ok) break;
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
         }
-        // ---- the visit is complete.  Its count of outstanding work passes to
-        // the kept block or to its own next visit; a second follow-up adds one;
-        // with none the counts go down.  The watchdog heartbeat is bumped on
-        // every eighth visit of a wave.
+        // ---- the visit is complete.  A kept block inherits this visit's count
+        // of outstanding work; otherwise the counts go down.  The watchdog
+        // heartbeat is bumped on every eighth visit of a wave.
         int last = 0;
-        const int follow = (keep >= 0 ? 1 : 0) + requeue;
         if (ln == 0) {
             if ((st.revisit & 7u) == 0u)
                 __hip_atomic_fetch_add(&w->progress, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (!ok) __hip_atomic_store(&w->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (follow == 2) {
-                __hip_atomic_fetch_add(a.tile_pending + ti, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __hip_atomic_fetch_add(&w->pending, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            } else if (follow == 0) {
+            if (keep < 0) {
                 const uint32_t left = __hip_atomic_fetch_sub(a.tile_pending + ti, 1u, __ATOMIC_RELAXED,
                                                              __HIP_MEMORY_SCOPE_AGENT);
                 const uint32_t all = __hip_atomic_fetch_sub(&w->pending, 1u, __ATOMIC_RELAXED,
@@ -1444,12 +1419,8 @@ __global__ __launch_bounds__(64) void revisit_drain(TaskTable tt, KArgs a) {
                 last = all == 1u;
             }
         }
-        if (requeue && ok) ok = ring_push(a, ring_cap, gb);
         if (uniform(last)) release_waiters(a, ring_cap);
-        if (!ok) {
-            if (ln == 0) __hip_atomic_store(&w->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            break;
-        }
+        if (!ok) break;
     }
     flush_stats(w, st);
 }
