@@ -102,7 +102,9 @@ typedef struct {
                                   2 = also seed the border requests, but do not drain them */
     int32_t timing;            /* 1: record HIP events between the kernels of each launch so
                                   that recon_last_stats reports per-kernel durations */
-    int32_t reserved[3];
+    int32_t drain_budget;      /* queue rounds a revisit drains before switching to a round
+                                  of sweeps (1..4096; 0 = default 32) */
+    int32_t reserved[2];
 } recon_config;
 
 /* Per-call statistics of the last completed launch (for tests and tuning). */

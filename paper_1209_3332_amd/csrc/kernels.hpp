@@ -140,6 +140,8 @@ struct KArgs {
     int32_t qcap;
     int32_t scan_rounds;
     uint64_t watchdog_ticks;   // wall-clock ticks without progress before giving up
+    int32_t drain_budget;      // queue rounds of a revisit before a sweep round takes over
+    int32_t pad;
 };
 
 // ---------------------------------------------------------------------------
@@ -930,16 +932,17 @@ __device__ bool drain(Lds<BH> &L, int qcap, uint32_t &head, uint32_t &tail, bool
 // border_only: the first seed looks at the block's border only (valid when the
 // interior is already converged and only the halo changed); re-seeds after a
 // queue overflow are always dense.
-// On a revisit, a drain that is still running after DRAIN_BUDGET rounds is
-// following long paths (a flood entering the block) one pixel per round; it
-// is cut short and a round of sweeps (which move whole row runs at once) takes
-// over, followed by a dense seed, at most SWEEP_FALLBACKS times.  A first
-// visit has had its sweep rounds already and drains to the end.
-constexpr int DRAIN_BUDGET = 32;
+// On a revisit, a drain that is still running after `budget` rounds is
+// following long paths (a flood or a corridor entering the block) one pixel
+// per round; it is cut short and a round of sweeps (which move whole row and
+// column runs at once) takes over, followed by a dense seed, at most
+// SWEEP_FALLBACKS times.  A first visit has had its sweep rounds already and
+// drains to the end.
 constexpr int SWEEP_FALLBACKS = 4;
 
 template <int BH, int CONN>
-__device__ bool converge_block(Lds<BH> &L, int qcap, WaveStats &st, bool border_only, int bh, int bw) {
+__device__ bool converge_block(Lds<BH> &L, int qcap, WaveStats &st, bool border_only, int bh, int bw,
+                               int budget) {
     bool changed = false;
     int fallbacks = border_only ? SWEEP_FALLBACKS : 0;
     for (int round = 0; round <= (1 << 16); ++round) {   // each round raises pixels; bounded anyway
@@ -950,7 +953,7 @@ __device__ bool converge_block(Lds<BH> &L, int qcap, WaveStats &st, bool border_
         else
             seed_pass<BH, CONN>(L, qcap, head, tail, overflow, changed);
         __syncthreads();
-        const bool drained = drain<BH, CONN>(L, qcap, head, tail, overflow, fallbacks > 0 ? DRAIN_BUDGET : -1);
+        const bool drained = drain<BH, CONN>(L, qcap, head, tail, overflow, fallbacks > 0 ? budget : -1);
         __syncthreads();
         if (!drained) {
             --fallbacks;
@@ -1162,7 +1165,7 @@ __device__ void dense_block(const TaskDev &t, const BlockGeom &g, Lds<BH> &L, Wa
         __syncthreads();
         if (!__ballot(c)) break;
     }
-    converge_block<BH, CONN>(L, t.qcap, st, false, g.bh, g.bw);
+    converge_block<BH, CONN>(L, t.qcap, st, false, g.bh, g.bw, -1);
 }
 
 template <int BH>
@@ -1375,8 +1378,8 @@ __global__ __launch_bounds__(64) void revisit_drain(TaskTable tt, KArgs a) {
             if (pass > 0) load_halo<BH>(t, g, L);   // a re-run: neighbours changed meanwhile
             for (int r = ln; r < BH; r += LANES) L.rowdirty[r] = 0;
             __syncthreads();
-            const bool changed = t.conn == 8 ? converge_block<BH, 8>(L, t.qcap, st, true, g.bh, g.bw)
-                                             : converge_block<BH, 4>(L, t.qcap, st, true, g.bh, g.bw);
+            const bool changed = t.conn == 8 ? converge_block<BH, 8>(L, t.qcap, st, true, g.bh, g.bw, a.drain_budget)
+                                             : converge_block<BH, 4>(L, t.qcap, st, true, g.bh, g.bw, a.drain_budget);
             if (changed) {
                 store_block<BH, true>(t, g, L, false);
                 vm_sync();   // the stores are complete before any request below
