@@ -93,7 +93,7 @@ typedef struct {
     int32_t block_rows;        /* rows per work block: 16, 32 or 64 (default: tuned) */
     int32_t queue_capacity;    /* LDS queue entries per workgroup: a power of two in 64..8192 */
     int32_t scan_rounds;       /* directional pass rounds on a block's first visit,
-                                  1..8; 0 = default (2); -1 = none */
+                                  1..8; 0 = default (3); -1 = none */
     int32_t wg_per_cu;         /* cap on resident workgroups per CU (0 = occupancy limit) */
     int64_t serve_mem_cap;     /* serving admission cap in device bytes (default 64 GiB) */
     int32_t serve_slots;       /* serving in-flight task slots (default 256) */
@@ -102,9 +102,11 @@ typedef struct {
                                   2 = also seed the border requests, but do not drain them */
     int32_t timing;            /* 1: record HIP events between the kernels of each launch so
                                   that recon_last_stats reports per-kernel durations */
-    int32_t drain_budget;      /* queue rounds a revisit drains before switching to a round
-                                  of sweeps (1..4096; 0 = default 32) */
-    int32_t reserved[2];
+    int32_t drain_budget;      /* queue rounds a revisit of a dilate task drains before a round
+                                  of sweeps takes over (1..4096; 0 = default 128) */
+    int32_t fill_drain_budget; /* the same for fill-holes tasks, whose binary masks flood whole
+                                  regions at once (1..4096; 0 = default 4) */
+    int32_t reserved[1];
 } recon_config;
 
 /* Per-call statistics of the last completed launch (for tests and tuning). */

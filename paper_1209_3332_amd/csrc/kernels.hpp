@@ -140,8 +140,8 @@ struct KArgs {
     int32_t qcap;
     int32_t scan_rounds;
     uint64_t watchdog_ticks;   // wall-clock ticks without progress before giving up
-    int32_t drain_budget;      // queue rounds of a revisit before a sweep round takes over
-    int32_t pad;
+    int32_t drain_budget;      // queue rounds of a revisit before a sweep round takes over (dilate)
+    int32_t fill_drain_budget; // the same for fill-holes tasks
 };
 
 // ---------------------------------------------------------------------------
@@ -1378,8 +1378,9 @@ __global__ __launch_bounds__(64) void revisit_drain(TaskTable tt, KArgs a) {
             if (pass > 0) load_halo<BH>(t, g, L);   // a re-run: neighbours changed meanwhile
             for (int r = ln; r < BH; r += LANES) L.rowdirty[r] = 0;
             __syncthreads();
-            const bool changed = t.conn == 8 ? converge_block<BH, 8>(L, t.qcap, st, true, g.bh, g.bw, a.drain_budget)
-                                             : converge_block<BH, 4>(L, t.qcap, st, true, g.bh, g.bw, a.drain_budget);
+            const int budget = t.op == OP_FILL ? a.fill_drain_budget : a.drain_budget;
+            const bool changed = t.conn == 8 ? converge_block<BH, 8>(L, t.qcap, st, true, g.bh, g.bw, budget)
+                                             : converge_block<BH, 4>(L, t.qcap, st, true, g.bh, g.bw, budget);
             if (changed) {
                 store_block<BH, true>(t, g, L, false);
                 vm_sync();   // the stores are complete before any request below

@@ -56,7 +56,7 @@ def config_for(cache: dict, h: int, w: int, conn: int, arch: str | None = None) 
     """Tuned {block_rows, scan_rounds, queue_capacity} for a tile (defaults if untuned)."""
     entry = cache.get(arch or cache.get("arch", ""), {}) if cache else {}
     return entry.get("%s/conn%d" % (bucket_of(h, w), conn),
-                     {"block_rows": 32, "scan_rounds": 2, "queue_capacity": 2048})
+                     {"block_rows": 32, "scan_rounds": 3, "queue_capacity": 2048})
 
 
 def tuned_batch(cache: dict, tasks: list) -> tuple[int, list]:
