@@ -229,25 +229,32 @@ def main():
 
     def step(s):
         ctx.dilate(markers[s], d_mask, 8, stream)
-        a = ctx.last_stats()
         ctx.fill_holes(images[s], 8, stream)
-        b = ctx.last_stats()
-        return a, b
 
     for s in range(args.warmup):
         step(s)
     torch.cuda.synchronize()
-    kd, kf = [], []
+    # the timed region: launches back to back, one synchronisation at the end
     t_start = time.perf_counter()
     for s in range(args.warmup, n_sets):
-        a, b = step(s)
-        kd.append(a)
-        kf.append(b)
+        step(s)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
     ms_per_step = wall * 1e3 / args.steps
     value = px_step / (wall / args.steps) / 1e6
     log("headline: %.3f ms/step, %.0f Mpixel/s" % (ms_per_step, value))
+    # kernel durations of every timed launch, from the library's HIP events on
+    # the launch stream (launch 2k is step k's dilate, 2k+1 its fill-holes)
+    n_q = min(2 * args.steps, 64)   # the library keeps the marks of the last 64 launches
+    times = [ctx.launch_times(back) for back in range(n_q - 1, -1, -1)]
+    kd, kf = times[0::2], times[1::2]
+    # counters of one more (untimed) launch of each operation
+    spare_m = torch.from_numpy(marker).to(dev)
+    spare_i = torch.from_numpy(binary).to(dev)
+    ctx.dilate(spare_m, d_mask, 8, stream)
+    sd = ctx.last_stats()
+    ctx.fill_holes(spare_i, 8, stream)
+    sf = ctx.last_stats()
 
     # parity of the last step against the oracle (whole tile, bit-exact)
     parity = {"dilate": bool(np.array_equal(markers[-1].cpu().numpy(), oracle.recon_dilate(marker, mask, 8))),
@@ -256,10 +263,12 @@ def main():
     avg = lambda xs, k: sum(x[k] for x in xs) / len(xs)
     kernels = {"dilate": {"dense_pass_ms": avg(kd, "dense_ms"), "border_seed_ms": avg(kd, "seed_ms"),
                           "revisit_drain_ms": avg(kd, "drain_ms"), "launch_ms": avg(kd, "total_ms"),
-                          "revisits": avg(kd, "revisits"), "queue_overflows": avg(kd, "queue_overflows")},
+                          "revisits": sd["revisits"], "reruns": sd["reruns"],
+                          "queue_overflows": sd["queue_overflows"]},
                "fill_holes": {"dense_pass_ms": avg(kf, "dense_ms"), "border_seed_ms": avg(kf, "seed_ms"),
                               "revisit_drain_ms": avg(kf, "drain_ms"), "launch_ms": avg(kf, "total_ms"),
-                              "revisits": avg(kf, "revisits"), "queue_overflows": avg(kf, "queue_overflows")}}
+                              "revisits": sf["revisits"], "reruns": sf["reruns"],
+                              "queue_overflows": sf["queue_overflows"]}}
     # dominant kernel of the step (by average duration) and its roofline.  The
     # algorithmic bytes of a kernel: dense_pass reads mask and marker and writes
     # the marker once per pixel (3 B/px; fill-holes 2 B/px, its marker is

@@ -161,6 +161,17 @@ int recon_serve_stop(recon_ctx *ctx);
  * 8 s), in which case its results are incomplete. */
 int recon_last_stats(recon_ctx *ctx, recon_stats *out);
 
+/* Kernel durations in ms of a recent launch of a context created with
+ * timing = 1: `back` = 0 is the last launch sequence, 1 the one before, up to
+ * 63.  dense_ms, seed_ms, drain_ms: the dense pass (K1), border seeding (K2)
+ * and revisit drain (K3); total_ms: the whole launch.  A replayed graph reports
+ * only its total (the others are -1).  Waits (up to 60 s) for that launch to
+ * complete.  RECON_EINVAL if the context does not time its launches or that
+ * launch is no longer kept.  Lets a caller time many launches issued back to
+ * back and read all their durations after one synchronisation. */
+int recon_launch_times(recon_ctx *ctx, int back, float *dense_ms, float *seed_ms, float *drain_ms,
+                       float *total_ms);
+
 /* Message describing the last failure on the calling thread ("" if none). */
 const char *recon_last_error(void);
 

@@ -26,7 +26,7 @@ RECON_OP_DILATE, RECON_OP_FILL_HOLES = 0, 1
 EXPORTED = (
     "recon_create", "recon_destroy", "recon_dilate", "recon_fill_holes", "recon_batch",
     "recon_submit", "recon_poll", "recon_wait", "recon_serve_stop", "recon_last_stats",
-    "recon_last_error",
+    "recon_launch_times", "recon_last_error",
 )
 
 
@@ -80,7 +80,7 @@ def load_library(path: str = LIB_PATH):
     if _lib is not None:
         return _lib
     if not os.path.exists(path):
-        raise ImportError("librecon.so is not built (%s); run `python -m paper_1209_3332_amd.build`" % path)
+        raise ImportError("librecon.so is not built (%s); run `python paper_1209_3332_amd/build.py`" % path)
     import torch  # noqa: F401  (load torch's HIP runtime first so one runtime serves both)
     lib = ctypes.CDLL(path)
     P = ctypes.c_void_p
@@ -94,6 +94,8 @@ def load_library(path: str = LIB_PATH):
     lib.recon_wait.argtypes = [P, ctypes.c_uint64, ctypes.c_int64]
     lib.recon_serve_stop.argtypes = [P]
     lib.recon_last_stats.argtypes = [P, ctypes.POINTER(recon_stats)]
+    F = ctypes.POINTER(ctypes.c_float)
+    lib.recon_launch_times.argtypes = [P, ctypes.c_int, F, F, F, F]
     lib.recon_last_error.argtypes = []
     lib.recon_last_error.restype = ctypes.c_char_p
     for name in EXPORTED:
@@ -201,6 +203,13 @@ def recon_serve_stop(ctx: int) -> None:
     _check(load_library().recon_serve_stop(ctx))
 
 
+def recon_launch_times(ctx: int, back: int = 0) -> dict:
+    """Kernel durations (ms) of a recent launch: back = 0 the last, up to 63."""
+    t = [ctypes.c_float() for _ in range(4)]
+    _check(load_library().recon_launch_times(ctx, int(back), *[ctypes.byref(x) for x in t]))
+    return dict(zip(("dense_ms", "seed_ms", "drain_ms", "total_ms"), (x.value for x in t)))
+
+
 def recon_last_stats(ctx: int) -> dict:
     s = recon_stats()
     _check(load_library().recon_last_stats(ctx, ctypes.byref(s)))
@@ -272,6 +281,10 @@ class Recon:
 
     def last_stats(self) -> dict:
         return recon_last_stats(self.ctx)
+
+    def launch_times(self, back: int = 0) -> dict:
+        """Kernel durations of the launch `back` launches ago (timing contexts)."""
+        return recon_launch_times(self.ctx, back)
 
 
 # Fail loudly at import when the native library is missing.

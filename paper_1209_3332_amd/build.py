@@ -1,6 +1,7 @@
 """Build librecon.so (HIP, gfx950) in-tree with hipcc.
 
-Usage: ``python -m paper_1209_3332_amd.build`` (or ``build()`` from Python).
+Usage: ``python paper_1209_3332_amd/build.py`` (run as a script: importing the
+package first would load the library this builds).
 The library lands next to this file so that it travels with the source tree.
 """
 from __future__ import annotations

@@ -54,6 +54,7 @@ using rk::BatchHdr;
 static_assert(sizeof(BatchHdr) == 64, "header size");
 
 constexpr int kVariants = 3;   // block rows 16, 32, 64
+constexpr int kTimingRing = 64; // launches whose timing marks are kept
 constexpr int kBlockRows[kVariants] = {16, 32, 64};
 
 int variant_of(int rows) {
@@ -117,7 +118,10 @@ struct recon_ctx {
     rk::Work *h_work = nullptr;
     hipEvent_t table_used = nullptr;  // the last copy out of h_table has finished
     hipEvent_t last_done = nullptr;
-    hipEvent_t tev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};   // timing marks
+    // timing marks of the last kTimingRing launches (before K1, after K1, K2, K3, the launch)
+    hipEvent_t tev[kTimingRing][5] = {};
+    bool tev_graph[kTimingRing] = {};   // that launch replayed a graph (only its total is marked)
+    uint64_t launches = 0;              // launch sequences enqueued so far
     bool have_last = false;
     bool last_was_graph = false;   // the last launch replayed a graph (only its total is timed)
     int resident[kVariants] = {0, 0, 0};
@@ -327,7 +331,8 @@ int enqueue_kernels(recon_ctx *c, int v, const rk::TaskTable &tt, uint32_t total
     const bool timing = c->cfg.timing != 0 && !dynamic_sizes;
     hipLaunchKernelGGL(rk::reset_work, dim3(64), dim3(256), 0, s, tt, c->d_work, c->d_state, c->d_ring,
                        c->d_tile_pending, c->d_tile_done);
-    if (timing) HIP_TRY(hipEventRecord(c->tev[0], s));
+    hipEvent_t *tev = c->tev[c->launches % kTimingRing];
+    if (timing) HIP_TRY(hipEventRecord(tev[0], s));
 #define RK_LAUNCH(K, GRID)                                                                        \
     switch (v) {                                                                                  \
         case 0: hipLaunchKernelGGL(rk::K<16>, dim3(GRID), dim3(64), lds, s, tt, ka); break;      \
@@ -335,14 +340,14 @@ int enqueue_kernels(recon_ctx *c, int v, const rk::TaskTable &tt, uint32_t total
         default: hipLaunchKernelGGL(rk::K<64>, dim3(GRID), dim3(64), lds, s, tt, ka); break;     \
     }
     RK_LAUNCH(dense_pass, grid12);
-    if (timing) HIP_TRY(hipEventRecord(c->tev[1], s));
+    if (timing) HIP_TRY(hipEventRecord(tev[1], s));
     if (stop == 0 || stop >= 2) RK_LAUNCH(border_seed, grid12);
-    if (timing) HIP_TRY(hipEventRecord(c->tev[2], s));
+    if (timing) HIP_TRY(hipEventRecord(tev[2], s));
     if (stop == 0 || stop >= 3) RK_LAUNCH(revisit_drain, grid3);
-    if (timing) HIP_TRY(hipEventRecord(c->tev[3], s));
+    if (timing) HIP_TRY(hipEventRecord(tev[3], s));
 #undef RK_LAUNCH
     if (any_fill) hipLaunchKernelGGL(rk::fill_finish, dim3(1024), dim3(256), 0, s, tt);
-    if (timing) HIP_TRY(hipEventRecord(c->tev[4], s));
+    if (timing) HIP_TRY(hipEventRecord(tev[4], s));
     HIP_TRY(hipGetLastError());
     return RECON_OK;
 }
@@ -412,9 +417,10 @@ int run_tasks(recon_ctx *c, const recon_task *tasks, int n, hipStream_t stream, 
             c->graph_cap_tasks[v] = c->cap_tasks;
             c->graph_cap_scratch[v] = c->cap_scratch;
         }
-        if (c->cfg.timing) HIP_TRY(hipEventRecord(c->tev[0], stream));
+        hipEvent_t *tev = c->tev[c->launches % kTimingRing];
+        if (c->cfg.timing) HIP_TRY(hipEventRecord(tev[0], stream));
         HIP_TRY(hipGraphLaunch(c->graph[v], stream));
-        if (c->cfg.timing) HIP_TRY(hipEventRecord(c->tev[4], stream));
+        if (c->cfg.timing) HIP_TRY(hipEventRecord(tev[4], stream));
         HIP_TRY(hipEventRecord(c->table_used, stream));
     } else {
         if (!inline_table) {
@@ -428,6 +434,8 @@ int run_tasks(recon_ctx *c, const recon_task *tasks, int n, hipStream_t stream, 
     HIP_TRY(hipEventRecord(c->last_done, stream));
     c->have_last = true;
     c->last_was_graph = use_graph;
+    c->tev_graph[c->launches % kTimingRing] = use_graph;
+    c->launches += 1;
     return RECON_OK;
 }
 
@@ -503,11 +511,12 @@ int make_ctx(recon_ctx **out, int device, const recon_config &c) {
         return fail(RECON_EDEVICE, "device query / event / pinned allocation failed");
     }
     if (c.timing)
-        for (auto &ev : ctx->tev)
-            if (hipEventCreate(&ev) != hipSuccess) {
-                delete ctx;
-                return fail(RECON_EDEVICE, "timing event creation failed");
-            }
+        for (auto &set : ctx->tev)
+            for (auto &ev : set)
+                if (hipEventCreate(&ev) != hipSuccess) {
+                    delete ctx;
+                    return fail(RECON_EDEVICE, "timing event creation failed");
+                }
     int clock_khz = 0;
     if (hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, device) != hipSuccess || clock_khz <= 0)
         clock_khz = 100000;
@@ -726,8 +735,9 @@ int recon_destroy(recon_ctx *ctx) {
     if (ctx->h_work) (void)hipHostFree(ctx->h_work);
     if (ctx->table_used) (void)hipEventDestroy(ctx->table_used);
     if (ctx->last_done) (void)hipEventDestroy(ctx->last_done);
-    for (auto &ev : ctx->tev)
-        if (ev) (void)hipEventDestroy(ev);
+    for (auto &set : ctx->tev)
+        for (auto &ev : set)
+            if (ev) (void)hipEventDestroy(ev);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     delete ctx;
     return RECON_OK;
@@ -772,6 +782,22 @@ int recon_batch(recon_ctx *ctx, const recon_task *tasks, int32_t n, void *stream
     return run_tasks(ctx, tasks, n, (hipStream_t)stream, true);
 }
 
+// Durations (ms) of a recent launch from its timing marks: K1, K2, K3, whole
+// launch; -1 where a mark was not recorded (graph replays mark only the whole).
+static void launch_times(recon_ctx *ctx, int back, float t[4]) {
+    const int i = (int)((ctx->launches - 1 - (uint64_t)back) % kTimingRing);
+    hipEvent_t *tev = ctx->tev[i];
+    t[0] = t[1] = t[2] = t[3] = -1.f;
+    float ms = 0.f;
+    if (!ctx->tev_graph[i]) {
+        if (hipEventElapsedTime(&ms, tev[0], tev[1]) == hipSuccess) t[0] = ms;
+        if (hipEventElapsedTime(&ms, tev[1], tev[2]) == hipSuccess) t[1] = ms;
+        if (hipEventElapsedTime(&ms, tev[2], tev[3]) == hipSuccess) t[2] = ms;
+    }
+    if (hipEventElapsedTime(&ms, tev[0], tev[4]) == hipSuccess) t[3] = ms;
+    (void)hipGetLastError();   // a mark that was not recorded must not leave an error behind
+}
+
 int recon_last_stats(recon_ctx *ctx, recon_stats *out) {
     if (!ctx || !out) return fail(RECON_EINVAL, "null argument");
     std::memset(out, 0, sizeof(*out));
@@ -796,18 +822,35 @@ int recon_last_stats(recon_ctx *ctx, recon_stats *out) {
     out->requests = (int64_t)w.stat_request;
     out->aborted = (int64_t)w.abort;
     if (ctx->cfg.timing) {
-        float ms = 0.f;
-        if (ctx->last_was_graph) {
-            out->dense_ms = out->seed_ms = out->drain_ms = -1.f;   // not timed per kernel
-        } else {
-            if (hipEventElapsedTime(&ms, ctx->tev[0], ctx->tev[1]) == hipSuccess) out->dense_ms = ms;
-            if (hipEventElapsedTime(&ms, ctx->tev[1], ctx->tev[2]) == hipSuccess) out->seed_ms = ms;
-            if (hipEventElapsedTime(&ms, ctx->tev[2], ctx->tev[3]) == hipSuccess) out->drain_ms = ms;
-        }
-        if (hipEventElapsedTime(&ms, ctx->tev[0], ctx->tev[4]) == hipSuccess) out->total_ms = ms;
-        (void)hipGetLastError();   // a stage that was not recorded must not leave an error behind
+        float t[4];
+        launch_times(ctx, 0, t);
+        out->dense_ms = t[0];
+        out->seed_ms = t[1];
+        out->drain_ms = t[2];
+        out->total_ms = t[3];
     }
     if (w.abort) return fail(RECON_EDEVICE, "scheduler watchdog expired: the last launch did not converge");
+    return RECON_OK;
+}
+
+int recon_launch_times(recon_ctx *ctx, int back, float *dense_ms, float *seed_ms, float *drain_ms,
+                       float *total_ms) {
+    if (!ctx || !dense_ms || !seed_ms || !drain_ms || !total_ms) return fail(RECON_EINVAL, "null argument");
+    if (!ctx->cfg.timing) return fail(RECON_EINVAL, "the context was created without timing");
+    if (back < 0 || back >= kTimingRing || (uint64_t)back >= ctx->launches)
+        return fail(RECON_EINVAL, "launch %d back is not kept (%llu launches, %d kept)", back,
+                    (unsigned long long)ctx->launches, kTimingRing);
+    int rc = ensure_device(ctx);
+    if (rc) return rc;
+    hipEvent_t *tev = ctx->tev[(ctx->launches - 1 - (uint64_t)back) % kTimingRing];
+    rc = wait_event(tev[4], 60.0, "the timed launch");
+    if (rc) return rc;
+    float t[4];
+    launch_times(ctx, back, t);
+    *dense_ms = t[0];
+    *seed_ms = t[1];
+    *drain_ms = t[2];
+    *total_ms = t[3];
     return RECON_OK;
 }
 
