@@ -171,6 +171,144 @@ def batched_vs_per_tile(recon, torch, ctx_cfg, n_tiles, size, workers, spiral_si
     return res
 
 
+def _gen_uneven(args):
+    import synth
+    i, h, w, hv, config = args
+    mask = synth.scaled_config1_tile(h, w, synth.seed_for(config, i))
+    return i, synth.hdome_marker(mask, hv), mask
+
+
+def uneven_pool(n_tiles, config, workers):
+    """Tiles of the uneven workload (sides from {512, ..., 4096}, conn 4 or 8, h in [10, 40])."""
+    import multiprocessing as mp
+    import synth
+    shapes = synth.config4_shapes(n_tiles, synth.seed_for(config, 999_999))
+    out = [None] * n_tiles
+    with mp.get_context("fork").Pool(workers) as pool:
+        for i, marker, mask in pool.imap_unordered(_gen_uneven, [(i, h, w, hv, config)
+                                                                  for i, (h, w, _, hv) in enumerate(shapes)]):
+            out[i] = (marker, mask, shapes[i][2])
+    return out
+
+
+def uneven_batched_vs_per_tile(recon, torch, n_tiles, workers):
+    """The uneven batch as one autotuned graph launch vs as plain per-tile calls."""
+    import numpy as np
+    import oracle
+    from paper_1209_3332_amd import tune
+    t0 = time.perf_counter()
+    tiles = uneven_pool(n_tiles, 4, workers)
+    log("uneven batch: generated %d tiles in %.1f s" % (n_tiles, time.perf_counter() - t0))
+    dev = torch.device("cuda:0")
+    masks = [torch.from_numpy(m).to(dev) for _, m, _ in tiles]
+    pristine = [torch.from_numpy(j).to(dev) for j, _, _ in tiles]
+    conns = [c for _, _, c in tiles]
+    px = sum(m.numel() for m in masks)
+    cache = tune.load_cache()
+    bh, qcap, tuned = tune.tuned_batch(cache, [{"op": "dilate", "image": p, "mask": m, "conn": c}
+                                              for p, m, c in zip(pristine, masks, conns)])
+    res = {"tiles": n_tiles, "pixels": px, "tuned": bool(cache), "block_rows": bh, "queue_capacity": qcap}
+    stream = torch.cuda.current_stream()
+    with recon.Recon(0, block_rows=bh, queue_capacity=qcap, timing=1) as ctx:
+        for rep in range(3):
+            work = [p.clone() for p in pristine]
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            ctx.batch([dict(tk, image=w) for tk, w in zip(tuned, work)], stream)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t
+        launch_ms = ctx.last_stats()["total_ms"]
+        res["batched"] = {"Mpixel_s": px / wall / 1e6, "ms": wall * 1e3, "launch_ms": launch_ms}
+        check = [0, n_tiles // 2, n_tiles - 1]
+        res["parity_ok"] = all(bool(np.array_equal(work[i].cpu().numpy(),
+                                                   oracle.recon_dilate(tiles[i][0], tiles[i][1], conns[i])))
+                               for i in check)
+    with recon.Recon(0, timing=1) as ctx:
+        for rep in range(2):
+            work = [p.clone() for p in pristine]
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for w, m, c in zip(work, masks, conns):
+                ctx.dilate(w, m, c, stream)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t
+        lat = [ctx.launch_times(b)["total_ms"] for b in range(min(64, n_tiles))]
+        res["per_tile"] = {"Mpixel_s": px / wall / 1e6, "ms": wall * 1e3,
+                           "launch_ms_p50": percentile(lat, 50), "launch_ms_p99": percentile(lat, 99),
+                           "latency_sample": "the last %d launches" % len(lat)}
+    res["batched_over_per_tile"] = res["batched"]["Mpixel_s"] / res["per_tile"]["Mpixel_s"]
+    return res
+
+
+def serving(recon, torch, rates, seconds, pool_tiles, workers):
+    """Poisson arrivals of uneven tiles (host-pinned pool) at each rate: upload,
+    submit (retrying while admission is full), poll; latency = arrival to
+    completion seen by poll, upload included.  Every 100th result is checked
+    against the oracle."""
+    import numpy as np
+    import oracle
+    pool = uneven_pool(pool_tiles, 5, workers)
+    pinned = [(torch.from_numpy(j).pin_memory(), torch.from_numpy(m).pin_memory(), c) for j, m, c in pool]
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(min(16, len(os.sched_getaffinity(0)))) as ex:
+        want = list(ex.map(lambda t: oracle.recon_dilate(t[0], t[1], t[2]), pool))
+    dev = torch.device("cuda:0")
+    copy_stream = torch.cuda.Stream()
+    rng = np.random.default_rng(5)
+    out = []
+    with recon.Recon(0) as ctx:
+        for rate in rates:
+            arrivals = np.cumsum(rng.exponential(1.0 / rate, size=int(rate * seconds * 1.5) + 16))
+            arrivals = arrivals[arrivals < seconds]
+            picks = rng.integers(0, pool_tiles, size=len(arrivals))
+            inflight, lat, checked, bad, again = [], [], 0, 0, 0
+            px = 0
+            t0 = time.perf_counter()
+            k = 0
+
+            def reap():
+                nonlocal checked, bad
+                still = []
+                for tk, t_arr, buf, idx, n in inflight:
+                    if ctx.poll(tk):
+                        lat.append((time.perf_counter() - t0 - t_arr) * 1e3)
+                        if n % 100 == 0:
+                            checked += 1
+                            bad += int(not np.array_equal(buf[0].cpu().numpy(), want[idx]))
+                    else:
+                        still.append((tk, t_arr, buf, idx, n))
+                inflight[:] = still
+
+            while k < len(arrivals) or inflight:
+                now = time.perf_counter() - t0
+                if k < len(arrivals) and now >= arrivals[k]:
+                    j, m, c = pinned[picks[k]]
+                    with torch.cuda.stream(copy_stream):
+                        dj = j.to(dev, non_blocking=True)
+                        dm = m.to(dev, non_blocking=True)
+                    copy_stream.synchronize()
+                    while True:
+                        try:
+                            tk = ctx.submit("dilate", dj, dm, c)
+                            break
+                        except recon.ReconAgain:
+                            again += 1
+                            reap()
+                    inflight.append((tk, arrivals[k], (dj, dm), int(picks[k]), k))
+                    px += dj.numel()
+                    k += 1
+                else:
+                    reap()
+            wall = time.perf_counter() - t0
+            out.append({"rate_tiles_s": rate, "requests": len(arrivals), "tiles_s": len(arrivals) / wall,
+                        "Mpixel_s": px / wall / 1e6, "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99),
+                        "admission_retries": again, "checked": checked, "mismatches": bad})
+            log("serving at %d tiles/s: %.0f tiles/s done, p50 %.2f ms, p99 %.2f ms, %d checked, %d bad" % (
+                rate, out[-1]["tiles_s"], out[-1]["p50_ms"] or 0, out[-1]["p99_ms"] or 0, checked, bad))
+        ctx.serve_stop()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -179,6 +317,11 @@ def main():
     ap.add_argument("--size", type=int, default=4096)
     ap.add_argument("--batch-tiles", type=int, default=64, help="0 skips the batched-vs-per-tile comparison")
     ap.add_argument("--spiral-size", type=int, default=1024, help="side of the spiral-corridor tiles of the batch")
+    ap.add_argument("--uneven-tiles", type=int, default=256, help="0 skips the uneven autotuned batch")
+    ap.add_argument("--serve-rates", default="50,200,1000,2000",
+                    help="Poisson arrival rates (tiles/s) of the serving run; empty skips it")
+    ap.add_argument("--serve-seconds", type=float, default=2.0)
+    ap.add_argument("--serve-pool", type=int, default=64)
     ap.add_argument("--block-rows", type=int, default=0)
     ap.add_argument("--scan-rounds", type=int, default=0)
     ap.add_argument("--queue", type=int, default=0)
@@ -304,6 +447,14 @@ def main():
         b = out["batched_vs_per_tile"]
         log("batch of %d: batched %.0f Mpixel/s vs per-tile %.0f Mpixel/s" % (
             args.batch_tiles, b["batched"]["Mpixel_s"], b["per_tile"]["Mpixel_s"]))
+    if args.uneven_tiles:
+        out["uneven_batched_vs_per_tile"] = uneven_batched_vs_per_tile(recon, torch, args.uneven_tiles, args.workers)
+        u = out["uneven_batched_vs_per_tile"]
+        log("uneven batch of %d: batched %.0f Mpixel/s vs per-tile %.0f Mpixel/s" % (
+            args.uneven_tiles, u["batched"]["Mpixel_s"], u["per_tile"]["Mpixel_s"]))
+    if args.serve_rates:
+        rates = [int(r) for r in args.serve_rates.split(",") if r]
+        out["serving"] = serving(recon, torch, rates, args.serve_seconds, args.serve_pool, args.workers)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(marker, mask, binary)
         log("cpu baseline: %.1f Mpixel/s on %d cores" % (out["cpu_baseline"]["value"], out["cpu_baseline"]["cores"]))

@@ -26,7 +26,7 @@ DEFAULT_CACHE = os.environ.get("RECON_TUNE_CACHE", os.path.join(HERE, "tune_cach
 
 BLOCK_ROWS = (16, 32, 64)
 QUEUE_CAPACITY = (512, 2048, 8192)
-SCAN_ROUNDS = (-1, 1, 2, 3)
+SCAN_ROUNDS = (1, 2, 3, 4)
 # size buckets by tile area (pixels): representative side length of each
 BUCKETS = (("small", 1 << 20, 768), ("medium", 6 << 20, 2048), ("large", 1 << 62, 4096))
 
@@ -59,18 +59,22 @@ def config_for(cache: dict, h: int, w: int, conn: int, arch: str | None = None) 
                      {"block_rows": 32, "scan_rounds": 3, "queue_capacity": 2048})
 
 
-def tuned_batch(cache: dict, tasks: list) -> tuple[int, list]:
-    """Block rows for the launch (the choice of the bucket holding most pixels) and
-    the tasks with their per-task scan rounds and queue capacity filled in."""
+def tuned_batch(cache: dict, tasks: list) -> tuple[int, int, list]:
+    """Block rows for the launch (the choice of the bucket holding most pixels),
+    the context's queue capacity (the largest per-task choice: it sizes the LDS
+    of every workgroup) and the tasks with their per-task scan rounds and queue
+    capacity filled in."""
     weight = {}
     out = []
+    qmax = 0
     for t in tasks:
         h, w = t["image"].shape
         cfg = config_for(cache, h, w, t.get("conn", 8))
         weight[cfg["block_rows"]] = weight.get(cfg["block_rows"], 0) + h * w
+        qmax = max(qmax, cfg["queue_capacity"])
         out.append(dict(t, scan_rounds=cfg["scan_rounds"], queue_capacity=cfg["queue_capacity"]))
     bh = max(weight, key=weight.get) if weight else 32
-    return bh, out
+    return bh, qmax or 2048, out
 
 
 def _workload(side: int, conn: int, n_px_target: int):
@@ -96,9 +100,11 @@ def tune(reps: int = 3, n_px_target: int = 48 << 20, log=print) -> dict:
             pristine = [torch.from_numpy(j).to(dev) for j, _ in tiles]
             work = [p.clone() for p in pristine]
             best = None
-            for bh in BLOCK_ROWS:
-                with recon.Recon(0, block_rows=bh, queue_capacity=max(QUEUE_CAPACITY), timing=1) as ctx:
-                    for sr, qc in itertools.product(SCAN_ROUNDS, QUEUE_CAPACITY):
+            for bh, qc in itertools.product(BLOCK_ROWS, QUEUE_CAPACITY):
+                # the context's queue capacity sizes every workgroup's LDS (and so
+                # the occupancy): tune it together with the per-task value
+                with recon.Recon(0, block_rows=bh, queue_capacity=qc, timing=1) as ctx:
+                    for sr in SCAN_ROUNDS:
                         times = []
                         for _ in range(reps + 1):
                             for w_, p_ in zip(work, pristine):
