@@ -406,11 +406,12 @@ def main():
     avg = lambda xs, k: sum(x[k] for x in xs) / len(xs)
     kernels = {"dilate": {"dense_pass_ms": avg(kd, "dense_ms"), "border_seed_ms": avg(kd, "seed_ms"),
                           "revisit_drain_ms": avg(kd, "drain_ms"), "launch_ms": avg(kd, "total_ms"),
-                          "revisits": sd["revisits"], "reruns": sd["reruns"],
+                          "dense_visits": sd["dense_visits"], "revisits": sd["revisits"], "reruns": sd["reruns"],
                           "queue_overflows": sd["queue_overflows"]},
                "fill_holes": {"dense_pass_ms": avg(kf, "dense_ms"), "border_seed_ms": avg(kf, "seed_ms"),
                               "revisit_drain_ms": avg(kf, "drain_ms"), "launch_ms": avg(kf, "total_ms"),
-                              "revisits": sf["revisits"], "reruns": sf["reruns"],
+                              "dense_visits": sf["dense_visits"], "revisits": sf["revisits"],
+                              "reruns": sf["reruns"],
                               "queue_overflows": sf["queue_overflows"]}}
     # dominant kernel of the step (by average duration) and its roofline.  The
     # algorithmic bytes of a kernel: dense_pass reads mask and marker and writes
@@ -418,12 +419,14 @@ def main():
     # implicit); a revisit reads a block's mask and marker and writes it back
     # (3 B/px of the block per visit).
     bh = cfg.get("block_rows", 32)
+    # (the persistent pipeline makes every block's first visit inside
+    # revisit_drain too: its visits are first visits + revisits)
     cand = [("dense_pass (dilate)", kernels["dilate"]["dense_pass_ms"], BYTES_DILATE * mask.size),
             ("revisit_drain (dilate)", kernels["dilate"]["revisit_drain_ms"],
-             3.0 * bh * 256 * kernels["dilate"]["revisits"]),
+             3.0 * bh * 256 * (kernels["dilate"]["revisits"] + kernels["dilate"]["dense_visits"])),
             ("dense_pass (fill_holes)", kernels["fill_holes"]["dense_pass_ms"], BYTES_FILL * mask.size),
             ("revisit_drain (fill_holes)", kernels["fill_holes"]["revisit_drain_ms"],
-             3.0 * bh * 256 * kernels["fill_holes"]["revisits"])]
+             3.0 * bh * 256 * (kernels["fill_holes"]["revisits"] + kernels["fill_holes"]["dense_visits"]))]
     dom = max(cand, key=lambda c: c[1])
     achieved = dom[2] / (dom[1] * 1e-3) / 1e9
     traffic = committed_traffic(dom[0])

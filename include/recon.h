@@ -97,9 +97,12 @@ typedef struct {
     int32_t wg_per_cu;         /* cap on resident workgroups per CU (0 = occupancy limit) */
     int64_t serve_mem_cap;     /* serving admission cap in device bytes (default 64 GiB) */
     int32_t serve_slots;       /* serving in-flight task slots (default 256) */
-    int32_t stop_after_stage;  /* test hook: 0 = full pipeline; 1 = stop after the dense
+    int32_t stop_after_stage;  /* 0 = the persistent pipeline (default).  Test hooks that run
+                                  the staged pipeline instead (dense pass, border seeding and
+                                  revisits as separate kernels): 1 = stop after the dense
                                   per-block pass (each block reconstructed on its own);
-                                  2 = also seed the border requests, but do not drain them */
+                                  2 = also seed the border requests, but do not drain them;
+                                  3 = run the staged pipeline to the end */
     int32_t timing;            /* 1: record HIP events between the kernels of each launch so
                                   that recon_last_stats reports per-kernel durations */
     int32_t drain_budget;      /* queue rounds a revisit of a dilate task drains before a round

@@ -70,6 +70,7 @@ constexpr int MAX_DRAIN_GRID = 4096;  // upper bound of the revisit kernel's gri
 // block state bits (revisit scheduler)
 constexpr uint32_t ST_R = 2u;  // a wave owns the block
 constexpr uint32_t ST_D = 4u;  // visit requested (queued, or re-run pending)
+constexpr uint32_t ST_V = 8u;  // the block has had its first (dense) visit
 
 enum { OP_DILATE = 0, OP_FILL = 1 };
 
@@ -1042,8 +1043,8 @@ __device__ bool request_neighbours(const KArgs &a, uint32_t ring_cap, int ti, ui
     if (mine) {
         uint32_t old;
         if (ln == cand) {
-            uint32_t expected = 0u;
-            kept = __hip_atomic_compare_exchange_strong(state_word(a, nb), &expected, ST_R, __ATOMIC_RELAXED,
+            uint32_t expected = ST_V;   // idle: visited, not owned, not requested
+            kept = __hip_atomic_compare_exchange_strong(state_word(a, nb), &expected, ST_V | ST_R, __ATOMIC_RELAXED,
                                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             old = kept ? 0u : __hip_atomic_fetch_or(state_word(a, nb), ST_D, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         } else {
@@ -1357,6 +1358,7 @@ __global__ __launch_bounds__(64) void revisit_drain(TaskTable tt, KArgs a) {
         // ---- claim: clear D, set R (a kept block is owned already).  The previous owner and every requester
         // completed their (coherent) stores before updating the state word, so
         // loads issued after the claim returned see them.
+        int first = 0;   // the block's first visit: a dense pass
         if (ln == 0) {
             if (!claimed) {
                 uint32_t s = __hip_atomic_load(state_word(a, gb), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1366,9 +1368,14 @@ __global__ __launch_bounds__(64) void revisit_drain(TaskTable tt, KArgs a) {
                                                              __HIP_MEMORY_SCOPE_AGENT))
                         break;
                 }
+                first = (s & ST_V) ? 0 : 1;
             }
-            st.revisit += 1;
+            if (first)
+                st.dense += 1;
+            else
+                st.revisit += 1;
         }
+        first = uniform(first);
         __syncthreads();
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
 
@@ -1378,11 +1385,20 @@ __global__ __launch_bounds__(64) void revisit_drain(TaskTable tt, KArgs a) {
             if (pass > 0) load_halo<BH>(t, g, L);   // a re-run: neighbours changed meanwhile
             for (int r = ln; r < BH; r += LANES) L.rowdirty[r] = 0;
             __syncthreads();
-            const int budget = t.op == OP_FILL ? a.fill_drain_budget : a.drain_budget;
-            const bool changed = t.conn == 8 ? converge_block<BH, 8>(L, t.qcap, st, true, g.bh, g.bw, budget)
-                                             : converge_block<BH, 4>(L, t.qcap, st, true, g.bh, g.bw, budget);
+            const bool dense = first && pass == 0;
+            bool changed = true;
+            if (dense) {   // sweeps, dense seed and drain, with the halo as it is now
+                if (t.conn == 8)
+                    dense_block<BH, 8>(t, g, L, st);
+                else
+                    dense_block<BH, 4>(t, g, L, st);
+            } else {       // the interior is converged: seed from the border
+                const int budget = t.op == OP_FILL ? a.fill_drain_budget : a.drain_budget;
+                changed = t.conn == 8 ? converge_block<BH, 8>(L, t.qcap, st, true, g.bh, g.bw, budget)
+                                      : converge_block<BH, 4>(L, t.qcap, st, true, g.bh, g.bw, budget);
+            }
             if (changed) {
-                store_block<BH, true>(t, g, L, false);
+                store_block<BH, true>(t, g, L, dense);
                 vm_sync();   // the stores are complete before any request below
                 ok = check_neighbours<BH>(a, ring_cap, ti, t, g, by, bx, L, &keep, st);
             }
@@ -1391,7 +1407,7 @@ __global__ __launch_bounds__(64) void revisit_drain(TaskTable tt, KArgs a) {
             if (ln == 0) {
                 uint32_t s = __hip_atomic_load(state_word(a, gb), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 for (int k = 0; k < 1024; ++k) {
-                    const uint32_t ns = (s & ST_D) ? (s & ~ST_D) : (s & ~ST_R);
+                    const uint32_t ns = ((s & ST_D) ? (s & ~ST_D) : (s & ~ST_R)) | ST_V;
                     if (__hip_atomic_compare_exchange_strong(state_word(a, gb), &s, ns, __ATOMIC_RELAXED,
                                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
                         rerun = (s & ST_D) ? 1 : 0;
@@ -1439,25 +1455,49 @@ __global__ void copy_table(const uint8_t *src, uint8_t *dst, uint32_t bytes) {
 }
 
 // Reset the scheduling state of the batch.
+// queue_all: every block starts requested and in the ring (in block order), so
+// that the persistent revisit kernel makes each block's first visit itself;
+// otherwise the scheduler starts empty (the dense and border kernels run first).
 __global__ void reset_work(TaskTable tt, Work *w, uint32_t *state, uint32_t *ring,
-                           uint32_t *tile_pending, uint32_t *tile_done) {
+                           uint32_t *tile_pending, uint32_t *tile_done, int queue_all) {
     const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t nth = gridDim.x * blockDim.x;
     const uint32_t n_tasks = n_tasks_of(tt), total = total_blocks_of(tt), ring_cap = ring_cap_of(tt);
     if (tid == 0) {
-        w->pending = 0;
+        w->pending = queue_all ? total : 0u;
         w->done = 0;
         w->ring_head = 0;
-        w->ring_tail = 0;
+        w->ring_tail = queue_all ? total : 0u;
         w->abort = 0;
         w->progress = 0;
         w->stat_dense = w->stat_revisit = w->stat_rerun = w->stat_overflow = w->stat_request = 0;
     }
-    for (uint32_t i = tid; i < total; i += nth) state[(size_t)i * STATE_STRIDE] = 0;
-    for (uint32_t i = tid; i < ring_cap; i += nth) ring[(size_t)i * RING_STRIDE] = 0;
+    // (without queue_all the dense pass visits every block first)
+    for (uint32_t i = tid; i < total; i += nth) state[(size_t)i * STATE_STRIDE] = queue_all ? ST_D : ST_V;
+    for (uint32_t i = tid; i < ring_cap; i += nth) ring[(size_t)i * RING_STRIDE] = queue_all && i < total ? i + 1u : 0u;
     for (uint32_t i = tid; i < n_tasks; i += nth) {
-        tile_pending[i] = 0;
+        const TaskDev t = task_of(tt, (int)i);
+        tile_pending[i] = queue_all ? (uint32_t)(t.nby * t.nbx) : 0u;
         tile_done[i] = 0;
+    }
+}
+
+// Initial fill-holes marker in the scratch plane of every fill task: the mask
+// 255 - X on the image frame, 0 inside (so that any block can read any other's
+// marker before that block's first visit).
+__global__ void fill_init(TaskTable tt) {
+    const uint32_t n = n_tasks_of(tt);
+    for (uint32_t k = 0; k < n; ++k) {
+        const TaskDev t = task_of(tt, (int)k);
+        if (t.op != OP_FILL) continue;
+        const uint32_t dw = (uint32_t)(t.w + 3) / 4u;
+        const uint64_t total = (uint64_t)t.h * dw;
+        for (uint64_t i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (uint64_t)gridDim.x * blockDim.x) {
+            const int y = (int)(i / dw), x = (int)(i % dw) * 4;
+            const int valid = min(4, t.w - x);
+            const uint32_t m = mask4(t, y, x, valid);
+            gstore4(t.j + (int64_t)y * t.pitch_j, x, valid, t.aligned, fill_init4(t, y, x, valid, m));
+        }
     }
 }
 

@@ -329,8 +329,13 @@ int enqueue_kernels(recon_ctx *c, int v, const rk::TaskTable &tt, uint32_t total
     // per-kernel timing marks on plain launches only: events recorded inside a
     // captured graph cannot be timed (a graph launch is timed as a whole)
     const bool timing = c->cfg.timing != 0 && !dynamic_sizes;
+    // stop 0: the persistent pipeline (every block's first visit inside the
+    // revisit kernel); 1-3: the staged pipeline (dense pass, border seeding,
+    // revisits as separate kernels), stopped after that stage (test hooks)
+    const bool merged = stop == 0;
     hipLaunchKernelGGL(rk::reset_work, dim3(64), dim3(256), 0, s, tt, c->d_work, c->d_state, c->d_ring,
-                       c->d_tile_pending, c->d_tile_done);
+                       c->d_tile_pending, c->d_tile_done, merged ? 1 : 0);
+    if (merged && any_fill) hipLaunchKernelGGL(rk::fill_init, dim3(1024), dim3(256), 0, s, tt);
     hipEvent_t *tev = c->tev[c->launches % kTimingRing];
     if (timing) HIP_TRY(hipEventRecord(tev[0], s));
 #define RK_LAUNCH(K, GRID)                                                                        \
@@ -339,11 +344,11 @@ int enqueue_kernels(recon_ctx *c, int v, const rk::TaskTable &tt, uint32_t total
         case 1: hipLaunchKernelGGL(rk::K<32>, dim3(GRID), dim3(64), lds, s, tt, ka); break;      \
         default: hipLaunchKernelGGL(rk::K<64>, dim3(GRID), dim3(64), lds, s, tt, ka); break;     \
     }
-    RK_LAUNCH(dense_pass, grid12);
+    if (!merged) RK_LAUNCH(dense_pass, grid12);
     if (timing) HIP_TRY(hipEventRecord(tev[1], s));
-    if (stop == 0 || stop >= 2) RK_LAUNCH(border_seed, grid12);
+    if (stop >= 2) RK_LAUNCH(border_seed, grid12);
     if (timing) HIP_TRY(hipEventRecord(tev[2], s));
-    if (stop == 0 || stop >= 3) RK_LAUNCH(revisit_drain, grid3);
+    if (merged || stop >= 3) RK_LAUNCH(revisit_drain, grid3);
     if (timing) HIP_TRY(hipEventRecord(tev[3], s));
 #undef RK_LAUNCH
     if (any_fill) hipLaunchKernelGGL(rk::fill_finish, dim3(1024), dim3(256), 0, s, tt);

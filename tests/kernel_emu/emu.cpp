@@ -303,7 +303,10 @@ int emu_run(const EmuTask *tasks, int n, int bh, int qcap, int scan_rounds, int 
                 fn();
             }
     };
-    grid_run([&] { reset_work(tt, work, state, ring, tpend, tdone); }, 4, 64);
+    // stop_after 0: the persistent pipeline; 1..3: the staged one, stopped after that stage
+    const bool merged = stop_after == 0;
+    grid_run([&] { reset_work(tt, work, state, ring, tpend, tdone, merged ? 1 : 0); }, 4, 64);
+    if (merged && any_fill) grid_run([&] { fill_init(tt); }, 8, 64);
 
     KArgs ka;
     ka.work = work;
@@ -341,9 +344,9 @@ int emu_run(const EmuTask *tasks, int n, int bh, int qcap, int scan_rounds, int 
         }
         for (auto &t : th) t.join();
     };
-    run_grid(1, n_waves);
-    if (stop_after == 0 || stop_after >= 2) run_grid(2, n_waves);
-    if (stop_after == 0 || stop_after >= 3) run_grid(3, n_waves);
+    if (!merged) run_grid(1, n_waves);
+    if (stop_after >= 2) run_grid(2, n_waves);
+    if (merged || stop_after >= 3) run_grid(3, n_waves);
     if (any_fill) grid_run([&] { fill_finish(tt); }, 4, 64);
 
     for (int k = 0; k < n; ++k) {

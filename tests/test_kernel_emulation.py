@@ -59,6 +59,18 @@ def test_fill_holes(emu_exe, oracle_mod, conn):
     _check(emu_exe, oracle_mod, tasks, n_waves=3)
 
 
+def test_staged_pipeline(emu_exe, oracle_mod):
+    """The staged pipeline (dense pass, border seeding and revisits as separate
+    kernels) run to the end gives the same bytes as the persistent one."""
+    marker, mask, binary = synth.config2_tile(seed=synth.seed_for(2, 23), size=96, n_gauss=2)
+    mask = np.ascontiguousarray(np.concatenate([mask, mask[:, ::-1]], 1))[:, :300]
+    marker = synth.hdome_marker(mask, 20)
+    img = np.where(mask > 40, 255, 0).astype(np.uint8)
+    tasks = [{"op": "dilate", "marker": marker, "mask": mask, "conn": 8},
+             {"op": "fill_holes", "img": img, "conn": 4}]
+    _check(emu_exe, oracle_mod, tasks, n_waves=3, stop_after=3)
+
+
 def test_large_batch_table_in_memory(emu_exe, oracle_mod):
     # more tasks than fit in the kernel arguments: the table lives in memory
     rng = np.random.default_rng(77)
