@@ -105,10 +105,10 @@ typedef struct {
                                   3 = run the staged pipeline to the end */
     int32_t timing;            /* 1: record HIP events between the kernels of each launch so
                                   that recon_last_stats reports per-kernel durations */
-    int32_t drain_budget;      /* queue rounds a revisit of a dilate task drains before a round
-                                  of sweeps takes over (1..4096; 0 = default 128) */
-    int32_t fill_drain_budget; /* the same for fill-holes tasks, whose binary masks flood whole
-                                  regions at once (1..4096; 0 = default 4) */
+    int32_t drain_budget;      /* queue rounds a revisit drains before a round of sweeps takes
+                                  over (1..4096; 0 = default 128) */
+    int32_t binary_drain_budget; /* the same for blocks whose mask is binary (0 / 255 only),
+                                  where a raise floods whole regions (1..4096; 0 = default 4) */
     int32_t reserved[1];
 } recon_config;
 

@@ -59,7 +59,7 @@ class recon_config(ctypes.Structure):
                 ("scan_rounds", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32),
                 ("serve_mem_cap", ctypes.c_int64), ("serve_slots", ctypes.c_int32),
                 ("stop_after_stage", ctypes.c_int32), ("timing", ctypes.c_int32),
-                ("drain_budget", ctypes.c_int32), ("fill_drain_budget", ctypes.c_int32),
+                ("drain_budget", ctypes.c_int32), ("binary_drain_budget", ctypes.c_int32),
                 ("reserved", ctypes.c_int32 * 1)]
 
 

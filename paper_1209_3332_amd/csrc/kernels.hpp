@@ -141,8 +141,8 @@ struct KArgs {
     int32_t qcap;
     int32_t scan_rounds;
     uint64_t watchdog_ticks;   // wall-clock ticks without progress before giving up
-    int32_t drain_budget;      // queue rounds of a revisit before a sweep round takes over (dilate)
-    int32_t fill_drain_budget; // the same for fill-holes tasks
+    int32_t drain_budget;        // queue rounds of a revisit before a sweep round takes over
+    int32_t binary_drain_budget; // the same for blocks whose mask is binary (0 / 255)
 };
 
 // ---------------------------------------------------------------------------
@@ -554,7 +554,20 @@ __device__ void load_halo(const TaskDev &t, const BlockGeom &g, Lds<BH> &L) {
     halo_store<BH>(h, L);
 }
 
-// A revisit's load: the block (mask, and marker from the device-coherent
+// true if every byte of v is 0 or 255 (all bits of each byte equal)
+__device__ __forceinline__ bool binary4(uint32_t v) { return ((v ^ (v >> 1)) & 0x7f7f7f7fu) == 0u; }
+
+// Whether the block's mask (in LDS) is binary, 0 / 255 only: there a raise
+// floods whole regions, which sweeps move faster than the queue.
+template <int BH>
+__device__ bool mask_is_binary(Lds<BH> &L) {
+    const int ln = lane_id();
+    bool bin = true;
+    for (int r = 0; r < BH; ++r) bin = bin && binary4(*L.Iw(r, ln));
+    return __ballot(!bin) == 0;
+}
+
+// A visit's load: the block (mask, and marker from the device-coherent
 // level) and its halo, with all loads of a whole-width aligned block of up to
 // 32 rows in flight together.
 template <int BH>
@@ -1380,6 +1393,8 @@ __global__ __launch_bounds__(64) void revisit_drain(TaskTable tt, KArgs a) {
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
 
         load_visit<BH>(t, g, L);
+        __syncthreads();
+        const int budget = mask_is_binary<BH>(L) ? a.binary_drain_budget : a.drain_budget;
         bool ok = true;
         for (int pass = 0;; ++pass) {
             if (pass > 0) load_halo<BH>(t, g, L);   // a re-run: neighbours changed meanwhile
@@ -1393,7 +1408,6 @@ __global__ __launch_bounds__(64) void revisit_drain(TaskTable tt, KArgs a) {
                 else
                     dense_block<BH, 4>(t, g, L, st);
             } else {       // the interior is converged: seed from the border
-                const int budget = t.op == OP_FILL ? a.fill_drain_budget : a.drain_budget;
                 changed = t.conn == 8 ? converge_block<BH, 8>(L, t.qcap, st, true, g.bh, g.bw, budget)
                                       : converge_block<BH, 4>(L, t.qcap, st, true, g.bh, g.bw, budget);
             }

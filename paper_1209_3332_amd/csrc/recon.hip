@@ -316,7 +316,7 @@ int enqueue_kernels(recon_ctx *c, int v, const rk::TaskTable &tt, uint32_t total
     ka.scan_rounds = c->cfg.scan_rounds;
     ka.watchdog_ticks = c->watchdog_ticks;
     ka.drain_budget = c->cfg.drain_budget;
-    ka.fill_drain_budget = c->cfg.fill_drain_budget;
+    ka.binary_drain_budget = c->cfg.binary_drain_budget;
     const size_t lds = lds_for(v, c->cfg.queue_capacity);
     const int resident = resident_wgs(c, v);
     // K1/K2 are grid-stride: with sizes known only on the device (captured
@@ -700,9 +700,9 @@ int recon_create(recon_ctx **out, int device, const recon_config *cfg) {
         return fail(RECON_EINVAL, "queue_capacity must be a power of two in 64..8192");
     if (c.scan_rounds < -1 || c.scan_rounds > 8) return fail(RECON_EINVAL, "scan_rounds must be in -1..8");
     if (c.drain_budget == 0) c.drain_budget = 128;
-    if (c.fill_drain_budget == 0) c.fill_drain_budget = 4;
-    if (c.drain_budget < 1 || c.drain_budget > 4096 || c.fill_drain_budget < 1 || c.fill_drain_budget > 4096)
-        return fail(RECON_EINVAL, "drain_budget and fill_drain_budget must be in 1..4096");
+    if (c.binary_drain_budget == 0) c.binary_drain_budget = 4;
+    if (c.drain_budget < 1 || c.drain_budget > 4096 || c.binary_drain_budget < 1 || c.binary_drain_budget > 4096)
+        return fail(RECON_EINVAL, "drain_budget and binary_drain_budget must be in 1..4096");
     if (c.scan_rounds == 0) c.scan_rounds = 3;
     if (c.scan_rounds < 0) c.scan_rounds = 0;
     if (c.wg_per_cu < 0) return fail(RECON_EINVAL, "wg_per_cu must be >= 0");

@@ -318,7 +318,7 @@ int emu_run(const EmuTask *tasks, int n, int bh, int qcap, int scan_rounds, int 
     ka.scan_rounds = scan_rounds;
     ka.watchdog_ticks = (uint64_t)(watchdog_s * 1e8);
     ka.drain_budget = 128;
-    ka.fill_drain_budget = 4;
+    ka.binary_drain_budget = 4;
     const size_t lds = bh == 16 ? lds_bytes<16>(qcap) : bh == 32 ? lds_bytes<32>(qcap) : lds_bytes<64>(qcap);
     std::atomic<int> bad{0};
     auto run_grid = [&](int stage, int waves) {

@@ -186,8 +186,8 @@ def test_unaligned_pitch_and_offset(torch_mod, rc, oracle_mod):
 @pytest.mark.parametrize("cfg", [dict(block_rows=16), dict(block_rows=64), dict(queue_capacity=64),
                                  dict(scan_rounds=-1), dict(scan_rounds=4, block_rows=64),
                                  dict(wg_per_cu=1), dict(stop_after_stage=3),
-                                 dict(drain_budget=1, fill_drain_budget=1),
-                                 dict(drain_budget=4096, fill_drain_budget=4096)], ids=str)
+                                 dict(drain_budget=1, binary_drain_budget=1),
+                                 dict(drain_budget=4096, binary_drain_budget=4096)], ids=str)
 def test_tuning_invariance(torch_mod, lib, oracle_mod, cfg):
     marker, mask, binary = synth.config2_tile(seed=synth.seed_for(2, 11), size=768, n_gauss=106)
     sm, smask, _ = synth.spiral_tile(300, 520, "inner")
