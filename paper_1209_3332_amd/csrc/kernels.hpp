@@ -903,51 +903,6 @@ __host__ __device__ constexpr int nb_dx(int k) { return k == 2 || k == 4 || k ==
 // pixel's value to its neighbours, one direction at a time.
 // At most `budget` rounds (no limit if negative); returns false if the ring was
 // not empty when the budget ran out.
-// A front of a single pixel (a thin path, e.g. a corridor) is followed by
-// lane 0 alone: while exactly one neighbour is raised it continues from that
-// neighbour at once (it is as good as popped); when none or several are, it
-// pushes them and the wave resumes.  At most CHASE_STEPS steps per chase.
-constexpr int CHASE_STEPS = 4096;
-
-template <int BH, int CONN>
-__device__ uint32_t chase(Lds<BH> &L, uint32_t p, int qcap, uint32_t tail) {
-    volatile RK_LDS uint8_t *Jv = L.J;
-    volatile RK_LDS uint16_t *Qv = L.Q;
-    uint32_t pushed = 0;
-    for (int step = 0; step < CHASE_STEPS; ++step) {
-        const int y = (int)(p >> 8), x = (int)(p & 255u);
-        const int a = (y + 1) * JP + JOFF + x;
-        const uint32_t v = Jv[a];
-        uint32_t cur[CONN], tgt[CONN];
-#pragma unroll
-        for (int k = 0; k < CONN; ++k) cur[k] = Jv[a + nb_dy(k) * JP + nb_dx(k)];
-#pragma unroll
-        for (int k = 0; k < CONN; ++k) tgt[k] = min(v, (uint32_t)L.I[a + nb_dy(k) * JP + nb_dx(k)]);
-        uint32_t raised = 0;
-#pragma unroll
-        for (int k = 0; k < CONN; ++k) {
-            const bool in = (nb_dy(k) < 0 ? y > 0 : nb_dy(k) > 0 ? y < BH - 1 : true) &&
-                            (nb_dx(k) < 0 ? x > 0 : nb_dx(k) > 0 ? x < BW - 1 : true);
-            if (in && cur[k] < tgt[k]) {
-                Jv[a + nb_dy(k) * JP + nb_dx(k)] = (uint8_t)tgt[k];
-                L.rowdirty[y + nb_dy(k)] = 1;
-                raised |= 1u << k;
-            }
-        }
-        if (__builtin_popcount(raised) == 1 && step + 1 < CHASE_STEPS) {
-            const int k = __builtin_ctz(raised);
-            p = p + (uint32_t)(nb_dy(k) * BW + nb_dx(k));
-            continue;
-        }
-        // none (the path ends) or several (it branches): push them, resume the wave
-        for (int k = 0; k < CONN; ++k)
-            if ((raised >> k) & 1u)
-                Qv[(tail + pushed++) & (uint32_t)(qcap - 1)] = (uint16_t)(p + (uint32_t)(nb_dy(k) * BW + nb_dx(k)));
-        break;
-    }
-    return pushed;
-}
-
 template <int BH, int CONN>
 __device__ bool drain(Lds<BH> &L, int qcap, uint32_t &head, uint32_t &tail, bool &overflow, int budget) {
     const int ln = lane_id();
@@ -956,13 +911,6 @@ __device__ bool drain(Lds<BH> &L, int qcap, uint32_t &head, uint32_t &tail, bool
     while (head != tail) {
         if (budget-- == 0) return false;
         RK_LANE_SYNC();
-        if (tail - head == 1u) {   // single-pixel front: chase (qcap >= 64 leaves room for 8 pushes)
-            uint32_t np = 0;
-            if (ln == 0) np = chase<BH, CONN>(L, (uint32_t)Qv[head & (uint32_t)(qcap - 1)], qcap, tail);
-            head += 1;
-            tail += uniform(np);
-            continue;
-        }
         const uint32_t n = min(tail - head, (uint32_t)LANES);
         const bool valid = (uint32_t)ln < n;
         const uint32_t p = valid ? (uint32_t)Qv[(head + ln) & (uint32_t)(qcap - 1)] : 0u;
