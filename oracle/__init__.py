@@ -47,6 +47,12 @@ def _load():
         lib.oracle_fill_holes.restype = ctypes.c_int
         lib.oracle_recon_dilate_many.argtypes = [u8p, u8p, u8p, i64, i64, i64, ctypes.c_int]
         lib.oracle_recon_dilate_many.restype = ctypes.c_int
+        lib.oracle_recon_erode.argtypes = [u8p, u8p, u8p, i64, i64, ctypes.c_int]
+        lib.oracle_recon_erode.restype = ctypes.c_int
+        lib.oracle_hdome.argtypes = [u8p, u8p, i64, i64, ctypes.c_int, ctypes.c_int]
+        lib.oracle_hdome.restype = ctypes.c_int
+        lib.oracle_regional_max.argtypes = [u8p, u8p, i64, i64, ctypes.c_int]
+        lib.oracle_regional_max.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -99,10 +105,53 @@ def recon_dilate_many(markers, masks, conn: int = 8) -> np.ndarray:
     return out
 
 
+def recon_erode(marker, mask, conn: int = 8) -> np.ndarray:
+    """rho^e_mask(marker): reconstruction by erosion (marker raised over mask)."""
+    marker, mask = _u8(marker), _u8(mask)
+    if marker.shape != mask.shape or marker.ndim != 2:
+        raise ValueError("marker and mask must be 2-D arrays of one shape")
+    out = np.empty_like(marker)
+    h, w = marker.shape
+    rc = _load().oracle_recon_erode(marker.ctypes.data, mask.ctypes.data, out.ctypes.data, h, w, int(conn))
+    if rc != 0:
+        raise ValueError("oracle_recon_erode failed with %d" % rc)
+    return out
+
+
+def hdome(img, h: int, conn: int = 8) -> np.ndarray:
+    """h-dome I - rho_I(max(I - h, 0)), h in 1..255."""
+    img = _u8(img)
+    if img.ndim != 2:
+        raise ValueError("image must be 2-D")
+    out = np.empty_like(img)
+    rc = _load().oracle_hdome(img.ctypes.data, out.ctypes.data, img.shape[0], img.shape[1], int(h), int(conn))
+    if rc != 0:
+        raise ValueError("oracle_hdome failed with %d" % rc)
+    return out
+
+
+def regional_max(img, conn: int = 8) -> np.ndarray:
+    """Regional maxima: 255 where the 1-dome is positive, else 0."""
+    img = _u8(img)
+    if img.ndim != 2:
+        raise ValueError("image must be 2-D")
+    out = np.empty_like(img)
+    rc = _load().oracle_regional_max(img.ctypes.data, out.ctypes.data, img.shape[0], img.shape[1], int(conn))
+    if rc != 0:
+        raise ValueError("oracle_regional_max failed with %d" % rc)
+    return out
+
+
 def run_task(task) -> np.ndarray:
     """Oracle result of one task dict {op, marker/img, mask, conn} (host arrays)."""
     if task["op"] == "dilate":
         return recon_dilate(task["marker"], task["mask"], task["conn"])
     if task["op"] == "fill_holes":
         return fill_holes(task["img"], task["conn"])
+    if task["op"] == "erode":
+        return recon_erode(task["marker"], task["mask"], task["conn"])
+    if task["op"] == "hdome":
+        return hdome(task["img"], task["h"], task["conn"])
+    if task["op"] == "regional_max":
+        return regional_max(task["img"], task["conn"])
     raise ValueError("unknown op %r" % (task["op"],))

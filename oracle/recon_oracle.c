@@ -37,6 +37,23 @@
  * frame and 0 inside.  `conn` is the connectivity of that reconstruction,
  * i.e. of the background.
  *
+ * Reconstruction by erosion (the dual operation, the first of the operations
+ * built next on the same propagation):
+ *
+ *   rho^e_I(J) = fixed point of  J_{n+1} = max(eps_B(J_n), I),  J_0 = max(J, I)
+ *
+ * with eps_B the flat erosion (pixels outside the image do not exist: 255
+ * padding for the min).  The oracle runs Vincent's hybrid algorithm for it
+ * directly, with min and max exchanged -- not through the complement -- so
+ * that the duality rho^e_I(J) = 255 - rho_{255-I}(255-J) is a check between
+ * two independent codes.
+ *
+ * The h-dome of I (Vincent's regional-maxima machinery, used by the paper's
+ * ReconToNuclei step):  D_h(I) = I - rho_I(max(I - h, 0)),  h >= 1.  Regional
+ * maxima: the pixels where D_1(I) > 0 (255 there, 0 elsewhere); a plateau at
+ * value 0 is never reported (with any nonzero pixel present it borders a
+ * higher one; an all-zero image has no reported maximum -- a reading).
+ *
  * Images are dense row-major uint8 arrays of height*width bytes.
  * Return value: 0 on success, -1 on bad arguments, -2 on allocation failure.
  */
@@ -214,5 +231,108 @@ int oracle_recon_dilate_many(const uint8_t *markers, const uint8_t *masks, uint8
                                      height, width, conn);
         if (rc != 0) return rc;
     }
+    return 0;
+}
+
+/* Reconstruction by erosion of mask I from marker J, in place on J: Vincent's
+ * hybrid algorithm with min and max exchanged. */
+static int recon_erode_in_place(uint8_t *J, const uint8_t *I, int64_t h, int64_t w, int conn)
+{
+    const int (*early)[2] = conn == 8 ? EARLY8 : EARLY4;
+    const int (*late)[2] = conn == 8 ? LATE8 : LATE4;
+    const int nhalf = conn == 8 ? 4 : 2;
+    const int64_t n = h * w;
+
+    /* 1. marker raised over the mask */
+    for (int64_t i = 0; i < n; ++i)
+        J[i] = u8max(J[i], I[i]);
+
+    /* 2. raster scan: min over the pixel and its already-visited neighbours, floored by the mask */
+    for (int64_t y = 0; y < h; ++y) {
+        for (int64_t x = 0; x < w; ++x) {
+            uint8_t m = J[y * w + x];
+            for (int k = 0; k < nhalf; ++k) {
+                int64_t qy = y + early[k][0], qx = x + early[k][1];
+                if (inside(qy, qx, h, w)) m = u8min(m, J[qy * w + qx]);
+            }
+            J[y * w + x] = u8max(m, I[y * w + x]);
+        }
+    }
+
+    /* 3. anti-raster scan, seeding the FIFO with pixels that can still lower a later neighbour */
+    fifo_t q;
+    if (fifo_init(&q, n / 8 + 16) != 0) return -2;
+    for (int64_t y = h - 1; y >= 0; --y) {
+        for (int64_t x = w - 1; x >= 0; --x) {
+            const int64_t p = y * w + x;
+            uint8_t m = J[p];
+            for (int k = 0; k < nhalf; ++k) {
+                int64_t qy = y + late[k][0], qx = x + late[k][1];
+                if (inside(qy, qx, h, w)) m = u8min(m, J[qy * w + qx]);
+            }
+            J[p] = u8max(m, I[p]);
+            for (int k = 0; k < nhalf; ++k) {
+                int64_t qy = y + late[k][0], qx = x + late[k][1];
+                if (!inside(qy, qx, h, w)) continue;
+                const int64_t r = qy * w + qx;
+                if (J[r] > J[p] && J[r] > I[r]) {
+                    if (fifo_push(&q, p) != 0) { free(q.buf); return -2; }
+                    break;
+                }
+            }
+        }
+    }
+
+    /* 4. FIFO propagation over the full neighbourhood */
+    while (q.count > 0) {
+        const int64_t p = fifo_pop(&q);
+        const int64_t y = p / w, x = p % w;
+        for (int half = 0; half < 2; ++half) {
+            const int (*nb)[2] = half == 0 ? early : late;
+            for (int k = 0; k < nhalf; ++k) {
+                int64_t qy = y + nb[k][0], qx = x + nb[k][1];
+                if (!inside(qy, qx, h, w)) continue;
+                const int64_t r = qy * w + qx;
+                if (J[r] > J[p] && J[r] != I[r]) {
+                    J[r] = u8max(J[p], I[r]);
+                    if (fifo_push(&q, r) != 0) { free(q.buf); return -2; }
+                }
+            }
+        }
+    }
+    free(q.buf);
+    return 0;
+}
+
+/* rho^e_mask(marker) into out (out may alias marker, not mask). */
+int oracle_recon_erode(const uint8_t *marker, const uint8_t *mask, uint8_t *out,
+                       int64_t height, int64_t width, int conn)
+{
+    if (!marker || !mask || !out || height < 1 || width < 1) return -1;
+    if (conn != 4 && conn != 8) return -1;
+    if (out != marker) memcpy(out, marker, (size_t)(height * width));
+    return recon_erode_in_place(out, mask, height, width, conn);
+}
+
+/* h-dome D_h(I) = I - rho_I(max(I - h, 0)) into out; h in 1..255. */
+int oracle_hdome(const uint8_t *img, uint8_t *out, int64_t height, int64_t width, int hval, int conn)
+{
+    if (!img || !out || height < 1 || width < 1 || hval < 1 || hval > 255) return -1;
+    if (conn != 4 && conn != 8) return -1;
+    const int64_t n = height * width;
+    for (int64_t i = 0; i < n; ++i) out[i] = (uint8_t)(img[i] > hval ? img[i] - hval : 0);
+    int rc = recon_in_place(out, img, height, width, conn);
+    if (rc != 0) return rc;
+    for (int64_t i = 0; i < n; ++i) out[i] = (uint8_t)(img[i] - out[i]);
+    return 0;
+}
+
+/* Regional maxima: 255 where D_1(I) > 0, else 0. */
+int oracle_regional_max(const uint8_t *img, uint8_t *out, int64_t height, int64_t width, int conn)
+{
+    int rc = oracle_hdome(img, out, height, width, 1, conn);
+    if (rc != 0) return rc;
+    const int64_t n = height * width;
+    for (int64_t i = 0; i < n; ++i) out[i] = out[i] ? 255 : 0;
     return 0;
 }

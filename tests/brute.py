@@ -14,6 +14,10 @@ Nothing here imports the oracle or the GPU library.
 * ``fill_holes_by_levels``: fill-holes through scipy's binary_fill_holes at
   every grey level t (its structure is the background connectivity):
   F(p) = max{t : p in fill({X >= t})}.
+* ``iterate_erosion``: the defining iteration of reconstruction by erosion,
+  J_{n+1} = max(eps_B(J_n), I) from max(J, I) (out-of-image pixels absent).
+* ``regional_max_by_plateaus``: regional maxima straight from their
+  definition, plateau by plateau through scipy.ndimage.label.
 """
 from __future__ import annotations
 
@@ -49,6 +53,51 @@ def iterate_definition(marker, mask, conn: int, max_iter: int | None = None):
         j = nxt
         if max_iter is not None and n >= max_iter:
             raise RuntimeError("no fixed point within max_iter")
+
+
+def erode(j: np.ndarray, conn: int) -> np.ndarray:
+    """Flat erosion over the last two axes; pixels outside the image are absent."""
+    j = np.asarray(j)
+    pad = [(0, 0)] * (j.ndim - 2) + [(1, 1), (1, 1)]
+    p = np.pad(j, pad, mode="constant", constant_values=255)
+    h, w = j.shape[-2:]
+    out = j.copy()
+    for dy in (-1, 0, 1):
+        for dx in (-1, 0, 1):
+            if conn == 4 and dy != 0 and dx != 0:
+                continue
+            out = np.minimum(out, p[..., 1 + dy:1 + dy + h, 1 + dx:1 + dx + w])
+    return out
+
+
+def iterate_erosion(marker, mask, conn: int):
+    """Iterated elementary geodesic erosion to stability: J <- max(erode(J), I) from max(J, I)."""
+    mask = np.asarray(mask)
+    j = np.maximum(np.asarray(marker), mask)
+    while True:
+        nxt = np.maximum(erode(j, conn), mask)
+        if np.array_equal(nxt, j):
+            return j
+        j = nxt
+
+
+def regional_max_by_plateaus(img, conn: int) -> np.ndarray:
+    """Regional maxima from their definition: a connected plateau (one value,
+    connectivity conn) none of whose neighbouring pixels is higher; 255 there.
+    Plateaus at value 0 are left out (the reading the oracle states)."""
+    img = np.asarray(img)
+    out = np.zeros(img.shape, np.uint8)
+    st = structure(conn)
+    for v in np.unique(img):
+        if v == 0:
+            continue
+        lab, n = ndi.label(img == v, structure=st)
+        for k in range(1, n + 1):
+            comp = lab == k
+            ring = ndi.binary_dilation(comp, structure=st) & ~comp
+            if not (img[ring] > v).any():
+                out[comp] = 255
+    return out
 
 
 def structure(conn: int) -> np.ndarray:

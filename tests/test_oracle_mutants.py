@@ -27,11 +27,20 @@ MUTANTS = {
     "anti_raster_mask_cap": ("J[p] = u8min(m, I[p]);", "J[p] = m;"),
     "fifo_ignores_mask": ("J[r] = u8min(J[p], I[r]);", "J[r] = J[p];"),
     "seed_test_wrong_side": ("if (J[r] < J[p] && J[r] < I[r]) {", "if (J[r] > J[p] && J[r] < I[r]) {"),
-    "no_fifo_push": ("if (fifo_push(&q, r) != 0) { free(q.buf); return -2; }", "(void)0;"),
+    "no_fifo_push": ("J[r] = u8min(J[p], I[r]);\n                    if (fifo_push(&q, r) != 0) { free(q.buf); return -2; }",
+                     "J[r] = u8min(J[p], I[r]);\n                    (void)0;"),
     "raster_mask_cap": ("J[y * w + x] = u8min(m, I[y * w + x]);", "J[y * w + x] = m;"),
     "fill_frame_rows_only": ("y == 0 || y == height - 1 || x == 0 || x == width - 1",
                              "y == 0 || y == height - 1"),
     "fill_not_complemented": ("out[i] = (uint8_t)(255 - out[i]);", "(void)0;"),
+    # reconstruction by erosion, h-dome, regional maxima
+    "erode_raster_floor": ("J[y * w + x] = u8max(m, I[y * w + x]);", "J[y * w + x] = m;"),
+    "erode_fifo_floor": ("J[r] = u8max(J[p], I[r]);", "J[r] = J[p];"),
+    "erode_seed_wrong_side": ("if (J[r] > J[p] && J[r] > I[r]) {", "if (J[r] < J[p] && J[r] > I[r]) {"),
+    "erode_no_fifo_push": ("J[r] = u8max(J[p], I[r]);\n                    if (fifo_push(&q, r) != 0) { free(q.buf); return -2; }",
+                           "J[r] = u8max(J[p], I[r]);\n                    (void)0;"),
+    "hdome_marker_off_by_one": ("img[i] > hval ? img[i] - hval : 0", "img[i] > hval ? img[i] - hval + 1 : 0"),
+    "rmax_threshold": ("out[i] = out[i] ? 255 : 0;", "out[i] = out[i] > 1 ? 255 : 0;"),
 }
 
 
@@ -45,9 +54,16 @@ def _build_mutant(tmp_path, name):
     subprocess.run(["gcc", "-O1", "-std=c99", "-fPIC", "-shared", "-o", str(so), str(path)],
                    check=True)
     lib = ctypes.CDLL(str(so))
+    _declare(lib)
+    return lib
+
+
+def _declare(lib):
     lib.oracle_recon_dilate_many.argtypes = [ctypes.c_void_p] * 3 + [ctypes.c_int64] * 3 + [ctypes.c_int]
     lib.oracle_fill_holes.argtypes = [ctypes.c_void_p] * 2 + [ctypes.c_int64] * 2 + [ctypes.c_int]
-    return lib
+    lib.oracle_recon_erode.argtypes = [ctypes.c_void_p] * 3 + [ctypes.c_int64] * 2 + [ctypes.c_int]
+    lib.oracle_hdome.argtypes = [ctypes.c_void_p] * 2 + [ctypes.c_int64] * 2 + [ctypes.c_int, ctypes.c_int]
+    lib.oracle_regional_max.argtypes = [ctypes.c_void_p] * 2 + [ctypes.c_int64] * 2 + [ctypes.c_int]
 
 
 def _pins_pass(lib):
@@ -74,6 +90,24 @@ def _pins_pass(lib):
             lib.oracle_fill_holes(x.ctypes.data, out.ctypes.data, 9, 11, conn)
             if not np.array_equal(out, brute.fill_holes_binary(x, conn)):
                 return False
+    # reconstruction by erosion, h-dome and regional maxima against their definitions
+    for conn in (4, 8):
+        for _ in range(30):
+            h, w = rng.integers(1, 9, size=2)
+            mask = rng.integers(0, 4, size=(h, w)).astype(np.uint8) * 60
+            marker = np.clip(mask.astype(int) + rng.integers(0, 200, size=(h, w)), 0, 255).astype(np.uint8)
+            out = np.empty_like(mask)
+            lib.oracle_recon_erode(marker.ctypes.data, mask.ctypes.data, out.ctypes.data, h, w, conn)
+            if not np.array_equal(out, brute.iterate_erosion(marker, mask, conn)):
+                return False
+            img = rng.integers(0, 256, size=(h, w)).astype(np.uint8)
+            lib.oracle_hdome(img.ctypes.data, out.ctypes.data, h, w, 9, conn)
+            want = img - brute.iterate_definition(np.clip(img.astype(int) - 9, 0, 255).astype(np.uint8), img, conn)
+            if not np.array_equal(out, want):
+                return False
+            lib.oracle_regional_max(img.ctypes.data, out.ctypes.data, h, w, conn)
+            if not np.array_equal(out, brute.regional_max_by_plateaus(img, conn)):
+                return False
     return True
 
 
@@ -84,8 +118,7 @@ def test_unmutated_copy_passes(tmp_path):
     so = tmp_path / "same.so"
     subprocess.run(["gcc", "-O1", "-std=c99", "-fPIC", "-shared", "-o", str(so), str(path)], check=True)
     lib = ctypes.CDLL(str(so))
-    lib.oracle_recon_dilate_many.argtypes = [ctypes.c_void_p] * 3 + [ctypes.c_int64] * 3 + [ctypes.c_int]
-    lib.oracle_fill_holes.argtypes = [ctypes.c_void_p] * 2 + [ctypes.c_int64] * 2 + [ctypes.c_int]
+    _declare(lib)
     assert _pins_pass(lib)
 
 
