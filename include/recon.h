@@ -1,6 +1,7 @@
 /*
  * recon.h -- C ABI of librecon: grayscale morphological reconstruction by
- * dilation and fill-holes on uint8 image tiles, for AMD Instinct MI355X
+ * dilation and by erosion, and the operations built on it (fill-holes,
+ * h-dome, regional maxima), on uint8 image tiles, for AMD Instinct MI355X
  * (gfx950).
  *
  * What is computed
@@ -22,6 +23,18 @@
  * image frame and 0 elsewhere; `conn` is the connectivity of that
  * reconstruction, i.e. of the background.
  *
+ * The MR-based operations of Table 1 (ReconToNuclei, RBC detection,
+ * Pre-Watershed) follow Vincent's grayscale reconstruction, which also defines
+ * the dual and the derived transforms provided here:
+ * * reconstruction by erosion rho^e_I(J): the fixed point of
+ *   J <- max(erode(J), I) started from max(J, I) (erode: flat erosion over the
+ *   same neighbourhood); computed as 255 - rho_{255-I}(255 - J);
+ * * the h-dome D_h(I) = I - rho_I(max(I - h, 0)), 1 <= h <= 255;
+ * * the regional maxima of I: 255 where D_1(I) > 0, else 0 (a plateau of
+ *   value 0 is never one).
+ * The marker max(I - h, 0) of the h-dome is the marker form of the
+ * reconstruction the paper's benchmark tiles are quoted with.
+ *
  * Conventions
  * -----------
  * * Images are single-channel uint8, row-major, `pitch` bytes between rows
@@ -29,8 +42,9 @@
  *   caller owns every image buffer; the library never allocates or frees
  *   them, and they must stay valid until the work on `stream` (or the
  *   ticket) has completed.
- * * Results are written in place: into the marker (recon_dilate) or the image
- *   (recon_fill_holes).  The marker and the mask must not overlap.
+ * * Results are written in place: into the marker (recon_dilate,
+ *   recon_erode) or the image (recon_fill_holes, recon_hdome,
+ *   recon_regional_max).  The marker and the mask must not overlap.
  * * `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
  *   device work is enqueued asynchronously on it; the call returns once the
  *   work is enqueued.
@@ -62,7 +76,13 @@ typedef enum {
     RECON_ETIMEDOUT = -5   /* recon_wait timed out; the work is still in flight */
 } recon_status;
 
-enum { RECON_OP_DILATE = 0, RECON_OP_FILL_HOLES = 1 };
+enum {
+    RECON_OP_DILATE = 0,
+    RECON_OP_FILL_HOLES = 1,
+    RECON_OP_ERODE = 2,
+    RECON_OP_HDOME = 3,
+    RECON_OP_REGIONAL_MAX = 4
+};
 
 typedef struct recon_ctx recon_ctx;
 
@@ -75,8 +95,13 @@ typedef struct {
 } recon_image;
 
 /* One unit of work for recon_batch / recon_submit.
- * op == RECON_OP_DILATE:     image = marker (in: J, out: rho_mask(J)), mask = I.
- * op == RECON_OP_FILL_HOLES: image = X (in: X, out: filled), mask ignored. */
+ * op == RECON_OP_DILATE:       image = marker (in: J, out: rho_mask(J)), mask = I.
+ * op == RECON_OP_FILL_HOLES:   image = X (in: X, out: filled), mask ignored.
+ * op == RECON_OP_ERODE:        image = marker (in: J, out: rho^e_mask(J)), mask = I.
+ * op == RECON_OP_HDOME:        image = I (in: I, out: D_h(I)), h = the height, mask ignored.
+ * op == RECON_OP_REGIONAL_MAX: image = I (in: I, out: 0 / 255), mask ignored.
+ * Fill-holes, h-dome and regional maxima hold their marker in a scratch plane
+ * of the context (width rounded up to 4, times height bytes). */
 typedef struct {
     int32_t op;
     int32_t conn;          /* 4 or 8 */
@@ -86,6 +111,7 @@ typedef struct {
                               -1 = none, 1..8) */
     int32_t queue_capacity;/* per-task tuning: LDS queue entries, a power of two (0 = context
                               default; at most the context's queue_capacity) */
+    int32_t h;             /* RECON_OP_HDOME: dome height 1..255; ignored by the others */
 } recon_task;
 
 /* Tuning and capacity knobs; zero fields take the defaults. */
@@ -143,6 +169,23 @@ int recon_dilate(recon_ctx *ctx, recon_image *marker, const recon_image *mask, i
  * connectivity.  Enqueued on `stream`. */
 int recon_fill_holes(recon_ctx *ctx, recon_image *img, int conn, void *stream);
 
+/* Reconstruction by erosion of `mask` from `marker`, in place on marker:
+ * the fixed point of J <- max(erode(J), mask) from max(marker, mask).  Shapes
+ * must match and the two must not overlap; conn is 4 or 8.  The marker is
+ * complemented in place while the work runs (it holds 255 - J in between).
+ * Enqueued on `stream`. */
+int recon_erode(recon_ctx *ctx, recon_image *marker, const recon_image *mask, int conn,
+                void *stream);
+
+/* h-dome of `img`, in place: img <- img - rho_img(max(img - h, 0)), with h in
+ * 1..255 (RECON_EINVAL otherwise).  conn is 4 or 8.  Enqueued on `stream`. */
+int recon_hdome(recon_ctx *ctx, recon_image *img, int h, int conn, void *stream);
+
+/* Regional maxima of `img`, in place: 255 where the 1-dome is positive (the
+ * pixel belongs to a connected plateau with no higher neighbour, of value
+ * > 0), else 0.  conn is 4 or 8.  Enqueued on `stream`. */
+int recon_regional_max(recon_ctx *ctx, recon_image *img, int conn, void *stream);
+
 /* Run n tasks (any mix of ops, shapes and connectivities) in one persistent
  * launch sequence, replayed from a HIP graph.  Enqueued on `stream`. */
 int recon_batch(recon_ctx *ctx, const recon_task *tasks, int32_t n, void *stream);
@@ -159,7 +202,7 @@ int recon_wait(recon_ctx *ctx, uint64_t ticket, int64_t timeout_us);
 int recon_serve_stop(recon_ctx *ctx);
 
 /* Statistics of the last completed recon_dilate / recon_fill_holes /
- * recon_batch launch (synchronises with it).  Returns RECON_EDEVICE if that
+ * recon_erode / recon_hdome / recon_regional_max / recon_batch launch (synchronises with it).  Returns RECON_EDEVICE if that
  * launch was stopped by the scheduler watchdog (no block visit completed for
  * 8 s), in which case its results are incomplete. */
 int recon_last_stats(recon_ctx *ctx, recon_stats *out);

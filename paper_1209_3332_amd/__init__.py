@@ -1,5 +1,6 @@
-"""Python binding of librecon: grayscale reconstruction by dilation and fill-holes
-on uint8 tiles, hand-written HIP for AMD MI355X (gfx950).
+"""Python binding of librecon: grayscale reconstruction by dilation and by
+erosion, fill-holes, h-dome and regional maxima on uint8 tiles, hand-written HIP
+for AMD MI355X (gfx950).
 
 Argument marshalling only: every step of the computation runs in the HIP
 kernels of ``librecon.so``.  torch provides device memory (uint8 CUDA/HIP
@@ -8,8 +9,9 @@ tensors, whose ``data_ptr()`` is passed through) and streams
 built library raises; there is no CPU fallback.
 
 Low-level functions keep the C names (``recon_create``, ``recon_dilate``,
-``recon_fill_holes``, ``recon_batch``, ``recon_submit``, ``recon_poll``,
-``recon_wait``, ...); ``Recon`` wraps a context for convenience.
+``recon_fill_holes``, ``recon_erode``, ``recon_hdome``, ``recon_regional_max``,
+``recon_batch``, ``recon_submit``, ``recon_poll``, ``recon_wait``, ...);
+``Recon`` wraps a context for convenience.
 """
 from __future__ import annotations
 
@@ -20,11 +22,15 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librecon.so")
 
 RECON_OK, RECON_EINVAL, RECON_ENOMEM, RECON_EDEVICE, RECON_EAGAIN, RECON_ETIMEDOUT = 0, -1, -2, -3, -4, -5
-RECON_OP_DILATE, RECON_OP_FILL_HOLES = 0, 1
+RECON_OP_DILATE, RECON_OP_FILL_HOLES, RECON_OP_ERODE, RECON_OP_HDOME, RECON_OP_REGIONAL_MAX = 0, 1, 2, 3, 4
+OPS = {"dilate": RECON_OP_DILATE, "fill_holes": RECON_OP_FILL_HOLES, "erode": RECON_OP_ERODE,
+       "hdome": RECON_OP_HDOME, "regional_max": RECON_OP_REGIONAL_MAX}
+TWO_PLANE_OPS = ("dilate", "erode")   # marker and mask are two images
 
 # every symbol the C header declares
 EXPORTED = (
-    "recon_create", "recon_destroy", "recon_dilate", "recon_fill_holes", "recon_batch",
+    "recon_create", "recon_destroy", "recon_dilate", "recon_fill_holes", "recon_erode",
+    "recon_hdome", "recon_regional_max", "recon_batch",
     "recon_submit", "recon_poll", "recon_wait", "recon_serve_stop", "recon_last_stats",
     "recon_launch_times", "recon_last_error",
 )
@@ -51,7 +57,8 @@ class recon_image(ctypes.Structure):
 
 class recon_task(ctypes.Structure):
     _fields_ = [("op", ctypes.c_int32), ("conn", ctypes.c_int32), ("image", recon_image),
-                ("mask", recon_image), ("scan_rounds", ctypes.c_int32), ("queue_capacity", ctypes.c_int32)]
+                ("mask", recon_image), ("scan_rounds", ctypes.c_int32), ("queue_capacity", ctypes.c_int32),
+                ("h", ctypes.c_int32)]
 
 
 class recon_config(ctypes.Structure):
@@ -88,6 +95,9 @@ def load_library(path: str = LIB_PATH):
     lib.recon_destroy.argtypes = [P]
     lib.recon_dilate.argtypes = [P, ctypes.POINTER(recon_image), ctypes.POINTER(recon_image), ctypes.c_int, P]
     lib.recon_fill_holes.argtypes = [P, ctypes.POINTER(recon_image), ctypes.c_int, P]
+    lib.recon_erode.argtypes = [P, ctypes.POINTER(recon_image), ctypes.POINTER(recon_image), ctypes.c_int, P]
+    lib.recon_hdome.argtypes = [P, ctypes.POINTER(recon_image), ctypes.c_int, ctypes.c_int, P]
+    lib.recon_regional_max.argtypes = [P, ctypes.POINTER(recon_image), ctypes.c_int, P]
     lib.recon_batch.argtypes = [P, ctypes.POINTER(recon_task), ctypes.c_int32, P]
     lib.recon_submit.argtypes = [P, ctypes.POINTER(recon_task), ctypes.POINTER(ctypes.c_uint64)]
     lib.recon_poll.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int)]
@@ -163,16 +173,34 @@ def recon_fill_holes(ctx: int, img, conn: int = 8, stream=None) -> None:
     _check(load_library().recon_fill_holes(ctx, ctypes.byref(m), int(conn), _stream_ptr(stream)))
 
 
-def make_task(op: str, image, mask=None, conn: int = 8, scan_rounds: int = 0, queue_capacity: int = 0) -> recon_task:
+def recon_erode(ctx: int, marker, mask, conn: int = 8, stream=None) -> None:
+    m, k = image_of(marker), image_of(mask)
+    _check(load_library().recon_erode(ctx, ctypes.byref(m), ctypes.byref(k), int(conn), _stream_ptr(stream)))
+
+
+def recon_hdome(ctx: int, img, h: int, conn: int = 8, stream=None) -> None:
+    m = image_of(img)
+    _check(load_library().recon_hdome(ctx, ctypes.byref(m), int(h), int(conn), _stream_ptr(stream)))
+
+
+def recon_regional_max(ctx: int, img, conn: int = 8, stream=None) -> None:
+    m = image_of(img)
+    _check(load_library().recon_regional_max(ctx, ctypes.byref(m), int(conn), _stream_ptr(stream)))
+
+
+def make_task(op: str, image, mask=None, conn: int = 8, scan_rounds: int = 0, queue_capacity: int = 0,
+              h: int = 0) -> recon_task:
+    """recon_task for op in OPS; `mask` for dilate / erode, `h` for hdome."""
+    if op not in OPS:
+        raise ValueError("op must be one of %s" % ", ".join(OPS))
     t = recon_task()
+    t.op = OPS[op]
     t.scan_rounds = int(scan_rounds)
     t.queue_capacity = int(queue_capacity)
-    t.op = RECON_OP_DILATE if op == "dilate" else RECON_OP_FILL_HOLES
-    if op not in ("dilate", "fill_holes"):
-        raise ValueError("op must be 'dilate' or 'fill_holes'")
     t.conn = int(conn)
+    t.h = int(h)
     t.image = image_of(image)
-    if op == "dilate":
+    if op in TWO_PLANE_OPS:
         t.mask = image_of(mask)
     return t
 
@@ -255,14 +283,30 @@ class Recon:
         recon_fill_holes(self.ctx, img, conn, stream)
         return img
 
+    def erode(self, marker, mask, conn: int = 8, stream=None):
+        """In place: marker <- reconstruction by erosion of mask from marker."""
+        recon_erode(self.ctx, marker, mask, conn, stream)
+        return marker
+
+    def hdome(self, img, h: int, conn: int = 8, stream=None):
+        """In place: img <- img - rho_img(max(img - h, 0))."""
+        recon_hdome(self.ctx, img, h, conn, stream)
+        return img
+
+    def regional_max(self, img, conn: int = 8, stream=None):
+        """In place: img <- 255 on the regional maxima of img, 0 elsewhere."""
+        recon_regional_max(self.ctx, img, conn, stream)
+        return img
+
     def batch(self, tasks, stream=None):
-        """tasks: list of dicts {op, image, mask?, conn} of device tensors (results in place)."""
+        """tasks: list of dicts {op, image, mask?, conn, h?} of device tensors (results in place)."""
         recon_batch(self.ctx, [make_task(t["op"], t["image"], t.get("mask"), t.get("conn", 8),
-                                         t.get("scan_rounds", 0), t.get("queue_capacity", 0))
+                                         t.get("scan_rounds", 0), t.get("queue_capacity", 0), t.get("h", 0))
                                for t in tasks], stream)
 
-    def submit(self, op, image, mask=None, conn: int = 8, scan_rounds: int = 0, queue_capacity: int = 0) -> int:
-        tk = recon_submit(self.ctx, make_task(op, image, mask, conn, scan_rounds, queue_capacity))
+    def submit(self, op, image, mask=None, conn: int = 8, scan_rounds: int = 0, queue_capacity: int = 0,
+               h: int = 0) -> int:
+        tk = recon_submit(self.ctx, make_task(op, image, mask, conn, scan_rounds, queue_capacity, h))
         self._keep[tk] = (image, mask)
         return tk
 

@@ -39,10 +39,18 @@
 // raise pixels.  So any read gives a valid lower bound, and a missed update is
 // always caught by the border check of the block that made it.
 //
-// Fill-holes runs the same kernels on the implicit mask 255 - X with the
-// marker held in a scratch plane: K1 computes the initial marker (255 - X on
-// the image frame, 0 inside) on the fly, and fill_finish writes 255 - J back
-// into the image.
+// The other operations run the same kernels on a transformed pair (the
+// transform is applied when the mask is read, and by init_marker to the
+// marker plane before the first visit; finish_result maps the fixed point
+// back):
+//   fill-holes       mask 255 - X, marker in a scratch plane: 255 - X on the
+//                    image frame, 0 inside; result 255 - J into the image;
+//   erosion          mask 255 - I, marker 255 - J complemented in place in the
+//                    caller's marker plane; result 255 - J in the same plane
+//                    (reconstruction by erosion is the dual of dilation);
+//   h-dome           mask I, marker max(I - h, 0) in a scratch plane; result
+//                    I - J into the image;
+//   regional maxima  the 1-dome, result 255 where it is positive, else 0.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -72,17 +80,20 @@ constexpr uint32_t ST_R = 2u;  // a wave owns the block
 constexpr uint32_t ST_D = 4u;  // visit requested (queued, or re-run pending)
 constexpr uint32_t ST_V = 8u;  // the block has had its first (dense) visit
 
-enum { OP_DILATE = 0, OP_FILL = 1 };
+enum { OP_DILATE = 0, OP_FILL = 1, OP_ERODE = 2, OP_HDOME = 3, OP_RMAX = 4 };
 
 struct TaskDev {
-    uint8_t *j;            // marker plane (dilate) or fill scratch plane
-    const uint8_t *i;      // mask plane (dilate) or the image X (fill: mask = 255 - X)
-    uint8_t *img;          // fill: image receiving 255 - J at the end; dilate: unused
+    uint8_t *j;            // marker plane: the caller's (dilate, erode) or a scratch plane
+    const uint8_t *i;      // mask plane, or the image the mask is derived from
+    uint8_t *img;          // plane receiving the mapped result at the end (unused by dilate)
     int64_t pitch_j;
     int64_t pitch_i;
+    int64_t pitch_img;
     int32_t h, w;
     int32_t conn;
     int32_t op;
+    int32_t minv;          // 1: the mask is 255 - (the plane i) (fill-holes, erosion)
+    int32_t hval;          // h-dome height (h-dome: h, regional maxima: 1)
     int32_t nby, nbx;
     uint32_t block0;       // first global block id of this task
     int32_t aligned;       // 1 if both planes allow dword access (4-aligned base and pitch)
@@ -95,7 +106,7 @@ struct BatchHdr {
     uint32_t n_tasks;
     uint32_t total_blocks;
     uint32_t ring_cap;
-    uint32_t any_fill;
+    uint32_t any_mapped;   // some task needs init_marker / finish_result
     uint32_t pad[12];
 };
 
@@ -297,10 +308,10 @@ __device__ __forceinline__ void cstore4(uint8_t *row, int x, int valid, int alig
     for (int k = 0; k < valid && k < 4; ++k) cstore8(row + x + k, v >> (8 * k));
 }
 
-// mask value of 4 pixels: I, or 255 - X for fill-holes (0 outside the image)
+// mask value of 4 pixels: I, or 255 - I for a complemented mask (0 outside the image)
 __device__ __forceinline__ uint32_t mask4(const TaskDev &t, int gy, int gx, int valid) {
     uint32_t v = gload4(t.i + (int64_t)gy * t.pitch_i, gx, valid, t.aligned);
-    if (t.op == OP_FILL) {
+    if (t.minv) {
         const uint32_t keep = valid >= 4 ? 0xffffffffu : (valid <= 0 ? 0u : ((1u << (8 * valid)) - 1u));
         v = (~v) & keep;
     }
@@ -309,7 +320,7 @@ __device__ __forceinline__ uint32_t mask4(const TaskDev &t, int gy, int gx, int 
 
 __device__ __forceinline__ uint32_t mask1(const TaskDev &t, int gy, int gx) {
     const uint32_t v = gp(t.i)[(int64_t)gy * t.pitch_i + gx];
-    return t.op == OP_FILL ? 255u - v : v;
+    return t.minv ? 255u - v : v;
 }
 
 // current marker value of one pixel, clipped under its mask
@@ -443,7 +454,7 @@ __device__ void load_block(const TaskDev &t, const BlockGeom &g, Lds<BH> &L, boo
             for (int k = 0; k < CH; ++k) {
                 const int r = r0 + k;
                 const bool in = r < g.bh;
-                const uint32_t m = in ? (t.op == OP_FILL ? ~iv[k] : iv[k]) : 0u;
+                const uint32_t m = in ? (t.minv ? ~iv[k] : iv[k]) : 0u;
                 *L.Iw(r, ln) = m;
                 *L.Jw(r, ln) = fill_initial ? fill_init4(t, g.y0 + r, g.x0 + x, in ? 4 : 0, m) : bmin4(jr[k], m);
             }
@@ -591,7 +602,7 @@ __device__ void load_visit(const TaskDev &t, const BlockGeom &g, Lds<BH> &L) {
 #pragma unroll
     for (int k = 0; k < BH; ++k) {
         const bool in = k < g.bh;
-        const uint32_t m = in ? (t.op == OP_FILL ? ~iv[k] : iv[k]) : 0u;
+        const uint32_t m = in ? (t.minv ? ~iv[k] : iv[k]) : 0u;
         *L.Iw(k, ln) = m;
         *L.Jw(k, ln) = bmin4(jr[k], m);
     }
@@ -1496,36 +1507,66 @@ __global__ void reset_work(TaskTable tt, Work *w, uint32_t *state, uint32_t *rin
     }
 }
 
-// Initial fill-holes marker in the scratch plane of every fill task: the mask
-// 255 - X on the image frame, 0 inside (so that any block can read any other's
-// marker before that block's first visit).
-__global__ void fill_init(TaskTable tt) {
+// Initial marker plane of every task that is not a plain dilation, written
+// before any block is visited (so that any block can read any other's marker
+// before that block's first visit): fill-holes 255 - X on the image frame and
+// 0 inside; erosion 255 - J over the caller's marker; h-dome and regional
+// maxima max(I - h, 0).  Grid-stride over dwords of each task in turn.
+__global__ void init_marker(TaskTable tt) {
     const uint32_t n = n_tasks_of(tt);
     for (uint32_t k = 0; k < n; ++k) {
         const TaskDev t = task_of(tt, (int)k);
-        if (t.op != OP_FILL) continue;
+        if (t.op == OP_DILATE) continue;
+        const uint32_t dw = (uint32_t)(t.w + 3) / 4u;
+        const uint64_t total = (uint64_t)t.h * dw;
+        const uint32_t hh = (uint32_t)t.hval * 0x01010101u;
+        for (uint64_t i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (uint64_t)gridDim.x * blockDim.x) {
+            const int y = (int)(i / dw), x = (int)(i % dw) * 4;
+            const int valid = min(4, t.w - x);
+            uint8_t *jrow = t.j + (int64_t)y * t.pitch_j;
+            uint32_t v;
+            if (t.op == OP_FILL) {
+                v = fill_init4(t, y, x, valid, mask4(t, y, x, valid));
+            } else if (t.op == OP_ERODE) {
+                v = ~gload4(jrow, x, valid, t.aligned);
+            } else {
+                // max(I - h, 0) bytewise: I - min(I, h) never borrows across bytes
+                const uint32_t iv = gload4(t.i + (int64_t)y * t.pitch_i, x, valid, t.aligned);
+                v = iv - bmin4(iv, hh);
+            }
+            gstore4(jrow, x, valid, t.aligned, v);
+        }
+    }
+}
+
+// Map the fixed point J back to each task's result: fill-holes and erosion
+// 255 - J; h-dome I - J (J <= I bytewise, so the dword difference never
+// borrows across bytes); regional maxima 255 where I - J > 0, else 0.
+__global__ void finish_result(TaskTable tt) {
+    const uint32_t n = n_tasks_of(tt);
+    for (uint32_t k = 0; k < n; ++k) {
+        const TaskDev t = task_of(tt, (int)k);
+        if (t.op == OP_DILATE) continue;
         const uint32_t dw = (uint32_t)(t.w + 3) / 4u;
         const uint64_t total = (uint64_t)t.h * dw;
         for (uint64_t i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (uint64_t)gridDim.x * blockDim.x) {
             const int y = (int)(i / dw), x = (int)(i % dw) * 4;
             const int valid = min(4, t.w - x);
-            const uint32_t m = mask4(t, y, x, valid);
-            gstore4(t.j + (int64_t)y * t.pitch_j, x, valid, t.aligned, fill_init4(t, y, x, valid, m));
-        }
-    }
-}
-
-// Fill-holes result: image = 255 - J.
-__global__ void fill_finish(TaskTable tt) {
-    const uint32_t n = n_tasks_of(tt);
-    for (uint32_t ti = 0; ti < n; ++ti) {
-        const TaskDev t = task_of(tt, (int)ti);
-        if (t.op != OP_FILL) continue;
-        const int64_t npx = (int64_t)t.h * t.w;
-        for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < npx;
-             p += (int64_t)gridDim.x * blockDim.x) {
-            const int y = (int)(p / t.w), x = (int)(p % t.w);
-            gp(t.img)[(int64_t)y * t.pitch_i + x] = (uint8_t)(255u - gp(t.j)[(int64_t)y * t.pitch_j + x]);
+            const uint32_t jv = gload4(t.j + (int64_t)y * t.pitch_j, x, valid, t.aligned);
+            uint32_t v;
+            if (t.op == OP_FILL || t.op == OP_ERODE) {
+                v = ~jv;
+            } else {
+                const uint32_t d = gload4(t.i + (int64_t)y * t.pitch_i, x, valid, t.aligned) - jv;
+                if (t.op == OP_HDOME) {
+                    v = d;
+                } else {
+                    // 0x80 in every byte of d that is nonzero, then 0x01 -> 0xff
+                    const uint32_t nz = (d | ((d & 0x7f7f7f7fu) + 0x7f7f7f7fu)) & 0x80808080u;
+                    v = (nz >> 7) * 0xffu;
+                }
+            }
+            gstore4(t.img + (int64_t)y * t.pitch_img, x, valid, t.aligned, v);
         }
     }
 }

@@ -236,9 +236,14 @@ bool overlaps(const recon_image &a, const recon_image &b) {
     return a0 < b1 && b0 < a1;
 }
 
+// ops whose marker and mask are two caller images (the others derive both from one)
+bool two_planes(int op) { return op == RECON_OP_DILATE || op == RECON_OP_ERODE; }
+
 int check_task(const recon_task &t, const recon_config *cfg = nullptr) {
-    if (t.op != RECON_OP_DILATE && t.op != RECON_OP_FILL_HOLES)
+    if (t.op < RECON_OP_DILATE || t.op > RECON_OP_REGIONAL_MAX)
         return fail(RECON_EINVAL, "unknown op %d", t.op);
+    if (t.op == RECON_OP_HDOME && (t.h < 1 || t.h > 255))
+        return fail(RECON_EINVAL, "h-dome height must be in 1..255, got %d", t.h);
     if (t.scan_rounds < -1 || t.scan_rounds > 8) return fail(RECON_EINVAL, "task scan_rounds must be in -1..8");
     if (t.queue_capacity != 0 &&
         (t.queue_capacity < 64 || (cfg && t.queue_capacity > cfg->queue_capacity) ||
@@ -246,9 +251,9 @@ int check_task(const recon_task &t, const recon_config *cfg = nullptr) {
         return fail(RECON_EINVAL, "task queue_capacity must be a power of two in 64..%d",
                     cfg ? cfg->queue_capacity : 8192);
     if (t.conn != 4 && t.conn != 8) return fail(RECON_EINVAL, "conn must be 4 or 8, got %d", t.conn);
-    int rc = check_image(&t.image, t.op == RECON_OP_DILATE ? "marker" : "image");
+    int rc = check_image(&t.image, two_planes(t.op) ? "marker" : "image");
     if (rc) return rc;
-    if (t.op == RECON_OP_DILATE) {
+    if (two_planes(t.op)) {
         rc = check_image(&t.mask, "mask");
         if (rc) return rc;
         if (t.mask.height != t.image.height || t.mask.width != t.image.width)
@@ -262,12 +267,17 @@ int check_task(const recon_task &t, const recon_config *cfg = nullptr) {
 bool aligned4(const void *p, int64_t pitch) { return ((uintptr_t)p % 4 == 0) && (pitch % 4 == 0); }
 
 // Host-side task table for `n` tasks (fill scratch planes as offsets, patched later).
+// Device task table of a launch.  Tasks that need a scratch marker plane get
+// its offset into the context's scratch area in `j` (relocated by the caller
+// once the area is allocated) and uses_scratch[k] = 1.
 void build_table(const recon_config &cfg, const recon_task *tasks, int n, int bh, std::vector<rk::TaskDev> &out,
-                 uint32_t &total_blocks, size_t &scratch_bytes, bool &any_fill) {
+                 std::vector<char> &uses_scratch, uint32_t &total_blocks, size_t &scratch_bytes,
+                 bool &any_mapped) {
     out.resize(n);
+    uses_scratch.assign(n, 0);
     total_blocks = 0;
     scratch_bytes = 0;
-    any_fill = false;
+    any_mapped = false;
     for (int k = 0; k < n; ++k) {
         const recon_task &t = tasks[k];
         rk::TaskDev d{};
@@ -280,31 +290,38 @@ void build_table(const recon_config &cfg, const recon_task *tasks, int n, int bh
         total_blocks += (uint32_t)(d.nby * d.nbx);
         d.scan_rounds = t.scan_rounds == 0 ? cfg.scan_rounds : (t.scan_rounds < 0 ? 0 : t.scan_rounds);
         d.qcap = t.queue_capacity == 0 ? cfg.queue_capacity : t.queue_capacity;
-        if (t.op == RECON_OP_DILATE) {
-            d.op = rk::OP_DILATE;
+        d.minv = (t.op == RECON_OP_FILL_HOLES || t.op == RECON_OP_ERODE) ? 1 : 0;
+        d.hval = t.op == RECON_OP_HDOME ? t.h : (t.op == RECON_OP_REGIONAL_MAX ? 1 : 0);
+        if (two_planes(t.op)) {
+            // marker in place in the caller's plane (erosion complements it
+            // before and after the reconstruction)
+            d.op = t.op == RECON_OP_DILATE ? rk::OP_DILATE : rk::OP_ERODE;
             d.j = t.image.data;
             d.pitch_j = t.image.pitch;
             d.i = t.mask.data;
             d.pitch_i = t.mask.pitch;
-            d.img = nullptr;
+            d.img = t.op == RECON_OP_DILATE ? nullptr : t.image.data;
+            d.pitch_img = t.image.pitch;
             d.aligned = aligned4(d.j, d.pitch_j) && aligned4(d.i, d.pitch_i);
         } else {
-            d.op = rk::OP_FILL;
+            d.op = t.op == RECON_OP_FILL_HOLES ? rk::OP_FILL : (t.op == RECON_OP_HDOME ? rk::OP_HDOME : rk::OP_RMAX);
             d.i = t.image.data;
             d.pitch_i = t.image.pitch;
             d.img = t.image.data;
+            d.pitch_img = t.image.pitch;
             d.pitch_j = (int64_t)round_up((size_t)d.w, 4);
             d.j = (uint8_t *)(uintptr_t)scratch_bytes;   // offset into the scratch area
             scratch_bytes += round_up((size_t)d.pitch_j * d.h, 256);
             d.aligned = aligned4(d.i, d.pitch_i);
-            any_fill = true;
+            uses_scratch[k] = 1;
         }
+        if (t.op != RECON_OP_DILATE) any_mapped = true;
         out[k] = d;
     }
 }
 
 // Enqueue the kernels of one launch sequence on `s`.
-int enqueue_kernels(recon_ctx *c, int v, const rk::TaskTable &tt, uint32_t total_blocks, bool any_fill,
+int enqueue_kernels(recon_ctx *c, int v, const rk::TaskTable &tt, uint32_t total_blocks, bool any_mapped,
                     bool dynamic_sizes, hipStream_t s) {
     rk::KArgs ka;
     ka.work = c->d_work;
@@ -335,7 +352,7 @@ int enqueue_kernels(recon_ctx *c, int v, const rk::TaskTable &tt, uint32_t total
     const bool merged = stop == 0;
     hipLaunchKernelGGL(rk::reset_work, dim3(64), dim3(256), 0, s, tt, c->d_work, c->d_state, c->d_ring,
                        c->d_tile_pending, c->d_tile_done, merged ? 1 : 0);
-    if (merged && any_fill) hipLaunchKernelGGL(rk::fill_init, dim3(1024), dim3(256), 0, s, tt);
+    if (any_mapped) hipLaunchKernelGGL(rk::init_marker, dim3(1024), dim3(256), 0, s, tt);
     hipEvent_t *tev = c->tev[c->launches % kTimingRing];
     if (timing) HIP_TRY(hipEventRecord(tev[0], s));
 #define RK_LAUNCH(K, GRID)                                                                        \
@@ -351,7 +368,7 @@ int enqueue_kernels(recon_ctx *c, int v, const rk::TaskTable &tt, uint32_t total
     if (merged || stop >= 3) RK_LAUNCH(revisit_drain, grid3);
     if (timing) HIP_TRY(hipEventRecord(tev[3], s));
 #undef RK_LAUNCH
-    if (any_fill) hipLaunchKernelGGL(rk::fill_finish, dim3(1024), dim3(256), 0, s, tt);
+    if (any_mapped) hipLaunchKernelGGL(rk::finish_result, dim3(1024), dim3(256), 0, s, tt);
     if (timing) HIP_TRY(hipEventRecord(tev[4], s));
     HIP_TRY(hipGetLastError());
     return RECON_OK;
@@ -366,14 +383,19 @@ int run_tasks(recon_ctx *c, const recon_task *tasks, int n, hipStream_t stream, 
     const int bh = c->cfg.block_rows;
     const int v = variant_of(bh);
     std::vector<rk::TaskDev> table;
+    std::vector<char> uses_scratch;
     uint32_t total_blocks = 0;
     size_t scratch = 0;
-    bool any_fill = false;
-    build_table(c->cfg, tasks, n, bh, table, total_blocks, scratch, any_fill);
+    bool any_mapped = false;
+    build_table(c->cfg, tasks, n, bh, table, uses_scratch, total_blocks, scratch, any_mapped);
     rc = ensure_capacity(c, (size_t)n, (size_t)total_blocks, scratch);
     if (rc) return rc;
-    for (auto &d : table)
-        if (d.op == rk::OP_FILL) d.j = c->d_scratch + (uintptr_t)d.j;
+    for (int k = 0; k < n; ++k)
+        if (uses_scratch[k]) {
+            rk::TaskDev &d = table[k];
+            d.j = c->d_scratch + (uintptr_t)d.j;
+            if (!aligned4(d.j, d.pitch_j)) d.aligned = 0;
+        }
 
     rk::TaskTable tt{};
     const bool inline_table = !use_graph && n <= rk::MAX_INLINE_TASKS;
@@ -394,7 +416,7 @@ int run_tasks(recon_ctx *c, const recon_task *tasks, int n, hipStream_t stream, 
         hdr.n_tasks = (uint32_t)n;
         hdr.total_blocks = total_blocks;
         hdr.ring_cap = (uint32_t)ring_slots(c->cap_blocks);
-        hdr.any_fill = any_fill ? 1u : 0u;
+        hdr.any_mapped = any_mapped ? 1u : 0u;
         std::memcpy(c->h_table, &hdr, sizeof(hdr));
         std::memcpy(c->h_table + sizeof(hdr), table.data(), table.size() * sizeof(rk::TaskDev));
     }
@@ -433,7 +455,7 @@ int run_tasks(recon_ctx *c, const recon_task *tasks, int n, hipStream_t stream, 
                                table_bytes);
             HIP_TRY(hipEventRecord(c->table_used, stream));
         }
-        rc = enqueue_kernels(c, v, tt, total_blocks, any_fill, false, stream);
+        rc = enqueue_kernels(c, v, tt, total_blocks, any_mapped, false, stream);
         if (rc) return rc;
     }
     HIP_TRY(hipEventRecord(c->last_done, stream));
@@ -537,7 +559,7 @@ int make_ctx(recon_ctx **out, int device, const recon_config &c) {
 
 size_t task_bytes(const recon_task &t) {
     size_t b = (size_t)t.image.height * (size_t)t.image.pitch;
-    if (t.op == RECON_OP_DILATE) b += (size_t)t.mask.height * (size_t)t.mask.pitch;
+    if (two_planes(t.op)) b += (size_t)t.mask.height * (size_t)t.mask.pitch;
     else b += round_up((size_t)round_up((size_t)t.image.width, 4) * t.image.height, 256);
     return b;
 }
@@ -766,6 +788,44 @@ int recon_fill_holes(recon_ctx *ctx, recon_image *img, int conn, void *stream) {
     if (!img) return fail(RECON_EINVAL, "null image");
     recon_task t{};
     t.op = RECON_OP_FILL_HOLES;
+    t.conn = conn;
+    t.image = *img;
+    int rc = check_task(t);
+    if (rc) return rc;
+    return run_tasks(ctx, &t, 1, (hipStream_t)stream, false);
+}
+
+int recon_erode(recon_ctx *ctx, recon_image *marker, const recon_image *mask, int conn, void *stream) {
+    if (!ctx) return fail(RECON_EINVAL, "null context");
+    if (!marker || !mask) return fail(RECON_EINVAL, "null image");
+    recon_task t{};
+    t.op = RECON_OP_ERODE;
+    t.conn = conn;
+    t.image = *marker;
+    t.mask = *mask;
+    int rc = check_task(t);
+    if (rc) return rc;
+    return run_tasks(ctx, &t, 1, (hipStream_t)stream, false);
+}
+
+int recon_hdome(recon_ctx *ctx, recon_image *img, int h, int conn, void *stream) {
+    if (!ctx) return fail(RECON_EINVAL, "null context");
+    if (!img) return fail(RECON_EINVAL, "null image");
+    recon_task t{};
+    t.op = RECON_OP_HDOME;
+    t.conn = conn;
+    t.h = h;
+    t.image = *img;
+    int rc = check_task(t);
+    if (rc) return rc;
+    return run_tasks(ctx, &t, 1, (hipStream_t)stream, false);
+}
+
+int recon_regional_max(recon_ctx *ctx, recon_image *img, int conn, void *stream) {
+    if (!ctx) return fail(RECON_EINVAL, "null context");
+    if (!img) return fail(RECON_EINVAL, "null image");
+    recon_task t{};
+    t.op = RECON_OP_REGIONAL_MAX;
     t.conn = conn;
     t.image = *img;
     int rc = check_task(t);

@@ -27,21 +27,27 @@ def build(out_dir, sanitize=True):
     return exe
 
 
+OPS = {"dilate": 0, "fill_holes": 1, "erode": 2, "hdome": 3, "regional_max": 4}
+TWO_PLANE = ("dilate", "erode")
+
+
 def run(exe, tasks, bh=32, qcap=2048, scan_rounds=2, n_waves=4, watchdog_s=20.0, timeout=600, stop_after=0):
-    """tasks: list of dicts {op: 'dilate'|'fill_holes', marker+mask or img, conn}.
+    """tasks: list of dicts {op, marker+mask (dilate, erode) or img (fill_holes,
+    hdome, regional_max), conn, h (hdome)}.
     Returns (returncode, outputs, stdout+stderr)."""
     with tempfile.TemporaryDirectory() as d:
         lines = []
         for k, t in enumerate(tasks):
-            img = np.ascontiguousarray(t["marker"] if t["op"] == "dilate" else t["img"], dtype=np.uint8)
+            two = t["op"] in TWO_PLANE
+            img = np.ascontiguousarray(t["marker"] if two else t["img"], dtype=np.uint8)
             ip, mp, op = (os.path.join(d, "%d_%s.bin" % (k, s)) for s in ("img", "mask", "out"))
             img.tofile(ip)
-            if t["op"] == "dilate":
+            if two:
                 np.ascontiguousarray(t["mask"], dtype=np.uint8).tofile(mp)
             else:
                 mp = "-"
-            lines.append("%d %d %d %d %s %s %s" % (0 if t["op"] == "dilate" else 1, t["conn"],
-                                                   img.shape[0], img.shape[1], ip, mp, op))
+            lines.append("%d %d %d %d %d %s %s %s" % (OPS[t["op"]], t["conn"], t.get("h", 0),
+                                                      img.shape[0], img.shape[1], ip, mp, op))
         env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1",
                    UBSAN_OPTIONS="print_stacktrace=1")
         p = subprocess.run([exe, str(bh), str(qcap), str(scan_rounds), str(n_waves), str(watchdog_s),
@@ -49,7 +55,7 @@ def run(exe, tasks, bh=32, qcap=2048, scan_rounds=2, n_waves=4, watchdog_s=20.0,
                            text=True, timeout=timeout, env=env)
         outs = []
         for k, t in enumerate(tasks):
-            shape = (t["marker"] if t["op"] == "dilate" else t["img"]).shape
+            shape = (t["marker"] if t["op"] in TWO_PLANE else t["img"]).shape
             op = os.path.join(d, "%d_out.bin" % k)
             outs.append(np.fromfile(op, dtype=np.uint8).reshape(shape) if os.path.exists(op) else None)
         return p.returncode, outs, p.stdout + p.stderr

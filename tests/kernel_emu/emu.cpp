@@ -208,10 +208,11 @@ static bool run_wave(const std::function<void()> &body, size_t lds_size) {
 extern "C" {
 
 struct EmuTask {
-    int32_t op;        // 0 dilate, 1 fill-holes
+    int32_t op;        // 0 dilate, 1 fill-holes, 2 erode, 3 h-dome, 4 regional maxima
     int32_t conn;
+    int32_t hval;      // h-dome height
     int32_t h, w;
-    uint8_t *image;    // dilate: marker (in/out); fill: image (in/out); dense h x w
+    uint8_t *image;    // dilate / erode: marker (in/out); the others: image (in/out); dense h x w
     const uint8_t *mask;
 };
 
@@ -227,7 +228,7 @@ int emu_run(const EmuTask *tasks, int n, int bh, int qcap, int scan_rounds, int 
     std::vector<uint8_t *> jplanes(n), iplanes(n, nullptr), scratch(n, nullptr);
     std::vector<TaskDev> table(n);
     uint32_t total = 0;
-    bool any_fill = false;
+    bool any_mapped = false;
     for (int k = 0; k < n; ++k) {
         const EmuTask &e = tasks[k];
         const size_t px = (size_t)e.h * e.w;
@@ -243,28 +244,33 @@ int emu_run(const EmuTask *tasks, int n, int bh, int qcap, int scan_rounds, int 
         d.qcap = qcap;
         jplanes[k] = (uint8_t *)std::malloc(px);
         std::memcpy(jplanes[k], e.image, px);
-        if (e.op == 0) {
+        d.minv = (e.op == 1 || e.op == 2) ? 1 : 0;
+        d.hval = e.op == 3 ? e.hval : (e.op == 4 ? 1 : 0);
+        if (e.op == 0 || e.op == 2) {
             iplanes[k] = (uint8_t *)std::malloc(px);
             std::memcpy(iplanes[k], e.mask, px);
-            d.op = OP_DILATE;
+            d.op = e.op == 0 ? OP_DILATE : OP_ERODE;
             d.j = jplanes[k];
             d.pitch_j = e.w;
             d.i = iplanes[k];
             d.pitch_i = e.w;
+            d.img = e.op == 0 ? nullptr : jplanes[k];
+            d.pitch_img = e.w;
             d.aligned = (e.w % 4 == 0);
         } else {
             const int64_t pj = (e.w + 3) / 4 * 4;
             scratch[k] = (uint8_t *)std::malloc((size_t)pj * e.h);
-            std::memset(scratch[k], 0xee, (size_t)pj * e.h);   // garbage: K1 must not read it
-            d.op = OP_FILL;
+            std::memset(scratch[k], 0xee, (size_t)pj * e.h);   // garbage: init_marker overwrites it
+            d.op = e.op == 1 ? OP_FILL : (e.op == 3 ? OP_HDOME : OP_RMAX);
             d.i = jplanes[k];
             d.pitch_i = e.w;
             d.img = jplanes[k];
+            d.pitch_img = e.w;
             d.j = scratch[k];
             d.pitch_j = pj;
             d.aligned = (e.w % 4 == 0);
-            any_fill = true;
         }
+        if (e.op != 0) any_mapped = true;
         table[k] = d;
     }
     // task table: inline in the "kernel arguments" when small, else in memory
@@ -281,7 +287,7 @@ int emu_run(const EmuTask *tasks, int n, int bh, int qcap, int scan_rounds, int 
         hdr.n_tasks = (uint32_t)n;
         hdr.total_blocks = total;
         hdr.ring_cap = total + (uint32_t)n_waves + 1;
-        hdr.any_fill = any_fill ? 1u : 0u;
+        hdr.any_mapped = any_mapped ? 1u : 0u;
         std::memcpy(ext_mem.data(), &hdr, sizeof(hdr));
         std::memcpy(ext_mem.data() + sizeof(hdr), table.data(), n * sizeof(TaskDev));
         tt.hdr = (const BatchHdr *)ext_mem.data();
@@ -306,7 +312,7 @@ int emu_run(const EmuTask *tasks, int n, int bh, int qcap, int scan_rounds, int 
     // stop_after 0: the persistent pipeline; 1..3: the staged one, stopped after that stage
     const bool merged = stop_after == 0;
     grid_run([&] { reset_work(tt, work, state, ring, tpend, tdone, merged ? 1 : 0); }, 4, 64);
-    if (merged && any_fill) grid_run([&] { fill_init(tt); }, 8, 64);
+    if (any_mapped) grid_run([&] { init_marker(tt); }, 8, 64);
 
     KArgs ka;
     ka.work = work;
@@ -347,7 +353,7 @@ int emu_run(const EmuTask *tasks, int n, int bh, int qcap, int scan_rounds, int 
     if (!merged) run_grid(1, n_waves);
     if (stop_after >= 2) run_grid(2, n_waves);
     if (merged || stop_after >= 3) run_grid(3, n_waves);
-    if (any_fill) grid_run([&] { fill_finish(tt); }, 4, 64);
+    if (any_mapped) grid_run([&] { finish_result(tt); }, 4, 64);
 
     for (int k = 0; k < n; ++k) {
         const EmuTask &e = tasks[k];
@@ -378,7 +384,7 @@ int emu_run(const EmuTask *tasks, int n, int bh, int qcap, int scan_rounds, int 
 #ifdef KEMU_MAIN
 // Stand-alone driver (lets the sanitizer runtime link into the executable):
 //   kemu <bh> <qcap> <scan_rounds> <waves> <watchdog_s> <n> then n lines of
-//   "op conn h w image_path mask_path_or_- out_path" on stdin.
+//   "op conn hval h w image_path mask_path_or_- out_path" on stdin.
 #include <string>
 int main(int argc, char **argv) {
     if (argc < 7) return 2;
@@ -391,20 +397,22 @@ int main(int argc, char **argv) {
     std::vector<std::vector<uint8_t>> imgs(n), masks(n);
     std::vector<std::string> outs(n);
     for (int k = 0; k < n; ++k) {
-        int op, conn, h, w;
+        int op, conn, hval, h, w;
         char ip[1024], mp[1024], op_[1024];
-        if (std::scanf("%d %d %d %d %1023s %1023s %1023s", &op, &conn, &h, &w, ip, mp, op_) != 7) return 3;
+        if (std::scanf("%d %d %d %d %d %1023s %1023s %1023s", &op, &conn, &hval, &h, &w, ip, mp, op_) != 8)
+            return 3;
+        const bool two = op == 0 || op == 2;
         imgs[k].resize((size_t)h * w);
         FILE *f = std::fopen(ip, "rb");
         if (!f || std::fread(imgs[k].data(), 1, imgs[k].size(), f) != imgs[k].size()) return 4;
         std::fclose(f);
-        if (op == 0) {
+        if (two) {
             masks[k].resize((size_t)h * w);
             f = std::fopen(mp, "rb");
             if (!f || std::fread(masks[k].data(), 1, masks[k].size(), f) != masks[k].size()) return 5;
             std::fclose(f);
         }
-        tasks[k] = EmuTask{op, conn, h, w, imgs[k].data(), op == 0 ? masks[k].data() : nullptr};
+        tasks[k] = EmuTask{op, conn, hval, h, w, imgs[k].data(), two ? masks[k].data() : nullptr};
         outs[k] = op_;
     }
     EmuStats st{};

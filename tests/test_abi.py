@@ -2,6 +2,7 @@
 import ctypes
 import os
 import re
+import subprocess
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "recon.h")
@@ -17,7 +18,8 @@ def declared_functions():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for required in ("recon_dilate", "recon_fill_holes", "recon_batch", "recon_submit", "recon_poll",
-                     "recon_wait", "recon_create", "recon_destroy", "recon_last_error"):
+                     "recon_wait", "recon_create", "recon_destroy", "recon_last_error", "recon_erode",
+                     "recon_hdome", "recon_regional_max"):
         assert required in names
 
 
@@ -35,11 +37,27 @@ def test_binding_names_match_header():
         assert callable(getattr(p, name)), name
 
 
-def test_struct_layouts():
+def test_struct_layouts(tmp_path):
+    """The ctypes structures match the header's layout as a C compiler lays it out."""
     import paper_1209_3332_amd as p
-    assert ctypes.sizeof(p.recon_image) == 24
-    assert ctypes.sizeof(p.recon_task) == 64
-    assert ctypes.sizeof(p.recon_config) == 48
+    structs = {"recon_image": p.recon_image, "recon_task": p.recon_task, "recon_config": p.recon_config,
+               "recon_stats": p.recon_stats}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "recon.h"', 'int main(void) {']
+    for name, cls in structs.items():
+        lines.append('printf("%s %%zu\\n", sizeof(%s));' % (name, name))
+        for f, _ in cls._fields_:
+            lines.append('printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (name, f, name, f))
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)], check=True)
+    got = dict(line.split() for line in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                          check=True).stdout.splitlines())
+    for name, cls in structs.items():
+        assert int(got[name]) == ctypes.sizeof(cls), name
+        for f, _ in cls._fields_:
+            assert int(got["%s.%s" % (name, f)]) == getattr(cls, f).offset, (name, f)
 
 
 def test_last_error_is_a_string():

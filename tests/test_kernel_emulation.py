@@ -59,6 +59,27 @@ def test_fill_holes(emu_exe, oracle_mod, conn):
     _check(emu_exe, oracle_mod, tasks, n_waves=3)
 
 
+@pytest.mark.parametrize("conn", [8, 4])
+def test_erode_hdome_regional_max(emu_exe, oracle_mod, conn):
+    """Reconstruction by erosion, h-dome and regional maxima: ragged shapes,
+    a grey nuclei crop, unclipped markers and plateaus."""
+    rng = np.random.default_rng(60 + conn)
+    _, grey, _ = synth.config2_tile(seed=synth.seed_for(2, 24), size=96, n_gauss=2)
+    grey = np.ascontiguousarray(np.concatenate([grey, grey[:, ::-1]], 1))[:, :270]
+    tasks = []
+    for (h, w) in [(1, 1), (9, 1), (33, 257)]:
+        m, k = synth.random_pair(rng, h, w, 5)
+        tasks.append({"op": "erode", "marker": m, "mask": k, "conn": conn})
+    tasks.append({"op": "erode", "marker": np.full_like(grey, 255), "mask": grey, "conn": conn})
+    tasks.append({"op": "hdome", "img": grey, "h": 30, "conn": conn})
+    tasks.append({"op": "hdome", "img": rng.integers(0, 256, (20, 270)).astype(np.uint8), "h": 255,
+                  "conn": conn})
+    tasks.append({"op": "regional_max", "img": grey, "conn": conn})
+    tasks.append({"op": "regional_max", "img": rng.integers(0, 4, (40, 300)).astype(np.uint8), "conn": conn})
+    tasks.append({"op": "regional_max", "img": np.zeros((5, 7), np.uint8), "conn": conn})
+    _check(emu_exe, oracle_mod, tasks, n_waves=3)
+
+
 def test_staged_pipeline(emu_exe, oracle_mod):
     """The staged pipeline (dense pass, border seeding and revisits as separate
     kernels) run to the end gives the same bytes as the persistent one."""
@@ -67,7 +88,9 @@ def test_staged_pipeline(emu_exe, oracle_mod):
     marker = synth.hdome_marker(mask, 20)
     img = np.where(mask > 40, 255, 0).astype(np.uint8)
     tasks = [{"op": "dilate", "marker": marker, "mask": mask, "conn": 8},
-             {"op": "fill_holes", "img": img, "conn": 4}]
+             {"op": "fill_holes", "img": img, "conn": 4},
+             {"op": "erode", "marker": np.full_like(mask, 255), "mask": mask, "conn": 4},
+             {"op": "hdome", "img": mask, "h": 20, "conn": 8}]
     _check(emu_exe, oracle_mod, tasks, n_waves=3, stop_after=3)
 
 
