@@ -122,6 +122,67 @@ def cpu_baseline(marker, mask, binary, budget_s=20.0):
                       "single-core %.2f Mpixel/s" % (n, mask.shape[0], mask.shape[1], 2 * mask.size / one / 1e6)}
 
 
+def next_ops(recon, torch, mask, steps, conn=8, h=20):
+    """Reconstruction by erosion (marker I + h, capped: the dual of the headline
+    marker), the h-dome and the regional maxima of the headline tile, each
+    launched `steps` times back to back on fresh copies: throughput, kernel
+    times, bit-exact parity of the last launch against the oracle, and the
+    oracle's single-core time on the same tile."""
+    import numpy as np
+    import oracle
+    dev = torch.device("cuda:0")
+    up = np.minimum(mask.astype(np.int32) + h, 255).astype(np.uint8)
+    d_mask = torch.from_numpy(mask).to(dev)
+    ctx = recon.Recon(0, timing=1)
+    stream = torch.cuda.current_stream()
+    res = {"workload": "%dx%d nuclei-like tile, %d-conn, h %d; %d launches per op" % (
+        mask.shape[0], mask.shape[1], conn, h, steps)}
+    for op in ("erode", "hdome", "regional_max"):
+        src = up if op == "erode" else mask
+        bufs = [torch.from_numpy(src).to(dev) for _ in range(steps + 2)]
+        torch.cuda.synchronize()
+
+        def launch(b):
+            if op == "erode":
+                ctx.erode(b, d_mask, conn, stream)
+            elif op == "hdome":
+                ctx.hdome(b, h, conn, stream)
+            else:
+                ctx.regional_max(b, conn, stream)
+
+        for b in bufs[:2]:
+            launch(b)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for b in bufs[2:]:
+            launch(b)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        kt = [ctx.launch_times(back) for back in range(min(steps, 64))]
+        st = ctx.last_stats()
+        t0 = time.perf_counter()
+        if op == "erode":
+            want = oracle.recon_erode(up, mask, conn)
+        elif op == "hdome":
+            want = oracle.hdome(mask, h, conn)
+        else:
+            want = oracle.regional_max(mask, conn)
+        t_oracle = time.perf_counter() - t0
+        drain = sum(x["drain_ms"] for x in kt) / len(kt)
+        visits = st["dense_visits"] + st["revisits"]
+        res[op] = {"Mpixel_s": mask.size * steps / wall / 1e6, "ms_per_launch": wall * 1e3 / steps,
+                   "revisit_drain_ms": drain, "launch_ms": sum(x["total_ms"] for x in kt) / len(kt),
+                   "dense_visits": st["dense_visits"], "revisits": st["revisits"],
+                   "revisit_drain_GBs": 3.0 * 32 * 256 * visits / (drain * 1e-3) / 1e9,
+                   "oracle_single_core_Mpixel_s": mask.size / t_oracle / 1e6,
+                   "parity": bool(np.array_equal(bufs[-1].cpu().numpy(), want))}
+        log("%s: %.0f Mpixel/s (%.3f ms/launch), parity %s" % (op, res[op]["Mpixel_s"], res[op]["ms_per_launch"],
+                                                               res[op]["parity"]))
+        del bufs
+    ctx.close()
+    return res
+
+
 def batched_vs_per_tile(recon, torch, ctx_cfg, n_tiles, size, workers, spiral_size):
     import numpy as np
     import oracle
@@ -322,6 +383,8 @@ def main():
                     help="Poisson arrival rates (tiles/s) of the serving run; empty skips it")
     ap.add_argument("--serve-seconds", type=float, default=2.0)
     ap.add_argument("--serve-pool", type=int, default=64)
+    ap.add_argument("--next-ops-steps", type=int, default=10,
+                    help="launches per op of erosion / h-dome / regional maxima on the tile (0 skips)")
     ap.add_argument("--block-rows", type=int, default=0)
     ap.add_argument("--scan-rounds", type=int, default=0)
     ap.add_argument("--queue", type=int, default=0)
@@ -443,6 +506,8 @@ def main():
                       "pixels_per_step": px_step, "block_rows": cfg.get("block_rows", 32)},
            "kernels": kernels, "roofline": roofline, "parity": parity}
     ctx.close()
+    if args.next_ops_steps:
+        out["next_ops"] = next_ops(recon, torch, mask, args.next_ops_steps)
     if args.batch_tiles:
         out["batched_vs_per_tile"] = batched_vs_per_tile(recon, torch, {k: v for k, v in cfg.items()},
                                                          args.batch_tiles, args.size, args.workers,
@@ -463,6 +528,8 @@ def main():
         log("cpu baseline: %.1f Mpixel/s on %d cores" % (out["cpu_baseline"]["value"], out["cpu_baseline"]["cores"]))
     print(json.dumps(out), flush=True)
     if not (parity["dilate"] and parity["fill_holes"]):
+        sys.exit(1)
+    if "next_ops" in out and not all(out["next_ops"][op]["parity"] for op in ("erode", "hdome", "regional_max")):
         sys.exit(1)
 
 

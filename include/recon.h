@@ -116,7 +116,7 @@ typedef struct {
 
 /* Tuning and capacity knobs; zero fields take the defaults. */
 typedef struct {
-    int32_t block_rows;        /* rows per work block: 16, 32 or 64 (default: tuned) */
+    int32_t block_rows;        /* rows per work block: 16, 32 or 64 (default 32) */
     int32_t queue_capacity;    /* LDS queue entries per workgroup: a power of two in 64..8192 */
     int32_t scan_rounds;       /* directional pass rounds on a block's first visit,
                                   1..8; 0 = default (3); -1 = none */
@@ -147,7 +147,8 @@ typedef struct {
     int64_t requests;          /* block revisits requested by border checks */
     int64_t aborted;           /* 1 if the scheduler watchdog stopped the launch */
     /* with recon_config.timing: durations in ms of the dense pass (K1), the border
-       seeding (K2), the revisit drain (K3) and the whole launch; else 0.  A
+       seeding (K2), the revisit drain (K3) and the whole launch (scheduler reset
+       and marker preparation to result mapping); else 0.  A
        batch replayed from a captured graph is timed as a whole: the three
        kernel durations are then -1 */
     float dense_ms, seed_ms, drain_ms, total_ms;
@@ -210,7 +211,8 @@ int recon_last_stats(recon_ctx *ctx, recon_stats *out);
 /* Kernel durations in ms of a recent launch of a context created with
  * timing = 1: `back` = 0 is the last launch sequence, 1 the one before, up to
  * 63.  dense_ms, seed_ms, drain_ms: the dense pass (K1), border seeding (K2)
- * and revisit drain (K3); total_ms: the whole launch.  A replayed graph reports
+ * and revisit drain (K3); total_ms: the whole launch, from the scheduler reset
+ * and marker preparation to the result mapping.  A replayed graph reports
  * only its total (the others are -1).  Waits (up to 60 s) for that launch to
  * complete.  RECON_EINVAL if the context does not time its launches or that
  * launch is no longer kept.  Lets a caller time many launches issued back to

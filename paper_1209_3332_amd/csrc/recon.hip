@@ -119,7 +119,7 @@ struct recon_ctx {
     hipEvent_t table_used = nullptr;  // the last copy out of h_table has finished
     hipEvent_t last_done = nullptr;
     // timing marks of the last kTimingRing launches (before K1, after K1, K2, K3, the launch)
-    hipEvent_t tev[kTimingRing][5] = {};
+    hipEvent_t tev[kTimingRing][6] = {};   // [5] opens the launch, [0]..[4] close its steps
     bool tev_graph[kTimingRing] = {};   // that launch replayed a graph (only its total is marked)
     uint64_t launches = 0;              // launch sequences enqueued so far
     bool have_last = false;
@@ -350,10 +350,11 @@ int enqueue_kernels(recon_ctx *c, int v, const rk::TaskTable &tt, uint32_t total
     // revisit kernel); 1-3: the staged pipeline (dense pass, border seeding,
     // revisits as separate kernels), stopped after that stage (test hooks)
     const bool merged = stop == 0;
+    hipEvent_t *tev = c->tev[c->launches % kTimingRing];
+    if (timing) HIP_TRY(hipEventRecord(tev[5], s));
     hipLaunchKernelGGL(rk::reset_work, dim3(64), dim3(256), 0, s, tt, c->d_work, c->d_state, c->d_ring,
                        c->d_tile_pending, c->d_tile_done, merged ? 1 : 0);
     if (any_mapped) hipLaunchKernelGGL(rk::init_marker, dim3(1024), dim3(256), 0, s, tt);
-    hipEvent_t *tev = c->tev[c->launches % kTimingRing];
     if (timing) HIP_TRY(hipEventRecord(tev[0], s));
 #define RK_LAUNCH(K, GRID)                                                                        \
     switch (v) {                                                                                  \
@@ -445,7 +446,7 @@ int run_tasks(recon_ctx *c, const recon_task *tasks, int n, hipStream_t stream, 
             c->graph_cap_scratch[v] = c->cap_scratch;
         }
         hipEvent_t *tev = c->tev[c->launches % kTimingRing];
-        if (c->cfg.timing) HIP_TRY(hipEventRecord(tev[0], stream));
+        if (c->cfg.timing) HIP_TRY(hipEventRecord(tev[5], stream));
         HIP_TRY(hipGraphLaunch(c->graph[v], stream));
         if (c->cfg.timing) HIP_TRY(hipEventRecord(tev[4], stream));
         HIP_TRY(hipEventRecord(c->table_used, stream));
@@ -848,7 +849,8 @@ int recon_batch(recon_ctx *ctx, const recon_task *tasks, int32_t n, void *stream
 }
 
 // Durations (ms) of a recent launch from its timing marks: K1, K2, K3, whole
-// launch; -1 where a mark was not recorded (graph replays mark only the whole).
+// launch (from before the scheduler reset to after the result mapping); -1
+// where a mark was not recorded (graph replays mark only the whole).
 static void launch_times(recon_ctx *ctx, int back, float t[4]) {
     const int i = (int)((ctx->launches - 1 - (uint64_t)back) % kTimingRing);
     hipEvent_t *tev = ctx->tev[i];
@@ -859,7 +861,7 @@ static void launch_times(recon_ctx *ctx, int back, float t[4]) {
         if (hipEventElapsedTime(&ms, tev[1], tev[2]) == hipSuccess) t[1] = ms;
         if (hipEventElapsedTime(&ms, tev[2], tev[3]) == hipSuccess) t[2] = ms;
     }
-    if (hipEventElapsedTime(&ms, tev[0], tev[4]) == hipSuccess) t[3] = ms;
+    if (hipEventElapsedTime(&ms, tev[5], tev[4]) == hipSuccess) t[3] = ms;
     (void)hipGetLastError();   // a mark that was not recorded must not leave an error behind
 }
 
