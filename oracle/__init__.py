@@ -1,13 +1,15 @@
-"""CPU oracle for grayscale reconstruction by dilation and fill-holes.
+"""CPU oracle for grayscale reconstruction by dilation and fill-holes, the
+operations built on it (erosion, h-dome, regional maxima), and connected-
+component labelling with the area filter.
 
 TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by ``__graft_entry__.smoke()``
 and by the ``cpu_baseline`` leg of ``bench.py``.  The product library never
 imports, links or runs anything in this directory.
 
-The arithmetic lives in ``recon_oracle.c`` (plain C, built with gcc); this
-module only compiles it and marshals numpy arrays through ctypes.  See that
-file's header for the definition followed (the reconstruction the paper's
-Table 1 operations are built on, Sec. V-A) and for the sequential algorithm.
+The arithmetic lives in ``recon_oracle.c`` and ``label_oracle.c`` (plain C,
+built with gcc); this module only compiles them and marshals numpy arrays
+through ctypes.  See those files' headers for the definitions followed (the
+Table 1 operations of Sec. V-A) and for the sequential algorithms.
 """
 from __future__ import annotations
 
@@ -18,7 +20,7 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "recon_oracle.c")
+_SRCS = [os.path.join(_HERE, "recon_oracle.c"), os.path.join(_HERE, "label_oracle.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -27,8 +29,7 @@ def build(force: bool = True) -> str:
     """Compile the C oracle into ``oracle/liboracle.so`` with gcc."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.run(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-o", tmp, _SRC],
-                       check=True)
+        subprocess.run(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-o", tmp] + _SRCS, check=True)
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -53,6 +54,10 @@ def _load():
         lib.oracle_hdome.restype = ctypes.c_int
         lib.oracle_regional_max.argtypes = [u8p, u8p, i64, i64, ctypes.c_int]
         lib.oracle_regional_max.restype = ctypes.c_int
+        lib.oracle_label.argtypes = [u8p, u8p, i64, i64, ctypes.c_int]
+        lib.oracle_label.restype = i64
+        lib.oracle_area_threshold.argtypes = [u8p, u8p, i64, i64, ctypes.c_int, i64, i64]
+        lib.oracle_area_threshold.restype = i64
         _lib = lib
     return _lib
 
@@ -139,6 +144,32 @@ def regional_max(img, conn: int = 8) -> np.ndarray:
     rc = _load().oracle_regional_max(img.ctypes.data, out.ctypes.data, img.shape[0], img.shape[1], int(conn))
     if rc != 0:
         raise ValueError("oracle_regional_max failed with %d" % rc)
+    return out
+
+
+def label(img, conn: int = 8):
+    """Connected components of the nonzero pixels: (int32 labels 1..n in raster
+    order of first pixels, 0 on the background; n)."""
+    img = _u8(img)
+    if img.ndim != 2:
+        raise ValueError("image must be 2-D")
+    out = np.empty(img.shape, np.int32)
+    n = _load().oracle_label(img.ctypes.data, out.ctypes.data, img.shape[0], img.shape[1], int(conn))
+    if n < 0:
+        raise ValueError("oracle_label failed")
+    return out, int(n)
+
+
+def area_threshold(img, min_area: int, max_area: int, conn: int = 8) -> np.ndarray:
+    """255 on the components of the nonzero pixels whose area is in [min_area, max_area], else 0."""
+    img = _u8(img)
+    if img.ndim != 2:
+        raise ValueError("image must be 2-D")
+    out = np.empty_like(img)
+    n = _load().oracle_area_threshold(img.ctypes.data, out.ctypes.data, img.shape[0], img.shape[1], int(conn),
+                                      int(min_area), int(max_area))
+    if n < 0:
+        raise ValueError("oracle_area_threshold failed")
     return out
 
 

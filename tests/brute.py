@@ -18,6 +18,10 @@ Nothing here imports the oracle or the GPU library.
   J_{n+1} = max(eps_B(J_n), I) from max(J, I) (out-of-image pixels absent).
 * ``regional_max_by_plateaus``: regional maxima straight from their
   definition, plateau by plateau through scipy.ndimage.label.
+* ``label_by_propagation``: connected components of the nonzero pixels by
+  propagating the smallest pixel index over foreground neighbours until
+  nothing changes (the component's minimum index is its raster-first pixel),
+  then numbering the components by that index.
 """
 from __future__ import annotations
 
@@ -158,3 +162,30 @@ def row_closed_form(marker_row, mask_row) -> np.ndarray:
         acc = min(int(i[x]), max(int(j[x]), acc))
         bwd[x] = acc
     return np.maximum(fwd, bwd).astype(np.uint8)
+
+
+def label_by_propagation(img, conn: int):
+    """(labels, n) of the nonzero pixels of a 2-D image: each foreground pixel
+    starts with its raster index and takes the minimum over its foreground
+    neighbours (out-of-image pixels absent) until stable; components are then
+    numbered 1..n in increasing order of that minimum."""
+    fg = np.asarray(img) != 0
+    h, w = fg.shape
+    big = h * w
+    cur = np.where(fg, np.arange(big, dtype=np.int64).reshape(h, w), big)
+    while True:
+        p = np.pad(cur, 1, mode="constant", constant_values=big)
+        nxt = cur.copy()
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                if conn == 4 and dy != 0 and dx != 0:
+                    continue
+                nxt = np.minimum(nxt, p[1 + dy:1 + dy + h, 1 + dx:1 + dx + w])
+        nxt = np.where(fg, nxt, big)
+        if np.array_equal(nxt, cur):
+            break
+        cur = nxt
+    roots = np.unique(cur[fg])
+    labels = np.zeros((h, w), np.int32)
+    labels[fg] = np.searchsorted(roots, cur[fg]) + 1
+    return labels, len(roots)
