@@ -35,6 +35,12 @@
  * The marker max(I - h, 0) of the h-dome is the marker form of the
  * reconstruction the paper's benchmark tiles are quoted with.
  *
+ * BWLabel and AreaThreshold (Table 1) are provided too: the connected
+ * components of the nonzero pixels (4- or 8-connectivity, pixels outside the
+ * image absent), labelled 1..n in raster order of each component's first
+ * pixel (0 on the background), and the filter keeping the components whose
+ * pixel count lies in [min_area, max_area].
+ *
  * Conventions
  * -----------
  * * Images are single-channel uint8, row-major, `pitch` bytes between rows
@@ -186,6 +192,25 @@ int recon_hdome(recon_ctx *ctx, recon_image *img, int h, int conn, void *stream)
  * pixel belongs to a connected plateau with no higher neighbour, of value
  * > 0), else 0.  conn is 4 or 8.  Enqueued on `stream`. */
 int recon_regional_max(recon_ctx *ctx, recon_image *img, int conn, void *stream);
+
+/* Connected-component labelling (BWLabel) of `img` (nonzero = foreground):
+ * labels[y * label_pitch + x] <- the label of pixel (y, x): 1..n in raster
+ * order of each component's first pixel, 0 on the background.  `labels` is a
+ * DEVICE int32 plane of height rows and label_pitch >= width elements per row,
+ * owned by the caller and used as the union-find workspace while the work
+ * runs; height * label_pitch must stay below 2^31.  conn (4 or 8) is the
+ * foreground connectivity.  If `count` (a DEVICE int32) is not NULL it
+ * receives n.  The image is not written.  Enqueued on `stream`. */
+int recon_label(recon_ctx *ctx, const recon_image *img, int32_t *labels, int64_t label_pitch, int conn,
+                int32_t *count, void *stream);
+
+/* Area filter (AreaThreshold) of `img`, in place: 255 on the pixels of the
+ * components (of the nonzero pixels, connectivity conn) whose pixel count lies
+ * in [min_area, max_area] (inclusive; 0 <= min_area <= max_area), 0
+ * elsewhere.  Uses a context scratch area of about 8 bytes per pixel.
+ * Enqueued on `stream`. */
+int recon_area_threshold(recon_ctx *ctx, recon_image *img, int conn, int64_t min_area, int64_t max_area,
+                         void *stream);
 
 /* Run n tasks (any mix of ops, shapes and connectivities) in one persistent
  * launch sequence, replayed from a HIP graph.  Enqueued on `stream`. */

@@ -30,7 +30,7 @@ TWO_PLANE_OPS = ("dilate", "erode")   # marker and mask are two images
 # every symbol the C header declares
 EXPORTED = (
     "recon_create", "recon_destroy", "recon_dilate", "recon_fill_holes", "recon_erode",
-    "recon_hdome", "recon_regional_max", "recon_batch",
+    "recon_hdome", "recon_regional_max", "recon_label", "recon_area_threshold", "recon_batch",
     "recon_submit", "recon_poll", "recon_wait", "recon_serve_stop", "recon_last_stats",
     "recon_launch_times", "recon_last_error",
 )
@@ -98,6 +98,9 @@ def load_library(path: str = LIB_PATH):
     lib.recon_erode.argtypes = [P, ctypes.POINTER(recon_image), ctypes.POINTER(recon_image), ctypes.c_int, P]
     lib.recon_hdome.argtypes = [P, ctypes.POINTER(recon_image), ctypes.c_int, ctypes.c_int, P]
     lib.recon_regional_max.argtypes = [P, ctypes.POINTER(recon_image), ctypes.c_int, P]
+    lib.recon_label.argtypes = [P, ctypes.POINTER(recon_image), P, ctypes.c_int64, ctypes.c_int, P, P]
+    lib.recon_area_threshold.argtypes = [P, ctypes.POINTER(recon_image), ctypes.c_int, ctypes.c_int64,
+                                         ctypes.c_int64, P]
     lib.recon_batch.argtypes = [P, ctypes.POINTER(recon_task), ctypes.c_int32, P]
     lib.recon_submit.argtypes = [P, ctypes.POINTER(recon_task), ctypes.POINTER(ctypes.c_uint64)]
     lib.recon_poll.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int)]
@@ -186,6 +189,26 @@ def recon_hdome(ctx: int, img, h: int, conn: int = 8, stream=None) -> None:
 def recon_regional_max(ctx: int, img, conn: int = 8, stream=None) -> None:
     m = image_of(img)
     _check(load_library().recon_regional_max(ctx, ctypes.byref(m), int(conn), _stream_ptr(stream)))
+
+
+def recon_label(ctx: int, img, labels, conn: int = 8, count=None, stream=None) -> None:
+    """labels: 2-D torch.int32 device tensor of img's shape (rows may be padded);
+    count: optional 1-element torch.int32 device tensor receiving the number of labels."""
+    import torch
+    m = image_of(img)
+    if not isinstance(labels, torch.Tensor) or labels.dtype != torch.int32 or labels.dim() != 2 or \
+            not labels.is_cuda or tuple(labels.shape) != tuple(img.shape) or labels.stride(1) != 1:
+        raise TypeError("labels must be a 2-D int32 device tensor of the image's shape with contiguous rows")
+    if count is not None and (count.dtype != torch.int32 or not count.is_cuda or count.numel() < 1):
+        raise TypeError("count must be an int32 device tensor")
+    _check(load_library().recon_label(ctx, ctypes.byref(m), labels.data_ptr(), labels.stride(0), int(conn),
+                                      count.data_ptr() if count is not None else None, _stream_ptr(stream)))
+
+
+def recon_area_threshold(ctx: int, img, min_area: int, max_area: int, conn: int = 8, stream=None) -> None:
+    m = image_of(img)
+    _check(load_library().recon_area_threshold(ctx, ctypes.byref(m), int(conn), int(min_area), int(max_area),
+                                               _stream_ptr(stream)))
 
 
 def make_task(op: str, image, mask=None, conn: int = 8, scan_rounds: int = 0, queue_capacity: int = 0,
@@ -296,6 +319,19 @@ class Recon:
     def regional_max(self, img, conn: int = 8, stream=None):
         """In place: img <- 255 on the regional maxima of img, 0 elsewhere."""
         recon_regional_max(self.ctx, img, conn, stream)
+        return img
+
+    def label(self, img, labels=None, conn: int = 8, count=None, stream=None):
+        """Connected components of img's nonzero pixels into an int32 device plane (allocated if None)."""
+        import torch
+        if labels is None:
+            labels = torch.empty(tuple(img.shape), dtype=torch.int32, device=img.device)
+        recon_label(self.ctx, img, labels, conn, count, stream)
+        return labels
+
+    def area_threshold(self, img, min_area: int, max_area: int, conn: int = 8, stream=None):
+        """In place: img <- 255 on the components with min_area <= area <= max_area, else 0."""
+        recon_area_threshold(self.ctx, img, min_area, max_area, conn, stream)
         return img
 
     def batch(self, tasks, stream=None):

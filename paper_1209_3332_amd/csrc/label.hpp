@@ -1,0 +1,391 @@
+// label.hpp -- device code of connected-component labelling (BWLabel) and the
+// area filter (AreaThreshold) of binary uint8 images, for AMD MI355X (gfx950).
+//
+// Both are listed in Table 1 of the paper (Sec. V-A) among the segmentation
+// operations.  Definitions: the foreground is the set of nonzero pixels; two
+// foreground pixels are connected through foreground paths of 4- or
+// 8-neighbour steps (pixels outside the image do not exist); each component
+// gets one label 1..n, numbered in raster order of its first pixel; the
+// background gets 0.  The area filter keeps (255) the pixels of components
+// whose pixel count lies in [min_area, max_area] and clears the rest.
+//
+// Method (union-find on the label plane itself, then a rank relabelling):
+//   label_local     one wave per 16 x 256 tile: union-find in LDS over the
+//                   tile (link the larger root under the smaller with an LDS
+//                   atomic min), path compression, then every foreground
+//                   pixel's node id is written: the pitched index + 1 of its
+//                   tile root (0 on the background);
+//   label_merge     one wave per tile: the tile's top row and left column
+//                   against the neighbouring tiles' pixels, as a global
+//                   union-find with agent-scope atomic min on the label plane
+//                   (lock-free: a link only ever lowers a root's parent);
+//   label_flatten   every pixel's node id becomes its root's; a root (the
+//                   component's smallest pitched index, i.e. its raster-first
+//                   pixel) sets its bit in a bitmap over pitched indices;
+//   rank_*          exclusive prefix count of the bitmap words (per-segment
+//                   sums, one wave scanning the segments, per-word offsets);
+//   label_final     label = (roots before the pixel's root) + 1.
+// Node ids are pitched indices (y * pitch + x) + 1, so the order of ids is the
+// raster order and the parent of id a is stored at element a - 1.
+#pragma once
+#include "kernels.hpp"
+
+namespace rk {
+
+constexpr int LT_H = 16;     // rows of a labelling tile
+constexpr int LT_W = 256;    // columns (64 lanes x 4 pixels)
+constexpr uint32_t LT_BG = 0xffffffffu;
+constexpr int RANK_SEG = 1024;   // bitmap words per scan segment (64 lanes x 16)
+
+struct LabelArgs {
+    const uint8_t *img;     // input image (nonzero = foreground)
+    int64_t pitch_img;      // bytes
+    int32_t *lab;           // label plane (int32), written in place
+    int64_t pitch_lab;      // elements
+    int32_t h, w;
+    int32_t conn;
+    int32_t tiles_x;        // tiles per row of tiles
+    uint32_t *bits;         // root bitmap over pitched indices
+    uint32_t *word_off;     // roots before each bitmap word
+    uint32_t *seg_sum;      // roots per segment of RANK_SEG words
+    uint32_t n_words;
+    uint32_t n_segs;
+    int32_t *count;         // receives the number of components (may be null)
+};
+
+// ---- tile-local union-find in LDS (indices within the tile)
+
+__device__ __forceinline__ uint32_t lds_find(RK_LDS uint32_t *par, uint32_t a) {
+    while (true) {
+        const uint32_t p = __hip_atomic_load(par + a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (p == a) return a;
+        a = p;
+    }
+}
+
+__device__ __forceinline__ void lds_union(RK_LDS uint32_t *par, uint32_t a, uint32_t b) {
+    while (true) {
+        a = lds_find(par, a);
+        b = lds_find(par, b);
+        if (a == b) return;
+        if (a < b) {
+            const uint32_t t = a;
+            a = b;
+            b = t;
+        }
+        // a is (or was) a root above b: hang it under b unless someone linked it meanwhile
+        const uint32_t old = __hip_atomic_fetch_min(par + a, b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (old == a) return;
+        a = old;
+    }
+}
+
+// ---- global union-find on the label plane (node ids: pitched index + 1)
+
+__device__ __forceinline__ int32_t g_find(int32_t *lab, int32_t a) {
+    while (true) {
+        const int32_t p = __hip_atomic_load((RK_GLOBAL int32_t *)(lab + (a - 1)), __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT);
+        if (p == a) return a;
+        a = p;
+    }
+}
+
+__device__ __forceinline__ void g_union(int32_t *lab, int32_t a, int32_t b) {
+    while (true) {
+        a = g_find(lab, a);
+        b = g_find(lab, b);
+        if (a == b) return;
+        if (a < b) {
+            const int32_t t = a;
+            a = b;
+            b = t;
+        }
+        const int32_t old = __hip_atomic_fetch_min((RK_GLOBAL int32_t *)(lab + (a - 1)), b, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+        if (old == a) return;
+        a = old;
+    }
+}
+
+__device__ __forceinline__ int img_aligned(const LabelArgs &a) {
+    return (((uintptr_t)a.img | (uintptr_t)a.pitch_img) & 3u) == 0;
+}
+
+// Phase 1: tile-local labelling.  Grid: one 64-lane workgroup per tile
+// (grid-stride); dynamic LDS: LT_H * LT_W * 4 bytes.
+__global__ __launch_bounds__(64) void label_local(LabelArgs a) {
+    RK_LDS uint32_t *par = (RK_LDS uint32_t *)dyn_lds();
+    const int ln = lane_id();
+    const int n_tiles = a.tiles_x * ((a.h + LT_H - 1) / LT_H);
+    const int aligned = img_aligned(a);
+    for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        const int y0 = (tile / a.tiles_x) * LT_H, x0 = (tile % a.tiles_x) * LT_W;
+        const int th = min(LT_H, a.h - y0), tw = min(LT_W, a.w - x0);
+        const int c = 4 * ln;
+        const int valid = min(4, tw - c);
+        uint64_t fg = 0;   // bit 4r+k: pixel (r, c+k) is foreground
+#pragma unroll
+        for (int r = 0; r < LT_H; ++r) {
+            const uint32_t v = r < th ? gload4(a.img + (int64_t)(y0 + r) * a.pitch_img, x0 + c, valid, aligned) : 0u;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const bool f = ((v >> (8 * k)) & 0xffu) != 0u;
+                const uint32_t i = (uint32_t)(r * LT_W + c + k);
+                par[i] = f ? i : LT_BG;
+                fg |= (uint64_t)(f ? 1u : 0u) << (4 * r + k);
+            }
+        }
+        __syncthreads();
+        for (int r = 0; r < th; ++r) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (!((fg >> (4 * r + k)) & 1u)) continue;
+                const int x = c + k;
+                const uint32_t i = (uint32_t)(r * LT_W + x);
+                const bool left = x > 0 && (k > 0 ? ((fg >> (4 * r + k - 1)) & 1u) : par[i - 1] != LT_BG);
+                if (left) lds_union(par, i, i - 1);
+                if (r > 0) {
+                    if ((fg >> (4 * (r - 1) + k)) & 1u) lds_union(par, i, i - LT_W);
+                    if (a.conn == 8) {
+                        if (x > 0 && par[i - LT_W - 1] != LT_BG) lds_union(par, i, i - LT_W - 1);
+                        if (x + 1 < tw && par[i - LT_W + 1] != LT_BG) lds_union(par, i, i - LT_W + 1);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        for (int r = 0; r < th; ++r) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const uint32_t i = (uint32_t)(r * LT_W + c + k);
+                if ((fg >> (4 * r + k)) & 1u) par[i] = lds_find(par, i);
+            }
+        }
+        __syncthreads();
+        for (int r = 0; r < th; ++r) {
+            int32_t *row = a.lab + (int64_t)(y0 + r) * a.pitch_lab + x0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int x = c + k;
+                if (x >= tw) continue;
+                int32_t id = 0;
+                if ((fg >> (4 * r + k)) & 1u) {
+                    const uint32_t root = par[r * LT_W + x];
+                    const int ry = (int)(root / LT_W), rx = (int)(root % LT_W);
+                    id = (int32_t)((int64_t)(y0 + ry) * a.pitch_lab + x0 + rx + 1);
+                }
+                row[x] = id;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Phase 2: unions across tile borders.  One 64-lane workgroup per tile
+// (grid-stride).  The top row meets the row above (the tiles above), the left
+// column meets the column to the left; with 8-connectivity the diagonal
+// neighbours too.  Every pair of adjacent pixels in different tiles is met at
+// least once.
+__global__ __launch_bounds__(64) void label_merge(LabelArgs a) {
+    const int ln = lane_id();
+    const int n_tiles = a.tiles_x * ((a.h + LT_H - 1) / LT_H);
+    const int d = a.conn == 8 ? 1 : 0;
+    for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        const int y0 = (tile / a.tiles_x) * LT_H, x0 = (tile % a.tiles_x) * LT_W;
+        const int th = min(LT_H, a.h - y0), tw = min(LT_W, a.w - x0);
+        if (y0 > 0) {
+            for (int k = 0; k < 4; ++k) {
+                const int x = x0 + 4 * ln + k;
+                if (x >= x0 + tw) continue;
+                const int32_t self = a.lab[(int64_t)y0 * a.pitch_lab + x];
+                if (self == 0) continue;
+                for (int dx = -d; dx <= d; ++dx) {
+                    const int xx = x + dx;
+                    if (xx < 0 || xx >= a.w) continue;
+                    const int32_t other = a.lab[(int64_t)(y0 - 1) * a.pitch_lab + xx];
+                    if (other != 0) g_union(a.lab, self, other);
+                }
+            }
+        }
+        if (x0 > 0) {
+            for (int r = ln; r < th; r += LANES) {
+                const int y = y0 + r;
+                const int32_t self = a.lab[(int64_t)y * a.pitch_lab + x0];
+                if (self == 0) continue;
+                for (int dy = -d; dy <= d; ++dy) {
+                    const int yy = y + dy;
+                    if (yy < 0 || yy >= a.h) continue;
+                    const int32_t other = a.lab[(int64_t)yy * a.pitch_lab + x0 - 1];
+                    if (other != 0) g_union(a.lab, self, other);
+                }
+            }
+        }
+    }
+}
+
+// Clear a word array (a fill kernel rather than a memset node).
+__global__ void clear_words(uint32_t *p, uint32_t n) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0u;
+}
+
+// Phase 3: every foreground pixel takes its root's id; roots set their bit.
+// Grid-stride over (row, 256-column chunk), 64 lanes x 4 pixels.
+__global__ __launch_bounds__(64) void label_flatten(LabelArgs a) {
+    const int ln = lane_id();
+    const int chunks = (a.w + LT_W - 1) / LT_W;
+    const int64_t n = (int64_t)a.h * chunks;
+    for (int64_t q = blockIdx.x; q < n; q += gridDim.x) {
+        const int y = (int)(q / chunks), x0 = (int)(q % chunks) * LT_W;
+        int32_t *row = a.lab + (int64_t)y * a.pitch_lab;
+        for (int k = 0; k < 4; ++k) {
+            const int x = x0 + 4 * ln + k;
+            if (x >= a.w) continue;
+            const int32_t v = row[x];
+            if (v == 0) continue;
+            const int32_t root = g_find(a.lab, v);
+            row[x] = root;
+            const int32_t self = (int32_t)((int64_t)y * a.pitch_lab + x + 1);
+            if (root == self) {
+                const uint32_t bit = (uint32_t)(self - 1);
+                __hip_atomic_fetch_or(a.bits + (bit >> 5), 1u << (bit & 31u), __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+    }
+}
+
+// inclusive prefix sum over the 64 lanes of a wave
+__device__ __forceinline__ uint32_t wave_prefix(uint32_t v) {
+    const int ln = lane_id();
+#pragma unroll
+    for (int d = 1; d < LANES; d <<= 1) {
+        const uint32_t o = __shfl_up(v, (unsigned)d);
+        if (ln >= d) v += o;
+    }
+    return v;
+}
+
+// Phase 4a: roots per segment of RANK_SEG bitmap words.
+__global__ __launch_bounds__(64) void rank_segments(LabelArgs a) {
+    const int ln = lane_id();
+    for (uint32_t s = blockIdx.x; s < a.n_segs; s += gridDim.x) {
+        uint32_t sum = 0;
+        const uint32_t w0 = s * RANK_SEG + (uint32_t)ln * 16u;
+        for (uint32_t j = 0; j < 16u; ++j)
+            if (w0 + j < a.n_words) sum += (uint32_t)__popc(a.bits[w0 + j]);
+        const uint32_t tot = __shfl(wave_prefix(sum), LANES - 1);
+        if (ln == 0) a.seg_sum[s] = tot;
+    }
+}
+
+// Phase 4b: one wave turns the segment sums into exclusive offsets (in place)
+// and writes the number of components.
+__global__ __launch_bounds__(64) void rank_scan(LabelArgs a) {
+    const int ln = lane_id();
+    uint32_t carry = 0;
+    for (uint32_t s0 = 0; s0 < a.n_segs; s0 += LANES) {
+        const uint32_t s = s0 + (uint32_t)ln;
+        const uint32_t v = s < a.n_segs ? a.seg_sum[s] : 0u;
+        const uint32_t inc = wave_prefix(v);
+        if (s < a.n_segs) a.seg_sum[s] = carry + inc - v;
+        carry += __shfl(inc, LANES - 1);
+    }
+    if (ln == 0 && a.count) *a.count = (int32_t)carry;
+}
+
+// Phase 4c: roots before every bitmap word.
+__global__ __launch_bounds__(64) void rank_words(LabelArgs a) {
+    const int ln = lane_id();
+    for (uint32_t s = blockIdx.x; s < a.n_segs; s += gridDim.x) {
+        const uint32_t w0 = s * RANK_SEG + (uint32_t)ln * 16u;
+        uint32_t cnt[16];
+        uint32_t sum = 0;
+        for (uint32_t j = 0; j < 16u; ++j) {
+            cnt[j] = w0 + j < a.n_words ? (uint32_t)__popc(a.bits[w0 + j]) : 0u;
+            sum += cnt[j];
+        }
+        uint32_t run = a.seg_sum[s] + wave_prefix(sum) - sum;
+        for (uint32_t j = 0; j < 16u; ++j) {
+            if (w0 + j < a.n_words) a.word_off[w0 + j] = run;
+            run += cnt[j];
+        }
+    }
+}
+
+// Phase 5: final labels 1..n in raster order of the roots.
+__global__ __launch_bounds__(64) void label_final(LabelArgs a) {
+    const int ln = lane_id();
+    const int chunks = (a.w + LT_W - 1) / LT_W;
+    const int64_t n = (int64_t)a.h * chunks;
+    for (int64_t q = blockIdx.x; q < n; q += gridDim.x) {
+        const int y = (int)(q / chunks), x0 = (int)(q % chunks) * LT_W;
+        int32_t *row = a.lab + (int64_t)y * a.pitch_lab;
+        for (int k = 0; k < 4; ++k) {
+            const int x = x0 + 4 * ln + k;
+            if (x >= a.w) continue;
+            const int32_t v = row[x];
+            if (v == 0) continue;
+            const uint32_t r = (uint32_t)(v - 1);
+            const uint32_t below = a.bits[r >> 5] & ((1u << (r & 31u)) - 1u);
+            row[x] = (int32_t)(a.word_off[r >> 5] + (uint32_t)__popc(below) + 1u);
+        }
+    }
+}
+
+// ---- area filter (on a label plane made by the kernels above)
+
+struct AreaArgs {
+    const int32_t *lab;
+    int64_t pitch_lab;
+    uint32_t *area;         // pixel count per label (index 0 unused)
+    uint8_t *out;           // the image, overwritten with 255 / 0
+    int64_t pitch_out;
+    int32_t h, w;
+    int64_t min_area, max_area;
+};
+
+// Pixel counts per label: runs of equal labels inside a lane's 4 pixels are
+// added with one atomic each.
+__global__ __launch_bounds__(64) void area_count(AreaArgs a) {
+    const int ln = lane_id();
+    const int chunks = (a.w + LT_W - 1) / LT_W;
+    const int64_t n = (int64_t)a.h * chunks;
+    for (int64_t q = blockIdx.x; q < n; q += gridDim.x) {
+        const int y = (int)(q / chunks), x0 = (int)(q % chunks) * LT_W;
+        const int32_t *row = a.lab + (int64_t)y * a.pitch_lab;
+        int32_t cur = 0;
+        uint32_t run = 0;
+        for (int k = 0; k < 4; ++k) {
+            const int x = x0 + 4 * ln + k;
+            const int32_t v = x < a.w ? row[x] : 0;
+            if (v != cur) {
+                if (cur != 0) __hip_atomic_fetch_add(a.area + cur, run, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                cur = v;
+                run = 0;
+            }
+            run += 1;
+        }
+        if (cur != 0) __hip_atomic_fetch_add(a.area + cur, run, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+__global__ __launch_bounds__(64) void area_apply(AreaArgs a) {
+    const int ln = lane_id();
+    const int chunks = (a.w + LT_W - 1) / LT_W;
+    const int64_t n = (int64_t)a.h * chunks;
+    for (int64_t q = blockIdx.x; q < n; q += gridDim.x) {
+        const int y = (int)(q / chunks), x0 = (int)(q % chunks) * LT_W;
+        const int32_t *row = a.lab + (int64_t)y * a.pitch_lab;
+        uint8_t *orow = a.out + (int64_t)y * a.pitch_out;
+        for (int k = 0; k < 4; ++k) {
+            const int x = x0 + 4 * ln + k;
+            if (x >= a.w) continue;
+            const int32_t v = row[x];
+            const int64_t ar = v != 0 ? (int64_t)a.area[v] : -1;
+            orow[x] = (v != 0 && ar >= a.min_area && ar <= a.max_area) ? 255 : 0;
+        }
+    }
+}
+
+}  // namespace rk

@@ -28,6 +28,7 @@
 
 #include "../../include/recon.h"
 #include "kernels.hpp"
+#include "label.hpp"
 
 namespace {
 
@@ -832,6 +833,127 @@ int recon_regional_max(recon_ctx *ctx, recon_image *img, int conn, void *stream)
     int rc = check_task(t);
     if (rc) return rc;
     return run_tasks(ctx, &t, 1, (hipStream_t)stream, false);
+}
+
+// ---- connected-component labelling and the area filter
+
+// Scratch bytes of the labelling phases for an h x w image whose label plane
+// has `pitch_lab` elements per row: the root bitmap, per-word offsets and
+// per-segment sums.
+static void label_layout(int h, int w, int64_t pitch_lab, uint32_t &n_words, uint32_t &n_segs, size_t &bytes) {
+    const uint64_t nbits = (uint64_t)(h - 1) * (uint64_t)pitch_lab + (uint64_t)w;
+    n_words = (uint32_t)((nbits + 31) / 32);
+    n_segs = (n_words + rk::RANK_SEG - 1) / rk::RANK_SEG;
+    bytes = round_up((size_t)n_words * 4, 256) * 2 + round_up((size_t)n_segs * 4, 256);
+}
+
+static int check_label_args(const recon_image *img, int64_t pitch_lab, int conn) {
+    int rc = check_image(img, "image");
+    if (rc) return rc;
+    if (conn != 4 && conn != 8) return fail(RECON_EINVAL, "conn must be 4 or 8, got %d", conn);
+    if (pitch_lab < img->width)
+        return fail(RECON_EINVAL, "label pitch %lld < width %d", (long long)pitch_lab, img->width);
+    if ((uint64_t)img->height * (uint64_t)pitch_lab >= (uint64_t)INT32_MAX)
+        return fail(RECON_EINVAL, "height x label pitch must stay below 2^31 (node ids are int32)");
+    return RECON_OK;
+}
+
+// Enqueue the labelling phases: labels of `img` into `lab` (pitch_lab
+// elements per row); `scratch` holds label_layout's bytes.
+static int enqueue_label(const recon_image &img, int32_t *lab, int64_t pitch_lab, int conn, int32_t *count,
+                         uint8_t *scratch, hipStream_t s) {
+    rk::LabelArgs a{};
+    a.img = img.data;
+    a.pitch_img = img.pitch;
+    a.lab = lab;
+    a.pitch_lab = pitch_lab;
+    a.h = img.height;
+    a.w = img.width;
+    a.conn = conn;
+    a.tiles_x = (img.width + rk::LT_W - 1) / rk::LT_W;
+    size_t bytes = 0;
+    label_layout(img.height, img.width, pitch_lab, a.n_words, a.n_segs, bytes);
+    a.bits = (uint32_t *)scratch;
+    a.word_off = (uint32_t *)(scratch + round_up((size_t)a.n_words * 4, 256));
+    a.seg_sum = (uint32_t *)(scratch + 2 * round_up((size_t)a.n_words * 4, 256));
+    a.count = count;
+    const int64_t n_tiles = (int64_t)a.tiles_x * ((img.height + rk::LT_H - 1) / rk::LT_H);
+    const int64_t n_rows = (int64_t)img.height * a.tiles_x;
+    const int g_tiles = (int)std::min<int64_t>(n_tiles, 65535);
+    const int g_rows = (int)std::min<int64_t>(n_rows, 65535);
+    const int g_segs = (int)std::min<uint32_t>(a.n_segs, 65535u);
+    const int g_clear = (int)std::min<uint32_t>((a.n_words + 255) / 256, 4096u);
+    const size_t lds = (size_t)rk::LT_H * rk::LT_W * sizeof(uint32_t);
+    hipLaunchKernelGGL(rk::clear_words, dim3(g_clear), dim3(256), 0, s, a.bits, a.n_words);
+    hipLaunchKernelGGL(rk::label_local, dim3(g_tiles), dim3(64), lds, s, a);
+    hipLaunchKernelGGL(rk::label_merge, dim3(g_tiles), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(rk::label_flatten, dim3(g_rows), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(rk::rank_segments, dim3(g_segs), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(rk::rank_scan, dim3(1), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(rk::rank_words, dim3(g_segs), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(rk::label_final, dim3(g_rows), dim3(64), 0, s, a);
+    HIP_TRY(hipGetLastError());
+    return RECON_OK;
+}
+
+int recon_label(recon_ctx *ctx, const recon_image *img, int32_t *labels, int64_t label_pitch, int conn,
+                int32_t *count, void *stream) {
+    if (!ctx) return fail(RECON_EINVAL, "null context");
+    if (!labels) return fail(RECON_EINVAL, "null label plane");
+    int rc = check_label_args(img, label_pitch, conn);
+    if (rc) return rc;
+    rc = ensure_device(ctx);
+    if (rc) return rc;
+    uint32_t nw = 0, ns = 0;
+    size_t bytes = 0;
+    label_layout(img->height, img->width, label_pitch, nw, ns, bytes);
+    rc = ensure_capacity(ctx, 0, 0, bytes);
+    if (rc) return rc;
+    return enqueue_label(*img, labels, label_pitch, conn, count, ctx->d_scratch, (hipStream_t)stream);
+}
+
+int recon_area_threshold(recon_ctx *ctx, recon_image *img, int conn, int64_t min_area, int64_t max_area,
+                         void *stream) {
+    if (!ctx) return fail(RECON_EINVAL, "null context");
+    if (!img) return fail(RECON_EINVAL, "null image");
+    if (min_area < 0 || max_area < min_area)
+        return fail(RECON_EINVAL, "area bounds must satisfy 0 <= min_area <= max_area");
+    const int64_t pitch_lab = (int64_t)round_up((size_t)img->width, 64);
+    int rc = check_label_args(img, pitch_lab, conn);
+    if (rc) return rc;
+    rc = ensure_device(ctx);
+    if (rc) return rc;
+    uint32_t nw = 0, ns = 0;
+    size_t lbytes = 0;
+    label_layout(img->height, img->width, pitch_lab, nw, ns, lbytes);
+    const size_t plane = round_up((size_t)img->height * (size_t)pitch_lab * 4, 256);
+    const size_t n_area = (size_t)img->height * (size_t)img->width + 1;   // labels 1..n, n <= h * w
+    const size_t abytes = round_up(n_area * 4, 256);
+    rc = ensure_capacity(ctx, 0, 0, plane + abytes + lbytes);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    int32_t *lab = (int32_t *)ctx->d_scratch;
+    uint32_t *area = (uint32_t *)(ctx->d_scratch + plane);
+    rc = enqueue_label(*img, lab, pitch_lab, conn, nullptr, ctx->d_scratch + plane + abytes, s);
+    if (rc) return rc;
+    rk::AreaArgs a{};
+    a.lab = lab;
+    a.pitch_lab = pitch_lab;
+    a.area = area;
+    a.out = img->data;
+    a.pitch_out = img->pitch;
+    a.h = img->height;
+    a.w = img->width;
+    a.min_area = min_area;
+    a.max_area = max_area;
+    const int64_t n_rows = (int64_t)img->height * ((img->width + rk::LT_W - 1) / rk::LT_W);
+    const int g_rows = (int)std::min<int64_t>(n_rows, 65535);
+    hipLaunchKernelGGL(rk::clear_words, dim3((unsigned)std::min<size_t>((n_area + 255) / 256, 4096)), dim3(256), 0,
+                       s, area, (uint32_t)n_area);
+    hipLaunchKernelGGL(rk::area_count, dim3(g_rows), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(rk::area_apply, dim3(g_rows), dim3(64), 0, s, a);
+    HIP_TRY(hipGetLastError());
+    return RECON_OK;
 }
 
 int recon_batch(recon_ctx *ctx, const recon_task *tasks, int32_t n, void *stream) {

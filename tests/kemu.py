@@ -59,3 +59,22 @@ def run(exe, tasks, bh=32, qcap=2048, scan_rounds=2, n_waves=4, watchdog_s=20.0,
             op = os.path.join(d, "%d_out.bin" % k)
             outs.append(np.fromfile(op, dtype=np.uint8).reshape(shape) if os.path.exists(op) else None)
         return p.returncode, outs, p.stdout + p.stderr
+
+
+def run_label(exe, img, conn, min_area=0, max_area=1 << 40, n_waves=4, timeout=600):
+    """Labelling and area filter of one image on the emulated kernels.
+    Returns (returncode, labels int32, count, area-filtered uint8, log)."""
+    img = np.ascontiguousarray(img, dtype=np.uint8)
+    h, w = img.shape
+    with tempfile.TemporaryDirectory() as d:
+        ip, lp, ap = (os.path.join(d, s) for s in ("img.bin", "lab.bin", "area.bin"))
+        img.tofile(ip)
+        env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1", UBSAN_OPTIONS="print_stacktrace=1")
+        p = subprocess.run([exe, "label", str(conn), str(h), str(w), str(n_waves), str(min_area), str(max_area),
+                            ip, lp, ap], capture_output=True, text=True, timeout=timeout, env=env)
+        log = p.stdout + p.stderr
+        if p.returncode != 0 or not os.path.exists(lp):
+            return p.returncode, None, None, None, log
+        count = int(log.split("count")[1].split()[0])
+        return (p.returncode, np.fromfile(lp, np.int32).reshape(h, w), count,
+                np.fromfile(ap, np.uint8).reshape(h, w), log)

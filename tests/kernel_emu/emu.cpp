@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "../../paper_1209_3332_amd/csrc/kernels.hpp"
+#include "../../paper_1209_3332_amd/csrc/label.hpp"
 
 #if defined(__has_feature)
 #if __has_feature(address_sanitizer)
@@ -201,6 +202,94 @@ static bool run_wave(const std::function<void()> &body, size_t lds_size) {
 }
 
 }  // namespace kemu
+
+// ---------------------------------------------------------------------------
+// labelling driver: the phases of recon_label / recon_area_threshold in
+// order, each as a grid of emulated waves on concurrent threads.
+
+static int emu_label(const uint8_t *img_in, int h, int w, int conn, int n_waves, int32_t *labels_out,
+                     int32_t *count_out, int64_t min_area, int64_t max_area, uint8_t *area_out) {
+    using namespace rk;
+    // exact-size copies (the sanitizer bounds-checks every access); the label
+    // plane has a padded pitch so that pitched node ids are exercised
+    const int64_t pitch_img = w + 3, pitch_lab = w + 5;
+    std::vector<uint8_t> img((size_t)h * pitch_img, 0);
+    for (int y = 0; y < h; ++y) std::memcpy(&img[(size_t)y * pitch_img], img_in + (size_t)y * w, w);
+    int32_t *lab = (int32_t *)std::malloc((size_t)((h - 1) * pitch_lab + w) * sizeof(int32_t));
+    LabelArgs a{};
+    a.img = img.data() + 0;
+    a.pitch_img = pitch_img;
+    a.lab = lab;
+    a.pitch_lab = pitch_lab;
+    a.h = h;
+    a.w = w;
+    a.conn = conn;
+    a.tiles_x = (w + LT_W - 1) / LT_W;
+    const uint64_t nbits = (uint64_t)(h - 1) * pitch_lab + w;
+    a.n_words = (uint32_t)((nbits + 31) / 32);
+    a.n_segs = (a.n_words + RANK_SEG - 1) / RANK_SEG;
+    a.bits = (uint32_t *)std::malloc(a.n_words * 4);
+    a.word_off = (uint32_t *)std::malloc(a.n_words * 4);
+    a.seg_sum = (uint32_t *)std::malloc(a.n_segs * 4);
+    int32_t count = -1;
+    a.count = &count;
+    auto serial = [&](auto fn, uint32_t blocks, uint32_t threads) {
+        kemu::gridDim_.x = blocks;
+        kemu::blockDim_.x = threads;
+        for (uint32_t b = 0; b < blocks; ++b)
+            for (uint32_t t = 0; t < threads; ++t) {
+                kemu::blockIdx_.x = b;
+                kemu::threadIdx_.x = t;
+                fn();
+            }
+    };
+    std::atomic<int> bad{0};
+    auto waves = [&](int nw, size_t lds, const std::function<void()> &body) {
+        std::vector<std::thread> th;
+        for (int g = 0; g < nw; ++g)
+            th.emplace_back([&, g] {
+                kemu::blockIdx_.x = (uint32_t)g;
+                kemu::gridDim_.x = (uint32_t)nw;
+                kemu::blockDim_.x = 64;
+                if (!kemu::run_wave(body, lds)) bad++;
+            });
+        for (auto &t : th) t.join();
+    };
+    serial([&] { clear_words(a.bits, a.n_words); }, 2, 64);
+    waves(n_waves, (size_t)LT_H * LT_W * 4, [&] { label_local(a); });
+    waves(n_waves, 0, [&] { label_merge(a); });
+    waves(n_waves, 0, [&] { label_flatten(a); });
+    waves(n_waves, 0, [&] { rank_segments(a); });
+    waves(1, 0, [&] { rank_scan(a); });
+    waves(n_waves, 0, [&] { rank_words(a); });
+    waves(n_waves, 0, [&] { label_final(a); });
+    for (int y = 0; y < h; ++y) std::memcpy(labels_out + (size_t)y * w, lab + (size_t)y * pitch_lab, w * 4);
+    *count_out = count;
+    if (area_out) {
+        const size_t n_area = (size_t)h * w + 1;
+        uint32_t *area = (uint32_t *)std::malloc(n_area * 4);
+        AreaArgs b{};
+        b.lab = lab;
+        b.pitch_lab = pitch_lab;
+        b.area = area;
+        b.out = img.data();
+        b.pitch_out = pitch_img;
+        b.h = h;
+        b.w = w;
+        b.min_area = min_area;
+        b.max_area = max_area;
+        serial([&] { clear_words(area, (uint32_t)n_area); }, 2, 64);
+        waves(n_waves, 0, [&] { area_count(b); });
+        waves(n_waves, 0, [&] { area_apply(b); });
+        for (int y = 0; y < h; ++y) std::memcpy(area_out + (size_t)y * w, &img[(size_t)y * pitch_img], w);
+        std::free(area);
+    }
+    std::free(lab);
+    std::free(a.bits);
+    std::free(a.word_off);
+    std::free(a.seg_sum);
+    return bad ? -2 : 0;
+}
 
 // ---------------------------------------------------------------------------
 // driver (called through ctypes)
@@ -387,6 +476,27 @@ int emu_run(const EmuTask *tasks, int n, int bh, int qcap, int scan_rounds, int 
 //   "op conn hval h w image_path mask_path_or_- out_path" on stdin.
 #include <string>
 int main(int argc, char **argv) {
+    //   kemu label <conn> <h> <w> <waves> <min_area> <max_area> <image_path> <labels_out> <area_out>
+    if (argc == 11 && std::string(argv[1]) == "label") {
+        const int conn = std::atoi(argv[2]), h = std::atoi(argv[3]), w = std::atoi(argv[4]);
+        const int nw = std::atoi(argv[5]);
+        const int64_t lo = std::atoll(argv[6]), hi = std::atoll(argv[7]);
+        std::vector<uint8_t> img((size_t)h * w), area((size_t)h * w);
+        std::vector<int32_t> lab((size_t)h * w);
+        FILE *f = std::fopen(argv[8], "rb");
+        if (!f || std::fread(img.data(), 1, img.size(), f) != img.size()) return 4;
+        std::fclose(f);
+        int32_t count = -1;
+        const int rc = emu_label(img.data(), h, w, conn, nw, lab.data(), &count, lo, hi, area.data());
+        f = std::fopen(argv[9], "wb");
+        std::fwrite(lab.data(), 4, lab.size(), f);
+        std::fclose(f);
+        f = std::fopen(argv[10], "wb");
+        std::fwrite(area.data(), 1, area.size(), f);
+        std::fclose(f);
+        std::printf("rc %d count %d\n", rc, count);
+        return rc == 0 ? 0 : 1;
+    }
     if (argc < 7) return 2;
     const int bh = std::atoi(argv[1]), qcap = std::atoi(argv[2]), rounds = std::atoi(argv[3]);
     const int waves = std::atoi(argv[4]);

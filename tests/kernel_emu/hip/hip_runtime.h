@@ -27,6 +27,15 @@
 #define __hip_atomic_fetch_add(p, v, o, s) __atomic_fetch_add((p), (v), (o))
 #define __hip_atomic_fetch_sub(p, v, o, s) __atomic_fetch_sub((p), (v), (o))
 #define __hip_atomic_fetch_or(p, v, o, s) __atomic_fetch_or((p), (v), (o))
+// fetch-min: a compare-exchange loop on the host
+template <typename T>
+inline T kemu_fetch_min(T *p, T v) {
+    T cur = __atomic_load_n(p, __ATOMIC_SEQ_CST);
+    while (v < cur && !__atomic_compare_exchange_n(p, &cur, v, false, __ATOMIC_SEQ_CST, __ATOMIC_SEQ_CST)) {
+    }
+    return cur;
+}
+#define __hip_atomic_fetch_min(p, v, o, s) kemu_fetch_min((p), (v))
 #define __hip_atomic_exchange(p, v, o, s) __atomic_exchange_n((p), (v), (o))
 #define __hip_atomic_compare_exchange_strong(p, e, d, o1, o2, s) \
     __atomic_compare_exchange_n((p), (e), (d), false, (o1), (o2))
@@ -61,6 +70,7 @@ inline void __builtin_amdgcn_wave_barrier() { kemu::wave_sync(); }
 inline void __threadfence() { std::atomic_thread_fence(std::memory_order_seq_cst); }
 inline unsigned long long __ballot(int p) { return kemu::ballot(p != 0); }
 inline int __popcll(unsigned long long v) { return __builtin_popcountll(v); }
+inline int __popc(unsigned int v) { return __builtin_popcount(v); }
 inline uint64_t wall_clock64() { return kemu::wall_ticks(); }
 
 inline uint32_t __shfl(uint32_t v, int src) { return (uint32_t)kemu::exchange(v, src); }

@@ -141,3 +141,28 @@ def test_dense_pass_is_blockwise_reconstruction(emu_exe, oracle_mod):
             sl = np.s_[y0:y0 + 32, x0:x0 + 256]
             want[sl] = oracle_mod.recon_dilate(marker[sl], mask[sl], 8)
     assert np.array_equal(outs[0], want)
+
+
+@pytest.mark.parametrize("conn", [8, 4])
+def test_label_and_area_threshold(emu_exe, oracle_mod, conn):
+    """Connected-component labelling (tile-local union-find, merges across
+    tiles, rank relabelling) and the area filter, against the oracle: ragged
+    shapes spanning several 16 x 256 tiles, densities around the percolation
+    threshold, checkerboards, a spiral corridor crossing tiles, a nuclei crop."""
+    rng = np.random.default_rng(90 + conn)
+    imgs = [np.zeros((1, 1), np.uint8), np.full((3, 5), 7, np.uint8)]
+    for (h, w, p) in [(17, 300, 0.5), (40, 520, 0.62), (70, 260, 0.45), (33, 257, 0.9)]:
+        imgs.append(np.where(rng.random((h, w)) < p, 255, 0).astype(np.uint8))
+    yy, xx = np.mgrid[0:35, 0:300]
+    imgs.append(np.where((yy + xx) % 2 == 0, 255, 0).astype(np.uint8))
+    imgs.append(synth.spiral_tile(40, 520, "outer")[1])
+    _, _, binary = synth.config2_tile(seed=synth.seed_for(2, 25), size=96, n_gauss=2)
+    imgs.append(np.ascontiguousarray(np.concatenate([binary, binary[:, ::-1], binary], 1)))
+    for i, img in enumerate(imgs):
+        rc, lab, count, area, log = kemu.run_label(emu_exe, img, conn, min_area=3, max_area=40, n_waves=3)
+        assert rc == 0, log[-2000:]
+        assert "ERROR: AddressSanitizer" not in log and "runtime error" not in log, log[-2000:]
+        want, n = oracle_mod.label(img, conn)
+        assert count == n, (i, count, n)
+        assert np.array_equal(lab, want), "image %d: %d labels differ" % (i, int((lab != want).sum()))
+        assert np.array_equal(area, oracle_mod.area_threshold(img, 3, 40, conn)), "image %d area filter" % i
