@@ -10,11 +10,13 @@
 // whose pixel count lies in [min_area, max_area] and clears the rest.
 //
 // Method (union-find on the label plane itself, then a rank relabelling):
-//   label_local     one wave per 16 x 256 tile: union-find in LDS over the
-//                   tile (link the larger root under the smaller with an LDS
-//                   atomic min), path compression, then every foreground
-//                   pixel's node id is written: the pitched index + 1 of its
-//                   tile root (0 on the background);
+//   label_local     one wave per 16 x 256 tile: each row's runs of
+//                   foreground pixels become depth-one trees, then one
+//                   union-find link (LDS atomic min: the larger root under
+//                   the smaller) per pair of touching runs of adjacent rows,
+//                   path compression, then every foreground pixel's node id
+//                   is written: the pitched index + 1 of its tile root (0 on
+//                   the background);
 //   label_merge     one wave per tile: the tile's top row and left column
 //                   against the neighbouring tiles' pixels, as a global
 //                   union-find with agent-scope atomic min on the label plane
@@ -45,13 +47,44 @@ struct LabelArgs {
     int32_t h, w;
     int32_t conn;
     int32_t tiles_x;        // tiles per row of tiles
-    uint32_t *bits;         // root bitmap over pitched indices
+    uint32_t *bits;         // root bitmap over pitched indices (null: no ranks wanted)
     uint32_t *word_off;     // roots before each bitmap word
     uint32_t *seg_sum;      // roots per segment of RANK_SEG words
     uint32_t n_words;
     uint32_t n_segs;
     int32_t *count;         // receives the number of components (may be null)
+    int32_t lab_vec;        // 1: the label plane allows 16-byte accesses (base and row pitch)
 };
+
+typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+
+// 4 label elements at columns x..x+3 of a row (x a multiple of 4); elements
+// at or past w read 0 and are not written.
+__device__ __forceinline__ void lab_load4(const int32_t *row, int x, int w, int vec, int32_t v[4]) {
+    if (vec && x + 4 <= w) {
+        const i32x4 q = *(const RK_GLOBAL i32x4 *)(row + x);
+        v[0] = q.x;
+        v[1] = q.y;
+        v[2] = q.z;
+        v[3] = q.w;
+        return;
+    }
+    for (int k = 0; k < 4; ++k) v[k] = x + k < w ? ((const RK_GLOBAL int32_t *)row)[x + k] : 0;
+}
+
+__device__ __forceinline__ void lab_store4(int32_t *row, int x, int w, int vec, const int32_t v[4]) {
+    if (vec && x + 4 <= w) {
+        i32x4 q;
+        q.x = v[0];
+        q.y = v[1];
+        q.z = v[2];
+        q.w = v[3];
+        *(RK_GLOBAL i32x4 *)(row + x) = q;
+        return;
+    }
+    for (int k = 0; k < 4; ++k)
+        if (x + k < w) ((RK_GLOBAL int32_t *)row)[x + k] = v[k];
+}
 
 // ---- tile-local union-find in LDS (indices within the tile)
 
@@ -112,71 +145,128 @@ __device__ __forceinline__ int img_aligned(const LabelArgs &a) {
     return (((uintptr_t)a.img | (uintptr_t)a.pitch_img) & 3u) == 0;
 }
 
+// inclusive prefix maximum over the 64 lanes of a wave
+__device__ __forceinline__ int wave_prefix_max(int v) {
+    const int ln = lane_id();
+#pragma unroll
+    for (int d = 1; d < LANES; d <<= 1) {
+        const int o = (int)__shfl_up((uint32_t)v, (unsigned)d);
+        if (ln >= d) v = max(v, o);
+    }
+    return v;
+}
+
 // Phase 1: tile-local labelling.  Grid: one 64-lane workgroup per tile
-// (grid-stride); dynamic LDS: LT_H * LT_W * 4 bytes.
+// (grid-stride); dynamic LDS: LT_H * LT_W * 4 bytes.  Lane l holds columns
+// 4l..4l+3 of every row.
+//   a. runs: every foreground pixel's parent is the first pixel of its run of
+//      foreground pixels in the row (one prefix maximum over the lanes of the
+//      last background column), so a run is a tree of depth one;
+//   b. unions between each run and every run of the row above that touches
+//      it, issued once per pair of runs: by the pixel under (4-conn) or
+//      diagonally under (8-conn) the upper run's first pixel inside the
+//      window the run can reach;
+//   c. path compression; d. node ids out.
 __global__ __launch_bounds__(64) void label_local(LabelArgs a) {
     RK_LDS uint32_t *par = (RK_LDS uint32_t *)dyn_lds();
     const int ln = lane_id();
     const int n_tiles = a.tiles_x * ((a.h + LT_H - 1) / LT_H);
     const int aligned = img_aligned(a);
+    const int c = 4 * ln;
     for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         const int y0 = (tile / a.tiles_x) * LT_H, x0 = (tile % a.tiles_x) * LT_W;
         const int th = min(LT_H, a.h - y0), tw = min(LT_W, a.w - x0);
-        const int c = 4 * ln;
         const int valid = min(4, tw - c);
         uint64_t fg = 0;   // bit 4r+k: pixel (r, c+k) is foreground
+        uint32_t rows[LT_H];   // all loads in flight together
+#pragma unroll
+        for (int r = 0; r < LT_H; ++r)
+            rows[r] = r < th ? gload4(a.img + (int64_t)(y0 + r) * a.pitch_img, x0 + c, valid, aligned) : 0u;
 #pragma unroll
         for (int r = 0; r < LT_H; ++r) {
-            const uint32_t v = r < th ? gload4(a.img + (int64_t)(y0 + r) * a.pitch_img, x0 + c, valid, aligned) : 0u;
+            const uint32_t v = rows[r];
+            int lb = -1;          // last background column so far in this lane
+            int lbk[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 const bool f = ((v >> (8 * k)) & 0xffu) != 0u;
-                const uint32_t i = (uint32_t)(r * LT_W + c + k);
-                par[i] = f ? i : LT_BG;
                 fg |= (uint64_t)(f ? 1u : 0u) << (4 * r + k);
+                if (!f) lb = c + k;
+                lbk[k] = lb;
             }
-        }
-        __syncthreads();
-        for (int r = 0; r < th; ++r) {
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                if (!((fg >> (4 * r + k)) & 1u)) continue;
-                const int x = c + k;
-                const uint32_t i = (uint32_t)(r * LT_W + x);
-                const bool left = x > 0 && (k > 0 ? ((fg >> (4 * r + k - 1)) & 1u) : par[i - 1] != LT_BG);
-                if (left) lds_union(par, i, i - 1);
-                if (r > 0) {
-                    if ((fg >> (4 * (r - 1) + k)) & 1u) lds_union(par, i, i - LT_W);
-                    if (a.conn == 8) {
-                        if (x > 0 && par[i - LT_W - 1] != LT_BG) lds_union(par, i, i - LT_W - 1);
-                        if (x + 1 < tw && par[i - LT_W + 1] != LT_BG) lds_union(par, i, i - LT_W + 1);
-                    }
-                }
-            }
-        }
-        __syncthreads();
-        for (int r = 0; r < th; ++r) {
+            const int incl = wave_prefix_max(lb);
+            int excl = (int)__shfl_up((uint32_t)incl, 1u);
+            if (ln == 0) excl = -1;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 const uint32_t i = (uint32_t)(r * LT_W + c + k);
-                if ((fg >> (4 * r + k)) & 1u) par[i] = lds_find(par, i);
+                const bool f = (fg >> (4 * r + k)) & 1u;
+                par[i] = f ? (uint32_t)(r * LT_W + max(excl, lbk[k]) + 1) : LT_BG;
+            }
+        }
+        __syncthreads();
+        // the neighbouring lanes' foreground bits: 6-bit windows per row with
+        // bit 0 = column c-1, bits 1..4 = columns c..c+3, bit 5 = column c+4
+        // (no neighbour inside the tile: background; the tile borders are
+        // joined by label_merge)
+        const uint64_t fl = ((uint64_t)__shfl_up((uint32_t)(fg >> 32), 1u) << 32) | __shfl_up((uint32_t)fg, 1u);
+        const uint64_t fr = ((uint64_t)__shfl_down((uint32_t)(fg >> 32), 1u) << 32) | __shfl_down((uint32_t)fg, 1u);
+        auto window = [&](int r) -> uint32_t {
+            const uint32_t own = (uint32_t)(fg >> (4 * r)) & 15u;
+            const uint32_t l = ln > 0 ? (uint32_t)(fl >> (4 * r + 3)) & 1u : 0u;
+            const uint32_t rt = ln < LANES - 1 ? (uint32_t)(fr >> (4 * r)) & 1u : 0u;
+            return l | (own << 1) | (rt << 5);
+        };
+        uint32_t wup = window(0);
+        for (int r = 1; r < th; ++r) {
+            const uint32_t wr = window(r);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (!((wr >> (k + 1)) & 1u)) continue;
+                const uint32_t i = (uint32_t)(r * LT_W + c + k);
+                const uint32_t u = i - LT_W;   // the pixel above
+                const bool left = (wr >> k) & 1u;
+                const bool up_left = (wup >> k) & 1u;
+                const bool up = (wup >> (k + 1)) & 1u;
+                const bool up_right = (wup >> (k + 2)) & 1u;
+                if (a.conn == 8) {
+                    if (!left) {                                   // the run's first pixel
+                        if (up_left) lds_union(par, i, u - 1);
+                        else if (up) lds_union(par, i, u);
+                    }
+                    if (!up && up_right) lds_union(par, i, u + 1);
+                } else if (up && (!left || !up_left)) {
+                    lds_union(par, i, u);
+                }
+            }
+            wup = wr;
+        }
+        __syncthreads();
+        // path compression of the run starts (every other pixel's parent is its
+        // run's start, so afterwards its root is two steps away)
+        for (int r = 0; r < th; ++r) {
+            const uint32_t wr = window(r);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (((wr >> (k + 1)) & 1u) && !((wr >> k) & 1u)) {
+                    const uint32_t i = (uint32_t)(r * LT_W + c + k);
+                    par[i] = lds_find(par, i);
+                }
             }
         }
         __syncthreads();
         for (int r = 0; r < th; ++r) {
-            int32_t *row = a.lab + (int64_t)(y0 + r) * a.pitch_lab + x0;
+            int32_t ids[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                const int x = c + k;
-                if (x >= tw) continue;
-                int32_t id = 0;
+                ids[k] = 0;
                 if ((fg >> (4 * r + k)) & 1u) {
-                    const uint32_t root = par[r * LT_W + x];
+                    const uint32_t root = par[par[r * LT_W + c + k]];
                     const int ry = (int)(root / LT_W), rx = (int)(root % LT_W);
-                    id = (int32_t)((int64_t)(y0 + ry) * a.pitch_lab + x0 + rx + 1);
+                    ids[k] = (int32_t)((int64_t)(y0 + ry) * a.pitch_lab + x0 + rx + 1);
                 }
-                row[x] = id;
             }
+            lab_store4(a.lab + (int64_t)(y0 + r) * a.pitch_lab, x0 + c, a.w, a.lab_vec, ids);
         }
         __syncthreads();
     }
@@ -238,20 +328,23 @@ __global__ __launch_bounds__(64) void label_flatten(LabelArgs a) {
     for (int64_t q = blockIdx.x; q < n; q += gridDim.x) {
         const int y = (int)(q / chunks), x0 = (int)(q % chunks) * LT_W;
         int32_t *row = a.lab + (int64_t)y * a.pitch_lab;
+        const int xl = x0 + 4 * ln;
+        int32_t v[4];
+        lab_load4(row, xl, a.w, a.lab_vec, v);
+        bool any = false;
         for (int k = 0; k < 4; ++k) {
-            const int x = x0 + 4 * ln + k;
-            if (x >= a.w) continue;
-            const int32_t v = row[x];
-            if (v == 0) continue;
-            const int32_t root = g_find(a.lab, v);
-            row[x] = root;
-            const int32_t self = (int32_t)((int64_t)y * a.pitch_lab + x + 1);
-            if (root == self) {
+            if (v[k] == 0) continue;
+            const int32_t root = g_find(a.lab, v[k]);
+            any |= root != v[k];
+            v[k] = root;
+            const int32_t self = (int32_t)((int64_t)y * a.pitch_lab + xl + k + 1);
+            if (root == self && a.bits) {
                 const uint32_t bit = (uint32_t)(self - 1);
                 __hip_atomic_fetch_or(a.bits + (bit >> 5), 1u << (bit & 31u), __ATOMIC_RELAXED,
                                       __HIP_MEMORY_SCOPE_AGENT);
             }
         }
+        if (any) lab_store4(row, xl, a.w, a.lab_vec, v);
     }
 }
 
@@ -321,31 +414,36 @@ __global__ __launch_bounds__(64) void label_final(LabelArgs a) {
     for (int64_t q = blockIdx.x; q < n; q += gridDim.x) {
         const int y = (int)(q / chunks), x0 = (int)(q % chunks) * LT_W;
         int32_t *row = a.lab + (int64_t)y * a.pitch_lab;
+        const int xl = x0 + 4 * ln;
+        int32_t v[4];
+        lab_load4(row, xl, a.w, a.lab_vec, v);
+        if ((v[0] | v[1] | v[2] | v[3]) == 0) continue;
         for (int k = 0; k < 4; ++k) {
-            const int x = x0 + 4 * ln + k;
-            if (x >= a.w) continue;
-            const int32_t v = row[x];
-            if (v == 0) continue;
-            const uint32_t r = (uint32_t)(v - 1);
+            if (v[k] == 0) continue;
+            const uint32_t r = (uint32_t)(v[k] - 1);
             const uint32_t below = a.bits[r >> 5] & ((1u << (r & 31u)) - 1u);
-            row[x] = (int32_t)(a.word_off[r >> 5] + (uint32_t)__popc(below) + 1u);
+            v[k] = (int32_t)(a.word_off[r >> 5] + (uint32_t)__popc(below) + 1u);
         }
+        lab_store4(row, xl, a.w, a.lab_vec, v);
     }
 }
 
-// ---- area filter (on a label plane made by the kernels above)
+// ---- area filter (on a flattened label plane: every foreground pixel holds
+// its component's root id, so no rank relabelling is needed)
 
 struct AreaArgs {
     const int32_t *lab;
     int64_t pitch_lab;
-    uint32_t *area;         // pixel count per label (index 0 unused)
+    int32_t lab_vec;
+    uint32_t *area;         // pixel count per root id (index 0 unused)
     uint8_t *out;           // the image, overwritten with 255 / 0
     int64_t pitch_out;
+    int32_t out_aligned;    // 1: the image allows dword accesses
     int32_t h, w;
     int64_t min_area, max_area;
 };
 
-// Pixel counts per label: runs of equal labels inside a lane's 4 pixels are
+// Pixel counts per root id: runs of equal ids inside a lane's 4 pixels are
 // added with one atomic each.
 __global__ __launch_bounds__(64) void area_count(AreaArgs a) {
     const int ln = lane_id();
@@ -354,11 +452,12 @@ __global__ __launch_bounds__(64) void area_count(AreaArgs a) {
     for (int64_t q = blockIdx.x; q < n; q += gridDim.x) {
         const int y = (int)(q / chunks), x0 = (int)(q % chunks) * LT_W;
         const int32_t *row = a.lab + (int64_t)y * a.pitch_lab;
+        int32_t vv[4];
+        lab_load4(row, x0 + 4 * ln, a.w, a.lab_vec, vv);
         int32_t cur = 0;
         uint32_t run = 0;
         for (int k = 0; k < 4; ++k) {
-            const int x = x0 + 4 * ln + k;
-            const int32_t v = x < a.w ? row[x] : 0;
+            const int32_t v = vv[k];
             if (v != cur) {
                 if (cur != 0) __hip_atomic_fetch_add(a.area + cur, run, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 cur = v;
@@ -378,13 +477,16 @@ __global__ __launch_bounds__(64) void area_apply(AreaArgs a) {
         const int y = (int)(q / chunks), x0 = (int)(q % chunks) * LT_W;
         const int32_t *row = a.lab + (int64_t)y * a.pitch_lab;
         uint8_t *orow = a.out + (int64_t)y * a.pitch_out;
+        const int xl = x0 + 4 * ln;
+        int32_t vv[4];
+        lab_load4(row, xl, a.w, a.lab_vec, vv);
+        uint32_t out = 0;
         for (int k = 0; k < 4; ++k) {
-            const int x = x0 + 4 * ln + k;
-            if (x >= a.w) continue;
-            const int32_t v = row[x];
+            const int32_t v = vv[k];
             const int64_t ar = v != 0 ? (int64_t)a.area[v] : -1;
-            orow[x] = (v != 0 && ar >= a.min_area && ar <= a.max_area) ? 255 : 0;
+            if (v != 0 && ar >= a.min_area && ar <= a.max_area) out |= 0xffu << (8 * k);
         }
+        gstore4(orow, xl, min(4, a.w - xl), a.out_aligned, out);
     }
 }
 

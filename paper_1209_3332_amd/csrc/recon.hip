@@ -859,9 +859,11 @@ static int check_label_args(const recon_image *img, int64_t pitch_lab, int conn)
 }
 
 // Enqueue the labelling phases: labels of `img` into `lab` (pitch_lab
-// elements per row); `scratch` holds label_layout's bytes.
+// elements per row); `scratch` holds label_layout's bytes.  With ranks =
+// false the phases stop after flattening: every foreground pixel then holds
+// its component's root id (the pitched index + 1 of its raster-first pixel).
 static int enqueue_label(const recon_image &img, int32_t *lab, int64_t pitch_lab, int conn, int32_t *count,
-                         uint8_t *scratch, hipStream_t s) {
+                         uint8_t *scratch, bool ranks, hipStream_t s) {
     rk::LabelArgs a{};
     a.img = img.data;
     a.pitch_img = img.pitch;
@@ -873,10 +875,11 @@ static int enqueue_label(const recon_image &img, int32_t *lab, int64_t pitch_lab
     a.tiles_x = (img.width + rk::LT_W - 1) / rk::LT_W;
     size_t bytes = 0;
     label_layout(img.height, img.width, pitch_lab, a.n_words, a.n_segs, bytes);
-    a.bits = (uint32_t *)scratch;
+    a.bits = ranks ? (uint32_t *)scratch : nullptr;
     a.word_off = (uint32_t *)(scratch + round_up((size_t)a.n_words * 4, 256));
     a.seg_sum = (uint32_t *)(scratch + 2 * round_up((size_t)a.n_words * 4, 256));
     a.count = count;
+    a.lab_vec = (((uintptr_t)lab | (uintptr_t)(pitch_lab * 4)) & 15u) == 0 ? 1 : 0;
     const int64_t n_tiles = (int64_t)a.tiles_x * ((img.height + rk::LT_H - 1) / rk::LT_H);
     const int64_t n_rows = (int64_t)img.height * a.tiles_x;
     const int g_tiles = (int)std::min<int64_t>(n_tiles, 65535);
@@ -884,10 +887,14 @@ static int enqueue_label(const recon_image &img, int32_t *lab, int64_t pitch_lab
     const int g_segs = (int)std::min<uint32_t>(a.n_segs, 65535u);
     const int g_clear = (int)std::min<uint32_t>((a.n_words + 255) / 256, 4096u);
     const size_t lds = (size_t)rk::LT_H * rk::LT_W * sizeof(uint32_t);
-    hipLaunchKernelGGL(rk::clear_words, dim3(g_clear), dim3(256), 0, s, a.bits, a.n_words);
+    if (ranks) hipLaunchKernelGGL(rk::clear_words, dim3(g_clear), dim3(256), 0, s, a.bits, a.n_words);
     hipLaunchKernelGGL(rk::label_local, dim3(g_tiles), dim3(64), lds, s, a);
     hipLaunchKernelGGL(rk::label_merge, dim3(g_tiles), dim3(64), 0, s, a);
     hipLaunchKernelGGL(rk::label_flatten, dim3(g_rows), dim3(64), 0, s, a);
+    if (!ranks) {
+        HIP_TRY(hipGetLastError());
+        return RECON_OK;
+    }
     hipLaunchKernelGGL(rk::rank_segments, dim3(g_segs), dim3(64), 0, s, a);
     hipLaunchKernelGGL(rk::rank_scan, dim3(1), dim3(64), 0, s, a);
     hipLaunchKernelGGL(rk::rank_words, dim3(g_segs), dim3(64), 0, s, a);
@@ -909,7 +916,7 @@ int recon_label(recon_ctx *ctx, const recon_image *img, int32_t *labels, int64_t
     label_layout(img->height, img->width, label_pitch, nw, ns, bytes);
     rc = ensure_capacity(ctx, 0, 0, bytes);
     if (rc) return rc;
-    return enqueue_label(*img, labels, label_pitch, conn, count, ctx->d_scratch, (hipStream_t)stream);
+    return enqueue_label(*img, labels, label_pitch, conn, count, ctx->d_scratch, true, (hipStream_t)stream);
 }
 
 int recon_area_threshold(recon_ctx *ctx, recon_image *img, int conn, int64_t min_area, int64_t max_area,
@@ -923,22 +930,23 @@ int recon_area_threshold(recon_ctx *ctx, recon_image *img, int conn, int64_t min
     if (rc) return rc;
     rc = ensure_device(ctx);
     if (rc) return rc;
-    uint32_t nw = 0, ns = 0;
-    size_t lbytes = 0;
-    label_layout(img->height, img->width, pitch_lab, nw, ns, lbytes);
+    // the label plane holds root ids (pitched index + 1 of each component's
+    // first pixel), which index the area counts directly: no ranks needed
     const size_t plane = round_up((size_t)img->height * (size_t)pitch_lab * 4, 256);
-    const size_t n_area = (size_t)img->height * (size_t)img->width + 1;   // labels 1..n, n <= h * w
+    const size_t n_area = (size_t)img->height * (size_t)pitch_lab + 1;
     const size_t abytes = round_up(n_area * 4, 256);
-    rc = ensure_capacity(ctx, 0, 0, plane + abytes + lbytes);
+    rc = ensure_capacity(ctx, 0, 0, plane + abytes);
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
     int32_t *lab = (int32_t *)ctx->d_scratch;
     uint32_t *area = (uint32_t *)(ctx->d_scratch + plane);
-    rc = enqueue_label(*img, lab, pitch_lab, conn, nullptr, ctx->d_scratch + plane + abytes, s);
+    rc = enqueue_label(*img, lab, pitch_lab, conn, nullptr, nullptr, false, s);
     if (rc) return rc;
     rk::AreaArgs a{};
     a.lab = lab;
     a.pitch_lab = pitch_lab;
+    a.lab_vec = (((uintptr_t)lab | (uintptr_t)(pitch_lab * 4)) & 15u) == 0 ? 1 : 0;
+    a.out_aligned = aligned4(img->data, img->pitch) ? 1 : 0;
     a.area = area;
     a.out = img->data;
     a.pitch_out = img->pitch;

@@ -212,7 +212,7 @@ static int emu_label(const uint8_t *img_in, int h, int w, int conn, int n_waves,
     using namespace rk;
     // exact-size copies (the sanitizer bounds-checks every access); the label
     // plane has a padded pitch so that pitched node ids are exercised
-    const int64_t pitch_img = w + 3, pitch_lab = w + 5;
+    const int64_t pitch_img = w + 3, pitch_lab = (w + 3) / 4 * 4 + 4;   // 16-byte rows: vector path
     std::vector<uint8_t> img((size_t)h * pitch_img, 0);
     for (int y = 0; y < h; ++y) std::memcpy(&img[(size_t)y * pitch_img], img_in + (size_t)y * w, w);
     int32_t *lab = (int32_t *)std::malloc((size_t)((h - 1) * pitch_lab + w) * sizeof(int32_t));
@@ -233,6 +233,7 @@ static int emu_label(const uint8_t *img_in, int h, int w, int conn, int n_waves,
     a.seg_sum = (uint32_t *)std::malloc(a.n_segs * 4);
     int32_t count = -1;
     a.count = &count;
+    a.lab_vec = (((uintptr_t)lab | (uintptr_t)(pitch_lab * 4)) & 15u) == 0 ? 1 : 0;
     auto serial = [&](auto fn, uint32_t blocks, uint32_t threads) {
         kemu::gridDim_.x = blocks;
         kemu::blockDim_.x = threads;
@@ -259,6 +260,8 @@ static int emu_label(const uint8_t *img_in, int h, int w, int conn, int n_waves,
     waves(n_waves, (size_t)LT_H * LT_W * 4, [&] { label_local(a); });
     waves(n_waves, 0, [&] { label_merge(a); });
     waves(n_waves, 0, [&] { label_flatten(a); });
+    std::vector<int32_t> roots((size_t)((h - 1) * pitch_lab + w));   // the flattened plane (root ids)
+    std::memcpy(roots.data(), lab, roots.size() * 4);
     waves(n_waves, 0, [&] { rank_segments(a); });
     waves(1, 0, [&] { rank_scan(a); });
     waves(n_waves, 0, [&] { rank_words(a); });
@@ -266,11 +269,15 @@ static int emu_label(const uint8_t *img_in, int h, int w, int conn, int n_waves,
     for (int y = 0; y < h; ++y) std::memcpy(labels_out + (size_t)y * w, lab + (size_t)y * pitch_lab, w * 4);
     *count_out = count;
     if (area_out) {
-        const size_t n_area = (size_t)h * w + 1;
+        // as the library does: counts per root id on the flattened plane
+        std::memcpy(lab, roots.data(), roots.size() * 4);
+        const size_t n_area = (size_t)h * pitch_lab + 1;
         uint32_t *area = (uint32_t *)std::malloc(n_area * 4);
         AreaArgs b{};
         b.lab = lab;
         b.pitch_lab = pitch_lab;
+        b.lab_vec = a.lab_vec;
+        b.out_aligned = (((uintptr_t)img.data() | (uintptr_t)pitch_img) & 3u) == 0 ? 1 : 0;
         b.area = area;
         b.out = img.data();
         b.pitch_out = pitch_img;
