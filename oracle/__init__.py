@@ -1,14 +1,15 @@
 """CPU oracle for grayscale reconstruction by dilation and fill-holes, the
 operations built on it (erosion, h-dome, regional maxima), and connected-
-component labelling with the area filter.
+component labelling with the area filter, and the exact distance transform
+with the Pre-Watershed markers.
 
 TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by ``__graft_entry__.smoke()``
 and by the ``cpu_baseline`` leg of ``bench.py``.  The product library never
 imports, links or runs anything in this directory.
 
-The arithmetic lives in ``recon_oracle.c`` and ``label_oracle.c`` (plain C,
-built with gcc); this module only compiles them and marshals numpy arrays
-through ctypes.  See those files' headers for the definitions followed (the
+The arithmetic lives in ``recon_oracle.c``, ``label_oracle.c`` and
+``distance_oracle.c`` (plain C, built with gcc); this module only compiles
+them and marshals numpy arrays through ctypes.  See those files' headers for the definitions followed (the
 Table 1 operations of Sec. V-A) and for the sequential algorithms.
 """
 from __future__ import annotations
@@ -20,7 +21,8 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRCS = [os.path.join(_HERE, "recon_oracle.c"), os.path.join(_HERE, "label_oracle.c")]
+_SRCS = [os.path.join(_HERE, "recon_oracle.c"), os.path.join(_HERE, "label_oracle.c"),
+         os.path.join(_HERE, "distance_oracle.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -58,6 +60,11 @@ def _load():
         lib.oracle_label.restype = i64
         lib.oracle_area_threshold.argtypes = [u8p, u8p, i64, i64, ctypes.c_int, i64, i64]
         lib.oracle_area_threshold.restype = i64
+        for name in ("oracle_distance2", "oracle_distance8"):
+            getattr(lib, name).argtypes = [u8p, u8p, i64, i64]
+            getattr(lib, name).restype = ctypes.c_int
+        lib.oracle_pre_watershed.argtypes = [u8p, u8p, i64, i64, ctypes.c_int]
+        lib.oracle_pre_watershed.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -170,6 +177,40 @@ def area_threshold(img, min_area: int, max_area: int, conn: int = 8) -> np.ndarr
                                       int(min_area), int(max_area))
     if n < 0:
         raise ValueError("oracle_area_threshold failed")
+    return out
+
+
+def distance2(img) -> np.ndarray:
+    """Squared Euclidean distance (int32) of every pixel to the nearest 0 pixel
+    (2^31 - 1 if there is none)."""
+    img = _u8(img)
+    if img.ndim != 2:
+        raise ValueError("image must be 2-D")
+    out = np.empty(img.shape, np.int32)
+    if _load().oracle_distance2(img.ctypes.data, out.ctypes.data, img.shape[0], img.shape[1]) != 0:
+        raise ValueError("oracle_distance2 failed")
+    return out
+
+
+def distance8(img) -> np.ndarray:
+    """min(floor(sqrt(distance2)), 255) as uint8."""
+    img = _u8(img)
+    if img.ndim != 2:
+        raise ValueError("image must be 2-D")
+    out = np.empty_like(img)
+    if _load().oracle_distance8(img.ctypes.data, out.ctypes.data, img.shape[0], img.shape[1]) != 0:
+        raise ValueError("oracle_distance8 failed")
+    return out
+
+
+def pre_watershed(img, conn: int = 8) -> np.ndarray:
+    """Pre-Watershed markers: 255 on the regional maxima of distance8(img), else 0."""
+    img = _u8(img)
+    if img.ndim != 2:
+        raise ValueError("image must be 2-D")
+    out = np.empty_like(img)
+    if _load().oracle_pre_watershed(img.ctypes.data, out.ctypes.data, img.shape[0], img.shape[1], int(conn)) != 0:
+        raise ValueError("oracle_pre_watershed failed")
     return out
 
 
