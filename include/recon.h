@@ -41,6 +41,12 @@
  * pixel (0 on the background), and the filter keeping the components whose
  * pixel count lies in [min_area, max_area].
  *
+ * Pre-Watershed (Table 1: reconstruction and a distance transformation) is
+ * provided as the exact Euclidean distance transform -- dist2(p) = min over
+ * the 0 pixels q of |p - q|^2, pixels outside the image not background,
+ * 2^31 - 1 without any 0 pixel -- and the markers it feeds to the watershed:
+ * the regional maxima of D8 = min(floor(sqrt(dist2)), 255).
+ *
  * Conventions
  * -----------
  * * Images are single-channel uint8, row-major, `pitch` bytes between rows
@@ -211,6 +217,19 @@ int recon_label(recon_ctx *ctx, const recon_image *img, int32_t *labels, int64_t
  * Enqueued on `stream`. */
 int recon_area_threshold(recon_ctx *ctx, recon_image *img, int conn, int64_t min_area, int64_t max_area,
                          void *stream);
+
+/* Exact squared Euclidean distance transform of `img`: dist2[y * dist_pitch
+ * + x] <- the squared distance from (y, x) to the nearest 0 pixel of the image
+ * (0 on 0 pixels; 2^31 - 1 if the image has no 0 pixel).  `dist2` is a DEVICE
+ * int32 plane (dist_pitch >= width elements per row) owned by the caller;
+ * height and width at most 16384.  Enqueued on `stream`. */
+int recon_distance(recon_ctx *ctx, const recon_image *img, int32_t *dist2, int64_t dist_pitch, void *stream);
+
+/* Pre-Watershed markers of `img`, in place: 255 on the regional maxima
+ * (connectivity conn) of D8 = min(floor(sqrt(dist2)), 255), 0 elsewhere
+ * (background pixels never).  Height and width at most 16384; uses a context
+ * scratch area of 4 bytes per pixel.  Enqueued on `stream`. */
+int recon_pre_watershed(recon_ctx *ctx, recon_image *img, int conn, void *stream);
 
 /* Run n tasks (any mix of ops, shapes and connectivities) in one persistent
  * launch sequence, replayed from a HIP graph.  Enqueued on `stream`. */

@@ -30,7 +30,8 @@ TWO_PLANE_OPS = ("dilate", "erode")   # marker and mask are two images
 # every symbol the C header declares
 EXPORTED = (
     "recon_create", "recon_destroy", "recon_dilate", "recon_fill_holes", "recon_erode",
-    "recon_hdome", "recon_regional_max", "recon_label", "recon_area_threshold", "recon_batch",
+    "recon_hdome", "recon_regional_max", "recon_label", "recon_area_threshold", "recon_distance",
+    "recon_pre_watershed", "recon_batch",
     "recon_submit", "recon_poll", "recon_wait", "recon_serve_stop", "recon_last_stats",
     "recon_launch_times", "recon_last_error",
 )
@@ -101,6 +102,8 @@ def load_library(path: str = LIB_PATH):
     lib.recon_label.argtypes = [P, ctypes.POINTER(recon_image), P, ctypes.c_int64, ctypes.c_int, P, P]
     lib.recon_area_threshold.argtypes = [P, ctypes.POINTER(recon_image), ctypes.c_int, ctypes.c_int64,
                                          ctypes.c_int64, P]
+    lib.recon_distance.argtypes = [P, ctypes.POINTER(recon_image), P, ctypes.c_int64, P]
+    lib.recon_pre_watershed.argtypes = [P, ctypes.POINTER(recon_image), ctypes.c_int, P]
     lib.recon_batch.argtypes = [P, ctypes.POINTER(recon_task), ctypes.c_int32, P]
     lib.recon_submit.argtypes = [P, ctypes.POINTER(recon_task), ctypes.POINTER(ctypes.c_uint64)]
     lib.recon_poll.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int)]
@@ -209,6 +212,22 @@ def recon_area_threshold(ctx: int, img, min_area: int, max_area: int, conn: int 
     m = image_of(img)
     _check(load_library().recon_area_threshold(ctx, ctypes.byref(m), int(conn), int(min_area), int(max_area),
                                                _stream_ptr(stream)))
+
+
+def recon_distance(ctx: int, img, dist2, stream=None) -> None:
+    """dist2: 2-D torch.int32 device tensor of img's shape (rows may be padded)."""
+    import torch
+    m = image_of(img)
+    if not isinstance(dist2, torch.Tensor) or dist2.dtype != torch.int32 or dist2.dim() != 2 or \
+            not dist2.is_cuda or tuple(dist2.shape) != tuple(img.shape) or dist2.stride(1) != 1:
+        raise TypeError("dist2 must be a 2-D int32 device tensor of the image's shape with contiguous rows")
+    _check(load_library().recon_distance(ctx, ctypes.byref(m), dist2.data_ptr(), dist2.stride(0),
+                                         _stream_ptr(stream)))
+
+
+def recon_pre_watershed(ctx: int, img, conn: int = 8, stream=None) -> None:
+    m = image_of(img)
+    _check(load_library().recon_pre_watershed(ctx, ctypes.byref(m), int(conn), _stream_ptr(stream)))
 
 
 def make_task(op: str, image, mask=None, conn: int = 8, scan_rounds: int = 0, queue_capacity: int = 0,
@@ -332,6 +351,19 @@ class Recon:
     def area_threshold(self, img, min_area: int, max_area: int, conn: int = 8, stream=None):
         """In place: img <- 255 on the components with min_area <= area <= max_area, else 0."""
         recon_area_threshold(self.ctx, img, min_area, max_area, conn, stream)
+        return img
+
+    def distance(self, img, dist2=None, stream=None):
+        """Exact squared Euclidean distance to the nearest 0 pixel, into an int32 plane (allocated if None)."""
+        import torch
+        if dist2 is None:
+            dist2 = torch.empty(tuple(img.shape), dtype=torch.int32, device=img.device)
+        recon_distance(self.ctx, img, dist2, stream)
+        return dist2
+
+    def pre_watershed(self, img, conn: int = 8, stream=None):
+        """In place: img <- 255 on the regional maxima of min(floor(sqrt(dist2)), 255), else 0."""
+        recon_pre_watershed(self.ctx, img, conn, stream)
         return img
 
     def batch(self, tasks, stream=None):

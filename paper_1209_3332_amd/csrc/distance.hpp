@@ -1,0 +1,120 @@
+// distance.hpp -- device code of the exact Euclidean distance transform and
+// the distance map of the Pre-Watershed operation (Table 1 of the paper,
+// Sec. V-A: Pre-Watershed is built on a distance transformation and
+// morphological reconstruction), for AMD MI355X (gfx950).
+//
+// dist2(p) = min over the 0 pixels q of the image of |p - q|^2 (an exact
+// integer; pixels outside the image are not background; 2^31 - 1 when the
+// image has no 0 pixel).  D8(p) = min(floor(sqrt(dist2(p))), 255).  The
+// Pre-Watershed markers are the regional maxima of D8, computed by the
+// reconstruction kernels (the 1-dome) on the D8 plane.
+//
+// Separable, in two passes:
+//   edt_cols  g(y, x) = distance along column x from row y to the nearest 0
+//             pixel of that column (EDT_NONE if none).  Threads own one
+//             column of one segment of EDT_SEG rows; a segment finds the
+//             nearest 0 above and below it by scanning outward from its ends
+//             (it stops at the first 0), then scans down and up inside.
+//   edt_rows  one workgroup per row: the row of g is staged in LDS, then
+//             every pixel takes min over x' of (x - x')^2 + g(x')^2,
+//             searched outward from x and stopped once (x - x')^2 alone
+//             reaches the best value (no farther column can do better; the
+//             pixel's own column bounds the search by g(x)).  Writes dist2
+//             (int32) or D8 (uint8), in place over the row it read.
+#pragma once
+#include "kernels.hpp"
+
+namespace rk {
+
+constexpr int32_t EDT_NONE = 0x3fffffff;   // no 0 pixel in the column
+constexpr int EDT_SEG = 256;               // rows per column segment
+constexpr int EDT_MAX_W = 16384;           // widest row staged in LDS (64 KiB)
+
+struct EdtArgs {
+    const uint8_t *img;    // input (0 = background)
+    int64_t pitch_img;     // bytes
+    int32_t *g;            // column distances, then (mode 0) dist2 in place
+    int64_t pitch_g;       // elements
+    uint8_t *d8;           // mode 1: D8 output (may be the input image)
+    int64_t pitch_d8;      // bytes
+    int32_t h, w;
+    int32_t mode;          // 0: dist2 into g; 1: D8 into d8
+};
+
+// Column pass.  Grid-stride over (segment, column) with consecutive threads on
+// consecutive columns (coalesced byte loads and int32 stores).
+__global__ void edt_cols(EdtArgs a) {
+    const int64_t n_seg = (a.h + EDT_SEG - 1) / EDT_SEG;
+    const int64_t n = n_seg * a.w;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
+        const int x = (int)(q % a.w);
+        const int y0 = (int)(q / a.w) * EDT_SEG, y1 = min(a.h, y0 + EDT_SEG);
+        const RK_GLOBAL uint8_t *col = gp(a.img) + x;
+        // nearest 0 above the segment (rows < y0) and below it (rows >= y1)
+        int above = EDT_NONE, below = EDT_NONE;
+        for (int y = y0 - 1; y >= 0; --y)
+            if (col[(int64_t)y * a.pitch_img] == 0) {
+                above = y0 - y;
+                break;
+            }
+        for (int y = y1; y < a.h; ++y)
+            if (col[(int64_t)y * a.pitch_img] == 0) {
+                below = y - (y1 - 1);
+                break;
+            }
+        RK_GLOBAL int32_t *gc = (RK_GLOBAL int32_t *)a.g + x;
+        int d = above;   // distance from row y to the nearest 0 at or above it
+        for (int y = y0; y < y1; ++y) {
+            if (col[(int64_t)y * a.pitch_img] == 0) d = 0;
+            else if (y > y0 && d != EDT_NONE) d += 1;
+            gc[(int64_t)y * a.pitch_g] = d;
+        }
+        d = below;       // ... at or below it
+        for (int y = y1 - 1; y >= y0; --y) {
+            if (col[(int64_t)y * a.pitch_img] == 0) d = 0;
+            else if (y < y1 - 1 && d != EDT_NONE) d += 1;
+            const int64_t o = (int64_t)y * a.pitch_g;
+            if (d < gc[o]) gc[o] = d;
+        }
+    }
+}
+
+__device__ __forceinline__ uint32_t isqrt_cap255(int64_t v) {
+    if (v >= 255 * 255) return 255u;
+    int64_t r = (int64_t)sqrt((double)v);
+    while (r * r > v) --r;
+    while ((r + 1) * (r + 1) <= v) ++r;
+    return (uint32_t)r;
+}
+
+// Row pass.  One workgroup (any size) per row, grid-stride over rows; dynamic
+// LDS: w * 4 bytes.
+__global__ void edt_rows(EdtArgs a) {
+    RK_LDS int32_t *row = (RK_LDS int32_t *)dyn_lds();
+    for (int y = blockIdx.x; y < a.h; y += gridDim.x) {
+        RK_GLOBAL int32_t *gr = (RK_GLOBAL int32_t *)a.g + (int64_t)y * a.pitch_g;
+        for (int x = threadIdx.x; x < a.w; x += blockDim.x) row[x] = gr[x];
+        __syncthreads();
+        for (int x = threadIdx.x; x < a.w; x += blockDim.x) {
+            const int32_t gx = row[x];
+            int64_t best = gx == EDT_NONE ? INT64_MAX : (int64_t)gx * gx;
+            for (int64_t step = 1; step < a.w && step * step < best; ++step) {
+                if (x - step >= 0) {
+                    const int32_t v = row[x - step];
+                    if (v != EDT_NONE && step * step + (int64_t)v * v < best) best = step * step + (int64_t)v * v;
+                }
+                if (x + step < a.w) {
+                    const int32_t v = row[x + step];
+                    if (v != EDT_NONE && step * step + (int64_t)v * v < best) best = step * step + (int64_t)v * v;
+                }
+            }
+            if (a.mode == 0)
+                gr[x] = best == INT64_MAX ? 0x7fffffff : (int32_t)best;
+            else
+                gp(a.d8)[(int64_t)y * a.pitch_d8 + x] = (uint8_t)(best == INT64_MAX ? 255u : isqrt_cap255(best));
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace rk

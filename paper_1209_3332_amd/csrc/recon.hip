@@ -29,6 +29,7 @@
 #include "../../include/recon.h"
 #include "kernels.hpp"
 #include "label.hpp"
+#include "distance.hpp"
 
 namespace {
 
@@ -962,6 +963,78 @@ int recon_area_threshold(recon_ctx *ctx, recon_image *img, int conn, int64_t min
     hipLaunchKernelGGL(rk::area_apply, dim3(g_rows), dim3(64), 0, s, a);
     HIP_TRY(hipGetLastError());
     return RECON_OK;
+}
+
+// ---- exact distance transform and Pre-Watershed markers
+
+static int check_edt_image(const recon_image *img) {
+    int rc = check_image(img, "image");
+    if (rc) return rc;
+    if (img->width > rk::EDT_MAX_W || img->height > rk::EDT_MAX_W)
+        return fail(RECON_EINVAL, "distance transform: height and width must be at most %d", rk::EDT_MAX_W);
+    return RECON_OK;
+}
+
+static int enqueue_edt(const rk::EdtArgs &a, hipStream_t s) {
+    const int64_t n_cols = ((int64_t)(a.h + rk::EDT_SEG - 1) / rk::EDT_SEG) * a.w;
+    const int g_cols = (int)std::min<int64_t>((n_cols + 255) / 256, 65535);
+    hipLaunchKernelGGL(rk::edt_cols, dim3(g_cols), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(rk::edt_rows, dim3(std::min(a.h, 65535)), dim3(256), (size_t)a.w * sizeof(int32_t), s, a);
+    HIP_TRY(hipGetLastError());
+    return RECON_OK;
+}
+
+int recon_distance(recon_ctx *ctx, const recon_image *img, int32_t *dist2, int64_t dist_pitch, void *stream) {
+    if (!ctx) return fail(RECON_EINVAL, "null context");
+    if (!dist2) return fail(RECON_EINVAL, "null distance plane");
+    int rc = check_edt_image(img);
+    if (rc) return rc;
+    if (dist_pitch < img->width)
+        return fail(RECON_EINVAL, "distance pitch %lld < width %d", (long long)dist_pitch, img->width);
+    rc = ensure_device(ctx);
+    if (rc) return rc;
+    rk::EdtArgs a{};
+    a.img = img->data;
+    a.pitch_img = img->pitch;
+    a.g = dist2;
+    a.pitch_g = dist_pitch;
+    a.h = img->height;
+    a.w = img->width;
+    a.mode = 0;
+    return enqueue_edt(a, (hipStream_t)stream);
+}
+
+int recon_pre_watershed(recon_ctx *ctx, recon_image *img, int conn, void *stream) {
+    if (!ctx) return fail(RECON_EINVAL, "null context");
+    int rc = check_edt_image(img);
+    if (rc) return rc;
+    if (conn != 4 && conn != 8) return fail(RECON_EINVAL, "conn must be 4 or 8, got %d", conn);
+    rc = ensure_device(ctx);
+    if (rc) return rc;
+    const int64_t pitch_g = (int64_t)round_up((size_t)img->width, 64);
+    rc = ensure_capacity(ctx, 0, 0, round_up((size_t)img->height * (size_t)pitch_g * 4, 256));
+    if (rc) return rc;
+    rk::EdtArgs a{};
+    a.img = img->data;
+    a.pitch_img = img->pitch;
+    a.g = (int32_t *)ctx->d_scratch;
+    a.pitch_g = pitch_g;
+    a.d8 = img->data;     // D8 replaces the image (its input is read by edt_cols only)
+    a.pitch_d8 = img->pitch;
+    a.h = img->height;
+    a.w = img->width;
+    a.mode = 1;
+    rc = enqueue_edt(a, (hipStream_t)stream);
+    if (rc) return rc;
+    // the regional maxima of D8, in place (the reconstruction reuses the
+    // scratch area once the row pass, earlier on the stream, has read it)
+    recon_task t{};
+    t.op = RECON_OP_REGIONAL_MAX;
+    t.conn = conn;
+    t.image = *img;
+    rc = check_task(t);
+    if (rc) return rc;
+    return run_tasks(ctx, &t, 1, (hipStream_t)stream, false);
 }
 
 int recon_batch(recon_ctx *ctx, const recon_task *tasks, int32_t n, void *stream) {

@@ -78,3 +78,19 @@ def run_label(exe, img, conn, min_area=0, max_area=1 << 40, n_waves=4, timeout=6
         count = int(log.split("count")[1].split()[0])
         return (p.returncode, np.fromfile(lp, np.int32).reshape(h, w), count,
                 np.fromfile(ap, np.uint8).reshape(h, w), log)
+
+
+def run_edt(exe, img, n_waves=3, timeout=600):
+    """Distance transform of one image on the emulated kernels: (rc, dist2 int32, D8 uint8, log)."""
+    img = np.ascontiguousarray(img, dtype=np.uint8)
+    h, w = img.shape
+    with tempfile.TemporaryDirectory() as d:
+        ip, dp, ep = (os.path.join(d, s) for s in ("img.bin", "d2.bin", "d8.bin"))
+        img.tofile(ip)
+        env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1", UBSAN_OPTIONS="print_stacktrace=1")
+        p = subprocess.run([exe, "edt", str(h), str(w), str(n_waves), ip, dp, ep], capture_output=True, text=True,
+                           timeout=timeout, env=env)
+        log = p.stdout + p.stderr
+        if p.returncode != 0 or not os.path.exists(dp):
+            return p.returncode, None, None, log
+        return p.returncode, np.fromfile(dp, np.int32).reshape(h, w), np.fromfile(ep, np.uint8).reshape(h, w), log

@@ -20,6 +20,7 @@
 
 #include "../../paper_1209_3332_amd/csrc/kernels.hpp"
 #include "../../paper_1209_3332_amd/csrc/label.hpp"
+#include "../../paper_1209_3332_amd/csrc/distance.hpp"
 
 #if defined(__has_feature)
 #if __has_feature(address_sanitizer)
@@ -83,6 +84,12 @@ struct Wave {
 thread_local Wave *tw = nullptr;
 
 int lane() { return tw->cur; }
+// The lanes of an emulated wave share one OS thread, so a thread_local index
+// cannot tell them apart: inside a wave the thread index is the lane.
+Dim3 thread_idx() {
+    if (tw) return Dim3{(uint32_t)tw->cur, 0, 0};
+    return threadIdx_;
+}
 uint8_t *wave_lds() { return tw->lds; }
 
 uint64_t wall_ticks() {
@@ -299,6 +306,51 @@ static int emu_label(const uint8_t *img_in, int h, int w, int conn, int n_waves,
 }
 
 // ---------------------------------------------------------------------------
+// distance-transform driver: mode 0 writes dist2 (int32), mode 1 D8 (uint8)
+
+static int emu_edt(const uint8_t *img_in, int h, int w, int mode, int n_waves, int32_t *d2_out, uint8_t *d8_out) {
+    using namespace rk;
+    const int64_t pitch_img = w + 1, pitch_g = w + 2;   // padded pitches, exact-size allocations
+    std::vector<uint8_t> img((size_t)(h - 1) * pitch_img + w);
+    for (int y = 0; y < h; ++y) std::memcpy(&img[(size_t)y * pitch_img], img_in + (size_t)y * w, w);
+    std::vector<int32_t> g((size_t)(h - 1) * pitch_g + w, -5);
+    EdtArgs a{};
+    a.img = img.data();
+    a.pitch_img = pitch_img;
+    a.g = g.data();
+    a.pitch_g = pitch_g;
+    a.d8 = img.data();   // in place over the input, as the library does
+    a.pitch_d8 = pitch_img;
+    a.h = h;
+    a.w = w;
+    a.mode = mode;
+    kemu::gridDim_.x = 3;
+    kemu::blockDim_.x = 64;
+    for (uint32_t b = 0; b < 3; ++b)
+        for (uint32_t t = 0; t < 64; ++t) {
+            kemu::blockIdx_.x = b;
+            kemu::threadIdx_.x = t;
+            edt_cols(a);
+        }
+    std::atomic<int> bad{0};
+    std::vector<std::thread> th;
+    for (int gi = 0; gi < n_waves; ++gi)
+        th.emplace_back([&, gi] {
+            kemu::blockIdx_.x = (uint32_t)gi;
+            kemu::gridDim_.x = (uint32_t)n_waves;
+            kemu::blockDim_.x = 64;
+            if (!kemu::run_wave([&] { edt_rows(a); }, (size_t)w * 4))
+                bad++;
+        });
+    for (auto &t : th) t.join();
+    for (int y = 0; y < h; ++y) {
+        if (mode == 0) std::memcpy(d2_out + (size_t)y * w, &g[(size_t)y * pitch_g], (size_t)w * 4);
+        else std::memcpy(d8_out + (size_t)y * w, &img[(size_t)y * pitch_img], (size_t)w);
+    }
+    return bad ? -2 : 0;
+}
+
+// ---------------------------------------------------------------------------
 // driver (called through ctypes)
 
 extern "C" {
@@ -502,6 +554,25 @@ int main(int argc, char **argv) {
         std::fwrite(area.data(), 1, area.size(), f);
         std::fclose(f);
         std::printf("rc %d count %d\n", rc, count);
+        return rc == 0 ? 0 : 1;
+    }
+    //   kemu edt <h> <w> <waves> <image_path> <dist2_out> <d8_out>
+    if (argc == 8 && std::string(argv[1]) == "edt") {
+        const int h = std::atoi(argv[2]), w = std::atoi(argv[3]), nw = std::atoi(argv[4]);
+        std::vector<uint8_t> img((size_t)h * w), d8((size_t)h * w);
+        std::vector<int32_t> d2((size_t)h * w);
+        FILE *f = std::fopen(argv[5], "rb");
+        if (!f || std::fread(img.data(), 1, img.size(), f) != img.size()) return 4;
+        std::fclose(f);
+        int rc = emu_edt(img.data(), h, w, 0, nw, d2.data(), nullptr);
+        if (rc == 0) rc = emu_edt(img.data(), h, w, 1, nw, nullptr, d8.data());
+        f = std::fopen(argv[6], "wb");
+        std::fwrite(d2.data(), 4, d2.size(), f);
+        std::fclose(f);
+        f = std::fopen(argv[7], "wb");
+        std::fwrite(d8.data(), 1, d8.size(), f);
+        std::fclose(f);
+        std::printf("rc %d\n", rc);
         return rc == 0 ? 0 : 1;
     }
     if (argc < 7) return 2;

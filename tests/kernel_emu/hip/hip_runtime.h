@@ -6,6 +6,7 @@
 #pragma once
 #include <atomic>
 #include <chrono>
+#include <cmath>
 #include <cstdint>
 #include <cstring>
 #include <thread>
@@ -48,6 +49,7 @@ struct Dim3 { uint32_t x = 0, y = 0, z = 0; };
 extern thread_local Dim3 blockIdx_, threadIdx_, blockDim_, gridDim_;
 
 int lane();                           // current lane of the running wave
+Dim3 thread_idx();                    // inside a wave: (lane, 0, 0); else threadIdx_
 void wave_sync();                     // all 64 lanes reach this point
 uint64_t exchange(uint64_t v, int src_lane);   // value of `v` in lane src_lane
 uint64_t ballot(bool p);
@@ -58,7 +60,7 @@ void check_lds(const void *p, size_t n);       // bounds check of an LDS access
 }  // namespace kemu
 
 #define blockIdx kemu::blockIdx_
-#define threadIdx kemu::threadIdx_
+#define threadIdx kemu::thread_idx()
 #define blockDim kemu::blockDim_
 #define gridDim kemu::gridDim_
 

@@ -166,3 +166,23 @@ def test_label_and_area_threshold(emu_exe, oracle_mod, conn):
         assert count == n, (i, count, n)
         assert np.array_equal(lab, want), "image %d: %d labels differ" % (i, int((lab != want).sum()))
         assert np.array_equal(area, oracle_mod.area_threshold(img, 3, 40, conn)), "image %d area filter" % i
+
+
+def test_distance_transform(emu_exe, oracle_mod):
+    """Column segments (with carries from outside the segment) and the row
+    search, against the oracle's exact squared distances and capped D8."""
+    rng = np.random.default_rng(77)
+    imgs = [np.zeros((1, 1), np.uint8), np.full((1, 1), 5, np.uint8), np.full((3, 7), 9, np.uint8)]
+    for (h, w, p) in [(300, 40, 0.9), (530, 23, 0.995), (17, 300, 0.7), (260, 270, 0.97)]:
+        imgs.append(np.where(rng.random((h, w)) < p, 255, 0).astype(np.uint8))
+    one = np.full((600, 5), 255, np.uint8)
+    one[599, 2] = 0                     # distances beyond 255: the D8 cap, carries across segments
+    imgs.append(one)
+    _, _, binary = synth.config2_tile(seed=synth.seed_for(2, 26), size=96, n_gauss=2)
+    imgs.append(binary)
+    for i, img in enumerate(imgs):
+        rc, d2, d8, log = kemu.run_edt(emu_exe, img)
+        assert rc == 0, log[-2000:]
+        assert "ERROR: AddressSanitizer" not in log and "runtime error" not in log, log[-2000:]
+        assert np.array_equal(d2, oracle_mod.distance2(img)), "image %d dist2" % i
+        assert np.array_equal(d8, oracle_mod.distance8(img)), "image %d D8" % i
