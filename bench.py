@@ -244,6 +244,61 @@ def labelling(recon, torch, binary, steps, conn=8, lo=20, hi=1000):
     return res
 
 
+def distance(recon, torch, binary, steps, conn=8):
+    """Exact distance transform (int32 squared distances) and Pre-Watershed
+    markers of the headline tile's binary image, each launched `steps` times
+    back to back: throughput, per-launch time from events on the launch
+    stream, bit-exact parity of the last launch against the oracle, the
+    oracle's single-core rate."""
+    import numpy as np
+    import oracle
+    dev = torch.device("cuda:0")
+    d_img = torch.from_numpy(binary).to(dev)
+    planes = [torch.empty(binary.shape, dtype=torch.int32, device=dev) for _ in range(2)]
+    ctx = recon.Recon(0)
+    stream = torch.cuda.current_stream()
+    res = {"workload": "%dx%d binary nuclei tile (I > 120); markers %d-conn; %d launches each" % (
+        binary.shape[0], binary.shape[1], conn, steps)}
+    for op in ("distance", "pre_watershed"):
+        bufs = [d_img.clone() for _ in range(steps + 2)] if op == "pre_watershed" else None
+
+        def launch(s):
+            if op == "distance":
+                ctx.distance(d_img, planes[s % 2], stream)
+            else:
+                ctx.pre_watershed(bufs[s], conn, stream)
+
+        for s in range(2):
+            launch(s)
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        t0 = time.perf_counter()
+        ev[0].record(stream)
+        for s in range(steps):
+            launch(2 + s)
+            ev[s + 1].record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        per = [ev[s].elapsed_time(ev[s + 1]) for s in range(steps)]
+        t0 = time.perf_counter()
+        if op == "distance":
+            ok = bool(np.array_equal(planes[(2 + steps - 1) % 2].cpu().numpy(), oracle.distance2(binary)))
+        else:
+            ok = bool(np.array_equal(bufs[-1].cpu().numpy(), oracle.pre_watershed(binary, conn)))
+        t_oracle = time.perf_counter() - t0
+        # algorithmic bytes: read the image, write int32 distances (5 B/px);
+        # the markers read and write the image (2 B/px)
+        bpp = 5.0 if op == "distance" else 2.0
+        res[op] = {"Mpixel_s": binary.size * steps / wall / 1e6, "ms_per_launch": wall * 1e3 / steps,
+                   "launch_ms_median": float(np.median(per)),
+                   "algorithmic_GBs": bpp * binary.size / (float(np.median(per)) * 1e-3) / 1e9,
+                   "oracle_single_core_Mpixel_s": binary.size / t_oracle / 1e6, "parity": ok}
+        log("%s: %.0f Mpixel/s (%.3f ms/launch), parity %s" % (op, res[op]["Mpixel_s"], res[op]["ms_per_launch"], ok))
+        del bufs
+    ctx.close()
+    return res
+
+
 def batched_vs_per_tile(recon, torch, ctx_cfg, n_tiles, size, workers, spiral_size):
     import numpy as np
     import oracle
@@ -448,6 +503,8 @@ def main():
                     help="launches per op of erosion / h-dome / regional maxima on the tile (0 skips)")
     ap.add_argument("--label-steps", type=int, default=10,
                     help="launches of labelling and of the area filter on the binary tile (0 skips)")
+    ap.add_argument("--distance-steps", type=int, default=10,
+                    help="launches of the distance transform and of the Pre-Watershed markers (0 skips)")
     ap.add_argument("--block-rows", type=int, default=0)
     ap.add_argument("--scan-rounds", type=int, default=0)
     ap.add_argument("--queue", type=int, default=0)
@@ -573,6 +630,8 @@ def main():
         out["next_ops"] = next_ops(recon, torch, mask, args.next_ops_steps)
     if args.label_steps:
         out["labelling"] = labelling(recon, torch, binary, args.label_steps)
+    if args.distance_steps:
+        out["distance"] = distance(recon, torch, binary, args.distance_steps)
     if args.batch_tiles:
         out["batched_vs_per_tile"] = batched_vs_per_tile(recon, torch, {k: v for k, v in cfg.items()},
                                                          args.batch_tiles, args.size, args.workers,
@@ -597,6 +656,8 @@ def main():
     if "next_ops" in out and not all(out["next_ops"][op]["parity"] for op in ("erode", "hdome", "regional_max")):
         sys.exit(1)
     if "labelling" in out and not all(out["labelling"][op]["parity"] for op in ("label", "area_threshold")):
+        sys.exit(1)
+    if "distance" in out and not all(out["distance"][op]["parity"] for op in ("distance", "pre_watershed")):
         sys.exit(1)
 
 

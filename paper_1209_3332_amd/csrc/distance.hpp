@@ -10,11 +10,14 @@
 // reconstruction kernels (the 1-dome) on the D8 plane.
 //
 // Separable, in two passes:
+//   edt_zeros per column segment of EDT_SEG rows: the first and the last row
+//             holding a 0 pixel (-1 if none);
 //   edt_cols  g(y, x) = distance along column x from row y to the nearest 0
-//             pixel of that column (EDT_NONE if none).  Threads own one
-//             column of one segment of EDT_SEG rows; a segment finds the
-//             nearest 0 above and below it by scanning outward from its ends
-//             (it stops at the first 0), then scans down and up inside.
+//             pixel of that column (EDT_NONE if none).  A thread owns one
+//             column of one segment: it holds the segment's pixels in
+//             registers, takes the nearest 0 above and below the segment from
+//             the other segments' summaries (the nearest segment that has
+//             one), scans down and up and writes g once.
 //   edt_rows  one workgroup per row: the row of g is staged in LDS, then
 //             every pixel takes min over x' of (x - x')^2 + g(x')^2,
 //             searched outward from x and stopped once (x - x')^2 alone
@@ -27,7 +30,7 @@
 namespace rk {
 
 constexpr int32_t EDT_NONE = 0x3fffffff;   // no 0 pixel in the column
-constexpr int EDT_SEG = 256;               // rows per column segment
+constexpr int EDT_SEG = 32;                // rows per column segment (held in registers)
 constexpr int EDT_MAX_W = 16384;           // widest row staged in LDS (64 KiB)
 
 struct EdtArgs {
@@ -39,43 +42,84 @@ struct EdtArgs {
     int64_t pitch_d8;      // bytes
     int32_t h, w;
     int32_t mode;          // 0: dist2 into g; 1: D8 into d8
+    int32_t *zfirst;       // per (segment, column): first row of the segment with a 0 pixel, or -1
+    int32_t *zlast;        // ... last such row, or -1
 };
 
-// Column pass.  Grid-stride over (segment, column) with consecutive threads on
-// consecutive columns (coalesced byte loads and int32 stores).
-__global__ void edt_cols(EdtArgs a) {
+// Column-segment summaries.  Grid-stride over (segment, column), consecutive
+// threads on consecutive columns.
+__global__ void edt_zeros(EdtArgs a) {
     const int64_t n_seg = (a.h + EDT_SEG - 1) / EDT_SEG;
     const int64_t n = n_seg * a.w;
     for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
         const int x = (int)(q % a.w);
-        const int y0 = (int)(q / a.w) * EDT_SEG, y1 = min(a.h, y0 + EDT_SEG);
+        const int y0 = (int)(q / a.w) * EDT_SEG;
         const RK_GLOBAL uint8_t *col = gp(a.img) + x;
-        // nearest 0 above the segment (rows < y0) and below it (rows >= y1)
+        uint8_t v[EDT_SEG];
+#pragma unroll
+        for (int r = 0; r < EDT_SEG; ++r) v[r] = y0 + r < a.h ? col[(int64_t)(y0 + r) * a.pitch_img] : 1;
+        int first = -1, last = -1;
+#pragma unroll
+        for (int r = 0; r < EDT_SEG; ++r)
+            if (v[r] == 0) {
+                if (first < 0) first = y0 + r;
+                last = y0 + r;
+            }
+        a.zfirst[q] = first;
+        a.zlast[q] = last;
+    }
+}
+
+// Column pass.  Grid-stride over (segment, column) with consecutive threads on
+// consecutive columns (coalesced byte loads and int32 stores).
+__global__ void edt_cols(EdtArgs a) {
+    const int n_seg = (a.h + EDT_SEG - 1) / EDT_SEG;
+    const int64_t n = (int64_t)n_seg * a.w;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
+        const int x = (int)(q % a.w);
+        const int s = (int)(q / a.w);
+        const int y0 = s * EDT_SEG, y1 = min(a.h, y0 + EDT_SEG);
+        const RK_GLOBAL uint8_t *col = gp(a.img) + x;
+        uint8_t v[EDT_SEG];
+#pragma unroll
+        for (int r = 0; r < EDT_SEG; ++r) v[r] = y0 + r < a.h ? col[(int64_t)(y0 + r) * a.pitch_img] : 1;
+        // nearest 0 above row y0 and below row y1 - 1, from the summaries
         int above = EDT_NONE, below = EDT_NONE;
-        for (int y = y0 - 1; y >= 0; --y)
-            if (col[(int64_t)y * a.pitch_img] == 0) {
-                above = y0 - y;
+        for (int t = s - 1; t >= 0; --t) {
+            const int z = a.zlast[(int64_t)t * a.w + x];
+            if (z >= 0) {
+                above = y0 - z;
                 break;
             }
-        for (int y = y1; y < a.h; ++y)
-            if (col[(int64_t)y * a.pitch_img] == 0) {
-                below = y - (y1 - 1);
+        }
+        for (int t = s + 1; t < n_seg; ++t) {
+            const int z = a.zfirst[(int64_t)t * a.w + x];
+            if (z >= 0) {
+                below = z - (y1 - 1);
                 break;
             }
+        }
+        int g[EDT_SEG];
+        int d = above;   // distance from row y0 + r to the nearest 0 at or above it
+#pragma unroll
+        for (int r = 0; r < EDT_SEG; ++r) {
+            if (v[r] == 0) d = 0;
+            else if (r > 0 && d != EDT_NONE) d += 1;
+            g[r] = d;
+        }
+        d = below;       // ... at or below it (rows past the image are never 0)
+        const int last = y1 - 1 - y0;
+#pragma unroll
+        for (int r = EDT_SEG - 1; r >= 0; --r) {
+            if (r > last) continue;
+            if (v[r] == 0) d = 0;
+            else if (r < last && d != EDT_NONE) d += 1;
+            if (d < g[r]) g[r] = d;
+        }
         RK_GLOBAL int32_t *gc = (RK_GLOBAL int32_t *)a.g + x;
-        int d = above;   // distance from row y to the nearest 0 at or above it
-        for (int y = y0; y < y1; ++y) {
-            if (col[(int64_t)y * a.pitch_img] == 0) d = 0;
-            else if (y > y0 && d != EDT_NONE) d += 1;
-            gc[(int64_t)y * a.pitch_g] = d;
-        }
-        d = below;       // ... at or below it
-        for (int y = y1 - 1; y >= y0; --y) {
-            if (col[(int64_t)y * a.pitch_img] == 0) d = 0;
-            else if (y < y1 - 1 && d != EDT_NONE) d += 1;
-            const int64_t o = (int64_t)y * a.pitch_g;
-            if (d < gc[o]) gc[o] = d;
-        }
+#pragma unroll
+        for (int r = 0; r < EDT_SEG; ++r)
+            if (y0 + r < a.h) gc[(int64_t)(y0 + r) * a.pitch_g] = g[r];
     }
 }
 

@@ -975,9 +975,19 @@ static int check_edt_image(const recon_image *img) {
     return RECON_OK;
 }
 
-static int enqueue_edt(const rk::EdtArgs &a, hipStream_t s) {
+// Scratch bytes of the column-segment summaries.
+static size_t edt_summary_bytes(int h, int w) {
+    const size_t n = (size_t)((h + rk::EDT_SEG - 1) / rk::EDT_SEG) * (size_t)w;
+    return 2 * round_up(n * 4, 256);
+}
+
+// `summary` holds edt_summary_bytes.
+static int enqueue_edt(rk::EdtArgs a, uint8_t *summary, hipStream_t s) {
     const int64_t n_cols = ((int64_t)(a.h + rk::EDT_SEG - 1) / rk::EDT_SEG) * a.w;
+    a.zfirst = (int32_t *)summary;
+    a.zlast = (int32_t *)(summary + round_up((size_t)n_cols * 4, 256));
     const int g_cols = (int)std::min<int64_t>((n_cols + 255) / 256, 65535);
+    hipLaunchKernelGGL(rk::edt_zeros, dim3(g_cols), dim3(256), 0, s, a);
     hipLaunchKernelGGL(rk::edt_cols, dim3(g_cols), dim3(256), 0, s, a);
     hipLaunchKernelGGL(rk::edt_rows, dim3(std::min(a.h, 65535)), dim3(256), (size_t)a.w * sizeof(int32_t), s, a);
     HIP_TRY(hipGetLastError());
@@ -993,6 +1003,8 @@ int recon_distance(recon_ctx *ctx, const recon_image *img, int32_t *dist2, int64
         return fail(RECON_EINVAL, "distance pitch %lld < width %d", (long long)dist_pitch, img->width);
     rc = ensure_device(ctx);
     if (rc) return rc;
+    rc = ensure_capacity(ctx, 0, 0, edt_summary_bytes(img->height, img->width));
+    if (rc) return rc;
     rk::EdtArgs a{};
     a.img = img->data;
     a.pitch_img = img->pitch;
@@ -1001,7 +1013,7 @@ int recon_distance(recon_ctx *ctx, const recon_image *img, int32_t *dist2, int64
     a.h = img->height;
     a.w = img->width;
     a.mode = 0;
-    return enqueue_edt(a, (hipStream_t)stream);
+    return enqueue_edt(a, ctx->d_scratch, (hipStream_t)stream);
 }
 
 int recon_pre_watershed(recon_ctx *ctx, recon_image *img, int conn, void *stream) {
@@ -1012,7 +1024,8 @@ int recon_pre_watershed(recon_ctx *ctx, recon_image *img, int conn, void *stream
     rc = ensure_device(ctx);
     if (rc) return rc;
     const int64_t pitch_g = (int64_t)round_up((size_t)img->width, 64);
-    rc = ensure_capacity(ctx, 0, 0, round_up((size_t)img->height * (size_t)pitch_g * 4, 256));
+    const size_t plane = round_up((size_t)img->height * (size_t)pitch_g * 4, 256);
+    rc = ensure_capacity(ctx, 0, 0, plane + edt_summary_bytes(img->height, img->width));
     if (rc) return rc;
     rk::EdtArgs a{};
     a.img = img->data;
@@ -1024,7 +1037,7 @@ int recon_pre_watershed(recon_ctx *ctx, recon_image *img, int conn, void *stream
     a.h = img->height;
     a.w = img->width;
     a.mode = 1;
-    rc = enqueue_edt(a, (hipStream_t)stream);
+    rc = enqueue_edt(a, ctx->d_scratch + plane, (hipStream_t)stream);
     if (rc) return rc;
     // the regional maxima of D8, in place (the reconstruction reuses the
     // scratch area once the row pass, earlier on the stream, has read it)

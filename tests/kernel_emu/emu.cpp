@@ -324,14 +324,20 @@ static int emu_edt(const uint8_t *img_in, int h, int w, int mode, int n_waves, i
     a.h = h;
     a.w = w;
     a.mode = mode;
+    const size_t n_sum = (size_t)((h + EDT_SEG - 1) / EDT_SEG) * w;
+    std::vector<int32_t> zf(n_sum, -9), zl(n_sum, -9);
+    a.zfirst = zf.data();
+    a.zlast = zl.data();
     kemu::gridDim_.x = 3;
     kemu::blockDim_.x = 64;
-    for (uint32_t b = 0; b < 3; ++b)
-        for (uint32_t t = 0; t < 64; ++t) {
-            kemu::blockIdx_.x = b;
-            kemu::threadIdx_.x = t;
-            edt_cols(a);
-        }
+    for (int kern = 0; kern < 2; ++kern)
+        for (uint32_t b = 0; b < 3; ++b)
+            for (uint32_t t = 0; t < 64; ++t) {
+                kemu::blockIdx_.x = b;
+                kemu::threadIdx_.x = t;
+                if (kern == 0) edt_zeros(a);
+                else edt_cols(a);
+            }
     std::atomic<int> bad{0};
     std::vector<std::thread> th;
     for (int gi = 0; gi < n_waves; ++gi)
