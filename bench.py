@@ -122,6 +122,94 @@ def cpu_baseline(marker, mask, binary, budget_s=20.0):
                       "single-core %.2f Mpixel/s" % (n, mask.shape[0], mask.shape[1], 2 * mask.size / one / 1e6)}
 
 
+def headline(recon, torch, cfg, marker, mask, binary, steps, warmup, mode):
+    """The headline step on one tile -- 8-conn reconstruction by dilation of
+    (max(I - 20, 0), I) and 8-conn fill-holes of 255 * (I > 120) -- timed over
+    `steps` steps after `warmup`, each step on its own untouched inputs resident
+    in HBM.  mode "batched": both operations in one recon_batch launch per
+    step; "plain": recon_dilate then recon_fill_holes.  Returns throughput,
+    the kernels' durations from the library's events on the launch stream, the
+    parity of the last step, and the roofline of the dominant kernel."""
+    import numpy as np
+    import oracle
+    dev = torch.device("cuda:0")
+    d_mask = torch.from_numpy(mask).to(dev)
+    n_sets = warmup + steps
+    markers = [torch.from_numpy(marker).to(dev) for _ in range(n_sets)]
+    images = [torch.from_numpy(binary).to(dev) for _ in range(n_sets)]
+    torch.cuda.synchronize()
+    ctx = recon.Recon(0, **cfg)
+    stream = torch.cuda.current_stream()
+
+    def step(s):
+        if mode == "batched":
+            ctx.batch([{"op": "dilate", "image": markers[s], "mask": d_mask, "conn": 8},
+                       {"op": "fill_holes", "image": images[s], "conn": 8}], stream)
+        else:
+            ctx.dilate(markers[s], d_mask, 8, stream)
+            ctx.fill_holes(images[s], 8, stream)
+
+    for s in range(warmup):
+        step(s)
+    torch.cuda.synchronize()
+    # the timed region: launches back to back, one synchronisation at the end
+    t_start = time.perf_counter()
+    for s in range(warmup, n_sets):
+        step(s)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    ms_per_step = wall * 1e3 / steps
+    value = 2 * mask.size / (wall / steps) / 1e6
+    log("headline (%s): %.3f ms/step, %.0f Mpixel/s" % (mode, ms_per_step, value))
+    # kernel durations of every timed launch, from the library's HIP events on
+    # the launch stream (plain: launch 2k is step k's dilate, 2k+1 its fill-holes)
+    per_step = 1 if mode == "batched" else 2
+    n_q = min(per_step * steps, 64)   # the library keeps the marks of the last 64 launches
+    times = [ctx.launch_times(back) for back in range(n_q - 1, -1, -1)]
+    groups = {"dilate + fill_holes": times} if mode == "batched" else {"dilate": times[0::2],
+                                                                        "fill_holes": times[1::2]}
+    # counters of one more (untimed) launch of each kind
+    spare_m = torch.from_numpy(marker).to(dev)
+    spare_i = torch.from_numpy(binary).to(dev)
+    stats = {}
+    if mode == "batched":
+        ctx.batch([{"op": "dilate", "image": spare_m, "mask": d_mask, "conn": 8},
+                   {"op": "fill_holes", "image": spare_i, "conn": 8}], stream)
+        stats["dilate + fill_holes"] = ctx.last_stats()
+    else:
+        ctx.dilate(spare_m, d_mask, 8, stream)
+        stats["dilate"] = ctx.last_stats()
+        ctx.fill_holes(spare_i, 8, stream)
+        stats["fill_holes"] = ctx.last_stats()
+    parity = {"dilate": bool(np.array_equal(markers[-1].cpu().numpy(), oracle.recon_dilate(marker, mask, 8))),
+              "fill_holes": bool(np.array_equal(images[-1].cpu().numpy(), oracle.fill_holes(binary, 8)))}
+    ctx.close()
+
+    avg = lambda xs, k: sum(x[k] for x in xs) / len(xs)
+    kernels = {}
+    for name, ts in groups.items():
+        st = stats[name]
+        kernels[name] = {"dense_pass_ms": avg(ts, "dense_ms"), "border_seed_ms": avg(ts, "seed_ms"),
+                         "revisit_drain_ms": avg(ts, "drain_ms"), "launch_ms": avg(ts, "total_ms"),
+                         "dense_visits": st["dense_visits"], "revisits": st["revisits"], "reruns": st["reruns"],
+                         "queue_overflows": st["queue_overflows"]}
+    # dominant kernel (by average duration) and its roofline.  Algorithmic
+    # bytes: the persistent pipeline makes every visit, first or later, in
+    # revisit_drain; a visit reads a block's mask and marker and writes the
+    # marker back (3 B/px of the block).
+    bh = cfg.get("block_rows", 32)
+    cand = [("revisit_drain (%s)" % name, kv["revisit_drain_ms"],
+             3.0 * bh * 256 * (kv["revisits"] + kv["dense_visits"])) for name, kv in kernels.items()]
+    dom = max(cand, key=lambda c: c[1])
+    achieved = dom[2] / (dom[1] * 1e-3) / 1e9
+    roofline = {"kernel": dom[0], "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": committed_traffic(dom[0]), "algorithmic_bytes": dom[2],
+                "kernel_ms": dom[1],
+                "step_GBs": (BYTES_DILATE + BYTES_FILL) * mask.size / (ms_per_step * 1e-3) / 1e9,
+                "kernel_source": kernel_sha()}
+    return {"ms_per_step": ms_per_step, "value": value, "kernels": kernels, "parity": parity, "roofline": roofline}
+
+
 def next_ops(recon, torch, mask, steps, conn=8, h=20):
     """Reconstruction by erosion (marker I + h, capped: the dual of the headline
     marker), the h-dome and the regional maxima of the headline tile, each
@@ -505,6 +593,10 @@ def main():
                     help="launches of labelling and of the area filter on the binary tile (0 skips)")
     ap.add_argument("--distance-steps", type=int, default=10,
                     help="launches of the distance transform and of the Pre-Watershed markers (0 skips)")
+    ap.add_argument("--step-mode", choices=("batched", "plain"), default="batched",
+                    help="headline step: both operations in one batched launch, or two plain calls")
+    ap.add_argument("--plain-steps", type=int, default=20,
+                    help="with --step-mode batched: also time the step as plain calls (0 skips)")
     ap.add_argument("--block-rows", type=int, default=0)
     ap.add_argument("--scan-rounds", type=int, default=0)
     ap.add_argument("--queue", type=int, default=0)
@@ -535,14 +627,6 @@ def main():
     import synth
 
     marker, mask, binary = synth.config2_tile(size=args.size, n_gauss=round(3000 * args.size ** 2 / 4096 ** 2))
-    dev = torch.device("cuda:0")
-    d_mask = torch.from_numpy(mask).to(dev)
-    n_sets = args.warmup + args.steps
-    markers = [torch.from_numpy(marker).to(dev) for _ in range(n_sets)]
-    images = [torch.from_numpy(binary).to(dev) for _ in range(n_sets)]
-    torch.cuda.synchronize()
-    px_step = 2 * mask.size
-
     cfg = dict(timing=1)
     if args.block_rows:
         cfg["block_rows"] = args.block_rows
@@ -550,82 +634,24 @@ def main():
         cfg["scan_rounds"] = args.scan_rounds
     if args.queue:
         cfg["queue_capacity"] = args.queue
-    ctx = recon.Recon(0, **cfg)
-    stream = torch.cuda.current_stream()
-
-    def step(s):
-        ctx.dilate(markers[s], d_mask, 8, stream)
-        ctx.fill_holes(images[s], 8, stream)
-
-    for s in range(args.warmup):
-        step(s)
-    torch.cuda.synchronize()
-    # the timed region: launches back to back, one synchronisation at the end
-    t_start = time.perf_counter()
-    for s in range(args.warmup, n_sets):
-        step(s)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t_start
-    ms_per_step = wall * 1e3 / args.steps
-    value = px_step / (wall / args.steps) / 1e6
-    log("headline: %.3f ms/step, %.0f Mpixel/s" % (ms_per_step, value))
-    # kernel durations of every timed launch, from the library's HIP events on
-    # the launch stream (launch 2k is step k's dilate, 2k+1 its fill-holes)
-    n_q = min(2 * args.steps, 64)   # the library keeps the marks of the last 64 launches
-    times = [ctx.launch_times(back) for back in range(n_q - 1, -1, -1)]
-    kd, kf = times[0::2], times[1::2]
-    # counters of one more (untimed) launch of each operation
-    spare_m = torch.from_numpy(marker).to(dev)
-    spare_i = torch.from_numpy(binary).to(dev)
-    ctx.dilate(spare_m, d_mask, 8, stream)
-    sd = ctx.last_stats()
-    ctx.fill_holes(spare_i, 8, stream)
-    sf = ctx.last_stats()
-
-    # parity of the last step against the oracle (whole tile, bit-exact)
-    parity = {"dilate": bool(np.array_equal(markers[-1].cpu().numpy(), oracle.recon_dilate(marker, mask, 8))),
-              "fill_holes": bool(np.array_equal(images[-1].cpu().numpy(), oracle.fill_holes(binary, 8)))}
-
-    avg = lambda xs, k: sum(x[k] for x in xs) / len(xs)
-    kernels = {"dilate": {"dense_pass_ms": avg(kd, "dense_ms"), "border_seed_ms": avg(kd, "seed_ms"),
-                          "revisit_drain_ms": avg(kd, "drain_ms"), "launch_ms": avg(kd, "total_ms"),
-                          "dense_visits": sd["dense_visits"], "revisits": sd["revisits"], "reruns": sd["reruns"],
-                          "queue_overflows": sd["queue_overflows"]},
-               "fill_holes": {"dense_pass_ms": avg(kf, "dense_ms"), "border_seed_ms": avg(kf, "seed_ms"),
-                              "revisit_drain_ms": avg(kf, "drain_ms"), "launch_ms": avg(kf, "total_ms"),
-                              "dense_visits": sf["dense_visits"], "revisits": sf["revisits"],
-                              "reruns": sf["reruns"],
-                              "queue_overflows": sf["queue_overflows"]}}
-    # dominant kernel of the step (by average duration) and its roofline.  The
-    # algorithmic bytes of a kernel: dense_pass reads mask and marker and writes
-    # the marker once per pixel (3 B/px; fill-holes 2 B/px, its marker is
-    # implicit); a revisit reads a block's mask and marker and writes it back
-    # (3 B/px of the block per visit).
-    bh = cfg.get("block_rows", 32)
-    # (the persistent pipeline makes every block's first visit inside
-    # revisit_drain too: its visits are first visits + revisits)
-    cand = [("dense_pass (dilate)", kernels["dilate"]["dense_pass_ms"], BYTES_DILATE * mask.size),
-            ("revisit_drain (dilate)", kernels["dilate"]["revisit_drain_ms"],
-             3.0 * bh * 256 * (kernels["dilate"]["revisits"] + kernels["dilate"]["dense_visits"])),
-            ("dense_pass (fill_holes)", kernels["fill_holes"]["dense_pass_ms"], BYTES_FILL * mask.size),
-            ("revisit_drain (fill_holes)", kernels["fill_holes"]["revisit_drain_ms"],
-             3.0 * bh * 256 * (kernels["fill_holes"]["revisits"] + kernels["fill_holes"]["dense_visits"]))]
-    dom = max(cand, key=lambda c: c[1])
-    achieved = dom[2] / (dom[1] * 1e-3) / 1e9
-    traffic = committed_traffic(dom[0])
-    roofline = {"kernel": dom[0], "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "algorithmic_bytes": dom[2],
-                "kernel_ms": dom[1],
-                "step_GBs": (BYTES_DILATE + BYTES_FILL) * mask.size / (ms_per_step * 1e-3) / 1e9,
-                "kernel_source": kernel_sha()}
+    main = headline(recon, torch, cfg, marker, mask, binary, args.steps, args.warmup, args.step_mode)
+    ms_per_step, value, kernels, parity, roofline = (main[k] for k in ("ms_per_step", "value", "kernels", "parity",
+                                                                        "roofline"))
+    how = ("both in one batched launch per tile" if args.step_mode == "batched"
+           else "as two plain per-tile launches")
     out = {"metric": METRIC, "value": value, "unit": "Mpixel/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "u8", "data": "synthetic",
            "config": {"workload": "one uint8 %dx%d nuclei-like tile: 8-conn reconstruction (marker I-20) + "
-                                  "8-conn fill-holes of I>120; plain per-tile launches" % (args.size, args.size),
-                      "pixels_per_step": px_step, "block_rows": cfg.get("block_rows", 32)},
+                                  "8-conn fill-holes of I>120, %s" % (args.size, args.size, how),
+                      "pixels_per_step": 2 * mask.size, "block_rows": cfg.get("block_rows", 32)},
            "kernels": kernels, "roofline": roofline, "parity": parity}
-    ctx.close()
+    if args.step_mode == "batched" and args.plain_steps:
+        # the same step as two plain per-tile calls, with each operation's kernels
+        plain = headline(recon, torch, cfg, marker, mask, binary, args.plain_steps, args.warmup, "plain")
+        out["plain_per_op"] = {k: plain[k] for k in ("ms_per_step", "value", "kernels", "parity")}
+        out["plain_per_op"]["roofline_dominant"] = {k: plain["roofline"][k] for k in
+                                                    ("kernel", "achieved", "frac", "traffic", "kernel_ms")}
     if args.next_ops_steps:
         out["next_ops"] = next_ops(recon, torch, mask, args.next_ops_steps)
     if args.label_steps:

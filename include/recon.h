@@ -232,7 +232,9 @@ int recon_distance(recon_ctx *ctx, const recon_image *img, int32_t *dist2, int64
 int recon_pre_watershed(recon_ctx *ctx, recon_image *img, int conn, void *stream);
 
 /* Run n tasks (any mix of ops, shapes and connectivities) in one persistent
- * launch sequence, replayed from a HIP graph.  Enqueued on `stream`. */
+ * launch sequence, replayed from a HIP graph (a context created with timing = 1
+ * launches batches of at most 12 tasks directly instead, so that each of their
+ * kernels is timed).  Enqueued on `stream`. */
 int recon_batch(recon_ctx *ctx, const recon_task *tasks, int32_t n, void *stream);
 
 /* Serving: admit one task into the resident request loop.  On success

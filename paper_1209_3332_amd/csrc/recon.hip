@@ -1061,7 +1061,10 @@ int recon_batch(recon_ctx *ctx, const recon_task *tasks, int32_t n, void *stream
             return fail(rc, "task %d: %s", k, m.c_str());
         }
     }
-    return run_tasks(ctx, tasks, n, (hipStream_t)stream, true);
+    // a timing context launches small batches directly (every kernel timed);
+    // otherwise batches replay the captured graph
+    const bool use_graph = !(ctx->cfg.timing && n <= rk::MAX_INLINE_TASKS);
+    return run_tasks(ctx, tasks, n, (hipStream_t)stream, use_graph);
 }
 
 // Durations (ms) of a recent launch from its timing marks: K1, K2, K3, whole

@@ -298,3 +298,22 @@ def test_argument_errors(torch_mod, rc, lib):
         rc.dilate(a, a, 8)  # marker and mask overlap
     with pytest.raises(lib.ReconError):
         rc.fill_holes(a, 5)
+
+
+def test_small_batch_in_timing_context(torch_mod, lib, oracle_mod):
+    """A timing context launches a batch of at most 12 tasks directly: every
+    kernel is timed, and the bytes equal the oracle's (the headline step runs
+    a tile's reconstruction and fill-holes this way)."""
+    marker, mask, binary = synth.config2_tile(seed=synth.seed_for(2, 14), size=1024, n_gauss=188)
+    with lib.Recon(0, timing=1) as ctx:
+        for rep in range(2):
+            m, k, b = dev(torch_mod, marker), dev(torch_mod, mask), dev(torch_mod, binary)
+            ctx.batch([{"op": "dilate", "image": m, "mask": k, "conn": 8},
+                       {"op": "fill_holes", "image": b, "conn": 8}])
+            st = ctx.last_stats()
+            assert st["drain_ms"] > 0 and st["total_ms"] >= st["drain_ms"]
+            assert st["dense_visits"] == 2 * 32 * 4
+            t = ctx.launch_times(0)
+            assert t["drain_ms"] == st["drain_ms"]
+            assert_same(m.cpu().numpy(), oracle_mod.recon_dilate(marker, mask, 8), "batched dilate %d" % rep)
+            assert_same(b.cpu().numpy(), oracle_mod.fill_holes(binary, 8), "batched fill %d" % rep)
