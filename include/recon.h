@@ -204,7 +204,8 @@ int recon_regional_max(recon_ctx *ctx, recon_image *img, int conn, void *stream)
  * order of each component's first pixel, 0 on the background.  `labels` is a
  * DEVICE int32 plane of height rows and label_pitch >= width elements per row,
  * owned by the caller and used as the union-find workspace while the work
- * runs; height * label_pitch must stay below 2^31.  conn (4 or 8) is the
+ * runs; it must not overlap the image; height * label_pitch must stay below
+ * 2^31.  conn (4 or 8) is the
  * foreground connectivity.  If `count` (a DEVICE int32) is not NULL it
  * receives n.  The image is not written.  Enqueued on `stream`. */
 int recon_label(recon_ctx *ctx, const recon_image *img, int32_t *labels, int64_t label_pitch, int conn,
@@ -221,8 +222,8 @@ int recon_area_threshold(recon_ctx *ctx, recon_image *img, int conn, int64_t min
 /* Exact squared Euclidean distance transform of `img`: dist2[y * dist_pitch
  * + x] <- the squared distance from (y, x) to the nearest 0 pixel of the image
  * (0 on 0 pixels; 2^31 - 1 if the image has no 0 pixel).  `dist2` is a DEVICE
- * int32 plane (dist_pitch >= width elements per row) owned by the caller;
- * height and width at most 16384.  Enqueued on `stream`. */
+ * int32 plane (dist_pitch >= width elements per row) owned by the caller,
+ * not overlapping the image; height and width at most 16384.  Enqueued on `stream`. */
 int recon_distance(recon_ctx *ctx, const recon_image *img, int32_t *dist2, int64_t dist_pitch, void *stream);
 
 /* Pre-Watershed markers of `img`, in place: 255 on the regional maxima

@@ -848,6 +848,16 @@ static void label_layout(int h, int w, int64_t pitch_lab, uint32_t &n_words, uin
     bytes = round_up((size_t)n_words * 4, 256) * 2 + round_up((size_t)n_segs * 4, 256);
 }
 
+// true if the int32 plane (h rows of pitch elements, w used) overlaps the image's bytes
+static bool plane_overlaps(const recon_image &img, const int32_t *plane, int64_t pitch) {
+    recon_image p{};
+    p.data = (uint8_t *)plane;
+    p.height = img.height;
+    p.width = img.width * 4;
+    p.pitch = pitch * 4;
+    return overlaps(img, p);
+}
+
 static int check_label_args(const recon_image *img, int64_t pitch_lab, int conn) {
     int rc = check_image(img, "image");
     if (rc) return rc;
@@ -910,6 +920,7 @@ int recon_label(recon_ctx *ctx, const recon_image *img, int32_t *labels, int64_t
     if (!labels) return fail(RECON_EINVAL, "null label plane");
     int rc = check_label_args(img, label_pitch, conn);
     if (rc) return rc;
+    if (plane_overlaps(*img, labels, label_pitch)) return fail(RECON_EINVAL, "label plane and image overlap");
     rc = ensure_device(ctx);
     if (rc) return rc;
     uint32_t nw = 0, ns = 0;
@@ -1001,6 +1012,7 @@ int recon_distance(recon_ctx *ctx, const recon_image *img, int32_t *dist2, int64
     if (rc) return rc;
     if (dist_pitch < img->width)
         return fail(RECON_EINVAL, "distance pitch %lld < width %d", (long long)dist_pitch, img->width);
+    if (plane_overlaps(*img, dist2, dist_pitch)) return fail(RECON_EINVAL, "distance plane and image overlap");
     rc = ensure_device(ctx);
     if (rc) return rc;
     rc = ensure_capacity(ctx, 0, 0, edt_summary_bytes(img->height, img->width));

@@ -134,5 +134,7 @@ def test_argument_errors(torch_mod, rc, lib):
     wide = lib.recon_image(img.data_ptr(), 1, 20000, 20000)                                        # too wide
     assert L.recon_distance(rc.ctx, ctypes.byref(wide), d.data_ptr(), 20000, None) == lib.RECON_EINVAL
     assert L.recon_pre_watershed(rc.ctx, ctypes.byref(wide), 8, None) == lib.RECON_EINVAL
+    alias = lib.recon_image(d.data_ptr(), 4, 5, 20)       # the image inside the distance plane
+    assert L.recon_distance(rc.ctx, ctypes.byref(alias), d.data_ptr(), 5, None) == lib.RECON_EINVAL
     with pytest.raises(TypeError):
         rc.distance(img, torch_mod.zeros((4, 5), dtype=torch_mod.int64, device="cuda"))

@@ -169,6 +169,9 @@ def test_argument_errors(torch_mod, rc, lib):
     import ctypes
     m = lib.image_of(img)
     assert lib.load_library().recon_label(rc.ctx, ctypes.byref(m), lab.data_ptr(), 3, 8, None, None) == lib.RECON_EINVAL
+    alias = lib.recon_image(lab.data_ptr(), 4, 5, 20)     # the image inside the label plane
+    assert lib.load_library().recon_label(rc.ctx, ctypes.byref(alias), lab.data_ptr(), 5, 8, None,
+                                          None) == lib.RECON_EINVAL
     rc.label(img, lab, 8)                        # nothing was enqueued by the failures
     torch_mod.cuda.synchronize()
     assert int(lab.abs().sum()) == 0
