@@ -202,9 +202,13 @@ def headline(recon, torch, cfg, marker, mask, binary, steps, warmup, mode):
              3.0 * bh * 256 * (kv["revisits"] + kv["dense_visits"])) for name, kv in kernels.items()]
     dom = max(cand, key=lambda c: c[1])
     achieved = dom[2] / (dom[1] * 1e-3) / 1e9
+    traffic = committed_traffic(dom[0])
     roofline = {"kernel": dom[0], "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": committed_traffic(dom[0]), "algorithmic_bytes": dom[2],
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "algorithmic_bytes": dom[2],
                 "kernel_ms": dom[1],
+                # counted bandwidth: the profiled HBM bytes of one launch over the live kernel time
+                "counted_GBs": traffic / (dom[1] * 1e-3) / 1e9 if traffic else None,
+                "counted_frac": traffic / (dom[1] * 1e-3) / 1e9 / HBM_PEAK_GBS if traffic else None,
                 "step_GBs": (BYTES_DILATE + BYTES_FILL) * mask.size / (ms_per_step * 1e-3) / 1e9,
                 "kernel_source": kernel_sha()}
     return {"ms_per_step": ms_per_step, "value": value, "kernels": kernels, "parity": parity, "roofline": roofline}

@@ -317,3 +317,15 @@ def test_small_batch_in_timing_context(torch_mod, lib, oracle_mod):
             assert t["drain_ms"] == st["drain_ms"]
             assert_same(m.cpu().numpy(), oracle_mod.recon_dilate(marker, mask, 8), "batched dilate %d" % rep)
             assert_same(b.cpu().numpy(), oracle_mod.fill_holes(binary, 8), "batched fill %d" % rep)
+
+
+def test_max_size_tile(torch_mod, rc, oracle_mod):
+    """The largest tile of the tests: 16384 x 16384 (268 Mpx per plane, 65536
+    blocks), the nuclei generator scaled to its area; reconstruction and
+    fill-holes compared with the oracle over the whole tile."""
+    mask = synth.scaled_config1_tile(16384, 16384, synth.seed_for(6, 0))
+    marker = synth.hdome_marker(mask, 30)
+    assert_same(gpu_dilate(torch_mod, rc, marker, mask, 8), oracle_mod.recon_dilate(marker, mask, 8),
+                "16384 nuclei dilate")
+    binary = np.where(mask > 120, 255, 0).astype(np.uint8)
+    assert_same(gpu_fill(torch_mod, rc, binary, 8), oracle_mod.fill_holes(binary, 8), "16384 fill")
