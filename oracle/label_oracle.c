@@ -28,7 +28,7 @@
  * and labels the whole component from it by a breadth-first flood over the
  * connectivity's neighbours (an explicit FIFO of pixel indices), so labels
  * come out in raster order of first pixels by construction.  The area filter
- * counts the pixels of every label, then writes each pixel's verdict.
+ * counts the pixels of every label, then writes each pixel's result.
  */
 #include <stdint.h>
 #include <stdlib.h>
