@@ -643,6 +643,8 @@ def main():
     ap.add_argument("--block-rows", type=int, default=0)
     ap.add_argument("--scan-rounds", type=int, default=0)
     ap.add_argument("--queue", type=int, default=0)
+    ap.add_argument("--drain-budget", type=int, default=0, help="context knob (0 = library default)")
+    ap.add_argument("--binary-drain-budget", type=int, default=0, help="context knob (0 = library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only copy this many bytes device-to-device 5 times (counter calibration) and exit")
@@ -676,6 +678,10 @@ def main():
         cfg["scan_rounds"] = args.scan_rounds
     if args.queue:
         cfg["queue_capacity"] = args.queue
+    if args.drain_budget:
+        cfg["drain_budget"] = args.drain_budget
+    if args.binary_drain_budget:
+        cfg["binary_drain_budget"] = args.binary_drain_budget
     main = headline(recon, torch, cfg, marker, mask, binary, args.steps, args.warmup, args.step_mode)
     ms_per_step, value, kernels, roofline = (main[k] for k in ("ms_per_step", "value", "kernels", "roofline"))
     parity = {"dilate": None, "fill_holes": None}   # filled by the oracle leg
