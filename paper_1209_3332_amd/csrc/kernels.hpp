@@ -964,6 +964,11 @@ __device__ bool drain(Lds<BH> &L, int qcap, uint32_t &head, uint32_t &tail, bool
 // SWEEP_FALLBACKS times.  A first visit has had its sweep rounds already and
 // drains to the end.
 constexpr int SWEEP_FALLBACKS = 4;
+// A border seed that queues at least this many pixels (a wave's worth) is a
+// wide front entering the block: it goes straight to a sweep round, which
+// carries a front across the block in one pass, instead of draining it one
+// pixel step per round first.
+constexpr uint32_t WIDE_FRONT = 64;
 
 template <int BH, int CONN>
 __device__ bool converge_block(Lds<BH> &L, int qcap, WaveStats &st, bool border_only, int bh, int bw,
@@ -978,7 +983,8 @@ __device__ bool converge_block(Lds<BH> &L, int qcap, WaveStats &st, bool border_
         else
             seed_pass<BH, CONN>(L, qcap, head, tail, overflow, changed);
         __syncthreads();
-        const bool drained = drain<BH, CONN>(L, qcap, head, tail, overflow, fallbacks > 0 ? budget : -1);
+        const bool wide = border_only && round == 0 && fallbacks > 0 && tail - head >= WIDE_FRONT;
+        const bool drained = !wide && drain<BH, CONN>(L, qcap, head, tail, overflow, fallbacks > 0 ? budget : -1);
         __syncthreads();
         if (!drained) {
             --fallbacks;
