@@ -967,12 +967,17 @@ constexpr int SWEEP_FALLBACKS = 4;
 // A border seed that queues at least this many pixels (a wave's worth) is a
 // wide front entering the block: it goes straight to a sweep round, which
 // carries a front across the block in one pass, instead of draining it one
-// pixel step per round first.
+// pixel step per round first.  That shortens the chains of visits a launch
+// waits on, at the price of the extra sweep work, so it is applied only when
+// the launch is latency-bound: at most WIDE_FRONT_LOAD blocks per wave of the
+// grid (a single tile); a launch with many more blocks than waves (a large
+// batch) is throughput-bound and drains first.
 constexpr uint32_t WIDE_FRONT = 64;
+constexpr uint32_t WIDE_FRONT_LOAD = 4;
 
 template <int BH, int CONN>
 __device__ bool converge_block(Lds<BH> &L, int qcap, WaveStats &st, bool border_only, int bh, int bw,
-                               int budget) {
+                               int budget, bool wide_first = false) {
     bool changed = false;
     int fallbacks = border_only ? SWEEP_FALLBACKS : 0;
     for (int round = 0; round <= (1 << 16); ++round) {   // each round raises pixels; bounded anyway
@@ -983,7 +988,7 @@ __device__ bool converge_block(Lds<BH> &L, int qcap, WaveStats &st, bool border_
         else
             seed_pass<BH, CONN>(L, qcap, head, tail, overflow, changed);
         __syncthreads();
-        const bool wide = border_only && round == 0 && fallbacks > 0 && tail - head >= WIDE_FRONT;
+        const bool wide = wide_first && border_only && round == 0 && fallbacks > 0 && tail - head >= WIDE_FRONT;
         const bool drained = !wide && drain<BH, CONN>(L, qcap, head, tail, overflow, fallbacks > 0 ? budget : -1);
         __syncthreads();
         if (!drained) {
@@ -1352,6 +1357,7 @@ __global__ __launch_bounds__(64) void revisit_drain(TaskTable tt, KArgs a) {
     const uint32_t ring_cap = ring_cap_of(tt);
     WaveStats st;
     int keep = -1;   // block this wave requested and keeps for its next visit
+    const bool wide_first = total_blocks_of(tt) <= WIDE_FRONT_LOAD * gridDim.x;   // latency-bound launch
     {   // nothing was requested at all: no visit will ever complete, leave now
         uint32_t pend = 0;
         if (ln == 0) pend = __hip_atomic_load(&w->pending, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
@@ -1425,8 +1431,8 @@ __global__ __launch_bounds__(64) void revisit_drain(TaskTable tt, KArgs a) {
                 else
                     dense_block<BH, 4>(t, g, L, st);
             } else {       // the interior is converged: seed from the border
-                changed = t.conn == 8 ? converge_block<BH, 8>(L, t.qcap, st, true, g.bh, g.bw, budget)
-                                      : converge_block<BH, 4>(L, t.qcap, st, true, g.bh, g.bw, budget);
+                changed = t.conn == 8 ? converge_block<BH, 8>(L, t.qcap, st, true, g.bh, g.bw, budget, wide_first)
+                                      : converge_block<BH, 4>(L, t.qcap, st, true, g.bh, g.bw, budget, wide_first);
             }
             if (changed) {
                 store_block<BH, true>(t, g, L, dense);
