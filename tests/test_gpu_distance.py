@@ -138,3 +138,11 @@ def test_argument_errors(torch_mod, rc, lib):
     assert L.recon_distance(rc.ctx, ctypes.byref(alias), d.data_ptr(), 5, None) == lib.RECON_EINVAL
     with pytest.raises(TypeError):
         rc.distance(img, torch_mod.zeros((4, 5), dtype=torch_mod.int64, device="cuda"))
+
+
+def test_widest_rows(torch_mod, rc, oracle_mod):
+    """Rows of the largest width (16384: a row of column distances fills 64 KiB of LDS)."""
+    rng = np.random.default_rng(16384)
+    img = np.where(rng.random((9, 16384)) < 0.995, 255, 0).astype(np.uint8)
+    assert_same(gpu_distance(torch_mod, rc, img), oracle_mod.distance2(img), "16384-wide dist2")
+    assert_same(gpu_markers(torch_mod, rc, img, 8), oracle_mod.pre_watershed(img, 8), "16384-wide markers")

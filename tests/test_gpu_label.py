@@ -175,3 +175,14 @@ def test_argument_errors(torch_mod, rc, lib):
     rc.label(img, lab, 8)                        # nothing was enqueued by the failures
     torch_mod.cuda.synchronize()
     assert int(lab.abs().sum()) == 0
+
+
+def test_max_size_tile(torch_mod, rc, oracle_mod):
+    """The largest tile of the tests: 16384 x 16384, the binary nuclei image of
+    the generator scaled to its area (65536 tiles of 16 x 256)."""
+    mask = synth.scaled_config1_tile(16384, 16384, synth.seed_for(6, 1))
+    binary = np.where(mask > 60, 255, 0).astype(np.uint8)
+    n = check_label(torch_mod, rc, oracle_mod, binary, 8, "16384 nuclei labels")
+    assert n > 10000
+    assert np.array_equal(gpu_area(torch_mod, rc, binary, 20, 1000, 8),
+                          oracle_mod.area_threshold(binary, 20, 1000, 8)), "16384 area filter"
