@@ -145,15 +145,18 @@ __device__ __forceinline__ int img_aligned(const LabelArgs &a) {
     return (((uintptr_t)a.img | (uintptr_t)a.pitch_img) & 3u) == 0;
 }
 
-// inclusive prefix maximum over the 64 lanes of a wave
-__device__ __forceinline__ int wave_prefix_max(int v) {
-    const int ln = lane_id();
-#pragma unroll
-    for (int d = 1; d < LANES; d <<= 1) {
-        const int o = (int)__shfl_up((uint32_t)v, (unsigned)d);
-        if (ln >= d) v = max(v, o);
-    }
-    return v;
+// inclusive prefix maximum over the 64 lanes of a wave (unsigned values; 0
+// is the identity): DPP row shifts inside each 16-lane row, then the totals of
+// the rows before through readlane
+__device__ __forceinline__ uint32_t wave_prefix_max(uint32_t v) {
+    v = max(v, dpp_or<DPP_ROW_SHR + 1>(0u, v));
+    v = max(v, dpp_or<DPP_ROW_SHR + 2>(0u, v));
+    v = max(v, dpp_or<DPP_ROW_SHR + 4>(0u, v));
+    v = max(v, dpp_or<DPP_ROW_SHR + 8>(0u, v));
+    const uint32_t r0 = (uint32_t)__builtin_amdgcn_readlane((int)v, 15);
+    const uint32_t r1 = max(r0, (uint32_t)__builtin_amdgcn_readlane((int)v, 31));
+    const uint32_t r2 = max(r1, (uint32_t)__builtin_amdgcn_readlane((int)v, 47));
+    return max(v, sel_row(lane_id() >> 4, 0u, r0, r1, r2));
 }
 
 // Phase 1: tile-local labelling.  Grid: one 64-lane workgroup per tile
@@ -194,9 +197,9 @@ __global__ __launch_bounds__(64) void label_local(LabelArgs a) {
                 if (!f) lb = c + k;
                 lbk[k] = lb;
             }
-            const int incl = wave_prefix_max(lb);
-            int excl = (int)__shfl_up((uint32_t)incl, 1u);
-            if (ln == 0) excl = -1;
+            // last background column before this lane (-1: none), through
+            // values shifted by one so that 0 is the identity
+            const int excl = (int)from_lower(wave_prefix_max((uint32_t)(lb + 1))) - 1;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 const uint32_t i = (uint32_t)(r * LT_W + c + k);
