@@ -1,8 +1,9 @@
 /*
  * recon.h -- C ABI of librecon: grayscale morphological reconstruction by
- * dilation and by erosion, and the operations built on it (fill-holes,
- * h-dome, regional maxima), on uint8 image tiles, for AMD Instinct MI355X
- * (gfx950).
+ * dilation and by erosion and the operations built on it (fill-holes, h-dome,
+ * regional maxima), connected-component labelling with the area filter, and
+ * the exact distance transform with the Pre-Watershed markers, on uint8 image
+ * tiles, for AMD Instinct MI355X (gfx950).
  *
  * What is computed
  * ----------------
@@ -32,8 +33,6 @@
  * * the h-dome D_h(I) = I - rho_I(max(I - h, 0)), 1 <= h <= 255;
  * * the regional maxima of I: 255 where D_1(I) > 0, else 0 (a plateau of
  *   value 0 is never one).
- * The marker max(I - h, 0) of the h-dome is the marker form of the
- * reconstruction the paper's benchmark tiles are quoted with.
  *
  * BWLabel and AreaThreshold (Table 1) are provided too: the connected
  * components of the nonzero pixels (4- or 8-connectivity, pixels outside the
@@ -56,7 +55,10 @@
  *   ticket) has completed.
  * * Results are written in place: into the marker (recon_dilate,
  *   recon_erode) or the image (recon_fill_holes, recon_hdome,
- *   recon_regional_max).  The marker and the mask must not overlap.
+ *   recon_regional_max, recon_area_threshold, recon_pre_watershed); labels
+ *   and distances go into an int32 plane the caller passes (recon_label,
+ *   recon_distance).  The marker and the mask must not overlap, nor an int32
+ *   plane and its image.
  * * `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
  *   device work is enqueued asynchronously on it; the call returns once the
  *   work is enqueued.
