@@ -29,8 +29,10 @@
 
 namespace rk {
 
+typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+
 constexpr int32_t EDT_NONE = 0x3fffffff;   // no 0 pixel in the column
-constexpr int EDT_SEG = 32;                // rows per column segment (held in registers)
+constexpr int EDT_SEG = 16;                // rows per column segment (held in registers)
 constexpr int EDT_MAX_W = 16384;           // widest row staged in LDS (64 KiB)
 
 struct EdtArgs {
@@ -47,9 +49,37 @@ struct EdtArgs {
 };
 
 // Column-segment summaries.  Grid-stride over (segment, column), consecutive
-// threads on consecutive columns.
+// threads on consecutive columns; with dword-aligned rows a thread takes 4
+// adjacent columns at once (dword loads).
 __global__ void edt_zeros(EdtArgs a) {
     const int64_t n_seg = (a.h + EDT_SEG - 1) / EDT_SEG;
+    if (((((uintptr_t)a.img) | (uintptr_t)a.pitch_img | (uintptr_t)a.w) & 3u) == 0) {
+        const int w4 = a.w / 4;
+        const int64_t n4 = n_seg * w4;
+        for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n4; q += (int64_t)gridDim.x * blockDim.x) {
+            const int x = (int)(q % w4) * 4;
+            const int64_t s = q / w4;
+            const int y0 = (int)s * EDT_SEG;
+            const RK_GLOBAL uint32_t *col = (const RK_GLOBAL uint32_t *)(gp(a.img) + x);
+            uint32_t v[EDT_SEG];
+#pragma unroll
+            for (int r = 0; r < EDT_SEG; ++r)
+                v[r] = y0 + r < a.h ? col[(int64_t)(y0 + r) * (a.pitch_img / 4)] : 0x01010101u;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                int first = -1, last = -1;
+#pragma unroll
+                for (int r = 0; r < EDT_SEG; ++r)
+                    if (((v[r] >> (8 * c)) & 0xffu) == 0u) {
+                        if (first < 0) first = y0 + r;
+                        last = y0 + r;
+                    }
+                a.zfirst[s * a.w + x + c] = first;
+                a.zlast[s * a.w + x + c] = last;
+            }
+        }
+        return;
+    }
     const int64_t n = n_seg * a.w;
     for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
         const int x = (int)(q % a.w);
@@ -71,9 +101,78 @@ __global__ void edt_zeros(EdtArgs a) {
 }
 
 // Column pass.  Grid-stride over (segment, column) with consecutive threads on
-// consecutive columns (coalesced byte loads and int32 stores).
+// consecutive columns (coalesced byte loads and int32 stores); with dword-
+// aligned image rows a thread takes 4 adjacent columns at once (dword loads,
+// and 16-byte stores where the distance plane allows them).
 __global__ void edt_cols(EdtArgs a) {
     const int n_seg = (a.h + EDT_SEG - 1) / EDT_SEG;
+    if (((((uintptr_t)a.img) | (uintptr_t)a.pitch_img | (uintptr_t)a.w) & 3u) == 0) {
+        const int w4 = a.w / 4;
+        const int64_t n4 = (int64_t)n_seg * w4;
+        const bool vec = ((((uintptr_t)a.g) | (uintptr_t)(a.pitch_g * 4)) & 15u) == 0;
+        for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n4; q += (int64_t)gridDim.x * blockDim.x) {
+            const int x = (int)(q % w4) * 4;
+            const int s = (int)(q / w4);
+            const int y0 = s * EDT_SEG, y1 = min(a.h, y0 + EDT_SEG);
+            const RK_GLOBAL uint32_t *col = (const RK_GLOBAL uint32_t *)(gp(a.img) + x);
+            uint32_t v[EDT_SEG];
+#pragma unroll
+            for (int r = 0; r < EDT_SEG; ++r)
+                v[r] = y0 + r < a.h ? col[(int64_t)(y0 + r) * (a.pitch_img / 4)] : 0x01010101u;
+            int g[EDT_SEG][4];
+            const int last = y1 - 1 - y0;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                int above = EDT_NONE, below = EDT_NONE;
+                for (int t = s - 1; t >= 0; --t) {
+                    const int z = a.zlast[(int64_t)t * a.w + x + c];
+                    if (z >= 0) {
+                        above = y0 - z;
+                        break;
+                    }
+                }
+                for (int t = s + 1; t < n_seg; ++t) {
+                    const int z = a.zfirst[(int64_t)t * a.w + x + c];
+                    if (z >= 0) {
+                        below = z - (y1 - 1);
+                        break;
+                    }
+                }
+                int d = above;
+#pragma unroll
+                for (int r = 0; r < EDT_SEG; ++r) {
+                    if (((v[r] >> (8 * c)) & 0xffu) == 0u) d = 0;
+                    else if (r > 0 && d != EDT_NONE) d += 1;
+                    g[r][c] = d;
+                }
+                d = below;
+#pragma unroll
+                for (int r = EDT_SEG - 1; r >= 0; --r) {
+                    if (r > last) continue;
+                    if (((v[r] >> (8 * c)) & 0xffu) == 0u) d = 0;
+                    else if (r < last && d != EDT_NONE) d += 1;
+                    if (d < g[r][c]) g[r][c] = d;
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < EDT_SEG; ++r) {
+                if (y0 + r >= a.h) continue;
+                int32_t *row = a.g + (int64_t)(y0 + r) * a.pitch_g + x;
+                if (vec) {
+                    i32x4 o;
+                    o.x = g[r][0];
+                    o.y = g[r][1];
+                    o.z = g[r][2];
+                    o.w = g[r][3];
+                    *(RK_GLOBAL i32x4 *)row = o;
+                } else {
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) ((RK_GLOBAL int32_t *)row)[c] = g[r][c];
+                }
+            }
+        }
+        return;
+    }
     const int64_t n = (int64_t)n_seg * a.w;
     for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
         const int x = (int)(q % a.w);

@@ -310,7 +310,8 @@ static int emu_label(const uint8_t *img_in, int h, int w, int conn, int n_waves,
 
 static int emu_edt(const uint8_t *img_in, int h, int w, int mode, int n_waves, int32_t *d2_out, uint8_t *d8_out) {
     using namespace rk;
-    const int64_t pitch_img = w + 1, pitch_g = w + 2;   // padded pitches, exact-size allocations
+    // padded pitches, exact-size allocations; widths divisible by 4 take the dword path
+    const int64_t pitch_img = w % 4 == 0 ? w + 4 : w + 1, pitch_g = w % 4 == 0 ? w + 4 : w + 2;
     std::vector<uint8_t> img((size_t)(h - 1) * pitch_img + w);
     for (int y = 0; y < h; ++y) std::memcpy(&img[(size_t)y * pitch_img], img_in + (size_t)y * w, w);
     std::vector<int32_t> g((size_t)(h - 1) * pitch_g + w, -5);
