@@ -620,6 +620,15 @@ __device__ __forceinline__ void side_bytes(Lds<BH> &L, int y, uint32_t v, uint32
     right = ln == LANES - 1 ? (uint32_t)L.Jb(y, BW) : (dn & 0xffu);
 }
 
+// the same with the row's two halo bytes (hl = pixel -1, hr = pixel BW) given
+__device__ __forceinline__ void side_from(uint32_t v, uint32_t hl, uint32_t hr, uint32_t &left, uint32_t &right) {
+    const int ln = lane_id();
+    const uint32_t up = from_lower(v);
+    const uint32_t dn = from_upper(v);
+    left = ln == 0 ? hl : (up >> 24);
+    right = ln == LANES - 1 ? hr : (dn & 0xffu);
+}
+
 // ---------------------------------------------------------------------------
 // Directional sweeps with row closure.
 //
@@ -740,6 +749,11 @@ __device__ uint32_t row_closure(uint32_t lo4, uint32_t hi4, uint32_t vl, uint32_
 // then closed along its length, with the halo pixels at both ends as inputs.
 // This is a raster (or anti-raster) pass in which every row run is complete.
 // Returns true if anything changed.
+//
+// The row's own loads do not depend on the row before it (only row r is
+// written while row r is closed), so each row's marker, mask and halo bytes are
+// read one row ahead and their latency overlaps the closure of the row before.
+// After the last block row the read-ahead lands on the halo row, which exists.
 template <int BH, int CONN>
 __device__ bool sweep(Lds<BH> &L, int dir) {
     constexpr int conn = CONN;
@@ -749,24 +763,31 @@ __device__ bool sweep(Lds<BH> &L, int dir) {
     uint32_t prev = *L.Jw(rprev, ln);
     uint32_t pl, pr;
     side_bytes(L, rprev, prev, pl, pr);
+    uint32_t ncur = *L.Jw(r0, ln), nhi = *L.Iw(r0, ln);
+    uint32_t nvl = L.Jb(r0, -1), nvr = L.Jb(r0, BW);
     bool changed = false;
     for (int k = 0; k < BH; ++k) {
         const int r = r0 + dir * k;
-        const uint32_t cur = *L.Jw(r, ln);
-        const uint32_t hi = *L.Iw(r, ln);
+        const uint32_t cur = ncur, hi = nhi, vl = nvl, vr = nvr;
+        const int rn = r + dir;   // -1 .. BH
+        ncur = *L.Jw(rn, ln);
+        nhi = *L.Iw(rn, ln);
+        nvl = L.Jb(rn, -1);
+        nvr = L.Jb(rn, BW);
+        __builtin_amdgcn_sched_barrier(0);   // keep the read-ahead issued here, before the closure
         uint32_t m = bmax4(cur, prev);
         if (conn == 8) {
             m = bmax4(m, (prev << 8) | pl);
             m = bmax4(m, (prev >> 8) | (pr << 24));
         }
-        const uint32_t nv = row_closure(bmin4(m, hi), hi, L.Jb(r, -1), L.Jb(r, BW));
+        const uint32_t nv = row_closure(bmin4(m, hi), hi, vl, vr);
         if (nv != cur) {
             *L.Jw(r, ln) = nv;
             L.rowdirty[r] = 1;
             changed = true;
         }
         prev = nv;
-        side_bytes(L, r, prev, pl, pr);
+        side_from(prev, vl, vr, pl, pr);
     }
     return changed;
 }
@@ -794,26 +815,33 @@ __device__ __forceinline__ volatile RK_LDS uint8_t &jv(Lds<BH> &L, int y, int x)
 }
 
 // Seed pass: raise every pixel that a neighbour (block or halo) can raise and push it.
+// Rows r-1, r and r+1 are carried from one row to the next (row r+1 is not
+// written while row r is seeded, row r is carried as written), so each row
+// reads one new marker row, read a row ahead, and its mask row.
 template <int BH, int CONN>
 __device__ void seed_pass(Lds<BH> &L, int qcap, uint32_t head, uint32_t &tail,
                           bool &overflow, bool &changed) {
     constexpr int conn = CONN;
     const int ln = lane_id();
+    uint32_t a = *L.Jw(-1, ln), c = *L.Jw(0, ln), b = *L.Jw(1, ln);
+    uint32_t ahl = L.Jb(-1, -1), ahr = L.Jb(-1, BW), chl = L.Jb(0, -1), chr = L.Jb(0, BW);
+    uint32_t bhl = L.Jb(1, -1), bhr = L.Jb(1, BW);
     for (int r = 0; r < BH; ++r) {
-        const uint32_t a = *L.Jw(r - 1, ln);
-        const uint32_t c = *L.Jw(r, ln);
-        const uint32_t b = *L.Jw(r + 1, ln);
+        const int rn = min(r + 2, BH);   // the row after b (the halo row at most)
+        const uint32_t nb = *L.Jw(rn, ln), nbhl = L.Jb(rn, -1), nbhr = L.Jb(rn, BW);
+        const uint32_t hi = *L.Iw(r, ln);
+        __builtin_amdgcn_sched_barrier(0);   // keep the read-ahead issued here
         uint32_t al, ar, cl, cr, bl, br;
-        side_bytes(L, r - 1, a, al, ar);
-        side_bytes(L, r, c, cl, cr);
-        side_bytes(L, r + 1, b, bl, br);
+        side_from(a, ahl, ahr, al, ar);
+        side_from(c, chl, chr, cl, cr);
+        side_from(b, bhl, bhr, bl, br);
         uint32_t m = bmax4(c, bmax4(a, b));
         m = bmax4(m, bmax4((c << 8) | cl, (c >> 8) | (cr << 24)));
         if (conn == 8) {
             m = bmax4(m, bmax4((a << 8) | al, (a >> 8) | (ar << 24)));
             m = bmax4(m, bmax4((b << 8) | bl, (b >> 8) | (br << 24)));
         }
-        const uint32_t nv = bmin4(m, *L.Iw(r, ln));
+        const uint32_t nv = bmin4(m, hi);
         const uint32_t dm = diff_bytes(nv, c);
         if (dm) {
             *L.Jw(r, ln) = nv;
@@ -826,6 +854,15 @@ __device__ void seed_pass(Lds<BH> &L, int qcap, uint32_t head, uint32_t &tail,
                 if (!push_bits(L.Q, qcap, head, tail, p, (uint32_t)(r * BW + 4 * ln + j))) overflow = true;
             }
         }
+        a = nv;
+        ahl = chl;
+        ahr = chr;
+        c = b;
+        chl = bhl;
+        chr = bhr;
+        b = nb;
+        bhl = nbhl;
+        bhr = nbhr;
     }
 }
 

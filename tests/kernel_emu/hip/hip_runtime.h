@@ -98,6 +98,8 @@ inline uint32_t __builtin_amdgcn_mbcnt_hi(uint32_t m, uint32_t acc) {
     return acc + (uint32_t)__builtin_popcount(below);
 }
 inline void __builtin_amdgcn_s_sleep(int) { std::this_thread::yield(); }
+// an instruction-scheduling hint for the compiler: no effect on what a wave computes
+inline void __builtin_amdgcn_sched_barrier(int) {}
 inline int __builtin_amdgcn_readfirstlane(int v) { return (int)(uint32_t)kemu::exchange((uint32_t)v, 0); }
 // DPP data movement as used by the kernels: row shifts (within 16-lane rows),
 // whole-wave shifts by one lane, and the row broadcasts.  A lane whose source
