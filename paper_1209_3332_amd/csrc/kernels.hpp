@@ -973,19 +973,30 @@ __device__ bool drain(Lds<BH> &L, int qcap, uint32_t &head, uint32_t &tail, bool
         uint32_t iv[CONN];
 #pragma unroll
         for (int k = 0; k < CONN; ++k) iv[k] = L.I[a + nb_dy(k) * JP + nb_dx(k)];
+        // Direction k's neighbour is read right after direction k-1's store (so
+        // it sees that raise), and direction k-1's push, which touches only the
+        // ring, is issued while that read is in flight.
+        bool prev_raised = false;
 #pragma unroll
         for (int k = 0; k < CONN; ++k) {
             const int off = nb_dy(k) * JP + nb_dx(k);
             const bool in = (nb_dy(k) < 0 ? ok_n : nb_dy(k) > 0 ? ok_s : valid) &&
                             (nb_dx(k) < 0 ? ok_w : nb_dx(k) > 0 ? ok_e : true);
             const uint32_t tgt = min(v, iv[k]);
-            const bool raised = in && (uint32_t)Jv[a + off] < tgt;
+            RK_LANE_SYNC();   // every lane's store of direction k-1 is issued before this read
+            const uint32_t cur = Jv[a + off];
+            if (k > 0 &&
+                !push_bits(L.Q, qcap, head, tail, prev_raised, p + (uint32_t)(nb_dy(k - 1) * BW + nb_dx(k - 1))))
+                overflow = true;
+            const bool raised = in && cur < tgt;
             if (raised) {
                 Jv[a + off] = (uint8_t)tgt;
                 L.rowdirty[y + nb_dy(k)] = 1;
             }
-            if (!push_bits(L.Q, qcap, head, tail, raised, p + (uint32_t)(nb_dy(k) * BW + nb_dx(k)))) overflow = true;
+            prev_raised = raised;
         }
+        if (!push_bits(L.Q, qcap, head, tail, prev_raised, p + (uint32_t)(nb_dy(CONN - 1) * BW + nb_dx(CONN - 1))))
+            overflow = true;
     }
     return true;
 }
