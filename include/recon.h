@@ -180,6 +180,24 @@ int recon_destroy(recon_ctx *ctx);
 int recon_dilate(recon_ctx *ctx, recon_image *marker, const recon_image *mask, int conn,
                  void *stream);
 
+/* recon_dilate for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same reconstruction, identical bytes, with the block scheduler's workspace
+ * (counters, one state word per block, the visit ring) in a fixed device array
+ * of the library (about 1.8 MB, held by every GPU the library runs on until
+ * the process ends) instead of the context's allocations.  This call issues
+ * no device or host allocation.  Limit: the image may have at most 8192
+ * blocks of block_rows x 256 pixels (a 4096 x 4096 image at block_rows 16 or
+ * more, 8192 x 8192 at 32 or more); larger images return RECON_EINVAL.  The
+ * context must run the persistent pipeline (stop_after_stage 0).  The fixed
+ * array is shared by every call on that GPU, from any context or thread, and
+ * keeps the last call's contents (each call resets what it uses): calls whose
+ * work overlaps in time on one GPU race and give wrong results, so order them
+ * on one stream or synchronise between them.  recon_last_stats reports the
+ * call's statistics until the next call on the device.  Enqueued on `stream`. */
+int recon_dilate_noalloc(recon_ctx *ctx, recon_image *marker, const recon_image *mask, int conn,
+                         void *stream);
+
 /* Fill-holes of `img`, in place.  conn (4 or 8) is the background
  * connectivity.  Enqueued on `stream`. */
 int recon_fill_holes(recon_ctx *ctx, recon_image *img, int conn, void *stream);

@@ -29,7 +29,7 @@ TWO_PLANE_OPS = ("dilate", "erode")   # marker and mask are two images
 
 # every symbol the C header declares
 EXPORTED = (
-    "recon_create", "recon_destroy", "recon_dilate", "recon_fill_holes", "recon_erode",
+    "recon_create", "recon_destroy", "recon_dilate", "recon_dilate_noalloc", "recon_fill_holes", "recon_erode",
     "recon_hdome", "recon_regional_max", "recon_label", "recon_area_threshold", "recon_distance",
     "recon_pre_watershed", "recon_batch",
     "recon_submit", "recon_poll", "recon_wait", "recon_serve_stop", "recon_last_stats",
@@ -95,6 +95,8 @@ def load_library(path: str = LIB_PATH):
     lib.recon_create.argtypes = [ctypes.POINTER(P), ctypes.c_int, ctypes.POINTER(recon_config)]
     lib.recon_destroy.argtypes = [P]
     lib.recon_dilate.argtypes = [P, ctypes.POINTER(recon_image), ctypes.POINTER(recon_image), ctypes.c_int, P]
+    lib.recon_dilate_noalloc.argtypes = [P, ctypes.POINTER(recon_image), ctypes.POINTER(recon_image),
+                                         ctypes.c_int, P]
     lib.recon_fill_holes.argtypes = [P, ctypes.POINTER(recon_image), ctypes.c_int, P]
     lib.recon_erode.argtypes = [P, ctypes.POINTER(recon_image), ctypes.POINTER(recon_image), ctypes.c_int, P]
     lib.recon_hdome.argtypes = [P, ctypes.POINTER(recon_image), ctypes.c_int, ctypes.c_int, P]
@@ -172,6 +174,12 @@ def recon_destroy(ctx: int) -> None:
 def recon_dilate(ctx: int, marker, mask, conn: int = 8, stream=None) -> None:
     m, k = image_of(marker), image_of(mask)
     _check(load_library().recon_dilate(ctx, ctypes.byref(m), ctypes.byref(k), int(conn), _stream_ptr(stream)))
+
+
+def recon_dilate_noalloc(ctx: int, marker, mask, conn: int = 8, stream=None) -> None:
+    m, k = image_of(marker), image_of(mask)
+    _check(load_library().recon_dilate_noalloc(ctx, ctypes.byref(m), ctypes.byref(k), int(conn),
+                                               _stream_ptr(stream)))
 
 
 def recon_fill_holes(ctx: int, img, conn: int = 8, stream=None) -> None:
@@ -318,6 +326,11 @@ class Recon:
     def dilate(self, marker, mask, conn: int = 8, stream=None):
         """In place: marker <- reconstruction by dilation of mask from marker."""
         recon_dilate(self.ctx, marker, mask, conn, stream)
+        return marker
+
+    def dilate_noalloc(self, marker, mask, conn: int = 8, stream=None):
+        """recon_dilate with the library's fixed device workspace (no allocation)."""
+        recon_dilate_noalloc(self.ctx, marker, mask, conn, stream)
         return marker
 
     def fill_holes(self, img, conn: int = 8, stream=None):

@@ -96,6 +96,26 @@ int wait_event(hipEvent_t ev, double seconds, const char *what) {
     }
 }
 
+// ---- the fixed workspace of recon_dilate_noalloc
+// A file-scope device array holds the scheduler workspace of one launch of at
+// most NOALLOC_MAX_BLOCKS blocks: the counters, the per-tile counts, one state
+// word per block and the visit ring.  Every GPU the library runs on holds its
+// own copy until the process ends.  Host code never passes the array's name to
+// a kernel (on the host it is only a stand-in for the symbol): recon_create
+// looks up each device's address once with hipGetSymbolAddress, and launches
+// use that address.
+constexpr size_t NOALLOC_MAX_BLOCKS = 8192;
+constexpr size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+constexpr size_t NOALLOC_TILE_OFF = align256(sizeof(rk::Work));
+constexpr size_t NOALLOC_STATE_OFF = NOALLOC_TILE_OFF + 256;   // tile_pending, tile_done
+constexpr size_t NOALLOC_RING_OFF =
+    NOALLOC_STATE_OFF + align256(NOALLOC_MAX_BLOCKS * rk::STATE_STRIDE * sizeof(uint32_t));
+constexpr size_t NOALLOC_BYTES =
+    NOALLOC_RING_OFF +
+    align256((NOALLOC_MAX_BLOCKS + rk::MAX_DRAIN_GRID + 1) * rk::RING_STRIDE * sizeof(uint32_t));
+
+__device__ __align__(256) uint8_t scratch[NOALLOC_BYTES];
+
 }  // namespace
 
 struct recon_ctx {
@@ -125,6 +145,8 @@ struct recon_ctx {
     bool tev_graph[kTimingRing] = {};   // that launch replayed a graph (only its total is marked)
     uint64_t launches = 0;              // launch sequences enqueued so far
     bool have_last = false;
+    rk::Work *last_work = nullptr;      // the counters of the last launch (context or fixed workspace)
+    uint8_t *noalloc = nullptr;         // this device's fixed workspace (recon_dilate_noalloc)
     bool last_was_graph = false;   // the last launch replayed a graph (only its total is timed)
     int resident[kVariants] = {0, 0, 0};
     // captured batch graphs per variant
@@ -185,17 +207,17 @@ void drop_graphs(recon_ctx *c) {
     }
 }
 
-// Grow the workspace to hold n_tasks tasks, n_blocks blocks and `scratch`
-// bytes of fill-holes planes.  Growing synchronises the device and drops the
+// Grow the workspace to hold n_tasks tasks, n_blocks blocks and `area_bytes`
+// bytes of scratch planes.  Growing synchronises the device and drops the
 // captured graphs (they hold the old pointers).
-int ensure_capacity(recon_ctx *c, size_t n_tasks, size_t n_blocks, size_t scratch) {
-    if (n_tasks <= c->cap_tasks && n_blocks <= c->cap_blocks && scratch <= c->cap_scratch)
+int ensure_capacity(recon_ctx *c, size_t n_tasks, size_t n_blocks, size_t area_bytes) {
+    if (n_tasks <= c->cap_tasks && n_blocks <= c->cap_blocks && area_bytes <= c->cap_scratch)
         return RECON_OK;
     HIP_TRY(hipDeviceSynchronize());
     drop_graphs(c);
     const size_t nt = std::max(c->cap_tasks, std::max<size_t>(n_tasks, 64));
     const size_t nb = std::max(c->cap_blocks, std::max<size_t>(n_blocks, 4096));
-    const size_t ns = std::max(c->cap_scratch, scratch);
+    const size_t ns = std::max(c->cap_scratch, area_bytes);
     free_workspace(c);
     const size_t table = sizeof(BatchHdr) + nt * sizeof(rk::TaskDev);
     if (hipMalloc(&c->d_table, table) != hipSuccess ||
@@ -322,15 +344,30 @@ void build_table(const recon_config &cfg, const recon_task *tasks, int n, int bh
     }
 }
 
+// The scheduler workspace a launch runs on: the context's (allocated by
+// ensure_capacity) or the fixed device array of recon_dilate_noalloc.
+struct Workspace {
+    rk::Work *work;
+    uint32_t *state;
+    uint32_t *ring;
+    uint32_t *tile_pending;
+    uint32_t *tile_done;
+    size_t cap_blocks;   // blocks the state words and the ring hold
+};
+
+Workspace ctx_workspace(const recon_ctx *c) {
+    return Workspace{c->d_work, c->d_state, c->d_ring, c->d_tile_pending, c->d_tile_done, c->cap_blocks};
+}
+
 // Enqueue the kernels of one launch sequence on `s`.
-int enqueue_kernels(recon_ctx *c, int v, const rk::TaskTable &tt, uint32_t total_blocks, bool any_mapped,
-                    bool dynamic_sizes, hipStream_t s) {
+int enqueue_kernels(recon_ctx *c, const Workspace &ws, int v, const rk::TaskTable &tt, uint32_t total_blocks,
+                    bool any_mapped, bool dynamic_sizes, hipStream_t s) {
     rk::KArgs ka;
-    ka.work = c->d_work;
-    ka.state = c->d_state;
-    ka.ring = c->d_ring;
-    ka.tile_pending = c->d_tile_pending;
-    ka.tile_done = c->d_tile_done;
+    ka.work = ws.work;
+    ka.state = ws.state;
+    ka.ring = ws.ring;
+    ka.tile_pending = ws.tile_pending;
+    ka.tile_done = ws.tile_done;
     ka.qcap = c->cfg.queue_capacity;
     ka.scan_rounds = c->cfg.scan_rounds;
     ka.watchdog_ticks = c->watchdog_ticks;
@@ -340,7 +377,7 @@ int enqueue_kernels(recon_ctx *c, int v, const rk::TaskTable &tt, uint32_t total
     const int resident = resident_wgs(c, v);
     // K1/K2 are grid-stride: with sizes known only on the device (captured
     // graphs), launch enough workgroups for the largest batch the workspace holds.
-    const uint32_t nblk = dynamic_sizes ? (uint32_t)c->cap_blocks : total_blocks;
+    const uint32_t nblk = dynamic_sizes ? (uint32_t)ws.cap_blocks : total_blocks;
     const int grid12 = (int)std::max<uint32_t>(1u, std::min<uint32_t>(nblk, 65535u));
     const int grid3 = std::max(1, std::min<int>(std::min(resident, rk::MAX_DRAIN_GRID),
                                                 (int)std::max<uint32_t>(1u, nblk)));
@@ -354,8 +391,8 @@ int enqueue_kernels(recon_ctx *c, int v, const rk::TaskTable &tt, uint32_t total
     const bool merged = stop == 0;
     hipEvent_t *tev = c->tev[c->launches % kTimingRing];
     if (timing) HIP_TRY(hipEventRecord(tev[5], s));
-    hipLaunchKernelGGL(rk::reset_work, dim3(64), dim3(256), 0, s, tt, c->d_work, c->d_state, c->d_ring,
-                       c->d_tile_pending, c->d_tile_done, merged ? 1 : 0);
+    hipLaunchKernelGGL(rk::reset_work, dim3(64), dim3(256), 0, s, tt, ws.work, ws.state, ws.ring,
+                       ws.tile_pending, ws.tile_done, merged ? 1 : 0);
     if (any_mapped) hipLaunchKernelGGL(rk::init_marker, dim3(1024), dim3(256), 0, s, tt);
     if (timing) HIP_TRY(hipEventRecord(tev[0], s));
 #define RK_LAUNCH(K, GRID)                                                                        \
@@ -388,10 +425,10 @@ int run_tasks(recon_ctx *c, const recon_task *tasks, int n, hipStream_t stream, 
     std::vector<rk::TaskDev> table;
     std::vector<char> uses_scratch;
     uint32_t total_blocks = 0;
-    size_t scratch = 0;
+    size_t scratch_need = 0;
     bool any_mapped = false;
-    build_table(c->cfg, tasks, n, bh, table, uses_scratch, total_blocks, scratch, any_mapped);
-    rc = ensure_capacity(c, (size_t)n, (size_t)total_blocks, scratch);
+    build_table(c->cfg, tasks, n, bh, table, uses_scratch, total_blocks, scratch_need, any_mapped);
+    rc = ensure_capacity(c, (size_t)n, (size_t)total_blocks, scratch_need);
     if (rc) return rc;
     for (int k = 0; k < n; ++k)
         if (uses_scratch[k]) {
@@ -436,7 +473,7 @@ int run_tasks(recon_ctx *c, const recon_task *tasks, int n, hipStream_t stream, 
             const uint32_t max_bytes = (uint32_t)(sizeof(BatchHdr) + c->cap_tasks * sizeof(rk::TaskDev));
             hipLaunchKernelGGL(rk::copy_table, dim3(16), dim3(256), 0, c->cap_stream, c->h_table, c->d_table,
                                max_bytes);
-            rc = enqueue_kernels(c, v, tt, total_blocks, true, true, c->cap_stream);
+            rc = enqueue_kernels(c, ctx_workspace(c), v, tt, total_blocks, true, true, c->cap_stream);
             hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
             if (rc) return rc;
             if (e != hipSuccess) return fail(RECON_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
@@ -458,11 +495,12 @@ int run_tasks(recon_ctx *c, const recon_task *tasks, int n, hipStream_t stream, 
                                table_bytes);
             HIP_TRY(hipEventRecord(c->table_used, stream));
         }
-        rc = enqueue_kernels(c, v, tt, total_blocks, any_mapped, false, stream);
+        rc = enqueue_kernels(c, ctx_workspace(c), v, tt, total_blocks, any_mapped, false, stream);
         if (rc) return rc;
     }
     HIP_TRY(hipEventRecord(c->last_done, stream));
     c->have_last = true;
+    c->last_work = c->d_work;
     c->last_was_graph = use_graph;
     c->tev_graph[c->launches % kTimingRing] = use_graph;
     c->launches += 1;
@@ -737,8 +775,12 @@ int recon_create(recon_ctx **out, int device, const recon_config *cfg) {
     if (c.serve_slots == 0) c.serve_slots = 256;
     e = hipSetDevice(device);
     if (e != hipSuccess) return fail(RECON_EDEVICE, "hipSetDevice failed: %s", hipGetErrorString(e));
+    // once per device, with it current: the self-test, and the address of this
+    // device's copy of the fixed workspace
     static std::mutex tested_mu;
     static std::vector<int> tested;
+    static std::unordered_map<int, uint8_t *> noalloc_ptr;
+    uint8_t *fixed = nullptr;
     {
         std::lock_guard<std::mutex> lk(tested_mu);
         if (std::find(tested.begin(), tested.end(), device) == tested.end()) {
@@ -747,10 +789,19 @@ int recon_create(recon_ctx **out, int device, const recon_config *cfg) {
                 std::string m = g_err;
                 return fail(rc, "device self-test failed: %s", m.c_str());
             }
+            void *ptr = nullptr;
+            e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !ptr)
+                return fail(RECON_EDEVICE, "hipGetSymbolAddress of the fixed workspace failed: %s",
+                            hipGetErrorString(e));
+            noalloc_ptr[device] = (uint8_t *)ptr;
             tested.push_back(device);
         }
+        fixed = noalloc_ptr[device];
     }
-    return make_ctx(out, device, c);
+    int rc = make_ctx(out, device, c);
+    if (rc == RECON_OK) (*out)->noalloc = fixed;
+    return rc;
 }
 
 int recon_destroy(recon_ctx *ctx) {
@@ -784,6 +835,60 @@ int recon_dilate(recon_ctx *ctx, recon_image *marker, const recon_image *mask, i
     int rc = check_task(t);
     if (rc) return rc;
     return run_tasks(ctx, &t, 1, (hipStream_t)stream, false);
+}
+
+int recon_dilate_noalloc(recon_ctx *ctx, recon_image *marker, const recon_image *mask, int conn, void *stream) {
+    if (!ctx) return fail(RECON_EINVAL, "null context");
+    if (!marker || !mask) return fail(RECON_EINVAL, "null image");
+    if (!ctx->noalloc) return fail(RECON_EDEVICE, "the fixed workspace of this device was not set up");
+    if (ctx->cfg.stop_after_stage != 0)
+        return fail(RECON_EINVAL, "recon_dilate_noalloc runs the persistent pipeline only (stop_after_stage = 0)");
+    recon_task t{};
+    t.op = RECON_OP_DILATE;
+    t.conn = conn;
+    t.image = *marker;
+    t.mask = *mask;
+    int rc = check_task(t);
+    if (rc) return rc;
+    const int bh = ctx->cfg.block_rows;
+    const size_t blocks = (size_t)((t.image.height + bh - 1) / bh) * (size_t)((t.image.width + rk::BW - 1) / rk::BW);
+    if (blocks > NOALLOC_MAX_BLOCKS)
+        return fail(RECON_EINVAL,
+                    "recon_dilate_noalloc: a %dx%d image has %zu blocks of %dx%d pixels, above the fixed "
+                    "workspace's %zu", t.image.height, t.image.width, blocks, bh, rk::BW, NOALLOC_MAX_BLOCKS);
+    rc = ensure_device(ctx);
+    if (rc) return rc;
+    std::vector<rk::TaskDev> table;
+    std::vector<char> uses_scratch;
+    uint32_t total_blocks = 0;
+    size_t scratch_bytes = 0;
+    bool any_mapped = false;
+    build_table(ctx->cfg, &t, 1, bh, table, uses_scratch, total_blocks, scratch_bytes, any_mapped);
+    uint8_t *base = ctx->noalloc;
+    Workspace ws;
+    ws.work = (rk::Work *)base;
+    ws.tile_pending = (uint32_t *)(base + NOALLOC_TILE_OFF);
+    ws.tile_done = ws.tile_pending + 1;
+    ws.state = (uint32_t *)(base + NOALLOC_STATE_OFF);
+    ws.ring = (uint32_t *)(base + NOALLOC_RING_OFF);
+    ws.cap_blocks = total_blocks;
+    rk::TaskTable tt{};
+    tt.hdr = nullptr;
+    tt.ext = nullptr;
+    tt.n_inline = 1;
+    tt.total_inline = total_blocks;
+    tt.ring_cap_inline = (uint32_t)ring_slots(total_blocks);
+    tt.inl[0] = table[0];
+    const hipStream_t s = (hipStream_t)stream;
+    rc = enqueue_kernels(ctx, ws, variant_of(bh), tt, total_blocks, false, false, s);
+    if (rc) return rc;
+    HIP_TRY(hipEventRecord(ctx->last_done, s));
+    ctx->have_last = true;
+    ctx->last_work = ws.work;
+    ctx->last_was_graph = false;
+    ctx->tev_graph[ctx->launches % kTimingRing] = false;
+    ctx->launches += 1;
+    return RECON_OK;
 }
 
 int recon_fill_holes(recon_ctx *ctx, recon_image *img, int conn, void *stream) {
@@ -870,11 +975,11 @@ static int check_label_args(const recon_image *img, int64_t pitch_lab, int conn)
 }
 
 // Enqueue the labelling phases: labels of `img` into `lab` (pitch_lab
-// elements per row); `scratch` holds label_layout's bytes.  With ranks =
+// elements per row); `area` holds label_layout's bytes.  With ranks =
 // false the phases stop after flattening: every foreground pixel then holds
 // its component's root id (the pitched index + 1 of its raster-first pixel).
 static int enqueue_label(const recon_image &img, int32_t *lab, int64_t pitch_lab, int conn, int32_t *count,
-                         uint8_t *scratch, bool ranks, hipStream_t s) {
+                         uint8_t *area, bool ranks, hipStream_t s) {
     rk::LabelArgs a{};
     a.img = img.data;
     a.pitch_img = img.pitch;
@@ -886,9 +991,9 @@ static int enqueue_label(const recon_image &img, int32_t *lab, int64_t pitch_lab
     a.tiles_x = (img.width + rk::LT_W - 1) / rk::LT_W;
     size_t bytes = 0;
     label_layout(img.height, img.width, pitch_lab, a.n_words, a.n_segs, bytes);
-    a.bits = ranks ? (uint32_t *)scratch : nullptr;
-    a.word_off = (uint32_t *)(scratch + round_up((size_t)a.n_words * 4, 256));
-    a.seg_sum = (uint32_t *)(scratch + 2 * round_up((size_t)a.n_words * 4, 256));
+    a.bits = ranks ? (uint32_t *)area : nullptr;
+    a.word_off = (uint32_t *)(area + round_up((size_t)a.n_words * 4, 256));
+    a.seg_sum = (uint32_t *)(area + 2 * round_up((size_t)a.n_words * 4, 256));
     a.count = count;
     a.lab_vec = (((uintptr_t)lab | (uintptr_t)(pitch_lab * 4)) & 15u) == 0 ? 1 : 0;
     const int64_t n_tiles = (int64_t)a.tiles_x * ((img.height + rk::LT_H - 1) / rk::LT_H);
@@ -1105,7 +1210,7 @@ int recon_last_stats(recon_ctx *ctx, recon_stats *out) {
     rc = wait_event(ctx->last_done, 60.0, "the last launch");
     if (rc) return rc;
     // read the counters through a kernel into pinned memory
-    hipLaunchKernelGGL(rk::copy_table, dim3(1), dim3(64), 0, nullptr, (const uint8_t *)ctx->d_work,
+    hipLaunchKernelGGL(rk::copy_table, dim3(1), dim3(64), 0, nullptr, (const uint8_t *)ctx->last_work,
                        (uint8_t *)ctx->h_work, (uint32_t)sizeof(rk::Work));
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipEventRecord(ctx->last_done, nullptr));
