@@ -8,11 +8,11 @@
  * What is computed
  * ----------------
  * Morphological reconstruction (MR) is the operation the paper's nucleus
- * segmentation stage is built on: Table 1 ("Sources of CPU and GPU
- * implementations of operations in the segmentation and feature computation
- * stages", Sec. V-A) lists ReconToNuclei, FillHoles, Pre-Watershed and RBC
- * detection as MR-based, and the paragraph that follows it describes MR as
- * an irregular wave-propagation computation.  The reconstruction of a mask I
+ * segmentation stage is built on: Table 1 (Sec. V-A), which lists where the
+ * CPU and GPU versions of each segmentation and feature operation come from,
+ * marks ReconToNuclei, FillHoles, Pre-Watershed and RBC detection as MR-based,
+ * and the paragraph that follows it describes MR as an irregular
+ * wave-propagation computation.  The reconstruction of a mask I
  * from a marker J is the fixed point of J <- min(dilate(J), I) started from
  * min(J, I), where dilate is the flat dilation over the 4- or 8-neighbourhood
  * (pixels outside the image do not exist).  The result is unique, so every
@@ -149,7 +149,10 @@ typedef struct {
                                   over (1..4096; 0 = default 128) */
     int32_t binary_drain_budget; /* the same for blocks whose mask is binary (0 / 255 only),
                                   where a raise floods whole regions (1..4096; 0 = default 4) */
-    int32_t reserved[1];
+    int32_t test_fault;        /* test hook, 0 in production: 1 = every compare-and-swap that
+                                  claims a block is made to fail, so that launches give up
+                                  (their calls then report RECON_EDEVICE) */
+    int32_t reserved[3];
 } recon_config;
 
 /* Per-call statistics of the last completed launch (for tests and tuning). */
@@ -255,16 +258,29 @@ int recon_pre_watershed(recon_ctx *ctx, recon_image *img, int conn, void *stream
 /* Run n tasks (any mix of ops, shapes and connectivities) in one persistent
  * launch sequence, replayed from a HIP graph (a context created with timing = 1
  * launches batches of at most 12 tasks directly instead, so that each of their
- * kernels is timed).  Enqueued on `stream`. */
+ * kernels is timed).  The paper processes a dataset as a bag of independent
+ * tile tasks (Sec. III-B: a stage instance is an (input chunk, stage) pair,
+ * handed out on demand); here the bag is drained inside one launch, whose
+ * waves pull blocks of any task as they free up, each task converging on its
+ * own.  `tasks` is a host array read before the call returns; the images are
+ * the caller's device buffers.  Enqueued on `stream`. */
 int recon_batch(recon_ctx *ctx, const recon_task *tasks, int32_t n, void *stream);
 
-/* Serving: admit one task into the resident request loop.  On success
- * *ticket identifies it.  Returns RECON_EAGAIN when the admission cap (device
- * bytes or slots) is reached; poll earlier tickets and retry. */
+/* Serving: a request loop in the manner of the paper's demand-driven
+ * execution (Sec. III-B: workers ask for more work as they finish, with a
+ * bounded number of instances in flight, the window size) and its overlap of
+ * transfers with computation (Sec. IV-D).  recon_submit admits one task: on
+ * success *ticket identifies it.  Admission counts the task's device bytes
+ * (its images and scratch plane) and one slot against serve_mem_cap and
+ * serve_slots; RECON_EAGAIN when either is reached (poll earlier tickets and
+ * retry).  The task's images must stay valid until the ticket completes. */
 int recon_submit(recon_ctx *ctx, const recon_task *task, uint64_t *ticket);
-/* Non-blocking: *done = 1 once the ticket's result is in its image buffer. */
+/* Non-blocking (Sec. III-B's completion notice): *done = 1 once the ticket's
+ * result is in its image buffer; a completed ticket is forgotten after the
+ * call that reports it. */
 int recon_poll(recon_ctx *ctx, uint64_t ticket, int *done);
-/* Block until the ticket completes or timeout_us elapses (< 0: no limit). */
+/* Block until the ticket completes or timeout_us elapses (< 0: no limit);
+ * RECON_ETIMEDOUT leaves the ticket in flight. */
 int recon_wait(recon_ctx *ctx, uint64_t ticket, int64_t timeout_us);
 /* Stop the request loop after the admitted work has drained. */
 int recon_serve_stop(recon_ctx *ctx);

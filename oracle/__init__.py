@@ -31,7 +31,10 @@ def build(force: bool = True) -> str:
     """Compile the C oracle into ``oracle/liboracle.so`` with gcc."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.run(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-o", tmp] + _SRCS, check=True)
+        # -O3; x86-64-v3 (AVX2) rather than -march=native, because the library may be
+        # built on one machine and loaded on another whose CPU lacks newer extensions
+        subprocess.run(["gcc", "-O3", "-march=x86-64-v3", "-std=c99", "-fPIC", "-shared", "-o", tmp] + _SRCS,
+                       check=True)
         os.replace(tmp, _LIB)
     return _LIB
 

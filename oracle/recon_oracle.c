@@ -7,8 +7,8 @@
  *
  * What it computes
  * ----------------
- * The paper (Sec. V-A, Table 1 "Sources of CPU and GPU implementations"; and
- * the paragraph after it on irregular operations) builds its ReconToNuclei,
+ * The paper (Table 1 in Sec. V-A, and the paragraph after it on irregular
+ * operations) builds its ReconToNuclei,
  * FillHoles, Pre-Watershed and RBC-detection operations on morphological
  * reconstruction (MR) and names Vincent's wave-propagation algorithm as the
  * fast CPU method.  The paper does not restate the definition, so the oracle

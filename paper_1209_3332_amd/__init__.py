@@ -68,7 +68,7 @@ class recon_config(ctypes.Structure):
                 ("serve_mem_cap", ctypes.c_int64), ("serve_slots", ctypes.c_int32),
                 ("stop_after_stage", ctypes.c_int32), ("timing", ctypes.c_int32),
                 ("drain_budget", ctypes.c_int32), ("binary_drain_budget", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 1)]
+                ("test_fault", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class recon_stats(ctypes.Structure):

@@ -154,6 +154,7 @@ struct KArgs {
     uint64_t watchdog_ticks;   // wall-clock ticks without progress before giving up
     int32_t drain_budget;        // queue rounds of a revisit before a sweep round takes over
     int32_t binary_drain_budget; // the same for blocks whose mask is binary (0 / 255)
+    int32_t test_fault;          // test hook: 1 = every claim's compare-and-swap is made to fail
 };
 
 // ---------------------------------------------------------------------------
@@ -1090,6 +1091,12 @@ __device__ __forceinline__ void backoff(int k) {
 }
 
 constexpr uint32_t SLOT_EXIT = 0xffffffffu;   // ring slot value: no more work will come
+// Compare-and-swap attempts on a block state word before a launch gives up.
+// Only the owner, requesters (setting D) and the claim touch a word, so a
+// retry fails only while another wave's update lands in between; this many
+// failures in a row means something is wrong, and the launch is abandoned
+// (abort flag, RECON_EDEVICE on the host) rather than run unowned.
+constexpr int CAS_TRIES = 1024;
 
 __device__ __forceinline__ void flush_stats(Work *w, const WaveStats &st) {
     if (lane_id() != 0) return;
@@ -1443,22 +1450,35 @@ __global__ __launch_bounds__(64) void revisit_drain(TaskTable tt, KArgs a) {
         // completed their (coherent) stores before updating the state word, so
         // loads issued after the claim returned see them.
         int first = 0;   // the block's first visit: a dense pass
+        int lost = 0;    // the claim's compare-and-swap failed CAS_TRIES times in a row
         if (ln == 0) {
             if (!claimed) {
                 uint32_t s = __hip_atomic_load(state_word(a, gb), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                for (int k = 0; k < 1024; ++k) {
-                    if (__hip_atomic_compare_exchange_strong(state_word(a, gb), &s, (s & ~ST_D) | ST_R,
+                lost = 1;
+                // (the test hook expects a bit no state word has, so that every attempt fails)
+                const uint32_t skew = a.test_fault == 1 ? 0x80000000u : 0u;
+                for (int k = 0; k < CAS_TRIES; ++k) {
+                    uint32_t e = s ^ skew;
+                    if (__hip_atomic_compare_exchange_strong(state_word(a, gb), &e, (s & ~ST_D) | ST_R,
                                                              __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                                             __HIP_MEMORY_SCOPE_AGENT))
+                                                             __HIP_MEMORY_SCOPE_AGENT)) {
+                        lost = 0;
                         break;
+                    }
+                    s = e;
                 }
                 first = (s & ST_V) ? 0 : 1;
             }
-            if (first)
+            if (lost)
+                __hip_atomic_store(&w->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            else if (first)
                 st.dense += 1;
             else
                 st.revisit += 1;
         }
+        // never work on a block this wave does not own: give the launch up
+        // instead (the host call reports RECON_EDEVICE)
+        if (uniform(lost)) break;
         first = uniform(first);
         __syncthreads();
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
@@ -1488,20 +1508,23 @@ __global__ __launch_bounds__(64) void revisit_drain(TaskTable tt, KArgs a) {
                 ok = check_neighbours<BH>(a, ring_cap, ti, t, g, by, bx, L, &keep, st);
             }
             // ---- finish: re-run if requested meanwhile, else release
-            int rerun = 0;
+            int rerun = 0, stuck = 1;
             if (ln == 0) {
                 uint32_t s = __hip_atomic_load(state_word(a, gb), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                for (int k = 0; k < 1024; ++k) {
+                for (int k = 0; k < CAS_TRIES; ++k) {
                     const uint32_t ns = ((s & ST_D) ? (s & ~ST_D) : (s & ~ST_R)) | ST_V;
                     if (__hip_atomic_compare_exchange_strong(state_word(a, gb), &s, ns, __ATOMIC_RELAXED,
                                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
                         rerun = (s & ST_D) ? 1 : 0;
+                        stuck = 0;
                         break;
                     }
                 }
                 if (rerun) st.rerun += 1;
             }
             rerun = uniform(rerun);
+            // a block that could not be released stays owned: the launch gives up
+            if (uniform(stuck)) ok = false;
             __syncthreads();
             if (!rerun || !ok) break;
             __atomic_signal_fence(__ATOMIC_SEQ_CST);

@@ -373,6 +373,7 @@ int enqueue_kernels(recon_ctx *c, const Workspace &ws, int v, const rk::TaskTabl
     ka.watchdog_ticks = c->watchdog_ticks;
     ka.drain_budget = c->cfg.drain_budget;
     ka.binary_drain_budget = c->cfg.binary_drain_budget;
+    ka.test_fault = c->cfg.test_fault;
     const size_t lds = lds_for(v, c->cfg.queue_capacity);
     const int resident = resident_wgs(c, v);
     // K1/K2 are grid-stride: with sizes known only on the device (captured
@@ -770,6 +771,7 @@ int recon_create(recon_ctx **out, int device, const recon_config *cfg) {
     if (c.scan_rounds < 0) c.scan_rounds = 0;
     if (c.wg_per_cu < 0) return fail(RECON_EINVAL, "wg_per_cu must be >= 0");
     if (c.stop_after_stage < 0 || c.stop_after_stage > 3) return fail(RECON_EINVAL, "stop_after_stage must be 0..3");
+    if (c.test_fault < 0 || c.test_fault > 1) return fail(RECON_EINVAL, "test_fault must be 0 or 1");
     if (c.serve_mem_cap < 0 || c.serve_slots < 0) return fail(RECON_EINVAL, "serving limits must be >= 0");
     if (c.serve_mem_cap == 0) c.serve_mem_cap = (int64_t)64 << 30;
     if (c.serve_slots == 0) c.serve_slots = 256;

@@ -480,6 +480,10 @@ int emu_run(const EmuTask *tasks, int n, int bh, int qcap, int scan_rounds, int 
     ka.watchdog_ticks = (uint64_t)(watchdog_s * 1e8);
     ka.drain_budget = 128;
     ka.binary_drain_budget = 4;
+    {   // test hook of the block claims (see KArgs::test_fault)
+        const char *f = std::getenv("KEMU_TEST_FAULT");
+        ka.test_fault = f ? std::atoi(f) : 0;
+    }
     const size_t lds = bh == 16 ? lds_bytes<16>(qcap) : bh == 32 ? lds_bytes<32>(qcap) : lds_bytes<64>(qcap);
     std::atomic<int> bad{0};
     auto run_grid = [&](int stage, int waves) {

@@ -329,3 +329,16 @@ def test_max_size_tile(torch_mod, rc, oracle_mod):
                 "16384 nuclei dilate")
     binary = np.where(mask > 120, 255, 0).astype(np.uint8)
     assert_same(gpu_fill(torch_mod, rc, binary, 8), oracle_mod.fill_holes(binary, 8), "16384 fill")
+
+
+def test_failed_claims_report_edevice(torch_mod, lib):
+    """A launch whose block claims keep failing gives up (every wave leaves)
+    and the host reports RECON_EDEVICE instead of a silently wrong result.
+    The context's test hook makes every claim's compare-and-swap fail."""
+    mask = synth.gaussian_tile(100, 300, 5, seed=3)
+    with lib.Recon(0, test_fault=1) as ctx:
+        m = dev(torch_mod, synth.hdome_marker(mask, 30))
+        ctx.dilate(m, dev(torch_mod, mask), 8)
+        with pytest.raises(lib.ReconError) as e:
+            ctx.last_stats()
+        assert e.value.code == lib.RECON_EDEVICE

@@ -186,3 +186,15 @@ def test_distance_transform(emu_exe, oracle_mod):
         assert "ERROR: AddressSanitizer" not in log and "runtime error" not in log, log[-2000:]
         assert np.array_equal(d2, oracle_mod.distance2(img)), "image %d dist2" % i
         assert np.array_equal(d8, oracle_mod.distance8(img)), "image %d D8" % i
+
+
+def test_failed_claims_abort_the_launch(emu_exe):
+    """A block claim whose compare-and-swap keeps failing gives the launch up
+    (abort flag set, every wave leaves) instead of working on a block the wave
+    does not own.  The test hook makes every claim fail from the host."""
+    rng = np.random.default_rng(77)
+    m, k = synth.random_pair(rng, 70, 300, 4)
+    rc, _, log = kemu.run(emu_exe, [{"op": "dilate", "marker": m, "mask": k, "conn": 8}], n_waves=3,
+                          test_fault=1, timeout=120)
+    assert "ERROR: AddressSanitizer" not in log and "runtime error" not in log, log[-2000:]
+    assert rc != 0 and "rc -3" in log and "aborted 1" in log, log[-2000:]
