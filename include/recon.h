@@ -152,7 +152,16 @@ typedef struct {
     int32_t test_fault;        /* test hook, 0 in production: 1 = every compare-and-swap that
                                   claims a block is made to fail, so that launches give up
                                   (their calls then report RECON_EDEVICE) */
-    int32_t reserved[3];
+    int32_t component_route;   /* 0 (default): a task whose mask takes at most two values, 0
+                                  and one c > 0 (a binary mask; fill-holes of a binary image),
+                                  is reconstructed through connected-component labelling: the
+                                  result is then, on each component of the nonzero mask pixels,
+                                  the largest min(marker, mask) over that component, and 0
+                                  elsewhere -- the same bytes, without the block visits a long
+                                  corridor would chain.  Each task then also holds an int32
+                                  label plane in the context's scratch area (4 bytes per pixel).
+                                  -1: every task takes the block route */
+    int32_t reserved[2];
 } recon_config;
 
 /* Per-call statistics of the last completed launch (for tests and tuning). */
@@ -169,6 +178,11 @@ typedef struct {
        batch replayed from a captured graph is timed as a whole: the three
        kernel durations are then -1 */
     float dense_ms, seed_ms, drain_ms, total_ms;
+    int64_t component_tasks;   /* tasks reconstructed by the component route (see recon_config) */
+    float route_ms;            /* with recon_config.timing: duration in ms of the component
+                                  route's kernels (classification, labelling, maxima), -1 for
+                                  a replayed graph, 0 when the route is off */
+    float reserved_f;
 } recon_stats;
 
 /* Create a context on HIP device `device`.  cfg may be NULL.  Runs a small
@@ -295,13 +309,14 @@ int recon_last_stats(recon_ctx *ctx, recon_stats *out);
  * timing = 1: `back` = 0 is the last launch sequence, 1 the one before, up to
  * 63.  dense_ms, seed_ms, drain_ms: the dense pass (K1), border seeding (K2)
  * and revisit drain (K3); total_ms: the whole launch, from the scheduler reset
- * and marker preparation to the result mapping.  A replayed graph reports
+ * and marker preparation to the result mapping; route_ms: the component
+ * route's kernels.  A replayed graph reports
  * only its total (the others are -1).  Waits (up to 60 s) for that launch to
  * complete.  RECON_EINVAL if the context does not time its launches or that
  * launch is no longer kept.  Lets a caller time many launches issued back to
  * back and read all their durations after one synchronisation. */
 int recon_launch_times(recon_ctx *ctx, int back, float *dense_ms, float *seed_ms, float *drain_ms,
-                       float *total_ms);
+                       float *total_ms, float *route_ms);
 
 /* Message describing the last failure on the calling thread ("" if none). */
 const char *recon_last_error(void);

@@ -68,7 +68,8 @@ class recon_config(ctypes.Structure):
                 ("serve_mem_cap", ctypes.c_int64), ("serve_slots", ctypes.c_int32),
                 ("stop_after_stage", ctypes.c_int32), ("timing", ctypes.c_int32),
                 ("drain_budget", ctypes.c_int32), ("binary_drain_budget", ctypes.c_int32),
-                ("test_fault", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("test_fault", ctypes.c_int32), ("component_route", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class recon_stats(ctypes.Structure):
@@ -76,7 +77,8 @@ class recon_stats(ctypes.Structure):
                 ("reruns", ctypes.c_int64), ("queue_overflows", ctypes.c_int64),
                 ("requests", ctypes.c_int64), ("aborted", ctypes.c_int64),
                 ("dense_ms", ctypes.c_float), ("seed_ms", ctypes.c_float), ("drain_ms", ctypes.c_float),
-                ("total_ms", ctypes.c_float)]
+                ("total_ms", ctypes.c_float), ("component_tasks", ctypes.c_int64),
+                ("route_ms", ctypes.c_float), ("reserved_f", ctypes.c_float)]
 
 
 _lib = None
@@ -113,7 +115,7 @@ def load_library(path: str = LIB_PATH):
     lib.recon_serve_stop.argtypes = [P]
     lib.recon_last_stats.argtypes = [P, ctypes.POINTER(recon_stats)]
     F = ctypes.POINTER(ctypes.c_float)
-    lib.recon_launch_times.argtypes = [P, ctypes.c_int, F, F, F, F]
+    lib.recon_launch_times.argtypes = [P, ctypes.c_int, F, F, F, F, F]
     lib.recon_last_error.argtypes = []
     lib.recon_last_error.restype = ctypes.c_char_p
     for name in EXPORTED:
@@ -283,9 +285,9 @@ def recon_serve_stop(ctx: int) -> None:
 
 def recon_launch_times(ctx: int, back: int = 0) -> dict:
     """Kernel durations (ms) of a recent launch: back = 0 the last, up to 63."""
-    t = [ctypes.c_float() for _ in range(4)]
+    t = [ctypes.c_float() for _ in range(5)]
     _check(load_library().recon_launch_times(ctx, int(back), *[ctypes.byref(x) for x in t]))
-    return dict(zip(("dense_ms", "seed_ms", "drain_ms", "total_ms"), (x.value for x in t)))
+    return dict(zip(("dense_ms", "seed_ms", "drain_ms", "total_ms", "route_ms"), (x.value for x in t)))
 
 
 def recon_last_stats(ctx: int) -> dict:

@@ -99,6 +99,8 @@ struct TaskDev {
     int32_t aligned;       // 1 if both planes allow dword access (4-aligned base and pitch)
     int32_t scan_rounds;   // directional pass rounds on the dense pass
     int32_t qcap;          // LDS queue entries (<= the launch's LDS allocation)
+    int32_t *lab;          // int32 label plane of the component route (null: the task never takes it)
+    int64_t pitch_lab;     // its row pitch in elements (a multiple of 4)
 };
 
 // Batch header in device memory, in front of a device task table.
@@ -140,7 +142,8 @@ struct Work {
     unsigned long long stat_rerun;
     unsigned long long stat_overflow;
     unsigned long long stat_request;
-    unsigned long long pad4[11];
+    unsigned long long stat_route;   // tasks reconstructed by the component route
+    unsigned long long pad4[10];
 };
 
 struct KArgs {
@@ -155,6 +158,7 @@ struct KArgs {
     int32_t drain_budget;        // queue rounds of a revisit before a sweep round takes over
     int32_t binary_drain_budget; // the same for blocks whose mask is binary (0 / 255)
     int32_t test_fault;          // test hook: 1 = every claim's compare-and-swap is made to fail
+    uint32_t *route;             // per task: OR and AND of its nonzero mask values (component route)
 };
 
 // ---------------------------------------------------------------------------
@@ -188,6 +192,16 @@ __device__ __forceinline__ int find_task(const TaskTable &tt, uint32_t gblock) {
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 __device__ __forceinline__ uint32_t uniform(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+
+// Whether task k takes the component route (component.hpp): its mask holds at
+// most one nonzero value, by the OR and AND of its nonzero mask values that
+// comp_classify left in the task's two route words.  Read only by kernels
+// launched after the classification.
+__device__ __forceinline__ bool on_component_route(const KArgs &a, const TaskDev &t, int k) {
+    if (!t.lab) return false;
+    const uint32_t o = a.route[2 * k], n = a.route[2 * k + 1];
+    return o == 0u || o == n;
 }
 
 // ---------------------------------------------------------------------------
@@ -1445,6 +1459,22 @@ __global__ __launch_bounds__(64) void revisit_drain(TaskTable tt, KArgs a) {
         const int lb = (int)(gb - t.block0);
         const int by = lb / t.nbx, bx = lb % t.nbx;
         const BlockGeom g = geom<BH>(t, by, bx);
+        if (on_component_route(a, t, ti)) {
+            // the task was reconstructed by the component route: the block's
+            // visit is complete without any work (no wave ever requests it)
+            int last = 0;
+            if (ln == 0) {
+                const uint32_t left = __hip_atomic_fetch_sub(a.tile_pending + ti, 1u, __ATOMIC_RELAXED,
+                                                             __HIP_MEMORY_SCOPE_AGENT);
+                const uint32_t all = __hip_atomic_fetch_sub(&w->pending, 1u, __ATOMIC_RELAXED,
+                                                            __HIP_MEMORY_SCOPE_AGENT);
+                if (left == 1u)
+                    __hip_atomic_store(a.tile_done + ti, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                last = all == 1u;
+            }
+            if (uniform(last)) release_waiters(a, ring_cap);
+            continue;
+        }
 
         // ---- claim: clear D, set R (a kept block is owned already).  The previous owner and every requester
         // completed their (coherent) stores before updating the state word, so
@@ -1567,7 +1597,7 @@ __global__ void copy_table(const uint8_t *src, uint8_t *dst, uint32_t bytes) {
 // that the persistent revisit kernel makes each block's first visit itself;
 // otherwise the scheduler starts empty (the dense and border kernels run first).
 __global__ void reset_work(TaskTable tt, Work *w, uint32_t *state, uint32_t *ring,
-                           uint32_t *tile_pending, uint32_t *tile_done, int queue_all) {
+                           uint32_t *tile_pending, uint32_t *tile_done, uint32_t *route, int queue_all) {
     const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t nth = gridDim.x * blockDim.x;
     const uint32_t n_tasks = n_tasks_of(tt), total = total_blocks_of(tt), ring_cap = ring_cap_of(tt);
@@ -1579,6 +1609,7 @@ __global__ void reset_work(TaskTable tt, Work *w, uint32_t *state, uint32_t *rin
         w->abort = 0;
         w->progress = 0;
         w->stat_dense = w->stat_revisit = w->stat_rerun = w->stat_overflow = w->stat_request = 0;
+        w->stat_route = 0;
     }
     // (without queue_all the dense pass visits every block first)
     for (uint32_t i = tid; i < total; i += nth) state[(size_t)i * STATE_STRIDE] = queue_all ? ST_D : ST_V;
@@ -1587,6 +1618,10 @@ __global__ void reset_work(TaskTable tt, Work *w, uint32_t *state, uint32_t *rin
         const TaskDev t = task_of(tt, (int)i);
         tile_pending[i] = queue_all ? (uint32_t)(t.nby * t.nbx) : 0u;
         tile_done[i] = 0;
+        if (route) {   // the OR and AND identities of the mask classification
+            route[2 * i] = 0u;
+            route[2 * i + 1] = 0xffu;
+        }
     }
 }
 

@@ -54,6 +54,7 @@ struct LabelArgs {
     uint32_t n_segs;
     int32_t *count;         // receives the number of components (may be null)
     int32_t lab_vec;        // 1: the label plane allows 16-byte accesses (base and row pitch)
+    int32_t fg_inv;         // 1: the foreground is the pixels below 255 (the complement's nonzero pixels)
 };
 
 typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
@@ -159,6 +160,17 @@ __device__ __forceinline__ uint32_t wave_prefix_max(uint32_t v) {
     return max(v, sel_row(lane_id() >> 4, 0u, r0, r1, r2));
 }
 
+// The 4 pixels at columns x..x+3 of row y as foreground bytes: nonzero where
+// the pixel is foreground (fg_inv: below 255), 0 elsewhere and past the image.
+__device__ __forceinline__ uint32_t fg_load4(const LabelArgs &a, int y, int x, int valid, int aligned) {
+    uint32_t v = gload4(a.img + (int64_t)y * a.pitch_img, x, valid, aligned);
+    if (a.fg_inv) {
+        const uint32_t keep = valid >= 4 ? 0xffffffffu : (valid <= 0 ? 0u : ((1u << (8 * valid)) - 1u));
+        v = (~v) & keep;
+    }
+    return v;
+}
+
 // Phase 1: tile-local labelling.  Grid: one 64-lane workgroup per tile
 // (grid-stride); dynamic LDS: LT_H * LT_W * 4 bytes.  Lane l holds columns
 // 4l..4l+3 of every row.
@@ -170,21 +182,19 @@ __device__ __forceinline__ uint32_t wave_prefix_max(uint32_t v) {
 //      diagonally under (8-conn) the upper run's first pixel inside the
 //      window the run can reach;
 //   c. path compression; d. node ids out.
-__global__ __launch_bounds__(64) void label_local(LabelArgs a) {
-    RK_LDS uint32_t *par = (RK_LDS uint32_t *)dyn_lds();
+// label_tile is one tile (all lanes of the wave; `par` holds LT_H * LT_W
+// words of LDS); label_local runs it over the tiles of one image.
+__device__ void label_tile(const LabelArgs &a, RK_LDS uint32_t *par, int y0, int x0, int aligned) {
     const int ln = lane_id();
-    const int n_tiles = a.tiles_x * ((a.h + LT_H - 1) / LT_H);
-    const int aligned = img_aligned(a);
     const int c = 4 * ln;
-    for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-        const int y0 = (tile / a.tiles_x) * LT_H, x0 = (tile % a.tiles_x) * LT_W;
+    {
         const int th = min(LT_H, a.h - y0), tw = min(LT_W, a.w - x0);
         const int valid = min(4, tw - c);
         uint64_t fg = 0;   // bit 4r+k: pixel (r, c+k) is foreground
         uint32_t rows[LT_H];   // all loads in flight together
 #pragma unroll
         for (int r = 0; r < LT_H; ++r)
-            rows[r] = r < th ? gload4(a.img + (int64_t)(y0 + r) * a.pitch_img, x0 + c, valid, aligned) : 0u;
+            rows[r] = r < th ? fg_load4(a, y0 + r, x0 + c, valid, aligned) : 0u;
 #pragma unroll
         for (int r = 0; r < LT_H; ++r) {
             const uint32_t v = rows[r];
@@ -275,17 +285,23 @@ __global__ __launch_bounds__(64) void label_local(LabelArgs a) {
     }
 }
 
+__global__ __launch_bounds__(64) void label_local(LabelArgs a) {
+    RK_LDS uint32_t *par = (RK_LDS uint32_t *)dyn_lds();
+    const int n_tiles = a.tiles_x * ((a.h + LT_H - 1) / LT_H);
+    const int aligned = img_aligned(a);
+    for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x)
+        label_tile(a, par, (tile / a.tiles_x) * LT_H, (tile % a.tiles_x) * LT_W, aligned);
+}
+
 // Phase 2: unions across tile borders.  One 64-lane workgroup per tile
 // (grid-stride).  The top row meets the row above (the tiles above), the left
 // column meets the column to the left; with 8-connectivity the diagonal
 // neighbours too.  Every pair of adjacent pixels in different tiles is met at
 // least once.
-__global__ __launch_bounds__(64) void label_merge(LabelArgs a) {
+__device__ void merge_tile(const LabelArgs &a, int y0, int x0) {
     const int ln = lane_id();
-    const int n_tiles = a.tiles_x * ((a.h + LT_H - 1) / LT_H);
     const int d = a.conn == 8 ? 1 : 0;
-    for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-        const int y0 = (tile / a.tiles_x) * LT_H, x0 = (tile % a.tiles_x) * LT_W;
+    {
         const int th = min(LT_H, a.h - y0), tw = min(LT_W, a.w - x0);
         if (y0 > 0) {
             for (int k = 0; k < 4; ++k) {
@@ -315,6 +331,12 @@ __global__ __launch_bounds__(64) void label_merge(LabelArgs a) {
             }
         }
     }
+}
+
+__global__ __launch_bounds__(64) void label_merge(LabelArgs a) {
+    const int n_tiles = a.tiles_x * ((a.h + LT_H - 1) / LT_H);
+    for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x)
+        merge_tile(a, (tile / a.tiles_x) * LT_H, (tile % a.tiles_x) * LT_W);
 }
 
 // Clear a word array (a fill kernel rather than a memset node).

@@ -29,6 +29,7 @@
 #include "../../include/recon.h"
 #include "kernels.hpp"
 #include "label.hpp"
+#include "component.hpp"
 #include "distance.hpp"
 
 namespace {
@@ -132,6 +133,7 @@ struct recon_ctx {
     size_t cap_blocks = 0;
     uint32_t *d_tile_pending = nullptr;
     uint32_t *d_tile_done = nullptr;
+    uint32_t *d_route = nullptr;      // two mask-classification words per task (component route)
     uint8_t *d_scratch = nullptr;     // fill-holes marker planes
     size_t cap_scratch = 0;
     // pinned staging (task table in, statistics out)
@@ -141,7 +143,8 @@ struct recon_ctx {
     hipEvent_t table_used = nullptr;  // the last copy out of h_table has finished
     hipEvent_t last_done = nullptr;
     // timing marks of the last kTimingRing launches (before K1, after K1, K2, K3, the launch)
-    hipEvent_t tev[kTimingRing][6] = {};   // [5] opens the launch, [0]..[4] close its steps
+    // [5] opens the launch, [0]..[4] close its steps, [6] closes the component route (after [0])
+    hipEvent_t tev[kTimingRing][7] = {};
     bool tev_graph[kTimingRing] = {};   // that launch replayed a graph (only its total is marked)
     uint64_t launches = 0;              // launch sequences enqueued so far
     bool have_last = false;
@@ -191,10 +194,11 @@ void free_workspace(recon_ctx *c) {
     (void)hipFree(c->d_ring);
     (void)hipFree(c->d_tile_pending);
     (void)hipFree(c->d_tile_done);
+    (void)hipFree(c->d_route);
     (void)hipFree(c->d_scratch);
     c->d_table = nullptr;
     c->d_work = nullptr;
-    c->d_state = c->d_ring = c->d_tile_pending = c->d_tile_done = nullptr;
+    c->d_state = c->d_ring = c->d_tile_pending = c->d_tile_done = c->d_route = nullptr;
     c->d_scratch = nullptr;
     c->cap_tasks = c->cap_blocks = c->cap_scratch = 0;
 }
@@ -226,6 +230,7 @@ int ensure_capacity(recon_ctx *c, size_t n_tasks, size_t n_blocks, size_t area_b
         hipMalloc(&c->d_ring, ring_slots(nb) * rk::RING_STRIDE * sizeof(uint32_t)) != hipSuccess ||
         hipMalloc(&c->d_tile_pending, nt * sizeof(uint32_t)) != hipSuccess ||
         hipMalloc(&c->d_tile_done, nt * sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc(&c->d_route, 2 * nt * sizeof(uint32_t)) != hipSuccess ||
         (ns > 0 && hipMalloc(&c->d_scratch, ns) != hipSuccess)) {
         free_workspace(c);
         return fail(RECON_ENOMEM, "workspace allocation (%zu tasks, %zu blocks, %zu scratch bytes) failed",
@@ -294,11 +299,14 @@ bool aligned4(const void *p, int64_t pitch) { return ((uintptr_t)p % 4 == 0) && 
 // Device task table of a launch.  Tasks that need a scratch marker plane get
 // its offset into the context's scratch area in `j` (relocated by the caller
 // once the area is allocated) and uses_scratch[k] = 1.
+// With `with_route`, every task whose node ids fit also gets an int32 label
+// plane for the component route (its offset in lab_off, else SIZE_MAX).
 void build_table(const recon_config &cfg, const recon_task *tasks, int n, int bh, std::vector<rk::TaskDev> &out,
                  std::vector<char> &uses_scratch, uint32_t &total_blocks, size_t &scratch_bytes,
-                 bool &any_mapped) {
+                 bool &any_mapped, bool with_route, std::vector<size_t> &lab_off) {
     out.resize(n);
     uses_scratch.assign(n, 0);
+    lab_off.assign(n, SIZE_MAX);
     total_blocks = 0;
     scratch_bytes = 0;
     any_mapped = false;
@@ -340,6 +348,12 @@ void build_table(const recon_config &cfg, const recon_task *tasks, int n, int bh
             uses_scratch[k] = 1;
         }
         if (t.op != RECON_OP_DILATE) any_mapped = true;
+        d.lab = nullptr;
+        d.pitch_lab = (int64_t)round_up((size_t)d.w, 4);
+        if (with_route && (uint64_t)d.h * (uint64_t)d.pitch_lab < (uint64_t)rk::COMP_ENC) {
+            lab_off[k] = scratch_bytes;
+            scratch_bytes += round_up((size_t)d.pitch_lab * d.h * 4, 256);
+        }
         out[k] = d;
     }
 }
@@ -352,16 +366,18 @@ struct Workspace {
     uint32_t *ring;
     uint32_t *tile_pending;
     uint32_t *tile_done;
+    uint32_t *route;     // mask classification words (null: no task takes the component route)
     size_t cap_blocks;   // blocks the state words and the ring hold
 };
 
 Workspace ctx_workspace(const recon_ctx *c) {
-    return Workspace{c->d_work, c->d_state, c->d_ring, c->d_tile_pending, c->d_tile_done, c->cap_blocks};
+    return Workspace{c->d_work, c->d_state, c->d_ring, c->d_tile_pending, c->d_tile_done, c->d_route,
+                     c->cap_blocks};
 }
 
 // Enqueue the kernels of one launch sequence on `s`.
 int enqueue_kernels(recon_ctx *c, const Workspace &ws, int v, const rk::TaskTable &tt, uint32_t total_blocks,
-                    bool any_mapped, bool dynamic_sizes, hipStream_t s) {
+                    bool any_mapped, bool route, bool dynamic_sizes, hipStream_t s) {
     rk::KArgs ka;
     ka.work = ws.work;
     ka.state = ws.state;
@@ -374,6 +390,7 @@ int enqueue_kernels(recon_ctx *c, const Workspace &ws, int v, const rk::TaskTabl
     ka.drain_budget = c->cfg.drain_budget;
     ka.binary_drain_budget = c->cfg.binary_drain_budget;
     ka.test_fault = c->cfg.test_fault;
+    ka.route = route ? ws.route : nullptr;
     const size_t lds = lds_for(v, c->cfg.queue_capacity);
     const int resident = resident_wgs(c, v);
     // K1/K2 are grid-stride: with sizes known only on the device (captured
@@ -393,9 +410,31 @@ int enqueue_kernels(recon_ctx *c, const Workspace &ws, int v, const rk::TaskTabl
     hipEvent_t *tev = c->tev[c->launches % kTimingRing];
     if (timing) HIP_TRY(hipEventRecord(tev[5], s));
     hipLaunchKernelGGL(rk::reset_work, dim3(64), dim3(256), 0, s, tt, ws.work, ws.state, ws.ring,
-                       ws.tile_pending, ws.tile_done, merged ? 1 : 0);
+                       ws.tile_pending, ws.tile_done, ka.route, merged ? 1 : 0);
     if (any_mapped) hipLaunchKernelGGL(rk::init_marker, dim3(1024), dim3(256), 0, s, tt);
+
     if (timing) HIP_TRY(hipEventRecord(tev[0], s));
+    if (route) {
+        // the component route: classify every task's mask, then label and
+        // reconstruct the two-valued ones (the others' waves exit at once)
+        const int bh = kBlockRows[v];
+        const int g_rows = (int)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)nblk * bh, 16384));
+        const int g_tiles = (int)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)nblk * (bh / rk::LT_H), 16384));
+        const size_t lds_lab = (size_t)rk::LT_H * rk::LT_W * sizeof(uint32_t);
+#define RK_COMP(K, GRID, LDS)                                                                     \
+    switch (v) {                                                                                  \
+        case 0: hipLaunchKernelGGL(rk::K<16>, dim3(GRID), dim3(64), LDS, s, tt, ka); break;      \
+        case 1: hipLaunchKernelGGL(rk::K<32>, dim3(GRID), dim3(64), LDS, s, tt, ka); break;      \
+        default: hipLaunchKernelGGL(rk::K<64>, dim3(GRID), dim3(64), LDS, s, tt, ka); break;     \
+    }
+        RK_COMP(comp_classify, g_rows, 0);
+        RK_COMP(comp_label_local, g_tiles, lds_lab);
+        RK_COMP(comp_label_merge, g_tiles, 0);
+        RK_COMP(comp_flatten_max, g_rows, 0);
+        RK_COMP(comp_write, g_rows, 0);
+#undef RK_COMP
+    }
+    if (timing) HIP_TRY(hipEventRecord(tev[6], s));
 #define RK_LAUNCH(K, GRID)                                                                        \
     switch (v) {                                                                                  \
         case 0: hipLaunchKernelGGL(rk::K<16>, dim3(GRID), dim3(64), lds, s, tt, ka); break;      \
@@ -425,18 +464,23 @@ int run_tasks(recon_ctx *c, const recon_task *tasks, int n, hipStream_t stream, 
     const int v = variant_of(bh);
     std::vector<rk::TaskDev> table;
     std::vector<char> uses_scratch;
+    std::vector<size_t> lab_off;
     uint32_t total_blocks = 0;
     size_t scratch_need = 0;
     bool any_mapped = false;
-    build_table(c->cfg, tasks, n, bh, table, uses_scratch, total_blocks, scratch_need, any_mapped);
+    const bool with_route = c->cfg.component_route >= 0 && c->cfg.stop_after_stage == 0;
+    build_table(c->cfg, tasks, n, bh, table, uses_scratch, total_blocks, scratch_need, any_mapped, with_route,
+                lab_off);
     rc = ensure_capacity(c, (size_t)n, (size_t)total_blocks, scratch_need);
     if (rc) return rc;
-    for (int k = 0; k < n; ++k)
+    for (int k = 0; k < n; ++k) {
+        rk::TaskDev &d = table[k];
         if (uses_scratch[k]) {
-            rk::TaskDev &d = table[k];
             d.j = c->d_scratch + (uintptr_t)d.j;
             if (!aligned4(d.j, d.pitch_j)) d.aligned = 0;
         }
+        if (lab_off[k] != SIZE_MAX) d.lab = (int32_t *)(c->d_scratch + lab_off[k]);
+    }
 
     rk::TaskTable tt{};
     const bool inline_table = !use_graph && n <= rk::MAX_INLINE_TASKS;
@@ -474,7 +518,7 @@ int run_tasks(recon_ctx *c, const recon_task *tasks, int n, hipStream_t stream, 
             const uint32_t max_bytes = (uint32_t)(sizeof(BatchHdr) + c->cap_tasks * sizeof(rk::TaskDev));
             hipLaunchKernelGGL(rk::copy_table, dim3(16), dim3(256), 0, c->cap_stream, c->h_table, c->d_table,
                                max_bytes);
-            rc = enqueue_kernels(c, ctx_workspace(c), v, tt, total_blocks, true, true, c->cap_stream);
+            rc = enqueue_kernels(c, ctx_workspace(c), v, tt, total_blocks, true, with_route, true, c->cap_stream);
             hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
             if (rc) return rc;
             if (e != hipSuccess) return fail(RECON_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
@@ -496,7 +540,7 @@ int run_tasks(recon_ctx *c, const recon_task *tasks, int n, hipStream_t stream, 
                                table_bytes);
             HIP_TRY(hipEventRecord(c->table_used, stream));
         }
-        rc = enqueue_kernels(c, ctx_workspace(c), v, tt, total_blocks, any_mapped, false, stream);
+        rc = enqueue_kernels(c, ctx_workspace(c), v, tt, total_blocks, any_mapped, with_route, false, stream);
         if (rc) return rc;
     }
     HIP_TRY(hipEventRecord(c->last_done, stream));
@@ -599,10 +643,13 @@ int make_ctx(recon_ctx **out, int device, const recon_config &c) {
     return RECON_OK;
 }
 
-size_t task_bytes(const recon_task &t) {
+// Device bytes a serving request holds while admitted: its images, its scratch
+// marker plane and, with the component route, its label plane.
+size_t task_bytes(const recon_task &t, const recon_config &cfg) {
     size_t b = (size_t)t.image.height * (size_t)t.image.pitch;
     if (two_planes(t.op)) b += (size_t)t.mask.height * (size_t)t.mask.pitch;
     else b += round_up((size_t)round_up((size_t)t.image.width, 4) * t.image.height, 256);
+    if (cfg.component_route >= 0) b += round_up(round_up((size_t)t.image.width, 4) * t.image.height * 4, 256);
     return b;
 }
 
@@ -772,6 +819,8 @@ int recon_create(recon_ctx **out, int device, const recon_config *cfg) {
     if (c.wg_per_cu < 0) return fail(RECON_EINVAL, "wg_per_cu must be >= 0");
     if (c.stop_after_stage < 0 || c.stop_after_stage > 3) return fail(RECON_EINVAL, "stop_after_stage must be 0..3");
     if (c.test_fault < 0 || c.test_fault > 1) return fail(RECON_EINVAL, "test_fault must be 0 or 1");
+    if (c.component_route < -1 || c.component_route > 0)
+        return fail(RECON_EINVAL, "component_route must be 0 (on) or -1 (off)");
     if (c.serve_mem_cap < 0 || c.serve_slots < 0) return fail(RECON_EINVAL, "serving limits must be >= 0");
     if (c.serve_mem_cap == 0) c.serve_mem_cap = (int64_t)64 << 30;
     if (c.serve_slots == 0) c.serve_slots = 256;
@@ -865,7 +914,8 @@ int recon_dilate_noalloc(recon_ctx *ctx, recon_image *marker, const recon_image 
     uint32_t total_blocks = 0;
     size_t scratch_bytes = 0;
     bool any_mapped = false;
-    build_table(ctx->cfg, &t, 1, bh, table, uses_scratch, total_blocks, scratch_bytes, any_mapped);
+    std::vector<size_t> lab_off;
+    build_table(ctx->cfg, &t, 1, bh, table, uses_scratch, total_blocks, scratch_bytes, any_mapped, false, lab_off);
     uint8_t *base = ctx->noalloc;
     Workspace ws;
     ws.work = (rk::Work *)base;
@@ -873,6 +923,7 @@ int recon_dilate_noalloc(recon_ctx *ctx, recon_image *marker, const recon_image 
     ws.tile_done = ws.tile_pending + 1;
     ws.state = (uint32_t *)(base + NOALLOC_STATE_OFF);
     ws.ring = (uint32_t *)(base + NOALLOC_RING_OFF);
+    ws.route = nullptr;   // no label plane: the block route only
     ws.cap_blocks = total_blocks;
     rk::TaskTable tt{};
     tt.hdr = nullptr;
@@ -882,7 +933,7 @@ int recon_dilate_noalloc(recon_ctx *ctx, recon_image *marker, const recon_image 
     tt.ring_cap_inline = (uint32_t)ring_slots(total_blocks);
     tt.inl[0] = table[0];
     const hipStream_t s = (hipStream_t)stream;
-    rc = enqueue_kernels(ctx, ws, variant_of(bh), tt, total_blocks, false, false, s);
+    rc = enqueue_kernels(ctx, ws, variant_of(bh), tt, total_blocks, false, false, false, s);
     if (rc) return rc;
     HIP_TRY(hipEventRecord(ctx->last_done, s));
     ctx->have_last = true;
@@ -1189,15 +1240,16 @@ int recon_batch(recon_ctx *ctx, const recon_task *tasks, int32_t n, void *stream
 // Durations (ms) of a recent launch from its timing marks: K1, K2, K3, whole
 // launch (from before the scheduler reset to after the result mapping); -1
 // where a mark was not recorded (graph replays mark only the whole).
-static void launch_times(recon_ctx *ctx, int back, float t[4]) {
+static void launch_times(recon_ctx *ctx, int back, float t[5]) {
     const int i = (int)((ctx->launches - 1 - (uint64_t)back) % kTimingRing);
     hipEvent_t *tev = ctx->tev[i];
-    t[0] = t[1] = t[2] = t[3] = -1.f;
+    t[0] = t[1] = t[2] = t[3] = t[4] = -1.f;
     float ms = 0.f;
     if (!ctx->tev_graph[i]) {
-        if (hipEventElapsedTime(&ms, tev[0], tev[1]) == hipSuccess) t[0] = ms;
+        if (hipEventElapsedTime(&ms, tev[6], tev[1]) == hipSuccess) t[0] = ms;
         if (hipEventElapsedTime(&ms, tev[1], tev[2]) == hipSuccess) t[1] = ms;
         if (hipEventElapsedTime(&ms, tev[2], tev[3]) == hipSuccess) t[2] = ms;
+        if (hipEventElapsedTime(&ms, tev[0], tev[6]) == hipSuccess) t[4] = ms;
     }
     if (hipEventElapsedTime(&ms, tev[5], tev[4]) == hipSuccess) t[3] = ms;
     (void)hipGetLastError();   // a mark that was not recorded must not leave an error behind
@@ -1226,21 +1278,24 @@ int recon_last_stats(recon_ctx *ctx, recon_stats *out) {
     out->queue_overflows = (int64_t)w.stat_overflow;
     out->requests = (int64_t)w.stat_request;
     out->aborted = (int64_t)w.abort;
+    out->component_tasks = (int64_t)w.stat_route;
     if (ctx->cfg.timing) {
-        float t[4];
+        float t[5];
         launch_times(ctx, 0, t);
         out->dense_ms = t[0];
         out->seed_ms = t[1];
         out->drain_ms = t[2];
         out->total_ms = t[3];
+        out->route_ms = t[4];
     }
     if (w.abort) return fail(RECON_EDEVICE, "scheduler watchdog expired: the last launch did not converge");
     return RECON_OK;
 }
 
 int recon_launch_times(recon_ctx *ctx, int back, float *dense_ms, float *seed_ms, float *drain_ms,
-                       float *total_ms) {
-    if (!ctx || !dense_ms || !seed_ms || !drain_ms || !total_ms) return fail(RECON_EINVAL, "null argument");
+                       float *total_ms, float *route_ms) {
+    if (!ctx || !dense_ms || !seed_ms || !drain_ms || !total_ms || !route_ms)
+        return fail(RECON_EINVAL, "null argument");
     if (!ctx->cfg.timing) return fail(RECON_EINVAL, "the context was created without timing");
     if (back < 0 || back >= kTimingRing || (uint64_t)back >= ctx->launches)
         return fail(RECON_EINVAL, "launch %d back is not kept (%llu launches, %d kept)", back,
@@ -1250,12 +1305,13 @@ int recon_launch_times(recon_ctx *ctx, int back, float *dense_ms, float *seed_ms
     hipEvent_t *tev = ctx->tev[(ctx->launches - 1 - (uint64_t)back) % kTimingRing];
     rc = wait_event(tev[4], 60.0, "the timed launch");
     if (rc) return rc;
-    float t[4];
+    float t[5];
     launch_times(ctx, back, t);
     *dense_ms = t[0];
     *seed_ms = t[1];
     *drain_ms = t[2];
     *total_ms = t[3];
+    *route_ms = t[4];
     return RECON_OK;
 }
 
@@ -1270,7 +1326,7 @@ int recon_submit(recon_ctx *ctx, const recon_task *task, uint64_t *ticket) {
         if (rc) return rc;
     }
     recon_ctx::Serve *S = ctx->serve;
-    const size_t bytes = task_bytes(*task);
+    const size_t bytes = task_bytes(*task, ctx->cfg);
     {
         std::lock_guard<std::mutex> lk(S->mu);
         if (S->stop) return fail(RECON_EINVAL, "serving has been stopped");

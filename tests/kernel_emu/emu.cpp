@@ -20,6 +20,7 @@
 
 #include "../../paper_1209_3332_amd/csrc/kernels.hpp"
 #include "../../paper_1209_3332_amd/csrc/label.hpp"
+#include "../../paper_1209_3332_amd/csrc/component.hpp"
 #include "../../paper_1209_3332_amd/csrc/distance.hpp"
 
 #if defined(__has_feature)
@@ -372,7 +373,7 @@ struct EmuTask {
 };
 
 struct EmuStats {
-    int64_t dense, revisit, rerun, overflow, aborted;
+    int64_t dense, revisit, rerun, overflow, aborted, route;
 };
 
 int emu_run(const EmuTask *tasks, int n, int bh, int qcap, int scan_rounds, int n_waves,
@@ -381,6 +382,10 @@ int emu_run(const EmuTask *tasks, int n, int bh, int qcap, int scan_rounds, int 
     if (bh != 16 && bh != 32 && bh != 64) return -1;
     // exact-size copies so that the sanitizer bounds-checks global accesses
     std::vector<uint8_t *> jplanes(n), iplanes(n, nullptr), scratch(n, nullptr);
+    // the component route (KEMU_COMPONENT=1): an exact-size int32 label plane per task
+    const char *ce = std::getenv("KEMU_COMPONENT");
+    const bool component = ce && std::atoi(ce) == 1 && stop_after == 0;
+    std::vector<int32_t *> labs(n, nullptr);
     std::vector<TaskDev> table(n);
     uint32_t total = 0;
     bool any_mapped = false;
@@ -426,6 +431,12 @@ int emu_run(const EmuTask *tasks, int n, int bh, int qcap, int scan_rounds, int 
             d.aligned = (e.w % 4 == 0);
         }
         if (e.op != 0) any_mapped = true;
+        d.lab = nullptr;
+        d.pitch_lab = (e.w + 3) / 4 * 4 + 4;   // padded: pitched node ids are exercised
+        if (component) {
+            labs[k] = (int32_t *)std::malloc(((size_t)(e.h - 1) * d.pitch_lab + e.w) * sizeof(int32_t));
+            d.lab = labs[k];
+        }
         table[k] = d;
     }
     // task table: inline in the "kernel arguments" when small, else in memory
@@ -453,6 +464,7 @@ int emu_run(const EmuTask *tasks, int n, int bh, int qcap, int scan_rounds, int 
     uint32_t *ring = (uint32_t *)std::malloc((size_t)(total + n_waves + 1) * RING_STRIDE * sizeof(uint32_t));
     uint32_t *tpend = (uint32_t *)std::malloc(n * sizeof(uint32_t));
     uint32_t *tdone = (uint32_t *)std::malloc(n * sizeof(uint32_t));
+    uint32_t *route = component ? (uint32_t *)std::malloc(2 * n * sizeof(uint32_t)) : nullptr;
 
     auto grid_run = [&](auto fn, uint32_t blocks, uint32_t threads) {
         kemu::gridDim_.x = blocks;
@@ -466,7 +478,7 @@ int emu_run(const EmuTask *tasks, int n, int bh, int qcap, int scan_rounds, int 
     };
     // stop_after 0: the persistent pipeline; 1..3: the staged one, stopped after that stage
     const bool merged = stop_after == 0;
-    grid_run([&] { reset_work(tt, work, state, ring, tpend, tdone, merged ? 1 : 0); }, 4, 64);
+    grid_run([&] { reset_work(tt, work, state, ring, tpend, tdone, route, merged ? 1 : 0); }, 4, 64);
     if (any_mapped) grid_run([&] { init_marker(tt); }, 8, 64);
 
     KArgs ka;
@@ -480,6 +492,7 @@ int emu_run(const EmuTask *tasks, int n, int bh, int qcap, int scan_rounds, int 
     ka.watchdog_ticks = (uint64_t)(watchdog_s * 1e8);
     ka.drain_budget = 128;
     ka.binary_drain_budget = 4;
+    ka.route = route;
     {   // test hook of the block claims (see KArgs::test_fault)
         const char *f = std::getenv("KEMU_TEST_FAULT");
         ka.test_fault = f ? std::atoi(f) : 0;
@@ -509,6 +522,38 @@ int emu_run(const EmuTask *tasks, int n, int bh, int qcap, int scan_rounds, int 
         }
         for (auto &t : th) t.join();
     };
+    if (component) {   // classification, labelling and the per-component maxima, as the library runs them
+        auto comp_grid = [&](int which, size_t lds_sz) {
+            std::vector<std::thread> th;
+            for (int g = 0; g < n_waves; ++g) {
+                th.emplace_back([&, g, which, lds_sz] {
+                    kemu::blockIdx_.x = (uint32_t)g;
+                    kemu::gridDim_.x = (uint32_t)n_waves;
+                    kemu::blockDim_.x = 64;
+                    std::function<void()> body;
+#define KEMU_PICK(K)                                            \
+    switch (bh) {                                               \
+        case 16: body = [&] { K<16>(tt, ka); }; break;          \
+        case 32: body = [&] { K<32>(tt, ka); }; break;          \
+        default: body = [&] { K<64>(tt, ka); }; break;          \
+    }
+                    if (which == 0) { KEMU_PICK(comp_classify) }
+                    else if (which == 1) { KEMU_PICK(comp_label_local) }
+                    else if (which == 2) { KEMU_PICK(comp_label_merge) }
+                    else if (which == 3) { KEMU_PICK(comp_flatten_max) }
+                    else { KEMU_PICK(comp_write) }
+#undef KEMU_PICK
+                    if (!kemu::run_wave(body, lds_sz)) bad++;
+                });
+            }
+            for (auto &t : th) t.join();
+        };
+        comp_grid(0, 0);
+        comp_grid(1, (size_t)LT_H * LT_W * 4);
+        comp_grid(2, 0);
+        comp_grid(3, 0);
+        comp_grid(4, 0);
+    }
     if (!merged) run_grid(1, n_waves);
     if (stop_after >= 2) run_grid(2, n_waves);
     if (merged || stop_after >= 3) run_grid(3, n_waves);
@@ -520,6 +565,7 @@ int emu_run(const EmuTask *tasks, int n, int bh, int qcap, int scan_rounds, int 
         std::free(jplanes[k]);
         if (iplanes[k]) std::free(iplanes[k]);
         if (scratch[k]) std::free(scratch[k]);
+        if (labs[k]) std::free(labs[k]);
     }
     if (stats) {
         stats->dense = (int64_t)work->stat_dense;
@@ -527,6 +573,7 @@ int emu_run(const EmuTask *tasks, int n, int bh, int qcap, int scan_rounds, int 
         stats->rerun = (int64_t)work->stat_rerun;
         stats->overflow = (int64_t)work->stat_overflow;
         stats->aborted = (int64_t)work->abort;
+        stats->route = (int64_t)work->stat_route;
     }
     const bool full = stop_after == 0 || stop_after >= 3;
     const int rc = bad ? -2 : (work->abort ? -3 : (full && work->pending != 0 ? -4 : 0));
@@ -535,6 +582,7 @@ int emu_run(const EmuTask *tasks, int n, int bh, int qcap, int scan_rounds, int 
     std::free(ring);
     std::free(tpend);
     std::free(tdone);
+    std::free(route);
     return rc;
 }
 
@@ -621,9 +669,9 @@ int main(int argc, char **argv) {
         std::fwrite(imgs[k].data(), 1, imgs[k].size(), f);
         std::fclose(f);
     }
-    std::printf("rc %d dense %lld revisit %lld rerun %lld overflow %lld aborted %lld\n", rc,
+    std::printf("rc %d dense %lld revisit %lld rerun %lld overflow %lld aborted %lld route %lld\n", rc,
                 (long long)st.dense, (long long)st.revisit, (long long)st.rerun, (long long)st.overflow,
-                (long long)st.aborted);
+                (long long)st.aborted, (long long)st.route);
     return rc == 0 ? 0 : 1;
 }
 #endif

@@ -37,6 +37,15 @@ inline T kemu_fetch_min(T *p, T v) {
     return cur;
 }
 #define __hip_atomic_fetch_min(p, v, o, s) kemu_fetch_min((p), (v))
+template <typename T>
+inline T kemu_fetch_max(T *p, T v) {
+    T cur = __atomic_load_n(p, __ATOMIC_SEQ_CST);
+    while (v > cur && !__atomic_compare_exchange_n(p, &cur, v, false, __ATOMIC_SEQ_CST, __ATOMIC_SEQ_CST)) {
+    }
+    return cur;
+}
+#define __hip_atomic_fetch_max(p, v, o, s) kemu_fetch_max((p), (v))
+#define __hip_atomic_fetch_and(p, v, o, s) __atomic_fetch_and((p), (v), (o))
 #define __hip_atomic_exchange(p, v, o, s) __atomic_exchange_n((p), (v), (o))
 #define __hip_atomic_compare_exchange_strong(p, e, d, o1, o2, s) \
     __atomic_compare_exchange_n((p), (e), (d), false, (o1), (o2))
@@ -81,6 +90,10 @@ inline uint32_t __shfl_up(uint32_t v, unsigned d) {
     const int l = kemu::lane();
     const uint32_t r = (uint32_t)kemu::exchange(v, l - (int)d >= 0 ? l - (int)d : l);
     return r;
+}
+inline int __shfl_xor(int v, int m) {
+    const int l = kemu::lane();
+    return (int)kemu::exchange((uint32_t)v, l ^ m);
 }
 inline uint32_t __shfl_down(uint32_t v, unsigned d) {
     const int l = kemu::lane();

@@ -1,0 +1,169 @@
+"""GPU parity of the component route: tasks whose mask takes at most two
+values (0 and one c > 0) are reconstructed through connected-component
+labelling (a maximum of min(marker, mask) per component of the nonzero mask
+pixels); grey tasks in the same launch take the block route.  Every result
+must equal the oracle byte for byte, whichever route a task takes.
+
+Also the adversarial workload at its full size: spiral corridors of
+4096 x 4096 (one 1-pixel corridor of 8.4 M pixels), alone and inside a batch of
+4096 x 4096 nuclei-like tiles as in the 64-tile configuration.
+"""
+import multiprocessing as mp
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def lib(torch_mod):
+    import paper_1209_3332_amd as p
+    return p
+
+
+def dev(torch_mod, a):
+    return torch_mod.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def assert_same(got, want, what):
+    if not np.array_equal(got, want):
+        bad = np.argwhere(got != want)
+        y, x = bad[0]
+        raise AssertionError("%s: %d pixels differ, first at (%d, %d): got %d want %d"
+                             % (what, len(bad), y, x, got[y, x], want[y, x]))
+
+
+def _mixed_tasks(rng, conn):
+    tasks = []
+    for (h, w) in [(1, 1), (1, 9), (9, 1), (37, 300), (70, 530), (300, 777)]:
+        mask = np.where(rng.random((h, w)) < 0.55, 255, 0).astype(np.uint8)
+        marker = rng.integers(0, 256, (h, w)).astype(np.uint8) * (rng.random((h, w)) < 0.01)
+        tasks.append({"op": "dilate", "marker": marker, "mask": mask, "conn": conn})
+    m7 = np.where(rng.random((50, 260)) < 0.6, 7, 0).astype(np.uint8)
+    tasks.append({"op": "dilate", "marker": rng.integers(0, 256, (50, 260)).astype(np.uint8), "mask": m7,
+                  "conn": conn})
+    tasks.append({"op": "dilate", "marker": rng.integers(0, 9, (20, 40)).astype(np.uint8),
+                  "mask": np.zeros((20, 40), np.uint8), "conn": conn})
+    tasks.append({"op": "dilate", "marker": (rng.random((30, 270)) < 0.001).astype(np.uint8) * 9,
+                  "mask": np.full((30, 270), 200, np.uint8), "conn": conn})
+    spiral, seed = synth.spiral_tile(301, 517, "inner")[:2]
+    tasks.append({"op": "dilate", "marker": seed, "mask": spiral, "conn": conn})
+    binary = np.where(rng.random((266, 600)) < 0.6, 255, 0).astype(np.uint8)
+    tasks.append({"op": "fill_holes", "img": binary, "conn": conn})
+    tasks.append({"op": "erode", "marker": np.full_like(binary, 255), "mask": binary, "conn": conn})
+    tasks.append({"op": "hdome", "img": binary, "h": 40, "conn": conn})
+    tasks.append({"op": "regional_max", "img": binary, "conn": conn})
+    n_two = len(tasks)
+    m, k = synth.random_pair(rng, 40, 300, 5)
+    tasks.append({"op": "dilate", "marker": m, "mask": k, "conn": conn})
+    tasks.append({"op": "fill_holes", "img": rng.integers(0, 256, (20, 270)).astype(np.uint8), "conn": conn})
+    return tasks, n_two
+
+
+def _spec(torch_mod, t):
+    two = t["op"] in ("dilate", "erode")
+    img = dev(torch_mod, t["marker"] if two else t["img"])
+    s = {"op": t["op"], "image": img, "conn": t["conn"], "h": t.get("h", 0)}
+    if two:
+        s["mask"] = dev(torch_mod, t["mask"])
+    return img, s
+
+
+@pytest.mark.parametrize("conn", [8, 4])
+def test_mixed_batch_and_plain_calls(torch_mod, lib, oracle_mod, conn):
+    rng = np.random.default_rng(4400 + conn)
+    tasks, n_two = _mixed_tasks(rng, conn)
+    with lib.Recon(0) as ctx:
+        # one batch (the captured graph) holding both routes
+        outs, specs = zip(*[_spec(torch_mod, t) for t in tasks])
+        ctx.batch(list(specs))
+        st = ctx.last_stats()
+        assert st["component_tasks"] == n_two
+        for i, (t, o) in enumerate(zip(tasks, outs)):
+            assert_same(o.cpu().numpy(), oracle_mod.run_task(t), "batch task %d (%s)" % (i, t["op"]))
+        # the same tasks as plain calls
+        for i, t in enumerate(tasks):
+            img, s = _spec(torch_mod, t)
+            op = t["op"]
+            if op == "dilate":
+                ctx.dilate(img, s["mask"], conn)
+            elif op == "erode":
+                ctx.erode(img, s["mask"], conn)
+            elif op == "fill_holes":
+                ctx.fill_holes(img, conn)
+            elif op == "hdome":
+                ctx.hdome(img, t["h"], conn)
+            else:
+                ctx.regional_max(img, conn)
+            st = ctx.last_stats()
+            assert st["component_tasks"] == (1 if i < n_two else 0), (i, op)
+            assert_same(img.cpu().numpy(), oracle_mod.run_task(t), "plain task %d (%s)" % (i, op))
+
+
+def test_route_off_takes_the_block_route(torch_mod, lib, oracle_mod):
+    rng = np.random.default_rng(4500)
+    tasks, _ = _mixed_tasks(rng, 8)
+    with lib.Recon(0, component_route=-1) as ctx:
+        outs, specs = zip(*[_spec(torch_mod, t) for t in tasks])
+        ctx.batch(list(specs))
+        assert ctx.last_stats()["component_tasks"] == 0
+        for i, (t, o) in enumerate(zip(tasks, outs)):
+            assert_same(o.cpu().numpy(), oracle_mod.run_task(t), "block-route task %d (%s)" % (i, t["op"]))
+
+
+@pytest.mark.parametrize("seed_at", ["outer", "inner"])
+def test_spiral_4096(torch_mod, lib, seed_at):
+    """The full-size adversarial corridor: one component of 8.4 M pixels; the
+    result is the mask itself (every corridor pixel reached at 255)."""
+    marker, mask, _ = synth.spiral_tile(4096, 4096, seed_at)
+    with lib.Recon(0) as ctx:
+        for conn in (8, 4):
+            print("spiral 4096 %s conn %d" % (seed_at, conn), flush=True)
+            m, k = dev(torch_mod, marker), dev(torch_mod, mask)
+            ctx.dilate(m, k, conn)
+            st = ctx.last_stats()
+            assert st["component_tasks"] == 1
+            assert_same(m.cpu().numpy(), mask, "spiral 4096 %s conn %d" % (seed_at, conn))
+
+
+def _gen(i):
+    mask = synth.scaled_config1_tile(4096, 4096, synth.seed_for(3, i))
+    return i, synth.hdome_marker(mask, 30), mask
+
+
+def test_config3_batch_at_full_size(torch_mod, lib, oracle_mod):
+    """The first 16 tiles of the 64-tile configuration at their stated size:
+    4096 x 4096 nuclei-like tiles with two 4096 x 4096 spiral corridors (tile 7
+    seeded at the outer end, tile 15 at the inner end), one batched launch;
+    every nuclei tile equals the oracle, every spiral its mask."""
+    n = 16
+    tiles = [None] * n
+    with mp.get_context("fork").Pool(8) as pool:
+        for i, marker, mask in pool.imap_unordered(_gen, [i for i in range(n) if i % 8 != 7]):
+            tiles[i] = ("nuclei", marker, mask)
+    for i in (7, 15):
+        marker, mask, _ = synth.spiral_tile(4096, 4096, "outer" if i == 7 else "inner")
+        tiles[i] = ("spiral", marker, mask)
+    with ThreadPoolExecutor(8) as ex:
+        wants = list(ex.map(lambda t: t[2] if t[0] == "spiral" else oracle_mod.recon_dilate(t[1], t[2], 8), tiles))
+    with lib.Recon(0) as ctx:
+        outs = [dev(torch_mod, t[1]) for t in tiles]
+        masks = [dev(torch_mod, t[2]) for t in tiles]
+        print("config-3 batch: %d tiles of 4096 x 4096" % n, flush=True)
+        ctx.batch([{"op": "dilate", "image": o, "mask": k, "conn": 8} for o, k in zip(outs, masks)])
+        st = ctx.last_stats()
+        assert st["component_tasks"] == 2
+        for i, (o, want) in enumerate(zip(outs, wants)):
+            assert_same(o.cpu().numpy(), want, "config-3 tile %d (%s)" % (i, tiles[i][0]))

@@ -158,11 +158,15 @@ def test_fill_holes_grey_and_ragged(torch_mod, rc, oracle_mod, conn):
         assert_same(gpu_fill(torch_mod, rc, b, conn), oracle_mod.fill_holes(b, conn), "binary fill %s" % (shape,))
 
 
+@pytest.mark.parametrize("route", [0, -1], ids=["component", "block"])
 @pytest.mark.parametrize("seed_at", ["outer", "inner"])
-def test_spiral_1024(torch_mod, rc, seed_at):
+def test_spiral_1024(torch_mod, lib, seed_at, route):
+    # both routes: labelling (the default for a two-valued mask) and block visits
     marker, mask, _ = synth.spiral_tile(1024, 1024, seed_at)
-    for conn in (8, 4):
-        assert_same(gpu_dilate(torch_mod, rc, marker, mask, conn), mask, "spiral %s conn %d" % (seed_at, conn))
+    with lib.Recon(0, component_route=route) as ctx:
+        for conn in (8, 4):
+            assert_same(gpu_dilate(torch_mod, ctx, marker, mask, conn), mask,
+                        "spiral %s conn %d route %d" % (seed_at, conn, route))
 
 
 def test_unaligned_pitch_and_offset(torch_mod, rc, oracle_mod):
@@ -191,13 +195,16 @@ def test_unaligned_pitch_and_offset(torch_mod, rc, oracle_mod):
 def test_tuning_invariance(torch_mod, lib, oracle_mod, cfg):
     marker, mask, binary = synth.config2_tile(seed=synth.seed_for(2, 11), size=768, n_gauss=106)
     sm, smask, _ = synth.spiral_tile(300, 520, "inner")
-    with lib.Recon(0, **cfg) as ctx:
-        for conn in (8, 4):
-            assert_same(gpu_dilate(torch_mod, ctx, marker, mask, conn), oracle_mod.recon_dilate(marker, mask, conn),
-                        "%s conn %d" % (cfg, conn))
-            assert_same(gpu_fill(torch_mod, ctx, binary, conn), oracle_mod.fill_holes(binary, conn),
-                        "%s fill conn %d" % (cfg, conn))
-            assert_same(gpu_dilate(torch_mod, ctx, sm, smask, conn), smask, "%s spiral conn %d" % (cfg, conn))
+    # the binary fill and the spiral take the block route too (component_route -1)
+    for route in (0, -1):
+        with lib.Recon(0, component_route=route, **cfg) as ctx:
+            for conn in (8, 4):
+                what = "%s conn %d route %d" % (cfg, conn, route)
+                assert_same(gpu_dilate(torch_mod, ctx, marker, mask, conn),
+                            oracle_mod.recon_dilate(marker, mask, conn), what)
+                assert_same(gpu_fill(torch_mod, ctx, binary, conn), oracle_mod.fill_holes(binary, conn),
+                            "fill " + what)
+                assert_same(gpu_dilate(torch_mod, ctx, sm, smask, conn), smask, "spiral " + what)
 
 
 def test_determinism(torch_mod, rc):
@@ -312,7 +319,9 @@ def test_small_batch_in_timing_context(torch_mod, lib, oracle_mod):
                        {"op": "fill_holes", "image": b, "conn": 8}])
             st = ctx.last_stats()
             assert st["drain_ms"] > 0 and st["total_ms"] >= st["drain_ms"]
-            assert st["dense_visits"] == 2 * 32 * 4
+            # the binary fill-holes takes the component route: only the
+            # reconstruction's 32 x 4 blocks are visited
+            assert st["dense_visits"] == 32 * 4 and st["component_tasks"] == 1
             t = ctx.launch_times(0)
             assert t["drain_ms"] == st["drain_ms"]
             assert_same(m.cpu().numpy(), oracle_mod.recon_dilate(marker, mask, 8), "batched dilate %d" % rep)

@@ -198,3 +198,48 @@ def test_failed_claims_abort_the_launch(emu_exe):
                           test_fault=1, timeout=120)
     assert "ERROR: AddressSanitizer" not in log and "runtime error" not in log, log[-2000:]
     assert rc != 0 and "rc -3" in log and "aborted 1" in log, log[-2000:]
+
+
+def _route_count(log):
+    return int(log.split(" route ")[1].split()[0])
+
+
+@pytest.mark.parametrize("conn", [8, 4])
+@pytest.mark.parametrize("bh", [16, 32, 64])
+def test_component_route(emu_exe, oracle_mod, conn, bh):
+    """Two-valued masks take the component route (labelling and a maximum per
+    component), grey ones the block route, in one launch; every result equals
+    the oracle.  Covers binary dilation with grey markers, markers above the
+    mask, a mask of one nonzero value other than 255, all-zero and constant
+    masks, fill-holes (complemented mask), erosion, h-dome and regional maxima
+    of binary images, spirals, ragged shapes and tiles wider than one block."""
+    rng = np.random.default_rng(900 + conn + bh)
+    tasks = []
+    two_valued = 0
+    for (h, w) in [(1, 1), (1, 9), (9, 1), (37, 300), (70, 530)]:
+        mask = np.where(rng.random((h, w)) < 0.55, 255, 0).astype(np.uint8)
+        marker = rng.integers(0, 256, (h, w)).astype(np.uint8) * (rng.random((h, w)) < 0.02)
+        tasks.append({"op": "dilate", "marker": marker, "mask": mask, "conn": conn})
+        two_valued += 1
+    m7 = np.where(rng.random((50, 260)) < 0.6, 7, 0).astype(np.uint8)          # {0, 7}, markers above it
+    tasks.append({"op": "dilate", "marker": rng.integers(0, 256, (50, 260)).astype(np.uint8), "mask": m7,
+                  "conn": conn})
+    tasks.append({"op": "dilate", "marker": rng.integers(0, 9, (20, 40)).astype(np.uint8),
+                  "mask": np.zeros((20, 40), np.uint8), "conn": conn})                # all zero
+    tasks.append({"op": "dilate", "marker": (rng.random((30, 270)) < 0.001).astype(np.uint8) * 9,
+                  "mask": np.full((30, 270), 200, np.uint8), "conn": conn})           # constant
+    two_valued += 3
+    spiral, seed = synth.spiral_tile(61, 300, "inner")[:2]
+    tasks.append({"op": "dilate", "marker": seed, "mask": spiral, "conn": conn})
+    two_valued += 1
+    binary = np.where(rng.random((66, 300)) < 0.6, 255, 0).astype(np.uint8)
+    tasks.append({"op": "fill_holes", "img": binary, "conn": conn})
+    tasks.append({"op": "erode", "marker": np.full_like(binary, 255), "mask": binary, "conn": conn})
+    tasks.append({"op": "hdome", "img": binary, "h": 40, "conn": conn})
+    tasks.append({"op": "regional_max", "img": binary, "conn": conn})
+    two_valued += 4
+    m, k = synth.random_pair(rng, 40, 300, 5)                   # grey: the block route
+    tasks.append({"op": "dilate", "marker": m, "mask": k, "conn": conn})
+    tasks.append({"op": "fill_holes", "img": rng.integers(0, 256, (20, 270)).astype(np.uint8), "conn": conn})
+    log = _check(emu_exe, oracle_mod, tasks, n_waves=3, bh=bh, component=1)
+    assert _route_count(log) == two_valued, log[-500:]
