@@ -16,11 +16,10 @@ Alongside, in the same run: the per-kernel HIP-event durations of the timed
 steps and the dominant kernel's roofline (with the HBM traffic of the
 committed counter summary when it was taken on the current kernel source);
 erosion, h-dome and regional maxima; labelling and the area filter; the
-distance transform and Pre-Watershed markers; a 64-tile batch (every eighth
-tile a spiral corridor, 1024 x 1024 by default: a corridor is one sequential
-chain, and a 4096 x 4096 one takes tens of seconds; --spiral-size 4096 runs
-it) and an uneven 256-tile autotuned batch against per-tile calls; the
-serving loop at several arrival rates.  Last comes the oracle leg: the CPU
+distance transform and Pre-Watershed markers; a 64-tile batch of 4096 x 4096
+tiles (every eighth a 4096 x 4096 spiral corridor, which takes the component
+route) and an uneven 256-tile autotuned batch against per-tile calls; the
+serving loop at arrival rates from 50 to 2000 tiles/s.  Last comes the oracle leg: the CPU
 oracle timed on the host cores on a bounded sample, then the comparison of
 every section's recorded outputs with the oracle (the only part of this
 script that runs the oracle; --no-cpu-baseline skips it).
@@ -129,15 +128,29 @@ def _set_at(out, path, value):
     node[path[-1]] = value
 
 
-def run_checks(out):
-    """The oracle leg: evaluate every deferred comparison; returns True if all agree."""
+def run_checks(out, workers=4):
+    """The oracle leg: evaluate every deferred comparison (on a thread pool: the
+    oracle runs in C without the interpreter lock); returns True if all agree.
+    A path checked several times holds the conjunction of its verdicts."""
+    from concurrent.futures import ThreadPoolExecutor
     import numpy as np
     import oracle
-    all_ok = True
-    for c in CHECKS:
+
+    def solve(c):
         t0 = time.perf_counter()
         want = getattr(oracle, c["fn"])(*c["args"])
-        dt = time.perf_counter() - t0
+        return want, time.perf_counter() - t0
+
+    # the comparisons that report a single-core rate run alone, the others in parallel
+    timed = [c for c in CHECKS if c["rate_path"]]
+    rest = [c for c in CHECKS if not c["rate_path"]]
+    results = {id(c): solve(c) for c in timed}
+    with ThreadPoolExecutor(max(1, workers)) as ex:
+        for c, r in zip(rest, ex.map(solve, rest)):
+            results[id(c)] = r
+    all_ok = True
+    for c in CHECKS:
+        want, dt = results[id(c)]
         if c["fn"] == "label":
             ok = bool(np.array_equal(c["got"][0], want[0]) and c["got"][1] == want[1])
         else:
@@ -149,7 +162,11 @@ def run_checks(out):
             node["checked"] = node.get("checked", 0) + 1
             node["mismatches"] = node.get("mismatches", 0) + int(not ok)
         else:
-            _set_at(out, c["path"], ok)
+            node = out
+            for key in c["path"][:-1]:
+                node = node[key]
+            prev = node.get(c["path"][-1])
+            node[c["path"][-1]] = ok if prev is None else bool(prev and ok)
         if c["rate_path"]:
             _set_at(out, c["rate_path"], c["px"] / dt / 1e6)
         all_ok &= ok
@@ -240,30 +257,51 @@ def headline(recon, torch, cfg, marker, mask, binary, steps, warmup, mode):
 
     avg = lambda xs, k: sum(x[k] for x in xs) / len(xs)
     kernels = {}
+    op_bytes = {"dilate": BYTES_DILATE * mask.size, "fill_holes": BYTES_FILL * mask.size}
+    ops_of = {"dilate + fill_holes": ("dilate", "fill_holes"), "dilate": ("dilate",), "fill_holes": ("fill_holes",)}
     for name, ts in groups.items():
         st = stats[name]
+        # which operations the launch completed in revisit_drain and which in the
+        # component route (the binary fill-holes takes the route; the grey
+        # reconstruction the block visits)
+        on_route = ("fill_holes",) if st["component_tasks"] == 1 and "fill_holes" in ops_of[name] else ()
         kernels[name] = {"dense_pass_ms": avg(ts, "dense_ms"), "border_seed_ms": avg(ts, "seed_ms"),
-                         "revisit_drain_ms": avg(ts, "drain_ms"), "launch_ms": avg(ts, "total_ms"),
+                         "revisit_drain_ms": avg(ts, "drain_ms"), "component_route_ms": avg(ts, "route_ms"),
+                         "launch_ms": avg(ts, "total_ms"),
                          "dense_visits": st["dense_visits"], "revisits": st["revisits"], "reruns": st["reruns"],
-                         "queue_overflows": st["queue_overflows"]}
-    # dominant kernel (by average duration) and its roofline.  Algorithmic
-    # bytes: the persistent pipeline makes every visit, first or later, in
-    # revisit_drain; a visit reads a block's mask and marker and writes the
-    # marker back (3 B/px of the block).
+                         "queue_overflows": st["queue_overflows"], "component_tasks": st["component_tasks"],
+                         "ops_in_revisit_drain": [o for o in ops_of[name] if o not in on_route],
+                         "ops_in_component_route": list(on_route)}
+    # dominant kernel (by average duration) and its roofline.  Algorithmic bytes
+    # per the method's own traffic: 3 B/px for a reconstruction (read the mask,
+    # read the marker, write the result), 2 B/px for a fill-holes (read the
+    # image, write the result), counted for the operations that kernel
+    # completes.  The bytes a visit schedule moves (3 B/px of a block per
+    # visit, first or later) are reported beside them as per_visit_bytes.
     bh = cfg.get("block_rows", 32)
-    cand = [("revisit_drain (%s)" % name, kv["revisit_drain_ms"],
-             3.0 * bh * 256 * (kv["revisits"] + kv["dense_visits"])) for name, kv in kernels.items()]
+    cand = []
+    for name, kv in kernels.items():
+        cand.append(("revisit_drain (%s)" % name, kv["revisit_drain_ms"],
+                     sum(op_bytes[o] for o in kv["ops_in_revisit_drain"]),
+                     3.0 * bh * 256 * (kv["revisits"] + kv["dense_visits"])))
+        if kv["ops_in_component_route"]:
+            cand.append(("component route (%s)" % name, kv["component_route_ms"],
+                         sum(op_bytes[o] for o in kv["ops_in_component_route"]), None))
     dom = max(cand, key=lambda c: c[1])
     achieved = dom[2] / (dom[1] * 1e-3) / 1e9
     traffic = committed_traffic(dom[0])
     roofline = {"kernel": dom[0], "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "algorithmic_bytes": dom[2],
-                "kernel_ms": dom[1],
+                "kernel_ms": dom[1], "per_visit_bytes": dom[3],
+                "per_visit_GBs": dom[3] / (dom[1] * 1e-3) / 1e9 if dom[3] else None,
                 # counted bandwidth: the profiled HBM bytes of one launch over the live kernel time
                 "counted_GBs": traffic / (dom[1] * 1e-3) / 1e9 if traffic else None,
                 "counted_frac": traffic / (dom[1] * 1e-3) / 1e9 / HBM_PEAK_GBS if traffic else None,
+                "traffic_over_algorithmic": traffic / dom[2] if traffic else None,
                 "step_GBs": (BYTES_DILATE + BYTES_FILL) * mask.size / (ms_per_step * 1e-3) / 1e9,
-                "kernel_source": kernel_sha()}
+                "kernel_source": kernel_sha(),
+                "others": [{"kernel": c[0], "kernel_ms": c[1], "algorithmic_bytes": c[2],
+                            "achieved": c[2] / (c[1] * 1e-3) / 1e9 if c[1] > 0 else None} for c in cand if c is not dom]}
     return {"ms_per_step": ms_per_step, "value": value, "kernels": kernels, "roofline": roofline,
             "outputs": outputs}
 
@@ -436,34 +474,56 @@ def distance(recon, torch, binary, steps, conn=8):
 
 
 def batched_vs_per_tile(recon, torch, ctx_cfg, n_tiles, size, workers, spiral_size):
+    """The 64-tile workload: one batched graph launch of all tiles against the
+    same tiles as plain per-tile calls; also the 56 nuclei tiles alone and the 8
+    spiral corridors alone as batched launches, so that the nuclei tiles'
+    batched rate and the spirals' makespan are reported apart."""
     t0 = time.perf_counter()
     batch = make_batch(n_tiles, size, workers, spiral_size)
     log("batch: generated %d tiles in %.1f s" % (n_tiles, time.perf_counter() - t0))
     dev = torch.device("cuda:0")
     masks = [torch.from_numpy(b[2]).to(dev) for b in batch]
     pristine = [torch.from_numpy(b[1]).to(dev) for b in batch]
-    px = sum(m.numel() for m in masks)
     kinds = [b[0] for b in batch]
-    res = {"tiles": n_tiles, "tile": [size, size], "spirals": kinds.count("spiral"),
-           "spiral_tile": [spiral_size, spiral_size], "pixels": px}
+    px_of = lambda idx: sum(masks[i].numel() for i in idx)
+    every = list(range(n_tiles))
+    nuclei = [i for i in every if kinds[i] == "nuclei"]
+    spirals = [i for i in every if kinds[i] == "spiral"]
+    res = {"tiles": n_tiles, "tile": [size, size], "spirals": len(spirals),
+           "spiral_tile": [spiral_size, spiral_size], "pixels": px_of(every)}
     with recon.Recon(0, **ctx_cfg) as ctx:
         stream = torch.cuda.current_stream()
-        # batched: one graph replay over the whole batch (warm once)
-        for rep in range(2):
-            work = [p.clone() for p in pristine]
-            torch.cuda.synchronize()
-            t = time.perf_counter()
-            ctx.batch([{"op": "dilate", "image": w, "mask": m, "conn": 8} for w, m in zip(work, masks)], stream)
-            st = ctx.last_stats()
-            torch.cuda.synchronize()
-            wall = time.perf_counter() - t
-        res["batched"] = {"Mpixel_s": px / wall / 1e6, "ms": wall * 1e3, "launch_ms": st["total_ms"],
-                          "revisits": st["revisits"]}
-        # a spiral corridor's reconstruction is its mask; a nuclei tile goes to the oracle leg
-        res["spirals_equal_mask"] = all(torch.equal(work[i], masks[i]) for i in range(n_tiles) if kinds[i] == "spiral")
+
+        def batched(idx):
+            # one graph replay over the tiles idx (the second of two runs is timed)
+            for rep in range(2):
+                work = {i: pristine[i].clone() for i in idx}
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                ctx.batch([{"op": "dilate", "image": work[i], "mask": masks[i], "conn": 8} for i in idx], stream)
+                st = ctx.last_stats()
+                torch.cuda.synchronize()
+                wall = time.perf_counter() - t
+            return work, {"Mpixel_s": px_of(idx) / wall / 1e6, "ms": wall * 1e3, "launch_ms": st["total_ms"],
+                          "revisits": st["revisits"], "component_tasks": st["component_tasks"]}
+
+        work, res["batched"] = batched(every)
+        # a spiral corridor's reconstruction is its mask; nuclei tiles go to the oracle leg
+        res["spirals_equal_mask"] = all(torch.equal(work[i], masks[i]) for i in spirals)
+        res["parity_checked_tiles"] = [nuclei[j] for j in sorted({0, len(nuclei) // 3, 2 * len(nuclei) // 3,
+                                                                   len(nuclei) - 1})] if nuclei else []
         res["parity_ok"] = None
-        defer_check(("batched_vs_per_tile", "parity_ok"), work[0].cpu().numpy(), "recon_dilate", batch[0][1],
-                    batch[0][2], 8)
+        for i in res["parity_checked_tiles"]:
+            defer_check(("batched_vs_per_tile", "parity_ok"), work[i].cpu().numpy(), "recon_dilate", batch[i][1],
+                        batch[i][2], 8)
+        del work
+        if nuclei and spirals:
+            res["batched_nuclei_only"] = batched(nuclei)[1]
+            w_s, res["batched_spirals_only"] = batched(spirals)
+            res["batched_spirals_only"]["makespan_ms"] = res["batched_spirals_only"]["ms"]
+            res["spirals_equal_mask"] = res["spirals_equal_mask"] and all(torch.equal(w_s[i], masks[i])
+                                                                           for i in spirals)
+            del w_s
         # per-tile: the same tiles as plain calls, one after another
         work = [p.clone() for p in pristine]
         torch.cuda.synchronize()
@@ -476,10 +536,14 @@ def batched_vs_per_tile(recon, torch, ctx_cfg, n_tiles, size, workers, spiral_si
         wall = time.perf_counter() - t
         nuc = [l for l, k in zip(lat, kinds) if k == "nuclei"]
         spi = [l for l, k in zip(lat, kinds) if k == "spiral"]
-        res["per_tile"] = {"Mpixel_s": px / wall / 1e6, "ms": wall * 1e3,
+        res["per_tile"] = {"Mpixel_s": px_of(every) / wall / 1e6, "ms": wall * 1e3,
                            "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99),
                                           "nuclei_p50": percentile(nuc, 50), "nuclei_p99": percentile(nuc, 99),
                                           "spiral_max": max(spi) if spi else None}}
+        res["spirals_equal_mask"] = res["spirals_equal_mask"] and all(torch.equal(work[i], masks[i])
+                                                                       for i in spirals)
+        if nuc:
+            res["per_tile"]["nuclei_Mpixel_s"] = px_of(nuclei) / (sum(nuc) * 1e-3) / 1e6
         res["batched_over_per_tile"] = res["batched"]["Mpixel_s"] / res["per_tile"]["Mpixel_s"]
     return res
 
@@ -528,27 +592,53 @@ def uneven_batched_vs_per_tile(recon, torch, n_tiles, workers):
             ctx.batch([dict(tk, image=w) for tk, w in zip(tuned, work)], stream)
             torch.cuda.synchronize()
             wall = time.perf_counter() - t
-        launch_ms = ctx.last_stats()["total_ms"]
-        res["batched"] = {"Mpixel_s": px / wall / 1e6, "ms": wall * 1e3, "launch_ms": launch_ms}
-        res["parity_checked_tiles"] = sorted({0, n_tiles // 2, n_tiles - 1})
-        for j, i in enumerate(res["parity_checked_tiles"]):
-            res["parity_tile_%d" % j] = None
-            defer_check(("uneven_batched_vs_per_tile", "parity_tile_%d" % j), work[i].cpu().numpy(), "recon_dilate",
+        st = ctx.last_stats()
+        res["batched"] = {"Mpixel_s": px / wall / 1e6, "ms": wall * 1e3, "launch_ms": st["total_ms"],
+                          "queue_overflows": st["queue_overflows"], "revisits": st["revisits"],
+                          "reruns": st["reruns"]}
+        # parity on a stratified sample: two tiles of every size bucket and connectivity
+        strata = {}
+        for i, (j, m, c) in enumerate(tiles):
+            strata.setdefault((tune.bucket_of(*m.shape), c), []).append(i)
+        picks = sorted(i for idx in strata.values() for i in (idx[0], idx[-1]))
+        res["parity_checked_tiles"] = sorted(set(picks))
+        res["parity_strata"] = sorted("%s/conn%d" % k for k in strata)
+        res["parity_ok"] = None
+        for i in res["parity_checked_tiles"]:
+            defer_check(("uneven_batched_vs_per_tile", "parity_ok"), work[i].cpu().numpy(), "recon_dilate",
                         tiles[i][0], tiles[i][1], conns[i])
-    with recon.Recon(0, timing=1) as ctx:
-        for rep in range(2):
-            work = [p.clone() for p in pristine]
-            torch.cuda.synchronize()
-            t = time.perf_counter()
-            for w, m, c in zip(work, masks, conns):
-                ctx.dilate(w, m, c, stream)
-            torch.cuda.synchronize()
-            wall = time.perf_counter() - t
-        lat = [ctx.launch_times(b)["total_ms"] for b in range(min(64, n_tiles))]
-        res["per_tile"] = {"Mpixel_s": px / wall / 1e6, "ms": wall * 1e3,
-                           "launch_ms_p50": percentile(lat, 50), "launch_ms_p99": percentile(lat, 99),
-                           "latency_sample": "the last %d launches" % len(lat)}
+
+    def per_tile(tuned_calls):
+        """256 plain launches, one tile each: with the library defaults, or with
+        each tile's own tuned knobs (a context per tuned block height, the
+        tile's scan rounds and queue capacity as a one-task launch)."""
+        ctxs = {}
+        try:
+            for rep in range(2):
+                work = [p.clone() for p in pristine]
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                for w, m, c, tk in zip(work, masks, conns, tuned):
+                    if tuned_calls:
+                        tb = tune.config_for(cache, *m.shape, c)["block_rows"]
+                        if tb not in ctxs:
+                            ctxs[tb] = recon.Recon(0, block_rows=tb, queue_capacity=qcap, timing=1)
+                        ctxs[tb].batch([dict(tk, image=w)], stream)
+                    else:
+                        if None not in ctxs:
+                            ctxs[None] = recon.Recon(0, timing=1)
+                        ctxs[None].dilate(w, m, c, stream)
+                torch.cuda.synchronize()
+                wall = time.perf_counter() - t
+        finally:
+            for cx in ctxs.values():
+                cx.close()
+        return {"Mpixel_s": px / wall / 1e6, "ms": wall * 1e3}
+
+    res["per_tile"] = per_tile(False)
+    res["per_tile_tuned"] = per_tile(True)
     res["batched_over_per_tile"] = res["batched"]["Mpixel_s"] / res["per_tile"]["Mpixel_s"]
+    res["batched_over_per_tile_tuned"] = res["batched"]["Mpixel_s"] / res["per_tile_tuned"]["Mpixel_s"]
     return res
 
 
@@ -624,12 +714,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--size", type=int, default=4096)
     ap.add_argument("--batch-tiles", type=int, default=64, help="0 skips the batched-vs-per-tile comparison")
-    ap.add_argument("--spiral-size", type=int, default=1024, help="side of the spiral-corridor tiles of the batch")
+    ap.add_argument("--spiral-size", type=int, default=4096, help="side of the spiral-corridor tiles of the batch")
     ap.add_argument("--uneven-tiles", type=int, default=256, help="0 skips the uneven autotuned batch")
-    ap.add_argument("--serve-rates", default="50,200,1000,2000",
+    ap.add_argument("--serve-rates", default="50,100,200,500,1000,2000",
                     help="Poisson arrival rates (tiles/s) of the serving run; empty skips it")
-    ap.add_argument("--serve-seconds", type=float, default=2.0)
-    ap.add_argument("--serve-pool", type=int, default=64)
+    ap.add_argument("--serve-seconds", type=float, default=10.0, help="seconds of arrivals per rate")
+    ap.add_argument("--serve-pool", type=int, default=256)
     ap.add_argument("--next-ops-steps", type=int, default=10,
                     help="launches per op of erosion / h-dome / regional maxima on the tile (0 skips)")
     ap.add_argument("--label-steps", type=int, default=10,
@@ -731,7 +821,7 @@ def main():
         # the oracle leg: its rate on the host cores, then every deferred comparison
         out["cpu_baseline"] = cpu_baseline(marker, mask, binary)
         log("cpu baseline: %.1f Mpixel/s on %d cores" % (out["cpu_baseline"]["value"], out["cpu_baseline"]["cores"]))
-        ok = run_checks(out)
+        ok = run_checks(out, args.workers)
         log("oracle checks: %d compared, %s" % (len(CHECKS), "all equal" if ok else "MISMATCH"))
     print(json.dumps(out), flush=True)
     if not ok:

@@ -42,3 +42,25 @@ def test_deferred_checks(oracle_mod):
     b.CHECKS.clear()
     b.defer_check(("labelling", "label", "parity"), (lab, n + 1), "label", binary, 8)
     assert not b.run_checks(out) and out["labelling"]["label"]["parity"] is False   # a wrong count fails
+
+
+def test_repeated_path_is_the_conjunction(oracle_mod):
+    """Several sampled tiles report into one parity field: one bad tile makes it False."""
+    b = _bench()
+    rng = np.random.default_rng(4)
+    mask = rng.integers(0, 256, (30, 50)).astype(np.uint8)
+    marker = np.maximum(mask.astype(np.int32) - 20, 0).astype(np.uint8)
+    good = oracle_mod.recon_dilate(marker, mask, 8)
+    bad = good.copy()
+    bad[3, 3] ^= 4
+    out = {"batch": {"parity_ok": None}}
+    b.CHECKS.clear()
+    for got in (good, bad, good):
+        b.defer_check(("batch", "parity_ok"), got, "recon_dilate", marker, mask, 8)
+    assert not b.run_checks(out, workers=3)
+    assert out["batch"]["parity_ok"] is False
+    b.CHECKS.clear()
+    out = {"batch": {"parity_ok": None}}
+    for got in (good, good):
+        b.defer_check(("batch", "parity_ok"), got, "recon_dilate", marker, mask, 8)
+    assert b.run_checks(out) and out["batch"]["parity_ok"] is True
