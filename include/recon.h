@@ -152,15 +152,19 @@ typedef struct {
     int32_t test_fault;        /* test hook, 0 in production: 1 = every compare-and-swap that
                                   claims a block is made to fail, so that launches give up
                                   (their calls then report RECON_EDEVICE) */
-    int32_t component_route;   /* 0 (default): a task whose mask takes at most two values, 0
-                                  and one c > 0 (a binary mask; fill-holes of a binary image),
-                                  is reconstructed through connected-component labelling: the
-                                  result is then, on each component of the nonzero mask pixels,
-                                  the largest min(marker, mask) over that component, and 0
-                                  elsewhere -- the same bytes, without the block visits a long
-                                  corridor would chain.  Each task then also holds an int32
-                                  label plane in the context's scratch area (4 bytes per pixel).
-                                  -1: every task takes the block route */
+    int32_t component_route;   /* The component route: a task whose mask takes at most two
+                                  values, 0 and one c > 0 (a binary mask; fill-holes of a binary
+                                  image), can be reconstructed through connected-component
+                                  labelling: the result is then, on each component of the
+                                  nonzero mask pixels, the largest min(marker, mask) over that
+                                  component, and 0 elsewhere -- the same bytes, without the
+                                  chains of block visits a long corridor causes.  0 (default):
+                                  taken where it pays -- the foreground is thin (short runs:
+                                  corridors, noise), or the launch has no grey task whose block
+                                  visits the two-valued task's visits would overlap with.
+                                  1: taken by every two-valued mask.  -1: never.  With 0 or 1
+                                  each task holds an int32 label plane in the context's
+                                  scratch area (4 bytes per pixel). */
     int32_t reserved[2];
 } recon_config;
 

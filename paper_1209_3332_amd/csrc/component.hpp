@@ -34,10 +34,13 @@
 //                     root's own entry of the label plane, encoded as
 //                     ENC + value (ENC is above every node id, so a root
 //                     entry at or above ENC marks a root that has an offer);
-//   comp_write        J <- 0 on mask 0, else the value its root's entry holds
-//                     (0 for a root without any offer).
-// The revisit kernel then completes the blocks of these tasks without
-// visiting them, and finish_result maps J as for any task.
+//   comp_write        the reconstruction: 0 on mask 0, else the value its
+//                     root's entry holds (0 for a root without any offer),
+//                     written as the task's result (into the caller's marker
+//                     for a dilation, mapped as finish_result would otherwise).
+// These tasks need no marker plane (the offers derive their initial marker
+// as init_marker would), and none of their blocks is ever queued: init_marker,
+// the ring and finish_result skip them.
 #pragma once
 #include "kernels.hpp"
 #include "label.hpp"
@@ -58,7 +61,7 @@ __device__ __forceinline__ LabelArgs comp_label_args(const TaskDev &t) {
     la.conn = t.conn;
     la.tiles_x = t.nbx;     // LT_W == BW: a block column is a tile column
     la.bits = nullptr;
-    la.lab_vec = (((uintptr_t)t.lab | (uintptr_t)(t.pitch_lab * 4)) & 15u) == 0 ? 1 : 0;
+    la.lab_vec = 1;   // the planes are 256-byte aligned with a pitch of a multiple of 4 elements
     la.fg_inv = t.minv;
     return la;
 }
@@ -78,68 +81,116 @@ struct UnitWalk {
     }
 };
 
+// A first look at every task's mask: one wave per task samples 1024 pixels
+// spread over the image (16 rows of 64 columns) and records the OR and AND of
+// the nonzero values found.  A grey mask nearly always shows two different
+// nonzero values here, and the full classification then skips it whole.  The
+// samples also estimate how thin the foreground is: the share of sampled
+// foreground pixels that start a horizontal run (whose left neighbour is
+// background) -- about 1 / (mean run length); at least 1/32 counts as thin
+// (a corridor, noise), as does a sample without foreground.  A task without
+// a label plane, or a grey one, marks the launch as having block-route work.
+__global__ __launch_bounds__(64) void comp_sample(TaskTable tt, KArgs a) {
+    const int ln = lane_id();
+    const uint32_t n = n_tasks_of(tt);
+    for (uint32_t k = blockIdx.x; k < n; k += gridDim.x) {
+        const TaskDev t = task_of(tt, (int)k);
+        if (!t.lab) {
+            if (ln == 0) a.work->has_grey = 1u;
+            continue;
+        }
+        uint32_t o = 0, an = 0xffu, fg = 0, starts = 0;
+        for (int r = 0; r < 16; ++r) {
+            const int y = (int)(((int64_t)(2 * r + 1) * t.h) / 32);
+            const int x = (int)(((int64_t)(2 * ln + 1) * t.w) / 128);
+            const uint32_t b = mask1(t, y, x);
+            if (b) {
+                o |= b;
+                an &= b;
+                fg += 1;
+                if (x == 0 || mask1(t, y, x - 1) == 0u) starts += 1;
+            }
+        }
+        for (int d = 1; d < LANES; d <<= 1) {
+            o |= (uint32_t)__shfl_xor((int)o, d);
+            an &= (uint32_t)__shfl_xor((int)an, d);
+            fg += (uint32_t)__shfl_xor((int)fg, d);
+            starts += (uint32_t)__shfl_xor((int)starts, d);
+        }
+        if (ln == 0) {   // the task's words are still at their identities: no other writer yet
+            a.route[ROUTE_WORDS * k] = o;
+            a.route[ROUTE_WORDS * k + 1] = an;
+            a.route[ROUTE_WORDS * k + 4] = (fg == 0u || 32u * starts >= fg) ? 1u : 0u;
+            if (o != 0u && o != an) a.work->has_grey = 1u;
+        }
+    }
+}
+
+// Classification: one wave per block (grid-stride), the block's rows loaded
+// together; each lane keeps the OR and AND of its nonzero mask bytes, the
+// wave combines them once per task it leaves, and only a combination that
+// changes a task's words is written.  A wave skips the blocks of a task whose
+// words already show two different nonzero values (it can never take the
+// route); the words are read with plain loads there, a stale copy only
+// skipping less.
 template <int BH>
 __global__ __launch_bounds__(64) void comp_classify(TaskTable tt, KArgs a) {
     const int ln = lane_id();
-    const uint64_t n = (uint64_t)total_blocks_of(tt) * BH;
+    const uint32_t n = total_blocks_of(tt);
     UnitWalk wk;
     int acc_k = -1;                 // task whose partial OR / AND this wave holds
     uint32_t acc_or = 0, acc_and = 0xffu;
     auto flush = [&]() {
-        if (acc_k >= 0 && ln == 0) {
-            uint32_t *wo = a.route + 2 * acc_k, *wa = wo + 1;
-            // only values that change a word are written (most waves change nothing)
-            const uint32_t co = __hip_atomic_load(wo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if ((co | acc_or) != co) __hip_atomic_fetch_or(wo, acc_or, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const uint32_t ca = __hip_atomic_load(wa, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if ((ca & acc_and) != ca) __hip_atomic_fetch_and(wa, acc_and, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        acc_or = 0;
-        acc_and = 0xffu;
-    };
-    for (uint64_t u = blockIdx.x; u < n; u += gridDim.x) {
-        const uint32_t gb = (uint32_t)(u / BH);
-        const int r = (int)(u % BH);
-        wk.at(tt, gb);
-        const TaskDev &t = wk.t;
-        if (!t.lab) continue;
-        const int lb = (int)(gb - t.block0);
-        const int y = (lb / t.nbx) * BH + r, x0 = (lb % t.nbx) * BW;
-        if (y >= t.h) continue;
-        if (wk.cur != acc_k) {
-            flush();
-            acc_k = wk.cur;
-        }
-        // a task already seen with two different nonzero values is grey: skip its rows
-        uint32_t seen_or = 0, seen_and = 0;
-        if (ln == 0) {
-            seen_or = __hip_atomic_load(a.route + 2 * wk.cur, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            seen_and = __hip_atomic_load(a.route + 2 * wk.cur + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        seen_or = uniform(seen_or);
-        seen_and = uniform(seen_and);
-        if (seen_or != 0u && seen_or != seen_and) continue;
-        const int x = x0 + 4 * ln;
-        const int valid = min(4, t.w - x);
-        const uint32_t m = valid > 0 ? mask4(t, y, x, valid) : 0u;
-        for (int j = 0; j < 4; ++j) {
-            const uint32_t b = byte_of(m, j);
-            if (b) {
-                acc_or |= b;
-                acc_and &= b;
-            }
-        }
-        // across the wave: lanes' partial values combined before any atomic
+        if (acc_k < 0) return;
         for (int d = 1; d < LANES; d <<= 1) {
             acc_or |= (uint32_t)__shfl_xor((int)acc_or, d);
             acc_and &= (uint32_t)__shfl_xor((int)acc_and, d);
         }
+        if (ln == 0) {
+            uint32_t *wo = a.route + ROUTE_WORDS * acc_k, *wa = wo + 1;
+            const uint32_t co = __hip_atomic_load(wo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if ((co | acc_or) != co) __hip_atomic_fetch_or(wo, acc_or, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t ca = __hip_atomic_load(wa, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if ((ca & acc_and) != ca) __hip_atomic_fetch_and(wa, acc_and, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t no = co | acc_or, na = ca & acc_and;
+            if (no != 0u && no != na) a.work->has_grey = 1u;   // this task is grey (any writer, same value)
+        }
+        acc_or = 0;
+        acc_and = 0xffu;
+    };
+    for (uint32_t gb = blockIdx.x; gb < n; gb += gridDim.x) {
+        wk.at(tt, gb);
+        const TaskDev &t = wk.t;
+        if (!t.lab) continue;
+        if (wk.cur != acc_k) {
+            flush();
+            acc_k = wk.cur;
+        }
+        const uint32_t seen_or = a.route[ROUTE_WORDS * wk.cur], seen_and = a.route[ROUTE_WORDS * wk.cur + 1];
+        if (uniform(seen_or != 0u && seen_or != seen_and ? 1 : 0)) continue;
+        const int lb = (int)(gb - t.block0);
+        const BlockGeom g = geom<BH>(t, lb / t.nbx, lb % t.nbx);
+        const int x = g.x0 + 4 * ln;
+        const int valid = min(4, g.bw - 4 * ln);
+        uint32_t m[BH];
+#pragma unroll
+        for (int r = 0; r < BH; ++r) m[r] = (r < g.bh && valid > 0) ? mask4(t, g.y0 + r, x, valid) : 0u;
+#pragma unroll
+        for (int r = 0; r < BH; ++r)
+            for (int j = 0; j < 4; ++j) {
+                const uint32_t b = byte_of(m[r], j);
+                if (b) {
+                    acc_or |= b;
+                    acc_and &= b;
+                }
+            }
     }
     flush();
 }
 
 template <int BH>
 __global__ __launch_bounds__(64) void comp_label_local(TaskTable tt, KArgs a) {
+    if (!a.work->route_any) return;   // no task of the launch takes the route
     RK_LDS uint32_t *par = (RK_LDS uint32_t *)dyn_lds();
     constexpr int PER = BH / LT_H;
     const uint64_t n = (uint64_t)total_blocks_of(tt) * PER;
@@ -158,6 +209,7 @@ __global__ __launch_bounds__(64) void comp_label_local(TaskTable tt, KArgs a) {
 
 template <int BH>
 __global__ __launch_bounds__(64) void comp_label_merge(TaskTable tt, KArgs a) {
+    if (!a.work->route_any) return;   // no task of the launch takes the route
     constexpr int PER = BH / LT_H;
     const uint64_t n = (uint64_t)total_blocks_of(tt) * PER;
     UnitWalk wk;
@@ -172,12 +224,14 @@ __global__ __launch_bounds__(64) void comp_label_merge(TaskTable tt, KArgs a) {
     }
 }
 
-// The root of node id a (every find ends at a root: an entry equal to its own
-// id, or an entry at or above COMP_ENC, which only a root's entry becomes).
-__device__ __forceinline__ int32_t comp_find(int32_t *lab, int32_t a) {
+// The root of node id a: every find ends at a root, an entry equal to its own
+// id or at or above COMP_ENC (which only a root's entry becomes).  Plain loads:
+// while this runs, entries only change to an ancestor (a pixel's own final
+// root) or, at roots, to COMP_ENC + offer, so a stale value still leads to the
+// root.  (No path compression here: a pixel's entry must end as its root.)
+__device__ __forceinline__ int32_t comp_find(const int32_t *lab, int32_t a) {
     while (true) {
-        const int32_t p = __hip_atomic_load((RK_GLOBAL int32_t *)(lab + (a - 1)), __ATOMIC_RELAXED,
-                                            __HIP_MEMORY_SCOPE_AGENT);
+        const int32_t p = ((const RK_GLOBAL int32_t *)lab)[a - 1];
         if (p == a || p >= COMP_ENC) return a;
         a = p;
     }
@@ -185,6 +239,7 @@ __device__ __forceinline__ int32_t comp_find(int32_t *lab, int32_t a) {
 
 template <int BH>
 __global__ __launch_bounds__(64) void comp_flatten_max(TaskTable tt, KArgs a) {
+    if (!a.work->route_any) return;   // no task of the launch takes the route
     const int ln = lane_id();
     const uint64_t n = (uint64_t)total_blocks_of(tt) * BH;
     UnitWalk wk;
@@ -200,17 +255,33 @@ __global__ __launch_bounds__(64) void comp_flatten_max(TaskTable tt, KArgs a) {
         const int valid = min(4, t.w - x);
         int32_t *row = t.lab + (int64_t)y * t.pitch_lab;
         int32_t v[4] = {0, 0, 0, 0};
-        for (int k = 0; k < 4 && k < valid; ++k)
-            v[k] = __hip_atomic_load((RK_GLOBAL int32_t *)(row + x + k), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        // the offers: min(J, I) of the foreground pixels (J clipped under its mask)
-        const uint32_t jm = valid > 0 ? marker4(t, y, x, valid) : 0u;
+        if (valid > 0) lab_load4(row, x, t.w, 1, v);   // label rows are 16-byte aligned (pitch a multiple of 4)
+        // the offers: min(J, I) of the foreground pixels, J the task's initial
+        // marker (the caller's for a dilation, else derived here: no marker
+        // plane is prepared for a task on this route)
+        uint32_t jm = 0;
+        if (valid > 0) {
+            const uint8_t *jrow = t.j + (int64_t)y * t.pitch_j;
+            const uint32_t j0 = t.op == OP_DILATE ? gload4(jrow, x, valid, t.aligned) : initial_marker4(t, jrow, y, x, valid);
+            jm = bmin4(j0, mask4(t, y, x, valid));
+        }
         int32_t root = 0;       // the lane's current root and the largest offer made to it
         uint32_t best = 0;
+        int32_t last_v = 0, last_r = 0;   // the lane's pixels mostly share one tile root: one find for them
         for (int k = 0; k < 4 && k < valid; ++k) {
             if (v[k] == 0) continue;   // mask 0
             const int32_t self = (int32_t)((int64_t)y * t.pitch_lab + x + k + 1);
             // v[k] at or above COMP_ENC: this pixel is a root that already has an offer
-            const int32_t r = v[k] >= COMP_ENC ? self : comp_find(t.lab, v[k]);
+            int32_t r;
+            if (v[k] >= COMP_ENC) {
+                r = self;
+            } else if (v[k] == last_v) {
+                r = last_r;
+            } else {
+                r = comp_find(t.lab, v[k]);
+                last_v = v[k];
+                last_r = r;
+            }
             if (r != v[k] && v[k] < COMP_ENC)   // a non-root points straight at its root
                 __hip_atomic_store((RK_GLOBAL int32_t *)(row + x + k), r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const uint32_t off = byte_of(jm, k);
@@ -237,6 +308,7 @@ __global__ __launch_bounds__(64) void comp_flatten_max(TaskTable tt, KArgs a) {
 
 template <int BH>
 __global__ __launch_bounds__(64) void comp_write(TaskTable tt, KArgs a) {
+    if (!a.work->route_any) return;   // no task of the launch takes the route
     const int ln = lane_id();
     const uint64_t n = (uint64_t)total_blocks_of(tt) * BH;
     UnitWalk wk;
@@ -254,14 +326,21 @@ __global__ __launch_bounds__(64) void comp_write(TaskTable tt, KArgs a) {
         const int valid = min(4, t.w - x);
         if (valid <= 0) continue;
         const int32_t *row = t.lab + (int64_t)y * t.pitch_lab;
+        int32_t ev[4];
+        lab_load4(row, x, t.w, 1, ev);
         uint32_t out = 0;
         for (int k = 0; k < 4 && k < valid; ++k) {
-            const int32_t e = row[x + k];
+            const int32_t e = ev[k];
             if (e == 0) continue;                   // mask 0
             const int32_t r = e >= COMP_ENC ? e : t.lab[e - 1];   // own entry (a root) or the root's
             if (r >= COMP_ENC) out |= (uint32_t)(r - COMP_ENC) << (8 * k);
         }
-        gstore4(t.j + (int64_t)y * t.pitch_j, x, valid, t.aligned, out);
+        // the result itself: the reconstruction into the caller's marker for a
+        // dilation, else mapped into the task's result plane
+        if (t.op == OP_DILATE)
+            gstore4(t.j + (int64_t)y * t.pitch_j, x, valid, t.aligned, out);
+        else
+            gstore4(t.img + (int64_t)y * t.pitch_img, x, valid, t.aligned, mapped_result4(t, out, y, x, valid));
     }
 }
 

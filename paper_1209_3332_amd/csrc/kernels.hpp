@@ -143,7 +143,9 @@ struct Work {
     unsigned long long stat_overflow;
     unsigned long long stat_request;
     unsigned long long stat_route;   // tasks reconstructed by the component route
-    unsigned long long pad4[10];
+    uint32_t route_any;              // some task of the launch takes the component route
+    uint32_t has_grey;               // some task of the launch keeps the block route whatever it looks like
+    unsigned long long pad4[9];
 };
 
 struct KArgs {
@@ -158,8 +160,15 @@ struct KArgs {
     int32_t drain_budget;        // queue rounds of a revisit before a sweep round takes over
     int32_t binary_drain_budget; // the same for blocks whose mask is binary (0 / 255)
     int32_t test_fault;          // test hook: 1 = every claim's compare-and-swap is made to fail
-    uint32_t *route;             // per task: OR and AND of its nonzero mask values (component route)
+    uint32_t *route;             // ROUTE_WORDS per task (below)
+    int32_t route_policy;        // 0: the component route where it pays (auto); 1: for every two-valued mask
 };
+
+// Route words of a task: [0] OR and [1] AND of its nonzero mask values (the
+// component route's classification), [2] the ring position of its first block,
+// [3] 1 if the task takes the component route (decided by queue_tasks),
+// [4] 1 if its sampled foreground is thin (runs of at most ~32 pixels on average).
+constexpr int ROUTE_WORDS = 8;
 
 // ---------------------------------------------------------------------------
 // task table access (all indices wave-uniform)
@@ -194,14 +203,19 @@ __device__ __forceinline__ uint32_t uniform(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
 }
 
-// Whether task k takes the component route (component.hpp): its mask holds at
-// most one nonzero value, by the OR and AND of its nonzero mask values that
-// comp_classify left in the task's two route words.  Read only by kernels
-// launched after the classification.
-__device__ __forceinline__ bool on_component_route(const KArgs &a, const TaskDev &t, int k) {
-    if (!t.lab) return false;
-    const uint32_t o = a.route[2 * k], n = a.route[2 * k + 1];
+// Whether task k takes the component route (component.hpp), as queue_tasks
+// decided: its mask holds at most one nonzero value (two_valued: by the OR and
+// AND of its nonzero mask values that comp_classify left in its route words),
+// and the route pays.  Read only by kernels launched after queue_tasks.
+__device__ __forceinline__ bool two_valued(const uint32_t *route, int k) {
+    const uint32_t o = route[ROUTE_WORDS * k], n = route[ROUTE_WORDS * k + 1];
     return o == 0u || o == n;
+}
+__device__ __forceinline__ bool on_component_route(const uint32_t *route, const TaskDev &t, int k) {
+    return t.lab && route && route[ROUTE_WORDS * k + 3] == 1u;
+}
+__device__ __forceinline__ bool on_component_route(const KArgs &a, const TaskDev &t, int k) {
+    return on_component_route(a.route, t, k);
 }
 
 // ---------------------------------------------------------------------------
@@ -1459,22 +1473,6 @@ __global__ __launch_bounds__(64) void revisit_drain(TaskTable tt, KArgs a) {
         const int lb = (int)(gb - t.block0);
         const int by = lb / t.nbx, bx = lb % t.nbx;
         const BlockGeom g = geom<BH>(t, by, bx);
-        if (on_component_route(a, t, ti)) {
-            // the task was reconstructed by the component route: the block's
-            // visit is complete without any work (no wave ever requests it)
-            int last = 0;
-            if (ln == 0) {
-                const uint32_t left = __hip_atomic_fetch_sub(a.tile_pending + ti, 1u, __ATOMIC_RELAXED,
-                                                             __HIP_MEMORY_SCOPE_AGENT);
-                const uint32_t all = __hip_atomic_fetch_sub(&w->pending, 1u, __ATOMIC_RELAXED,
-                                                            __HIP_MEMORY_SCOPE_AGENT);
-                if (left == 1u)
-                    __hip_atomic_store(a.tile_done + ti, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                last = all == 1u;
-            }
-            if (uniform(last)) release_waiters(a, ring_cap);
-            continue;
-        }
 
         // ---- claim: clear D, set R (a kept block is owned already).  The previous owner and every requester
         // completed their (coherent) stores before updating the state word, so
@@ -1593,14 +1591,22 @@ __global__ void copy_table(const uint8_t *src, uint8_t *dst, uint32_t bytes) {
 }
 
 // Reset the scheduling state of the batch.
-// queue_all: every block starts requested and in the ring (in block order), so
-// that the persistent revisit kernel makes each block's first visit itself;
-// otherwise the scheduler starts empty (the dense and border kernels run first).
+//   RESET_STAGED     the scheduler starts empty (the dense and border kernels
+//                    of the staged pipeline run first);
+//   RESET_QUEUE_ALL  every block starts requested and in the ring (in block
+//                    order), so that the persistent revisit kernel makes each
+//                    block's first visit itself;
+//   RESET_ROUTE      counters and route words only: queue_tasks and
+//                    queue_blocks fill the ring after the classification, with
+//                    the blocks of the tasks that do not take the component route.
+enum { RESET_STAGED = 0, RESET_QUEUE_ALL = 1, RESET_ROUTE = 2 };
+
 __global__ void reset_work(TaskTable tt, Work *w, uint32_t *state, uint32_t *ring,
-                           uint32_t *tile_pending, uint32_t *tile_done, uint32_t *route, int queue_all) {
+                           uint32_t *tile_pending, uint32_t *tile_done, uint32_t *route, int mode) {
     const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t nth = gridDim.x * blockDim.x;
     const uint32_t n_tasks = n_tasks_of(tt), total = total_blocks_of(tt), ring_cap = ring_cap_of(tt);
+    const bool queue_all = mode == RESET_QUEUE_ALL;
     if (tid == 0) {
         w->pending = queue_all ? total : 0u;
         w->done = 0;
@@ -1610,81 +1616,139 @@ __global__ void reset_work(TaskTable tt, Work *w, uint32_t *state, uint32_t *rin
         w->progress = 0;
         w->stat_dense = w->stat_revisit = w->stat_rerun = w->stat_overflow = w->stat_request = 0;
         w->stat_route = 0;
+        w->route_any = 0;
+        w->has_grey = 0;
     }
-    // (without queue_all the dense pass visits every block first)
-    for (uint32_t i = tid; i < total; i += nth) state[(size_t)i * STATE_STRIDE] = queue_all ? ST_D : ST_V;
-    for (uint32_t i = tid; i < ring_cap; i += nth) ring[(size_t)i * RING_STRIDE] = queue_all && i < total ? i + 1u : 0u;
+    if (mode != RESET_ROUTE) {
+        // (without queue_all the dense pass visits every block first)
+        for (uint32_t i = tid; i < total; i += nth) state[(size_t)i * STATE_STRIDE] = queue_all ? ST_D : ST_V;
+        for (uint32_t i = tid; i < ring_cap; i += nth)
+            ring[(size_t)i * RING_STRIDE] = queue_all && i < total ? i + 1u : 0u;
+    }
     for (uint32_t i = tid; i < n_tasks; i += nth) {
         const TaskDev t = task_of(tt, (int)i);
         tile_pending[i] = queue_all ? (uint32_t)(t.nby * t.nbx) : 0u;
         tile_done[i] = 0;
         if (route) {   // the OR and AND identities of the mask classification
-            route[2 * i] = 0u;
-            route[2 * i + 1] = 0xffu;
+            route[ROUTE_WORDS * i] = 0u;
+            route[ROUTE_WORDS * i + 1] = 0xffu;
+            for (int q = 2; q < ROUTE_WORDS; ++q) route[ROUTE_WORDS * i + q] = 0u;
         }
     }
+}
+
+// After the classification (RESET_ROUTE), the route of every task.  A
+// two-valued mask takes the component route when its foreground is thin (there
+// block visits would chain along corridors), when the launch has no task that
+// keeps the block route anyway (nothing for its visits to overlap with), or
+// when the policy asks for it for every two-valued mask; a thick two-valued
+// mask in a launch with grey tasks stays on the block route, whose visits then
+// fill the compute units the grey tasks' dependency chains leave idle.
+// Each task that keeps the block route reserves a range of ring positions for
+// its blocks and counts them as outstanding; a task on the component route is
+// complete as far as the block scheduler is concerned, and marks the launch as
+// having one (route_any, so that the route's kernels return at once when no
+// task takes it).
+__global__ void queue_tasks(TaskTable tt, KArgs a) {
+    const uint32_t n_tasks = n_tasks_of(tt);
+    const bool grey_work = a.work->has_grey != 0u;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_tasks; i += gridDim.x * blockDim.x) {
+        const TaskDev t = task_of(tt, (int)i);
+        const bool take = t.lab && two_valued(a.route, (int)i) &&
+                          (a.route_policy == 1 || !grey_work || a.route[ROUTE_WORDS * i + 4] != 0u);
+        a.route[ROUTE_WORDS * i + 3] = take ? 1u : 0u;
+        if (take) {
+            a.tile_done[i] = 1u;
+            a.work->route_any = 1u;   // (any writer, same value)
+            continue;
+        }
+        const uint32_t nb = (uint32_t)(t.nby * t.nbx);
+        a.route[ROUTE_WORDS * i + 2] =
+            __hip_atomic_fetch_add(&a.work->ring_tail, nb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        a.tile_pending[i] = nb;
+        __hip_atomic_fetch_add(&a.work->pending, nb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// Then every block: requested and in its task's ring range, or idle (a task
+// on the component route, whose blocks nobody ever requests); ring positions
+// past the queued blocks are cleared.
+__global__ void queue_blocks(TaskTable tt, KArgs a) {
+    const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t nth = gridDim.x * blockDim.x;
+    const uint32_t total = total_blocks_of(tt), ring_cap = ring_cap_of(tt);
+    const uint32_t queued = a.work->ring_tail;
+    for (uint32_t gb = tid; gb < total; gb += nth) {
+        const int k = find_task(tt, gb);
+        const TaskDev t = task_of(tt, k);
+        if (on_component_route(a, t, k)) {
+            a.state[(size_t)gb * STATE_STRIDE] = ST_V;
+        } else {
+            a.state[(size_t)gb * STATE_STRIDE] = ST_D;
+            a.ring[(size_t)(a.route[ROUTE_WORDS * k + 2] + (gb - t.block0)) * RING_STRIDE] = gb + 1u;
+        }
+    }
+    for (uint32_t i = queued + tid; i < ring_cap; i += nth) a.ring[(size_t)i * RING_STRIDE] = 0u;
+}
+
+// The initial marker of 4 pixels of a task that is not a plain dilation:
+// fill-holes 255 - X on the image frame and 0 inside; erosion 255 - J (the
+// caller's marker); h-dome and regional maxima max(I - h, 0) bytewise (I -
+// min(I, h) never borrows across bytes).  `jrow` is the marker row.
+__device__ __forceinline__ uint32_t initial_marker4(const TaskDev &t, const uint8_t *jrow, int y, int x, int valid) {
+    if (t.op == OP_FILL) return fill_init4(t, y, x, valid, mask4(t, y, x, valid));
+    if (t.op == OP_ERODE) return ~gload4(jrow, x, valid, t.aligned);
+    const uint32_t iv = gload4(t.i + (int64_t)y * t.pitch_i, x, valid, t.aligned);
+    return iv - bmin4(iv, (uint32_t)t.hval * 0x01010101u);
+}
+
+// The result of 4 pixels from the fixed point jv: fill-holes and erosion
+// 255 - J; h-dome I - J (J <= I bytewise, so the dword difference never
+// borrows across bytes); regional maxima 255 where I - J > 0, else 0.
+__device__ __forceinline__ uint32_t mapped_result4(const TaskDev &t, uint32_t jv, int y, int x, int valid) {
+    if (t.op == OP_FILL || t.op == OP_ERODE) return ~jv;
+    const uint32_t d = gload4(t.i + (int64_t)y * t.pitch_i, x, valid, t.aligned) - jv;
+    if (t.op == OP_HDOME) return d;
+    // 0x80 in every byte of d that is nonzero, then 0x01 -> 0xff
+    const uint32_t nz = (d | ((d & 0x7f7f7f7fu) + 0x7f7f7f7fu)) & 0x80808080u;
+    return (nz >> 7) * 0xffu;
 }
 
 // Initial marker plane of every task that is not a plain dilation, written
 // before any block is visited (so that any block can read any other's marker
-// before that block's first visit): fill-holes 255 - X on the image frame and
-// 0 inside; erosion 255 - J over the caller's marker; h-dome and regional
-// maxima max(I - h, 0).  Grid-stride over dwords of each task in turn.
-__global__ void init_marker(TaskTable tt) {
+// before that block's first visit).  Tasks on the component route are
+// skipped (their kernels derive the marker themselves; `route` null: no
+// task takes it).  Grid-stride over dwords of each task in turn.
+__global__ void init_marker(TaskTable tt, const uint32_t *route) {
     const uint32_t n = n_tasks_of(tt);
     for (uint32_t k = 0; k < n; ++k) {
         const TaskDev t = task_of(tt, (int)k);
-        if (t.op == OP_DILATE) continue;
+        if (t.op == OP_DILATE || on_component_route(route, t, (int)k)) continue;
         const uint32_t dw = (uint32_t)(t.w + 3) / 4u;
         const uint64_t total = (uint64_t)t.h * dw;
-        const uint32_t hh = (uint32_t)t.hval * 0x01010101u;
         for (uint64_t i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (uint64_t)gridDim.x * blockDim.x) {
             const int y = (int)(i / dw), x = (int)(i % dw) * 4;
             const int valid = min(4, t.w - x);
             uint8_t *jrow = t.j + (int64_t)y * t.pitch_j;
-            uint32_t v;
-            if (t.op == OP_FILL) {
-                v = fill_init4(t, y, x, valid, mask4(t, y, x, valid));
-            } else if (t.op == OP_ERODE) {
-                v = ~gload4(jrow, x, valid, t.aligned);
-            } else {
-                // max(I - h, 0) bytewise: I - min(I, h) never borrows across bytes
-                const uint32_t iv = gload4(t.i + (int64_t)y * t.pitch_i, x, valid, t.aligned);
-                v = iv - bmin4(iv, hh);
-            }
-            gstore4(jrow, x, valid, t.aligned, v);
+            gstore4(jrow, x, valid, t.aligned, initial_marker4(t, jrow, y, x, valid));
         }
     }
 }
 
-// Map the fixed point J back to each task's result: fill-holes and erosion
-// 255 - J; h-dome I - J (J <= I bytewise, so the dword difference never
-// borrows across bytes); regional maxima 255 where I - J > 0, else 0.
-__global__ void finish_result(TaskTable tt) {
+// Map the fixed point J back to each task's result (mapped_result4), except
+// for tasks on the component route, whose kernels write their result.
+__global__ void finish_result(TaskTable tt, const uint32_t *route) {
     const uint32_t n = n_tasks_of(tt);
     for (uint32_t k = 0; k < n; ++k) {
         const TaskDev t = task_of(tt, (int)k);
-        if (t.op == OP_DILATE) continue;
+        if (t.op == OP_DILATE || on_component_route(route, t, (int)k)) continue;
         const uint32_t dw = (uint32_t)(t.w + 3) / 4u;
         const uint64_t total = (uint64_t)t.h * dw;
         for (uint64_t i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (uint64_t)gridDim.x * blockDim.x) {
             const int y = (int)(i / dw), x = (int)(i % dw) * 4;
             const int valid = min(4, t.w - x);
             const uint32_t jv = gload4(t.j + (int64_t)y * t.pitch_j, x, valid, t.aligned);
-            uint32_t v;
-            if (t.op == OP_FILL || t.op == OP_ERODE) {
-                v = ~jv;
-            } else {
-                const uint32_t d = gload4(t.i + (int64_t)y * t.pitch_i, x, valid, t.aligned) - jv;
-                if (t.op == OP_HDOME) {
-                    v = d;
-                } else {
-                    // 0x80 in every byte of d that is nonzero, then 0x01 -> 0xff
-                    const uint32_t nz = (d | ((d & 0x7f7f7f7fu) + 0x7f7f7f7fu)) & 0x80808080u;
-                    v = (nz >> 7) * 0xffu;
-                }
-            }
-            gstore4(t.img + (int64_t)y * t.pitch_img, x, valid, t.aligned, v);
+            gstore4(t.img + (int64_t)y * t.pitch_img, x, valid, t.aligned, mapped_result4(t, jv, y, x, valid));
         }
     }
 }

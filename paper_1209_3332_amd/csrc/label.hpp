@@ -116,12 +116,22 @@ __device__ __forceinline__ void lds_union(RK_LDS uint32_t *par, uint32_t a, uint
 
 // ---- global union-find on the label plane (node ids: pitched index + 1)
 
+// Find with path halving: every other node on the path is pointed at its
+// grandparent (an atomic minimum: a parent always has the smaller id, so the
+// entry only moves up its own tree, whatever other waves write meanwhile).
+// Without it, a component spanning many tiles (a background, a corridor)
+// builds chains as long as the tiles it crosses, each step a round trip to
+// the device-coherent level.
 __device__ __forceinline__ int32_t g_find(int32_t *lab, int32_t a) {
     while (true) {
         const int32_t p = __hip_atomic_load((RK_GLOBAL int32_t *)(lab + (a - 1)), __ATOMIC_RELAXED,
                                             __HIP_MEMORY_SCOPE_AGENT);
         if (p == a) return a;
-        a = p;
+        const int32_t gp = __hip_atomic_load((RK_GLOBAL int32_t *)(lab + (p - 1)), __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+        if (gp == p) return p;
+        __hip_atomic_fetch_min((RK_GLOBAL int32_t *)(lab + (a - 1)), gp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        a = gp;
     }
 }
 
@@ -298,36 +308,61 @@ __global__ __launch_bounds__(64) void label_local(LabelArgs a) {
 // column meets the column to the left; with 8-connectivity the diagonal
 // neighbours too.  Every pair of adjacent pixels in different tiles is met at
 // least once.
+// Unions across the tile's top row and left column, issued once per pair of
+// touching runs (the rule label_tile uses inside a tile): along the top row,
+// pixel x of the tile's row (c) and the row above (a); a pixel whose left
+// neighbour c[x-1] is foreground joins a[x-1] and a[x] through it, and a[x+1]
+// through a[x] when that is foreground; so with 8-connectivity c[x] links
+// a[x-1] (or else a[x]) only if it starts a run, and a[x+1] only if a[x] is
+// background; with 4-connectivity a[x] only if c[x-1] and a[x-1] are not both
+// foreground.  The left column is the same along the rows (a: column x0 - 1).
+// A skip relies on c[x-1] joined to c[x] and a[x-1] to a[x], so it is taken
+// only where c[x-1] lies inside this tile (label_tile joined the run); the
+// first pixel of the row (or column) always links explicitly.  Then every
+// implied link rests on links inside one tile, and a pair of diagonal or
+// cross-corner neighbours in other tiles is always linked explicitly.  A
+// component spanning many tiles (a background) costs a few unions per tile
+// instead of one per border pixel.
 __device__ void merge_tile(const LabelArgs &a, int y0, int x0) {
     const int ln = lane_id();
-    const int d = a.conn == 8 ? 1 : 0;
-    {
-        const int th = min(LT_H, a.h - y0), tw = min(LT_W, a.w - x0);
-        if (y0 > 0) {
-            for (int k = 0; k < 4; ++k) {
-                const int x = x0 + 4 * ln + k;
-                if (x >= x0 + tw) continue;
-                const int32_t self = a.lab[(int64_t)y0 * a.pitch_lab + x];
-                if (self == 0) continue;
-                for (int dx = -d; dx <= d; ++dx) {
-                    const int xx = x + dx;
-                    if (xx < 0 || xx >= a.w) continue;
-                    const int32_t other = a.lab[(int64_t)(y0 - 1) * a.pitch_lab + xx];
-                    if (other != 0) g_union(a.lab, self, other);
+    const int th = min(LT_H, a.h - y0), tw = min(LT_W, a.w - x0);
+    auto fg = [&](int y, int x) -> bool {
+        return y >= 0 && y < a.h && x >= 0 && x < a.w && a.lab[(int64_t)y * a.pitch_lab + x] != 0;
+    };
+    auto node = [&](int y, int x) -> int32_t { return a.lab[(int64_t)y * a.pitch_lab + x]; };
+    if (y0 > 0) {
+        for (int k = 0; k < 4; ++k) {
+            const int x = x0 + 4 * ln + k;
+            if (x >= x0 + tw || !fg(y0, x)) continue;
+            const bool in = x - 1 >= x0;   // c[x-1] inside this tile
+            const bool cl = in && fg(y0, x - 1), al = fg(y0 - 1, x - 1), au = fg(y0 - 1, x), ar = fg(y0 - 1, x + 1);
+            const int32_t self = node(y0, x);
+            if (a.conn == 8) {
+                if (!cl) {
+                    if (al) g_union(a.lab, self, node(y0 - 1, x - 1));
+                    else if (au) g_union(a.lab, self, node(y0 - 1, x));
                 }
+                if (!au && ar) g_union(a.lab, self, node(y0 - 1, x + 1));
+            } else if (au && (!cl || !(in && al))) {
+                g_union(a.lab, self, node(y0 - 1, x));
             }
         }
-        if (x0 > 0) {
-            for (int r = ln; r < th; r += LANES) {
-                const int y = y0 + r;
-                const int32_t self = a.lab[(int64_t)y * a.pitch_lab + x0];
-                if (self == 0) continue;
-                for (int dy = -d; dy <= d; ++dy) {
-                    const int yy = y + dy;
-                    if (yy < 0 || yy >= a.h) continue;
-                    const int32_t other = a.lab[(int64_t)yy * a.pitch_lab + x0 - 1];
-                    if (other != 0) g_union(a.lab, self, other);
+    }
+    if (x0 > 0) {
+        for (int r = ln; r < th; r += LANES) {
+            const int y = y0 + r;
+            if (!fg(y, x0)) continue;
+            const bool in = r >= 1;   // the pixel above inside this tile
+            const bool cl = in && fg(y - 1, x0), al = fg(y - 1, x0 - 1), au = fg(y, x0 - 1), ar = fg(y + 1, x0 - 1);
+            const int32_t self = node(y, x0);
+            if (a.conn == 8) {
+                if (!cl) {
+                    if (al) g_union(a.lab, self, node(y - 1, x0 - 1));
+                    else if (au) g_union(a.lab, self, node(y, x0 - 1));
                 }
+                if (!au && ar) g_union(a.lab, self, node(y + 1, x0 - 1));
+            } else if (au && (!cl || !(in && al))) {
+                g_union(a.lab, self, node(y, x0 - 1));
             }
         }
     }

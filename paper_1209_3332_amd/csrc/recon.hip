@@ -146,6 +146,7 @@ struct recon_ctx {
     // [5] opens the launch, [0]..[4] close its steps, [6] closes the component route (after [0])
     hipEvent_t tev[kTimingRing][7] = {};
     bool tev_graph[kTimingRing] = {};   // that launch replayed a graph (only its total is marked)
+    bool tev_route[kTimingRing] = {};   // that launch ran the component route (on the second stream)
     uint64_t launches = 0;              // launch sequences enqueued so far
     bool have_last = false;
     rk::Work *last_work = nullptr;      // the counters of the last launch (context or fixed workspace)
@@ -154,6 +155,10 @@ struct recon_ctx {
     int resident[kVariants] = {0, 0, 0};
     // captured batch graphs per variant
     hipStream_t cap_stream = nullptr;
+    // the component route's labelling kernels run on a second stream beside
+    // the revisit kernel (fork and join events, also inside captured graphs)
+    hipStream_t aux_stream = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     hipGraphExec_t graph[kVariants] = {nullptr, nullptr, nullptr};
     size_t graph_cap_blocks[kVariants] = {0, 0, 0};
     size_t graph_cap_tasks[kVariants] = {0, 0, 0};
@@ -230,7 +235,7 @@ int ensure_capacity(recon_ctx *c, size_t n_tasks, size_t n_blocks, size_t area_b
         hipMalloc(&c->d_ring, ring_slots(nb) * rk::RING_STRIDE * sizeof(uint32_t)) != hipSuccess ||
         hipMalloc(&c->d_tile_pending, nt * sizeof(uint32_t)) != hipSuccess ||
         hipMalloc(&c->d_tile_done, nt * sizeof(uint32_t)) != hipSuccess ||
-        hipMalloc(&c->d_route, 2 * nt * sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc(&c->d_route, rk::ROUTE_WORDS * nt * sizeof(uint32_t)) != hipSuccess ||
         (ns > 0 && hipMalloc(&c->d_scratch, ns) != hipSuccess)) {
         free_workspace(c);
         return fail(RECON_ENOMEM, "workspace allocation (%zu tasks, %zu blocks, %zu scratch bytes) failed",
@@ -377,7 +382,12 @@ Workspace ctx_workspace(const recon_ctx *c) {
 
 // Enqueue the kernels of one launch sequence on `s`.
 int enqueue_kernels(recon_ctx *c, const Workspace &ws, int v, const rk::TaskTable &tt, uint32_t total_blocks,
-                    bool any_mapped, bool route, bool dynamic_sizes, hipStream_t s) {
+                    uint32_t n_tasks_host, bool any_mapped, bool route, bool dynamic_sizes, hipStream_t s) {
+    if (route && !c->aux_stream) {
+        HIP_TRY(hipStreamCreateWithFlags(&c->aux_stream, hipStreamNonBlocking));
+        HIP_TRY(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+        HIP_TRY(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+    }
     rk::KArgs ka;
     ka.work = ws.work;
     ka.state = ws.state;
@@ -391,6 +401,7 @@ int enqueue_kernels(recon_ctx *c, const Workspace &ws, int v, const rk::TaskTabl
     ka.binary_drain_budget = c->cfg.binary_drain_budget;
     ka.test_fault = c->cfg.test_fault;
     ka.route = route ? ws.route : nullptr;
+    ka.route_policy = c->cfg.component_route == 1 ? 1 : 0;
     const size_t lds = lds_for(v, c->cfg.queue_capacity);
     const int resident = resident_wgs(c, v);
     // K1/K2 are grid-stride: with sizes known only on the device (captured
@@ -408,18 +419,19 @@ int enqueue_kernels(recon_ctx *c, const Workspace &ws, int v, const rk::TaskTabl
     // revisits as separate kernels), stopped after that stage (test hooks)
     const bool merged = stop == 0;
     hipEvent_t *tev = c->tev[c->launches % kTimingRing];
+    c->tev_route[c->launches % kTimingRing] = route;
     if (timing) HIP_TRY(hipEventRecord(tev[5], s));
+    const int reset_mode = !merged ? rk::RESET_STAGED : (route ? rk::RESET_ROUTE : rk::RESET_QUEUE_ALL);
     hipLaunchKernelGGL(rk::reset_work, dim3(64), dim3(256), 0, s, tt, ws.work, ws.state, ws.ring,
-                       ws.tile_pending, ws.tile_done, ka.route, merged ? 1 : 0);
-    if (any_mapped) hipLaunchKernelGGL(rk::init_marker, dim3(1024), dim3(256), 0, s, tt);
-
+                       ws.tile_pending, ws.tile_done, ka.route, reset_mode);
     if (timing) HIP_TRY(hipEventRecord(tev[0], s));
     if (route) {
         // the component route: classify every task's mask, then label and
         // reconstruct the two-valued ones (the others' waves exit at once)
         const int bh = kBlockRows[v];
-        const int g_rows = (int)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)nblk * bh, 16384));
-        const int g_tiles = (int)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)nblk * (bh / rk::LT_H), 16384));
+        const int g_rows = (int)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)nblk * bh, 4096));
+        const int g_tiles = (int)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)nblk * (bh / rk::LT_H), 4096));
+        const uint32_t ntask = dynamic_sizes ? (uint32_t)c->cap_tasks : n_tasks_host;
         const size_t lds_lab = (size_t)rk::LT_H * rk::LT_W * sizeof(uint32_t);
 #define RK_COMP(K, GRID, LDS)                                                                     \
     switch (v) {                                                                                  \
@@ -427,14 +439,38 @@ int enqueue_kernels(recon_ctx *c, const Workspace &ws, int v, const rk::TaskTabl
         case 1: hipLaunchKernelGGL(rk::K<32>, dim3(GRID), dim3(64), LDS, s, tt, ka); break;      \
         default: hipLaunchKernelGGL(rk::K<64>, dim3(GRID), dim3(64), LDS, s, tt, ka); break;     \
     }
-        RK_COMP(comp_classify, g_rows, 0);
-        RK_COMP(comp_label_local, g_tiles, lds_lab);
-        RK_COMP(comp_label_merge, g_tiles, 0);
-        RK_COMP(comp_flatten_max, g_rows, 0);
-        RK_COMP(comp_write, g_rows, 0);
-#undef RK_COMP
+        hipLaunchKernelGGL(rk::comp_sample, dim3(std::max<uint32_t>(1u, std::min<uint32_t>(ntask, 4096u))), dim3(64), 0,
+                           s, tt, ka);
+        RK_COMP(comp_classify, (int)std::max<uint32_t>(1u, std::min<uint32_t>(nblk, 1024u)), 0);
+        // the ring of the tasks that keep the block route, and route_any
+        hipLaunchKernelGGL(rk::queue_tasks, dim3(std::max<uint32_t>(1u, (ntask + 255) / 256)), dim3(256), 0, s, tt, ka);
+        // marker planes of the tasks that keep the block route, and the ring
+        if (any_mapped) hipLaunchKernelGGL(rk::init_marker, dim3(1024), dim3(256), 0, s, tt, ka.route);
+        hipLaunchKernelGGL(rk::queue_blocks, dim3(256), dim3(256), 0, s, tt, ka);
+        // labelling and maxima of the route's tasks on the second stream, while
+        // the revisit kernel works on the others (it leaves most compute units
+        // idle on a latency-bound tile; these kernels use little or no LDS)
+        HIP_TRY(hipEventRecord(c->ev_fork, s));
+        HIP_TRY(hipStreamWaitEvent(c->aux_stream, c->ev_fork, 0));
+        const hipStream_t s2 = c->aux_stream;
+#define RK_COMP2(K, GRID, LDS)                                                                    \
+    switch (v) {                                                                                  \
+        case 0: hipLaunchKernelGGL(rk::K<16>, dim3(GRID), dim3(64), LDS, s2, tt, ka); break;     \
+        case 1: hipLaunchKernelGGL(rk::K<32>, dim3(GRID), dim3(64), LDS, s2, tt, ka); break;     \
+        default: hipLaunchKernelGGL(rk::K<64>, dim3(GRID), dim3(64), LDS, s2, tt, ka); break;    \
     }
-    if (timing) HIP_TRY(hipEventRecord(tev[6], s));
+        RK_COMP2(comp_label_local, g_tiles, lds_lab);
+        RK_COMP2(comp_label_merge, g_tiles, 0);
+        RK_COMP2(comp_flatten_max, g_rows, 0);
+        RK_COMP2(comp_write, g_rows, 0);
+#undef RK_COMP2
+#undef RK_COMP
+        if (timing) HIP_TRY(hipEventRecord(tev[6], s2));
+        HIP_TRY(hipEventRecord(c->ev_join, s2));
+    } else if (any_mapped) {
+        hipLaunchKernelGGL(rk::init_marker, dim3(1024), dim3(256), 0, s, tt, ka.route);
+    }
+    if (timing && !route) HIP_TRY(hipEventRecord(tev[6], s));
 #define RK_LAUNCH(K, GRID)                                                                        \
     switch (v) {                                                                                  \
         case 0: hipLaunchKernelGGL(rk::K<16>, dim3(GRID), dim3(64), lds, s, tt, ka); break;      \
@@ -448,7 +484,8 @@ int enqueue_kernels(recon_ctx *c, const Workspace &ws, int v, const rk::TaskTabl
     if (merged || stop >= 3) RK_LAUNCH(revisit_drain, grid3);
     if (timing) HIP_TRY(hipEventRecord(tev[3], s));
 #undef RK_LAUNCH
-    if (any_mapped) hipLaunchKernelGGL(rk::finish_result, dim3(1024), dim3(256), 0, s, tt);
+    if (route) HIP_TRY(hipStreamWaitEvent(s, c->ev_join, 0));   // join the route's stream
+    if (any_mapped) hipLaunchKernelGGL(rk::finish_result, dim3(1024), dim3(256), 0, s, tt, ka.route);
     if (timing) HIP_TRY(hipEventRecord(tev[4], s));
     HIP_TRY(hipGetLastError());
     return RECON_OK;
@@ -518,7 +555,8 @@ int run_tasks(recon_ctx *c, const recon_task *tasks, int n, hipStream_t stream, 
             const uint32_t max_bytes = (uint32_t)(sizeof(BatchHdr) + c->cap_tasks * sizeof(rk::TaskDev));
             hipLaunchKernelGGL(rk::copy_table, dim3(16), dim3(256), 0, c->cap_stream, c->h_table, c->d_table,
                                max_bytes);
-            rc = enqueue_kernels(c, ctx_workspace(c), v, tt, total_blocks, true, with_route, true, c->cap_stream);
+            rc = enqueue_kernels(c, ctx_workspace(c), v, tt, total_blocks, (uint32_t)n, true, with_route, true,
+                                 c->cap_stream);
             hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
             if (rc) return rc;
             if (e != hipSuccess) return fail(RECON_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
@@ -540,7 +578,8 @@ int run_tasks(recon_ctx *c, const recon_task *tasks, int n, hipStream_t stream, 
                                table_bytes);
             HIP_TRY(hipEventRecord(c->table_used, stream));
         }
-        rc = enqueue_kernels(c, ctx_workspace(c), v, tt, total_blocks, any_mapped, with_route, false, stream);
+        rc = enqueue_kernels(c, ctx_workspace(c), v, tt, total_blocks, (uint32_t)n, any_mapped, with_route, false,
+                             stream);
         if (rc) return rc;
     }
     HIP_TRY(hipEventRecord(c->last_done, stream));
@@ -819,8 +858,8 @@ int recon_create(recon_ctx **out, int device, const recon_config *cfg) {
     if (c.wg_per_cu < 0) return fail(RECON_EINVAL, "wg_per_cu must be >= 0");
     if (c.stop_after_stage < 0 || c.stop_after_stage > 3) return fail(RECON_EINVAL, "stop_after_stage must be 0..3");
     if (c.test_fault < 0 || c.test_fault > 1) return fail(RECON_EINVAL, "test_fault must be 0 or 1");
-    if (c.component_route < -1 || c.component_route > 0)
-        return fail(RECON_EINVAL, "component_route must be 0 (on) or -1 (off)");
+    if (c.component_route < -1 || c.component_route > 1)
+        return fail(RECON_EINVAL, "component_route must be 0 (where it pays), 1 (every two-valued mask) or -1 (off)");
     if (c.serve_mem_cap < 0 || c.serve_slots < 0) return fail(RECON_EINVAL, "serving limits must be >= 0");
     if (c.serve_mem_cap == 0) c.serve_mem_cap = (int64_t)64 << 30;
     if (c.serve_slots == 0) c.serve_slots = 256;
@@ -871,6 +910,9 @@ int recon_destroy(recon_ctx *ctx) {
         for (auto &ev : set)
             if (ev) (void)hipEventDestroy(ev);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    if (ctx->aux_stream) (void)hipStreamDestroy(ctx->aux_stream);
+    if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
+    if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
     delete ctx;
     return RECON_OK;
 }
@@ -933,7 +975,7 @@ int recon_dilate_noalloc(recon_ctx *ctx, recon_image *marker, const recon_image 
     tt.ring_cap_inline = (uint32_t)ring_slots(total_blocks);
     tt.inl[0] = table[0];
     const hipStream_t s = (hipStream_t)stream;
-    rc = enqueue_kernels(ctx, ws, variant_of(bh), tt, total_blocks, false, false, false, s);
+    rc = enqueue_kernels(ctx, ws, variant_of(bh), tt, total_blocks, 1u, false, false, false, s);
     if (rc) return rc;
     HIP_TRY(hipEventRecord(ctx->last_done, s));
     ctx->have_last = true;
@@ -1246,7 +1288,10 @@ static void launch_times(recon_ctx *ctx, int back, float t[5]) {
     t[0] = t[1] = t[2] = t[3] = t[4] = -1.f;
     float ms = 0.f;
     if (!ctx->tev_graph[i]) {
-        if (hipEventElapsedTime(&ms, tev[6], tev[1]) == hipSuccess) t[0] = ms;
+        // (with the route the persistent pipeline runs: no dense pass; tev[6]
+        // then closes the route's kernels on the second stream)
+        if (ctx->tev_route[i]) t[0] = 0.f;
+        else if (hipEventElapsedTime(&ms, tev[6], tev[1]) == hipSuccess) t[0] = ms;
         if (hipEventElapsedTime(&ms, tev[1], tev[2]) == hipSuccess) t[1] = ms;
         if (hipEventElapsedTime(&ms, tev[2], tev[3]) == hipSuccess) t[2] = ms;
         if (hipEventElapsedTime(&ms, tev[0], tev[6]) == hipSuccess) t[4] = ms;

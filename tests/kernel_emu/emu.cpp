@@ -384,7 +384,9 @@ int emu_run(const EmuTask *tasks, int n, int bh, int qcap, int scan_rounds, int 
     std::vector<uint8_t *> jplanes(n), iplanes(n, nullptr), scratch(n, nullptr);
     // the component route (KEMU_COMPONENT=1): an exact-size int32 label plane per task
     const char *ce = std::getenv("KEMU_COMPONENT");
-    const bool component = ce && std::atoi(ce) == 1 && stop_after == 0;
+    // 1: every two-valued mask takes the route; 2: where it pays (the library's default)
+    const int component_mode = ce ? std::atoi(ce) : 0;
+    const bool component = (component_mode == 1 || component_mode == 2) && stop_after == 0;
     std::vector<int32_t *> labs(n, nullptr);
     std::vector<TaskDev> table(n);
     uint32_t total = 0;
@@ -464,7 +466,7 @@ int emu_run(const EmuTask *tasks, int n, int bh, int qcap, int scan_rounds, int 
     uint32_t *ring = (uint32_t *)std::malloc((size_t)(total + n_waves + 1) * RING_STRIDE * sizeof(uint32_t));
     uint32_t *tpend = (uint32_t *)std::malloc(n * sizeof(uint32_t));
     uint32_t *tdone = (uint32_t *)std::malloc(n * sizeof(uint32_t));
-    uint32_t *route = component ? (uint32_t *)std::malloc(2 * n * sizeof(uint32_t)) : nullptr;
+    uint32_t *route = component ? (uint32_t *)std::malloc(ROUTE_WORDS * n * sizeof(uint32_t)) : nullptr;
 
     auto grid_run = [&](auto fn, uint32_t blocks, uint32_t threads) {
         kemu::gridDim_.x = blocks;
@@ -478,8 +480,8 @@ int emu_run(const EmuTask *tasks, int n, int bh, int qcap, int scan_rounds, int 
     };
     // stop_after 0: the persistent pipeline; 1..3: the staged one, stopped after that stage
     const bool merged = stop_after == 0;
-    grid_run([&] { reset_work(tt, work, state, ring, tpend, tdone, route, merged ? 1 : 0); }, 4, 64);
-    if (any_mapped) grid_run([&] { init_marker(tt); }, 8, 64);
+    grid_run([&] { reset_work(tt, work, state, ring, tpend, tdone, route,
+                              !merged ? RESET_STAGED : (component ? RESET_ROUTE : RESET_QUEUE_ALL)); }, 4, 64);
 
     KArgs ka;
     ka.work = work;
@@ -493,6 +495,7 @@ int emu_run(const EmuTask *tasks, int n, int bh, int qcap, int scan_rounds, int 
     ka.drain_budget = 128;
     ka.binary_drain_budget = 4;
     ka.route = route;
+    ka.route_policy = component_mode == 1 ? 1 : 0;
     {   // test hook of the block claims (see KArgs::test_fault)
         const char *f = std::getenv("KEMU_TEST_FAULT");
         ka.test_fault = f ? std::atoi(f) : 0;
@@ -537,7 +540,8 @@ int emu_run(const EmuTask *tasks, int n, int bh, int qcap, int scan_rounds, int 
         case 32: body = [&] { K<32>(tt, ka); }; break;          \
         default: body = [&] { K<64>(tt, ka); }; break;          \
     }
-                    if (which == 0) { KEMU_PICK(comp_classify) }
+                    if (which == 5) body = [&] { comp_sample(tt, ka); };
+                    else if (which == 0) { KEMU_PICK(comp_classify) }
                     else if (which == 1) { KEMU_PICK(comp_label_local) }
                     else if (which == 2) { KEMU_PICK(comp_label_merge) }
                     else if (which == 3) { KEMU_PICK(comp_flatten_max) }
@@ -548,16 +552,22 @@ int emu_run(const EmuTask *tasks, int n, int bh, int qcap, int scan_rounds, int 
             }
             for (auto &t : th) t.join();
         };
+        comp_grid(5, 0);
         comp_grid(0, 0);
+        grid_run([&] { queue_tasks(tt, ka); }, 2, 64);
+        if (any_mapped) grid_run([&] { init_marker(tt, route); }, 8, 64);
         comp_grid(1, (size_t)LT_H * LT_W * 4);
         comp_grid(2, 0);
         comp_grid(3, 0);
         comp_grid(4, 0);
+        grid_run([&] { queue_blocks(tt, ka); }, 3, 64);
+    } else if (any_mapped) {
+        grid_run([&] { init_marker(tt, nullptr); }, 8, 64);
     }
     if (!merged) run_grid(1, n_waves);
     if (stop_after >= 2) run_grid(2, n_waves);
     if (merged || stop_after >= 3) run_grid(3, n_waves);
-    if (any_mapped) grid_run([&] { finish_result(tt); }, 4, 64);
+    if (any_mapped) grid_run([&] { finish_result(tt, route); }, 4, 64);
 
     for (int k = 0; k < n; ++k) {
         const EmuTask &e = tasks[k];

@@ -83,9 +83,10 @@ def _spec(torch_mod, t):
 
 @pytest.mark.parametrize("conn", [8, 4])
 def test_mixed_batch_and_plain_calls(torch_mod, lib, oracle_mod, conn):
+    # component_route 1: every two-valued mask takes the route
     rng = np.random.default_rng(4400 + conn)
     tasks, n_two = _mixed_tasks(rng, conn)
-    with lib.Recon(0) as ctx:
+    with lib.Recon(0, component_route=1) as ctx:
         # one batch (the captured graph) holding both routes
         outs, specs = zip(*[_spec(torch_mod, t) for t in tasks])
         ctx.batch(list(specs))
@@ -110,6 +111,29 @@ def test_mixed_batch_and_plain_calls(torch_mod, lib, oracle_mod, conn):
             st = ctx.last_stats()
             assert st["component_tasks"] == (1 if i < n_two else 0), (i, op)
             assert_same(img.cpu().numpy(), oracle_mod.run_task(t), "plain task %d (%s)" % (i, op))
+
+
+def test_default_policy(torch_mod, lib, oracle_mod):
+    """The default route policy: beside a grey reconstruction, the fill-holes
+    of a blob image (thick foreground) keeps the block route while a corridor
+    (thin) takes the component route; alone, the fill-holes takes the route.
+    Every result equals the oracle."""
+    marker, mask, binary = synth.config2_tile(seed=synth.seed_for(2, 41), size=1024, n_gauss=188)
+    sm, smask, _ = synth.spiral_tile(700, 900, "inner")
+    with lib.Recon(0) as ctx:
+        m, k, b = dev(torch_mod, marker), dev(torch_mod, mask), dev(torch_mod, binary)
+        sp, sk = dev(torch_mod, sm), dev(torch_mod, smask)
+        ctx.batch([{"op": "dilate", "image": m, "mask": k, "conn": 8},
+                   {"op": "fill_holes", "image": b, "conn": 8},
+                   {"op": "dilate", "image": sp, "mask": sk, "conn": 4}])
+        assert ctx.last_stats()["component_tasks"] == 1
+        assert_same(m.cpu().numpy(), oracle_mod.recon_dilate(marker, mask, 8), "grey dilate")
+        assert_same(b.cpu().numpy(), oracle_mod.fill_holes(binary, 8), "fill beside grey")
+        assert_same(sp.cpu().numpy(), smask, "corridor beside grey")
+        b = dev(torch_mod, binary)
+        ctx.fill_holes(b, 8)
+        assert ctx.last_stats()["component_tasks"] == 1
+        assert_same(b.cpu().numpy(), oracle_mod.fill_holes(binary, 8), "fill alone")
 
 
 def test_route_off_takes_the_block_route(torch_mod, lib, oracle_mod):

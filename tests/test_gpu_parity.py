@@ -319,9 +319,9 @@ def test_small_batch_in_timing_context(torch_mod, lib, oracle_mod):
                        {"op": "fill_holes", "image": b, "conn": 8}])
             st = ctx.last_stats()
             assert st["drain_ms"] > 0 and st["total_ms"] >= st["drain_ms"]
-            # the binary fill-holes takes the component route: only the
-            # reconstruction's 32 x 4 blocks are visited
-            assert st["dense_visits"] == 32 * 4 and st["component_tasks"] == 1
+            # beside the grey reconstruction the binary fill-holes (thick
+            # foreground) keeps the block route: both tasks' 32 x 4 blocks are visited
+            assert st["dense_visits"] == 2 * 32 * 4 and st["component_tasks"] == 0
             t = ctx.launch_times(0)
             assert t["drain_ms"] == st["drain_ms"]
             assert_same(m.cpu().numpy(), oracle_mod.recon_dilate(marker, mask, 8), "batched dilate %d" % rep)

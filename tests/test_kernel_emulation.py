@@ -155,6 +155,10 @@ def test_label_and_area_threshold(emu_exe, oracle_mod, conn):
         imgs.append(np.where(rng.random((h, w)) < p, 255, 0).astype(np.uint8))
     yy, xx = np.mgrid[0:35, 0:300]
     imgs.append(np.where((yy + xx) % 2 == 0, 255, 0).astype(np.uint8))
+    # thin diagonal lines crossing tile rows and columns anywhere, corners included
+    yy, xx = np.mgrid[0:50, 0:600]
+    imgs.append(np.where((xx - yy) % 7 == 0, 255, 0).astype(np.uint8))
+    imgs.append(np.where(((xx + yy) % 5 == 0) | ((xx - 2 * yy) % 13 == 0), 255, 0).astype(np.uint8))
     imgs.append(synth.spiral_tile(40, 520, "outer")[1])
     _, _, binary = synth.config2_tile(seed=synth.seed_for(2, 25), size=96, n_gauss=2)
     imgs.append(np.ascontiguousarray(np.concatenate([binary, binary[:, ::-1], binary], 1)))
@@ -243,3 +247,24 @@ def test_component_route(emu_exe, oracle_mod, conn, bh):
     tasks.append({"op": "fill_holes", "img": rng.integers(0, 256, (20, 270)).astype(np.uint8), "conn": conn})
     log = _check(emu_exe, oracle_mod, tasks, n_waves=3, bh=bh, component=1)
     assert _route_count(log) == two_valued, log[-500:]
+
+
+def test_component_route_policy(emu_exe, oracle_mod):
+    """The default policy: beside a grey task, a thick two-valued mask (the
+    fill-holes of blobs) keeps the block route and a thin one (a corridor)
+    takes the component route; alone, the thick one takes the route too.
+    Every result equals the oracle either way."""
+    rng = np.random.default_rng(5150)
+    m, k = synth.random_pair(rng, 40, 300, 5)
+    grey = {"op": "dilate", "marker": m, "mask": k, "conn": 8}
+    yy, xx = np.mgrid[0:64, 0:300]
+    blobs = np.where(((yy % 32) - 16) ** 2 + ((xx % 40) - 20) ** 2 < 60, 255, 0).astype(np.uint8)
+    thick = {"op": "fill_holes", "img": blobs, "conn": 8}
+    spiral, seed = synth.spiral_tile(61, 300, "outer")[:2]
+    thin = {"op": "dilate", "marker": seed, "mask": spiral, "conn": 4}
+    log = _check(emu_exe, oracle_mod, [grey, thick, thin], n_waves=3, component=2)
+    assert _route_count(log) == 1, log[-500:]
+    log = _check(emu_exe, oracle_mod, [thick], n_waves=3, component=2)
+    assert _route_count(log) == 1, log[-500:]
+    log = _check(emu_exe, oracle_mod, [grey, thick], n_waves=3, component=2)
+    assert _route_count(log) == 0, log[-500:]
