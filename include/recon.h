@@ -165,7 +165,12 @@ typedef struct {
                                   1: taken by every two-valued mask.  -1: never.  With 0 or 1
                                   each task holds an int32 label plane in the context's
                                   scratch area (4 bytes per pixel). */
-    int32_t reserved[2];
+    int32_t spill_capacity;    /* entries of each revisit wave's global spill queue, the level
+                                  under its LDS queue: pushes that do not fit the LDS queue go
+                                  there and are drained back when it runs empty; only when both
+                                  are full does the block re-seed.  0 = default 8192 (64..65536;
+                                  16 MiB per 1024 entries of the context's workspace), -1 = none */
+    int32_t reserved[1];
 } recon_config;
 
 /* Per-call statistics of the last completed launch (for tests and tuning). */
@@ -173,7 +178,8 @@ typedef struct {
     int64_t dense_visits;      /* first visits of work blocks */
     int64_t revisits;          /* later visits triggered by neighbour changes */
     int64_t reruns;            /* in-place re-runs of a block re-requested while running */
-    int64_t queue_overflows;   /* LDS queue overflows (each followed by a re-seed pass) */
+    int64_t queue_overflows;   /* queue overflows, LDS queue and spill queue both full (each
+                                  followed by a re-seed pass) */
     int64_t requests;          /* block revisits requested by border checks */
     int64_t aborted;           /* 1 if the scheduler watchdog stopped the launch */
     /* with recon_config.timing: durations in ms of the dense pass (K1), the border
@@ -187,6 +193,7 @@ typedef struct {
                                   route's kernels (classification, labelling, maxima), -1 for
                                   a replayed graph, 0 when the route is off */
     float reserved_f;
+    int64_t queue_spills;      /* queue entries pushed to the global spill queues */
 } recon_stats;
 
 /* Create a context on HIP device `device`.  cfg may be NULL.  Runs a small

@@ -69,7 +69,7 @@ class recon_config(ctypes.Structure):
                 ("stop_after_stage", ctypes.c_int32), ("timing", ctypes.c_int32),
                 ("drain_budget", ctypes.c_int32), ("binary_drain_budget", ctypes.c_int32),
                 ("test_fault", ctypes.c_int32), ("component_route", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("spill_capacity", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
 
 
 class recon_stats(ctypes.Structure):
@@ -78,7 +78,8 @@ class recon_stats(ctypes.Structure):
                 ("requests", ctypes.c_int64), ("aborted", ctypes.c_int64),
                 ("dense_ms", ctypes.c_float), ("seed_ms", ctypes.c_float), ("drain_ms", ctypes.c_float),
                 ("total_ms", ctypes.c_float), ("component_tasks", ctypes.c_int64),
-                ("route_ms", ctypes.c_float), ("reserved_f", ctypes.c_float)]
+                ("route_ms", ctypes.c_float), ("reserved_f", ctypes.c_float),
+                ("queue_spills", ctypes.c_int64)]
 
 
 _lib = None

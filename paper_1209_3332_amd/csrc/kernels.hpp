@@ -143,9 +143,10 @@ struct Work {
     unsigned long long stat_overflow;
     unsigned long long stat_request;
     unsigned long long stat_route;   // tasks reconstructed by the component route
+    unsigned long long stat_spill;   // queue entries pushed to a global spill queue
     uint32_t route_any;              // some task of the launch takes the component route
     uint32_t has_grey;               // some task of the launch keeps the block route whatever it looks like
-    unsigned long long pad4[9];
+    unsigned long long pad4[8];
 };
 
 struct KArgs {
@@ -162,6 +163,8 @@ struct KArgs {
     int32_t test_fault;          // test hook: 1 = every claim's compare-and-swap is made to fail
     uint32_t *route;             // ROUTE_WORDS per task (below)
     int32_t route_policy;        // 0: the component route where it pays (auto); 1: for every two-valued mask
+    uint16_t *spill;             // global spill queues: spill_cap entries per wave of the grid (null: none)
+    uint32_t spill_cap;
 };
 
 // Route words of a task: [0] OR and [1] AND of its nonzero mask values (the
@@ -391,6 +394,12 @@ struct Lds {
     RK_LDS uint8_t *I;
     RK_LDS uint8_t *rowdirty;   // BH bytes
     RK_LDS uint16_t *Q;         // queue ring (power-of-two entries)
+    // The wave's global spill queue (the second level under the LDS ring):
+    // pushes that do not fit the ring go there, and the drain takes them back
+    // when the ring runs empty.  Its state sits in LDS, read only on those
+    // cold paths: sp[0..1] the queue's base address, sp[2] its capacity,
+    // sp[3] the entries it holds.
+    RK_LDS uint32_t *sp;
     __device__ __forceinline__ RK_LDS uint32_t *Jw(int y, int d) {  // dword d of row y (y in -1..BH)
         return (RK_LDS uint32_t *)(J + (y + 1) * JP + JOFF + 4 * d);
     }
@@ -403,7 +412,7 @@ struct Lds {
 
 template <int BH>
 __host__ __device__ constexpr size_t lds_bytes(int qcap) {
-    return 2 * (size_t)(BH + 2) * JP + (size_t)((BH + 15) & ~15) + 2u * (size_t)qcap;
+    return 2 * (size_t)(BH + 2) * JP + (size_t)((BH + 15) & ~15) + 32u + 2u * (size_t)qcap;
 }
 
 // Lockstep point: the lanes of a wave execute in lockstep on the GPU, so this
@@ -428,7 +437,8 @@ __device__ __forceinline__ Lds<BH> lds_layout() {
     L.J = dyn_lds();
     L.I = L.J + (BH + 2) * JP;
     L.rowdirty = L.I + (BH + 2) * JP;
-    L.Q = (RK_LDS uint16_t *)(L.rowdirty + ((BH + 15) & ~15));
+    L.sp = (RK_LDS uint32_t *)(L.rowdirty + ((BH + 15) & ~15));
+    L.Q = (RK_LDS uint16_t *)(L.rowdirty + ((BH + 15) & ~15) + 32);
     return L;
 }
 
@@ -455,7 +465,7 @@ __device__ __forceinline__ BlockGeom geom(const TaskDev &t, int by, int bx) {
 // of a fill-holes block, J is the initial frame marker).  Outside the image: 0.
 // COH: marker read from the device-coherent level (revisits).
 template <int BH, bool COH>
-__device__ void load_block(const TaskDev &t, const BlockGeom &g, Lds<BH> &L, bool fill_initial) {
+__device__ __forceinline__ void load_block(const TaskDev &t, const BlockGeom &g, Lds<BH> &L, bool fill_initial) {
     const int ln = lane_id();
     const int x = 4 * ln;
     const int valid = min(4, g.bw - x);
@@ -516,7 +526,7 @@ __device__ void load_block(const TaskDev &t, const BlockGeom &g, Lds<BH> &L, boo
 
 // Set the halo ring to 0 (no neighbour information).
 template <int BH>
-__device__ void clear_halo(Lds<BH> &L) {
+__device__ __forceinline__ void clear_halo(Lds<BH> &L) {
     const int ln = lane_id();
     *L.Jw(-1, ln) = 0u;
     *L.Jw(BH, ln) = 0u;
@@ -588,7 +598,7 @@ __device__ __forceinline__ void halo_store(const HaloRegs &h, Lds<BH> &L) {
 }
 
 template <int BH>
-__device__ void load_halo(const TaskDev &t, const BlockGeom &g, Lds<BH> &L) {
+__device__ __forceinline__ void load_halo(const TaskDev &t, const BlockGeom &g, Lds<BH> &L) {
     HaloRegs h;
     halo_issue<BH>(t, g, h);
     halo_store<BH>(h, L);
@@ -600,7 +610,7 @@ __device__ __forceinline__ bool binary4(uint32_t v) { return ((v ^ (v >> 1)) & 0
 // Whether the block's mask (in LDS) is binary, 0 / 255 only: there a raise
 // floods whole regions, which sweeps move faster than the queue.
 template <int BH>
-__device__ bool mask_is_binary(Lds<BH> &L) {
+__device__ __forceinline__ bool mask_is_binary(Lds<BH> &L) {
     const int ln = lane_id();
     bool bin = true;
     for (int r = 0; r < BH; ++r) bin = bin && binary4(*L.Iw(r, ln));
@@ -611,7 +621,7 @@ __device__ bool mask_is_binary(Lds<BH> &L) {
 // level) and its halo, with all loads of a whole-width aligned block of up to
 // 32 rows in flight together.
 template <int BH>
-__device__ void load_visit(const TaskDev &t, const BlockGeom &g, Lds<BH> &L) {
+__device__ __forceinline__ void load_visit(const TaskDev &t, const BlockGeom &g, Lds<BH> &L) {
     if (!(t.aligned && g.bw == BW && BH <= 32)) {
         load_block<BH, true>(t, g, L, false);
         load_halo<BH>(t, g, L);
@@ -704,7 +714,7 @@ __device__ __forceinline__ uint32_t sel_row(int row, uint32_t e0, uint32_t e1, u
 // per pixel maps (byte j of lo4, hi4, lo <= hi), `vl` entering pixel 0 from the
 // left and `vr` entering pixel 255 from the right (both wave-uniform).  Returns
 // the pixels' values: max of the left-to-right and right-to-left scans.
-__device__ uint32_t row_closure(uint32_t lo4, uint32_t hi4, uint32_t vl, uint32_t vr) {
+__device__ __forceinline__ uint32_t row_closure(uint32_t lo4, uint32_t hi4, uint32_t vl, uint32_t vr) {
     const int ln = lane_id();
     const int row = ln >> 4;
     uint32_t lo[4], hi[4];
@@ -784,7 +794,7 @@ __device__ uint32_t row_closure(uint32_t lo4, uint32_t hi4, uint32_t vl, uint32_
 // read one row ahead and their latency overlaps the closure of the row before.
 // After the last block row the read-ahead lands on the halo row, which exists.
 template <int BH, int CONN>
-__device__ bool sweep(Lds<BH> &L, int dir) {
+__device__ __forceinline__ bool sweep(Lds<BH> &L, int dir) {
     constexpr int conn = CONN;
     const int ln = lane_id();
     const int r0 = dir > 0 ? 0 : BH - 1;
@@ -821,16 +831,59 @@ __device__ bool sweep(Lds<BH> &L, int dir) {
     return changed;
 }
 
-// push the pixels flagged by `pred` (one per lane) onto the LDS ring of qcap
-// (a power of two) entries; returns false (and pushes nothing) if they do not fit.
-__device__ __forceinline__ bool push_bits(RK_LDS uint16_t *Q, int qcap, uint32_t head, uint32_t &tail,
-                                          bool pred, uint32_t pix) {
+// A round of sweeps: down, then up.  One loop (not unrolled) holds one inlined
+// copy of the sweep, so that each call site of a round costs one copy.
+// Returns true if anything changed.
+template <int BH, int CONN>
+__device__ __forceinline__ bool sweep_round(Lds<BH> &L) {
+    bool c = false;
+#pragma unroll 1
+    for (int d = 0; d < 2; ++d) {
+        c |= sweep<BH, CONN>(L, d == 0 ? +1 : -1);
+        __syncthreads();
+    }
+    return c;
+}
+
+// The spill queue's base address (state in LDS, see Lds::sp)
+__device__ __forceinline__ uint16_t *spill_base(const volatile RK_LDS uint32_t *sp) {
+    return (uint16_t *)(((uint64_t)sp[1] << 32) | (uint64_t)sp[0]);
+}
+
+// Push the pixels flagged by `pred` (one per lane) onto the LDS ring of qcap
+// (a power of two) entries.  Returns false (and pushes nothing) if they do not
+// fit: the caller then keeps them aside and hands them to spill() once its
+// unit of work (a drain round, a seeded row) is done, so that the cold spill
+// path exists once per unit instead of at every push site.
+template <int BH>
+__device__ __forceinline__ bool push(Lds<BH> &L, int qcap, uint32_t head, uint32_t &tail, bool pred, uint32_t pix) {
     const unsigned long long m = __ballot(pred);
     if (m == 0) return true;
     const uint32_t cnt = (uint32_t)__popcll(m);
     if (tail - head + cnt > (uint32_t)qcap) return false;
-    if (pred) ((volatile RK_LDS uint16_t *)Q)[(tail + prefix_count(m)) & (uint32_t)(qcap - 1)] = (uint16_t)pix;
+    if (pred) ((volatile RK_LDS uint16_t *)L.Q)[(tail + prefix_count(m)) & (uint32_t)(qcap - 1)] = (uint16_t)pix;
     tail += cnt;
+    return true;
+}
+
+// Push the pixels flagged by `pred` to the wave's global spill queue; false
+// (nothing pushed) if it has no room.  The spill is written and read back by
+// its own wave only, at the device-coherent level (so that no cache level can
+// hold an older copy of an entry the wave rewrote), and read only after a wait
+// for the writes (drain).
+template <int BH>
+__device__ __forceinline__ bool spill(Lds<BH> &L, bool pred, uint32_t pix) {
+    const unsigned long long m = __ballot(pred);
+    if (m == 0) return true;
+    const uint32_t cnt = (uint32_t)__popcll(m);
+    volatile RK_LDS uint32_t *sp = L.sp;
+    const uint32_t n = uniform(sp[3]);
+    if (n + cnt > uniform(sp[2])) return false;
+    if (pred)
+        __hip_atomic_store((RK_GLOBAL uint16_t *)(spill_base(sp) + n + prefix_count(m)), (uint16_t)pix,
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    RK_LANE_SYNC();   // every lane has read the count before it moves
+    if (lane_id() == 0) sp[3] = n + cnt;
     return true;
 }
 
@@ -848,7 +901,7 @@ __device__ __forceinline__ volatile RK_LDS uint8_t &jv(Lds<BH> &L, int y, int x)
 // written while row r is seeded, row r is carried as written), so each row
 // reads one new marker row, read a row ahead, and its mask row.
 template <int BH, int CONN>
-__device__ void seed_pass(Lds<BH> &L, int qcap, uint32_t head, uint32_t &tail,
+__device__ __forceinline__ void seed_pass(Lds<BH> &L, int qcap, uint32_t head, uint32_t &tail,
                           bool &overflow, bool &changed) {
     constexpr int conn = CONN;
     const int ln = lane_id();
@@ -878,10 +931,18 @@ __device__ void seed_pass(Lds<BH> &L, int qcap, uint32_t head, uint32_t &tail,
         }
         if (__ballot(dm != 0)) {
             changed = true;
+            uint32_t lost = 0;      // bit j: this lane's pixel j did not fit the ring
+            bool any_lost = false;  // (a push fails for the whole wave: a uniform branch)
             for (int j = 0; j < 4; ++j) {
                 const bool p = (dm >> j) & 1u;
-                if (!push_bits(L.Q, qcap, head, tail, p, (uint32_t)(r * BW + 4 * ln + j))) overflow = true;
+                if (!push(L, qcap, head, tail, p, (uint32_t)(r * BW + 4 * ln + j))) {
+                    any_lost = true;
+                    lost |= (p ? 1u : 0u) << j;
+                }
             }
+            if (any_lost)
+                for (int j = 0; j < 4; ++j)
+                    if (!spill(L, (lost >> j) & 1u, (uint32_t)(r * BW + 4 * ln + j))) overflow = true;
         }
         a = nv;
         ahl = chl;
@@ -911,7 +972,7 @@ __device__ __forceinline__ bool raise_px(Lds<BH> &L, int y, int x, uint32_t targ
 // border can be raised by a neighbour (the interior was left converged by the
 // previous visit, and only the owner writes it).  Raise and push exactly those.
 template <int BH, int CONN>
-__device__ void seed_border(Lds<BH> &L, int bh, int bw, int qcap, uint32_t head, uint32_t &tail,
+__device__ __forceinline__ void seed_border(Lds<BH> &L, int bh, int bw, int qcap, uint32_t head, uint32_t &tail,
                             bool &overflow, bool &changed) {
     constexpr int conn = CONN;
     const int ln = lane_id();
@@ -940,10 +1001,18 @@ __device__ void seed_border(Lds<BH> &L, int bh, int bw, int qcap, uint32_t head,
         }
         if (__ballot(dm != 0)) {
             changed = true;
+            uint32_t lost = 0;
+            bool any_lost = false;
             for (int j = 0; j < 4; ++j) {
                 const bool p = (dm >> j) & 1u;
-                if (!push_bits(L.Q, qcap, head, tail, p, (uint32_t)(r * BW + 4 * ln + j))) overflow = true;
+                if (!push(L, qcap, head, tail, p, (uint32_t)(r * BW + 4 * ln + j))) {
+                    any_lost = true;
+                    lost |= (p ? 1u : 0u) << j;
+                }
             }
+            if (any_lost)
+                for (int j = 0; j < 4; ++j)
+                    if (!spill(L, (lost >> j) & 1u, (uint32_t)(r * BW + 4 * ln + j))) overflow = true;
         }
     }
     __syncthreads();
@@ -966,7 +1035,8 @@ __device__ void seed_border(Lds<BH> &L, int bh, int bw, int qcap, uint32_t head,
             if (raised) L.rowdirty[r] = 1;
         }
         if (__ballot(raised)) changed = true;
-        if (!push_bits(L.Q, qcap, head, tail, raised, (uint32_t)(r * BW + x))) overflow = true;
+        if (!push(L, qcap, head, tail, raised, (uint32_t)(r * BW + x)) && !spill(L, raised, (uint32_t)(r * BW + x)))
+            overflow = true;
         __syncthreads();
     }
 }
@@ -975,17 +1045,56 @@ __device__ void seed_border(Lds<BH> &L, int bh, int bw, int qcap, uint32_t head,
 __host__ __device__ constexpr int nb_dy(int k) { return k == 0 || k == 4 || k == 5 ? -1 : (k == 1 || k >= 6 ? 1 : 0); }
 __host__ __device__ constexpr int nb_dx(int k) { return k == 2 || k == 4 || k == 6 ? -1 : (k == 3 || k == 5 || k == 7 ? 1 : 0); }
 
-// Drain the LDS ring to empty; *overflow set if pushes had to be dropped.
+// Drain the LDS ring, and the wave's spill queue behind it, to empty;
+// *overflow set if pushes had to be dropped (the ring full, the spill queue
+// too, or a ring too small for a round).
 // Each round pops up to 64 pixels (one per lane) and offers every popped
 // pixel's value to its neighbours, one direction at a time.
 // At most `budget` rounds (no limit if negative); returns false if the ring was
 // not empty when the budget ran out.
 template <int BH, int CONN>
-__device__ bool drain(Lds<BH> &L, int qcap, uint32_t &head, uint32_t &tail, bool &overflow, int budget) {
+__device__ __forceinline__ bool drain(Lds<BH> &L, int qcap, uint32_t &head, uint32_t &tail, bool &overflow, int budget) {
     const int ln = lane_id();
-    const volatile RK_LDS uint16_t *Qv = L.Q;
+    volatile RK_LDS uint16_t *Qv = L.Q;
     volatile RK_LDS uint8_t *Jv = L.J;
-    while (head != tail) {
+    // room a round may need: up to 64 popped pixels x CONN pushes (at most
+    // half the ring, for small rings)
+    const uint32_t room = min((uint32_t)(LANES * CONN), (uint32_t)qcap / 2u);
+    while (true) {
+        if (tail - head + room > (uint32_t)qcap) {
+            // nearly full: the newest entries go to the spill queue first, so
+            // that no push of the round fails (cold; the round itself stays as
+            // it is without a spill)
+            volatile RK_LDS uint32_t *sp = L.sp;
+            const uint32_t held = uniform(sp[3]), cap = uniform(sp[2]);
+            const uint32_t m = min(tail - head + room - (uint32_t)qcap, cap - held);
+            for (uint32_t i = (uint32_t)ln; i < m; i += LANES)
+                __hip_atomic_store((RK_GLOBAL uint16_t *)(spill_base(sp) + held + i),
+                                   (uint16_t)Qv[(tail - m + i) & (uint32_t)(qcap - 1)], __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            tail -= m;
+            RK_LANE_SYNC();   // every lane has read the count before it moves
+            if (ln == 0) sp[3] = held + m;
+        }
+        if (head == tail) {
+            volatile RK_LDS uint32_t *sp = L.sp;
+            const uint32_t held = uniform(sp[3]);
+            if (held == 0) break;
+            // the ring ran empty: take the spill's last entries back into it
+            const uint32_t n = min(held, (uint32_t)qcap);
+            const uint32_t base = held - n;
+            vm_sync();   // the spill's stores have completed
+            for (uint32_t i = (uint32_t)ln; i < n; i += LANES)
+                Qv[(tail + i) & (uint32_t)(qcap - 1)] =
+                    __hip_atomic_load((RK_GLOBAL uint16_t *)(spill_base(sp) + base + i), __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT);
+            tail += n;
+            RK_LANE_SYNC();   // every lane has read the count before it moves
+            if (ln == 0) {
+                sp[3] = base;
+                sp[4] += n;   // entries taken back (statistics)
+            }
+        }
         if (budget-- == 0) return false;
         RK_LANE_SYNC();
         const uint32_t n = min(tail - head, (uint32_t)LANES);
@@ -1014,8 +1123,7 @@ __device__ bool drain(Lds<BH> &L, int qcap, uint32_t &head, uint32_t &tail, bool
             const uint32_t tgt = min(v, iv[k]);
             RK_LANE_SYNC();   // every lane's store of direction k-1 is issued before this read
             const uint32_t cur = Jv[a + off];
-            if (k > 0 &&
-                !push_bits(L.Q, qcap, head, tail, prev_raised, p + (uint32_t)(nb_dy(k - 1) * BW + nb_dx(k - 1))))
+            if (k > 0 && !push(L, qcap, head, tail, prev_raised, p + (uint32_t)(nb_dy(k - 1) * BW + nb_dx(k - 1))))
                 overflow = true;
             const bool raised = in && cur < tgt;
             if (raised) {
@@ -1024,7 +1132,7 @@ __device__ bool drain(Lds<BH> &L, int qcap, uint32_t &head, uint32_t &tail, bool
             }
             prev_raised = raised;
         }
-        if (!push_bits(L.Q, qcap, head, tail, prev_raised, p + (uint32_t)(nb_dy(CONN - 1) * BW + nb_dx(CONN - 1))))
+        if (!push(L, qcap, head, tail, prev_raised, p + (uint32_t)(nb_dy(CONN - 1) * BW + nb_dx(CONN - 1))))
             overflow = true;
     }
     return true;
@@ -1053,13 +1161,15 @@ constexpr uint32_t WIDE_FRONT = 64;
 constexpr uint32_t WIDE_FRONT_LOAD = 4;
 
 template <int BH, int CONN>
-__device__ bool converge_block(Lds<BH> &L, int qcap, WaveStats &st, bool border_only, int bh, int bw,
+__device__ __forceinline__ bool converge_block(Lds<BH> &L, int qcap, WaveStats &st, bool border_only, int bh, int bw,
                                int budget, bool wide_first = false) {
     bool changed = false;
     int fallbacks = border_only ? SWEEP_FALLBACKS : 0;
     for (int round = 0; round <= (1 << 16); ++round) {   // each round raises pixels; bounded anyway
         uint32_t head = 0, tail = 0;
         bool overflow = false;
+        if (lane_id() == 0) ((volatile RK_LDS uint32_t *)L.sp)[3] = 0u;   // a round starts with empty queues
+        __syncthreads();                                                  // (a seed finds every raisable pixel again)
         if (border_only && round == 0)
             seed_border<BH, CONN>(L, bh, bw, qcap, head, tail, overflow, changed);
         else
@@ -1070,10 +1180,7 @@ __device__ bool converge_block(Lds<BH> &L, int qcap, WaveStats &st, bool border_
         __syncthreads();
         if (!drained) {
             --fallbacks;
-            sweep<BH, CONN>(L, +1);
-            __syncthreads();
-            sweep<BH, CONN>(L, -1);
-            __syncthreads();
+            sweep_round<BH, CONN>(L);
             continue;
         }
         if (!__ballot(overflow)) break;
@@ -1087,7 +1194,7 @@ __device__ bool converge_block(Lds<BH> &L, int qcap, WaveStats &st, bool border_
 // Write back the rows flagged dirty (all rows if `all`).
 // COH: to the device-coherent level (revisits).
 template <int BH, bool COH>
-__device__ void store_block(const TaskDev &t, const BlockGeom &g, Lds<BH> &L, bool all) {
+__device__ __forceinline__ void store_block(const TaskDev &t, const BlockGeom &g, Lds<BH> &L, bool all) {
     const int ln = lane_id();
     const int x = 4 * ln;
     const int valid = min(4, g.bw - x);
@@ -1135,6 +1242,7 @@ __device__ __forceinline__ void flush_stats(Work *w, const WaveStats &st) {
         __hip_atomic_fetch_add(&w->stat_overflow, st.overflow, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (st.request)
         __hip_atomic_fetch_add(&w->stat_request, st.request, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+
 }
 
 // Request visits of the neighbouring blocks flagged in `want` (bit k:
@@ -1148,7 +1256,7 @@ __device__ __forceinline__ void flush_stats(Work *w, const WaveStats &st) {
 // caller's marker stores have completed before (vm_sync), so all atomics here
 // are relaxed.  Returns false if the watchdog expired while waiting for a ring
 // slot.
-__device__ bool request_neighbours(const KArgs &a, uint32_t ring_cap, int ti, uint32_t gb, int nbx, uint32_t want,
+__device__ __forceinline__ bool request_neighbours(const KArgs &a, uint32_t ring_cap, int ti, uint32_t gb, int nbx, uint32_t want,
                                    int *keep, WaveStats &st) {
     const int ln = lane_id();
     const int k = ln & 7;
@@ -1206,7 +1314,7 @@ __device__ bool request_neighbours(const KArgs &a, uint32_t ring_cap, int ti, ui
 // never higher, so a needed request is never missed; a stale one only costs a
 // visit that finds nothing to do.
 template <int BH>
-__device__ bool check_neighbours(const KArgs &a, uint32_t ring_cap, int ti, const TaskDev &t,
+__device__ __forceinline__ bool check_neighbours(const KArgs &a, uint32_t ring_cap, int ti, const TaskDev &t,
                                  const BlockGeom &g, int by, int bx, Lds<BH> &L, int *keep,
                                  WaveStats &st) {
     const int ln = lane_id();
@@ -1276,15 +1384,23 @@ __device__ bool check_neighbours(const KArgs &a, uint32_t ring_cap, int ti, cons
 
 // A block loaded with an empty halo: sweep rounds, then seed and drain.
 template <int BH, int CONN>
-__device__ void dense_block(const TaskDev &t, const BlockGeom &g, Lds<BH> &L, WaveStats &st) {
-    for (int k = 0; k < t.scan_rounds; ++k) {
-        bool c = sweep<BH, CONN>(L, +1);
-        __syncthreads();
-        c |= sweep<BH, CONN>(L, -1);
-        __syncthreads();
-        if (!__ballot(c)) break;
-    }
+__device__ __forceinline__ void dense_block(const TaskDev &t, const BlockGeom &g, Lds<BH> &L, WaveStats &st) {
+    for (int k = 0; k < t.scan_rounds; ++k)
+        if (!__ballot(sweep_round<BH, CONN>(L))) break;
     converge_block<BH, CONN>(L, t.qcap, st, false, g.bh, g.bw, -1);
+}
+
+// One visit's work on the loaded block: dense (a first visit: sweep rounds,
+// then a dense seed and a drain to the end) or from the border (a later
+// visit, with the revisit budget and fallbacks).  Returns whether anything
+// changed (a dense visit always writes its block back).
+template <int BH, int CONN>
+__device__ __forceinline__ bool visit_block(const TaskDev &t, Lds<BH> &L, WaveStats &st, bool dense, int bh, int bw,
+                                            int budget, bool wide_first) {
+    if (dense)
+        for (int k = 0; k < t.scan_rounds; ++k)
+            if (!__ballot(sweep_round<BH, CONN>(L))) break;
+    return converge_block<BH, CONN>(L, t.qcap, st, !dense, bh, bw, dense ? -1 : budget, wide_first && !dense);
 }
 
 template <int BH>
@@ -1373,7 +1489,7 @@ __global__ __launch_bounds__(64) void border_seed(TaskTable tt, KArgs a) {
 
 // Wait for the block id at ticket `ticket`.  Returns the global block id, -1
 // when all work is done, -2 on abort (watchdog).
-__device__ int wait_ticket(const KArgs &a, uint32_t ring_cap, uint32_t ticket) {
+__device__ __forceinline__ int wait_ticket(const KArgs &a, uint32_t ring_cap, uint32_t ticket) {
     const int ln = lane_id();
     Work *w = a.work;
     uint32_t *slot = a.ring + (size_t)(ticket % ring_cap) * RING_STRIDE;
@@ -1415,7 +1531,7 @@ __device__ int wait_ticket(const KArgs &a, uint32_t ring_cap, uint32_t ticket) {
 }
 
 // The last outstanding visit is complete: release every waiting ticket holder.
-__device__ void release_waiters(const KArgs &a, uint32_t ring_cap) {
+__device__ __forceinline__ void release_waiters(const KArgs &a, uint32_t ring_cap) {
     const int ln = lane_id();
     Work *w = a.work;
     uint32_t h = 0, tl = 0;
@@ -1435,6 +1551,16 @@ __device__ void release_waiters(const KArgs &a, uint32_t ring_cap) {
 template <int BH>
 __global__ __launch_bounds__(64) void revisit_drain(TaskTable tt, KArgs a) {
     Lds<BH> L = lds_layout<BH>();
+    if (lane_id() == 0) {   // this wave's spill queue (capacity 0: none)
+        const uint64_t sb = (uint64_t)(uintptr_t)(a.spill ? a.spill + (size_t)blockIdx.x * a.spill_cap : nullptr);
+        volatile RK_LDS uint32_t *sp = L.sp;
+        sp[0] = (uint32_t)sb;
+        sp[1] = (uint32_t)(sb >> 32);
+        sp[2] = a.spill ? a.spill_cap : 0u;
+        sp[3] = 0u;
+        sp[4] = 0u;
+    }
+    __syncthreads();
     const int ln = lane_id();
     Work *w = a.work;
     const uint32_t ring_cap = ring_cap_of(tt);
@@ -1520,16 +1646,12 @@ __global__ __launch_bounds__(64) void revisit_drain(TaskTable tt, KArgs a) {
             for (int r = ln; r < BH; r += LANES) L.rowdirty[r] = 0;
             __syncthreads();
             const bool dense = first && pass == 0;
-            bool changed = true;
-            if (dense) {   // sweeps, dense seed and drain, with the halo as it is now
-                if (t.conn == 8)
-                    dense_block<BH, 8>(t, g, L, st);
-                else
-                    dense_block<BH, 4>(t, g, L, st);
-            } else {       // the interior is converged: seed from the border
-                changed = t.conn == 8 ? converge_block<BH, 8>(L, t.qcap, st, true, g.bh, g.bw, budget, wide_first)
-                                      : converge_block<BH, 4>(L, t.qcap, st, true, g.bh, g.bw, budget, wide_first);
-            }
+            // a first visit: sweeps, dense seed and drain, with the halo as it
+            // is now; a later one: the interior is converged, seed from the
+            // border (one call site per connectivity keeps the kernel small)
+            bool changed = t.conn == 8 ? visit_block<BH, 8>(t, L, st, dense, g.bh, g.bw, budget, wide_first)
+                                       : visit_block<BH, 4>(t, L, st, dense, g.bh, g.bw, budget, wide_first);
+            if (dense) changed = true;
             if (changed) {
                 store_block<BH, true>(t, g, L, dense);
                 vm_sync();   // the stores are complete before any request below
@@ -1578,6 +1700,11 @@ __global__ __launch_bounds__(64) void revisit_drain(TaskTable tt, KArgs a) {
         if (uniform(last)) release_waiters(a, ring_cap);
         if (!ok) break;
     }
+    if (lane_id() == 0) {   // entries that went through the spill queue
+        const uint32_t taken = ((volatile RK_LDS uint32_t *)L.sp)[4];
+        if (taken) __hip_atomic_fetch_add(&w->stat_spill, (unsigned long long)taken, __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
+    }
     flush_stats(w, st);
 }
 
@@ -1616,6 +1743,7 @@ __global__ void reset_work(TaskTable tt, Work *w, uint32_t *state, uint32_t *rin
         w->progress = 0;
         w->stat_dense = w->stat_revisit = w->stat_rerun = w->stat_overflow = w->stat_request = 0;
         w->stat_route = 0;
+        w->stat_spill = 0;
         w->route_any = 0;
         w->has_grey = 0;
     }

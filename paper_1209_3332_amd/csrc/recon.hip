@@ -133,7 +133,8 @@ struct recon_ctx {
     size_t cap_blocks = 0;
     uint32_t *d_tile_pending = nullptr;
     uint32_t *d_tile_done = nullptr;
-    uint32_t *d_route = nullptr;      // two mask-classification words per task (component route)
+    uint32_t *d_route = nullptr;      // route words per task (component route)
+    uint16_t *d_spill = nullptr;      // global spill queues of the revisit kernel's waves
     uint8_t *d_scratch = nullptr;     // fill-holes marker planes
     size_t cap_scratch = 0;
     // pinned staging (task table in, statistics out)
@@ -200,6 +201,8 @@ void free_workspace(recon_ctx *c) {
     (void)hipFree(c->d_tile_pending);
     (void)hipFree(c->d_tile_done);
     (void)hipFree(c->d_route);
+    (void)hipFree(c->d_spill);
+    c->d_spill = nullptr;
     (void)hipFree(c->d_scratch);
     c->d_table = nullptr;
     c->d_work = nullptr;
@@ -236,6 +239,8 @@ int ensure_capacity(recon_ctx *c, size_t n_tasks, size_t n_blocks, size_t area_b
         hipMalloc(&c->d_tile_pending, nt * sizeof(uint32_t)) != hipSuccess ||
         hipMalloc(&c->d_tile_done, nt * sizeof(uint32_t)) != hipSuccess ||
         hipMalloc(&c->d_route, rk::ROUTE_WORDS * nt * sizeof(uint32_t)) != hipSuccess ||
+        (c->cfg.spill_capacity > 0 &&
+         hipMalloc(&c->d_spill, (size_t)rk::MAX_DRAIN_GRID * c->cfg.spill_capacity * sizeof(uint16_t)) != hipSuccess) ||
         (ns > 0 && hipMalloc(&c->d_scratch, ns) != hipSuccess)) {
         free_workspace(c);
         return fail(RECON_ENOMEM, "workspace allocation (%zu tasks, %zu blocks, %zu scratch bytes) failed",
@@ -372,12 +377,13 @@ struct Workspace {
     uint32_t *tile_pending;
     uint32_t *tile_done;
     uint32_t *route;     // mask classification words (null: no task takes the component route)
+    uint16_t *spill;     // spill queues, MAX_DRAIN_GRID x spill_cap entries (null: none)
     size_t cap_blocks;   // blocks the state words and the ring hold
 };
 
 Workspace ctx_workspace(const recon_ctx *c) {
     return Workspace{c->d_work, c->d_state, c->d_ring, c->d_tile_pending, c->d_tile_done, c->d_route,
-                     c->cap_blocks};
+                     c->d_spill, c->cap_blocks};
 }
 
 // Enqueue the kernels of one launch sequence on `s`.
@@ -402,6 +408,8 @@ int enqueue_kernels(recon_ctx *c, const Workspace &ws, int v, const rk::TaskTabl
     ka.test_fault = c->cfg.test_fault;
     ka.route = route ? ws.route : nullptr;
     ka.route_policy = c->cfg.component_route == 1 ? 1 : 0;
+    ka.spill = ws.spill;
+    ka.spill_cap = ws.spill ? (uint32_t)c->cfg.spill_capacity : 0u;
     const size_t lds = lds_for(v, c->cfg.queue_capacity);
     const int resident = resident_wgs(c, v);
     // K1/K2 are grid-stride: with sizes known only on the device (captured
@@ -858,6 +866,10 @@ int recon_create(recon_ctx **out, int device, const recon_config *cfg) {
     if (c.wg_per_cu < 0) return fail(RECON_EINVAL, "wg_per_cu must be >= 0");
     if (c.stop_after_stage < 0 || c.stop_after_stage > 3) return fail(RECON_EINVAL, "stop_after_stage must be 0..3");
     if (c.test_fault < 0 || c.test_fault > 1) return fail(RECON_EINVAL, "test_fault must be 0 or 1");
+    if (c.spill_capacity == 0) c.spill_capacity = 8192;
+    if (c.spill_capacity < -1 || (c.spill_capacity > 0 && (c.spill_capacity < 64 || c.spill_capacity > 65536)))
+        return fail(RECON_EINVAL, "spill_capacity must be -1 (none), 0 (default 8192) or 64..65536");
+    if (c.spill_capacity < 0) c.spill_capacity = 0;
     if (c.component_route < -1 || c.component_route > 1)
         return fail(RECON_EINVAL, "component_route must be 0 (where it pays), 1 (every two-valued mask) or -1 (off)");
     if (c.serve_mem_cap < 0 || c.serve_slots < 0) return fail(RECON_EINVAL, "serving limits must be >= 0");
@@ -966,6 +978,7 @@ int recon_dilate_noalloc(recon_ctx *ctx, recon_image *marker, const recon_image 
     ws.state = (uint32_t *)(base + NOALLOC_STATE_OFF);
     ws.ring = (uint32_t *)(base + NOALLOC_RING_OFF);
     ws.route = nullptr;   // no label plane: the block route only
+    ws.spill = nullptr;   // no spill queues: a full LDS queue re-seeds the block
     ws.cap_blocks = total_blocks;
     rk::TaskTable tt{};
     tt.hdr = nullptr;
@@ -1324,6 +1337,7 @@ int recon_last_stats(recon_ctx *ctx, recon_stats *out) {
     out->requests = (int64_t)w.stat_request;
     out->aborted = (int64_t)w.abort;
     out->component_tasks = (int64_t)w.stat_route;
+    out->queue_spills = (int64_t)w.stat_spill;
     if (ctx->cfg.timing) {
         float t[5];
         launch_times(ctx, 0, t);

@@ -32,7 +32,7 @@ TWO_PLANE = ("dilate", "erode")
 
 
 def run(exe, tasks, bh=32, qcap=2048, scan_rounds=2, n_waves=4, watchdog_s=20.0, timeout=600, stop_after=0,
-        test_fault=0, component=0):
+        test_fault=0, component=0, spill=0):
     """tasks: list of dicts {op, marker+mask (dilate, erode) or img (fill_holes,
     hdome, regional_max), conn, h (hdome)}.
     Returns (returncode, outputs, stdout+stderr)."""
@@ -51,7 +51,7 @@ def run(exe, tasks, bh=32, qcap=2048, scan_rounds=2, n_waves=4, watchdog_s=20.0,
                                                       img.shape[0], img.shape[1], ip, mp, op))
         env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1",
                    UBSAN_OPTIONS="print_stacktrace=1", KEMU_TEST_FAULT=str(int(test_fault)),
-                   KEMU_COMPONENT=str(int(component)))
+                   KEMU_COMPONENT=str(int(component)), KEMU_SPILL=str(int(spill)))
         p = subprocess.run([exe, str(bh), str(qcap), str(scan_rounds), str(n_waves), str(watchdog_s),
                             str(len(tasks)), str(stop_after)], input="\n".join(lines) + "\n", capture_output=True,
                            text=True, timeout=timeout, env=env)

@@ -373,7 +373,7 @@ struct EmuTask {
 };
 
 struct EmuStats {
-    int64_t dense, revisit, rerun, overflow, aborted, route;
+    int64_t dense, revisit, rerun, overflow, aborted, route, spill;
 };
 
 int emu_run(const EmuTask *tasks, int n, int bh, int qcap, int scan_rounds, int n_waves,
@@ -496,6 +496,12 @@ int emu_run(const EmuTask *tasks, int n, int bh, int qcap, int scan_rounds, int 
     ka.binary_drain_budget = 4;
     ka.route = route;
     ka.route_policy = component_mode == 1 ? 1 : 0;
+    // global spill queues (KEMU_SPILL = entries per wave; unset or 0: none), exact size
+    const char *se = std::getenv("KEMU_SPILL");
+    const uint32_t spill_cap = se ? (uint32_t)std::atoi(se) : 0u;
+    std::vector<uint16_t> spill_mem((size_t)n_waves * spill_cap + 1);
+    ka.spill = spill_cap ? spill_mem.data() : nullptr;
+    ka.spill_cap = spill_cap;
     {   // test hook of the block claims (see KArgs::test_fault)
         const char *f = std::getenv("KEMU_TEST_FAULT");
         ka.test_fault = f ? std::atoi(f) : 0;
@@ -584,6 +590,7 @@ int emu_run(const EmuTask *tasks, int n, int bh, int qcap, int scan_rounds, int 
         stats->overflow = (int64_t)work->stat_overflow;
         stats->aborted = (int64_t)work->abort;
         stats->route = (int64_t)work->stat_route;
+        stats->spill = (int64_t)work->stat_spill;
     }
     const bool full = stop_after == 0 || stop_after >= 3;
     const int rc = bad ? -2 : (work->abort ? -3 : (full && work->pending != 0 ? -4 : 0));
@@ -679,9 +686,9 @@ int main(int argc, char **argv) {
         std::fwrite(imgs[k].data(), 1, imgs[k].size(), f);
         std::fclose(f);
     }
-    std::printf("rc %d dense %lld revisit %lld rerun %lld overflow %lld aborted %lld route %lld\n", rc,
+    std::printf("rc %d dense %lld revisit %lld rerun %lld overflow %lld aborted %lld route %lld spill %lld\n", rc,
                 (long long)st.dense, (long long)st.revisit, (long long)st.rerun, (long long)st.overflow,
-                (long long)st.aborted, (long long)st.route);
+                (long long)st.aborted, (long long)st.route, (long long)st.spill);
     return rc == 0 ? 0 : 1;
 }
 #endif

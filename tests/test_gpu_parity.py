@@ -188,6 +188,7 @@ def test_unaligned_pitch_and_offset(torch_mod, rc, oracle_mod):
 
 
 @pytest.mark.parametrize("cfg", [dict(block_rows=16), dict(block_rows=64), dict(queue_capacity=64),
+                                 dict(queue_capacity=64, spill_capacity=-1), dict(queue_capacity=64, spill_capacity=64),
                                  dict(scan_rounds=-1), dict(scan_rounds=4, block_rows=64),
                                  dict(wg_per_cu=1), dict(stop_after_stage=3),
                                  dict(drain_budget=1, binary_drain_budget=1),
@@ -351,3 +352,22 @@ def test_failed_claims_report_edevice(torch_mod, lib):
         with pytest.raises(lib.ReconError) as e:
             ctx.last_stats()
         assert e.value.code == lib.RECON_EDEVICE
+
+
+def test_spill_queue_takes_the_overflow(torch_mod, lib, oracle_mod):
+    """With a 64-entry LDS queue, pushes that do not fit go to the wave's
+    global spill queue, and the block re-seeds only when that is full too;
+    without the spill every LDS overflow re-seeds.  Bytes equal the oracle's
+    both ways."""
+    marker, mask, _ = synth.config2_tile(seed=synth.seed_for(2, 42), size=1024, n_gauss=188)
+    want = oracle_mod.recon_dilate(marker, mask, 4)
+    seen = {}
+    for spill in (0, -1):
+        with lib.Recon(0, queue_capacity=64, scan_rounds=-1, spill_capacity=spill) as ctx:
+            m, k = dev(torch_mod, marker), dev(torch_mod, mask)
+            ctx.dilate(m, k, 4)
+            seen[spill] = ctx.last_stats()
+            assert_same(m.cpu().numpy(), want, "queue 64, spill %d" % spill)
+    assert seen[0]["queue_spills"] > 0, seen[0]
+    assert seen[-1]["queue_spills"] == 0 and seen[-1]["queue_overflows"] > 0, seen[-1]
+    assert seen[0]["queue_overflows"] < seen[-1]["queue_overflows"], (seen[0], seen[-1])

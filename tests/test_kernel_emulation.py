@@ -268,3 +268,27 @@ def test_component_route_policy(emu_exe, oracle_mod):
     assert _route_count(log) == 1, log[-500:]
     log = _check(emu_exe, oracle_mod, [grey, thick], n_waves=3, component=2)
     assert _route_count(log) == 0, log[-500:]
+
+
+def _stat(log, name):
+    return int(log.split(" %s " % name)[1].split()[0])
+
+
+@pytest.mark.parametrize("spill", [8192, 64])
+def test_spill_queue(emu_exe, oracle_mod, spill):
+    """A 64-entry LDS queue with the global spill queue under it: with a large
+    spill, pushes that do not fit the LDS ring go to the spill and come back
+    through the drain, with no re-seed; with a 64-entry spill both fill up and
+    the block re-seeds.  The bytes equal the oracle's either way."""
+    rng = np.random.default_rng(7000 + spill)
+    mask = rng.integers(0, 256, (70, 270)).astype(np.uint8)
+    tasks = [{"op": "dilate", "marker": synth.hdome_marker(mask, 40), "mask": mask, "conn": 8},
+             {"op": "dilate", "marker": synth.hdome_marker(mask, 40), "mask": mask, "conn": 4},
+             {"op": "fill_holes", "img": np.where(rng.random((60, 300)) < 0.6, 255, 0).astype(np.uint8),
+              "conn": 4}]
+    log = _check(emu_exe, oracle_mod, tasks, qcap=64, scan_rounds=0, n_waves=3, spill=spill)
+    assert _stat(log, "spill") > 0, log[-300:]
+    if spill == 8192:
+        assert _stat(log, "overflow") == 0, log[-300:]
+    else:
+        assert _stat(log, "overflow") > 0, log[-300:]
