@@ -310,6 +310,21 @@ int recon_wait(recon_ctx *ctx, uint64_t ticket, int64_t timeout_us);
 /* Stop the request loop after the admitted work has drained. */
 int recon_serve_stop(recon_ctx *ctx);
 
+/* Counters of the request loop since it started (all 0 before the first
+ * recon_submit): launches made, requests launched, the most requests one
+ * launch held, the most lanes running at once, and the tickets completed
+ * before their launch ended (a reconstruction by dilation completes as soon
+ * as its own last block visit has, Sec. III-B's per-instance completion
+ * notice; the other operations map their result at the end of the launch). */
+typedef struct {
+    int64_t launches;
+    int64_t requests;
+    int64_t max_batch;
+    int64_t max_busy_lanes;
+    int64_t early_completions;
+} recon_serve_counters;
+int recon_serve_stats(recon_ctx *ctx, recon_serve_counters *out);
+
 /* Statistics of the last completed recon_dilate / recon_fill_holes /
  * recon_erode / recon_hdome / recon_regional_max / recon_batch launch (synchronises with it).  Returns RECON_EDEVICE if that
  * launch was stopped by the scheduler watchdog (no block visit completed for

@@ -32,7 +32,7 @@ EXPORTED = (
     "recon_create", "recon_destroy", "recon_dilate", "recon_dilate_noalloc", "recon_fill_holes", "recon_erode",
     "recon_hdome", "recon_regional_max", "recon_label", "recon_area_threshold", "recon_distance",
     "recon_pre_watershed", "recon_batch",
-    "recon_submit", "recon_poll", "recon_wait", "recon_serve_stop", "recon_last_stats",
+    "recon_submit", "recon_poll", "recon_wait", "recon_serve_stop", "recon_serve_stats", "recon_last_stats",
     "recon_launch_times", "recon_last_error",
 )
 
@@ -82,6 +82,11 @@ class recon_stats(ctypes.Structure):
                 ("queue_spills", ctypes.c_int64)]
 
 
+class recon_serve_counters(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64), ("requests", ctypes.c_int64), ("max_batch", ctypes.c_int64),
+                ("max_busy_lanes", ctypes.c_int64), ("early_completions", ctypes.c_int64)]
+
+
 _lib = None
 
 
@@ -114,6 +119,7 @@ def load_library(path: str = LIB_PATH):
     lib.recon_poll.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int)]
     lib.recon_wait.argtypes = [P, ctypes.c_uint64, ctypes.c_int64]
     lib.recon_serve_stop.argtypes = [P]
+    lib.recon_serve_stats.argtypes = [P, ctypes.POINTER(recon_serve_counters)]
     lib.recon_last_stats.argtypes = [P, ctypes.POINTER(recon_stats)]
     F = ctypes.POINTER(ctypes.c_float)
     lib.recon_launch_times.argtypes = [P, ctypes.c_int, F, F, F, F, F]
@@ -284,6 +290,12 @@ def recon_serve_stop(ctx: int) -> None:
     _check(load_library().recon_serve_stop(ctx))
 
 
+def recon_serve_stats(ctx: int) -> dict:
+    s = recon_serve_counters()
+    _check(load_library().recon_serve_stats(ctx, ctypes.byref(s)))
+    return {f: getattr(s, f) for f, _ in recon_serve_counters._fields_}
+
+
 def recon_launch_times(ctx: int, back: int = 0) -> dict:
     """Kernel durations (ms) of a recent launch: back = 0 the last, up to 63."""
     t = [ctypes.c_float() for _ in range(5)]
@@ -406,6 +418,9 @@ class Recon:
 
     def serve_stop(self):
         recon_serve_stop(self.ctx)
+
+    def serve_stats(self) -> dict:
+        return recon_serve_stats(self.ctx)
 
     def last_stats(self) -> dict:
         return recon_last_stats(self.ctx)

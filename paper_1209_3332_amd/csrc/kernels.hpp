@@ -165,6 +165,8 @@ struct KArgs {
     int32_t route_policy;        // 0: the component route where it pays (auto); 1: for every two-valued mask
     uint16_t *spill;             // global spill queues: spill_cap entries per wave of the grid (null: none)
     uint32_t spill_cap;
+    uint32_t launch_seq;         // this launch's number (serving: written into host_done)
+    uint32_t *host_done;         // host-visible per-task completion words (null: none)
 };
 
 // Route words of a task: [0] OR and [1] AND of its nonzero mask values (the
@@ -1692,8 +1694,15 @@ __global__ __launch_bounds__(64) void revisit_drain(TaskTable tt, KArgs a) {
                                                              __HIP_MEMORY_SCOPE_AGENT);
                 const uint32_t all = __hip_atomic_fetch_sub(&w->pending, 1u, __ATOMIC_RELAXED,
                                                             __HIP_MEMORY_SCOPE_AGENT);
-                if (left == 1u)
+                if (left == 1u) {
                     __hip_atomic_store(a.tile_done + ti, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    // the task's last visit: every visit of it wrote its blocks back
+                    // and waited for the stores before its count went down, so the
+                    // host may take the result now (serving completes the ticket
+                    // without waiting for the rest of the launch)
+                    if (a.host_done)
+                        __hip_atomic_store(a.host_done + ti, a.launch_seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+                }
                 last = all == 1u;
             }
         }

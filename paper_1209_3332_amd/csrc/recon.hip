@@ -168,6 +168,11 @@ struct recon_ctx {
     struct Serve;
     Serve *serve = nullptr;
     bool is_lane = false;   // a serving lane's private context
+    // serving lanes: host-visible completion word per task of a launch (the
+    // revisit kernel writes the launch number there when the task's last
+    // visit completes) and the number of the lane's current launch
+    uint32_t *h_done = nullptr;
+    uint32_t launch_seq = 0;
 };
 
 namespace {
@@ -410,6 +415,8 @@ int enqueue_kernels(recon_ctx *c, const Workspace &ws, int v, const rk::TaskTabl
     ka.route_policy = c->cfg.component_route == 1 ? 1 : 0;
     ka.spill = ws.spill;
     ka.spill_cap = ws.spill ? (uint32_t)c->cfg.spill_capacity : 0u;
+    ka.launch_seq = c->launch_seq;
+    ka.host_done = dynamic_sizes ? nullptr : c->h_done;   // (never inside a captured graph)
     const size_t lds = lds_for(v, c->cfg.queue_capacity);
     const int resident = resident_wgs(c, v);
     // K1/K2 are grid-stride: with sizes known only on the device (captured
@@ -527,6 +534,7 @@ int run_tasks(recon_ctx *c, const recon_task *tasks, int n, hipStream_t stream, 
         if (lab_off[k] != SIZE_MAX) d.lab = (int32_t *)(c->d_scratch + lab_off[k]);
     }
 
+    c->launch_seq += 1;   // numbers the launch (serving lanes: the value the kernel reports per task)
     rk::TaskTable tt{};
     const bool inline_table = !use_graph && n <= rk::MAX_INLINE_TASKS;
     if (inline_table) {
@@ -717,12 +725,14 @@ struct recon_ctx::Serve {
         uint64_t ticket;
         recon_task task;
         size_t bytes;
+        bool finished = false;   // completed before its launch ended (its own tile converged)
     };
     struct Lane {
         recon_ctx *sub = nullptr;
         hipStream_t stream = nullptr;
         hipEvent_t done = nullptr;
         std::vector<Req> reqs;
+        uint32_t seq = 0;        // the launch number its tasks' completion words will show
         bool busy = false;
     };
     std::mutex mu;
@@ -731,7 +741,9 @@ struct recon_ctx::Serve {
     std::unordered_map<uint64_t, int> status;   // 0 waiting, 1 running, 2 done, -1 failed
     uint64_t next_ticket = 1;
     size_t bytes_admitted = 0;
+    size_t bytes_fixed = 0;      // the lanes' own resident workspace, counted against the cap
     int slots_admitted = 0;
+    recon_serve_counters stats{};
     bool stop = false;
     int error = RECON_OK;
     std::string error_msg;
@@ -748,12 +760,25 @@ void serve_loop(recon_ctx *ctx) {
     std::unique_lock<std::mutex> lk(S->mu);
     while (true) {
         bool any_busy = false;
-        // harvest finished lanes
+        // harvest finished lanes, and single tasks that finished inside a running launch
         for (auto &L : S->lanes) {
             if (!L.busy) continue;
             const hipError_t q = hipEventQuery(L.done);
             if (q == hipErrorNotReady) {
                 any_busy = true;
+                const volatile uint32_t *hd = L.sub->h_done;
+                for (size_t i = 0; i < L.reqs.size(); ++i) {
+                    recon_ctx::Serve::Req &r = L.reqs[i];
+                    // a reconstruction by dilation is complete when its last visit
+                    // is (other operations still map their result at the end)
+                    if (r.finished || r.task.op != RECON_OP_DILATE || hd[i] != L.seq) continue;
+                    r.finished = true;
+                    S->status[r.ticket] = 2;
+                    S->bytes_admitted -= r.bytes;
+                    S->slots_admitted -= 1;
+                    S->stats.early_completions += 1;
+                    S->cv_done.notify_all();
+                }
                 continue;
             }
             const int st = q == hipSuccess ? 2 : -1;
@@ -762,9 +787,12 @@ void serve_loop(recon_ctx *ctx) {
                 S->error_msg = std::string("serving launch failed: ") + hipGetErrorString(q);
             }
             for (auto &r : L.reqs) {
+                if (r.finished && st == 2) continue;   // completed already
                 S->status[r.ticket] = st;
-                S->bytes_admitted -= r.bytes;
-                S->slots_admitted -= 1;
+                if (!r.finished) {
+                    S->bytes_admitted -= r.bytes;
+                    S->slots_admitted -= 1;
+                }
             }
             L.reqs.clear();
             L.busy = false;
@@ -783,6 +811,7 @@ void serve_loop(recon_ctx *ctx) {
                 S->status[r.ticket] = 1;
             }
             int rc = run_tasks(L.sub, tasks.data(), (int)tasks.size(), L.stream, false);
+            L.seq = L.sub->launch_seq;
             if (rc == RECON_OK && hipEventRecord(L.done, L.stream) != hipSuccess) rc = RECON_EDEVICE;
             if (rc != RECON_OK) {
                 S->error = rc;
@@ -798,7 +827,13 @@ void serve_loop(recon_ctx *ctx) {
             }
             L.busy = true;
             any_busy = true;
+            S->stats.launches += 1;
+            S->stats.requests += (int64_t)L.reqs.size();
+            S->stats.max_batch = std::max<int64_t>(S->stats.max_batch, (int64_t)L.reqs.size());
         }
+        int busy_now = 0;
+        for (auto &L : S->lanes) busy_now += L.busy ? 1 : 0;
+        S->stats.max_busy_lanes = std::max<int64_t>(S->stats.max_busy_lanes, busy_now);
         if (S->stop && S->waiting.empty() && !any_busy) break;
         if (any_busy)
             S->cv_work.wait_for(lk, std::chrono::microseconds(20));
@@ -817,6 +852,13 @@ int serve_start(recon_ctx *ctx) {
         int rc = make_ctx(&L.sub, ctx->device, c);
         if (rc == RECON_OK) {
             L.sub->is_lane = true;
+            if (hipHostMalloc((void **)&L.sub->h_done, recon_ctx::Serve::kMaxPerLaunch * sizeof(uint32_t),
+                              hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess)
+                rc = fail(RECON_ENOMEM, "serving lane completion words: pinned allocation failed");
+            else
+                std::memset(L.sub->h_done, 0, recon_ctx::Serve::kMaxPerLaunch * sizeof(uint32_t));
+        }
+        if (rc == RECON_OK) {
             if (hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking) != hipSuccess ||
                 hipEventCreateWithFlags(&L.done, hipEventDisableTiming) != hipSuccess)
                 rc = fail(RECON_EDEVICE, "serving lane stream/event creation failed");
@@ -831,6 +873,11 @@ int serve_start(recon_ctx *ctx) {
             return rc;
         }
     }
+    // the lanes' resident workspace (spill queues, scheduler state for the
+    // largest launch) counts against the admission cap too
+    S->bytes_fixed = (size_t)recon_ctx::Serve::kLanes *
+                     ((size_t)rk::MAX_DRAIN_GRID * (size_t)std::max(0, c.spill_capacity) * sizeof(uint16_t) +
+                      ((size_t)4096 + (size_t)rk::MAX_DRAIN_GRID) * 256);
     ctx->serve = S;
     S->worker = std::thread(serve_loop, ctx);
     return RECON_OK;
@@ -916,6 +963,7 @@ int recon_destroy(recon_ctx *ctx) {
     free_workspace(ctx);
     if (ctx->h_table) (void)hipHostFree(ctx->h_table);
     if (ctx->h_work) (void)hipHostFree(ctx->h_work);
+    if (ctx->h_done) (void)hipHostFree(ctx->h_done);
     if (ctx->table_used) (void)hipEventDestroy(ctx->table_used);
     if (ctx->last_done) (void)hipEventDestroy(ctx->last_done);
     for (auto &set : ctx->tev)
@@ -1389,9 +1437,10 @@ int recon_submit(recon_ctx *ctx, const recon_task *task, uint64_t *ticket) {
     {
         std::lock_guard<std::mutex> lk(S->mu);
         if (S->stop) return fail(RECON_EINVAL, "serving has been stopped");
-        if ((int64_t)bytes > ctx->cfg.serve_mem_cap)
+        if ((int64_t)(bytes + S->bytes_fixed) > ctx->cfg.serve_mem_cap)
             return fail(RECON_EINVAL, "task needs %zu bytes, above the admission cap", bytes);
-        if ((int64_t)(S->bytes_admitted + bytes) > ctx->cfg.serve_mem_cap || S->slots_admitted >= ctx->cfg.serve_slots)
+        if ((int64_t)(S->bytes_fixed + S->bytes_admitted + bytes) > ctx->cfg.serve_mem_cap ||
+            S->slots_admitted >= ctx->cfg.serve_slots)
             return fail(RECON_EAGAIN, "admission full (%zu bytes, %d slots in flight)", S->bytes_admitted,
                         S->slots_admitted);
         const uint64_t tk = S->next_ticket++;
@@ -1450,6 +1499,16 @@ int recon_wait(recon_ctx *ctx, uint64_t ticket, int64_t timeout_us) {
             S->cv_done.wait_until(lk, std::min(deadline, std::chrono::steady_clock::now() + std::chrono::milliseconds(10)));
         }
     }
+}
+
+int recon_serve_stats(recon_ctx *ctx, recon_serve_counters *out) {
+    if (!ctx || !out) return fail(RECON_EINVAL, "null argument");
+    std::memset(out, 0, sizeof(*out));
+    recon_ctx::Serve *S = ctx->serve;
+    if (!S) return RECON_OK;
+    std::lock_guard<std::mutex> lk(S->mu);
+    *out = S->stats;
+    return RECON_OK;
 }
 
 int recon_serve_stop(recon_ctx *ctx) {

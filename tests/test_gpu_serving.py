@@ -38,12 +38,13 @@ def _task(rng, i):
 
 
 def _submit_all(torch_mod, ctx, tasks, lib, timeout_s=60.0):
+    # every image is uploaded first (one synchronisation), then the requests go
+    # in a burst, so that they arrive while earlier ones are on the GPU
     bufs, tickets = [], []
     for t in tasks:
-        m = torch_mod.from_numpy(t["marker"]).cuda()
-        k = torch_mod.from_numpy(t["mask"]).cuda()
-        torch_mod.cuda.synchronize()
-        bufs.append((m, k))
+        bufs.append((torch_mod.from_numpy(t["marker"]).cuda(), torch_mod.from_numpy(t["mask"]).cuda()))
+    torch_mod.cuda.synchronize()
+    for t, (m, k) in zip(tasks, bufs):
         deadline = time.time() + timeout_s
         while True:
             try:
@@ -70,6 +71,42 @@ def test_alone_and_in_the_mix(torch_mod, lib, oracle_mod):
         assert np.array_equal(outs[11], alone)
         for i, (t, got) in enumerate(zip(mix, outs)):
             assert np.array_equal(got, oracle_mod.run_task(t)), "request %d" % i
+        st = ctx.serve_stats()
+        # the requests overlapped on the device: some launch held several of them
+        # or several lanes ran at once
+        assert st["requests"] == 31 and (st["max_batch"] > 1 or st["max_busy_lanes"] > 1), st
+        ctx.serve_stop()
+
+
+def test_tickets_complete_with_their_own_tile(torch_mod, lib, oracle_mod):
+    """A launch holding large and small reconstructions completes each ticket
+    when its own tile converges: small tiles do not wait for the large ones
+    (counted as early completions), and every result equals the oracle."""
+    rng = np.random.default_rng(99)
+    big = []
+    for i in range(3):
+        mask = synth.scaled_config1_tile(2048, 2048, 9500 + i)
+        big.append({"op": "dilate", "marker": synth.hdome_marker(mask, 20), "mask": mask, "conn": 8})
+    small = [_task(rng, 200 + i) for i in range(40)]
+    tasks = [big[0], big[1], big[2]] + small
+    with lib.Recon(0) as ctx:
+        bufs = [(torch_mod.from_numpy(t["marker"]).cuda(), torch_mod.from_numpy(t["mask"]).cuda()) for t in tasks]
+        torch_mod.cuda.synchronize()
+        tickets = [ctx.submit("dilate", m, k, t["conn"]) for t, (m, k) in zip(tasks, bufs)]
+        # each result is copied out the moment its own ticket completes, while
+        # the rest of its launch may still run on the device
+        got = [None] * len(tasks)
+        deadline = time.time() + 60
+        while any(g is None for g in got):
+            assert time.time() < deadline, "tickets did not complete"
+            for i, tk in enumerate(tickets):
+                if got[i] is None and ctx.poll(tk):
+                    got[i] = bufs[i][0].cpu().numpy()
+        st = ctx.serve_stats()
+        for i, t in enumerate(tasks):
+            assert np.array_equal(got[i], oracle_mod.run_task(t)), "request %d" % i
+        assert st["max_batch"] > 1, st
+        assert st["early_completions"] > 0, st
         ctx.serve_stop()
 
 
