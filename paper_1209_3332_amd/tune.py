@@ -9,12 +9,15 @@ each size bucket.
 
 measures every combination on synthetic nuclei-like tiles of each size bucket
 and connectivity (timed with HIP events around the launch) and writes a JSON
-cache keyed by the GPU's architecture.  `tuned_batch()` applies a cache to a
-list of tasks.
+cache keyed by the GPU's architecture, stamped with a hash of the kernel
+source and the HIP runtime version it was measured on: a cache taken on other
+kernels or another runtime is ignored (defaults apply) until the tuner runs
+again.  `tuned_batch()` applies a cache to a list of tasks.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import itertools
 import json
 import os
@@ -31,6 +34,31 @@ SCAN_ROUNDS = (1, 2, 3, 4)
 BUCKETS = (("small", 1 << 20, 768), ("medium", 6 << 20, 2048), ("large", 1 << 62, 4096))
 
 
+KERNEL_SOURCES = ("kernels.hpp", "component.hpp", "label.hpp", "recon.hip")
+
+
+def kernel_sha() -> str:
+    """Hash of the device code the tuning depends on."""
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(HERE, "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def runtime_version() -> str:
+    import torch
+    return str(getattr(torch.version, "hip", None) or "unknown")
+
+
+def cache_valid(cache: dict, runtime: str | None = None) -> bool:
+    """True if the cache was measured on the current kernels (and, when
+    `runtime` is given, on that HIP runtime)."""
+    if not cache or cache.get("kernel_sha") != kernel_sha():
+        return False
+    return runtime is None or cache.get("hip_runtime") == runtime
+
+
 def bucket_of(h: int, w: int) -> str:
     area = h * w
     for name, limit, _ in BUCKETS:
@@ -39,11 +67,14 @@ def bucket_of(h: int, w: int) -> str:
     return BUCKETS[-1][0]
 
 
-def load_cache(path: str = DEFAULT_CACHE) -> dict:
-    if os.path.exists(path):
-        with open(path) as f:
-            return json.load(f)
-    return {}
+def load_cache(path: str = DEFAULT_CACHE, check_runtime: bool = True) -> dict:
+    """The tuning cache, or {} when there is none or it was measured on other
+    kernel source or another HIP runtime."""
+    if not os.path.exists(path):
+        return {}
+    with open(path) as f:
+        cache = json.load(f)
+    return cache if cache_valid(cache, runtime_version() if check_runtime else None) else {}
 
 
 def _arch() -> str:
@@ -121,7 +152,7 @@ def tune(reps: int = 3, n_px_target: int = 48 << 20, log=print) -> dict:
             best[1]["mpx_s"] = px / best[0] / 1e3
             result["%s/conn%d" % (bucket, conn)] = best[1]
             log("%s conn%d: %s" % (bucket, conn, best[1]))
-    return {"arch": _arch(), _arch(): result}
+    return {"arch": _arch(), _arch(): result, "kernel_sha": kernel_sha(), "hip_runtime": runtime_version()}
 
 
 def main():

@@ -27,3 +27,16 @@ def test_tuned_batch_picks_per_bucket():
     assert qmax == 8192                  # the context sizes LDS for the largest queue
     assert (out[0]["scan_rounds"], out[0]["queue_capacity"]) == (1, 512)
     assert (out[1]["scan_rounds"], out[1]["queue_capacity"]) == (4, 8192)
+
+
+def test_cache_is_stamped_and_stale_caches_are_ignored(tmp_path):
+    import json
+    good = {"arch": "gfx950", "gfx950": {}, "kernel_sha": tune.kernel_sha(), "hip_runtime": "x"}
+    stale = dict(good, kernel_sha="0000000000000000")
+    assert tune.cache_valid(good) and tune.cache_valid(good, "x") and not tune.cache_valid(good, "y")
+    assert not tune.cache_valid(stale) and not tune.cache_valid({})
+    p = tmp_path / "c.json"
+    p.write_text(json.dumps(stale))
+    assert tune.load_cache(str(p), check_runtime=False) == {}
+    p.write_text(json.dumps(good))
+    assert tune.load_cache(str(p), check_runtime=False) == good
