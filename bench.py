@@ -54,13 +54,18 @@ def percentile(xs, q):
     return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
 
 
-KERNEL_SOURCE = os.path.join(ROOT, "paper_1209_3332_amd", "csrc", "kernels.hpp")
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "revisit_drain_4k_nuclei_traffic.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1209_3332_amd", "csrc", f)
+                  for f in ("kernels.hpp", "component.hpp", "label.hpp", "recon.hip")]
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "revisit_drain_hbm_traffic.md")
 
 
 def kernel_sha():
-    with open(KERNEL_SOURCE, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Hash of the device code and its launch configuration (the library's sources)."""
+    h = hashlib.sha256()
+    for path in KERNEL_SOURCES:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def committed_traffic(kernel):
@@ -473,7 +478,20 @@ def distance(recon, torch, binary, steps, conn=8):
     return res
 
 
-def batched_vs_per_tile(recon, torch, ctx_cfg, n_tiles, size, workers, spiral_size):
+def batch_roofline(name, px, launch_ms):
+    """Roofline of a batched launch: the method's bytes (3 B/px per reconstruction)
+    over the launch, and the counted HBM bytes of its revisit kernel when the
+    committed counter summary covers this section on the current kernels."""
+    alg = BYTES_DILATE * px
+    achieved = alg / (launch_ms * 1e-3) / 1e9
+    traffic = committed_traffic("revisit_drain (%s)" % name)
+    return {"bound": "hbm", "algorithmic_bytes": alg, "launch_ms": launch_ms, "achieved": achieved,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "traffic_over_algorithmic": traffic / alg if traffic else None,
+            "counted_GBs_over_launch": traffic / (launch_ms * 1e-3) / 1e9 if traffic else None}
+
+
+def batched_vs_per_tile(recon, torch, ctx_cfg, n_tiles, size, workers, spiral_size, per_tile=True):
     """The 64-tile workload: one batched graph launch of all tiles against the
     same tiles as plain per-tile calls; also the 56 nuclei tiles alone and the 8
     spiral corridors alone as batched launches, so that the nuclei tiles'
@@ -508,6 +526,7 @@ def batched_vs_per_tile(recon, torch, ctx_cfg, n_tiles, size, workers, spiral_si
                           "revisits": st["revisits"], "component_tasks": st["component_tasks"]}
 
         work, res["batched"] = batched(every)
+        res["roofline"] = batch_roofline("64-tile batch", px_of(every), res["batched"]["launch_ms"])
         # a spiral corridor's reconstruction is its mask; nuclei tiles go to the oracle leg
         res["spirals_equal_mask"] = all(torch.equal(work[i], masks[i]) for i in spirals)
         res["parity_checked_tiles"] = [nuclei[j] for j in sorted({0, len(nuclei) // 3, 2 * len(nuclei) // 3,
@@ -524,6 +543,8 @@ def batched_vs_per_tile(recon, torch, ctx_cfg, n_tiles, size, workers, spiral_si
             res["spirals_equal_mask"] = res["spirals_equal_mask"] and all(torch.equal(w_s[i], masks[i])
                                                                            for i in spirals)
             del w_s
+        if not per_tile:
+            return res
         # per-tile: the same tiles as plain calls, one after another
         work = [p.clone() for p in pristine]
         torch.cuda.synchronize()
@@ -568,7 +589,7 @@ def uneven_pool(n_tiles, config, workers):
     return out
 
 
-def uneven_batched_vs_per_tile(recon, torch, n_tiles, workers):
+def uneven_batched_vs_per_tile(recon, torch, n_tiles, workers, per_tile_legs=True):
     """The uneven batch as one autotuned graph launch vs as plain per-tile calls."""
     from paper_1209_3332_amd import tune
     t0 = time.perf_counter()
@@ -594,8 +615,9 @@ def uneven_batched_vs_per_tile(recon, torch, n_tiles, workers):
             wall = time.perf_counter() - t
         st = ctx.last_stats()
         res["batched"] = {"Mpixel_s": px / wall / 1e6, "ms": wall * 1e3, "launch_ms": st["total_ms"],
-                          "queue_overflows": st["queue_overflows"], "revisits": st["revisits"],
-                          "reruns": st["reruns"]}
+                          "queue_overflows": st["queue_overflows"], "queue_spills": st["queue_spills"],
+                          "revisits": st["revisits"], "reruns": st["reruns"], "dense_visits": st["dense_visits"]}
+        res["roofline"] = batch_roofline("uneven batch", px, st["total_ms"])
         # parity on a stratified sample: two tiles of every size bucket and connectivity
         strata = {}
         for i, (j, m, c) in enumerate(tiles):
@@ -635,6 +657,8 @@ def uneven_batched_vs_per_tile(recon, torch, n_tiles, workers):
                 cx.close()
         return {"Mpixel_s": px / wall / 1e6, "ms": wall * 1e3}
 
+    if not per_tile_legs:
+        return res
     res["per_tile"] = per_tile(False)
     res["per_tile_tuned"] = per_tile(True)
     res["batched_over_per_tile"] = res["batched"]["Mpixel_s"] / res["per_tile"]["Mpixel_s"]
@@ -736,6 +760,8 @@ def main():
     ap.add_argument("--drain-budget", type=int, default=0, help="context knob (0 = library default)")
     ap.add_argument("--binary-drain-budget", type=int, default=0, help="context knob (0 = library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-per-tile", action="store_true",
+                    help="batch sections time the batched launches only (for counter runs)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only copy this many bytes device-to-device 5 times (counter calibration) and exit")
     ap.add_argument("--workers", type=int, default=min(16, len(os.sched_getaffinity(0))))
@@ -804,15 +830,16 @@ def main():
     if args.batch_tiles:
         out["batched_vs_per_tile"] = batched_vs_per_tile(recon, torch, {k: v for k, v in cfg.items()},
                                                          args.batch_tiles, args.size, args.workers,
-                                                         args.spiral_size)
+                                                         args.spiral_size, per_tile=not args.no_per_tile)
         b = out["batched_vs_per_tile"]
-        log("batch of %d: batched %.0f Mpixel/s vs per-tile %.0f Mpixel/s" % (
-            args.batch_tiles, b["batched"]["Mpixel_s"], b["per_tile"]["Mpixel_s"]))
+        log("batch of %d: batched %.0f Mpixel/s vs per-tile %s Mpixel/s" % (
+            args.batch_tiles, b["batched"]["Mpixel_s"], "%.0f" % b["per_tile"]["Mpixel_s"] if "per_tile" in b else "-"))
     if args.uneven_tiles:
-        out["uneven_batched_vs_per_tile"] = uneven_batched_vs_per_tile(recon, torch, args.uneven_tiles, args.workers)
+        out["uneven_batched_vs_per_tile"] = uneven_batched_vs_per_tile(recon, torch, args.uneven_tiles, args.workers,
+                                                                       per_tile_legs=not args.no_per_tile)
         u = out["uneven_batched_vs_per_tile"]
-        log("uneven batch of %d: batched %.0f Mpixel/s vs per-tile %.0f Mpixel/s" % (
-            args.uneven_tiles, u["batched"]["Mpixel_s"], u["per_tile"]["Mpixel_s"]))
+        log("uneven batch of %d: batched %.0f Mpixel/s vs per-tile %s Mpixel/s" % (
+            args.uneven_tiles, u["batched"]["Mpixel_s"], "%.0f" % u["per_tile"]["Mpixel_s"] if "per_tile" in u else "-"))
     if args.serve_rates:
         rates = [int(r) for r in args.serve_rates.split(",") if r]
         out["serving"] = serving(recon, torch, rates, args.serve_seconds, args.serve_pool, args.workers)
