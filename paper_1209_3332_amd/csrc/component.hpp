@@ -20,12 +20,16 @@
 //
 // Kernels (one 64-lane wave per workgroup, grid-stride over the blocks of all
 // tasks of the launch, in the scheduler's block numbering: a block of BH x 256
-// pixels is BH / 16 labelling tiles of 16 x 256, or BH rows of 256 pixels):
+// pixels is BH / 16 labelling tiles of 16 x 256, or BH rows of 256 pixels),
+// after reset_work has sampled every task's mask (sample_route):
 //   comp_classify     OR and AND of the nonzero (transformed) mask values of
-//                     every task, into two words per task; the task takes the
-//                     route when they are equal (one nonzero value) or the OR
-//                     is 0 (an all-zero mask).  A wave skips the rows of a task
-//                     already known to hold two different nonzero values;
+//                     every task, into two words per task: the mask is
+//                     two-valued when they are equal (one nonzero value) or the
+//                     OR is 0 (an all-zero mask).  A wave skips the rows of a
+//                     task already known to hold two different nonzero values.
+//                     The last workgroup decides every task's route
+//                     (decide_tasks), and prepare then fills the ring with the
+//                     blocks of the others;
 //   comp_label_local  tile-local labelling of {I != 0} (label.hpp's label_tile)
 //                     into the task's int32 label plane;
 //   comp_label_merge  unions across tile borders (merge_tile);
@@ -81,51 +85,6 @@ struct UnitWalk {
     }
 };
 
-// A first look at every task's mask: one wave per task samples 1024 pixels
-// spread over the image (16 rows of 64 columns) and records the OR and AND of
-// the nonzero values found.  A grey mask nearly always shows two different
-// nonzero values here, and the full classification then skips it whole.  The
-// samples also estimate how thin the foreground is: the share of sampled
-// foreground pixels that start a horizontal run (whose left neighbour is
-// background) -- about 1 / (mean run length); at least 1/32 counts as thin
-// (a corridor, noise), as does a sample without foreground.  A task without
-// a label plane, or a grey one, marks the launch as having block-route work.
-__global__ __launch_bounds__(64) void comp_sample(TaskTable tt, KArgs a) {
-    const int ln = lane_id();
-    const uint32_t n = n_tasks_of(tt);
-    for (uint32_t k = blockIdx.x; k < n; k += gridDim.x) {
-        const TaskDev t = task_of(tt, (int)k);
-        if (!t.lab) {
-            if (ln == 0) a.work->has_grey = 1u;
-            continue;
-        }
-        uint32_t o = 0, an = 0xffu, fg = 0, starts = 0;
-        for (int r = 0; r < 16; ++r) {
-            const int y = (int)(((int64_t)(2 * r + 1) * t.h) / 32);
-            const int x = (int)(((int64_t)(2 * ln + 1) * t.w) / 128);
-            const uint32_t b = mask1(t, y, x);
-            if (b) {
-                o |= b;
-                an &= b;
-                fg += 1;
-                if (x == 0 || mask1(t, y, x - 1) == 0u) starts += 1;
-            }
-        }
-        for (int d = 1; d < LANES; d <<= 1) {
-            o |= (uint32_t)__shfl_xor((int)o, d);
-            an &= (uint32_t)__shfl_xor((int)an, d);
-            fg += (uint32_t)__shfl_xor((int)fg, d);
-            starts += (uint32_t)__shfl_xor((int)starts, d);
-        }
-        if (ln == 0) {   // the task's words are still at their identities: no other writer yet
-            a.route[ROUTE_WORDS * k] = o;
-            a.route[ROUTE_WORDS * k + 1] = an;
-            a.route[ROUTE_WORDS * k + 4] = (fg == 0u || 32u * starts >= fg) ? 1u : 0u;
-            if (o != 0u && o != an) a.work->has_grey = 1u;
-        }
-    }
-}
-
 // Classification: one wave per block (grid-stride), the block's rows loaded
 // together; each lane keeps the OR and AND of its nonzero mask bytes, the
 // wave combines them once per task it leaves, and only a combination that
@@ -153,7 +112,7 @@ __global__ __launch_bounds__(64) void comp_classify(TaskTable tt, KArgs a) {
             const uint32_t ca = __hip_atomic_load(wa, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if ((ca & acc_and) != ca) __hip_atomic_fetch_and(wa, acc_and, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const uint32_t no = co | acc_or, na = ca & acc_and;
-            if (no != 0u && no != na) a.work->has_grey = 1u;   // this task is grey (any writer, same value)
+            if (no != 0u && no != na) a.work->has_grey = seq_of(tt);   // this task is grey (any writer, same value)
         }
         acc_or = 0;
         acc_and = 0xffu;
@@ -186,11 +145,18 @@ __global__ __launch_bounds__(64) void comp_classify(TaskTable tt, KArgs a) {
             }
     }
     flush();
+    // the last workgroup to finish decides every task's route (decide_tasks):
+    // the counter's acquire-release orders every workgroup's flush before it
+    __threadfence();
+    uint32_t prior = 0;
+    if (ln == 0)
+        prior = __hip_atomic_fetch_add(&a.work->classify_done, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (uniform(prior) + 1u == gridDim.x) decide_tasks(tt, a);
 }
 
 template <int BH>
 __global__ __launch_bounds__(64) void comp_label_local(TaskTable tt, KArgs a) {
-    if (!a.work->route_any) return;   // no task of the launch takes the route
+    if (a.work->route_any != seq_of(tt)) return;   // no task of the launch takes the route
     RK_LDS uint32_t *par = (RK_LDS uint32_t *)dyn_lds();
     constexpr int PER = BH / LT_H;
     const uint64_t n = (uint64_t)total_blocks_of(tt) * PER;
@@ -209,7 +175,7 @@ __global__ __launch_bounds__(64) void comp_label_local(TaskTable tt, KArgs a) {
 
 template <int BH>
 __global__ __launch_bounds__(64) void comp_label_merge(TaskTable tt, KArgs a) {
-    if (!a.work->route_any) return;   // no task of the launch takes the route
+    if (a.work->route_any != seq_of(tt)) return;   // no task of the launch takes the route
     constexpr int PER = BH / LT_H;
     const uint64_t n = (uint64_t)total_blocks_of(tt) * PER;
     UnitWalk wk;
@@ -239,7 +205,7 @@ __device__ __forceinline__ int32_t comp_find(const int32_t *lab, int32_t a) {
 
 template <int BH>
 __global__ __launch_bounds__(64) void comp_flatten_max(TaskTable tt, KArgs a) {
-    if (!a.work->route_any) return;   // no task of the launch takes the route
+    if (a.work->route_any != seq_of(tt)) return;   // no task of the launch takes the route
     const int ln = lane_id();
     const uint64_t n = (uint64_t)total_blocks_of(tt) * BH;
     UnitWalk wk;
@@ -308,7 +274,7 @@ __global__ __launch_bounds__(64) void comp_flatten_max(TaskTable tt, KArgs a) {
 
 template <int BH>
 __global__ __launch_bounds__(64) void comp_write(TaskTable tt, KArgs a) {
-    if (!a.work->route_any) return;   // no task of the launch takes the route
+    if (a.work->route_any != seq_of(tt)) return;   // no task of the launch takes the route
     const int ln = lane_id();
     const uint64_t n = (uint64_t)total_blocks_of(tt) * BH;
     UnitWalk wk;

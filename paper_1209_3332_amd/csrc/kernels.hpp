@@ -109,7 +109,8 @@ struct BatchHdr {
     uint32_t total_blocks;
     uint32_t ring_cap;
     uint32_t any_mapped;   // some task needs init_marker / finish_result
-    uint32_t pad[12];
+    uint32_t launch_seq;   // the launch's number (marks the per-launch flags of Work)
+    uint32_t pad[11];
 };
 
 // The task list of a launch: up to MAX_INLINE_TASKS tasks travel by value in
@@ -120,7 +121,7 @@ struct TaskTable {
     uint32_t n_inline;
     uint32_t total_inline;
     uint32_t ring_cap_inline;
-    uint32_t pad;
+    uint32_t seq_inline;
     TaskDev inl[MAX_INLINE_TASKS];
 };
 
@@ -144,9 +145,11 @@ struct Work {
     unsigned long long stat_request;
     unsigned long long stat_route;   // tasks reconstructed by the component route
     unsigned long long stat_spill;   // queue entries pushed to a global spill queue
-    uint32_t route_any;              // some task of the launch takes the component route
-    uint32_t has_grey;               // some task of the launch keeps the block route whatever it looks like
-    unsigned long long pad4[8];
+    uint32_t route_any;              // = the launch's number: some task takes the component route
+    uint32_t has_grey;               // = the launch's number: some task keeps the block route whatever it looks like
+    uint32_t classify_done;          // workgroups of the classification that have finished
+    uint32_t pad5[3];
+    unsigned long long pad4[6];
 };
 
 struct KArgs {
@@ -186,6 +189,10 @@ __device__ __forceinline__ uint32_t total_blocks_of(const TaskTable &tt) {
 }
 __device__ __forceinline__ uint32_t ring_cap_of(const TaskTable &tt) {
     return tt.hdr ? tt.hdr->ring_cap : tt.ring_cap_inline;
+}
+// the launch's number: Work flags holding it were set by this launch (no reset needed)
+__device__ __forceinline__ uint32_t seq_of(const TaskTable &tt) {
+    return tt.hdr ? tt.hdr->launch_seq : tt.seq_inline;
 }
 __device__ __forceinline__ uint32_t block0_of(const TaskTable &tt, int k) {
     return tt.hdr ? tt.ext[k].block0 : tt.inl[k].block0;
@@ -1732,10 +1739,52 @@ __global__ void copy_table(const uint8_t *src, uint8_t *dst, uint32_t bytes) {
 //   RESET_QUEUE_ALL  every block starts requested and in the ring (in block
 //                    order), so that the persistent revisit kernel makes each
 //                    block's first visit itself;
-//   RESET_ROUTE      counters and route words only: queue_tasks and
-//                    queue_blocks fill the ring after the classification, with
-//                    the blocks of the tasks that do not take the component route.
+//   RESET_ROUTE      counters only, and a first look at every task's mask for
+//                    the component route (sample_route); the ring is filled by
+//                    prepare after the classification, with the blocks of the
+//                    tasks that do not take the route.
 enum { RESET_STAGED = 0, RESET_QUEUE_ALL = 1, RESET_ROUTE = 2 };
+
+// A first look at task k's mask for the component route, by one wave: 1024
+// pixels spread over the image (16 rows of 64 columns), the OR and AND of
+// the nonzero values found, and how thin the foreground is: the share of
+// sampled foreground pixels that start a horizontal run (whose left neighbour
+// is background) -- about 1 / (mean run length); at least 1/32 counts as thin
+// (a corridor, noise), as does a sample without foreground.  The task's route
+// words are written whole here (their identities plus what the sample saw).
+// A grey mask nearly always shows two different nonzero values in the sample,
+// and the classification then skips it whole; it, or a task without a label
+// plane, marks the launch as having block-route work (has_grey).
+__device__ void sample_route(const TaskTable &tt, const TaskDev &t, int k, uint32_t *route, Work *w) {
+    const int ln = lane_id();
+    uint32_t o = 0, an = 0xffu, fg = 0, starts = 0;
+    if (t.lab)
+        for (int r = 0; r < 16; ++r) {
+            const int y = (int)(((int64_t)(2 * r + 1) * t.h) / 32);
+            const int x = (int)(((int64_t)(2 * ln + 1) * t.w) / 128);
+            const uint32_t b = mask1(t, y, x);
+            if (b) {
+                o |= b;
+                an &= b;
+                fg += 1;
+                if (x == 0 || mask1(t, y, x - 1) == 0u) starts += 1;
+            }
+        }
+    for (int d = 1; d < LANES; d <<= 1) {
+        o |= (uint32_t)__shfl_xor((int)o, d);
+        an &= (uint32_t)__shfl_xor((int)an, d);
+        fg += (uint32_t)__shfl_xor((int)fg, d);
+        starts += (uint32_t)__shfl_xor((int)starts, d);
+    }
+    if (ln == 0) {
+        uint32_t *rw = route + ROUTE_WORDS * k;
+        rw[0] = o;
+        rw[1] = an;
+        for (int q = 2; q < ROUTE_WORDS; ++q) rw[q] = 0u;
+        rw[4] = (fg == 0u || 32u * starts >= fg) ? 1u : 0u;
+        if (!t.lab || (o != 0u && o != an)) w->has_grey = seq_of(tt);   // (any writer, same value)
+    }
+}
 
 __global__ void reset_work(TaskTable tt, Work *w, uint32_t *state, uint32_t *ring,
                            uint32_t *tile_pending, uint32_t *tile_done, uint32_t *route, int mode) {
@@ -1753,8 +1802,7 @@ __global__ void reset_work(TaskTable tt, Work *w, uint32_t *state, uint32_t *rin
         w->stat_dense = w->stat_revisit = w->stat_rerun = w->stat_overflow = w->stat_request = 0;
         w->stat_route = 0;
         w->stat_spill = 0;
-        w->route_any = 0;
-        w->has_grey = 0;
+        w->classify_done = 0;
     }
     if (mode != RESET_ROUTE) {
         // (without queue_all the dense pass visits every block first)
@@ -1766,66 +1814,44 @@ __global__ void reset_work(TaskTable tt, Work *w, uint32_t *state, uint32_t *rin
         const TaskDev t = task_of(tt, (int)i);
         tile_pending[i] = queue_all ? (uint32_t)(t.nby * t.nbx) : 0u;
         tile_done[i] = 0;
-        if (route) {   // the OR and AND identities of the mask classification
-            route[ROUTE_WORDS * i] = 0u;
-            route[ROUTE_WORDS * i + 1] = 0xffu;
-            for (int q = 2; q < ROUTE_WORDS; ++q) route[ROUTE_WORDS * i + q] = 0u;
-        }
     }
+    if (mode == RESET_ROUTE)   // one wave per task (grid-stride over the waves of the grid)
+        for (uint32_t k = tid / LANES; k < n_tasks; k += nth / LANES)
+            sample_route(tt, task_of(tt, (int)k), (int)k, route, w);
 }
 
-// After the classification (RESET_ROUTE), the route of every task.  A
-// two-valued mask takes the component route when its foreground is thin (there
-// block visits would chain along corridors), when the launch has no task that
-// keeps the block route anyway (nothing for its visits to overlap with), or
-// when the policy asks for it for every two-valued mask; a thick two-valued
-// mask in a launch with grey tasks stays on the block route, whose visits then
-// fill the compute units the grey tasks' dependency chains leave idle.
-// Each task that keeps the block route reserves a range of ring positions for
-// its blocks and counts them as outstanding; a task on the component route is
-// complete as far as the block scheduler is concerned, and marks the launch as
-// having one (route_any, so that the route's kernels return at once when no
-// task takes it).
-__global__ void queue_tasks(TaskTable tt, KArgs a) {
-    const uint32_t n_tasks = n_tasks_of(tt);
-    const bool grey_work = a.work->has_grey != 0u;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_tasks; i += gridDim.x * blockDim.x) {
+// After the classification (RESET_ROUTE), the route of every task, decided
+// by one wave (the last workgroup of comp_classify).  A two-valued mask takes
+// the component route when its foreground is thin (there block visits would
+// chain along corridors), when the launch has no task that keeps the block
+// route anyway (nothing for its visits to overlap with), or when the policy
+// asks for it for every two-valued mask; a thick two-valued mask in a launch
+// with grey tasks stays on the block route, whose visits then fill the
+// compute units the grey tasks' dependency chains leave idle.  Each task that
+// keeps the block route reserves a range of ring positions for its blocks and
+// counts them as outstanding; a task on the component route is complete as
+// far as the block scheduler is concerned, and marks the launch as having one
+// (route_any, so that the route's kernels return at once when no task takes it).
+__device__ void decide_tasks(const TaskTable &tt, const KArgs &a) {
+    const uint32_t n_tasks = n_tasks_of(tt), seq = seq_of(tt);
+    const bool grey_work = __hip_atomic_load(&a.work->has_grey, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == seq;
+    for (uint32_t i = (uint32_t)lane_id(); i < n_tasks; i += LANES) {
         const TaskDev t = task_of(tt, (int)i);
-        const bool take = t.lab && two_valued(a.route, (int)i) &&
-                          (a.route_policy == 1 || !grey_work || a.route[ROUTE_WORDS * i + 4] != 0u);
-        a.route[ROUTE_WORDS * i + 3] = take ? 1u : 0u;
+        uint32_t *rw = a.route + ROUTE_WORDS * i;
+        const uint32_t o = __hip_atomic_load(rw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t an = __hip_atomic_load(rw + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const bool take = t.lab && (o == 0u || o == an) && (a.route_policy == 1 || !grey_work || rw[4] != 0u);
+        rw[3] = take ? 1u : 0u;
         if (take) {
             a.tile_done[i] = 1u;
-            a.work->route_any = 1u;   // (any writer, same value)
+            a.work->route_any = seq;   // (any writer, same value)
             continue;
         }
         const uint32_t nb = (uint32_t)(t.nby * t.nbx);
-        a.route[ROUTE_WORDS * i + 2] =
-            __hip_atomic_fetch_add(&a.work->ring_tail, nb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        rw[2] = __hip_atomic_fetch_add(&a.work->ring_tail, nb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         a.tile_pending[i] = nb;
         __hip_atomic_fetch_add(&a.work->pending, nb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-}
-
-// Then every block: requested and in its task's ring range, or idle (a task
-// on the component route, whose blocks nobody ever requests); ring positions
-// past the queued blocks are cleared.
-__global__ void queue_blocks(TaskTable tt, KArgs a) {
-    const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t nth = gridDim.x * blockDim.x;
-    const uint32_t total = total_blocks_of(tt), ring_cap = ring_cap_of(tt);
-    const uint32_t queued = a.work->ring_tail;
-    for (uint32_t gb = tid; gb < total; gb += nth) {
-        const int k = find_task(tt, gb);
-        const TaskDev t = task_of(tt, k);
-        if (on_component_route(a, t, k)) {
-            a.state[(size_t)gb * STATE_STRIDE] = ST_V;
-        } else {
-            a.state[(size_t)gb * STATE_STRIDE] = ST_D;
-            a.ring[(size_t)(a.route[ROUTE_WORDS * k + 2] + (gb - t.block0)) * RING_STRIDE] = gb + 1u;
-        }
-    }
-    for (uint32_t i = queued + tid; i < ring_cap; i += nth) a.ring[(size_t)i * RING_STRIDE] = 0u;
 }
 
 // The initial marker of 4 pixels of a task that is not a plain dilation:
@@ -1856,7 +1882,7 @@ __device__ __forceinline__ uint32_t mapped_result4(const TaskDev &t, uint32_t jv
 // before that block's first visit).  Tasks on the component route are
 // skipped (their kernels derive the marker themselves; `route` null: no
 // task takes it).  Grid-stride over dwords of each task in turn.
-__global__ void init_marker(TaskTable tt, const uint32_t *route) {
+__device__ void init_marker_all(const TaskTable &tt, const uint32_t *route) {
     const uint32_t n = n_tasks_of(tt);
     for (uint32_t k = 0; k < n; ++k) {
         const TaskDev t = task_of(tt, (int)k);
@@ -1871,6 +1897,8 @@ __global__ void init_marker(TaskTable tt, const uint32_t *route) {
         }
     }
 }
+
+__global__ void init_marker(TaskTable tt, const uint32_t *route) { init_marker_all(tt, route); }
 
 // Map the fixed point J back to each task's result (mapped_result4), except
 // for tasks on the component route, whose kernels write their result.
@@ -1888,6 +1916,29 @@ __global__ void finish_result(TaskTable tt, const uint32_t *route) {
             gstore4(t.img + (int64_t)y * t.pitch_img, x, valid, t.aligned, mapped_result4(t, jv, y, x, valid));
         }
     }
+}
+
+// After the route decisions (RESET_ROUTE): every block requested and in its
+// task's ring range, or idle (a task on the component route, whose blocks
+// nobody ever requests), ring positions past the queued blocks cleared; then
+// the marker planes of the tasks that keep the block route (as init_marker).
+__global__ void prepare(TaskTable tt, KArgs a, int any_mapped) {
+    const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t nth = gridDim.x * blockDim.x;
+    const uint32_t total = total_blocks_of(tt), ring_cap = ring_cap_of(tt);
+    const uint32_t queued = a.work->ring_tail;
+    for (uint32_t gb = tid; gb < total; gb += nth) {
+        const int k = find_task(tt, gb);
+        const TaskDev t = task_of(tt, k);
+        if (on_component_route(a, t, k)) {
+            a.state[(size_t)gb * STATE_STRIDE] = ST_V;
+        } else {
+            a.state[(size_t)gb * STATE_STRIDE] = ST_D;
+            a.ring[(size_t)(a.route[ROUTE_WORDS * k + 2] + (gb - t.block0)) * RING_STRIDE] = gb + 1u;
+        }
+    }
+    for (uint32_t i = queued + tid; i < ring_cap; i += nth) a.ring[(size_t)i * RING_STRIDE] = 0u;
+    if (any_mapped) init_marker_all(tt, a.route);
 }
 
 // Self-test input pattern for the row closure (shared with the host check).

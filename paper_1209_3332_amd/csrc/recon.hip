@@ -454,14 +454,12 @@ int enqueue_kernels(recon_ctx *c, const Workspace &ws, int v, const rk::TaskTabl
         case 1: hipLaunchKernelGGL(rk::K<32>, dim3(GRID), dim3(64), LDS, s, tt, ka); break;      \
         default: hipLaunchKernelGGL(rk::K<64>, dim3(GRID), dim3(64), LDS, s, tt, ka); break;     \
     }
-        hipLaunchKernelGGL(rk::comp_sample, dim3(std::max<uint32_t>(1u, std::min<uint32_t>(ntask, 4096u))), dim3(64), 0,
-                           s, tt, ka);
+        (void)ntask;
+        // (reset_work sampled every task's mask) the classification, whose last
+        // workgroup decides the routes; then the ring and the marker planes of
+        // the tasks that keep the block route
         RK_COMP(comp_classify, (int)std::max<uint32_t>(1u, std::min<uint32_t>(nblk, 1024u)), 0);
-        // the ring of the tasks that keep the block route, and route_any
-        hipLaunchKernelGGL(rk::queue_tasks, dim3(std::max<uint32_t>(1u, (ntask + 255) / 256)), dim3(256), 0, s, tt, ka);
-        // marker planes of the tasks that keep the block route, and the ring
-        if (any_mapped) hipLaunchKernelGGL(rk::init_marker, dim3(1024), dim3(256), 0, s, tt, ka.route);
-        hipLaunchKernelGGL(rk::queue_blocks, dim3(256), dim3(256), 0, s, tt, ka);
+        hipLaunchKernelGGL(rk::prepare, dim3(1024), dim3(256), 0, s, tt, ka, any_mapped ? 1 : 0);
         // labelling and maxima of the route's tasks on the second stream, while
         // the revisit kernel works on the others (it leaves most compute units
         // idle on a latency-bound tile; these kernels use little or no LDS)
@@ -543,6 +541,7 @@ int run_tasks(recon_ctx *c, const recon_task *tasks, int n, hipStream_t stream, 
         tt.n_inline = (uint32_t)n;
         tt.total_inline = total_blocks;
         tt.ring_cap_inline = (uint32_t)ring_slots(c->cap_blocks);
+        tt.seq_inline = c->launch_seq;
         for (int k = 0; k < n; ++k) tt.inl[k] = table[k];
     } else {
         tt.hdr = (const BatchHdr *)c->d_table;
@@ -555,6 +554,7 @@ int run_tasks(recon_ctx *c, const recon_task *tasks, int n, hipStream_t stream, 
         hdr.total_blocks = total_blocks;
         hdr.ring_cap = (uint32_t)ring_slots(c->cap_blocks);
         hdr.any_mapped = any_mapped ? 1u : 0u;
+        hdr.launch_seq = c->launch_seq;
         std::memcpy(c->h_table, &hdr, sizeof(hdr));
         std::memcpy(c->h_table + sizeof(hdr), table.data(), table.size() * sizeof(rk::TaskDev));
     }
@@ -1034,6 +1034,7 @@ int recon_dilate_noalloc(recon_ctx *ctx, recon_image *marker, const recon_image 
     tt.n_inline = 1;
     tt.total_inline = total_blocks;
     tt.ring_cap_inline = (uint32_t)ring_slots(total_blocks);
+    tt.seq_inline = ++ctx->launch_seq;
     tt.inl[0] = table[0];
     const hipStream_t s = (hipStream_t)stream;
     rc = enqueue_kernels(ctx, ws, variant_of(bh), tt, total_blocks, 1u, false, false, false, s);

@@ -448,6 +448,7 @@ int emu_run(const EmuTask *tasks, int n, int bh, int qcap, int scan_rounds, int 
         tt.n_inline = (uint32_t)n;
         tt.total_inline = total;
         tt.ring_cap_inline = total + (uint32_t)n_waves + 1;
+        tt.seq_inline = 1;   // the launch's number (Work starts zeroed)
         for (int k = 0; k < n; ++k) tt.inl[k] = table[k];
     } else {
         ext_mem.resize(sizeof(BatchHdr) + n * sizeof(TaskDev));
@@ -456,6 +457,7 @@ int emu_run(const EmuTask *tasks, int n, int bh, int qcap, int scan_rounds, int 
         hdr.total_blocks = total;
         hdr.ring_cap = total + (uint32_t)n_waves + 1;
         hdr.any_mapped = any_mapped ? 1u : 0u;
+        hdr.launch_seq = 1;
         std::memcpy(ext_mem.data(), &hdr, sizeof(hdr));
         std::memcpy(ext_mem.data() + sizeof(hdr), table.data(), n * sizeof(TaskDev));
         tt.hdr = (const BatchHdr *)ext_mem.data();
@@ -480,8 +482,21 @@ int emu_run(const EmuTask *tasks, int n, int bh, int qcap, int scan_rounds, int 
     };
     // stop_after 0: the persistent pipeline; 1..3: the staged one, stopped after that stage
     const bool merged = stop_after == 0;
-    grid_run([&] { reset_work(tt, work, state, ring, tpend, tdone, route,
-                              !merged ? RESET_STAGED : (component ? RESET_ROUTE : RESET_QUEUE_ALL)); }, 4, 64);
+    {   // reset_work samples the tasks' masks with cross-lane operations: run it as emulated waves
+        const int mode = !merged ? RESET_STAGED : (component ? RESET_ROUTE : RESET_QUEUE_ALL);
+        std::atomic<int> rbad{0};
+        std::vector<std::thread> th;
+        for (int g = 0; g < 4; ++g)
+            th.emplace_back([&, g] {
+                kemu::blockIdx_.x = (uint32_t)g;
+                kemu::gridDim_.x = 4;
+                kemu::blockDim_.x = 64;
+                if (!kemu::run_wave([&] { reset_work(tt, work, state, ring, tpend, tdone, route, mode); }, 16))
+                    rbad++;
+            });
+        for (auto &t : th) t.join();
+        if (rbad) return -2;
+    }
 
     KArgs ka;
     ka.work = work;
@@ -496,6 +511,8 @@ int emu_run(const EmuTask *tasks, int n, int bh, int qcap, int scan_rounds, int 
     ka.binary_drain_budget = 4;
     ka.route = route;
     ka.route_policy = component_mode == 1 ? 1 : 0;
+    ka.launch_seq = 1;
+    ka.host_done = nullptr;
     // global spill queues (KEMU_SPILL = entries per wave; unset or 0: none), exact size
     const char *se = std::getenv("KEMU_SPILL");
     const uint32_t spill_cap = se ? (uint32_t)std::atoi(se) : 0u;
@@ -546,8 +563,7 @@ int emu_run(const EmuTask *tasks, int n, int bh, int qcap, int scan_rounds, int 
         case 32: body = [&] { K<32>(tt, ka); }; break;          \
         default: body = [&] { K<64>(tt, ka); }; break;          \
     }
-                    if (which == 5) body = [&] { comp_sample(tt, ka); };
-                    else if (which == 0) { KEMU_PICK(comp_classify) }
+                    if (which == 0) { KEMU_PICK(comp_classify) }
                     else if (which == 1) { KEMU_PICK(comp_label_local) }
                     else if (which == 2) { KEMU_PICK(comp_label_merge) }
                     else if (which == 3) { KEMU_PICK(comp_flatten_max) }
@@ -558,15 +574,12 @@ int emu_run(const EmuTask *tasks, int n, int bh, int qcap, int scan_rounds, int 
             }
             for (auto &t : th) t.join();
         };
-        comp_grid(5, 0);
-        comp_grid(0, 0);
-        grid_run([&] { queue_tasks(tt, ka); }, 2, 64);
-        if (any_mapped) grid_run([&] { init_marker(tt, route); }, 8, 64);
+        comp_grid(0, 0);   // the classification; its last workgroup decides the routes
+        grid_run([&] { prepare(tt, ka, any_mapped ? 1 : 0); }, 8, 64);
         comp_grid(1, (size_t)LT_H * LT_W * 4);
         comp_grid(2, 0);
         comp_grid(3, 0);
         comp_grid(4, 0);
-        grid_run([&] { queue_blocks(tt, ka); }, 3, 64);
     } else if (any_mapped) {
         grid_run([&] { init_marker(tt, nullptr); }, 8, 64);
     }
