@@ -189,9 +189,11 @@ typedef struct {
        kernel durations are then -1 */
     float dense_ms, seed_ms, drain_ms, total_ms;
     int64_t component_tasks;   /* tasks reconstructed by the component route (see recon_config) */
-    float route_ms;            /* with recon_config.timing: duration in ms of the component
-                                  route's kernels (classification, labelling, maxima), -1 for
-                                  a replayed graph, 0 when the route is off */
+    float route_ms;            /* with recon_config.timing: duration in ms from the start of
+                                  the launch to the end of the component route's kernels
+                                  (scheduler reset and sampling, classification, labelling,
+                                  maxima; they run beside the revisit drain), -1 for a
+                                  replayed graph, 0 when the route is off */
     float reserved_f;
     int64_t queue_spills;      /* queue entries pushed to the global spill queues */
 } recon_stats;
@@ -281,9 +283,9 @@ int recon_distance(recon_ctx *ctx, const recon_image *img, int32_t *dist2, int64
 int recon_pre_watershed(recon_ctx *ctx, recon_image *img, int conn, void *stream);
 
 /* Run n tasks (any mix of ops, shapes and connectivities) in one persistent
- * launch sequence, replayed from a HIP graph (a context created with timing = 1
- * launches batches of at most 12 tasks directly instead, so that each of their
- * kernels is timed).  The paper processes a dataset as a bag of independent
+ * launch sequence: up to 12 tasks are launched directly (their table in the
+ * kernel arguments), larger batches replay a HIP graph captured once per block
+ * shape (timed as a whole with timing = 1).  The paper processes a dataset as a bag of independent
  * tile tasks (Sec. III-B: a stage instance is an (input chunk, stage) pair,
  * handed out on demand); here the bag is drained inside one launch, whose
  * waves pull blocks of any task as they free up, each task converging on its
@@ -335,8 +337,8 @@ int recon_last_stats(recon_ctx *ctx, recon_stats *out);
  * timing = 1: `back` = 0 is the last launch sequence, 1 the one before, up to
  * 63.  dense_ms, seed_ms, drain_ms: the dense pass (K1), border seeding (K2)
  * and revisit drain (K3); total_ms: the whole launch, from the scheduler reset
- * and marker preparation to the result mapping; route_ms: the component
- * route's kernels.  A replayed graph reports
+ * and marker preparation to the result mapping; route_ms: from the start of
+ * the launch to the end of the component route's kernels.  A replayed graph reports
  * only its total (the others are -1).  Waits (up to 60 s) for that launch to
  * complete.  RECON_EINVAL if the context does not time its launches or that
  * launch is no longer kept.  Lets a caller time many launches issued back to

@@ -26,10 +26,12 @@
 //                     every task, into two words per task: the mask is
 //                     two-valued when they are equal (one nonzero value) or the
 //                     OR is 0 (an all-zero mask).  A wave skips the rows of a
-//                     task already known to hold two different nonzero values.
+//                     task already known to hold two different nonzero values,
+//                     or that cannot take the route whatever its values.
 //                     The last workgroup decides every task's route
 //                     (decide_tasks), and prepare then fills the ring with the
-//                     blocks of the others;
+//                     blocks of the others.  The whole kernel returns at once
+//                     when the samples already decided every route;
 //   comp_label_local  tile-local labelling of {I != 0} (label.hpp's label_tile)
 //                     into the task's int32 label plane;
 //   comp_label_merge  unions across tile borders (merge_tile);
@@ -94,11 +96,14 @@ struct UnitWalk {
 // skipping less.
 template <int BH>
 __global__ __launch_bounds__(64) void comp_classify(TaskTable tt, KArgs a) {
+    if (a.work->classify_skip == seq_of(tt)) return;   // the samples decided every route
     const int ln = lane_id();
     const uint32_t n = total_blocks_of(tt);
     UnitWalk wk;
     int acc_k = -1;                 // task whose partial OR / AND this wave holds
     uint32_t acc_or = 0, acc_and = 0xffu;
+    const uint32_t seq = seq_of(tt);
+    bool wrote = false;             // (lane 0) this workgroup changed a route word or has_grey
     auto flush = [&]() {
         if (acc_k < 0) return;
         for (int d = 1; d < LANES; d <<= 1) {
@@ -112,7 +117,13 @@ __global__ __launch_bounds__(64) void comp_classify(TaskTable tt, KArgs a) {
             const uint32_t ca = __hip_atomic_load(wa, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if ((ca & acc_and) != ca) __hip_atomic_fetch_and(wa, acc_and, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const uint32_t no = co | acc_or, na = ca & acc_and;
-            if (no != 0u && no != na) a.work->has_grey = seq_of(tt);   // this task is grey (any writer, same value)
+            wrote |= (no != co) || (na != ca);
+            // this task is grey (any writer, same value; a plain load first so
+            // that a line already holding it is not written again by every wave)
+            if (no != 0u && no != na && a.work->has_grey != seq) {
+                a.work->has_grey = seq;
+                wrote = true;
+            }
         }
         acc_or = 0;
         acc_and = 0xffu;
@@ -125,8 +136,12 @@ __global__ __launch_bounds__(64) void comp_classify(TaskTable tt, KArgs a) {
             flush();
             acc_k = wk.cur;
         }
-        const uint32_t seen_or = a.route[ROUTE_WORDS * wk.cur], seen_and = a.route[ROUTE_WORDS * wk.cur + 1];
+        const uint32_t *rw = a.route + ROUTE_WORDS * wk.cur;
+        const uint32_t seen_or = rw[0], seen_and = rw[1];
         if (uniform(seen_or != 0u && seen_or != seen_and ? 1 : 0)) continue;
+        // a thick mask beside grey work keeps the block route whatever its
+        // values (decide_tasks), so it is not read either
+        if (uniform(a.route_policy != 1 && rw[4] == 0u && a.work->has_grey == seq ? 1 : 0)) continue;
         const int lb = (int)(gb - t.block0);
         const BlockGeom g = geom<BH>(t, lb / t.nbx, lb % t.nbx);
         const int x = g.x0 + 4 * ln;
@@ -146,12 +161,19 @@ __global__ __launch_bounds__(64) void comp_classify(TaskTable tt, KArgs a) {
     }
     flush();
     // the last workgroup to finish decides every task's route (decide_tasks):
-    // the counter's acquire-release orders every workgroup's flush before it
-    __threadfence();
+    // a workgroup that wrote releases its writes with its count, and the last
+    // one acquires them all (an agent-scope release or acquire writes back or
+    // invalidates this XCD's L2, so the others neither fence nor acquire)
     uint32_t prior = 0;
-    if (ln == 0)
-        prior = __hip_atomic_fetch_add(&a.work->classify_done, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    if (uniform(prior) + 1u == gridDim.x) decide_tasks(tt, a);
+    if (ln == 0) {
+        uint32_t *cnt = &a.work->classify_done;
+        prior = wrote ? __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT)
+                      : __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (uniform(prior) + 1u == gridDim.x) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        decide_tasks(tt, a);
+    }
 }
 
 template <int BH>

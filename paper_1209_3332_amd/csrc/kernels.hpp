@@ -148,8 +148,10 @@ struct Work {
     uint32_t route_any;              // = the launch's number: some task takes the component route
     uint32_t has_grey;               // = the launch's number: some task keeps the block route whatever it looks like
     uint32_t classify_done;          // workgroups of the classification that have finished
-    uint32_t pad5[3];
-    unsigned long long pad4[6];
+    uint32_t classify_skip;          // = the launch's number: the samples decided every route (no classification)
+    uint32_t pad5[2];
+    unsigned long long sample_word;  // (launch number << 32) | tasks sampled so far in that launch
+    unsigned long long pad4[5];
 };
 
 struct KArgs {
@@ -802,8 +804,9 @@ __device__ __forceinline__ uint32_t row_closure(uint32_t lo4, uint32_t hi4, uint
 // written while row r is closed), so each row's marker, mask and halo bytes are
 // read one row ahead and their latency overlaps the closure of the row before.
 // After the last block row the read-ahead lands on the halo row, which exists.
-template <int BH, int CONN>
-__device__ __forceinline__ bool sweep(Lds<BH> &L, int dir) {
+template <int BH, int CONN, int DIR>
+__device__ __forceinline__ bool sweep(Lds<BH> &L) {
+    constexpr int dir = DIR;
     constexpr int conn = CONN;
     const int ln = lane_id();
     const int r0 = dir > 0 ? 0 : BH - 1;
@@ -840,17 +843,17 @@ __device__ __forceinline__ bool sweep(Lds<BH> &L, int dir) {
     return changed;
 }
 
-// A round of sweeps: down, then up.  One loop (not unrolled) holds one inlined
-// copy of the sweep, so that each call site of a round costs one copy.
-// Returns true if anything changed.
+// A round of sweeps: down, then up, each with its direction a compile-time
+// constant (every LDS offset of the unrolled rows an immediate).  A block
+// visit has one call site of it (converge_block), which serves both a first
+// visit's sweep rounds and a revisit's fallback.  Returns true if anything
+// changed.
 template <int BH, int CONN>
 __device__ __forceinline__ bool sweep_round(Lds<BH> &L) {
-    bool c = false;
-#pragma unroll 1
-    for (int d = 0; d < 2; ++d) {
-        c |= sweep<BH, CONN>(L, d == 0 ? +1 : -1);
-        __syncthreads();
-    }
+    bool c = sweep<BH, CONN, +1>(L);
+    __syncthreads();
+    c |= sweep<BH, CONN, -1>(L);
+    __syncthreads();
     return c;
 }
 
@@ -1155,8 +1158,8 @@ __device__ __forceinline__ bool drain(Lds<BH> &L, int qcap, uint32_t &head, uint
 // following long paths (a flood or a corridor entering the block) one pixel
 // per round; it is cut short and a round of sweeps (which move whole row and
 // column runs at once) takes over, followed by a dense seed, at most
-// SWEEP_FALLBACKS times.  A first visit has had its sweep rounds already and
-// drains to the end.
+// SWEEP_FALLBACKS times.  A first visit starts with up to `pre_sweeps` sweep
+// rounds (while they change something) and then drains to the end.
 constexpr int SWEEP_FALLBACKS = 4;
 // A border seed that queues at least this many pixels (a wave's worth) is a
 // wide front entering the block: it goes straight to a sweep round, which
@@ -1171,10 +1174,20 @@ constexpr uint32_t WIDE_FRONT_LOAD = 4;
 
 template <int BH, int CONN>
 __device__ __forceinline__ bool converge_block(Lds<BH> &L, int qcap, WaveStats &st, bool border_only, int bh, int bw,
-                               int budget, bool wide_first = false) {
+                                               int budget, bool wide_first, int pre_sweeps) {
     bool changed = false;
     int fallbacks = border_only ? SWEEP_FALLBACKS : 0;
-    for (int round = 0; round <= (1 << 16); ++round) {   // each round raises pixels; bounded anyway
+    bool sweep_next = pre_sweeps > 0;
+    for (int round = 0; round <= (1 << 16);) {   // each round raises pixels; bounded anyway
+        if (sweep_next) {
+            // the first visit's sweep rounds (again while they change
+            // something, at most pre_sweeps), or one fallback round
+            const bool c = __ballot(sweep_round<BH, CONN>(L)) != 0;
+            sweep_next = pre_sweeps > 1 && c;
+            pre_sweeps = pre_sweeps > 0 ? pre_sweeps - 1 : 0;
+            if (sweep_next) continue;
+            pre_sweeps = 0;
+        }
         uint32_t head = 0, tail = 0;
         bool overflow = false;
         if (lane_id() == 0) ((volatile RK_LDS uint32_t *)L.sp)[3] = 0u;   // a round starts with empty queues
@@ -1187,9 +1200,10 @@ __device__ __forceinline__ bool converge_block(Lds<BH> &L, int qcap, WaveStats &
         const bool wide = wide_first && border_only && round == 0 && fallbacks > 0 && tail - head >= WIDE_FRONT;
         const bool drained = !wide && drain<BH, CONN>(L, qcap, head, tail, overflow, fallbacks > 0 ? budget : -1);
         __syncthreads();
+        ++round;
         if (!drained) {
             --fallbacks;
-            sweep_round<BH, CONN>(L);
+            sweep_next = true;
             continue;
         }
         if (!__ballot(overflow)) break;
@@ -1394,9 +1408,7 @@ __device__ __forceinline__ bool check_neighbours(const KArgs &a, uint32_t ring_c
 // A block loaded with an empty halo: sweep rounds, then seed and drain.
 template <int BH, int CONN>
 __device__ __forceinline__ void dense_block(const TaskDev &t, const BlockGeom &g, Lds<BH> &L, WaveStats &st) {
-    for (int k = 0; k < t.scan_rounds; ++k)
-        if (!__ballot(sweep_round<BH, CONN>(L))) break;
-    converge_block<BH, CONN>(L, t.qcap, st, false, g.bh, g.bw, -1);
+    converge_block<BH, CONN>(L, t.qcap, st, false, g.bh, g.bw, -1, false, t.scan_rounds);
 }
 
 // One visit's work on the loaded block: dense (a first visit: sweep rounds,
@@ -1406,10 +1418,8 @@ __device__ __forceinline__ void dense_block(const TaskDev &t, const BlockGeom &g
 template <int BH, int CONN>
 __device__ __forceinline__ bool visit_block(const TaskDev &t, Lds<BH> &L, WaveStats &st, bool dense, int bh, int bw,
                                             int budget, bool wide_first) {
-    if (dense)
-        for (int k = 0; k < t.scan_rounds; ++k)
-            if (!__ballot(sweep_round<BH, CONN>(L))) break;
-    return converge_block<BH, CONN>(L, t.qcap, st, !dense, bh, bw, dense ? -1 : budget, wide_first && !dense);
+    return converge_block<BH, CONN>(L, t.qcap, st, !dense, bh, bw, dense ? -1 : budget, wide_first && !dense,
+                                    dense ? t.scan_rounds : 0);
 }
 
 template <int BH>
@@ -1741,9 +1751,16 @@ __global__ void copy_table(const uint8_t *src, uint8_t *dst, uint32_t bytes) {
 //                    block's first visit itself;
 //   RESET_ROUTE      counters only, and a first look at every task's mask for
 //                    the component route (sample_route); the ring is filled by
-//                    prepare after the classification, with the blocks of the
-//                    tasks that do not take the route.
+//                    prepare after the routes are decided, with the blocks of
+//                    the tasks that do not take the route.  When the samples
+//                    alone show that no task can take it (every mask grey, or
+//                    thick beside grey work), the last sampling wave decides
+//                    every route and the classification is skipped.
 enum { RESET_STAGED = 0, RESET_QUEUE_ALL = 1, RESET_ROUTE = 2 };
+// Up to this many tasks, one wave samples them all (RESET_ROUTE).
+constexpr uint32_t SAMPLE_ONE_WAVE = 8;
+
+__device__ void decide_tasks(const TaskTable &tt, const KArgs &a);
 
 // A first look at task k's mask for the component route, by one wave: 1024
 // pixels spread over the image (16 rows of 64 columns), the OR and AND of
@@ -1758,18 +1775,26 @@ enum { RESET_STAGED = 0, RESET_QUEUE_ALL = 1, RESET_ROUTE = 2 };
 __device__ void sample_route(const TaskTable &tt, const TaskDev &t, int k, uint32_t *route, Work *w) {
     const int ln = lane_id();
     uint32_t o = 0, an = 0xffu, fg = 0, starts = 0;
-    if (t.lab)
+    if (t.lab) {
+        // every sampled pixel and its left neighbour loaded together (one
+        // round trip instead of one per sampled row)
+        const int x = (int)(((int64_t)(2 * ln + 1) * t.w) / 128), xl = x > 0 ? x - 1 : x;
+        uint32_t b[16], l[16];
+#pragma unroll
         for (int r = 0; r < 16; ++r) {
             const int y = (int)(((int64_t)(2 * r + 1) * t.h) / 32);
-            const int x = (int)(((int64_t)(2 * ln + 1) * t.w) / 128);
-            const uint32_t b = mask1(t, y, x);
-            if (b) {
-                o |= b;
-                an &= b;
-                fg += 1;
-                if (x == 0 || mask1(t, y, x - 1) == 0u) starts += 1;
-            }
+            b[r] = mask1(t, y, x);
+            l[r] = x > 0 ? mask1(t, y, xl) : 0u;
         }
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+            if (b[r]) {
+                o |= b[r];
+                an &= b[r];
+                fg += 1;
+                if (l[r] == 0u) starts += 1;
+            }
+    }
     for (int d = 1; d < LANES; d <<= 1) {
         o |= (uint32_t)__shfl_xor((int)o, d);
         an &= (uint32_t)__shfl_xor((int)an, d);
@@ -1786,8 +1811,49 @@ __device__ void sample_route(const TaskTable &tt, const TaskDev &t, int k, uint3
     }
 }
 
-__global__ void reset_work(TaskTable tt, Work *w, uint32_t *state, uint32_t *ring,
-                           uint32_t *tile_pending, uint32_t *tile_done, uint32_t *route, int mode) {
+// Counts one sampled task of the launch (lane 0 of the sampling wave, after
+// its route words are written): the count lives in the low half of a word
+// whose high half is the launch's number, so that no other kernel has to clear
+// it between launches.  The release orders the sample's writes (and, in the
+// wave holding thread 0, the counter resets) before the count; uniform true in
+// the wave whose count completes the launch's samples.
+__device__ __forceinline__ bool count_sample(const TaskTable &tt, Work *w, uint32_t n_tasks) {
+    uint32_t last = 0;
+    if (lane_id() == 0) {
+        const unsigned long long seq = seq_of(tt);
+        unsigned long long cur = __hip_atomic_load(&w->sample_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        unsigned long long nxt;
+        do {
+            nxt = (cur >> 32) == seq ? cur + 1ull : (seq << 32) | 1ull;
+        } while (!__hip_atomic_compare_exchange_weak(&w->sample_word, &cur, nxt, __ATOMIC_RELEASE, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT));
+        last = (uint32_t)nxt == n_tasks ? 1u : 0u;
+    }
+    return uniform(last) != 0u;
+}
+
+// After every sample (one wave): can some task still take the component
+// route?  Only a mask whose sample shows at most one nonzero value, and then
+// only when it is thin, or no task keeps the block route anyway, or the
+// policy asks for the route for every two-valued mask (as decide_tasks).
+__device__ __forceinline__ bool route_possible(const TaskTable &tt, const KArgs &a) {
+    const uint32_t n_tasks = n_tasks_of(tt);
+    const bool grey_work = __hip_atomic_load(&a.work->has_grey, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == seq_of(tt);
+    int any = 0;
+    for (uint32_t i = (uint32_t)lane_id(); i < n_tasks; i += LANES) {
+        const TaskDev t = task_of(tt, (int)i);
+        uint32_t *rw = a.route + ROUTE_WORDS * i;
+        const uint32_t o = __hip_atomic_load(rw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t an = __hip_atomic_load(rw + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t thin = __hip_atomic_load(rw + 4, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        any |= (t.lab && (o == 0u || o == an) && (a.route_policy == 1 || !grey_work || thin != 0u)) ? 1 : 0;
+    }
+    return __ballot(any != 0) != 0ull;
+}
+
+__global__ void reset_work(TaskTable tt, KArgs a, int mode) {
+    Work *w = a.work;
+    uint32_t *state = a.state, *ring = a.ring, *tile_pending = a.tile_pending, *tile_done = a.tile_done;
     const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t nth = gridDim.x * blockDim.x;
     const uint32_t n_tasks = n_tasks_of(tt), total = total_blocks_of(tt), ring_cap = ring_cap_of(tt);
@@ -1810,14 +1876,50 @@ __global__ void reset_work(TaskTable tt, Work *w, uint32_t *state, uint32_t *rin
         for (uint32_t i = tid; i < ring_cap; i += nth)
             ring[(size_t)i * RING_STRIDE] = queue_all && i < total ? i + 1u : 0u;
     }
-    for (uint32_t i = tid; i < n_tasks; i += nth) {
-        const TaskDev t = task_of(tt, (int)i);
-        tile_pending[i] = queue_all ? (uint32_t)(t.nby * t.nbx) : 0u;
-        tile_done[i] = 0;
+    if (mode != RESET_ROUTE) {
+        for (uint32_t i = tid; i < n_tasks; i += nth) {
+            const TaskDev t = task_of(tt, (int)i);
+            tile_pending[i] = queue_all ? (uint32_t)(t.nby * t.nbx) : 0u;
+            tile_done[i] = 0;
+        }
+        return;
     }
-    if (mode == RESET_ROUTE)   // one wave per task (grid-stride over the waves of the grid)
-        for (uint32_t k = tid / LANES; k < n_tasks; k += nth / LANES)
-            sample_route(tt, task_of(tt, (int)k), (int)k, route, w);
+    if (n_tasks <= SAMPLE_ONE_WAVE) {
+        // few tasks: the wave holding thread 0 samples them all in turn and
+        // decides at once (no counting across waves, no fences)
+        if (tid >= (uint32_t)LANES) return;
+        for (uint32_t k = 0; k < n_tasks; ++k) {
+            if (lane_id() == 0) {
+                tile_pending[k] = 0u;
+                tile_done[k] = 0u;
+            }
+            sample_route(tt, task_of(tt, (int)k), (int)k, a.route, w);
+        }
+        vm_sync();   // lane 0's writes are complete before the other lanes read them
+        RK_LANE_SYNC();
+        if (!route_possible(tt, a)) {
+            decide_tasks(tt, a);
+            if (lane_id() == 0) w->classify_skip = seq_of(tt);
+        }
+        return;
+    }
+    // one wave per task (grid-stride over the waves of the grid); the wave
+    // holding thread 0 takes task 0 first, so its resets above are released
+    // with that task's count
+    for (uint32_t k = tid / LANES; k < n_tasks; k += nth / LANES) {
+        if (lane_id() == 0) {
+            tile_pending[k] = 0u;
+            tile_done[k] = 0u;
+        }
+        sample_route(tt, task_of(tt, (int)k), (int)k, a.route, w);
+        if (count_sample(tt, w, n_tasks)) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            if (!route_possible(tt, a)) {
+                decide_tasks(tt, a);
+                if (lane_id() == 0) w->classify_skip = seq_of(tt);
+            }
+        }
+    }
 }
 
 // After the classification (RESET_ROUTE), the route of every task, decided
@@ -1834,23 +1936,44 @@ __global__ void reset_work(TaskTable tt, Work *w, uint32_t *state, uint32_t *rin
 // (route_any, so that the route's kernels return at once when no task takes it).
 __device__ void decide_tasks(const TaskTable &tt, const KArgs &a) {
     const uint32_t n_tasks = n_tasks_of(tt), seq = seq_of(tt);
+    const int ln = lane_id();
     const bool grey_work = __hip_atomic_load(&a.work->has_grey, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == seq;
-    for (uint32_t i = (uint32_t)lane_id(); i < n_tasks; i += LANES) {
-        const TaskDev t = task_of(tt, (int)i);
-        uint32_t *rw = a.route + ROUTE_WORDS * i;
-        const uint32_t o = __hip_atomic_load(rw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const uint32_t an = __hip_atomic_load(rw + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const bool take = t.lab && (o == 0u || o == an) && (a.route_policy == 1 || !grey_work || rw[4] != 0u);
-        rw[3] = take ? 1u : 0u;
-        if (take) {
-            a.tile_done[i] = 1u;
-            a.work->route_any = seq;   // (any writer, same value)
-            continue;
+    // the ring ranges follow task order: an exclusive prefix sum of the
+    // block counts of the tasks that keep the block route (one wave, 64 tasks
+    // per step; `base` carries the sum of the steps before)
+    uint32_t base = 0;
+    bool any_route = false;
+    for (uint32_t i0 = 0; i0 < n_tasks; i0 += LANES) {
+        const uint32_t i = i0 + (uint32_t)ln;
+        uint32_t nb = 0;
+        bool take = false;
+        if (i < n_tasks) {
+            const TaskDev t = task_of(tt, (int)i);
+            uint32_t *rw = a.route + ROUTE_WORDS * i;
+            const uint32_t o = __hip_atomic_load(rw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t an = __hip_atomic_load(rw + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t thin = __hip_atomic_load(rw + 4, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            take = t.lab && (o == 0u || o == an) && (a.route_policy == 1 || !grey_work || thin != 0u);
+            rw[3] = take ? 1u : 0u;
+            if (take) a.tile_done[i] = 1u;
+            else nb = (uint32_t)(t.nby * t.nbx);
         }
-        const uint32_t nb = (uint32_t)(t.nby * t.nbx);
-        rw[2] = __hip_atomic_fetch_add(&a.work->ring_tail, nb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        a.tile_pending[i] = nb;
-        __hip_atomic_fetch_add(&a.work->pending, nb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        uint32_t incl = nb;   // inclusive prefix sum over the wave
+        for (int d = 1; d < LANES; d <<= 1) {
+            const uint32_t o = __shfl_up(incl, (unsigned)d);
+            if (ln >= d) incl += o;
+        }
+        if (i < n_tasks && !take) {
+            a.route[ROUTE_WORDS * i + 2] = base + incl - nb;
+            a.tile_pending[i] = nb;
+        }
+        base += __shfl(incl, LANES - 1);
+        any_route |= __ballot(take) != 0ull;
+    }
+    if (ln == 0) {
+        a.work->ring_tail = base;
+        a.work->pending = base;
+        if (any_route) a.work->route_any = seq;
     }
 }
 
@@ -1859,7 +1982,10 @@ __device__ void decide_tasks(const TaskTable &tt, const KArgs &a) {
 // caller's marker); h-dome and regional maxima max(I - h, 0) bytewise (I -
 // min(I, h) never borrows across bytes).  `jrow` is the marker row.
 __device__ __forceinline__ uint32_t initial_marker4(const TaskDev &t, const uint8_t *jrow, int y, int x, int valid) {
-    if (t.op == OP_FILL) return fill_init4(t, y, x, valid, mask4(t, y, x, valid));
+    if (t.op == OP_FILL) {   // (only a word on the image frame reads the image)
+        const bool frame = y == 0 || y == t.h - 1 || x == 0 || x + 4 >= t.w;
+        return frame ? fill_init4(t, y, x, valid, mask4(t, y, x, valid)) : 0u;
+    }
     if (t.op == OP_ERODE) return ~gload4(jrow, x, valid, t.aligned);
     const uint32_t iv = gload4(t.i + (int64_t)y * t.pitch_i, x, valid, t.aligned);
     return iv - bmin4(iv, (uint32_t)t.hval * 0x01010101u);
@@ -1877,44 +2003,83 @@ __device__ __forceinline__ uint32_t mapped_result4(const TaskDev &t, uint32_t jv
     return (nz >> 7) * 0xffu;
 }
 
+// Row-strided walk over a task's plane, 16 bytes per thread: workgroup b
+// takes rows b, b + gridDim.x, ..., its threads a row's consecutive 16-byte
+// chunks (coalesced, no division of a flat index).  f(y, x, n): the chunk at
+// column x of row y, n (1..16) of its pixels inside the image.
+template <typename F>
+__device__ __forceinline__ void for_each_chunk(const TaskDev &t, F f) {
+    for (int y = (int)blockIdx.x; y < t.h; y += (int)gridDim.x)
+        for (int x = 16 * (int)threadIdx.x; x < t.w; x += 16 * (int)blockDim.x) f(y, x, min(16, t.w - x));
+}
+
+__device__ __forceinline__ bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0u; }
+typedef uint32_t u32x4 __attribute__((vector_size(16)));   // one 16-byte access
+
 // Initial marker plane of every task that is not a plain dilation, written
 // before any block is visited (so that any block can read any other's marker
 // before that block's first visit).  Tasks on the component route are
 // skipped (their kernels derive the marker themselves; `route` null: no
-// task takes it).  Grid-stride over dwords of each task in turn.
+// task takes it).  A whole aligned chunk is one 16-byte store.
 __device__ void init_marker_all(const TaskTable &tt, const uint32_t *route) {
     const uint32_t n = n_tasks_of(tt);
     for (uint32_t k = 0; k < n; ++k) {
         const TaskDev t = task_of(tt, (int)k);
         if (t.op == OP_DILATE || on_component_route(route, t, (int)k)) continue;
-        const uint32_t dw = (uint32_t)(t.w + 3) / 4u;
-        const uint64_t total = (uint64_t)t.h * dw;
-        for (uint64_t i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (uint64_t)gridDim.x * blockDim.x) {
-            const int y = (int)(i / dw), x = (int)(i % dw) * 4;
-            const int valid = min(4, t.w - x);
+        for_each_chunk(t, [&](int y, int x, int nx) {
             uint8_t *jrow = t.j + (int64_t)y * t.pitch_j;
-            gstore4(jrow, x, valid, t.aligned, initial_marker4(t, jrow, y, x, valid));
-        }
+            uint32_t v[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int valid = min(4, nx - 4 * q);
+                v[q] = valid > 0 ? initial_marker4(t, jrow, y, x + 4 * q, valid) : 0u;
+            }
+            if (nx == 16 && aligned16(jrow + x)) {
+                *(RK_GLOBAL u32x4 *)gp(jrow + x) = u32x4{v[0], v[1], v[2], v[3]};
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) gstore4(jrow, x + 4 * q, min(4, nx - 4 * q), t.aligned, v[q]);
+            }
+        });
     }
 }
 
 __global__ void init_marker(TaskTable tt, const uint32_t *route) { init_marker_all(tt, route); }
 
 // Map the fixed point J back to each task's result (mapped_result4), except
-// for tasks on the component route, whose kernels write their result.
+// for tasks on the component route, whose kernels write their result.  Whole
+// aligned chunks are one 16-byte load and one 16-byte store.
 __global__ void finish_result(TaskTable tt, const uint32_t *route) {
     const uint32_t n = n_tasks_of(tt);
     for (uint32_t k = 0; k < n; ++k) {
         const TaskDev t = task_of(tt, (int)k);
         if (t.op == OP_DILATE || on_component_route(route, t, (int)k)) continue;
-        const uint32_t dw = (uint32_t)(t.w + 3) / 4u;
-        const uint64_t total = (uint64_t)t.h * dw;
-        for (uint64_t i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (uint64_t)gridDim.x * blockDim.x) {
-            const int y = (int)(i / dw), x = (int)(i % dw) * 4;
-            const int valid = min(4, t.w - x);
-            const uint32_t jv = gload4(t.j + (int64_t)y * t.pitch_j, x, valid, t.aligned);
-            gstore4(t.img + (int64_t)y * t.pitch_img, x, valid, t.aligned, mapped_result4(t, jv, y, x, valid));
-        }
+        for_each_chunk(t, [&](int y, int x, int nx) {
+            const uint8_t *jrow = t.j + (int64_t)y * t.pitch_j;
+            uint8_t *orow = t.img + (int64_t)y * t.pitch_img;
+            const bool vec = nx == 16 && aligned16(jrow + x) && aligned16(orow + x);
+            uint32_t jv[4];
+            if (vec) {
+                const u32x4 q4 = *(const RK_GLOBAL u32x4 *)gp(jrow + x);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) jv[q] = q4[q];
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) jv[q] = gload4(jrow, x + 4 * q, min(4, nx - 4 * q), t.aligned);
+            }
+            uint32_t o[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int valid = min(4, nx - 4 * q);
+                o[q] = valid > 0 ? mapped_result4(t, jv[q], y, x + 4 * q, valid) : 0u;
+            }
+            if (vec) {
+                *(RK_GLOBAL u32x4 *)gp(orow + x) = u32x4{o[0], o[1], o[2], o[3]};
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) gstore4(orow, x + 4 * q, min(4, nx - 4 * q), t.aligned, o[q]);
+            }
+        });
     }
 }
 

@@ -148,6 +148,7 @@ struct recon_ctx {
     hipEvent_t tev[kTimingRing][7] = {};
     bool tev_graph[kTimingRing] = {};   // that launch replayed a graph (only its total is marked)
     bool tev_route[kTimingRing] = {};   // that launch ran the component route (on the second stream)
+    bool tev_merged[kTimingRing] = {};  // that launch ran the persistent pipeline (marks around K3 only)
     uint64_t launches = 0;              // launch sequences enqueued so far
     bool have_last = false;
     rk::Work *last_work = nullptr;      // the counters of the last launch (context or fixed workspace)
@@ -176,6 +177,19 @@ struct recon_ctx {
 };
 
 namespace {
+
+// Launch numbers, unique in the process and never 0 (the value of device
+// memory never written): the device-side flags keyed by them, in a context's
+// workspace or in the no-allocation entry point's, which every context on a
+// device shares, never take one launch's value for another's.
+std::atomic<uint32_t> g_launch_seq{0};
+uint32_t next_launch_seq() {
+    uint32_t v;
+    do {
+        v = g_launch_seq.fetch_add(1u, std::memory_order_relaxed) + 1u;
+    } while (v == 0u);
+    return v;
+}
 
 int ensure_device(recon_ctx *c) {
     HIP_TRY(hipSetDevice(c->device));
@@ -251,6 +265,9 @@ int ensure_capacity(recon_ctx *c, size_t n_tasks, size_t n_blocks, size_t area_b
         return fail(RECON_ENOMEM, "workspace allocation (%zu tasks, %zu blocks, %zu scratch bytes) failed",
                     nt, nb, ns);
     }
+    // the scheduler words start at 0: the flags keyed by a launch number must
+    // not find a stale number that some earlier owner of this memory left
+    HIP_TRY(hipMemset(c->d_work, 0, sizeof(rk::Work)));
     c->cap_tasks = nt;
     c->cap_blocks = nb;
     c->cap_scratch = ns;
@@ -394,7 +411,7 @@ Workspace ctx_workspace(const recon_ctx *c) {
 // Enqueue the kernels of one launch sequence on `s`.
 int enqueue_kernels(recon_ctx *c, const Workspace &ws, int v, const rk::TaskTable &tt, uint32_t total_blocks,
                     uint32_t n_tasks_host, bool any_mapped, bool route, bool dynamic_sizes, hipStream_t s) {
-    if (route && !c->aux_stream) {
+    if (route && dynamic_sizes && !c->aux_stream) {
         HIP_TRY(hipStreamCreateWithFlags(&c->aux_stream, hipStreamNonBlocking));
         HIP_TRY(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
         HIP_TRY(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
@@ -435,18 +452,24 @@ int enqueue_kernels(recon_ctx *c, const Workspace &ws, int v, const rk::TaskTabl
     const bool merged = stop == 0;
     hipEvent_t *tev = c->tev[c->launches % kTimingRing];
     c->tev_route[c->launches % kTimingRing] = route;
+    c->tev_merged[c->launches % kTimingRing] = merged;
     if (timing) HIP_TRY(hipEventRecord(tev[5], s));
     const int reset_mode = !merged ? rk::RESET_STAGED : (route ? rk::RESET_ROUTE : rk::RESET_QUEUE_ALL);
-    hipLaunchKernelGGL(rk::reset_work, dim3(64), dim3(256), 0, s, tt, ws.work, ws.state, ws.ring,
-                       ws.tile_pending, ws.tile_done, ka.route, reset_mode);
-    if (timing) HIP_TRY(hipEventRecord(tev[0], s));
+    hipLaunchKernelGGL(rk::reset_work, dim3(64), dim3(256), 0, s, tt, ka, reset_mode);
+    // (a mark between two kernels costs the gap of its own packet: the
+    // persistent pipeline marks only the revisit kernel, the route's end and
+    // the launch; the staged one every stage)
+    if (timing && !merged) HIP_TRY(hipEventRecord(tev[0], s));
+    // the stream of the block route's kernels: with the component route, a
+    // second stream forked after the classification
+    hipStream_t d = s;
     if (route) {
-        // the component route: classify every task's mask, then label and
+        // the component route: classify every task's mask (unless the samples
+        // reset_work took already decided every route), then label and
         // reconstruct the two-valued ones (the others' waves exit at once)
         const int bh = kBlockRows[v];
         const int g_rows = (int)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)nblk * bh, 4096));
         const int g_tiles = (int)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)nblk * (bh / rk::LT_H), 4096));
-        const uint32_t ntask = dynamic_sizes ? (uint32_t)c->cap_tasks : n_tasks_host;
         const size_t lds_lab = (size_t)rk::LT_H * rk::LT_W * sizeof(uint32_t);
 #define RK_COMP(K, GRID, LDS)                                                                     \
     switch (v) {                                                                                  \
@@ -454,50 +477,51 @@ int enqueue_kernels(recon_ctx *c, const Workspace &ws, int v, const rk::TaskTabl
         case 1: hipLaunchKernelGGL(rk::K<32>, dim3(GRID), dim3(64), LDS, s, tt, ka); break;      \
         default: hipLaunchKernelGGL(rk::K<64>, dim3(GRID), dim3(64), LDS, s, tt, ka); break;     \
     }
-        (void)ntask;
-        // (reset_work sampled every task's mask) the classification, whose last
-        // workgroup decides the routes; then the ring and the marker planes of
-        // the tasks that keep the block route
         RK_COMP(comp_classify, (int)std::max<uint32_t>(1u, std::min<uint32_t>(nblk, 1024u)), 0);
-        hipLaunchKernelGGL(rk::prepare, dim3(1024), dim3(256), 0, s, tt, ka, any_mapped ? 1 : 0);
-        // labelling and maxima of the route's tasks on the second stream, while
-        // the revisit kernel works on the others (it leaves most compute units
-        // idle on a latency-bound tile; these kernels use little or no LDS)
-        HIP_TRY(hipEventRecord(c->ev_fork, s));
-        HIP_TRY(hipStreamWaitEvent(c->aux_stream, c->ev_fork, 0));
-        const hipStream_t s2 = c->aux_stream;
-#define RK_COMP2(K, GRID, LDS)                                                                    \
-    switch (v) {                                                                                  \
-        case 0: hipLaunchKernelGGL(rk::K<16>, dim3(GRID), dim3(64), LDS, s2, tt, ka); break;     \
-        case 1: hipLaunchKernelGGL(rk::K<32>, dim3(GRID), dim3(64), LDS, s2, tt, ka); break;     \
-        default: hipLaunchKernelGGL(rk::K<64>, dim3(GRID), dim3(64), LDS, s2, tt, ka); break;    \
-    }
-        RK_COMP2(comp_label_local, g_tiles, lds_lab);
-        RK_COMP2(comp_label_merge, g_tiles, 0);
-        RK_COMP2(comp_flatten_max, g_rows, 0);
-        RK_COMP2(comp_write, g_rows, 0);
-#undef RK_COMP2
+        // A large batch (a replayed graph) forks: the ring and marker planes
+        // (prepare) and the revisit kernel of the tasks that keep the block
+        // route go to the second stream, while the route's labelling and
+        // maxima stay on this one, so that the route's work runs beside the
+        // revisit kernel (which leaves most compute units idle on
+        // latency-bound tiles).  The route's kernels are dispatched first:
+        // they need LDS (comp_label_local) that the persistent revisit kernel
+        // would otherwise hold until it ends.  A direct launch (at most 12
+        // tasks) runs everything on one stream: the route's kernels first
+        // (when no task takes the route they return at once), then the block
+        // route; the fork and join each cost more than that.
+        if (dynamic_sizes) {
+            HIP_TRY(hipEventRecord(c->ev_fork, s));
+            HIP_TRY(hipStreamWaitEvent(c->aux_stream, c->ev_fork, 0));
+            d = c->aux_stream;
+        }
+        RK_COMP(comp_label_local, g_tiles, lds_lab);
+        RK_COMP(comp_label_merge, g_tiles, 0);
+        RK_COMP(comp_flatten_max, g_rows, 0);
+        RK_COMP(comp_write, g_rows, 0);
 #undef RK_COMP
-        if (timing) HIP_TRY(hipEventRecord(tev[6], s2));
-        HIP_TRY(hipEventRecord(c->ev_join, s2));
+        if (timing) HIP_TRY(hipEventRecord(tev[6], s));
+        hipLaunchKernelGGL(rk::prepare, dim3(1024), dim3(256), 0, d, tt, ka, any_mapped ? 1 : 0);
     } else if (any_mapped) {
         hipLaunchKernelGGL(rk::init_marker, dim3(1024), dim3(256), 0, s, tt, ka.route);
     }
-    if (timing && !route) HIP_TRY(hipEventRecord(tev[6], s));
+    if (timing && !route && !merged) HIP_TRY(hipEventRecord(tev[6], s));
 #define RK_LAUNCH(K, GRID)                                                                        \
     switch (v) {                                                                                  \
-        case 0: hipLaunchKernelGGL(rk::K<16>, dim3(GRID), dim3(64), lds, s, tt, ka); break;      \
-        case 1: hipLaunchKernelGGL(rk::K<32>, dim3(GRID), dim3(64), lds, s, tt, ka); break;      \
-        default: hipLaunchKernelGGL(rk::K<64>, dim3(GRID), dim3(64), lds, s, tt, ka); break;     \
+        case 0: hipLaunchKernelGGL(rk::K<16>, dim3(GRID), dim3(64), lds, d, tt, ka); break;      \
+        case 1: hipLaunchKernelGGL(rk::K<32>, dim3(GRID), dim3(64), lds, d, tt, ka); break;      \
+        default: hipLaunchKernelGGL(rk::K<64>, dim3(GRID), dim3(64), lds, d, tt, ka); break;     \
     }
     if (!merged) RK_LAUNCH(dense_pass, grid12);
-    if (timing) HIP_TRY(hipEventRecord(tev[1], s));
+    if (timing && !merged) HIP_TRY(hipEventRecord(tev[1], d));
     if (stop >= 2) RK_LAUNCH(border_seed, grid12);
-    if (timing) HIP_TRY(hipEventRecord(tev[2], s));
+    if (timing) HIP_TRY(hipEventRecord(tev[2], d));
     if (merged || stop >= 3) RK_LAUNCH(revisit_drain, grid3);
-    if (timing) HIP_TRY(hipEventRecord(tev[3], s));
+    if (timing) HIP_TRY(hipEventRecord(tev[3], d));
 #undef RK_LAUNCH
-    if (route) HIP_TRY(hipStreamWaitEvent(s, c->ev_join, 0));   // join the route's stream
+    if (d != s) {   // join the block route's stream
+        HIP_TRY(hipEventRecord(c->ev_join, d));
+        HIP_TRY(hipStreamWaitEvent(s, c->ev_join, 0));
+    }
     if (any_mapped) hipLaunchKernelGGL(rk::finish_result, dim3(1024), dim3(256), 0, s, tt, ka.route);
     if (timing) HIP_TRY(hipEventRecord(tev[4], s));
     HIP_TRY(hipGetLastError());
@@ -532,7 +556,7 @@ int run_tasks(recon_ctx *c, const recon_task *tasks, int n, hipStream_t stream, 
         if (lab_off[k] != SIZE_MAX) d.lab = (int32_t *)(c->d_scratch + lab_off[k]);
     }
 
-    c->launch_seq += 1;   // numbers the launch (serving lanes: the value the kernel reports per task)
+    c->launch_seq = next_launch_seq();   // numbers the launch (serving lanes: the value the kernel reports per task)
     rk::TaskTable tt{};
     const bool inline_table = !use_graph && n <= rk::MAX_INLINE_TASKS;
     if (inline_table) {
@@ -1034,7 +1058,8 @@ int recon_dilate_noalloc(recon_ctx *ctx, recon_image *marker, const recon_image 
     tt.n_inline = 1;
     tt.total_inline = total_blocks;
     tt.ring_cap_inline = (uint32_t)ring_slots(total_blocks);
-    tt.seq_inline = ++ctx->launch_seq;
+    ctx->launch_seq = next_launch_seq();
+    tt.seq_inline = ctx->launch_seq;
     tt.inl[0] = table[0];
     const hipStream_t s = (hipStream_t)stream;
     rc = enqueue_kernels(ctx, ws, variant_of(bh), tt, total_blocks, 1u, false, false, false, s);
@@ -1335,9 +1360,11 @@ int recon_batch(recon_ctx *ctx, const recon_task *tasks, int32_t n, void *stream
             return fail(rc, "task %d: %s", k, m.c_str());
         }
     }
-    // a timing context launches small batches directly (every kernel timed);
-    // otherwise batches replay the captured graph
-    const bool use_graph = !(ctx->cfg.timing && n <= rk::MAX_INLINE_TASKS);
+    // a batch that fits the kernel arguments is launched directly (its table
+    // travels inline: no table copy, and fewer packets than a graph replay,
+    // which on this runtime costs more than the launches it saves); larger
+    // batches replay the context's captured graph
+    const bool use_graph = n > rk::MAX_INLINE_TASKS;
     return run_tasks(ctx, tasks, n, (hipStream_t)stream, use_graph);
 }
 
@@ -1350,13 +1377,18 @@ static void launch_times(recon_ctx *ctx, int back, float t[5]) {
     t[0] = t[1] = t[2] = t[3] = t[4] = -1.f;
     float ms = 0.f;
     if (!ctx->tev_graph[i]) {
-        // (with the route the persistent pipeline runs: no dense pass; tev[6]
-        // then closes the route's kernels on the second stream)
-        if (ctx->tev_route[i]) t[0] = 0.f;
-        else if (hipEventElapsedTime(&ms, tev[6], tev[1]) == hipSuccess) t[0] = ms;
-        if (hipEventElapsedTime(&ms, tev[1], tev[2]) == hipSuccess) t[1] = ms;
+        if (ctx->tev_merged[i]) {
+            // the persistent pipeline: no dense pass and no border kernel;
+            // the route's mark (tev[6], its own stream) closes its kernels,
+            // counted from the start of the launch
+            t[0] = t[1] = 0.f;
+            t[4] = 0.f;
+            if (ctx->tev_route[i] && hipEventElapsedTime(&ms, tev[5], tev[6]) == hipSuccess) t[4] = ms;
+        } else {
+            if (hipEventElapsedTime(&ms, tev[6], tev[1]) == hipSuccess) t[0] = ms;
+            if (hipEventElapsedTime(&ms, tev[1], tev[2]) == hipSuccess) t[1] = ms;
+        }
         if (hipEventElapsedTime(&ms, tev[2], tev[3]) == hipSuccess) t[2] = ms;
-        if (hipEventElapsedTime(&ms, tev[0], tev[6]) == hipSuccess) t[4] = ms;
     }
     if (hipEventElapsedTime(&ms, tev[5], tev[4]) == hipSuccess) t[3] = ms;
     (void)hipGetLastError();   // a mark that was not recorded must not leave an error behind

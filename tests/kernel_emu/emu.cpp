@@ -482,22 +482,6 @@ int emu_run(const EmuTask *tasks, int n, int bh, int qcap, int scan_rounds, int 
     };
     // stop_after 0: the persistent pipeline; 1..3: the staged one, stopped after that stage
     const bool merged = stop_after == 0;
-    {   // reset_work samples the tasks' masks with cross-lane operations: run it as emulated waves
-        const int mode = !merged ? RESET_STAGED : (component ? RESET_ROUTE : RESET_QUEUE_ALL);
-        std::atomic<int> rbad{0};
-        std::vector<std::thread> th;
-        for (int g = 0; g < 4; ++g)
-            th.emplace_back([&, g] {
-                kemu::blockIdx_.x = (uint32_t)g;
-                kemu::gridDim_.x = 4;
-                kemu::blockDim_.x = 64;
-                if (!kemu::run_wave([&] { reset_work(tt, work, state, ring, tpend, tdone, route, mode); }, 16))
-                    rbad++;
-            });
-        for (auto &t : th) t.join();
-        if (rbad) return -2;
-    }
-
     KArgs ka;
     ka.work = work;
     ka.state = state;
@@ -523,6 +507,22 @@ int emu_run(const EmuTask *tasks, int n, int bh, int qcap, int scan_rounds, int 
         const char *f = std::getenv("KEMU_TEST_FAULT");
         ka.test_fault = f ? std::atoi(f) : 0;
     }
+    {   // reset_work samples the tasks' masks with cross-lane operations: run it as emulated waves
+        const int mode = !merged ? RESET_STAGED : (component ? RESET_ROUTE : RESET_QUEUE_ALL);
+        std::atomic<int> rbad{0};
+        std::vector<std::thread> th;
+        for (int g = 0; g < 4; ++g)
+            th.emplace_back([&, g] {
+                kemu::blockIdx_.x = (uint32_t)g;
+                kemu::gridDim_.x = 4;
+                kemu::blockDim_.x = 64;
+                if (!kemu::run_wave([&] { reset_work(tt, ka, mode); }, 16))
+                    rbad++;
+            });
+        for (auto &t : th) t.join();
+        if (rbad) return -2;
+    }
+
     const size_t lds = bh == 16 ? lds_bytes<16>(qcap) : bh == 32 ? lds_bytes<32>(qcap) : lds_bytes<64>(qcap);
     std::atomic<int> bad{0};
     auto run_grid = [&](int stage, int waves) {

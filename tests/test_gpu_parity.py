@@ -253,8 +253,9 @@ def test_batch_mixed(torch_mod, rc, oracle_mod):
     outs = _run_batch(torch_mod, rc, tasks)
     for i, (t, got) in enumerate(zip(tasks, outs)):
         assert_same(got, oracle_mod.run_task(t), "batch task %d (%s)" % (i, t["op"]))
-    # replay of the captured graph with a different batch
-    tasks2 = _batch_tasks(np.random.default_rng(321), 9)
+    # replay of the captured graph with a different batch (more than the 12
+    # tasks a direct launch takes in its arguments)
+    tasks2 = _batch_tasks(np.random.default_rng(321), 13)
     outs2 = _run_batch(torch_mod, rc, tasks2)
     for i, (t, got) in enumerate(zip(tasks2, outs2)):
         assert_same(got, oracle_mod.run_task(t), "second batch task %d" % i)
@@ -309,9 +310,9 @@ def test_argument_errors(torch_mod, rc, lib):
 
 
 def test_small_batch_in_timing_context(torch_mod, lib, oracle_mod):
-    """A timing context launches a batch of at most 12 tasks directly: every
-    kernel is timed, and the bytes equal the oracle's (the headline step runs
-    a tile's reconstruction and fill-holes this way)."""
+    """A batch of at most 12 tasks is launched directly: in a timing context
+    every kernel is timed, and the bytes equal the oracle's (the headline step
+    runs a tile's reconstruction and fill-holes this way)."""
     marker, mask, binary = synth.config2_tile(seed=synth.seed_for(2, 14), size=1024, n_gauss=188)
     with lib.Recon(0, timing=1) as ctx:
         for rep in range(2):

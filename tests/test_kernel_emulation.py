@@ -268,6 +268,16 @@ def test_component_route_policy(emu_exe, oracle_mod):
     assert _route_count(log) == 1, log[-500:]
     log = _check(emu_exe, oracle_mod, [grey, thick], n_waves=3, component=2)
     assert _route_count(log) == 0, log[-500:]
+    # a mask whose sample looks two-valued but that is grey off the sampled
+    # pixels: the classification reads it whole and keeps it on the block
+    # route, and (grey work after all) the thick mask beside it too, unless
+    # the policy sends every two-valued mask to the route
+    sneaky_mask = np.full((64, 300), 255, np.uint8)
+    sneaky_mask[0, :5] = 100
+    sneaky = {"op": "dilate", "marker": synth.hdome_marker(sneaky_mask, 30), "mask": sneaky_mask, "conn": 8}
+    for mode, routed in ((2, 0), (1, 1)):
+        log = _check(emu_exe, oracle_mod, [sneaky, thick], n_waves=3, component=mode)
+        assert _route_count(log) == routed, (mode, log[-500:])
 
 
 def _stat(log, name):
