@@ -19,7 +19,10 @@ erosion, h-dome and regional maxima; labelling and the area filter; the
 distance transform and Pre-Watershed markers; a 64-tile batch of 4096 x 4096
 tiles (every eighth a 4096 x 4096 spiral corridor, which takes the component
 route) and an uneven 256-tile autotuned batch against per-tile calls; the
-serving loop at arrival rates from 50 to 2000 tiles/s.  Last comes the oracle leg: the CPU
+serving loop at arrival rates from 50 to 2000 tiles/s; the co-scheduled tile
+pipeline (h-dome, fill-holes, area filter, markers, labels of host tiles on the
+GPU and the host cores, FCFS against PATS, with and without data locality).
+Last comes the oracle leg: the CPU
 oracle timed on the host cores on a bounded sample, then the comparison of
 every section's recorded outputs with the oracle (the only part of this
 script that runs the oracle; --no-cpu-baseline skips it).
@@ -143,7 +146,14 @@ def run_checks(out, workers=4):
 
     def solve(c):
         t0 = time.perf_counter()
-        want = getattr(oracle, c["fn"])(*c["args"])
+        if c["fn"] == "pipeline_chain":
+            # the tile pipeline's outputs: hdome -> fill-holes -> area filter,
+            # then the markers and the labels of the filtered image
+            img, h, conn, lo, hi = c["args"]
+            a = oracle.area_threshold(oracle.fill_holes(oracle.hdome(img, h, conn), conn), lo, hi, conn)
+            want = (a, oracle.pre_watershed(a, conn), oracle.label(a, conn))
+        else:
+            want = getattr(oracle, c["fn"])(*c["args"])
         return want, time.perf_counter() - t0
 
     # the comparisons that report a single-core rate run alone, the others in parallel
@@ -158,6 +168,10 @@ def run_checks(out, workers=4):
         want, dt = results[id(c)]
         if c["fn"] == "label":
             ok = bool(np.array_equal(c["got"][0], want[0]) and c["got"][1] == want[1])
+        elif c["fn"] == "pipeline_chain":
+            g = c["got"]
+            ok = bool(np.array_equal(g["objects"], want[0]) and np.array_equal(g["markers"], want[1])
+                      and np.array_equal(g["labels"], want[2][0]) and g["count"] == want[2][1])
         else:
             ok = bool(np.array_equal(c["got"], want))
         if c["path"][-1] == "mismatches":     # sampled serving results: count the bad ones
@@ -731,6 +745,110 @@ def serving(recon, torch, rates, seconds, pool_tiles, workers):
     return out
 
 
+def _gen_pipe_tile(args):
+    import synth
+    i, size = args
+    return i, synth.config2_tile(seed=synth.seed_for(6, i), size=size,
+                                 n_gauss=round(3000 * size * size / 4096 ** 2))[1]
+
+
+PIPE_IN = {"hdome": 1, "fill_holes": 1, "area_threshold": 1, "markers": 1, "label": 1}    # bytes/px read
+PIPE_OUT = {"hdome": 1, "fill_holes": 1, "area_threshold": 1, "markers": 1, "label": 4}   # bytes/px written
+
+
+def pipeline(recon, torch, n_tiles, size, window, cpu_workers, workers, h=20, conn=8, lo=20, hi=1000):
+    """The co-scheduled tile pipeline (hdome -> fill-holes -> area filter ->
+    {Pre-Watershed markers, labels}) on n_tiles nuclei-like tiles from host
+    memory: the GPU alone, then the GPU beside cpu_workers CPU workers under
+    FCFS and PATS, without and with data locality, and PATS with the CPU workers
+    kept off the operations a core would take too long on.  Speedup estimates
+    come from a calibration on one tile (each operation's CPU variant against
+    its GPU variant, computation only); every run's outputs are compared byte
+    for byte with the GPU-only run's, and two tiles with the oracle."""
+    import multiprocessing as mp
+    import numpy as np
+    t0 = time.perf_counter()
+    tiles = [None] * n_tiles
+    with mp.get_context("fork").Pool(workers) as pool:
+        for i, img in pool.imap_unordered(_gen_pipe_tile, [(i, size) for i in range(n_tiles)]):
+            tiles[i] = img
+    log("pipeline: generated %d tiles in %.1f s" % (n_tiles, time.perf_counter() - t0))
+    ops = list(recon.PIPE_OPS)
+    base = dict(conn=conn, h=h, area_min=lo, area_max=hi)
+    # calibration: CPU variants on one tile, one core
+    cpu_ms = {}
+    x = tiles[0]
+    cfg1 = recon.pipe_config(**base)
+    for op in ops:
+        src = x if op in ("hdome", "fill_holes", "area_threshold") else a_img
+        t1 = time.perf_counter()
+        y = recon.recon_pipeline_host_op(op, src, cfg1)
+        cpu_ms[op] = (time.perf_counter() - t1) * 1e3
+        if op in ("hdome", "fill_holes", "area_threshold"):
+            x = y
+        if op == "area_threshold":
+            a_img = y
+    res = {"tiles": n_tiles, "tile": [size, size], "pixels": n_tiles * size * size, "window": window,
+           "cpu_workers": cpu_workers, "gpus": 1, "conn": conn, "h": h, "area": [lo, hi]}
+    with recon.Recon(0) as ctx:
+        # GPU variants on the same tile (3 copies, the last two counted)
+        _, st = recon.recon_pipeline_run(ctx.ctx, [tiles[0]], recon.pipe_config(cpu_workers=0, window=1, **base))
+        _, st = recon.recon_pipeline_run(ctx.ctx, [tiles[0]] * 2, recon.pipe_config(cpu_workers=0, window=1,
+                                                                                      **base))
+        gpu_ms = {op: st["busy_gpu_ms"][k] / max(1, st["ops_gpu"][k]) for k, op in enumerate(ops)}
+        gbs = (st["upload_bytes"] + st["download_bytes"]) / max(st["transfer_ms"], 1e-6) / 1e6
+        speedup = {op: cpu_ms[op] / max(gpu_ms[op], 1e-6) for op in ops}
+        xfer = {op: (PIPE_IN[op] + PIPE_OUT[op]) * size * size / (gbs * 1e6) for op in ops}   # ms at gbs GB/s
+        impact = {op: xfer[op] / (xfer[op] + gpu_ms[op]) for op in ops}
+        res["calibration"] = {"cpu_ms": cpu_ms, "gpu_ms": gpu_ms, "speedup": speedup,
+                              "transfer_GBs": gbs, "transfer_impact": impact}
+        log("pipeline calibration: speedups " + ", ".join("%s %.0f" % (o, speedup[o]) for o in ops))
+        runs = [("gpu_only", dict(policy="pats", cpu_workers=0, data_locality=True)),
+                ("fcfs", dict(policy="fcfs", cpu_workers=cpu_workers, data_locality=False)),
+                ("fcfs_dl", dict(policy="fcfs", cpu_workers=cpu_workers, data_locality=True)),
+                ("pats", dict(policy="pats", cpu_workers=cpu_workers, data_locality=False)),
+                ("pats_dl", dict(policy="pats", cpu_workers=cpu_workers, data_locality=True)),
+                ("pats_dl_cutoff", None)]
+        ref = None
+        res["runs"] = {}
+        for name, kw in runs:
+            if kw is None:
+                # CPU workers may take only the operations whose CPU time is at
+                # most a quarter of the GPU-only makespan of this batch
+                m = res["runs"]["gpu_only"]["makespan_ms"]
+                ok_ops = [o for o in ops if cpu_ms[o] <= m / 4]
+                limit = max((speedup[o] for o in ok_ops), default=0.5 * min(speedup.values()))
+                kw = dict(policy="pats", cpu_workers=cpu_workers, data_locality=True, cpu_max_speedup=limit)
+                res["cutoff"] = {"cpu_max_speedup": limit, "cpu_ops": ok_ops}
+            cfg = recon.pipe_config(window=window, speedup=speedup, transfer_impact=impact, **base, **kw)
+            outs, st = recon.recon_pipeline_run(ctx.ctx, tiles, cfg)
+            r = {"makespan_ms": st["makespan_ms"], "tiles_s": n_tiles / (st["makespan_ms"] * 1e-3),
+                 "Mpixel_s": res["pixels"] / (st["makespan_ms"] * 1e-3) / 1e6,
+                 "ops_cpu": dict(zip(ops, st["ops_cpu"])), "ops_gpu": dict(zip(ops, st["ops_gpu"])),
+                 "uploads": st["uploads"], "downloads": st["downloads"],
+                 "transfer_GB": (st["upload_bytes"] + st["download_bytes"]) / 1e9,
+                 "transfer_ms": st["transfer_ms"], "policy": kw["policy"], "data_locality": kw["data_locality"]}
+            if ref is None:
+                ref = outs
+                for i in (0, n_tiles - 1):
+                    defer_check(("pipeline", "parity_tiles_%d" % i), outs[i], "pipeline_chain", tiles[i], h, conn,
+                                lo, hi)
+                    res["parity_tiles_%d" % i] = None
+            else:
+                r["same_as_gpu_only"] = all(
+                    np.array_equal(o[k], q[k]) for o, q in zip(outs, ref) for k in ("objects", "markers", "labels")
+                ) and all(o["count"] == q["count"] for o, q in zip(outs, ref))
+            res["runs"][name] = r
+            log("pipeline %s: %.1f ms (%.1f tiles/s), CPU ops %s" % (
+                name, r["makespan_ms"], r["tiles_s"], sum(st["ops_cpu"])))
+            del outs
+        g = res["runs"]["gpu_only"]["makespan_ms"]
+        res["speedup_over_gpu_only"] = {k: g / v["makespan_ms"] for k, v in res["runs"].items()}
+        res["pats_over_fcfs"] = res["runs"]["fcfs"]["makespan_ms"] / res["runs"]["pats"]["makespan_ms"]
+        res["pats_dl_over_fcfs_dl"] = res["runs"]["fcfs_dl"]["makespan_ms"] / res["runs"]["pats_dl"]["makespan_ms"]
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -765,6 +883,10 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only copy this many bytes device-to-device 5 times (counter calibration) and exit")
     ap.add_argument("--workers", type=int, default=min(16, len(os.sched_getaffinity(0))))
+    ap.add_argument("--pipeline-tiles", type=int, default=64,
+                    help="tiles of the co-scheduled pipeline section (0 skips it)")
+    ap.add_argument("--pipeline-window", type=int, default=16)
+    ap.add_argument("--pipeline-cpu-workers", type=int, default=max(1, min(16, len(os.sched_getaffinity(0))) - 1))
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the reconstruction shards by tile with no communication, "
@@ -843,6 +965,9 @@ def main():
     if args.serve_rates:
         rates = [int(r) for r in args.serve_rates.split(",") if r]
         out["serving"] = serving(recon, torch, rates, args.serve_seconds, args.serve_pool, args.workers)
+    if args.pipeline_tiles:
+        out["pipeline"] = pipeline(recon, torch, args.pipeline_tiles, args.size, args.pipeline_window,
+                                   args.pipeline_cpu_workers, args.workers)
     ok = True
     if not args.no_cpu_baseline:
         # the oracle leg: its rate on the host cores, then every deferred comparison

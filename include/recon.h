@@ -346,6 +346,111 @@ int recon_last_stats(recon_ctx *ctx, recon_stats *out);
 int recon_launch_times(recon_ctx *ctx, int back, float *dense_ms, float *seed_ms, float *drain_ms,
                        float *total_ms, float *route_ms);
 
+/* ---- Co-scheduled tile pipeline (CPU cores + GPU)
+ *
+ * The paper's runtime maps the operations of each tile's analysis pipeline to
+ * CPU cores and GPUs one operation instance (a tile, operation pair) at a
+ * time, and its Performance Aware Task Scheduling (PATS, Sec. IV-B) orders the
+ * ready instances by their estimated GPU-over-CPU speedup: an idle CPU core
+ * takes the lowest, an idle GPU the highest; first-come-first-served (FCFS)
+ * hands out the oldest.  With data locality (DL, Sec. IV-C) the GPU prefers
+ * an instance whose inputs are in device memory already, unless another
+ * instance's speedup exceeds its own by more than the transfers would cost:
+ * the resident one is taken when S_resident >= S_other * (1 - transfer_impact
+ * of the other's operation).  Without DL every GPU assignment uploads its
+ * inputs and downloads its outputs.  A bounded number of tiles is in flight
+ * (the demand-driven window, Sec. III-B); a finished tile frees its slot for
+ * the next one.  An optional limit keeps the CPU workers off the operations
+ * whose estimated speedup exceeds it (on a GPU hundreds of times faster than
+ * a core, such an instance taken by a core can outlast the whole GPU run).
+ *
+ * The pipeline of each tile, after the MR-based segmentation operations of
+ * Table 1 (every operation's result is unique, so the bytes do not depend on
+ * where each instance ran):
+ *   RECON_PIPE_HDOME    A <- h-dome of the tile, D_h(I)            (ReconToNuclei)
+ *   RECON_PIPE_FILL     A <- fill-holes of A                       (FillHoles)
+ *   RECON_PIPE_AREA     A <- area filter of A, [area_min, area_max] (AreaThreshold)
+ *   RECON_PIPE_MARKERS  B <- Pre-Watershed markers of A            (Pre-Watershed)
+ *   RECON_PIPE_LABEL    L <- labels of A, and their count          (BWLabel)
+ * with the dependencies HDOME -> FILL -> AREA -> {MARKERS, LABEL}.  The GPU
+ * variants are this library's operations; the CPU variants are separate
+ * single-core implementations of the same definitions. */
+enum {
+    RECON_PIPE_HDOME = 0,
+    RECON_PIPE_FILL = 1,
+    RECON_PIPE_AREA = 2,
+    RECON_PIPE_MARKERS = 3,
+    RECON_PIPE_LABEL = 4,
+    RECON_PIPE_NOPS = 5
+};
+enum { RECON_SCHED_FCFS = 0, RECON_SCHED_PATS = 1 };
+
+typedef struct {
+    const uint8_t *image;   /* HOST: the grey tile, height x width, pitch bytes per row */
+    int32_t height, width;  /* 1..16384 each */
+    int64_t pitch;          /* >= width; also the row pitch of objects and markers */
+    uint8_t *objects;       /* HOST out (or NULL): A after the area filter, 255 / 0 */
+    uint8_t *markers;       /* HOST out (or NULL): B, the Pre-Watershed markers, 255 / 0 */
+    int32_t *labels;        /* HOST out (or NULL): L, label_pitch elements per row */
+    int64_t label_pitch;    /* >= width when labels is not NULL */
+    int32_t *count;         /* HOST out (or NULL): the number of labelled components */
+} recon_pipe_tile;
+
+typedef struct {
+    int32_t policy;         /* RECON_SCHED_FCFS or RECON_SCHED_PATS */
+    int32_t cpu_workers;    /* host threads running CPU variants, one core each (0..256) */
+    int32_t use_gpu;        /* 1: a GPU manager thread runs GPU variants through ctx */
+    int32_t window;         /* tiles in flight at once, 1..1024 */
+    int32_t data_locality;  /* 1: DL (the GPU keeps and prefers resident data) */
+    int32_t conn;           /* 4 or 8, every operation */
+    int32_t h;              /* dome height, 1..255 */
+    float cpu_max_speedup;  /* > 0: a CPU worker leaves every instance whose estimated speedup
+                               exceeds it to the GPU (0: no limit, the published PATS/FCFS) */
+    int64_t area_min, area_max;   /* 0 <= area_min <= area_max */
+    float speedup[RECON_PIPE_NOPS];          /* PATS: estimated GPU-over-CPU speedup per operation */
+    float transfer_impact[RECON_PIPE_NOPS];  /* DL with PATS: share of an operation's GPU time
+                                                spent on its transfers, 0..1 */
+} recon_pipe_config;
+
+typedef struct {
+    double makespan_ms;                      /* first admission to the last tile's results */
+    int64_t ops_cpu[RECON_PIPE_NOPS];        /* instances run by CPU workers, per operation */
+    int64_t ops_gpu[RECON_PIPE_NOPS];        /* instances run by the GPU */
+    double busy_cpu_ms[RECON_PIPE_NOPS];     /* summed compute time of those instances */
+    double busy_gpu_ms[RECON_PIPE_NOPS];     /* (GPU: enqueue to completion, transfers excluded) */
+    int64_t uploads, downloads;              /* plane transfers */
+    int64_t upload_bytes, download_bytes;
+    double transfer_ms;                      /* summed time of the transfers */
+} recon_pipe_stats;
+
+/* Run the pipeline on n host tiles and write each tile's outputs.  ctx may be
+ * NULL when use_gpu is 0 (CPU cores only); with use_gpu = 1 the calling
+ * thread's current device must be ctx's, and ctx must not be used by any
+ * other thread until the call returns.  The call allocates, for `window`
+ * tiles, pinned host planes and device planes of 6 bytes per pixel of the
+ * largest tile, and frees them before it returns; it blocks until every tile
+ * is done.  RECON_EINVAL for a bad configuration or tile (use_gpu without a
+ * context, neither a GPU nor a CPU worker, a shape out of range); an operation
+ * or transfer error stops the run and is returned (RECON_EDEVICE,
+ * RECON_ETIMEDOUT after 60 s without progress of a GPU stream, RECON_ENOMEM).
+ * `stats` (may be NULL) receives the run's counters; recon_pipeline_error()
+ * describes a failure. */
+int recon_pipeline_run(recon_ctx *ctx, const recon_pipe_tile *tiles, int32_t n,
+                       const recon_pipe_config *cfg, recon_pipe_stats *stats);
+
+/* Message of the calling thread's last failed recon_pipeline_run or
+ * recon_pipeline_host_op ("" after a success). */
+const char *recon_pipeline_error(void);
+
+/* One pipeline operation's CPU variant on a HOST image, in place (what a CPU
+ * worker of recon_pipeline_run executes, on the calling thread): op is a
+ * RECON_PIPE_* value; cfg supplies conn, h and the area bounds; for
+ * RECON_PIPE_LABEL the HOST labels plane (label_pitch >= width) receives the
+ * labels, *count (if not NULL) their number, and the image is not written.
+ * For calibrating speedup estimates and testing the CPU variants. */
+int recon_pipeline_host_op(int op, recon_image *img, const recon_pipe_config *cfg, int32_t *labels,
+                           int64_t label_pitch, int32_t *count);
+
 /* Message describing the last failure on the calling thread ("" if none). */
 const char *recon_last_error(void);
 

@@ -11,7 +11,11 @@ built library raises; there is no CPU fallback.
 Low-level functions keep the C names (``recon_create``, ``recon_dilate``,
 ``recon_fill_holes``, ``recon_erode``, ``recon_hdome``, ``recon_regional_max``,
 ``recon_batch``, ``recon_submit``, ``recon_poll``, ``recon_wait``, ...);
-``Recon`` wraps a context for convenience.
+``Recon`` wraps a context for convenience.  ``recon_pipeline_run`` runs the
+co-scheduled per-tile pipeline over host tiles: its GPU variants are the HIP
+operations; its CPU variants run in the library's own host code on the CPU
+workers the scheduler is given (the paper's CPU + GPU execution), never as a
+replacement for a missing GPU.
 """
 from __future__ import annotations
 
@@ -33,7 +37,8 @@ EXPORTED = (
     "recon_hdome", "recon_regional_max", "recon_label", "recon_area_threshold", "recon_distance",
     "recon_pre_watershed", "recon_batch",
     "recon_submit", "recon_poll", "recon_wait", "recon_serve_stop", "recon_serve_stats", "recon_last_stats",
-    "recon_launch_times", "recon_last_error",
+    "recon_launch_times", "recon_last_error", "recon_pipeline_run", "recon_pipeline_error",
+    "recon_pipeline_host_op",
 )
 
 
@@ -87,6 +92,34 @@ class recon_serve_counters(ctypes.Structure):
                 ("max_busy_lanes", ctypes.c_int64), ("early_completions", ctypes.c_int64)]
 
 
+# the co-scheduled tile pipeline (recon_pipeline_run)
+PIPE_OPS = ("hdome", "fill_holes", "area_threshold", "markers", "label")
+RECON_SCHED_FCFS, RECON_SCHED_PATS = 0, 1
+POLICIES = {"fcfs": RECON_SCHED_FCFS, "pats": RECON_SCHED_PATS}
+
+
+class recon_pipe_tile(ctypes.Structure):
+    _fields_ = [("image", ctypes.c_void_p), ("height", ctypes.c_int32), ("width", ctypes.c_int32),
+                ("pitch", ctypes.c_int64), ("objects", ctypes.c_void_p), ("markers", ctypes.c_void_p),
+                ("labels", ctypes.c_void_p), ("label_pitch", ctypes.c_int64), ("count", ctypes.c_void_p)]
+
+
+class recon_pipe_config(ctypes.Structure):
+    _fields_ = [("policy", ctypes.c_int32), ("cpu_workers", ctypes.c_int32), ("use_gpu", ctypes.c_int32),
+                ("window", ctypes.c_int32), ("data_locality", ctypes.c_int32), ("conn", ctypes.c_int32),
+                ("h", ctypes.c_int32), ("cpu_max_speedup", ctypes.c_float), ("area_min", ctypes.c_int64),
+                ("area_max", ctypes.c_int64), ("speedup", ctypes.c_float * 5),
+                ("transfer_impact", ctypes.c_float * 5)]
+
+
+class recon_pipe_stats(ctypes.Structure):
+    _fields_ = [("makespan_ms", ctypes.c_double), ("ops_cpu", ctypes.c_int64 * 5),
+                ("ops_gpu", ctypes.c_int64 * 5), ("busy_cpu_ms", ctypes.c_double * 5),
+                ("busy_gpu_ms", ctypes.c_double * 5), ("uploads", ctypes.c_int64), ("downloads", ctypes.c_int64),
+                ("upload_bytes", ctypes.c_int64), ("download_bytes", ctypes.c_int64),
+                ("transfer_ms", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -125,17 +158,24 @@ def load_library(path: str = LIB_PATH):
     lib.recon_launch_times.argtypes = [P, ctypes.c_int, F, F, F, F, F]
     lib.recon_last_error.argtypes = []
     lib.recon_last_error.restype = ctypes.c_char_p
+    lib.recon_pipeline_run.argtypes = [P, ctypes.POINTER(recon_pipe_tile), ctypes.c_int32,
+                                       ctypes.POINTER(recon_pipe_config), ctypes.POINTER(recon_pipe_stats)]
+    lib.recon_pipeline_error.argtypes = []
+    lib.recon_pipeline_error.restype = ctypes.c_char_p
+    lib.recon_pipeline_host_op.argtypes = [ctypes.c_int, ctypes.POINTER(recon_image),
+                                           ctypes.POINTER(recon_pipe_config), P, ctypes.c_int64, P]
     for name in EXPORTED:
-        if name != "recon_last_error":
+        if name not in ("recon_last_error", "recon_pipeline_error"):
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
 
 
-def _check(rc):
+def _check(rc, msg=None):
     if rc == RECON_OK:
         return
-    msg = _lib.recon_last_error().decode(errors="replace")
+    if msg is None:
+        msg = _lib.recon_last_error().decode(errors="replace")
     if rc == RECON_EAGAIN:
         raise ReconAgain(rc, msg)
     if rc == RECON_ETIMEDOUT:
@@ -311,6 +351,93 @@ def recon_last_stats(ctx: int) -> dict:
 
 def recon_last_error() -> str:
     return load_library().recon_last_error().decode(errors="replace")
+
+
+def pipe_config(policy: str = "pats", cpu_workers: int = 0, use_gpu: bool = True, window: int = 8,
+                data_locality: bool = True, conn: int = 8, h: int = 20, area_min: int = 20, area_max: int = 1000,
+                speedup=None, transfer_impact=None, cpu_max_speedup: float = 0.0) -> recon_pipe_config:
+    """recon_pipe_config; speedup / transfer_impact: dicts or sequences over PIPE_OPS."""
+    c = recon_pipe_config()
+    if policy not in POLICIES:
+        raise ValueError("policy must be one of %s" % ", ".join(POLICIES))
+    c.policy = POLICIES[policy]
+    c.cpu_workers, c.use_gpu, c.window = int(cpu_workers), int(bool(use_gpu)), int(window)
+    c.data_locality, c.conn, c.h = int(bool(data_locality)), int(conn), int(h)
+    c.area_min, c.area_max = int(area_min), int(area_max)
+    c.cpu_max_speedup = float(cpu_max_speedup)
+
+    def seq(v, default):
+        if v is None:
+            return [default] * 5
+        if isinstance(v, dict):
+            return [float(v.get(k, default)) for k in PIPE_OPS]
+        return [float(x) for x in v]
+    for i, x in enumerate(seq(speedup, 1.0)):
+        c.speedup[i] = x
+    for i, x in enumerate(seq(transfer_impact, 0.0)):
+        c.transfer_impact[i] = x
+    return c
+
+
+def recon_pipeline_run(ctx, images, cfg: recon_pipe_config):
+    """Run the tile pipeline on host uint8 numpy images (ctx may be None
+    without the GPU).  Returns (outputs, stats): per tile a dict of `objects`,
+    `markers` (uint8) and `labels` (int32) numpy arrays and `count`; stats as a dict."""
+    import numpy as np
+    lib = load_library()
+    n = len(images)
+    imgs = [np.ascontiguousarray(im, dtype=np.uint8) for im in images]
+    outs = []
+    arr = (recon_pipe_tile * max(n, 1))()
+    counts = (ctypes.c_int32 * max(n, 1))()
+    for i, im in enumerate(imgs):
+        if im.ndim != 2:
+            raise ValueError("images must be 2-D")
+        o = {"objects": np.empty_like(im), "markers": np.empty_like(im),
+             "labels": np.empty(im.shape, dtype=np.int32)}
+        outs.append(o)
+        t = arr[i]
+        t.image = im.ctypes.data
+        t.height, t.width = im.shape
+        t.pitch = im.strides[0]
+        t.objects, t.markers, t.labels = o["objects"].ctypes.data, o["markers"].ctypes.data, o["labels"].ctypes.data
+        t.label_pitch = im.shape[1]
+        t.count = ctypes.addressof(counts) + 4 * i
+    st = recon_pipe_stats()
+    rc = lib.recon_pipeline_run(ctx, arr, n, ctypes.byref(cfg), ctypes.byref(st))
+    _check(rc, lib.recon_pipeline_error().decode(errors="replace"))
+    for i, o in enumerate(outs):
+        o["count"] = int(counts[i])
+    stats = {}
+    for f, _ in recon_pipe_stats._fields_:
+        v = getattr(st, f)
+        stats[f] = list(v) if not isinstance(v, (int, float)) else v
+    return outs, stats
+
+
+def recon_pipeline_error() -> str:
+    """Message of the calling thread's last failed pipeline call."""
+    return load_library().recon_pipeline_error().decode(errors="replace")
+
+
+def recon_pipeline_host_op(op: str, image, cfg: recon_pipe_config):
+    """One operation's CPU variant on a host uint8 numpy image (a copy is
+    returned); for "label" returns (labels, count)."""
+    import numpy as np
+    lib = load_library()
+    if op not in PIPE_OPS:
+        raise ValueError("op must be one of %s" % ", ".join(PIPE_OPS))
+    im = np.array(image, dtype=np.uint8, copy=True, order="C")
+    if im.ndim != 2:
+        raise ValueError("image must be 2-D")
+    ri = recon_image(im.ctypes.data, im.shape[0], im.shape[1], im.strides[0])
+    labels = np.empty(im.shape, dtype=np.int32) if op == "label" else None
+    cnt = ctypes.c_int32(0)
+    rc = lib.recon_pipeline_host_op(PIPE_OPS.index(op), ctypes.byref(ri), ctypes.byref(cfg),
+                                    labels.ctypes.data if labels is not None else None,
+                                    im.shape[1], ctypes.byref(cnt))
+    _check(rc, lib.recon_pipeline_error().decode(errors="replace"))
+    return (labels, int(cnt.value)) if op == "label" else im
 
 
 class Recon:

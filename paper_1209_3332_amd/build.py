@@ -13,6 +13,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRC = os.path.join(HERE, "csrc", "recon.hip")
+# host-only translation units: the tile-pipeline scheduler and its CPU variants
+HOST_SRCS = [os.path.join(HERE, "csrc", f) for f in ("pipeline.cpp", "host_ops.cpp")]
 LIB = os.path.join(HERE, "librecon.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -29,9 +31,9 @@ FLAGS = [
 
 
 def build(verbose: bool = False) -> str:
-    """Compile csrc/recon.hip into librecon.so (always recompiles)."""
+    """Compile csrc/recon.hip and the host sources into librecon.so (always recompiles)."""
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC] + FLAGS + ["-o", tmp, SRC]
+    cmd = [HIPCC] + FLAGS + ["-o", tmp, SRC] + HOST_SRCS
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -1,0 +1,574 @@
+// pipeline.cpp -- co-scheduling of a per-tile operation pipeline over the host
+// cores and the GPU (see recon_pipeline_run in include/recon.h).
+//
+// The paper's Worker turns every tile into a graph of operation instances, the
+// (tile, operation) tuples, and maps each ready instance to an idle CPU core or
+// GPU (Sec. IV-B).  First-come-first-served hands the oldest ready instance to
+// whichever device asks.  PATS keeps the ready instances sorted by their
+// estimated GPU-over-CPU speedup: an idle CPU core takes the one with the
+// lowest estimate, an idle GPU the one with the highest.  Data locality
+// (Sec. IV-C) lets the GPU prefer an instance whose inputs are already in
+// device memory, unless a non-resident one is expected to gain more than the
+// transfers cost it.  The Worker holds a bounded number of tiles in flight
+// (the demand-driven window of Sec. III-B): a finished tile frees a slot for
+// the next one.
+//
+// Threads: one GPU manager thread (it calls the library's operations on its
+// own stream and waits for each instance) and `cpu_workers` CPU threads (each
+// runs the CPU variants of host_ops.cpp on one core).  Every tile slot owns
+// pinned host planes and device planes for the tile's data; a per-plane bit
+// set records where a valid copy lives, and a device moves a plane only when
+// it lacks a valid copy.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/recon.h"
+#include "host_ops.hpp"
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+thread_local std::string g_pipe_err;   // message of the calling thread's last failed pipeline call
+
+double ms_since(Clock::time_point t0) {
+    return std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
+}
+
+// The tile's planes: A carries the image through the dome, fill-holes and area
+// operations (each in place); B the markers; L the labels (int32) and the count.
+enum Plane { PA = 0, PB = 1, PL = 2, NPLANES = 3 };
+enum : uint8_t { ON_HOST = 1, ON_DEV = 2 };
+
+struct OpShape {
+    uint8_t in_mask;    // planes read
+    uint8_t out_mask;   // planes written
+    int next[2];        // dependent operations (-1: none)
+    int deps;           // operations it waits for
+};
+
+// hdome -> fill-holes -> area -> {markers, labels}
+constexpr OpShape kOps[RECON_PIPE_NOPS] = {
+    {1u << PA, 1u << PA, {RECON_PIPE_FILL, -1}, 0},
+    {1u << PA, 1u << PA, {RECON_PIPE_AREA, -1}, 1},
+    {1u << PA, 1u << PA, {RECON_PIPE_MARKERS, RECON_PIPE_LABEL}, 1},
+    {1u << PA, 1u << PB, {-1, -1}, 1},
+    {1u << PA, 1u << PL, {-1, -1}, 1},
+};
+
+struct Slot {
+    int tile = -1;                       // tile in the slot, -1 when free
+    uint8_t *h[NPLANES] = {};            // pinned host planes
+    uint8_t *d[NPLANES] = {};            // device planes
+    int32_t *d_count = nullptr;          // device component count
+    int32_t h_count = 0;
+    // ON_HOST | ON_DEV per plane: written under xfer_mu, read by the scheduler
+    // without it (a stale read only changes a placement preference)
+    std::atomic<uint8_t> where[NPLANES];
+    std::mutex xfer_mu;                  // one transfer of a slot's planes at a time
+    int waiting[RECON_PIPE_NOPS] = {};   // unfinished dependencies per operation
+    int left = 0;                        // unfinished operations of the tile
+    Slot() {
+        for (auto &w : where) w.store(0);
+    }
+};
+
+struct Ready {
+    int slot, op;
+    uint64_t seq;   // order of becoming ready (FCFS)
+    float speedup;
+};
+
+struct Device {
+    bool gpu;
+    hipStream_t stream = nullptr;
+    hostops::Scratch *scratch = nullptr;
+};
+
+struct Run {
+    recon_ctx *ctx;
+    const recon_pipe_tile *tiles;
+    int n;
+    recon_pipe_config cfg;
+    int H = 0, W = 0;            // plane geometry of the slots (largest tile)
+    int64_t pitch = 0;           // bytes per row of the uint8 planes
+    int64_t lpitch = 0;          // elements per row of the label plane
+    std::unique_ptr<Slot[]> slots;
+    int nslots = 0;
+    std::vector<Ready> ready;
+    std::mutex mu;
+    std::condition_variable cv;
+    uint64_t seq = 0;
+    int next_tile = 0, done_tiles = 0;
+    int err = RECON_OK;
+    std::string err_msg;
+    recon_pipe_stats st{};
+    int device = 0;
+
+    size_t plane_bytes(int p) const { return p == PL ? (size_t)H * lpitch * 4 : (size_t)H * pitch; }
+};
+
+int set_err(Run &r, int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    std::lock_guard<std::mutex> g(r.mu);
+    if (r.err == RECON_OK) {
+        r.err = code;
+        r.err_msg = buf;
+    }
+    r.cv.notify_all();
+    return code;
+}
+
+#define PIPE_HIP(run, expr)                                                                  \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return set_err(run, RECON_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+int sync_stream(Run &r, hipStream_t s) {
+    const auto t0 = Clock::now();
+    while (true) {
+        hipError_t q = hipStreamQuery(s);
+        if (q == hipSuccess) return RECON_OK;
+        if (q != hipErrorNotReady)
+            return set_err(r, RECON_EDEVICE, "pipeline stream failed: %s", hipGetErrorString(q));
+        if (ms_since(t0) > 60000.0) return set_err(r, RECON_ETIMEDOUT, "pipeline stream wait exceeded 60 s");
+        std::this_thread::sleep_for(std::chrono::microseconds(20));
+    }
+}
+
+// Copy plane p of the slot to the device or to the host on stream s (not waited for).
+int move_plane(Run &r, Slot &sl, int p, bool to_dev, hipStream_t s) {
+    const int th = r.tiles[sl.tile].height, tw = r.tiles[sl.tile].width;
+    const size_t row = p == PL ? (size_t)tw * 4 : (size_t)tw;
+    const size_t pitch = p == PL ? (size_t)r.lpitch * 4 : (size_t)r.pitch;
+    if (to_dev)
+        PIPE_HIP(r, hipMemcpy2DAsync(sl.d[p], pitch, sl.h[p], pitch, row, th, hipMemcpyHostToDevice, s));
+    else
+        PIPE_HIP(r, hipMemcpy2DAsync(sl.h[p], pitch, sl.d[p], pitch, row, th, hipMemcpyDeviceToHost, s));
+    if (p == PL && !to_dev)
+        PIPE_HIP(r, hipMemcpyAsync(&sl.h_count, sl.d_count, 4, hipMemcpyDeviceToHost, s));
+    return RECON_OK;
+}
+
+// Make the planes in `mask` valid on the host (to_dev false) or on the device,
+// copying those that lack a valid copy there (under the slot's transfer lock,
+// so two devices never move the same plane at once).  `exclusive` leaves the
+// copies only where they were brought (the basic mode, which reuses nothing).
+int stage(Run &r, Slot &sl, uint8_t mask, bool to_dev, hipStream_t s, bool exclusive = false) {
+    const uint8_t want = to_dev ? ON_DEV : ON_HOST;
+    std::lock_guard<std::mutex> xg(sl.xfer_mu);
+    uint8_t moved = 0;
+    const auto t0 = Clock::now();
+    int64_t bytes = 0;
+    for (int p = 0; p < NPLANES; ++p) {
+        if (!(mask & (1u << p)) || (sl.where[p].load() & want)) continue;
+        int rc = move_plane(r, sl, p, to_dev, s);
+        if (rc) return rc;
+        moved |= (uint8_t)(1u << p);
+        bytes += (int64_t)r.tiles[sl.tile].height * r.tiles[sl.tile].width * (p == PL ? 4 : 1);
+    }
+    if (!moved) return RECON_OK;
+    int rc = sync_stream(r, s);
+    if (rc) return rc;
+    for (int p = 0; p < NPLANES; ++p)
+        if (moved & (1u << p)) sl.where[p].store(exclusive ? want : (uint8_t)(sl.where[p].load() | want));
+    const double ms = ms_since(t0);
+    std::lock_guard<std::mutex> g(r.mu);
+    const int n = __builtin_popcount(moved);
+    if (to_dev) {
+        r.st.uploads += n;
+        r.st.upload_bytes += bytes;
+    } else {
+        r.st.downloads += n;
+        r.st.download_bytes += bytes;
+    }
+    r.st.transfer_ms += ms;
+    return RECON_OK;
+}
+
+recon_image dev_image(Run &r, Slot &sl, int p) {
+    recon_image im;
+    im.data = sl.d[p];
+    im.height = r.tiles[sl.tile].height;
+    im.width = r.tiles[sl.tile].width;
+    im.pitch = r.pitch;
+    return im;
+}
+
+int gpu_compute(Run &r, Slot &sl, int op, hipStream_t s) {
+    const recon_pipe_config &c = r.cfg;
+    recon_image a = dev_image(r, sl, PA);
+    int rc = RECON_OK;
+    switch (op) {
+        case RECON_PIPE_HDOME: rc = recon_hdome(r.ctx, &a, c.h, c.conn, s); break;
+        case RECON_PIPE_FILL: rc = recon_fill_holes(r.ctx, &a, c.conn, s); break;
+        case RECON_PIPE_AREA: rc = recon_area_threshold(r.ctx, &a, c.conn, c.area_min, c.area_max, s); break;
+        case RECON_PIPE_MARKERS: {
+            recon_image b = dev_image(r, sl, PB);
+            PIPE_HIP(r, hipMemcpy2DAsync(b.data, r.pitch, a.data, r.pitch, a.width, a.height,
+                                         hipMemcpyDeviceToDevice, s));
+            rc = recon_pre_watershed(r.ctx, &b, c.conn, s);
+            break;
+        }
+        case RECON_PIPE_LABEL:
+            rc = recon_label(r.ctx, &a, (int32_t *)sl.d[PL], r.lpitch, c.conn, sl.d_count, s);
+            break;
+    }
+    if (rc) return set_err(r, rc, "GPU operation %d failed: %s", op, recon_last_error());
+    return sync_stream(r, s);
+}
+
+int cpu_compute(Run &r, Slot &sl, int op, hostops::Scratch *scr) {
+    const recon_pipe_config &c = r.cfg;
+    const recon_pipe_tile &t = r.tiles[sl.tile];
+    hostops::Plane a{sl.h[PA], t.height, t.width, r.pitch};
+    try {
+        switch (op) {
+            case RECON_PIPE_HDOME: hostops::hdome(scr, a, c.h, c.conn); break;
+            case RECON_PIPE_FILL: hostops::fill_holes(scr, a, c.conn); break;
+            case RECON_PIPE_AREA: hostops::area_threshold(scr, a, c.conn, c.area_min, c.area_max); break;
+            case RECON_PIPE_MARKERS: {
+                hostops::Plane b{sl.h[PB], t.height, t.width, r.pitch};
+                for (int y = 0; y < t.height; ++y) std::memcpy(b.row(y), a.row(y), t.width);
+                hostops::pre_watershed(scr, b, c.conn);
+                break;
+            }
+            case RECON_PIPE_LABEL:
+                sl.h_count = hostops::label(scr, a, (int32_t *)sl.h[PL], r.lpitch, c.conn);
+                break;
+        }
+    } catch (const std::exception &e) {
+        return set_err(r, RECON_ENOMEM, "CPU operation %d failed: %s", op, e.what());
+    }
+    return RECON_OK;
+}
+
+// ---- admission and the ready list
+
+// Reserve free slots for the next tiles (under r.mu); returns the slots whose
+// image the caller copies in (outside the lock) before calling release_loaded.
+std::vector<int> reserve(Run &r) {
+    std::vector<int> got;
+    for (int k = 0; k < r.nslots && r.next_tile < r.n; ++k) {
+        Slot &sl = r.slots[k];
+        if (sl.tile >= 0) continue;
+        sl.tile = r.next_tile++;
+        got.push_back(k);
+    }
+    return got;
+}
+
+void load(Run &r, int k) {
+    Slot &sl = r.slots[k];
+    const recon_pipe_tile &t = r.tiles[sl.tile];
+    for (int y = 0; y < t.height; ++y)
+        std::memcpy(sl.h[PA] + (int64_t)y * r.pitch, t.image + (int64_t)y * t.pitch, t.width);
+    sl.where[PA].store(ON_HOST);
+    sl.where[PB].store(0);
+    sl.where[PL].store(0);
+    sl.left = RECON_PIPE_NOPS;
+    for (int o = 0; o < RECON_PIPE_NOPS; ++o) sl.waiting[o] = kOps[o].deps;
+}
+
+void admit(Run &r) {
+    std::vector<int> got;
+    {
+        std::lock_guard<std::mutex> g(r.mu);
+        got = reserve(r);
+    }
+    for (int k : got) load(r, k);
+    std::lock_guard<std::mutex> g(r.mu);
+    for (int k : got) r.ready.push_back({k, RECON_PIPE_HDOME, r.seq++, r.cfg.speedup[RECON_PIPE_HDOME]});
+    if (!got.empty()) r.cv.notify_all();
+}
+
+bool resident(const Run &r, const Ready &x) {
+    const Slot &sl = r.slots[x.slot];
+    for (int p = 0; p < NPLANES; ++p)
+        if ((kOps[x.op].in_mask & (1u << p)) && !(sl.where[p].load() & ON_DEV)) return false;
+    return true;
+}
+
+// Index (in r.ready) of the instance the device takes next, or -1 (under r.mu).
+int pick(const Run &r, bool gpu) {
+    const auto &q = r.ready;
+    if (q.empty()) return -1;
+    const bool pats = r.cfg.policy == RECON_SCHED_PATS;
+    auto before = [&](const Ready &a, const Ready &b) {
+        if (pats && a.speedup != b.speedup) return gpu ? a.speedup > b.speedup : a.speedup < b.speedup;
+        return a.seq < b.seq;
+    };
+    // a CPU worker may be kept off the instances a core would take too long on
+    const float limit = gpu ? 0.0f : r.cfg.cpu_max_speedup;
+    int best = -1;
+    for (int i = 0; i < (int)q.size(); ++i)
+        if ((limit <= 0.0f || q[i].speedup <= limit) && (best < 0 || before(q[i], q[best]))) best = i;
+    if (!gpu || !r.cfg.data_locality || best < 0) return best;
+    // data locality: the preferred instance among those whose inputs are in
+    // device memory already
+    int local = -1;
+    for (int i = 0; i < (int)q.size(); ++i)
+        if (resident(r, q[i]) && (local < 0 || before(q[i], q[local]))) local = i;
+    if (local < 0 || local == best) return best;
+    if (!pats) return local;   // without speedup estimates, reuse the data
+    const float impact = r.cfg.transfer_impact[q[best].op];
+    return q[local].speedup >= q[best].speedup * (1.0f - impact) ? local : best;
+}
+
+// Mark op of the slot done and queue the operations it releases (under r.mu);
+// true if it was the tile's last.
+bool complete(Run &r, int slot, int op) {
+    Slot &sl = r.slots[slot];
+    for (int k = 0; k < 2; ++k) {
+        const int nx = kOps[op].next[k];
+        if (nx >= 0 && --sl.waiting[nx] == 0) r.ready.push_back({slot, nx, r.seq++, r.cfg.speedup[nx]});
+    }
+    return --sl.left == 0;
+}
+
+// The tile's last operation finished: bring its results to the host, copy them
+// out, free the slot and admit the next tile.
+int finish_tile(Run &r, int slot, hipStream_t s) {
+    Slot &sl = r.slots[slot];
+    int rc = stage(r, sl, (1u << PA) | (1u << PB) | (1u << PL), false, s);
+    if (rc) return rc;
+    const recon_pipe_tile &t = r.tiles[sl.tile];
+    for (int y = 0; y < t.height; ++y) {
+        if (t.objects) std::memcpy(t.objects + (int64_t)y * t.pitch, sl.h[PA] + (int64_t)y * r.pitch, t.width);
+        if (t.markers) std::memcpy(t.markers + (int64_t)y * t.pitch, sl.h[PB] + (int64_t)y * r.pitch, t.width);
+        if (t.labels)
+            std::memcpy(t.labels + (int64_t)y * t.label_pitch, sl.h[PL] + (int64_t)y * r.lpitch * 4,
+                        (size_t)t.width * 4);
+    }
+    if (t.count) *t.count = sl.h_count;
+    {
+        std::lock_guard<std::mutex> g(r.mu);
+        sl.tile = -1;
+        ++r.done_tiles;
+        r.cv.notify_all();
+    }
+    admit(r);
+    return RECON_OK;
+}
+
+void worker(Run &r, Device dev) {
+    if (r.cfg.use_gpu && hipSetDevice(r.device) != hipSuccess) {
+        set_err(r, RECON_EDEVICE, "hipSetDevice failed in a pipeline thread");
+        return;
+    }
+    const bool basic = dev.gpu && !r.cfg.data_locality;
+    while (true) {
+        int slot, op;
+        {
+            std::unique_lock<std::mutex> lk(r.mu);
+            int i = -1;
+            r.cv.wait(lk, [&] { return r.err || r.done_tiles == r.n || (i = pick(r, dev.gpu)) >= 0; });
+            if (r.err || r.done_tiles == r.n) return;
+            slot = r.ready[i].slot;
+            op = r.ready[i].op;
+            r.ready.erase(r.ready.begin() + i);
+        }
+        Slot &sl = r.slots[slot];
+        const uint8_t in = kOps[op].in_mask, out = kOps[op].out_mask;
+        if (stage(r, sl, in, dev.gpu, dev.stream)) return;
+        const auto t0 = Clock::now();
+        if (dev.gpu ? gpu_compute(r, sl, op, dev.stream) : cpu_compute(r, sl, op, dev.scratch)) return;
+        const double ms = ms_since(t0);
+        {
+            // an in-place write leaves the only valid copy where it was made
+            std::lock_guard<std::mutex> xg(sl.xfer_mu);
+            for (int p = 0; p < NPLANES; ++p)
+                if (out & (1u << p)) sl.where[p].store(dev.gpu ? ON_DEV : ON_HOST);
+        }
+        // the basic mode brings every GPU assignment's outputs back to the host
+        // (and its inputs in again next time): no data stays on the device
+        if (basic && stage(r, sl, out, false, dev.stream, true)) return;
+        if (basic) {
+            std::lock_guard<std::mutex> xg(sl.xfer_mu);
+            for (int p = 0; p < NPLANES; ++p)
+                if (in & (1u << p)) sl.where[p].store(sl.where[p].load() & (uint8_t)~ON_DEV);
+        }
+        bool last;
+        {
+            std::lock_guard<std::mutex> g(r.mu);
+            if (dev.gpu) {
+                r.st.ops_gpu[op]++;
+                r.st.busy_gpu_ms[op] += ms;
+            } else {
+                r.st.ops_cpu[op]++;
+                r.st.busy_cpu_ms[op] += ms;
+            }
+            last = complete(r, slot, op);
+            r.cv.notify_all();
+        }
+        if (last && finish_tile(r, slot, dev.stream)) return;
+    }
+}
+
+int check_config(const recon_pipe_config *c, recon_ctx *ctx) {
+    if (c->policy != RECON_SCHED_FCFS && c->policy != RECON_SCHED_PATS) return 1;
+    if (c->cpu_workers < 0 || c->cpu_workers > 256 || c->window < 1 || c->window > 1024) return 1;
+    if (c->use_gpu && !ctx) return 1;
+    if (!c->use_gpu && c->cpu_workers == 0) return 1;
+    if (c->conn != 4 && c->conn != 8) return 1;
+    if (c->h < 1 || c->h > 255 || c->area_min < 0 || c->area_max < c->area_min) return 1;
+    if (!(c->cpu_max_speedup >= 0.0f)) return 1;
+    // without a GPU the CPU workers must be able to take every operation
+    if (!c->use_gpu && c->cpu_max_speedup > 0.0f)
+        for (int o = 0; o < RECON_PIPE_NOPS; ++o)
+            if (c->speedup[o] > c->cpu_max_speedup) return 1;
+    return 0;
+}
+
+int invalid(const char *what) {
+    g_pipe_err = what;
+    return RECON_EINVAL;
+}
+
+}  // namespace
+
+extern "C" const char *recon_pipeline_error(void) { return g_pipe_err.c_str(); }
+
+extern "C" int recon_pipeline_run(recon_ctx *ctx, const recon_pipe_tile *tiles, int32_t n,
+                                  const recon_pipe_config *cfg, recon_pipe_stats *stats) {
+    if (!tiles || n < 0 || !cfg) return invalid("null tiles or configuration, or n < 0");
+    if (check_config(cfg, ctx)) return invalid("bad pipeline configuration");
+    Run r;
+    r.ctx = ctx;
+    r.tiles = tiles;
+    r.n = n;
+    r.cfg = *cfg;
+    for (int i = 0; i < n; ++i) {
+        const recon_pipe_tile &t = tiles[i];
+        if (!t.image || t.height < 1 || t.width < 1 || t.pitch < t.width || t.height > 16384 || t.width > 16384 ||
+            (t.labels && t.label_pitch < t.width))
+            return invalid("bad tile shape, pitch or label pitch");
+        r.H = std::max(r.H, t.height);
+        r.W = std::max(r.W, t.width);
+    }
+    if (n == 0) {
+        if (stats) *stats = recon_pipe_stats{};
+        return RECON_OK;
+    }
+    r.pitch = (r.W + 255) / 256 * 256;
+    r.lpitch = r.pitch;
+    if (cfg->use_gpu && hipGetDevice(&r.device) != hipSuccess) {
+        g_pipe_err = "hipGetDevice failed";
+        return RECON_EDEVICE;
+    }
+
+    r.nslots = std::min(cfg->window, n);
+    r.slots.reset(new Slot[r.nslots]);
+    int rc = RECON_OK;
+    for (int k = 0; k < r.nslots; ++k) {
+        Slot &sl = r.slots[k];
+        for (int p = 0; p < NPLANES && rc == RECON_OK; ++p) {
+            if (cfg->use_gpu) {
+                if (hipHostMalloc((void **)&sl.h[p], r.plane_bytes(p), hipHostMallocDefault) != hipSuccess ||
+                    hipMalloc((void **)&sl.d[p], r.plane_bytes(p)) != hipSuccess)
+                    rc = RECON_ENOMEM;
+            } else {
+                sl.h[p] = (uint8_t *)malloc(r.plane_bytes(p));
+                if (!sl.h[p]) rc = RECON_ENOMEM;
+            }
+        }
+        if (rc == RECON_OK && cfg->use_gpu && hipMalloc((void **)&sl.d_count, 4) != hipSuccess) rc = RECON_ENOMEM;
+    }
+    if (rc) r.err_msg = "allocation of the tile slots failed";
+    std::vector<Device> devs;
+    if (rc == RECON_OK && cfg->use_gpu) {
+        Device g;
+        g.gpu = true;
+        if (hipStreamCreateWithFlags(&g.stream, hipStreamNonBlocking) != hipSuccess) rc = RECON_EDEVICE;
+        devs.push_back(g);
+    }
+    for (int k = 0; rc == RECON_OK && k < cfg->cpu_workers; ++k) {
+        Device c;
+        c.gpu = false;
+        c.scratch = hostops::scratch_new();
+        if (cfg->use_gpu && hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking) != hipSuccess)
+            rc = RECON_EDEVICE;
+        devs.push_back(c);
+    }
+    if (rc && r.err_msg.empty()) r.err_msg = "stream creation failed";
+    if (rc == RECON_OK) {
+        const auto t0 = Clock::now();
+        admit(r);
+        std::vector<std::thread> th;
+        for (auto &d : devs) th.emplace_back(worker, std::ref(r), d);
+        for (auto &t : th) t.join();
+        r.st.makespan_ms = ms_since(t0);
+        rc = r.err;
+    }
+    for (auto &d : devs) {
+        if (d.stream) (void)hipStreamDestroy(d.stream);
+        if (d.scratch) hostops::scratch_free(d.scratch);
+    }
+    for (int k = 0; k < r.nslots; ++k) {
+        Slot &sl = r.slots[k];
+        for (int p = 0; p < NPLANES; ++p) {
+            if (cfg->use_gpu) {
+                if (sl.h[p]) (void)hipHostFree(sl.h[p]);
+                if (sl.d[p]) (void)hipFree(sl.d[p]);
+            } else {
+                free(sl.h[p]);
+            }
+        }
+        if (sl.d_count) (void)hipFree(sl.d_count);
+    }
+    g_pipe_err = rc == RECON_OK ? std::string() : r.err_msg;
+    if (stats) *stats = r.st;
+    return rc;
+}
+
+extern "C" int recon_pipeline_host_op(int op, recon_image *img, const recon_pipe_config *cfg, int32_t *labels,
+                                      int64_t label_pitch, int32_t *count) {
+    if (!img || !img->data || !cfg || img->height < 1 || img->width < 1 || img->pitch < img->width)
+        return invalid("null image or configuration, or bad shape or pitch");
+    if (cfg->conn != 4 && cfg->conn != 8) return invalid("conn must be 4 or 8");
+    if (op == RECON_PIPE_HDOME && (cfg->h < 1 || cfg->h > 255)) return invalid("h must be in 1..255");
+    if (op == RECON_PIPE_AREA && (cfg->area_min < 0 || cfg->area_max < cfg->area_min))
+        return invalid("bad area bounds");
+    if (op == RECON_PIPE_LABEL && (!labels || label_pitch < img->width)) return invalid("bad labels plane");
+    if (op < 0 || op >= RECON_PIPE_NOPS) return invalid("unknown pipeline operation");
+    hostops::Scratch *s = hostops::scratch_new();
+    hostops::Plane a{img->data, img->height, img->width, img->pitch};
+    int rc = RECON_OK;
+    try {
+        switch (op) {
+            case RECON_PIPE_HDOME: hostops::hdome(s, a, cfg->h, cfg->conn); break;
+            case RECON_PIPE_FILL: hostops::fill_holes(s, a, cfg->conn); break;
+            case RECON_PIPE_AREA: hostops::area_threshold(s, a, cfg->conn, cfg->area_min, cfg->area_max); break;
+            case RECON_PIPE_MARKERS: hostops::pre_watershed(s, a, cfg->conn); break;
+            case RECON_PIPE_LABEL: {
+                const int32_t c = hostops::label(s, a, labels, label_pitch, cfg->conn);
+                if (count) *count = c;
+                break;
+            }
+        }
+    } catch (const std::exception &e) {
+        g_pipe_err = e.what();
+        rc = RECON_ENOMEM;
+    }
+    hostops::scratch_free(s);
+    if (rc == RECON_OK) g_pipe_err.clear();
+    return rc;
+}

@@ -64,3 +64,23 @@ def test_repeated_path_is_the_conjunction(oracle_mod):
     for got in (good, good):
         b.defer_check(("batch", "parity_ok"), got, "recon_dilate", marker, mask, 8)
     assert b.run_checks(out) and out["batch"]["parity_ok"] is True
+
+
+def test_pipeline_chain_check(oracle_mod):
+    """The tile pipeline's outputs are checked against the oracle's chain of the
+    same operations; a wrong marker pixel or count is reported."""
+    b = _bench()
+    import synth
+    img = synth.scaled_config1_tile(96, 130, synth.seed_for(9, 40))
+    a = oracle_mod.area_threshold(oracle_mod.fill_holes(oracle_mod.hdome(img, 20, 8), 8), 20, 1000, 8)
+    lab, n = oracle_mod.label(a, 8)
+    good = {"objects": a, "markers": oracle_mod.pre_watershed(a, 8), "labels": lab, "count": n}
+    bad = dict(good, markers=good["markers"].copy())
+    bad["markers"][3, 4] ^= 255
+    out = {"pipeline": {"parity_tiles_0": None, "parity_tiles_1": None, "parity_tiles_2": None}}
+    b.CHECKS.clear()
+    b.defer_check(("pipeline", "parity_tiles_0"), good, "pipeline_chain", img, 20, 8, 20, 1000)
+    b.defer_check(("pipeline", "parity_tiles_1"), bad, "pipeline_chain", img, 20, 8, 20, 1000)
+    b.defer_check(("pipeline", "parity_tiles_2"), dict(good, count=n + 1), "pipeline_chain", img, 20, 8, 20, 1000)
+    assert not b.run_checks(out)
+    assert out["pipeline"] == {"parity_tiles_0": True, "parity_tiles_1": False, "parity_tiles_2": False}

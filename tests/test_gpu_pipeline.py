@@ -1,0 +1,111 @@
+"""GPU parity of the co-scheduled tile pipeline (recon_pipeline_run) through
+the C ABI: the GPU alone and the GPU beside CPU workers, under FCFS and PATS,
+with and without data locality, at several window sizes.  Wherever each
+operation instance runs, every tile's outputs must equal the oracle's
+composition of the same operations (integer work: tolerance 0).  Inputs are
+seeded synthetic nuclei-like tiles of several shapes (ragged ones included)."""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+H, LO, HI = 20, 20, 1000
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def lib(torch_mod):
+    import paper_1209_3332_amd as p
+    return p
+
+
+@pytest.fixture(scope="module")
+def rc(lib):
+    ctx = lib.Recon(0)
+    yield ctx
+    ctx.close()
+
+
+@pytest.fixture(scope="module")
+def tiles():
+    rng = np.random.default_rng(31)
+    return [synth.scaled_config1_tile(512, 512, synth.seed_for(9, 20)),
+            synth.scaled_config1_tile(300, 410, synth.seed_for(9, 21)),
+            synth.scaled_config1_tile(777, 259, synth.seed_for(9, 22)),
+            rng.integers(0, 256, size=(1, 97), dtype=np.uint8),
+            synth.scaled_config1_tile(256, 1024, synth.seed_for(9, 23)),
+            np.zeros((19, 5), np.uint8),
+            synth.scaled_config1_tile(640, 480, synth.seed_for(9, 24))]
+
+
+@pytest.fixture(scope="module")
+def expected(tiles, oracle_mod):
+    out = {}
+    for conn in (4, 8):
+        res = []
+        for img in tiles:
+            d = oracle_mod.hdome(img, H, conn)
+            f = oracle_mod.fill_holes(d, conn)
+            a = oracle_mod.area_threshold(f, LO, HI, conn)
+            lab, n = oracle_mod.label(a, conn)
+            res.append({"objects": a, "markers": oracle_mod.pre_watershed(a, conn), "labels": lab, "count": n})
+        out[conn] = res
+    return out
+
+
+def check(outs, want):
+    for i, (o, w) in enumerate(zip(outs, want)):
+        for k in ("objects", "markers", "labels"):
+            assert np.array_equal(o[k], w[k]), (i, k, int((o[k] != w[k]).sum()))
+        assert o["count"] == w["count"], i
+
+
+SPEEDUP = {"hdome": 40.0, "fill_holes": 60.0, "area_threshold": 8.0, "markers": 25.0, "label": 3.0}
+
+
+@pytest.mark.parametrize("conn", [4, 8])
+def test_gpu_only(lib, rc, tiles, expected, conn):
+    cfg = lib.pipe_config(policy="pats", cpu_workers=0, use_gpu=True, window=3, conn=conn, h=H,
+                          area_min=LO, area_max=HI)
+    outs, st = lib.recon_pipeline_run(rc.ctx, tiles, cfg)
+    check(outs, expected[conn])
+    assert st["ops_gpu"] == [len(tiles)] * 5 and st["ops_cpu"] == [0] * 5
+    # data locality: the image goes up once and the three results come back once
+    assert st["uploads"] == len(tiles) and st["downloads"] == 3 * len(tiles)
+
+
+@pytest.mark.parametrize("policy", ["fcfs", "pats"])
+@pytest.mark.parametrize("dl", [True, False])
+@pytest.mark.parametrize("window", [1, 4])
+def test_gpu_and_cpu_workers(lib, rc, tiles, expected, policy, dl, window):
+    cfg = lib.pipe_config(policy=policy, cpu_workers=3, use_gpu=True, window=window, data_locality=dl,
+                          conn=8, h=H, area_min=LO, area_max=HI, speedup=SPEEDUP,
+                          transfer_impact={"label": 0.5, "markers": 0.2})
+    outs, st = lib.recon_pipeline_run(rc.ctx, tiles, cfg)
+    check(outs, expected[8])
+    assert [a + b for a, b in zip(st["ops_cpu"], st["ops_gpu"])] == [len(tiles)] * 5
+    if not dl:
+        # the basic mode moves every GPU assignment's inputs in and outputs out
+        assert st["uploads"] >= sum(st["ops_gpu"])
+
+
+def test_pipeline_twice_in_a_row_and_after_other_work(lib, rc, tiles, expected, torch_mod):
+    cfg = lib.pipe_config(policy="pats", cpu_workers=2, use_gpu=True, window=2, conn=8, h=H,
+                          area_min=LO, area_max=HI, speedup=SPEEDUP)
+    outs1, _ = lib.recon_pipeline_run(rc.ctx, tiles[:3], cfg)
+    # the context keeps serving ordinary calls between pipeline runs
+    m = torch_mod.from_numpy(tiles[0]).cuda()
+    rc.hdome(m, H, 8)
+    torch_mod.cuda.synchronize()
+    outs2, _ = lib.recon_pipeline_run(rc.ctx, tiles[2:], cfg)
+    check(outs1, expected[8][:3])
+    check(outs2, expected[8][2:])

@@ -1,0 +1,126 @@
+"""The co-scheduled tile pipeline on the host: the CPU variants of its
+operations and the scheduler with CPU workers only, against the oracle.
+
+The CPU variants (the library's own single-core code, a bucket flood for the
+reconstructions, two-pass union-find labelling, a parabola-envelope distance
+transform) share no code with the oracle and are compared with it element by
+element (integer work: tolerance 0), on seeded synthetic tiles, random images,
+ragged and degenerate shapes.  The scheduler runs here with CPU workers only
+(no GPU in the loop), under both policies and several window sizes: every
+tile's outputs must equal the oracle's composition of the same operations.
+"""
+import numpy as np
+import pytest
+
+import synth
+
+H_DEFAULT, LO, HI = 20, 20, 1000
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_1209_3332_amd as p
+    return p
+
+
+def oracle_chain(oracle_mod, img, h, conn, lo, hi):
+    d = oracle_mod.hdome(img, h, conn)
+    f = oracle_mod.fill_holes(d, conn)
+    a = oracle_mod.area_threshold(f, lo, hi, conn)
+    lab, n = oracle_mod.label(a, conn)
+    return {"objects": a, "markers": oracle_mod.pre_watershed(a, conn), "labels": lab, "count": n}
+
+
+def shapes_and_images():
+    rng = np.random.default_rng(1209)
+    out = [synth.scaled_config1_tile(300, 410, synth.seed_for(9, 1)),
+           synth.scaled_config1_tile(129, 257, synth.seed_for(9, 2))]
+    for h, w in ((1, 1), (1, 37), (41, 1), (2, 2), (3, 70), (65, 3)):
+        out.append(rng.integers(0, 256, size=(h, w), dtype=np.uint8))
+    out.append(np.zeros((17, 23), np.uint8))
+    out.append(np.full((17, 23), 255, np.uint8))
+    out.append(((np.indices((40, 40)).sum(0) % 2) * 255).astype(np.uint8))   # checkerboard
+    out.append((rng.random((90, 120)) < 0.55).astype(np.uint8) * 255)        # near percolation
+    return out
+
+
+@pytest.mark.parametrize("conn", [4, 8])
+def test_host_ops_match_oracle(lib, oracle_mod, conn):
+    for img in shapes_and_images():
+        for h in (1, 20, 255):
+            cfg = lib.pipe_config(conn=conn, h=h)
+            got = lib.recon_pipeline_host_op("hdome", img, cfg)
+            assert np.array_equal(got, oracle_mod.hdome(img, h, conn)), (img.shape, h)
+        cfg = lib.pipe_config(conn=conn)
+        assert np.array_equal(lib.recon_pipeline_host_op("fill_holes", img, cfg), oracle_mod.fill_holes(img, conn))
+        for lo, hi in ((0, 0), (1, 1), (2, 50), (20, 1000), (0, 1 << 40)):
+            c2 = lib.pipe_config(conn=conn, area_min=lo, area_max=hi)
+            assert np.array_equal(lib.recon_pipeline_host_op("area_threshold", img, c2),
+                                  oracle_mod.area_threshold(img, lo, hi, conn)), (img.shape, lo, hi)
+        assert np.array_equal(lib.recon_pipeline_host_op("markers", img, cfg), oracle_mod.pre_watershed(img, conn))
+        lab, n = lib.recon_pipeline_host_op("label", img, cfg)
+        want, wn = oracle_mod.label(img, conn)
+        assert n == wn and np.array_equal(lab, want), img.shape
+
+
+def test_host_ops_on_a_nuclei_tile(lib, oracle_mod):
+    _, mask, _ = synth.config2_tile(size=1024, n_gauss=3000 // 16)
+    cfg = lib.pipe_config(conn=8, h=H_DEFAULT)
+    want = oracle_chain(oracle_mod, mask, H_DEFAULT, 8, LO, HI)
+    a = lib.recon_pipeline_host_op("area_threshold", lib.recon_pipeline_host_op(
+        "fill_holes", lib.recon_pipeline_host_op("hdome", mask, cfg), cfg), cfg)
+    assert np.array_equal(a, want["objects"])
+    assert np.array_equal(lib.recon_pipeline_host_op("markers", a, cfg), want["markers"])
+    lab, n = lib.recon_pipeline_host_op("label", a, cfg)
+    assert n == want["count"] and np.array_equal(lab, want["labels"])
+
+
+@pytest.mark.parametrize("policy", ["fcfs", "pats"])
+@pytest.mark.parametrize("window,workers", [(1, 1), (2, 3), (5, 2)])
+def test_cpu_only_pipeline_matches_oracle(lib, oracle_mod, policy, window, workers):
+    rng = np.random.default_rng(7)
+    tiles = [synth.scaled_config1_tile(300, 410, synth.seed_for(9, 3)),
+             synth.scaled_config1_tile(64, 512, synth.seed_for(9, 4)),
+             rng.integers(0, 256, size=(33, 47), dtype=np.uint8),
+             synth.scaled_config1_tile(200, 200, synth.seed_for(9, 5)),
+             np.zeros((5, 9), np.uint8)]
+    cfg = lib.pipe_config(policy=policy, cpu_workers=workers, use_gpu=False, window=window, conn=8,
+                          h=H_DEFAULT, area_min=LO, area_max=HI,
+                          speedup={"hdome": 30, "fill_holes": 20, "area_threshold": 5, "markers": 10, "label": 2})
+    outs, st = lib.recon_pipeline_run(None, tiles, cfg)
+    for img, o in zip(tiles, outs):
+        want = oracle_chain(oracle_mod, img, H_DEFAULT, 8, LO, HI)
+        for k in ("objects", "markers", "labels"):
+            assert np.array_equal(o[k], want[k]), (img.shape, k)
+        assert o["count"] == want["count"]
+    assert st["ops_cpu"] == [len(tiles)] * 5 and st["ops_gpu"] == [0] * 5
+    assert st["uploads"] == 0 and st["downloads"] == 0
+
+
+def test_pipeline_conn4_and_other_parameters(lib, oracle_mod):
+    tiles = [synth.scaled_config1_tile(150, 333, synth.seed_for(9, 6 + i)) for i in range(3)]
+    cfg = lib.pipe_config(policy="pats", cpu_workers=2, use_gpu=False, window=2, conn=4, h=35,
+                          area_min=5, area_max=200)
+    outs, _ = lib.recon_pipeline_run(None, tiles, cfg)
+    for img, o in zip(tiles, outs):
+        want = oracle_chain(oracle_mod, img, 35, 4, 5, 200)
+        assert all(np.array_equal(o[k], want[k]) for k in ("objects", "markers", "labels"))
+
+
+def test_pipeline_argument_errors(lib):
+    img = [np.zeros((8, 8), np.uint8)]
+    bad = [dict(use_gpu=True, cpu_workers=1),           # a GPU run needs a context
+           dict(use_gpu=False, cpu_workers=0),          # nobody to run the operations
+           dict(use_gpu=False, cpu_workers=1, conn=6),
+           dict(use_gpu=False, cpu_workers=1, h=0),
+           dict(use_gpu=False, cpu_workers=1, h=256),
+           dict(use_gpu=False, cpu_workers=1, area_min=5, area_max=4),
+           dict(use_gpu=False, cpu_workers=1, window=0)]
+    for kw in bad:
+        with pytest.raises(lib.ReconError) as e:
+            lib.recon_pipeline_run(None, img, lib.pipe_config(**kw))
+        assert e.value.code == lib.RECON_EINVAL, kw
+    outs, st = lib.recon_pipeline_run(None, [], lib.pipe_config(use_gpu=False, cpu_workers=1))
+    assert outs == [] and st["makespan_ms"] == 0.0
+    with pytest.raises(lib.ReconError):
+        lib.recon_pipeline_host_op("hdome", img[0], lib.pipe_config(h=0))
