@@ -756,7 +756,7 @@ PIPE_IN = {"hdome": 1, "fill_holes": 1, "area_threshold": 1, "markers": 1, "labe
 PIPE_OUT = {"hdome": 1, "fill_holes": 1, "area_threshold": 1, "markers": 1, "label": 4}   # bytes/px written
 
 
-def pipeline(recon, torch, n_tiles, size, window, cpu_workers, workers, h=20, conn=8, lo=20, hi=1000):
+def pipeline(recon, torch, n_tiles, size, window, cpu_workers, workers, windows=(), h=20, conn=8, lo=20, hi=1000):
     """The co-scheduled tile pipeline (hdome -> fill-holes -> area filter ->
     {Pre-Watershed markers, labels}) on n_tiles nuclei-like tiles from host
     memory: the GPU alone, then the GPU beside cpu_workers CPU workers under
@@ -808,7 +808,8 @@ def pipeline(recon, torch, n_tiles, size, window, cpu_workers, workers, h=20, co
                 ("fcfs_dl", dict(policy="fcfs", cpu_workers=cpu_workers, data_locality=True)),
                 ("pats", dict(policy="pats", cpu_workers=cpu_workers, data_locality=False)),
                 ("pats_dl", dict(policy="pats", cpu_workers=cpu_workers, data_locality=True)),
-                ("pats_dl_cutoff", None)]
+                ("pats_dl_cutoff", None),
+                ("pats_dl_guard", dict(policy="pats", cpu_workers=cpu_workers, data_locality=True, cpu_guard=True))]
         ref = None
         res["runs"] = {}
         for name, kw in runs:
@@ -820,14 +821,16 @@ def pipeline(recon, torch, n_tiles, size, window, cpu_workers, workers, h=20, co
                 limit = max((speedup[o] for o in ok_ops), default=0.5 * min(speedup.values()))
                 kw = dict(policy="pats", cpu_workers=cpu_workers, data_locality=True, cpu_max_speedup=limit)
                 res["cutoff"] = {"cpu_max_speedup": limit, "cpu_ops": ok_ops}
-            cfg = recon.pipe_config(window=window, speedup=speedup, transfer_impact=impact, **base, **kw)
+            cfg = recon.pipe_config(window=window, speedup=speedup, transfer_impact=impact, gpu_ms=gpu_ms,
+                                    **base, **kw)
             outs, st = recon.recon_pipeline_run(ctx.ctx, tiles, cfg)
             r = {"makespan_ms": st["makespan_ms"], "tiles_s": n_tiles / (st["makespan_ms"] * 1e-3),
                  "Mpixel_s": res["pixels"] / (st["makespan_ms"] * 1e-3) / 1e6,
                  "ops_cpu": dict(zip(ops, st["ops_cpu"])), "ops_gpu": dict(zip(ops, st["ops_gpu"])),
                  "uploads": st["uploads"], "downloads": st["downloads"],
                  "transfer_GB": (st["upload_bytes"] + st["download_bytes"]) / 1e9,
-                 "transfer_ms": st["transfer_ms"], "policy": kw["policy"], "data_locality": kw["data_locality"]}
+                 "transfer_ms": st["transfer_ms"], "io_ms": st["io_ms"], "policy": kw["policy"],
+                 "data_locality": kw["data_locality"]}
             if ref is None:
                 ref = outs
                 for i in (0, n_tiles - 1):
@@ -842,6 +845,19 @@ def pipeline(recon, torch, n_tiles, size, window, cpu_workers, workers, h=20, co
             log("pipeline %s: %.1f ms (%.1f tiles/s), CPU ops %s" % (
                 name, r["makespan_ms"], r["tiles_s"], sum(st["ops_cpu"])))
             del outs
+        # the window sweep (Table 2's experiment): FCFS and PATS with data locality
+        res["window_sweep"] = {}
+        for w in windows:
+            for pol in ("fcfs", "pats"):
+                cfg = recon.pipe_config(policy=pol, cpu_workers=cpu_workers, window=w, data_locality=True,
+                                        speedup=speedup, transfer_impact=impact, **base)
+                outs, st = recon.recon_pipeline_run(ctx.ctx, tiles, cfg)
+                same = all(np.array_equal(o[k], q[k]) for o, q in zip(outs, ref)
+                           for k in ("objects", "markers", "labels"))
+                res["window_sweep"]["%s_dl/w%d" % (pol, w)] = {
+                    "makespan_ms": st["makespan_ms"], "cpu_ops": sum(st["ops_cpu"]), "same_as_gpu_only": same}
+                log("pipeline %s_dl window %d: %.1f ms" % (pol, w, st["makespan_ms"]))
+                del outs
         g = res["runs"]["gpu_only"]["makespan_ms"]
         res["speedup_over_gpu_only"] = {k: g / v["makespan_ms"] for k, v in res["runs"].items()}
         res["pats_over_fcfs"] = res["runs"]["fcfs"]["makespan_ms"] / res["runs"]["pats"]["makespan_ms"]
@@ -886,7 +902,10 @@ def main():
     ap.add_argument("--pipeline-tiles", type=int, default=64,
                     help="tiles of the co-scheduled pipeline section (0 skips it)")
     ap.add_argument("--pipeline-window", type=int, default=16)
-    ap.add_argument("--pipeline-cpu-workers", type=int, default=max(1, min(16, len(os.sched_getaffinity(0))) - 1))
+    # one core for the GPU manager thread and two for the I/O threads, the rest run CPU variants
+    ap.add_argument("--pipeline-cpu-workers", type=int, default=max(1, min(16, len(os.sched_getaffinity(0))) - 3))
+    ap.add_argument("--pipeline-windows", default="4,8,32",
+                    help="extra window sizes for the FCFS / PATS (with DL) sweep")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the reconstruction shards by tile with no communication, "
@@ -967,7 +986,8 @@ def main():
         out["serving"] = serving(recon, torch, rates, args.serve_seconds, args.serve_pool, args.workers)
     if args.pipeline_tiles:
         out["pipeline"] = pipeline(recon, torch, args.pipeline_tiles, args.size, args.pipeline_window,
-                                   args.pipeline_cpu_workers, args.workers)
+                                   args.pipeline_cpu_workers, args.workers,
+                                   windows=[int(w) for w in args.pipeline_windows.split(",") if w])
     ok = True
     if not args.no_cpu_baseline:
         # the oracle leg: its rate on the host cores, then every deferred comparison

@@ -126,6 +126,9 @@ typedef struct {
     int32_t queue_capacity;/* per-task tuning: LDS queue entries, a power of two (0 = context
                               default; at most the context's queue_capacity) */
     int32_t h;             /* RECON_OP_HDOME: dome height 1..255; ignored by the others */
+    int32_t block_rows;    /* per-task tuning: rows of the task's work blocks, 16, 32 or 64
+                              (0 = the context's block_rows); honoured by recon_batch, while
+                              the serving loop runs every request at the context's */
 } recon_task;
 
 /* Tuning and capacity knobs; zero fields take the defaults. */
@@ -285,7 +288,11 @@ int recon_pre_watershed(recon_ctx *ctx, recon_image *img, int conn, void *stream
 /* Run n tasks (any mix of ops, shapes and connectivities) in one persistent
  * launch sequence: up to 12 tasks are launched directly (their table in the
  * kernel arguments), larger batches replay a HIP graph captured once per block
- * shape (timed as a whole with timing = 1).  The paper processes a dataset as a bag of independent
+ * shape (timed as a whole with timing = 1).  Tasks whose block_rows differ
+ * run as one group per block height, each group's launch sequence on a stream
+ * of its own forked from `stream` and joined back into it (the groups' kernels
+ * run side by side; the call is timed as a whole, and recon_last_stats sums
+ * the groups' counters).  The paper processes a dataset as a bag of independent
  * tile tasks (Sec. III-B: a stage instance is an (input chunk, stage) pair,
  * handed out on demand); here the bag is drained inside one launch, whose
  * waves pull blocks of any task as they free up, each task converging on its
@@ -360,7 +367,9 @@ int recon_launch_times(recon_ctx *ctx, int back, float *dense_ms, float *seed_ms
  * of the other's operation).  Without DL every GPU assignment uploads its
  * inputs and downloads its outputs.  A bounded number of tiles is in flight
  * (the demand-driven window, Sec. III-B); a finished tile frees its slot for
- * the next one.  An optional limit keeps the CPU workers off the operations
+ * the next one.  Separate I/O threads download a finished tile's results and
+ * copy the next tile's image in while the devices compute (the asynchronous
+ * copies and prefetching of Sec. IV-D).  An optional limit keeps the CPU workers off the operations
  * whose estimated speedup exceeds it (on a GPU hundreds of times faster than
  * a core, such an instance taken by a core can outlast the whole GPU run).
  *
@@ -410,6 +419,13 @@ typedef struct {
     float speedup[RECON_PIPE_NOPS];          /* PATS: estimated GPU-over-CPU speedup per operation */
     float transfer_impact[RECON_PIPE_NOPS];  /* DL with PATS: share of an operation's GPU time
                                                 spent on its transfers, 0..1 */
+    int32_t io_threads;     /* threads that download finished tiles' results, copy them out and
+                               copy the next tiles' images in (0: 2; at most 64) */
+    int32_t cpu_guard;      /* 1: a CPU worker takes an instance only if its estimated CPU time
+                               (speedup x gpu_ms) is at most the GPU's estimated remaining work
+                               (gpu_ms summed over every instance not started yet); 0: off */
+    float gpu_ms[RECON_PIPE_NOPS];           /* cpu_guard: estimated GPU time per operation */
+    int32_t reserved;
 } recon_pipe_config;
 
 typedef struct {
@@ -421,6 +437,7 @@ typedef struct {
     int64_t uploads, downloads;              /* plane transfers */
     int64_t upload_bytes, download_bytes;
     double transfer_ms;                      /* summed time of the transfers */
+    double io_ms;                            /* summed time of tile completion and admission */
 } recon_pipe_stats;
 
 /* Run the pipeline on n host tiles and write each tile's outputs.  ctx may be

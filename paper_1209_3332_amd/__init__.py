@@ -64,7 +64,7 @@ class recon_image(ctypes.Structure):
 class recon_task(ctypes.Structure):
     _fields_ = [("op", ctypes.c_int32), ("conn", ctypes.c_int32), ("image", recon_image),
                 ("mask", recon_image), ("scan_rounds", ctypes.c_int32), ("queue_capacity", ctypes.c_int32),
-                ("h", ctypes.c_int32)]
+                ("h", ctypes.c_int32), ("block_rows", ctypes.c_int32)]
 
 
 class recon_config(ctypes.Structure):
@@ -109,7 +109,8 @@ class recon_pipe_config(ctypes.Structure):
                 ("window", ctypes.c_int32), ("data_locality", ctypes.c_int32), ("conn", ctypes.c_int32),
                 ("h", ctypes.c_int32), ("cpu_max_speedup", ctypes.c_float), ("area_min", ctypes.c_int64),
                 ("area_max", ctypes.c_int64), ("speedup", ctypes.c_float * 5),
-                ("transfer_impact", ctypes.c_float * 5)]
+                ("transfer_impact", ctypes.c_float * 5), ("io_threads", ctypes.c_int32),
+                ("cpu_guard", ctypes.c_int32), ("gpu_ms", ctypes.c_float * 5), ("reserved", ctypes.c_int32)]
 
 
 class recon_pipe_stats(ctypes.Structure):
@@ -117,7 +118,7 @@ class recon_pipe_stats(ctypes.Structure):
                 ("ops_gpu", ctypes.c_int64 * 5), ("busy_cpu_ms", ctypes.c_double * 5),
                 ("busy_gpu_ms", ctypes.c_double * 5), ("uploads", ctypes.c_int64), ("downloads", ctypes.c_int64),
                 ("upload_bytes", ctypes.c_int64), ("download_bytes", ctypes.c_int64),
-                ("transfer_ms", ctypes.c_double)]
+                ("transfer_ms", ctypes.c_double), ("io_ms", ctypes.c_double)]
 
 
 _lib = None
@@ -288,8 +289,9 @@ def recon_pre_watershed(ctx: int, img, conn: int = 8, stream=None) -> None:
 
 
 def make_task(op: str, image, mask=None, conn: int = 8, scan_rounds: int = 0, queue_capacity: int = 0,
-              h: int = 0) -> recon_task:
-    """recon_task for op in OPS; `mask` for dilate / erode, `h` for hdome."""
+              h: int = 0, block_rows: int = 0) -> recon_task:
+    """recon_task for op in OPS; `mask` for dilate / erode, `h` for hdome;
+    block_rows 0 = the context's."""
     if op not in OPS:
         raise ValueError("op must be one of %s" % ", ".join(OPS))
     t = recon_task()
@@ -298,6 +300,7 @@ def make_task(op: str, image, mask=None, conn: int = 8, scan_rounds: int = 0, qu
     t.queue_capacity = int(queue_capacity)
     t.conn = int(conn)
     t.h = int(h)
+    t.block_rows = int(block_rows)
     t.image = image_of(image)
     if op in TWO_PLANE_OPS:
         t.mask = image_of(mask)
@@ -355,7 +358,8 @@ def recon_last_error() -> str:
 
 def pipe_config(policy: str = "pats", cpu_workers: int = 0, use_gpu: bool = True, window: int = 8,
                 data_locality: bool = True, conn: int = 8, h: int = 20, area_min: int = 20, area_max: int = 1000,
-                speedup=None, transfer_impact=None, cpu_max_speedup: float = 0.0) -> recon_pipe_config:
+                speedup=None, transfer_impact=None, cpu_max_speedup: float = 0.0,
+                io_threads: int = 2, gpu_ms=None, cpu_guard: bool = False) -> recon_pipe_config:
     """recon_pipe_config; speedup / transfer_impact: dicts or sequences over PIPE_OPS."""
     c = recon_pipe_config()
     if policy not in POLICIES:
@@ -365,6 +369,8 @@ def pipe_config(policy: str = "pats", cpu_workers: int = 0, use_gpu: bool = True
     c.data_locality, c.conn, c.h = int(bool(data_locality)), int(conn), int(h)
     c.area_min, c.area_max = int(area_min), int(area_max)
     c.cpu_max_speedup = float(cpu_max_speedup)
+    c.io_threads = int(io_threads)
+    c.cpu_guard = int(bool(cpu_guard))
 
     def seq(v, default):
         if v is None:
@@ -376,6 +382,8 @@ def pipe_config(policy: str = "pats", cpu_workers: int = 0, use_gpu: bool = True
         c.speedup[i] = x
     for i, x in enumerate(seq(transfer_impact, 0.0)):
         c.transfer_impact[i] = x
+    for i, x in enumerate(seq(gpu_ms, 0.0)):
+        c.gpu_ms[i] = x
     return c
 
 
@@ -522,9 +530,11 @@ class Recon:
         return img
 
     def batch(self, tasks, stream=None):
-        """tasks: list of dicts {op, image, mask?, conn, h?} of device tensors (results in place)."""
+        """tasks: list of dicts {op, image, mask?, conn, h?, scan_rounds?, queue_capacity?,
+        block_rows?} of device tensors (results in place)."""
         recon_batch(self.ctx, [make_task(t["op"], t["image"], t.get("mask"), t.get("conn", 8),
-                                         t.get("scan_rounds", 0), t.get("queue_capacity", 0), t.get("h", 0))
+                                         t.get("scan_rounds", 0), t.get("queue_capacity", 0), t.get("h", 0),
+                                         t.get("block_rows", 0))
                                for t in tasks], stream)
 
     def submit(self, op, image, mask=None, conn: int = 8, scan_rounds: int = 0, queue_capacity: int = 0,

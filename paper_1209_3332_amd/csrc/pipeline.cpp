@@ -14,8 +14,9 @@
 // the next one.
 //
 // Threads: one GPU manager thread (it calls the library's operations on its
-// own stream and waits for each instance) and `cpu_workers` CPU threads (each
-// runs the CPU variants of host_ops.cpp on one core).  Every tile slot owns
+// own stream and waits for each instance), `cpu_workers` CPU threads (each
+// runs the CPU variants of host_ops.cpp on one core) and `io_threads` threads
+// that bring finished tiles' results out and the next tiles' images in.  Every tile slot owns
 // pinned host planes and device planes for the tile's data; a per-plane bit
 // set records where a valid copy lives, and a device moves a plane only when
 // it lacks a valid copy.
@@ -108,10 +109,12 @@ struct Run {
     std::unique_ptr<Slot[]> slots;
     int nslots = 0;
     std::vector<Ready> ready;
+    std::vector<int> finished;   // slots whose tile's last operation completed
     std::mutex mu;
     std::condition_variable cv;
     uint64_t seq = 0;
     int next_tile = 0, done_tiles = 0;
+    double gpu_left_ms = 0.0;    // estimated GPU time of the instances not started yet (cpu_guard)
     int err = RECON_OK;
     std::string err_msg;
     recon_pipe_stats st{};
@@ -316,11 +319,18 @@ int pick(const Run &r, bool gpu) {
         if (pats && a.speedup != b.speedup) return gpu ? a.speedup > b.speedup : a.speedup < b.speedup;
         return a.seq < b.seq;
     };
-    // a CPU worker may be kept off the instances a core would take too long on
+    // a CPU worker may be kept off the instances a core would take too long on:
+    // above a speedup limit, or (guard) longer than the GPU's remaining work
     const float limit = gpu ? 0.0f : r.cfg.cpu_max_speedup;
+    const bool guard = !gpu && r.cfg.cpu_guard && r.cfg.use_gpu;
+    auto allowed = [&](const Ready &x) {
+        if (limit > 0.0f && x.speedup > limit) return false;
+        if (guard && (double)x.speedup * r.cfg.gpu_ms[x.op] > r.gpu_left_ms - r.cfg.gpu_ms[x.op]) return false;
+        return true;
+    };
     int best = -1;
     for (int i = 0; i < (int)q.size(); ++i)
-        if ((limit <= 0.0f || q[i].speedup <= limit) && (best < 0 || before(q[i], q[best]))) best = i;
+        if (allowed(q[i]) && (best < 0 || before(q[i], q[best]))) best = i;
     if (!gpu || !r.cfg.data_locality || best < 0) return best;
     // data locality: the preferred instance among those whose inputs are in
     // device memory already
@@ -345,8 +355,10 @@ bool complete(Run &r, int slot, int op) {
 }
 
 // The tile's last operation finished: bring its results to the host, copy them
-// out, free the slot and admit the next tile.
+// out, free the slot and admit the next tile (whose image is copied into the
+// slot's pinned plane here, ahead of its first operation).
 int finish_tile(Run &r, int slot, hipStream_t s) {
+    const auto t0 = Clock::now();
     Slot &sl = r.slots[slot];
     int rc = stage(r, sl, (1u << PA) | (1u << PB) | (1u << PL), false, s);
     if (rc) return rc;
@@ -366,7 +378,30 @@ int finish_tile(Run &r, int slot, hipStream_t s) {
         r.cv.notify_all();
     }
     admit(r);
+    std::lock_guard<std::mutex> g(r.mu);
+    r.st.io_ms += ms_since(t0);
     return RECON_OK;
+}
+
+// Tile completion and admission run on their own threads (the paper's
+// asynchronous download and prefetch of Sec. IV-D), so that neither the GPU
+// manager nor a CPU worker spends its time copying whole tiles.
+void io_thread(Run &r, hipStream_t s) {
+    if (r.cfg.use_gpu && hipSetDevice(r.device) != hipSuccess) {
+        set_err(r, RECON_EDEVICE, "hipSetDevice failed in a pipeline thread");
+        return;
+    }
+    while (true) {
+        int slot;
+        {
+            std::unique_lock<std::mutex> lk(r.mu);
+            r.cv.wait(lk, [&] { return r.err || r.done_tiles == r.n || !r.finished.empty(); });
+            if (r.err || r.done_tiles == r.n) return;
+            slot = r.finished.back();
+            r.finished.pop_back();
+        }
+        if (finish_tile(r, slot, s)) return;
+    }
 }
 
 void worker(Run &r, Device dev) {
@@ -385,6 +420,7 @@ void worker(Run &r, Device dev) {
             slot = r.ready[i].slot;
             op = r.ready[i].op;
             r.ready.erase(r.ready.begin() + i);
+            r.gpu_left_ms -= r.cfg.gpu_ms[op];
         }
         Slot &sl = r.slots[slot];
         const uint8_t in = kOps[op].in_mask, out = kOps[op].out_mask;
@@ -419,18 +455,25 @@ void worker(Run &r, Device dev) {
             last = complete(r, slot, op);
             r.cv.notify_all();
         }
-        if (last && finish_tile(r, slot, dev.stream)) return;
+        if (last) {
+            std::lock_guard<std::mutex> g(r.mu);
+            r.finished.push_back(slot);
+            r.cv.notify_all();
+        }
     }
 }
 
 int check_config(const recon_pipe_config *c, recon_ctx *ctx) {
     if (c->policy != RECON_SCHED_FCFS && c->policy != RECON_SCHED_PATS) return 1;
     if (c->cpu_workers < 0 || c->cpu_workers > 256 || c->window < 1 || c->window > 1024) return 1;
+    if (c->io_threads < 0 || c->io_threads > 64) return 1;
     if (c->use_gpu && !ctx) return 1;
     if (!c->use_gpu && c->cpu_workers == 0) return 1;
     if (c->conn != 4 && c->conn != 8) return 1;
     if (c->h < 1 || c->h > 255 || c->area_min < 0 || c->area_max < c->area_min) return 1;
-    if (!(c->cpu_max_speedup >= 0.0f)) return 1;
+    if (!(c->cpu_max_speedup >= 0.0f) || c->cpu_guard < 0 || c->cpu_guard > 1) return 1;
+    for (int o = 0; o < RECON_PIPE_NOPS; ++o)
+        if (!(c->gpu_ms[o] >= 0.0f) || !(c->speedup[o] >= 0.0f)) return 1;
     // without a GPU the CPU workers must be able to take every operation
     if (!c->use_gpu && c->cpu_max_speedup > 0.0f)
         for (int o = 0; o < RECON_PIPE_NOPS; ++o)
@@ -508,16 +551,24 @@ extern "C" int recon_pipeline_run(recon_ctx *ctx, const recon_pipe_tile *tiles, 
             rc = RECON_EDEVICE;
         devs.push_back(c);
     }
+    const int n_io = cfg->io_threads > 0 ? cfg->io_threads : 2;
+    std::vector<hipStream_t> io_streams(n_io, nullptr);
+    for (int k = 0; rc == RECON_OK && cfg->use_gpu && k < n_io; ++k)
+        if (hipStreamCreateWithFlags(&io_streams[k], hipStreamNonBlocking) != hipSuccess) rc = RECON_EDEVICE;
     if (rc && r.err_msg.empty()) r.err_msg = "stream creation failed";
+    for (int o = 0; o < RECON_PIPE_NOPS; ++o) r.gpu_left_ms += (double)n * cfg->gpu_ms[o];
     if (rc == RECON_OK) {
         const auto t0 = Clock::now();
         admit(r);
         std::vector<std::thread> th;
         for (auto &d : devs) th.emplace_back(worker, std::ref(r), d);
+        for (int k = 0; k < n_io; ++k) th.emplace_back(io_thread, std::ref(r), io_streams[k]);
         for (auto &t : th) t.join();
         r.st.makespan_ms = ms_since(t0);
         rc = r.err;
     }
+    for (hipStream_t st : io_streams)
+        if (st) (void)hipStreamDestroy(st);
     for (auto &d : devs) {
         if (d.stream) (void)hipStreamDestroy(d.stream);
         if (d.scratch) hostops::scratch_free(d.scratch);

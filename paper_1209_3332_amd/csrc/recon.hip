@@ -174,6 +174,14 @@ struct recon_ctx {
     // visit completes) and the number of the lane's current launch
     uint32_t *h_done = nullptr;
     uint32_t launch_seq = 0;
+    // recon_batch with tasks of several block heights: one context per height
+    // (its own workspace and graphs) whose launch runs on a stream forked from
+    // the caller's; `last_shapes` (bit v) names those that ran the last batch
+    recon_ctx *shape_ctx[kVariants] = {nullptr, nullptr, nullptr};
+    hipStream_t shape_stream[kVariants] = {nullptr, nullptr, nullptr};
+    hipEvent_t shape_join[kVariants] = {nullptr, nullptr, nullptr};
+    hipEvent_t shape_fork = nullptr;
+    unsigned last_shapes = 0;
 };
 
 namespace {
@@ -312,6 +320,8 @@ int check_task(const recon_task &t, const recon_config *cfg = nullptr) {
         return fail(RECON_EINVAL, "task queue_capacity must be a power of two in 64..%d",
                     cfg ? cfg->queue_capacity : 8192);
     if (t.conn != 4 && t.conn != 8) return fail(RECON_EINVAL, "conn must be 4 or 8, got %d", t.conn);
+    if (t.block_rows != 0 && variant_of(t.block_rows) < 0)
+        return fail(RECON_EINVAL, "task block_rows must be 0, 16, 32 or 64, got %d", t.block_rows);
     int rc = check_image(&t.image, two_planes(t.op) ? "marker" : "image");
     if (rc) return rc;
     if (two_planes(t.op)) {
@@ -722,6 +732,53 @@ int make_ctx(recon_ctx **out, int device, const recon_config &c) {
     return RECON_OK;
 }
 
+// recon_batch of tasks with several block heights: each height's tasks run
+// as one launch sequence on that height's context, on a stream forked from
+// `stream`; `stream` waits for every group.  The call is timed as a whole on
+// the caller's context (a launch whose only mark is its total).
+int run_shape_groups(recon_ctx *c, const recon_task *tasks, int n, unsigned shapes, hipStream_t stream) {
+    int rc = ensure_device(c);
+    if (rc) return rc;
+    if (!c->shape_fork) HIP_TRY(hipEventCreateWithFlags(&c->shape_fork, hipEventDisableTiming));
+    const int v_ctx = variant_of(c->cfg.block_rows);
+    std::vector<recon_task> group[kVariants];
+    for (int k = 0; k < n; ++k)
+        group[tasks[k].block_rows ? variant_of(tasks[k].block_rows) : v_ctx].push_back(tasks[k]);
+    for (int v = 0; v < kVariants; ++v) {
+        if (!(shapes & (1u << v)) || c->shape_ctx[v]) continue;
+        recon_config cfg = c->cfg;
+        cfg.block_rows = kBlockRows[v];
+        cfg.timing = 0;
+        rc = make_ctx(&c->shape_ctx[v], c->device, cfg);
+        if (rc) return rc;
+        c->shape_ctx[v]->noalloc = c->noalloc;
+        if (hipStreamCreateWithFlags(&c->shape_stream[v], hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&c->shape_join[v], hipEventDisableTiming) != hipSuccess)
+            return fail(RECON_EDEVICE, "stream / event creation for block height %d failed", kBlockRows[v]);
+    }
+    hipEvent_t *tev = c->tev[c->launches % kTimingRing];
+    if (c->cfg.timing) HIP_TRY(hipEventRecord(tev[5], stream));
+    HIP_TRY(hipEventRecord(c->shape_fork, stream));
+    for (int v = 0; v < kVariants; ++v) {
+        if (!(shapes & (1u << v))) continue;
+        HIP_TRY(hipStreamWaitEvent(c->shape_stream[v], c->shape_fork, 0));
+        const int m = (int)group[v].size();
+        rc = run_tasks(c->shape_ctx[v], group[v].data(), m, c->shape_stream[v], m > rk::MAX_INLINE_TASKS);
+        if (rc) return rc;
+        HIP_TRY(hipEventRecord(c->shape_join[v], c->shape_stream[v]));
+        HIP_TRY(hipStreamWaitEvent(stream, c->shape_join[v], 0));
+    }
+    if (c->cfg.timing) HIP_TRY(hipEventRecord(tev[4], stream));
+    HIP_TRY(hipEventRecord(c->last_done, stream));
+    c->have_last = true;
+    c->last_work = nullptr;
+    c->last_shapes = shapes;
+    c->last_was_graph = true;
+    c->tev_graph[c->launches % kTimingRing] = true;
+    c->launches += 1;
+    return RECON_OK;
+}
+
 // Device bytes a serving request holds while admitted: its images, its scratch
 // marker plane and, with the component route, its label plane.
 size_t task_bytes(const recon_task &t, const recon_config &cfg) {
@@ -997,6 +1054,12 @@ int recon_destroy(recon_ctx *ctx) {
     if (ctx->aux_stream) (void)hipStreamDestroy(ctx->aux_stream);
     if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
     if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
+    for (int v = 0; v < kVariants; ++v) {
+        if (ctx->shape_ctx[v]) (void)recon_destroy(ctx->shape_ctx[v]);
+        if (ctx->shape_stream[v]) (void)hipStreamDestroy(ctx->shape_stream[v]);
+        if (ctx->shape_join[v]) (void)hipEventDestroy(ctx->shape_join[v]);
+    }
+    if (ctx->shape_fork) (void)hipEventDestroy(ctx->shape_fork);
     delete ctx;
     return RECON_OK;
 }
@@ -1360,12 +1423,20 @@ int recon_batch(recon_ctx *ctx, const recon_task *tasks, int32_t n, void *stream
             return fail(rc, "task %d: %s", k, m.c_str());
         }
     }
-    // a batch that fits the kernel arguments is launched directly (its table
-    // travels inline: no table copy, and fewer packets than a graph replay,
-    // which on this runtime costs more than the launches it saves); larger
-    // batches replay the context's captured graph
-    const bool use_graph = n > rk::MAX_INLINE_TASKS;
-    return run_tasks(ctx, tasks, n, (hipStream_t)stream, use_graph);
+    const int v_ctx = variant_of(ctx->cfg.block_rows);
+    unsigned shapes = 0;
+    for (int k = 0; k < n; ++k)
+        shapes |= 1u << (tasks[k].block_rows ? variant_of(tasks[k].block_rows) : v_ctx);
+    if (shapes == (1u << v_ctx)) {
+        // a batch that fits the kernel arguments is launched directly (its table
+        // travels inline: no table copy, and fewer packets than a graph replay,
+        // which on this runtime costs more than the launches it saves); larger
+        // batches replay the context's captured graph
+        ctx->last_shapes = 0;
+        const bool use_graph = n > rk::MAX_INLINE_TASKS;
+        return run_tasks(ctx, tasks, n, (hipStream_t)stream, use_graph);
+    }
+    return run_shape_groups(ctx, tasks, n, shapes, (hipStream_t)stream);
 }
 
 // Durations (ms) of a recent launch from its timing marks: K1, K2, K3, whole
@@ -1394,6 +1465,27 @@ static void launch_times(recon_ctx *ctx, int back, float t[5]) {
     (void)hipGetLastError();   // a mark that was not recorded must not leave an error behind
 }
 
+}  // extern "C"
+
+namespace {
+
+// The scheduler counters of `work` (device memory of ctx's device), read
+// through a kernel into ctx's pinned buffer once ctx's last launch is done.
+int read_work(recon_ctx *ctx, const rk::Work *work, rk::Work &w) {
+    hipLaunchKernelGGL(rk::copy_table, dim3(1), dim3(64), 0, nullptr, (const uint8_t *)work,
+                       (uint8_t *)ctx->h_work, (uint32_t)sizeof(rk::Work));
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipEventRecord(ctx->last_done, nullptr));
+    int rc = wait_event(ctx->last_done, 60.0, "the statistics read-back");
+    if (rc) return rc;
+    std::memcpy(&w, (const void *)ctx->h_work, sizeof(w));
+    return RECON_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int recon_last_stats(recon_ctx *ctx, recon_stats *out) {
     if (!ctx || !out) return fail(RECON_EINVAL, "null argument");
     std::memset(out, 0, sizeof(*out));
@@ -1402,23 +1494,30 @@ int recon_last_stats(recon_ctx *ctx, recon_stats *out) {
     if (rc) return rc;
     rc = wait_event(ctx->last_done, 60.0, "the last launch");
     if (rc) return rc;
-    // read the counters through a kernel into pinned memory
-    hipLaunchKernelGGL(rk::copy_table, dim3(1), dim3(64), 0, nullptr, (const uint8_t *)ctx->last_work,
-                       (uint8_t *)ctx->h_work, (uint32_t)sizeof(rk::Work));
-    HIP_TRY(hipGetLastError());
-    HIP_TRY(hipEventRecord(ctx->last_done, nullptr));
-    rc = wait_event(ctx->last_done, 60.0, "the statistics read-back");
-    if (rc) return rc;
-    rk::Work w;
-    std::memcpy(&w, (const void *)ctx->h_work, sizeof(w));
-    out->dense_visits = (int64_t)w.stat_dense;
-    out->revisits = (int64_t)w.stat_revisit;
-    out->reruns = (int64_t)w.stat_rerun;
-    out->queue_overflows = (int64_t)w.stat_overflow;
-    out->requests = (int64_t)w.stat_request;
-    out->aborted = (int64_t)w.abort;
-    out->component_tasks = (int64_t)w.stat_route;
-    out->queue_spills = (int64_t)w.stat_spill;
+    // the counters of the last launch, summed over its block-height groups
+    std::vector<std::pair<recon_ctx *, const rk::Work *>> parts;
+    if (ctx->last_shapes) {
+        for (int v = 0; v < kVariants; ++v)
+            if ((ctx->last_shapes & (1u << v)) && ctx->shape_ctx[v])
+                parts.emplace_back(ctx->shape_ctx[v], ctx->shape_ctx[v]->last_work);
+    } else {
+        parts.emplace_back(ctx, ctx->last_work);
+    }
+    bool aborted = false;
+    for (auto &pt : parts) {
+        rk::Work w;
+        rc = read_work(pt.first, pt.second, w);
+        if (rc) return rc;
+        out->dense_visits += (int64_t)w.stat_dense;
+        out->revisits += (int64_t)w.stat_revisit;
+        out->reruns += (int64_t)w.stat_rerun;
+        out->queue_overflows += (int64_t)w.stat_overflow;
+        out->requests += (int64_t)w.stat_request;
+        out->aborted |= (int64_t)w.abort;
+        out->component_tasks += (int64_t)w.stat_route;
+        out->queue_spills += (int64_t)w.stat_spill;
+        aborted |= w.abort != 0;
+    }
     if (ctx->cfg.timing) {
         float t[5];
         launch_times(ctx, 0, t);
@@ -1428,7 +1527,7 @@ int recon_last_stats(recon_ctx *ctx, recon_stats *out) {
         out->total_ms = t[3];
         out->route_ms = t[4];
     }
-    if (w.abort) return fail(RECON_EDEVICE, "scheduler watchdog expired: the last launch did not converge");
+    if (aborted) return fail(RECON_EDEVICE, "scheduler watchdog expired: the last launch did not converge");
     return RECON_OK;
 }
 

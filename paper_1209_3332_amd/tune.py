@@ -1,9 +1,10 @@
 """Autotuner for librecon: block rows, LDS queue capacity and scan-pass rounds.
 
-The knobs change speed, never bytes (the reconstruction is unique).  Block rows
-are fixed per launch (they set the kernels' LDS layout); scan rounds and queue
-capacity travel per task, so one batched launch can use a different setting for
-each size bucket.
+The knobs change speed, never bytes (the reconstruction is unique).  All three
+travel per task, so one batched call can use a different setting for each size
+bucket: scan rounds and queue capacity inside one launch, block rows (which set
+the kernels' LDS layout) by running each block height's tasks as a launch of
+their own, side by side with the others.
 
     python -m paper_1209_3332_amd.tune [--out FILE] [--reps N]
 
@@ -91,10 +92,10 @@ def config_for(cache: dict, h: int, w: int, conn: int, arch: str | None = None) 
 
 
 def tuned_batch(cache: dict, tasks: list) -> tuple[int, int, list]:
-    """Block rows for the launch (the choice of the bucket holding most pixels),
+    """Block rows for the context (the choice of the bucket holding most pixels),
     the context's queue capacity (the largest per-task choice: it sizes the LDS
-    of every workgroup) and the tasks with their per-task scan rounds and queue
-    capacity filled in."""
+    of every workgroup) and the tasks with their per-task block rows, scan
+    rounds and queue capacity filled in."""
     weight = {}
     out = []
     qmax = 0
@@ -103,7 +104,8 @@ def tuned_batch(cache: dict, tasks: list) -> tuple[int, int, list]:
         cfg = config_for(cache, h, w, t.get("conn", 8))
         weight[cfg["block_rows"]] = weight.get(cfg["block_rows"], 0) + h * w
         qmax = max(qmax, cfg["queue_capacity"])
-        out.append(dict(t, scan_rounds=cfg["scan_rounds"], queue_capacity=cfg["queue_capacity"]))
+        out.append(dict(t, scan_rounds=cfg["scan_rounds"], queue_capacity=cfg["queue_capacity"],
+                        block_rows=cfg["block_rows"]))
     bh = max(weight, key=weight.get) if weight else 32
     return bh, qmax or 2048, out
 

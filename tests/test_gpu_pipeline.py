@@ -98,6 +98,23 @@ def test_gpu_and_cpu_workers(lib, rc, tiles, expected, policy, dl, window):
         assert st["uploads"] >= sum(st["ops_gpu"])
 
 
+@pytest.mark.parametrize("policy", ["fcfs", "pats"])
+def test_cpu_limits(lib, rc, tiles, expected, policy):
+    """The CPU cut-off and the remaining-work guard change who runs what, never the bytes."""
+    gpu_ms = {"hdome": 0.5, "fill_holes": 0.5, "area_threshold": 0.2, "markers": 0.3, "label": 0.1}
+    for kw in (dict(cpu_max_speedup=10.0), dict(cpu_guard=True, gpu_ms=gpu_ms),
+               dict(cpu_max_speedup=30.0, cpu_guard=True, gpu_ms=gpu_ms)):
+        cfg = lib.pipe_config(policy=policy, cpu_workers=3, use_gpu=True, window=4, conn=8, h=H, area_min=LO,
+                              area_max=HI, speedup=SPEEDUP, **kw)
+        outs, st = lib.recon_pipeline_run(rc.ctx, tiles, cfg)
+        check(outs, expected[8])
+        if "cpu_max_speedup" in kw:
+            # the workers never take an operation whose estimate is above the limit
+            for k, op in enumerate(lib.PIPE_OPS):
+                if SPEEDUP[op] > kw["cpu_max_speedup"]:
+                    assert st["ops_cpu"][k] == 0, (kw, op)
+
+
 def test_pipeline_twice_in_a_row_and_after_other_work(lib, rc, tiles, expected, torch_mod):
     cfg = lib.pipe_config(policy="pats", cpu_workers=2, use_gpu=True, window=2, conn=8, h=H,
                           area_min=LO, area_max=HI, speedup=SPEEDUP)

@@ -97,6 +97,18 @@ def test_cpu_only_pipeline_matches_oracle(lib, oracle_mod, policy, window, worke
     assert st["uploads"] == 0 and st["downloads"] == 0
 
 
+def test_cpu_only_run_ignores_the_guard(lib, oracle_mod):
+    """Without a GPU the CPU workers take everything, whatever the guard says."""
+    tiles = [synth.scaled_config1_tile(100, 140, synth.seed_for(9, 12 + i)) for i in range(3)]
+    cfg = lib.pipe_config(policy="pats", cpu_workers=2, use_gpu=False, window=2, cpu_guard=True,
+                          gpu_ms={"hdome": 1.0}, speedup={"hdome": 1000.0})
+    outs, st = lib.recon_pipeline_run(None, tiles, cfg)
+    assert st["ops_cpu"] == [3] * 5
+    for img, o in zip(tiles, outs):
+        want = oracle_chain(oracle_mod, img, H_DEFAULT, 8, LO, HI)
+        assert all(np.array_equal(o[k], want[k]) for k in ("objects", "markers", "labels"))
+
+
 def test_pipeline_conn4_and_other_parameters(lib, oracle_mod):
     tiles = [synth.scaled_config1_tile(150, 333, synth.seed_for(9, 6 + i)) for i in range(3)]
     cfg = lib.pipe_config(policy="pats", cpu_workers=2, use_gpu=False, window=2, conn=4, h=35,

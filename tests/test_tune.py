@@ -25,8 +25,8 @@ def test_tuned_batch_picks_per_bucket():
     bh, qmax, out = tune.tuned_batch(cache, tasks)
     assert bh == 64                      # the bucket holding most pixels
     assert qmax == 8192                  # the context sizes LDS for the largest queue
-    assert (out[0]["scan_rounds"], out[0]["queue_capacity"]) == (1, 512)
-    assert (out[1]["scan_rounds"], out[1]["queue_capacity"]) == (4, 8192)
+    assert (out[0]["scan_rounds"], out[0]["queue_capacity"], out[0]["block_rows"]) == (1, 512, 16)
+    assert (out[1]["scan_rounds"], out[1]["queue_capacity"], out[1]["block_rows"]) == (4, 8192, 64)
 
 
 def test_cache_is_stamped_and_stale_caches_are_ignored(tmp_path):
