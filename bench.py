@@ -523,6 +523,17 @@ def batched_vs_per_tile(recon, torch, ctx_cfg, n_tiles, size, workers, spiral_si
     spirals = [i for i in every if kinds[i] == "spiral"]
     res = {"tiles": n_tiles, "tile": [size, size], "spirals": len(spirals),
            "spiral_tile": [spiral_size, spiral_size], "pixels": px_of(every)}
+    # the autotuner's block rows, queue capacity and scan rounds for these tiles
+    # (every tile has one size and 8-connectivity; knobs given on the command
+    # line win), used by the batched launches and the per-tile calls alike
+    from paper_1209_3332_amd import tune
+    cache = tune.load_cache()
+    knobs = tune.config_for(cache, size, size, 8)
+    ctx_cfg = dict(ctx_cfg)
+    for k in ("block_rows", "queue_capacity", "scan_rounds"):
+        ctx_cfg.setdefault(k, knobs[k])
+    res.update({"tuned": bool(cache), "block_rows": ctx_cfg["block_rows"],
+                "queue_capacity": ctx_cfg["queue_capacity"], "scan_rounds": ctx_cfg["scan_rounds"]})
     with recon.Recon(0, **ctx_cfg) as ctx:
         stream = torch.cuda.current_stream()
 
@@ -904,7 +915,7 @@ def main():
     ap.add_argument("--pipeline-window", type=int, default=16)
     # one core for the GPU manager thread and two for the I/O threads, the rest run CPU variants
     ap.add_argument("--pipeline-cpu-workers", type=int, default=max(1, min(16, len(os.sched_getaffinity(0))) - 3))
-    ap.add_argument("--pipeline-windows", default="4,8,32",
+    ap.add_argument("--pipeline-windows", default="8,32",
                     help="extra window sizes for the FCFS / PATS (with DL) sweep")
     args = ap.parse_args()
     if args.gpus != 1:

@@ -30,7 +30,7 @@ DEFAULT_CACHE = os.environ.get("RECON_TUNE_CACHE", os.path.join(HERE, "tune_cach
 
 BLOCK_ROWS = (16, 32, 64)
 QUEUE_CAPACITY = (512, 2048, 8192)
-SCAN_ROUNDS = (1, 2, 3, 4)
+SCAN_ROUNDS = (-1, 1, 2, 3, 4)   # -1: no sweep on first visits (seed and queue only)
 # size buckets by tile area (pixels): representative side length of each
 BUCKETS = (("small", 1 << 20, 768), ("medium", 6 << 20, 2048), ("large", 1 << 62, 4096))
 
