@@ -126,3 +126,22 @@ def test_pipeline_twice_in_a_row_and_after_other_work(lib, rc, tiles, expected, 
     outs2, _ = lib.recon_pipeline_run(rc.ctx, tiles[2:], cfg)
     check(outs1, expected[8][:3])
     check(outs2, expected[8][2:])
+
+
+def test_pipeline_full_size_tiles(lib, rc, oracle_mod):
+    """Two 4096 x 4096 nuclei-like tiles (the benchmark's tile size) through
+    the pipeline with CPU workers under PATS with the remaining-work guard,
+    against the oracle's chain."""
+    tiles = [synth.config2_tile(seed=synth.seed_for(6, 900 + i))[1] for i in range(2)]
+    gpu_ms = {"hdome": 1.5, "fill_holes": 2.0, "area_threshold": 0.6, "markers": 0.8, "label": 0.4}
+    speed = {"hdome": 450.0, "fill_holes": 200.0, "area_threshold": 240.0, "markers": 260.0, "label": 200.0}
+    cfg = lib.pipe_config(policy="pats", cpu_workers=4, use_gpu=True, window=2, conn=8, h=H, area_min=LO,
+                          area_max=HI, speedup=speed, gpu_ms=gpu_ms, cpu_guard=True)
+    outs, st = lib.recon_pipeline_run(rc.ctx, tiles, cfg)
+    want = []
+    for img in tiles:
+        a = oracle_mod.area_threshold(oracle_mod.fill_holes(oracle_mod.hdome(img, H, 8), 8), LO, HI, 8)
+        lab, n = oracle_mod.label(a, 8)
+        want.append({"objects": a, "markers": oracle_mod.pre_watershed(a, 8), "labels": lab, "count": n})
+    check(outs, want)
+    assert [a + b for a, b in zip(st["ops_cpu"], st["ops_gpu"])] == [2] * 5
