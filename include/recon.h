@@ -425,8 +425,19 @@ typedef struct {
                                (speedup x gpu_ms) is at most the GPU's estimated remaining work
                                (gpu_ms summed over every instance not started yet); 0: off */
     float gpu_ms[RECON_PIPE_NOPS];           /* cpu_guard: estimated GPU time per operation */
-    int32_t reserved;
+    int32_t trace_cap;      /* entries of `trace` (0: no trace) */
+    struct recon_pipe_event *trace;  /* HOST out (or NULL): one entry per operation instance, in
+                                        the order the devices took them (the first trace_cap) */
 } recon_pipe_config;
+
+/* One operation instance of a recon_pipeline_run, as it ran. */
+typedef struct recon_pipe_event {
+    int32_t tile;           /* index into the tiles array */
+    int32_t op;             /* RECON_PIPE_* */
+    int32_t device;         /* 0: the GPU; 1 + k: CPU worker k */
+    int32_t reserved;
+    double start_ms, end_ms;   /* from the start of the run: taken (inputs staged next), computed */
+} recon_pipe_event;
 
 typedef struct {
     double makespan_ms;                      /* first admission to the last tile's results */
@@ -438,6 +449,7 @@ typedef struct {
     int64_t upload_bytes, download_bytes;
     double transfer_ms;                      /* summed time of the transfers */
     double io_ms;                            /* summed time of tile completion and admission */
+    int64_t trace_n;                         /* entries written to cfg->trace */
 } recon_pipe_stats;
 
 /* Run the pipeline on n host tiles and write each tile's outputs.  ctx may be

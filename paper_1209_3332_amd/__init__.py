@@ -104,13 +104,19 @@ class recon_pipe_tile(ctypes.Structure):
                 ("labels", ctypes.c_void_p), ("label_pitch", ctypes.c_int64), ("count", ctypes.c_void_p)]
 
 
+class recon_pipe_event(ctypes.Structure):
+    _fields_ = [("tile", ctypes.c_int32), ("op", ctypes.c_int32), ("device", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("start_ms", ctypes.c_double), ("end_ms", ctypes.c_double)]
+
+
 class recon_pipe_config(ctypes.Structure):
     _fields_ = [("policy", ctypes.c_int32), ("cpu_workers", ctypes.c_int32), ("use_gpu", ctypes.c_int32),
                 ("window", ctypes.c_int32), ("data_locality", ctypes.c_int32), ("conn", ctypes.c_int32),
                 ("h", ctypes.c_int32), ("cpu_max_speedup", ctypes.c_float), ("area_min", ctypes.c_int64),
                 ("area_max", ctypes.c_int64), ("speedup", ctypes.c_float * 5),
                 ("transfer_impact", ctypes.c_float * 5), ("io_threads", ctypes.c_int32),
-                ("cpu_guard", ctypes.c_int32), ("gpu_ms", ctypes.c_float * 5), ("reserved", ctypes.c_int32)]
+                ("cpu_guard", ctypes.c_int32), ("gpu_ms", ctypes.c_float * 5), ("trace_cap", ctypes.c_int32),
+                ("trace", ctypes.POINTER(recon_pipe_event))]
 
 
 class recon_pipe_stats(ctypes.Structure):
@@ -118,7 +124,7 @@ class recon_pipe_stats(ctypes.Structure):
                 ("ops_gpu", ctypes.c_int64 * 5), ("busy_cpu_ms", ctypes.c_double * 5),
                 ("busy_gpu_ms", ctypes.c_double * 5), ("uploads", ctypes.c_int64), ("downloads", ctypes.c_int64),
                 ("upload_bytes", ctypes.c_int64), ("download_bytes", ctypes.c_int64),
-                ("transfer_ms", ctypes.c_double), ("io_ms", ctypes.c_double)]
+                ("transfer_ms", ctypes.c_double), ("io_ms", ctypes.c_double), ("trace_n", ctypes.c_int64)]
 
 
 _lib = None
@@ -387,10 +393,13 @@ def pipe_config(policy: str = "pats", cpu_workers: int = 0, use_gpu: bool = True
     return c
 
 
-def recon_pipeline_run(ctx, images, cfg: recon_pipe_config):
+def recon_pipeline_run(ctx, images, cfg: recon_pipe_config, trace: bool = False):
     """Run the tile pipeline on host uint8 numpy images (ctx may be None
     without the GPU).  Returns (outputs, stats): per tile a dict of `objects`,
-    `markers` (uint8) and `labels` (int32) numpy arrays and `count`; stats as a dict."""
+    `markers` (uint8) and `labels` (int32) numpy arrays and `count`; stats as a
+    dict, with `trace` (a list of (tile, op name, device, start_ms, end_ms) in
+    the order the devices took the instances; device 0 is the GPU, 1 + k CPU
+    worker k) when asked for."""
     import numpy as np
     lib = load_library()
     n = len(images)
@@ -412,6 +421,13 @@ def recon_pipeline_run(ctx, images, cfg: recon_pipe_config):
         t.label_pitch = im.shape[1]
         t.count = ctypes.addressof(counts) + 4 * i
     st = recon_pipe_stats()
+    events = None
+    if trace:
+        cap = 5 * max(n, 1)
+        events = (recon_pipe_event * cap)()
+        cfg = recon_pipe_config.from_buffer_copy(cfg)
+        cfg.trace_cap = cap
+        cfg.trace = ctypes.cast(events, ctypes.POINTER(recon_pipe_event))
     rc = lib.recon_pipeline_run(ctx, arr, n, ctypes.byref(cfg), ctypes.byref(st))
     _check(rc, lib.recon_pipeline_error().decode(errors="replace"))
     for i, o in enumerate(outs):
@@ -420,6 +436,9 @@ def recon_pipeline_run(ctx, images, cfg: recon_pipe_config):
     for f, _ in recon_pipe_stats._fields_:
         v = getattr(st, f)
         stats[f] = list(v) if not isinstance(v, (int, float)) else v
+    if trace:
+        stats["trace"] = [(e.tile, PIPE_OPS[e.op], e.device, e.start_ms, e.end_ms)
+                          for e in events[:st.trace_n]]
     return outs, stats
 
 

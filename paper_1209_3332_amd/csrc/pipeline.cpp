@@ -94,6 +94,7 @@ struct Ready {
 
 struct Device {
     bool gpu;
+    int id = 0;   // 0: the GPU, 1 + k: CPU worker k
     hipStream_t stream = nullptr;
     hostops::Scratch *scratch = nullptr;
 };
@@ -115,6 +116,7 @@ struct Run {
     uint64_t seq = 0;
     int next_tile = 0, done_tiles = 0;
     double gpu_left_ms = 0.0;    // estimated GPU time of the instances not started yet (cpu_guard)
+    Clock::time_point t0;        // start of the run (trace times)
     int err = RECON_OK;
     std::string err_msg;
     recon_pipe_stats st{};
@@ -412,6 +414,7 @@ void worker(Run &r, Device dev) {
     const bool basic = dev.gpu && !r.cfg.data_locality;
     while (true) {
         int slot, op;
+        int64_t ev = -1;   // this instance's trace entry
         {
             std::unique_lock<std::mutex> lk(r.mu);
             int i = -1;
@@ -421,6 +424,16 @@ void worker(Run &r, Device dev) {
             op = r.ready[i].op;
             r.ready.erase(r.ready.begin() + i);
             r.gpu_left_ms -= r.cfg.gpu_ms[op];
+            if (r.cfg.trace && r.st.trace_n < r.cfg.trace_cap) {
+                ev = r.st.trace_n++;
+                recon_pipe_event &e = r.cfg.trace[ev];
+                e.tile = r.slots[slot].tile;
+                e.op = op;
+                e.device = dev.id;
+                e.reserved = 0;
+                e.start_ms = ms_since(r.t0);
+                e.end_ms = -1.0;
+            }
         }
         Slot &sl = r.slots[slot];
         const uint8_t in = kOps[op].in_mask, out = kOps[op].out_mask;
@@ -445,6 +458,7 @@ void worker(Run &r, Device dev) {
         bool last;
         {
             std::lock_guard<std::mutex> g(r.mu);
+            if (ev >= 0) r.cfg.trace[ev].end_ms = ms_since(r.t0);
             if (dev.gpu) {
                 r.st.ops_gpu[op]++;
                 r.st.busy_gpu_ms[op] += ms;
@@ -467,6 +481,7 @@ int check_config(const recon_pipe_config *c, recon_ctx *ctx) {
     if (c->policy != RECON_SCHED_FCFS && c->policy != RECON_SCHED_PATS) return 1;
     if (c->cpu_workers < 0 || c->cpu_workers > 256 || c->window < 1 || c->window > 1024) return 1;
     if (c->io_threads < 0 || c->io_threads > 64) return 1;
+    if (c->trace_cap < 0 || (c->trace_cap > 0 && !c->trace)) return 1;
     if (c->use_gpu && !ctx) return 1;
     if (!c->use_gpu && c->cpu_workers == 0) return 1;
     if (c->conn != 4 && c->conn != 8) return 1;
@@ -546,6 +561,7 @@ extern "C" int recon_pipeline_run(recon_ctx *ctx, const recon_pipe_tile *tiles, 
     for (int k = 0; rc == RECON_OK && k < cfg->cpu_workers; ++k) {
         Device c;
         c.gpu = false;
+        c.id = 1 + k;
         c.scratch = hostops::scratch_new();
         if (cfg->use_gpu && hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking) != hipSuccess)
             rc = RECON_EDEVICE;
@@ -559,6 +575,7 @@ extern "C" int recon_pipeline_run(recon_ctx *ctx, const recon_pipe_tile *tiles, 
     for (int o = 0; o < RECON_PIPE_NOPS; ++o) r.gpu_left_ms += (double)n * cfg->gpu_ms[o];
     if (rc == RECON_OK) {
         const auto t0 = Clock::now();
+        r.t0 = t0;
         admit(r);
         std::vector<std::thread> th;
         for (auto &d : devs) th.emplace_back(worker, std::ref(r), d);

@@ -43,7 +43,7 @@ def test_struct_layouts(tmp_path):
     structs = {"recon_image": p.recon_image, "recon_task": p.recon_task, "recon_config": p.recon_config,
                "recon_stats": p.recon_stats, "recon_serve_counters": p.recon_serve_counters,
                "recon_pipe_tile": p.recon_pipe_tile, "recon_pipe_config": p.recon_pipe_config,
-               "recon_pipe_stats": p.recon_pipe_stats}
+               "recon_pipe_stats": p.recon_pipe_stats, "recon_pipe_event": p.recon_pipe_event}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "recon.h"', 'int main(void) {']
     for name, cls in structs.items():
         lines.append('printf("%s %%zu\\n", sizeof(%s));' % (name, name))

@@ -115,6 +115,33 @@ def test_cpu_limits(lib, rc, tiles, expected, policy):
                     assert st["ops_cpu"][k] == 0, (kw, op)
 
 
+ORDER_SPEEDUP = {"hdome": 30, "fill_holes": 20, "area_threshold": 5, "markers": 10, "label": 2}
+SHORT = {"hdome": "h", "fill_holes": "f", "area_threshold": "a", "markers": "m", "label": "l"}
+
+
+@pytest.mark.parametrize("policy,dl,impact,want", [
+    # PATS on the GPU: the highest estimated speedup first
+    ("pats", False, 0.0, "h0 h1 h2 f0 f1 f2 a0 m0 a1 m1 a2 m2 l0 l1 l2"),
+    # data locality with PATS: a resident instance wins when its speedup is at
+    # least the best one's times (1 - transfer impact of the best one's operation)
+    ("pats", True, 0.0, "h0 h1 h2 f0 f1 f2 a0 m0 a1 m1 a2 m2 l0 l1 l2"),
+    ("pats", True, 0.5, "h0 f0 h1 f1 h2 f2 a0 m0 a1 m1 a2 m2 l0 l1 l2"),
+    # FCFS with data locality always prefers resident data (oldest first)
+    ("fcfs", True, 0.0, "h0 f0 a0 m0 l0 h1 f1 a1 m1 l1 h2 f2 a2 m2 l2"),
+    ("fcfs", False, 0.0, "h0 h1 h2 f0 f1 f2 a0 a1 a2 m0 l0 m1 l1 m2 l2"),
+])
+def test_policy_order_on_the_gpu(lib, rc, policy, dl, impact, want):
+    """With the GPU alone the order of the instances is fixed by the policy and
+    the data-locality rule; the trace must show exactly the rule."""
+    tiles = [synth.scaled_config1_tile(64, 96, synth.seed_for(9, 40 + i)) for i in range(3)]
+    cfg = lib.pipe_config(policy=policy, cpu_workers=0, use_gpu=True, window=3, data_locality=dl,
+                          speedup=ORDER_SPEEDUP, transfer_impact={k: impact for k in ORDER_SPEEDUP})
+    _, st = lib.recon_pipeline_run(rc.ctx, tiles, cfg, trace=True)
+    got = " ".join("%s%d" % (SHORT[op], tile) for tile, op, dev, t0, t1 in st["trace"])
+    assert got == want
+    assert all(dev == 0 for _, _, dev, _, _ in st["trace"])
+
+
 def test_pipeline_twice_in_a_row_and_after_other_work(lib, rc, tiles, expected, torch_mod):
     cfg = lib.pipe_config(policy="pats", cpu_workers=2, use_gpu=True, window=2, conn=8, h=H,
                           area_min=LO, area_max=HI, speedup=SPEEDUP)

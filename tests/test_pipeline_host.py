@@ -97,6 +97,34 @@ def test_cpu_only_pipeline_matches_oracle(lib, oracle_mod, policy, window, worke
     assert st["uploads"] == 0 and st["downloads"] == 0
 
 
+ORDER_SPEEDUP = {"hdome": 30, "fill_holes": 20, "area_threshold": 5, "markers": 10, "label": 2}
+SHORT = {"hdome": "h", "fill_holes": "f", "area_threshold": "a", "markers": "m", "label": "l"}
+
+
+def order_of(st):
+    return " ".join("%s%d" % (SHORT[op], tile) for tile, op, dev, t0, t1 in st["trace"])
+
+
+@pytest.mark.parametrize("policy,window,want", [
+    # FCFS: the oldest ready instance first (breadth-first over the tiles)
+    ("fcfs", 3, "h0 h1 h2 f0 f1 f2 a0 a1 a2 m0 l0 m1 l1 m2 l2"),
+    # PATS on a CPU core: the lowest estimated speedup first, ties to the oldest
+    ("pats", 3, "h0 f0 a0 l0 m0 h1 f1 a1 l1 m1 h2 f2 a2 l2 m2"),
+    # a window of one tile leaves one choice at a time (markers before labels
+    # under FCFS, labels first under PATS)
+    ("fcfs", 1, "h0 f0 a0 m0 l0 h1 f1 a1 m1 l1 h2 f2 a2 m2 l2"),
+    ("pats", 1, "h0 f0 a0 l0 m0 h1 f1 a1 l1 m1 h2 f2 a2 l2 m2"),
+])
+def test_policy_order_on_one_cpu_worker(lib, policy, window, want):
+    """With one CPU worker and no GPU the order of the instances is fixed by the
+    policy alone: the trace must show exactly the published rule."""
+    tiles = [synth.scaled_config1_tile(40, 70, synth.seed_for(9, 30 + i)) for i in range(3)]
+    cfg = lib.pipe_config(policy=policy, cpu_workers=1, use_gpu=False, window=window, speedup=ORDER_SPEEDUP)
+    _, st = lib.recon_pipeline_run(None, tiles, cfg, trace=True)
+    assert order_of(st) == want
+    assert st["trace_n"] == 15 and all(dev == 1 and t1 >= t0 >= 0 for _, _, dev, t0, t1 in st["trace"])
+
+
 def test_cpu_only_run_ignores_the_guard(lib, oracle_mod):
     """Without a GPU the CPU workers take everything, whatever the guard says."""
     tiles = [synth.scaled_config1_tile(100, 140, synth.seed_for(9, 12 + i)) for i in range(3)]
