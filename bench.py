@@ -767,7 +767,8 @@ PIPE_IN = {"hdome": 1, "fill_holes": 1, "area_threshold": 1, "markers": 1, "labe
 PIPE_OUT = {"hdome": 1, "fill_holes": 1, "area_threshold": 1, "markers": 1, "label": 4}   # bytes/px written
 
 
-def pipeline(recon, torch, n_tiles, size, window, cpu_workers, workers, windows=(), h=20, conn=8, lo=20, hi=1000):
+def pipeline(recon, torch, n_tiles, size, window, cpu_workers, workers, windows=(), io_threads=2, h=20, conn=8,
+             lo=20, hi=1000):
     """The co-scheduled tile pipeline (hdome -> fill-holes -> area filter ->
     {Pre-Watershed markers, labels}) on n_tiles nuclei-like tiles from host
     memory: the GPU alone, then the GPU beside cpu_workers CPU workers under
@@ -785,7 +786,7 @@ def pipeline(recon, torch, n_tiles, size, window, cpu_workers, workers, windows=
             tiles[i] = img
     log("pipeline: generated %d tiles in %.1f s" % (n_tiles, time.perf_counter() - t0))
     ops = list(recon.PIPE_OPS)
-    base = dict(conn=conn, h=h, area_min=lo, area_max=hi)
+    base = dict(conn=conn, h=h, area_min=lo, area_max=hi, io_threads=io_threads)
     # calibration: CPU variants on one tile, one core
     cpu_ms = {}
     x = tiles[0]
@@ -800,7 +801,7 @@ def pipeline(recon, torch, n_tiles, size, window, cpu_workers, workers, windows=
         if op == "area_threshold":
             a_img = y
     res = {"tiles": n_tiles, "tile": [size, size], "pixels": n_tiles * size * size, "window": window,
-           "cpu_workers": cpu_workers, "gpus": 1, "conn": conn, "h": h, "area": [lo, hi]}
+           "cpu_workers": cpu_workers, "io_threads": io_threads, "gpus": 1, "conn": conn, "h": h, "area": [lo, hi]}
     with recon.Recon(0) as ctx:
         # GPU variants on the same tile (3 copies, the last two counted)
         _, st = recon.recon_pipeline_run(ctx.ctx, [tiles[0]], recon.pipe_config(cpu_workers=0, window=1, **base))
@@ -915,6 +916,7 @@ def main():
     ap.add_argument("--pipeline-window", type=int, default=16)
     # one core for the GPU manager thread and two for the I/O threads, the rest run CPU variants
     ap.add_argument("--pipeline-cpu-workers", type=int, default=max(1, min(16, len(os.sched_getaffinity(0))) - 3))
+    ap.add_argument("--pipeline-io-threads", type=int, default=2)
     ap.add_argument("--pipeline-windows", default="8,32",
                     help="extra window sizes for the FCFS / PATS (with DL) sweep")
     args = ap.parse_args()
@@ -998,7 +1000,8 @@ def main():
     if args.pipeline_tiles:
         out["pipeline"] = pipeline(recon, torch, args.pipeline_tiles, args.size, args.pipeline_window,
                                    args.pipeline_cpu_workers, args.workers,
-                                   windows=[int(w) for w in args.pipeline_windows.split(",") if w])
+                                   windows=[int(w) for w in args.pipeline_windows.split(",") if w],
+                                   io_threads=args.pipeline_io_threads)
     ok = True
     if not args.no_cpu_baseline:
         # the oracle leg: its rate on the host cores, then every deferred comparison
