@@ -393,25 +393,41 @@ def pipe_config(policy: str = "pats", cpu_workers: int = 0, use_gpu: bool = True
     return c
 
 
-def recon_pipeline_run(ctx, images, cfg: recon_pipe_config, trace: bool = False):
+def pipe_outputs(images):
+    """Output buffers for recon_pipeline_run (reusable across runs)."""
+    import numpy as np
+    return [{"objects": np.empty(im.shape, np.uint8), "markers": np.empty(im.shape, np.uint8),
+             "labels": np.empty(im.shape, np.int32)} for im in images]
+
+
+def recon_pipeline_run(ctx, images, cfg: recon_pipe_config, trace: bool = False, outputs=None):
     """Run the tile pipeline on host uint8 numpy images (ctx may be None
     without the GPU).  Returns (outputs, stats): per tile a dict of `objects`,
-    `markers` (uint8) and `labels` (int32) numpy arrays and `count`; stats as a
-    dict, with `trace` (a list of (tile, op name, device, start_ms, end_ms) in
-    the order the devices took the instances; device 0 is the GPU, 1 + k CPU
-    worker k) when asked for."""
+    `markers` (uint8) and `labels` (int32) numpy arrays and `count` (the
+    caller's `outputs`, from pipe_outputs, when given: buffers reused across
+    runs); stats as a dict, with `trace` (a list of (tile, op name, device,
+    start_ms, end_ms) in the order the devices took the instances; device 0 is
+    the GPU, 1 + k CPU worker k) when asked for."""
     import numpy as np
     lib = load_library()
     n = len(images)
     imgs = [np.ascontiguousarray(im, dtype=np.uint8) for im in images]
+    if outputs is None:
+        outputs = pipe_outputs(imgs)
+    if len(outputs) != n:
+        raise ValueError("one output dict per image")
     outs = []
     arr = (recon_pipe_tile * max(n, 1))()
     counts = (ctypes.c_int32 * max(n, 1))()
     for i, im in enumerate(imgs):
         if im.ndim != 2:
             raise ValueError("images must be 2-D")
-        o = {"objects": np.empty_like(im), "markers": np.empty_like(im),
-             "labels": np.empty(im.shape, dtype=np.int32)}
+        o = outputs[i]
+        for k, dt in (("objects", np.uint8), ("markers", np.uint8), ("labels", np.int32)):
+            a = o[k]
+            if a.shape != im.shape or a.dtype != dt or not a.flags.c_contiguous:
+                raise ValueError("output %s of tile %d must be a C-contiguous %s array of the image's shape"
+                                 % (k, i, np.dtype(dt).name))
         outs.append(o)
         t = arr[i]
         t.image = im.ctypes.data

@@ -164,3 +164,23 @@ def test_pipeline_argument_errors(lib):
     assert outs == [] and st["makespan_ms"] == 0.0
     with pytest.raises(lib.ReconError):
         lib.recon_pipeline_host_op("hdome", img[0], lib.pipe_config(h=0))
+
+
+def test_pipeline_writes_into_reused_output_buffers(lib, oracle_mod):
+    tiles = [synth.scaled_config1_tile(90, 130, synth.seed_for(9, 50 + i)) for i in range(2)]
+    bufs = lib.pipe_outputs(tiles)
+    cfg = lib.pipe_config(policy="fcfs", cpu_workers=2, use_gpu=False, window=2)
+    for rep in range(2):
+        for o in bufs:   # stale contents must be overwritten
+            o["objects"][:] = 77
+            o["markers"][:] = 77
+            o["labels"][:] = -7
+        outs, _ = lib.recon_pipeline_run(None, tiles, cfg, outputs=bufs)
+        for img, o, b in zip(tiles, outs, bufs):
+            assert o["objects"] is b["objects"]
+            want = oracle_chain(oracle_mod, img, H_DEFAULT, 8, LO, HI)
+            assert all(np.array_equal(o[k], want[k]) for k in ("objects", "markers", "labels"))
+    bad = lib.pipe_outputs(tiles)
+    bad[1]["labels"] = np.empty(tiles[1].shape, np.int64)
+    with pytest.raises(ValueError):
+        lib.recon_pipeline_run(None, tiles, cfg, outputs=bad)
