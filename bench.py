@@ -930,9 +930,9 @@ def main():
     ap.add_argument("--pipeline-tiles", type=int, default=64,
                     help="tiles of the co-scheduled pipeline section (0 skips it)")
     ap.add_argument("--pipeline-window", type=int, default=16)
-    # one core for the GPU manager thread and two for the I/O threads, the rest run CPU variants
-    ap.add_argument("--pipeline-cpu-workers", type=int, default=max(1, min(16, len(os.sched_getaffinity(0))) - 3))
-    ap.add_argument("--pipeline-io-threads", type=int, default=2)
+    # one core for the GPU manager thread and four for the I/O threads, the rest run CPU variants
+    ap.add_argument("--pipeline-cpu-workers", type=int, default=max(1, min(16, len(os.sched_getaffinity(0))) - 5))
+    ap.add_argument("--pipeline-io-threads", type=int, default=4)
     ap.add_argument("--pipeline-windows", default="8,32",
                     help="extra window sizes for the FCFS / PATS (with DL) sweep")
     args = ap.parse_args()
