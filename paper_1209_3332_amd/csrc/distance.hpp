@@ -22,8 +22,10 @@
 //             every pixel takes min over x' of (x - x')^2 + g(x')^2,
 //             searched outward from x and stopped once (x - x')^2 alone
 //             reaches the best value (no farther column can do better; the
-//             pixel's own column bounds the search by g(x)).  Writes dist2
-//             (int32) or D8 (uint8), in place over the row it read.
+//             pixel's own column bounds the search by g(x)), inside the
+//             columns its segment's anchors found (the minimising column
+//             moves right with x).  Writes dist2 (int32) or D8 (uint8), in
+//             place over the row it read.
 #pragma once
 #include "kernels.hpp"
 
@@ -232,29 +234,103 @@ __device__ __forceinline__ uint32_t isqrt_cap255(int64_t v) {
 
 // Row pass.  One workgroup (any size) per row, grid-stride over rows; dynamic
 // LDS: w * 4 bytes.
+//
+// Every pixel x takes min over columns i of f_i(x) = (x - i)^2 + g(i)^2.  For
+// i < j, f_i - f_j = (j - i)(2x - i - j) + g(i)^2 - g(j)^2 grows strictly with
+// x, so every minimising column of a pixel lies at or right of every
+// minimising column of any pixel to its left (and at or left of those of any
+// pixel to its right).  The row is cut into segments of EDT_ANCHOR pixels:
+//   1. the anchors (the first pixel of every segment, and the last pixel of
+//      the row) search outward from their own column with no bound and store a
+//      minimising column in the g row, over their own entry (the row itself
+//      is in LDS by then);
+//   2. every other pixel searches outward from its own column, but only inside
+//      [column of its segment's anchor, column of the next anchor], stopping
+//      once (x - i)^2 alone reaches the best value;
+//   3. the anchors' own values follow from their columns.
+// A pixel's search is thus bounded by the distance to its best column, as an
+// unbounded outward search is, and also by the span between the anchors'
+// columns: an image with few 0 pixels no longer costs each pixel a search as
+// long as its distance (the anchors alone pay it).
+constexpr int EDT_ANCHOR = 256;
+
+__device__ __forceinline__ int64_t edt_f(RK_LDS const int32_t *row, int x, int i) {
+    const int32_t v = row[i];
+    return v == EDT_NONE ? INT64_MAX : (int64_t)(x - i) * (x - i) + (int64_t)v * v;
+}
+
+// Minimum of f_i(x) over i in [lo, hi], visiting columns by increasing |x - i|
+// and stopping once (x - i)^2 reaches the best value found; *arg receives a
+// minimising column (-1 if every column of the range is EDT_NONE).
+__device__ __forceinline__ int64_t edt_search(RK_LDS const int32_t *row, int x, int lo, int hi, int *arg) {
+    int64_t best = INT64_MAX;
+    int at = -1;
+    auto take = [&](int i) {
+        const int64_t f = edt_f(row, x, i);
+        if (f < best) {
+            best = f;
+            at = i;
+        }
+    };
+    if (x < lo) {
+        for (int i = lo; i <= hi && (int64_t)(i - x) * (i - x) < best; ++i) take(i);
+    } else if (x > hi) {
+        for (int i = hi; i >= lo && (int64_t)(x - i) * (x - i) < best; --i) take(i);
+    } else {
+        take(x);
+        for (int step = 1; (x - step >= lo || x + step <= hi) && (int64_t)step * step < best; ++step) {
+            if (x - step >= lo) take(x - step);
+            if (x + step <= hi) take(x + step);
+        }
+    }
+    *arg = at;
+    return best;
+}
+
+__device__ __forceinline__ void edt_put(const EdtArgs &a, RK_GLOBAL int32_t *gr, int y, int x, int64_t best) {
+    if (a.mode == 0)
+        gr[x] = best == INT64_MAX ? 0x7fffffff : (int32_t)best;
+    else
+        gp(a.d8)[(int64_t)y * a.pitch_d8 + x] = (uint8_t)(best == INT64_MAX ? 255u : isqrt_cap255(best));
+}
+
 __global__ void edt_rows(EdtArgs a) {
     RK_LDS int32_t *row = (RK_LDS int32_t *)dyn_lds();
+    const int w = a.w;
+    const int n_seg = (w + EDT_ANCHOR - 1) / EDT_ANCHOR;
+    // anchors: k * EDT_ANCHOR for k < n_seg, and w - 1 (index n_seg) unless it is one already
+    const int last = w - 1;
+    const bool extra = (n_seg - 1) * EDT_ANCHOR != last;
+    const int n_anchor = n_seg + (extra ? 1 : 0);
+    auto anchor_x = [&](int k) { return k < n_seg ? k * EDT_ANCHOR : last; };
     for (int y = blockIdx.x; y < a.h; y += gridDim.x) {
         RK_GLOBAL int32_t *gr = (RK_GLOBAL int32_t *)a.g + (int64_t)y * a.pitch_g;
-        for (int x = threadIdx.x; x < a.w; x += blockDim.x) row[x] = gr[x];
+        for (int x = threadIdx.x; x < w; x += blockDim.x) row[x] = gr[x];
         __syncthreads();
-        for (int x = threadIdx.x; x < a.w; x += blockDim.x) {
-            const int32_t gx = row[x];
-            int64_t best = gx == EDT_NONE ? INT64_MAX : (int64_t)gx * gx;
-            for (int64_t step = 1; step < a.w && step * step < best; ++step) {
-                if (x - step >= 0) {
-                    const int32_t v = row[x - step];
-                    if (v != EDT_NONE && step * step + (int64_t)v * v < best) best = step * step + (int64_t)v * v;
-                }
-                if (x + step < a.w) {
-                    const int32_t v = row[x + step];
-                    if (v != EDT_NONE && step * step + (int64_t)v * v < best) best = step * step + (int64_t)v * v;
-                }
-            }
-            if (a.mode == 0)
-                gr[x] = best == INT64_MAX ? 0x7fffffff : (int32_t)best;
-            else
-                gp(a.d8)[(int64_t)y * a.pitch_d8 + x] = (uint8_t)(best == INT64_MAX ? 255u : isqrt_cap255(best));
+        // 1. the anchors' columns, kept in the g row (the row is in LDS now)
+        for (int k = threadIdx.x; k < n_anchor; k += blockDim.x) {
+            int arg;
+            const int ax = anchor_x(k);
+            (void)edt_search(row, ax, 0, last, &arg);
+            gr[ax] = arg;
+        }
+        __syncthreads();
+        // 2. the other pixels, each inside its segment's pair of anchor columns
+        for (int x = threadIdx.x; x < w; x += blockDim.x) {
+            const int k = x / EDT_ANCHOR;
+            if (x == k * EDT_ANCHOR || (extra && x == last)) continue;
+            const int lo = gr[k * EDT_ANCHOR];
+            const int hi = gr[anchor_x(k + 1)];
+            int arg;
+            const int64_t best = lo < 0 ? INT64_MAX : edt_search(row, x, lo, hi, &arg);
+            edt_put(a, gr, y, x, best);
+        }
+        __syncthreads();
+        // 3. the anchors' values
+        for (int k = threadIdx.x; k < n_anchor; k += blockDim.x) {
+            const int ax = anchor_x(k);
+            const int col = gr[ax];
+            edt_put(a, gr, y, ax, col < 0 ? INT64_MAX : edt_f(row, ax, col));
         }
         __syncthreads();
     }

@@ -146,3 +146,37 @@ def test_widest_rows(torch_mod, rc, oracle_mod):
     img = np.where(rng.random((9, 16384)) < 0.995, 255, 0).astype(np.uint8)
     assert_same(gpu_distance(torch_mod, rc, img), oracle_mod.distance2(img), "16384-wide dist2")
     assert_same(gpu_markers(torch_mod, rc, img, 8), oracle_mod.pre_watershed(img, 8), "16384-wide markers")
+
+
+def test_few_zero_pixels(torch_mod, rc):
+    """Images with very few 0 pixels, where the distances are long and a
+    search bounded only by each pixel's distance would cost O(width) per pixel:
+    one 0 pixel in a corner of a 4096 x 4096 image, 0 pixels only along the
+    first row, and a 16384-wide strip with a single 0 pixel.  Their distances
+    have closed forms (the squared distance to the single 0 pixel, or to the
+    first row), which the results must equal; the 4096 x 4096 one is timed too
+    (it must stay a short kernel)."""
+    import time
+    corner = np.full((4096, 4096), 255, np.uint8)
+    corner[0, 0] = 0
+    yy, xx = np.indices(corner.shape, dtype=np.int64)
+    assert_same(gpu_distance(torch_mod, rc, corner), (yy * yy + xx * xx).astype(np.int32), "corner dist2")
+    top = np.full((1024, 2048), 255, np.uint8)
+    top[0, :] = 0
+    yy, _ = np.indices(top.shape, dtype=np.int64)
+    assert_same(gpu_distance(torch_mod, rc, top), (yy * yy).astype(np.int32), "top-row dist2")
+    strip = np.full((5, 16384), 255, np.uint8)
+    strip[2, 9000] = 0
+    yy, xx = np.indices(strip.shape, dtype=np.int64)
+    assert_same(gpu_distance(torch_mod, rc, strip), ((yy - 2) ** 2 + (xx - 9000) ** 2).astype(np.int32),
+                "strip dist2")
+    x = torch_mod.from_numpy(corner).cuda()
+    d = torch_mod.empty(corner.shape, dtype=torch_mod.int32, device="cuda")
+    rc.distance(x, d)
+    torch_mod.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        rc.distance(x, d)
+    torch_mod.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / 3
+    assert dt < 0.05, "one 0 pixel in 4096 x 4096 took %.3f s" % dt

@@ -182,6 +182,18 @@ def test_distance_transform(emu_exe, oracle_mod):
     one = np.full((600, 5), 255, np.uint8)
     one[599, 2] = 0                     # distances beyond 255: the D8 cap, carries across segments
     imgs.append(one)
+    # rows of several anchor segments (a last pixel that is, or is not, an anchor itself)
+    # with few 0 pixels, where the anchors' columns bound every other pixel's search
+    for (h, w, zeros) in [(3, 257, [(0, 256)]), (2, 513, [(1, 0)]), (5, 1030, [(4, 1029)]),
+                          (4, 1100, [(0, 0), (3, 700)]), (3, 769, [])]:
+        im = np.full((h, w), 255, np.uint8)
+        for zy, zx in zeros:
+            im[zy, zx] = 0
+        imgs.append(im)
+    top = np.full((40, 600), 255, np.uint8)
+    top[0, :] = 0                       # 0 pixels only in the first row: g = y everywhere
+    imgs.append(top)
+    imgs.append(np.where(rng.random((6, 1300)) < 0.999, 255, 0).astype(np.uint8))
     _, _, binary = synth.config2_tile(seed=synth.seed_for(2, 26), size=96, n_gauss=2)
     imgs.append(binary)
     for i, img in enumerate(imgs):
