@@ -235,24 +235,26 @@ __device__ __forceinline__ uint32_t isqrt_cap255(int64_t v) {
 // Row pass.  One workgroup (any size) per row, grid-stride over rows; dynamic
 // LDS: w * 4 bytes.
 //
-// Every pixel x takes min over columns i of f_i(x) = (x - i)^2 + g(i)^2.  For
-// i < j, f_i - f_j = (j - i)(2x - i - j) + g(i)^2 - g(j)^2 grows strictly with
-// x, so every minimising column of a pixel lies at or right of every
-// minimising column of any pixel to its left (and at or left of those of any
-// pixel to its right).  The row is cut into segments of EDT_ANCHOR pixels:
+// Every pixel x takes min over columns i of f_i(x) = (x - i)^2 + g(i)^2,
+// searched outward from its own column and stopped once (x - i)^2 alone
+// reaches the best value.  That search is as long as the pixel's distance, so
+// it is first tried with EDT_TRY steps, which settles every pixel of ordinary
+// images.  A row with pixels left over (few 0 pixels, long distances) bounds
+// their searches with anchors: for i < j, f_i - f_j = (j - i)(2x - i - j) +
+// g(i)^2 - g(j)^2 grows strictly with x, so every minimising column of a pixel
+// lies at or right of every minimising column of any pixel to its left (and
+// at or left of those of any pixel to its right).  The row is cut into
+// segments of EDT_ANCHOR pixels:
 //   1. the anchors (the first pixel of every segment, and the last pixel of
-//      the row) search outward from their own column with no bound and store a
-//      minimising column in the g row, over their own entry (the row itself
-//      is in LDS by then);
-//   2. every other pixel searches outward from its own column, but only inside
-//      [column of its segment's anchor, column of the next anchor], stopping
-//      once (x - i)^2 alone reaches the best value;
+//      the row) search without bound and store a minimising column in the g
+//      row, over their own entry (the row itself is in LDS by then);
+//   2. every pixel left over searches only inside [column of its segment's
+//      anchor, column of the next anchor];
 //   3. the anchors' own values follow from their columns.
-// A pixel's search is thus bounded by the distance to its best column, as an
-// unbounded outward search is, and also by the span between the anchors'
-// columns: an image with few 0 pixels no longer costs each pixel a search as
-// long as its distance (the anchors alone pay it).
+// The anchors alone pay the long searches (17 of them in a 4096-pixel row).
 constexpr int EDT_ANCHOR = 256;
+constexpr int EDT_TRY = 64;          // outward steps tried before a pixel is left over
+constexpr int EDT_MAX_PER_THREAD = 64;   // pixels per thread and row (16384 / 256); a mask bit each
 
 __device__ __forceinline__ int64_t edt_f(RK_LDS const int32_t *row, int x, int i) {
     const int32_t v = row[i];
@@ -260,9 +262,12 @@ __device__ __forceinline__ int64_t edt_f(RK_LDS const int32_t *row, int x, int i
 }
 
 // Minimum of f_i(x) over i in [lo, hi], visiting columns by increasing |x - i|
-// and stopping once (x - i)^2 reaches the best value found; *arg receives a
-// minimising column (-1 if every column of the range is EDT_NONE).
-__device__ __forceinline__ int64_t edt_search(RK_LDS const int32_t *row, int x, int lo, int hi, int *arg) {
+// and stopping once (x - i)^2 reaches the best value found, or after
+// max_steps distances; *arg receives a minimising column (-1 if every visited
+// column is EDT_NONE) and *done whether the search ended by itself (the
+// minimum is exact) rather than at max_steps.
+__device__ __forceinline__ int64_t edt_search(RK_LDS const int32_t *row, int x, int lo, int hi, int max_steps,
+                                              int *arg, bool *done) {
     int64_t best = INT64_MAX;
     int at = -1;
     auto take = [&](int i) {
@@ -272,18 +277,25 @@ __device__ __forceinline__ int64_t edt_search(RK_LDS const int32_t *row, int x, 
             at = i;
         }
     };
+    bool finished = true;
     if (x < lo) {
         for (int i = lo; i <= hi && (int64_t)(i - x) * (i - x) < best; ++i) take(i);
     } else if (x > hi) {
         for (int i = hi; i >= lo && (int64_t)(x - i) * (x - i) < best; --i) take(i);
     } else {
         take(x);
-        for (int step = 1; (x - step >= lo || x + step <= hi) && (int64_t)step * step < best; ++step) {
+        int step = 1;
+        for (; (x - step >= lo || x + step <= hi) && (int64_t)step * step < best; ++step) {
+            if (step > max_steps) {
+                finished = false;
+                break;
+            }
             if (x - step >= lo) take(x - step);
             if (x + step <= hi) take(x + step);
         }
     }
     *arg = at;
+    *done = finished;
     return best;
 }
 
@@ -297,9 +309,9 @@ __device__ __forceinline__ void edt_put(const EdtArgs &a, RK_GLOBAL int32_t *gr,
 __global__ void edt_rows(EdtArgs a) {
     RK_LDS int32_t *row = (RK_LDS int32_t *)dyn_lds();
     const int w = a.w;
+    const int last = w - 1;
     const int n_seg = (w + EDT_ANCHOR - 1) / EDT_ANCHOR;
     // anchors: k * EDT_ANCHOR for k < n_seg, and w - 1 (index n_seg) unless it is one already
-    const int last = w - 1;
     const bool extra = (n_seg - 1) * EDT_ANCHOR != last;
     const int n_anchor = n_seg + (extra ? 1 : 0);
     auto anchor_x = [&](int k) { return k < n_seg ? k * EDT_ANCHOR : last; };
@@ -307,32 +319,63 @@ __global__ void edt_rows(EdtArgs a) {
         RK_GLOBAL int32_t *gr = (RK_GLOBAL int32_t *)a.g + (int64_t)y * a.pitch_g;
         for (int x = threadIdx.x; x < w; x += blockDim.x) row[x] = gr[x];
         __syncthreads();
-        // 1. the anchors' columns, kept in the g row (the row is in LDS now)
-        for (int k = threadIdx.x; k < n_anchor; k += blockDim.x) {
-            int arg;
-            const int ax = anchor_x(k);
-            (void)edt_search(row, ax, 0, last, &arg);
-            gr[ax] = arg;
+        // every pixel: a short outward search; the pixels it does not settle are left over
+        uint64_t open = 0;   // bit m: this thread's m-th pixel (threadIdx.x + m * blockDim.x) is left over
+        int m = 0;
+        for (int x = threadIdx.x; x < w; x += blockDim.x, ++m) {
+            const int32_t gx = row[x];
+            int64_t best = gx == EDT_NONE ? INT64_MAX : (int64_t)gx * gx;
+            int step = 1;
+            for (; step < w && (int64_t)step * step < best && step <= EDT_TRY; ++step) {
+                if (x - step >= 0) {
+                    const int32_t v = row[x - step];
+                    if (v != EDT_NONE && (int64_t)step * step + (int64_t)v * v < best)
+                        best = (int64_t)step * step + (int64_t)v * v;
+                }
+                if (x + step < w) {
+                    const int32_t v = row[x + step];
+                    if (v != EDT_NONE && (int64_t)step * step + (int64_t)v * v < best)
+                        best = (int64_t)step * step + (int64_t)v * v;
+                }
+            }
+            if (step >= w || (int64_t)step * step >= best) edt_put(a, gr, y, x, best);
+            else open |= 1ull << m;
         }
-        __syncthreads();
-        // 2. the other pixels, each inside its segment's pair of anchor columns
-        for (int x = threadIdx.x; x < w; x += blockDim.x) {
-            const int k = x / EDT_ANCHOR;
-            if (x == k * EDT_ANCHOR || (extra && x == last)) continue;
-            const int lo = gr[k * EDT_ANCHOR];
-            const int hi = gr[anchor_x(k + 1)];
-            int arg;
-            const int64_t best = lo < 0 ? INT64_MAX : edt_search(row, x, lo, hi, &arg);
-            edt_put(a, gr, y, x, best);
+        if (__syncthreads_or(open != 0ull)) {
+            // the settled pixels' stores (anchors' among them) come before the entries below
+            __syncthreads();
+            // 1. the anchors' columns, kept in the g row
+            for (int k = threadIdx.x; k < n_anchor; k += blockDim.x) {
+                int arg;
+                bool done;
+                const int ax = anchor_x(k);
+                (void)edt_search(row, ax, 0, last, w, &arg, &done);
+                gr[ax] = arg;
+            }
+            __syncthreads();
+            // 2. the pixels left over, each inside its segment's pair of anchor columns
+            m = 0;
+            for (int x = threadIdx.x; x < w; x += blockDim.x, ++m) {
+                const int k = x / EDT_ANCHOR;
+                if (!((open >> m) & 1ull) || x == k * EDT_ANCHOR || (extra && x == last)) continue;
+                const int lo = gr[k * EDT_ANCHOR];
+                const int hi = gr[anchor_x(k + 1)];
+                int arg;
+                bool done;
+                const int64_t best = lo < 0 ? INT64_MAX : edt_search(row, x, lo, hi, w, &arg, &done);
+                edt_put(a, gr, y, x, best);
+            }
+            __syncthreads();
+            // 3. the anchors' values (every anchor: the entry of a settled one was overwritten in 1.)
+            for (int k = threadIdx.x; k < n_anchor; k += blockDim.x) {
+                const int ax = anchor_x(k);
+                const int col = gr[ax];
+                edt_put(a, gr, y, ax, col < 0 ? INT64_MAX : edt_f(row, ax, col));
+            }
+            __syncthreads();
         }
-        __syncthreads();
-        // 3. the anchors' values
-        for (int k = threadIdx.x; k < n_anchor; k += blockDim.x) {
-            const int ax = anchor_x(k);
-            const int col = gr[ax];
-            edt_put(a, gr, y, ax, col < 0 ? INT64_MAX : edt_f(row, ax, col));
-        }
-        __syncthreads();
+        // (without pixels left over, the barrier of the test above already
+        // orders this row's reads of the LDS row before the next row's staging)
     }
 }
 
