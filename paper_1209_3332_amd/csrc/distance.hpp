@@ -315,10 +315,22 @@ __global__ void edt_rows(EdtArgs a) {
     const bool extra = (n_seg - 1) * EDT_ANCHOR != last;
     const int n_anchor = n_seg + (extra ? 1 : 0);
     auto anchor_x = [&](int k) { return k < n_seg ? k * EDT_ANCHOR : last; };
-    for (int y = blockIdx.x; y < a.h; y += gridDim.x) {
+    // "some pixel of the row is left over", one word per parity of the row
+    // count: a row's word is cleared during the row before it (after that
+    // row's staging barrier, by which every thread has read the word for the
+    // row before), set during its first pass and read after the barrier that
+    // ends the pass; one barrier, where a workgroup reduction takes three
+    __shared__ int left_over[2];
+    if (threadIdx.x == 0) {
+        left_over[0] = 0;
+        left_over[1] = 0;
+    }
+    int it = 0;
+    for (int y = blockIdx.x; y < a.h; y += gridDim.x, ++it) {
         RK_GLOBAL int32_t *gr = (RK_GLOBAL int32_t *)a.g + (int64_t)y * a.pitch_g;
         for (int x = threadIdx.x; x < w; x += blockDim.x) row[x] = gr[x];
         __syncthreads();
+        if (threadIdx.x == 0) left_over[(it + 1) & 1] = 0;
         // every pixel: a short outward search; the pixels it does not settle are left over
         uint64_t open = 0;   // bit m: this thread's m-th pixel (threadIdx.x + m * blockDim.x) is left over
         int m = 0;
@@ -341,9 +353,12 @@ __global__ void edt_rows(EdtArgs a) {
             if (step >= w || (int64_t)step * step >= best) edt_put(a, gr, y, x, best);
             else open |= 1ull << m;
         }
-        if (__syncthreads_or(open != 0ull)) {
-            // the settled pixels' stores (anchors' among them) come before the entries below
-            __syncthreads();
+        if (open) left_over[it & 1] = 1;
+        // this barrier also orders the settled pixels' stores (anchors' among
+        // them) before the anchor entries below, and, when nothing is left
+        // over, this row's reads of the LDS row before the next row's staging
+        __syncthreads();
+        if (left_over[it & 1]) {
             // 1. the anchors' columns, kept in the g row
             for (int k = threadIdx.x; k < n_anchor; k += blockDim.x) {
                 int arg;
@@ -374,8 +389,6 @@ __global__ void edt_rows(EdtArgs a) {
             }
             __syncthreads();
         }
-        // (without pixels left over, the barrier of the test above already
-        // orders this row's reads of the LDS row before the next row's staging)
     }
 }
 

@@ -14,6 +14,9 @@
 #define __device__ inline
 #define __host__
 #define __global__
+// a kernel's __shared__ variable: one per emulated workgroup (a workgroup is
+// one wave, whose lanes are fibers of one OS thread)
+#define __shared__ static thread_local
 #define __forceinline__
 #define __launch_bounds__(x)
 #define __align__(x) __attribute__((aligned(x)))
@@ -75,8 +78,7 @@ void check_lds(const void *p, size_t n);       // bounds check of an LDS access
 
 inline int __lane_id() { return kemu::lane(); }
 inline void __syncthreads() { kemu::wave_sync(); }
-// one wave per emulated workgroup: the workgroup's OR is the wave's ballot
-inline int __syncthreads_or(int p) { return kemu::ballot(p != 0) != 0ull ? 1 : 0; }
+
 // The wave barrier orders memory accesses across the lanes of one wave (the
 // hardware runs them in lockstep); here it is a switch point like a barrier.
 inline void __builtin_amdgcn_wave_barrier() { kemu::wave_sync(); }
