@@ -35,7 +35,7 @@ typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int32_t EDT_NONE = 0x3fffffff;   // no 0 pixel in the column
 constexpr int EDT_SEG = 16;                // rows per column segment (held in registers)
-constexpr int EDT_MAX_W = 16384;           // widest row staged in LDS (64 KiB)
+constexpr int EDT_MAX_W = 16384;           // widest row staged in LDS
 
 struct EdtArgs {
     const uint8_t *img;    // input (0 = background)
@@ -256,9 +256,13 @@ constexpr int EDT_ANCHOR = 256;
 constexpr int EDT_TRY = 64;          // outward steps tried before a pixel is left over
 constexpr int EDT_MAX_PER_THREAD = 64;   // pixels per thread and row (16384 / 256); a mask bit each
 
-__device__ __forceinline__ int64_t edt_f(RK_LDS const int32_t *row, int x, int i) {
-    const int32_t v = row[i];
-    return v == EDT_NONE ? INT64_MAX : (int64_t)(x - i) * (x - i) + (int64_t)v * v;
+// In LDS a column distance takes 16 bits (it is below the height, at most
+// 16384); EDT_NONE16 marks a column without a 0 pixel.
+constexpr uint32_t EDT_NONE16 = 0xffffu;
+
+__device__ __forceinline__ int64_t edt_f(RK_LDS const uint16_t *row, int x, int i) {
+    const uint32_t v = row[i];
+    return v == EDT_NONE16 ? INT64_MAX : (int64_t)(x - i) * (x - i) + (int64_t)v * v;
 }
 
 // Minimum of f_i(x) over i in [lo, hi], visiting columns by increasing |x - i|
@@ -266,7 +270,7 @@ __device__ __forceinline__ int64_t edt_f(RK_LDS const int32_t *row, int x, int i
 // max_steps distances; *arg receives a minimising column (-1 if every visited
 // column is EDT_NONE) and *done whether the search ended by itself (the
 // minimum is exact) rather than at max_steps.
-__device__ __forceinline__ int64_t edt_search(RK_LDS const int32_t *row, int x, int lo, int hi, int max_steps,
+__device__ __forceinline__ int64_t edt_search(RK_LDS const uint16_t *row, int x, int lo, int hi, int max_steps,
                                               int *arg, bool *done) {
     int64_t best = INT64_MAX;
     int at = -1;
@@ -307,8 +311,14 @@ __device__ __forceinline__ void edt_put(const EdtArgs &a, RK_GLOBAL int32_t *gr,
 }
 
 __global__ void edt_rows(EdtArgs a) {
-    RK_LDS int32_t *row = (RK_LDS int32_t *)dyn_lds();
     const int w = a.w;
+    // the row of column distances, 16 bits each, then (rows wider than
+    // EDT_TRY, the only ones that can leave pixels over) two flag words: all
+    // inside the w * 4 bytes of dynamic LDS, so the kernel needs no static LDS
+    // (which would cost a workgroup per CU of occupancy)
+    RK_LDS uint16_t *row = (RK_LDS uint16_t *)dyn_lds();
+    RK_LDS int *left_over = (RK_LDS int *)(dyn_lds() + ((2 * w + 3) & ~3));
+    const bool may_leave = w > EDT_TRY;
     const int last = w - 1;
     const int n_seg = (w + EDT_ANCHOR - 1) / EDT_ANCHOR;
     // anchors: k * EDT_ANCHOR for k < n_seg, and w - 1 (index n_seg) unless it is one already
@@ -320,45 +330,47 @@ __global__ void edt_rows(EdtArgs a) {
     // row's staging barrier, by which every thread has read the word for the
     // row before), set during its first pass and read after the barrier that
     // ends the pass; one barrier, where a workgroup reduction takes three
-    __shared__ int left_over[2];
-    if (threadIdx.x == 0) {
+    if (may_leave && threadIdx.x == 0) {
         left_over[0] = 0;
         left_over[1] = 0;
     }
     int it = 0;
     for (int y = blockIdx.x; y < a.h; y += gridDim.x, ++it) {
         RK_GLOBAL int32_t *gr = (RK_GLOBAL int32_t *)a.g + (int64_t)y * a.pitch_g;
-        for (int x = threadIdx.x; x < w; x += blockDim.x) row[x] = gr[x];
+        for (int x = threadIdx.x; x < w; x += blockDim.x) {
+            const int32_t v = gr[x];
+            row[x] = (uint16_t)(v == EDT_NONE ? EDT_NONE16 : (uint32_t)v);
+        }
         __syncthreads();
-        if (threadIdx.x == 0) left_over[(it + 1) & 1] = 0;
+        if (may_leave && threadIdx.x == 0) left_over[(it + 1) & 1] = 0;
         // every pixel: a short outward search; the pixels it does not settle are left over
         uint64_t open = 0;   // bit m: this thread's m-th pixel (threadIdx.x + m * blockDim.x) is left over
         int m = 0;
         for (int x = threadIdx.x; x < w; x += blockDim.x, ++m) {
-            const int32_t gx = row[x];
-            int64_t best = gx == EDT_NONE ? INT64_MAX : (int64_t)gx * gx;
+            const uint32_t gx = row[x];
+            int64_t best = gx == EDT_NONE16 ? INT64_MAX : (int64_t)gx * gx;
             int step = 1;
             for (; step < w && (int64_t)step * step < best && step <= EDT_TRY; ++step) {
                 if (x - step >= 0) {
-                    const int32_t v = row[x - step];
-                    if (v != EDT_NONE && (int64_t)step * step + (int64_t)v * v < best)
+                    const uint32_t v = row[x - step];
+                    if (v != EDT_NONE16 && (int64_t)step * step + (int64_t)v * v < best)
                         best = (int64_t)step * step + (int64_t)v * v;
                 }
                 if (x + step < w) {
-                    const int32_t v = row[x + step];
-                    if (v != EDT_NONE && (int64_t)step * step + (int64_t)v * v < best)
+                    const uint32_t v = row[x + step];
+                    if (v != EDT_NONE16 && (int64_t)step * step + (int64_t)v * v < best)
                         best = (int64_t)step * step + (int64_t)v * v;
                 }
             }
             if (step >= w || (int64_t)step * step >= best) edt_put(a, gr, y, x, best);
             else open |= 1ull << m;
         }
-        if (open) left_over[it & 1] = 1;
+        if (open) left_over[it & 1] = 1;   // (only rows wider than EDT_TRY can leave a pixel over)
         // this barrier also orders the settled pixels' stores (anchors' among
         // them) before the anchor entries below, and, when nothing is left
         // over, this row's reads of the LDS row before the next row's staging
         __syncthreads();
-        if (left_over[it & 1]) {
+        if (may_leave && left_over[it & 1]) {
             // 1. the anchors' columns, kept in the g row
             for (int k = threadIdx.x; k < n_anchor; k += blockDim.x) {
                 int arg;
