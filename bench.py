@@ -830,12 +830,15 @@ def pipeline(recon, torch, n_tiles, size, window, cpu_workers, workers, windows=
                               "transfer_GBs": gbs, "transfer_impact": impact}
         log("pipeline calibration: speedups " + ", ".join("%s %.0f" % (o, speedup[o]) for o in ops))
         runs = [("gpu_only", dict(policy="pats", cpu_workers=0, data_locality=True)),
+                ("gpu_only_prefetch", dict(policy="pats", cpu_workers=0, data_locality=True, prefetch=True)),
                 ("fcfs", dict(policy="fcfs", cpu_workers=cpu_workers, data_locality=False)),
                 ("fcfs_dl", dict(policy="fcfs", cpu_workers=cpu_workers, data_locality=True)),
                 ("pats", dict(policy="pats", cpu_workers=cpu_workers, data_locality=False)),
                 ("pats_dl", dict(policy="pats", cpu_workers=cpu_workers, data_locality=True)),
                 ("pats_dl_cutoff", None),
-                ("pats_dl_guard", dict(policy="pats", cpu_workers=cpu_workers, data_locality=True, cpu_guard=True))]
+                ("pats_dl_guard", dict(policy="pats", cpu_workers=cpu_workers, data_locality=True, cpu_guard=True)),
+                ("pats_dl_guard_prefetch", dict(policy="pats", cpu_workers=cpu_workers, data_locality=True,
+                                                cpu_guard=True, prefetch=True))]
         ref = None
         res["runs"] = {}
         for name, kw in runs:
@@ -857,7 +860,7 @@ def pipeline(recon, torch, n_tiles, size, window, cpu_workers, workers, windows=
                  "uploads": st["uploads"], "downloads": st["downloads"],
                  "transfer_GB": (st["upload_bytes"] + st["download_bytes"]) / 1e9,
                  "transfer_ms": st["transfer_ms"], "io_ms": st["io_ms"], "policy": kw["policy"],
-                 "data_locality": kw["data_locality"]}
+                 "data_locality": kw["data_locality"], "prefetch": bool(kw.get("prefetch"))}
             if ref is None:
                 ref = [{k: (v.copy() if hasattr(v, "copy") else v) for k, v in o.items()} for o in outs]
                 for i in (0, n_tiles - 1):
@@ -886,7 +889,8 @@ def pipeline(recon, torch, n_tiles, size, window, cpu_workers, workers, windows=
                     "makespan_ms": st["makespan_ms"], "cpu_ops": sum(st["ops_cpu"]), "same_as_gpu_only": same}
                 log("pipeline %s_dl window %d: %.1f ms" % (pol, w, st["makespan_ms"]))
                 del outs
-        g = res["runs"]["gpu_only"]["makespan_ms"]
+        # against the better of the two GPU-only runs
+        g = min(res["runs"]["gpu_only"]["makespan_ms"], res["runs"]["gpu_only_prefetch"]["makespan_ms"])
         res["speedup_over_gpu_only"] = {k: g / v["makespan_ms"] for k, v in res["runs"].items()}
         res["pats_over_fcfs"] = res["runs"]["fcfs"]["makespan_ms"] / res["runs"]["pats"]["makespan_ms"]
         res["pats_dl_over_fcfs_dl"] = res["runs"]["fcfs_dl"]["makespan_ms"] / res["runs"]["pats_dl"]["makespan_ms"]

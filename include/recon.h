@@ -425,6 +425,8 @@ typedef struct {
                                (speedup x gpu_ms) is at most the GPU's estimated remaining work
                                (gpu_ms summed over every instance not started yet); 0: off */
     float gpu_ms[RECON_PIPE_NOPS];           /* cpu_guard: estimated GPU time per operation */
+    int32_t prefetch;       /* 1: a tile's image is uploaded when the tile is admitted, before its
+                               first operation is queued (Sec. IV-D's prefetching); 0: on demand */
     int32_t trace_cap;      /* entries of `trace` (0: no trace) */
     struct recon_pipe_event *trace;  /* HOST out (or NULL): one entry per operation instance, in
                                         the order the devices took them (the first trace_cap) */

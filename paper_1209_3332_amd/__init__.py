@@ -115,7 +115,8 @@ class recon_pipe_config(ctypes.Structure):
                 ("h", ctypes.c_int32), ("cpu_max_speedup", ctypes.c_float), ("area_min", ctypes.c_int64),
                 ("area_max", ctypes.c_int64), ("speedup", ctypes.c_float * 5),
                 ("transfer_impact", ctypes.c_float * 5), ("io_threads", ctypes.c_int32),
-                ("cpu_guard", ctypes.c_int32), ("gpu_ms", ctypes.c_float * 5), ("trace_cap", ctypes.c_int32),
+                ("cpu_guard", ctypes.c_int32), ("gpu_ms", ctypes.c_float * 5), ("prefetch", ctypes.c_int32),
+                ("trace_cap", ctypes.c_int32),
                 ("trace", ctypes.POINTER(recon_pipe_event))]
 
 
@@ -365,7 +366,8 @@ def recon_last_error() -> str:
 def pipe_config(policy: str = "pats", cpu_workers: int = 0, use_gpu: bool = True, window: int = 8,
                 data_locality: bool = True, conn: int = 8, h: int = 20, area_min: int = 20, area_max: int = 1000,
                 speedup=None, transfer_impact=None, cpu_max_speedup: float = 0.0,
-                io_threads: int = 2, gpu_ms=None, cpu_guard: bool = False) -> recon_pipe_config:
+                io_threads: int = 2, gpu_ms=None, cpu_guard: bool = False,
+                prefetch: bool = False) -> recon_pipe_config:
     """recon_pipe_config; speedup / transfer_impact: dicts or sequences over PIPE_OPS."""
     c = recon_pipe_config()
     if policy not in POLICIES:
@@ -377,6 +379,7 @@ def pipe_config(policy: str = "pats", cpu_workers: int = 0, use_gpu: bool = True
     c.cpu_max_speedup = float(cpu_max_speedup)
     c.io_threads = int(io_threads)
     c.cpu_guard = int(bool(cpu_guard))
+    c.prefetch = int(bool(prefetch))
 
     def seq(v, default):
         if v is None:

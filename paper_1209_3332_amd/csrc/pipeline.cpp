@@ -147,6 +147,10 @@ int set_err(Run &r, int code, const char *fmt, ...) {
             return set_err(run, RECON_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
     } while (0)
 
+// Wait for the stream's work with a deadline: polled without sleeping for the
+// first 2 ms (an operation or a plane copy usually ends within that, and a
+// sleep of the host scheduler would add more than the wait itself), then with
+// short sleeps.
 int sync_stream(Run &r, hipStream_t s) {
     const auto t0 = Clock::now();
     while (true) {
@@ -154,8 +158,9 @@ int sync_stream(Run &r, hipStream_t s) {
         if (q == hipSuccess) return RECON_OK;
         if (q != hipErrorNotReady)
             return set_err(r, RECON_EDEVICE, "pipeline stream failed: %s", hipGetErrorString(q));
-        if (ms_since(t0) > 60000.0) return set_err(r, RECON_ETIMEDOUT, "pipeline stream wait exceeded 60 s");
-        std::this_thread::sleep_for(std::chrono::microseconds(20));
+        const double ms = ms_since(t0);
+        if (ms > 60000.0) return set_err(r, RECON_ETIMEDOUT, "pipeline stream wait exceeded 60 s");
+        if (ms > 2.0) std::this_thread::sleep_for(std::chrono::microseconds(20));
     }
 }
 
@@ -293,16 +298,27 @@ void load(Run &r, int k) {
     for (int o = 0; o < RECON_PIPE_NOPS; ++o) sl.waiting[o] = kOps[o].deps;
 }
 
-void admit(Run &r) {
+// Admit the next tiles into free slots.  With prefetching (and a GPU) the
+// admitting thread also uploads each image to the slot's device plane on its
+// stream `s` before the tile's first operation is queued, so that the GPU
+// finds it resident (the paper's prefetching of inputs, Sec. IV-D).
+int admit(Run &r, hipStream_t s) {
     std::vector<int> got;
     {
         std::lock_guard<std::mutex> g(r.mu);
         got = reserve(r);
     }
-    for (int k : got) load(r, k);
+    for (int k : got) {
+        load(r, k);
+        if (r.cfg.prefetch && r.cfg.use_gpu) {
+            int rc = stage(r, r.slots[k], 1u << PA, true, s);
+            if (rc) return rc;
+        }
+    }
     std::lock_guard<std::mutex> g(r.mu);
     for (int k : got) r.ready.push_back({k, RECON_PIPE_HDOME, r.seq++, r.cfg.speedup[RECON_PIPE_HDOME]});
     if (!got.empty()) r.cv.notify_all();
+    return RECON_OK;
 }
 
 bool resident(const Run &r, const Ready &x) {
@@ -379,10 +395,10 @@ int finish_tile(Run &r, int slot, hipStream_t s) {
         ++r.done_tiles;
         r.cv.notify_all();
     }
-    admit(r);
+    rc = admit(r, s);
     std::lock_guard<std::mutex> g(r.mu);
     r.st.io_ms += ms_since(t0);
-    return RECON_OK;
+    return rc;
 }
 
 // Tile completion and admission run on their own threads (the paper's
@@ -482,6 +498,7 @@ int check_config(const recon_pipe_config *c, recon_ctx *ctx) {
     if (c->cpu_workers < 0 || c->cpu_workers > 256 || c->window < 1 || c->window > 1024) return 1;
     if (c->io_threads < 0 || c->io_threads > 64) return 1;
     if (c->trace_cap < 0 || (c->trace_cap > 0 && !c->trace)) return 1;
+    if (c->prefetch < 0 || c->prefetch > 1) return 1;
     if (c->use_gpu && !ctx) return 1;
     if (!c->use_gpu && c->cpu_workers == 0) return 1;
     if (c->conn != 4 && c->conn != 8) return 1;
@@ -576,7 +593,9 @@ extern "C" int recon_pipeline_run(recon_ctx *ctx, const recon_pipe_tile *tiles, 
     if (rc == RECON_OK) {
         const auto t0 = Clock::now();
         r.t0 = t0;
-        admit(r);
+        // the first tiles are admitted here (on the first I/O stream, before
+        // the I/O threads start)
+        if (admit(r, io_streams.empty() ? nullptr : io_streams[0]) != RECON_OK) r.cv.notify_all();
         std::vector<std::thread> th;
         for (auto &d : devs) th.emplace_back(worker, std::ref(r), d);
         for (int k = 0; k < n_io; ++k) th.emplace_back(io_thread, std::ref(r), io_streams[k]);

@@ -98,6 +98,18 @@ def test_gpu_and_cpu_workers(lib, rc, tiles, expected, policy, dl, window):
         assert st["uploads"] >= sum(st["ops_gpu"])
 
 
+@pytest.mark.parametrize("cpu_workers", [0, 3])
+def test_prefetch(lib, rc, tiles, expected, cpu_workers):
+    """Prefetching uploads each admitted image before its first operation:
+    the same bytes, and with the GPU alone one upload per tile, none on demand."""
+    cfg = lib.pipe_config(policy="pats", cpu_workers=cpu_workers, use_gpu=True, window=2, conn=8, h=H,
+                          area_min=LO, area_max=HI, speedup=SPEEDUP, prefetch=True)
+    outs, st = lib.recon_pipeline_run(rc.ctx, tiles, cfg)
+    check(outs, expected[8])
+    if cpu_workers == 0:
+        assert st["uploads"] == len(tiles) and st["downloads"] == 3 * len(tiles)
+
+
 @pytest.mark.parametrize("policy", ["fcfs", "pats"])
 def test_cpu_limits(lib, rc, tiles, expected, policy):
     """The CPU cut-off and the remaining-work guard change who runs what, never the bytes."""
