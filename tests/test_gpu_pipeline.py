@@ -184,3 +184,25 @@ def test_pipeline_full_size_tiles(lib, rc, oracle_mod):
         want.append({"objects": a, "markers": oracle_mod.pre_watershed(a, 8), "labels": lab, "count": n})
     check(outs, want)
     assert [a + b for a, b in zip(st["ops_cpu"], st["ops_gpu"])] == [2] * 5
+
+
+def test_many_workers_and_io_threads(lib, rc, oracle_mod):
+    """Twelve CPU workers, four I/O threads, prefetching, a window of 6 over 16
+    tiles of mixed shapes, both policies with data locality and the guard, with
+    the trace on: every instance runs once, and every tile equals the oracle's chain."""
+    tiles = [synth.scaled_config1_tile(96 + 37 * (i % 5), 160 + 61 * (i % 3), synth.seed_for(9, 70 + i))
+             for i in range(16)]
+    want = []
+    for img in tiles:
+        a = oracle_mod.area_threshold(oracle_mod.fill_holes(oracle_mod.hdome(img, H, 8), 8), LO, HI, 8)
+        lab, n = oracle_mod.label(a, 8)
+        want.append({"objects": a, "markers": oracle_mod.pre_watershed(a, 8), "labels": lab, "count": n})
+    gpu_ms = {"hdome": 0.2, "fill_holes": 0.2, "area_threshold": 0.1, "markers": 0.1, "label": 0.05}
+    for policy in ("fcfs", "pats"):
+        cfg = lib.pipe_config(policy=policy, cpu_workers=12, use_gpu=True, window=6, data_locality=True, conn=8,
+                              h=H, area_min=LO, area_max=HI, speedup=SPEEDUP, io_threads=4, prefetch=True,
+                              gpu_ms=gpu_ms, cpu_guard=(policy == "pats"))
+        outs, st = lib.recon_pipeline_run(rc.ctx, tiles, cfg, trace=True)
+        check(outs, want)
+        seen = sorted((t, op) for t, op, _, _, _ in st["trace"])
+        assert seen == sorted((t, op) for t in range(16) for op in lib.PIPE_OPS)
