@@ -243,7 +243,16 @@ int gpu_compute(Run &r, Slot &sl, int op, hipStream_t s) {
             break;
     }
     if (rc) return set_err(r, rc, "GPU operation %d failed: %s", op, recon_last_error());
-    return sync_stream(r, s);
+    rc = sync_stream(r, s);
+    if (rc) return rc;
+    // the reconstructions (h-dome, fill-holes, the markers' regional maxima)
+    // report a launch their scheduler gave up only through its counters
+    if (op == RECON_PIPE_HDOME || op == RECON_PIPE_FILL || op == RECON_PIPE_MARKERS) {
+        recon_stats st;
+        if (recon_last_stats(r.ctx, &st) != RECON_OK)
+            return set_err(r, RECON_EDEVICE, "GPU operation %d failed: %s", op, recon_last_error());
+    }
+    return RECON_OK;
 }
 
 int cpu_compute(Run &r, Slot &sl, int op, hostops::Scratch *scr) {
@@ -286,6 +295,7 @@ std::vector<int> reserve(Run &r) {
     return got;
 }
 
+// Copy the tile's image into the slot's pinned plane and reset its counters.
 void load(Run &r, int k) {
     Slot &sl = r.slots[k];
     const recon_pipe_tile &t = r.tiles[sl.tile];
@@ -302,6 +312,17 @@ void load(Run &r, int k) {
 // admitting thread also uploads each image to the slot's device plane on its
 // stream `s` before the tile's first operation is queued, so that the GPU
 // finds it resident (the paper's prefetching of inputs, Sec. IV-D).
+int load_slot(Run &r, int k, hipStream_t s) {
+    load(r, k);
+    return r.cfg.prefetch && r.cfg.use_gpu ? stage(r, r.slots[k], 1u << PA, true, s) : RECON_OK;
+}
+
+// Queue the first operation of the loaded slots, in order (under r.mu).
+void queue_first(Run &r, const std::vector<int> &got) {
+    for (int k : got) r.ready.push_back({k, RECON_PIPE_HDOME, r.seq++, r.cfg.speedup[RECON_PIPE_HDOME]});
+    if (!got.empty()) r.cv.notify_all();
+}
+
 int admit(Run &r, hipStream_t s) {
     std::vector<int> got;
     {
@@ -309,15 +330,43 @@ int admit(Run &r, hipStream_t s) {
         got = reserve(r);
     }
     for (int k : got) {
-        load(r, k);
-        if (r.cfg.prefetch && r.cfg.use_gpu) {
-            int rc = stage(r, r.slots[k], 1u << PA, true, s);
-            if (rc) return rc;
-        }
+        int rc = load_slot(r, k, s);
+        if (rc) return rc;
     }
     std::lock_guard<std::mutex> g(r.mu);
-    for (int k : got) r.ready.push_back({k, RECON_PIPE_HDOME, r.seq++, r.cfg.speedup[RECON_PIPE_HDOME]});
-    if (!got.empty()) r.cv.notify_all();
+    queue_first(r, got);
+    return RECON_OK;
+}
+
+// The first window of tiles: loaded (and prefetched) on the I/O threads'
+// streams side by side, then queued together in tile order, before any device
+// starts (so the order in which the devices see them does not depend on
+// which load ends first).
+int admit_first(Run &r, const std::vector<hipStream_t> &streams) {
+    std::vector<int> got;
+    {
+        std::lock_guard<std::mutex> g(r.mu);
+        got = reserve(r);
+    }
+    std::atomic<size_t> next{0};
+    std::atomic<int> rc{RECON_OK};
+    auto body = [&](hipStream_t s) {
+        if (r.cfg.use_gpu && hipSetDevice(r.device) != hipSuccess) {
+            rc = set_err(r, RECON_EDEVICE, "hipSetDevice failed in a pipeline thread");
+            return;
+        }
+        for (size_t i; rc == RECON_OK && (i = next++) < got.size();) {
+            const int e = load_slot(r, got[i], s);
+            if (e) rc = e;
+        }
+    };
+    std::vector<std::thread> th;
+    for (size_t k = 1; k < streams.size() && k < got.size(); ++k) th.emplace_back(body, streams[k]);
+    body(streams[0]);
+    for (auto &t : th) t.join();
+    if (rc != RECON_OK) return rc;
+    std::lock_guard<std::mutex> g(r.mu);
+    queue_first(r, got);
     return RECON_OK;
 }
 
@@ -593,9 +642,8 @@ extern "C" int recon_pipeline_run(recon_ctx *ctx, const recon_pipe_tile *tiles, 
     if (rc == RECON_OK) {
         const auto t0 = Clock::now();
         r.t0 = t0;
-        // the first tiles are admitted here (on the first I/O stream, before
-        // the I/O threads start)
-        if (admit(r, io_streams.empty() ? nullptr : io_streams[0]) != RECON_OK) r.cv.notify_all();
+        // the first tiles are admitted here, before the devices and the I/O threads start
+        if (admit_first(r, io_streams) != RECON_OK) r.cv.notify_all();
         std::vector<std::thread> th;
         for (auto &d : devs) th.emplace_back(worker, std::ref(r), d);
         for (int k = 0; k < n_io; ++k) th.emplace_back(io_thread, std::ref(r), io_streams[k]);

@@ -862,18 +862,25 @@ void serve_loop(recon_ctx *ctx) {
                 }
                 continue;
             }
-            const int st = q == hipSuccess ? 2 : -1;
+            // the launch's counters were copied into the lane's pinned buffer
+            // ahead of its completion event: a launch its watchdog gave up
+            // fails every request it had not completed
+            const bool gave_up = q == hipSuccess && L.sub->h_work->abort != 0;
+            const int st = q == hipSuccess && !gave_up ? 2 : -1;
             if (q != hipSuccess) {
                 S->error = RECON_EDEVICE;
                 S->error_msg = std::string("serving launch failed: ") + hipGetErrorString(q);
+            } else if (gave_up) {
+                S->error = RECON_EDEVICE;
+                S->error_msg = "serving launch: scheduler watchdog expired, the launch did not converge";
             }
             for (auto &r : L.reqs) {
-                if (r.finished && st == 2) continue;   // completed already
+                // completed already (its tile's last visit was done and its
+                // status handed out, perhaps taken by a wait)
+                if (r.finished) continue;
                 S->status[r.ticket] = st;
-                if (!r.finished) {
-                    S->bytes_admitted -= r.bytes;
-                    S->slots_admitted -= 1;
-                }
+                S->bytes_admitted -= r.bytes;
+                S->slots_admitted -= 1;
             }
             L.reqs.clear();
             L.busy = false;
@@ -893,7 +900,12 @@ void serve_loop(recon_ctx *ctx) {
             }
             int rc = run_tasks(L.sub, tasks.data(), (int)tasks.size(), L.stream, false);
             L.seq = L.sub->launch_seq;
-            if (rc == RECON_OK && hipEventRecord(L.done, L.stream) != hipSuccess) rc = RECON_EDEVICE;
+            if (rc == RECON_OK) {
+                hipLaunchKernelGGL(rk::copy_table, dim3(1), dim3(64), 0, L.stream, (const uint8_t *)L.sub->last_work,
+                                   (uint8_t *)L.sub->h_work, (uint32_t)sizeof(rk::Work));
+                if (hipGetLastError() != hipSuccess || hipEventRecord(L.done, L.stream) != hipSuccess)
+                    rc = RECON_EDEVICE;
+            }
             if (rc != RECON_OK) {
                 S->error = rc;
                 S->error_msg = g_err;

@@ -154,3 +154,19 @@ def test_unknown_ticket(torch_mod, lib):
     with lib.Recon(0) as ctx:
         with pytest.raises(lib.ReconError):
             ctx.poll(12345)
+
+
+def test_abandoned_launch_fails_its_requests(torch_mod, lib):
+    """A serving launch that its scheduler gives up (the context's test hook
+    makes every block claim fail, so the launch aborts at once) fails the
+    requests it had not completed: recon_wait reports RECON_EDEVICE instead of
+    handing out an unfinished reconstruction."""
+    mask = synth.gaussian_tile(100, 300, 5, seed=3)
+    with lib.Recon(0, test_fault=1) as ctx:
+        m = torch_mod.from_numpy(synth.hdome_marker(mask, 30)).cuda()
+        k = torch_mod.from_numpy(mask).cuda()
+        torch_mod.cuda.synchronize()
+        tk = ctx.submit("dilate", m, k, 8)
+        with pytest.raises(lib.ReconError) as e:
+            ctx.wait(tk, 30_000_000)
+        assert e.value.code == lib.RECON_EDEVICE
