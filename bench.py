@@ -773,7 +773,9 @@ def pipeline(recon, torch, n_tiles, size, window, cpu_workers, workers, windows=
     {Pre-Watershed markers, labels}) on n_tiles nuclei-like tiles from host
     memory: the GPU alone, then the GPU beside cpu_workers CPU workers under
     FCFS and PATS, without and with data locality, and PATS with the CPU workers
-    kept off the operations a core would take too long on.  Speedup estimates
+    kept off the operations a core would take too long on, and the GPU manager
+    keeping two instances enqueued at once, alone and beside the CPU workers.
+    Speedup estimates
     come from a calibration on one tile (each operation's CPU variant against
     its GPU variant, computation only); every run's outputs are compared byte
     for byte with the GPU-only run's, and two tiles with the oracle."""
@@ -838,7 +840,14 @@ def pipeline(recon, torch, n_tiles, size, window, cpu_workers, workers, windows=
                 ("pats_dl_cutoff", None),
                 ("pats_dl_guard", dict(policy="pats", cpu_workers=cpu_workers, data_locality=True, cpu_guard=True)),
                 ("pats_dl_guard_prefetch", dict(policy="pats", cpu_workers=cpu_workers, data_locality=True,
-                                                cpu_guard=True, prefetch=True))]
+                                                cpu_guard=True, prefetch=True)),
+                # the GPU manager keeping two instances enqueued (the next one is
+                # chosen and enqueued while the previous one runs)
+                ("gpu_only_prefetch_inflight2", dict(policy="pats", cpu_workers=0, data_locality=True,
+                                                     prefetch=True, gpu_inflight=2)),
+                ("pats_dl_guard_prefetch_inflight2", dict(policy="pats", cpu_workers=cpu_workers,
+                                                          data_locality=True, cpu_guard=True, prefetch=True,
+                                                          gpu_inflight=2))]
         ref = None
         res["runs"] = {}
         for name, kw in runs:
@@ -860,7 +869,8 @@ def pipeline(recon, torch, n_tiles, size, window, cpu_workers, workers, windows=
                  "uploads": st["uploads"], "downloads": st["downloads"],
                  "transfer_GB": (st["upload_bytes"] + st["download_bytes"]) / 1e9,
                  "transfer_ms": st["transfer_ms"], "io_ms": st["io_ms"], "policy": kw["policy"],
-                 "data_locality": kw["data_locality"], "prefetch": bool(kw.get("prefetch"))}
+                 "data_locality": kw["data_locality"], "prefetch": bool(kw.get("prefetch")),
+                 "gpu_inflight": max(1, kw.get("gpu_inflight", 1))}
             if ref is None:
                 ref = [{k: (v.copy() if hasattr(v, "copy") else v) for k, v in o.items()} for o in outs]
                 for i in (0, n_tiles - 1):
@@ -889,7 +899,7 @@ def pipeline(recon, torch, n_tiles, size, window, cpu_workers, workers, windows=
                     "makespan_ms": st["makespan_ms"], "cpu_ops": sum(st["ops_cpu"]), "same_as_gpu_only": same}
                 log("pipeline %s_dl window %d: %.1f ms" % (pol, w, st["makespan_ms"]))
                 del outs
-        # against the better of the two GPU-only runs
+        # against the better of the two GPU-only runs with one instance at a time
         g = min(res["runs"]["gpu_only"]["makespan_ms"], res["runs"]["gpu_only_prefetch"]["makespan_ms"])
         res["speedup_over_gpu_only"] = {k: g / v["makespan_ms"] for k, v in res["runs"].items()}
         res["pats_over_fcfs"] = res["runs"]["fcfs"]["makespan_ms"] / res["runs"]["pats"]["makespan_ms"]

@@ -340,6 +340,18 @@ int recon_serve_stats(recon_ctx *ctx, recon_serve_counters *out);
  * 8 s), in which case its results are incomplete. */
 int recon_last_stats(recon_ctx *ctx, recon_stats *out);
 
+/* Enqueue on `stream`, after the context's last launch (which must have been
+ * enqueued on the same stream or be ordered before it), a write of that
+ * launch's outcome into *host_flag: 0 if it converged, 1 if its scheduler
+ * gave up (the case in which recon_last_stats returns RECON_EDEVICE).
+ * Nothing waits: the caller reads the word once the stream has passed that
+ * point (an event recorded after this call), and can meanwhile enqueue more
+ * work on the context.  host_flag must be pinned, device-accessible host
+ * memory (hipHostMalloc) of the caller's, at least 4 bytes; the word is
+ * written once per call.  With no launch yet it receives 0.  For callers that
+ * keep several operations in flight (the tile pipeline's GPU manager). */
+int recon_enqueue_status(recon_ctx *ctx, uint32_t *host_flag, void *stream);
+
 /* Kernel durations in ms of a recent launch of a context created with
  * timing = 1: `back` = 0 is the last launch sequence, 1 the one before, up to
  * 63.  dense_ms, seed_ms, drain_ms: the dense pass (K1), border seeding (K2)
@@ -430,6 +442,12 @@ typedef struct {
     int32_t trace_cap;      /* entries of `trace` (0: no trace) */
     struct recon_pipe_event *trace;  /* HOST out (or NULL): one entry per operation instance, in
                                         the order the devices took them (the first trace_cap) */
+    int32_t gpu_inflight;   /* instances the GPU manager keeps enqueued on its stream at once, 1..4
+                               (0: 1, the paper's one instance at a time).  With more, the next
+                               instance is chosen and enqueued while the previous one runs, which
+                               hides the host's round trip between them; the choice is then made
+                               among the instances ready at that earlier moment */
+    int32_t reserved_pipe;  /* 0 */
 } recon_pipe_config;
 
 /* One operation instance of a recon_pipeline_run, as it ran. */

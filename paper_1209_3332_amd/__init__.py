@@ -38,7 +38,7 @@ EXPORTED = (
     "recon_pre_watershed", "recon_batch",
     "recon_submit", "recon_poll", "recon_wait", "recon_serve_stop", "recon_serve_stats", "recon_last_stats",
     "recon_launch_times", "recon_last_error", "recon_pipeline_run", "recon_pipeline_error",
-    "recon_pipeline_host_op",
+    "recon_pipeline_host_op", "recon_enqueue_status",
 )
 
 
@@ -117,7 +117,8 @@ class recon_pipe_config(ctypes.Structure):
                 ("transfer_impact", ctypes.c_float * 5), ("io_threads", ctypes.c_int32),
                 ("cpu_guard", ctypes.c_int32), ("gpu_ms", ctypes.c_float * 5), ("prefetch", ctypes.c_int32),
                 ("trace_cap", ctypes.c_int32),
-                ("trace", ctypes.POINTER(recon_pipe_event))]
+                ("trace", ctypes.POINTER(recon_pipe_event)), ("gpu_inflight", ctypes.c_int32),
+                ("reserved_pipe", ctypes.c_int32)]
 
 
 class recon_pipe_stats(ctypes.Structure):
@@ -162,6 +163,7 @@ def load_library(path: str = LIB_PATH):
     lib.recon_serve_stop.argtypes = [P]
     lib.recon_serve_stats.argtypes = [P, ctypes.POINTER(recon_serve_counters)]
     lib.recon_last_stats.argtypes = [P, ctypes.POINTER(recon_stats)]
+    lib.recon_enqueue_status.argtypes = [P, P, P]
     F = ctypes.POINTER(ctypes.c_float)
     lib.recon_launch_times.argtypes = [P, ctypes.c_int, F, F, F, F, F]
     lib.recon_last_error.argtypes = []
@@ -359,6 +361,12 @@ def recon_last_stats(ctx: int) -> dict:
     return {f: getattr(s, f) for f, _ in recon_stats._fields_}
 
 
+def recon_enqueue_status(ctx: int, host_flag: int, stream=None) -> None:
+    """Enqueue a write of the last launch's outcome (0 converged, 1 given up)
+    into the pinned host word at address host_flag, on `stream`."""
+    _check(load_library().recon_enqueue_status(ctx, ctypes.c_void_p(int(host_flag)), _stream_ptr(stream)))
+
+
 def recon_last_error() -> str:
     return load_library().recon_last_error().decode(errors="replace")
 
@@ -367,7 +375,7 @@ def pipe_config(policy: str = "pats", cpu_workers: int = 0, use_gpu: bool = True
                 data_locality: bool = True, conn: int = 8, h: int = 20, area_min: int = 20, area_max: int = 1000,
                 speedup=None, transfer_impact=None, cpu_max_speedup: float = 0.0,
                 io_threads: int = 2, gpu_ms=None, cpu_guard: bool = False,
-                prefetch: bool = False) -> recon_pipe_config:
+                prefetch: bool = False, gpu_inflight: int = 1) -> recon_pipe_config:
     """recon_pipe_config; speedup / transfer_impact: dicts or sequences over PIPE_OPS."""
     c = recon_pipe_config()
     if policy not in POLICIES:
@@ -380,6 +388,7 @@ def pipe_config(policy: str = "pats", cpu_workers: int = 0, use_gpu: bool = True
     c.io_threads = int(io_threads)
     c.cpu_guard = int(bool(cpu_guard))
     c.prefetch = int(bool(prefetch))
+    c.gpu_inflight = int(gpu_inflight)
 
     def seq(v, default):
         if v is None:

@@ -1743,6 +1743,18 @@ __global__ void copy_table(const uint8_t *src, uint8_t *dst, uint32_t bytes) {
         dst[i] = src[i];
 }
 
+// The outcome of a launch for the host, without a wait: 1 if the scheduler of
+// any of its (up to three) block-height groups gave up, else 0, stored into
+// pinned host memory.
+__global__ void launch_outcome(const Work *w0, const Work *w1, const Work *w2, uint32_t *out) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    uint32_t ab = 0;
+    const Work *ws[3] = {w0, w1, w2};
+    for (int k = 0; k < 3; ++k)
+        if (ws[k]) ab |= __hip_atomic_load((uint32_t *)&ws[k]->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(out, ab ? 1u : 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 // Reset the scheduling state of the batch.
 //   RESET_STAGED     the scheduler starts empty (the dense and border kernels
 //                    of the staged pipeline run first);

@@ -14,7 +14,8 @@
 // the next one.
 //
 // Threads: one GPU manager thread (it calls the library's operations on its
-// own stream and waits for each instance), `cpu_workers` CPU threads (each
+// own stream, keeps up to `gpu_inflight` instances enqueued there and retires
+// each when the stream has passed it), `cpu_workers` CPU threads (each
 // runs the CPU variants of host_ops.cpp on one core) and `io_threads` threads
 // that bring finished tiles' results out and the next tiles' images in.  Every tile slot owns
 // pinned host planes and device planes for the tile's data; a per-plane bit
@@ -27,6 +28,7 @@
 #include <chrono>
 #include <condition_variable>
 #include <cstdarg>
+#include <deque>
 #include <cstdio>
 #include <cstring>
 #include <memory>
@@ -96,6 +98,7 @@ struct Device {
     bool gpu;
     int id = 0;   // 0: the GPU, 1 + k: CPU worker k
     hipStream_t stream = nullptr;
+    hipStream_t xfer = nullptr;   // the GPU manager's plane transfers (its stream computes)
     hostops::Scratch *scratch = nullptr;
 };
 
@@ -116,6 +119,7 @@ struct Run {
     uint64_t seq = 0;
     int next_tile = 0, done_tiles = 0;
     double gpu_left_ms = 0.0;    // estimated GPU time of the instances not started yet (cpu_guard)
+    std::atomic<uint64_t> ready_gen{0};   // bumped whenever instances become ready (read without r.mu)
     Clock::time_point t0;        // start of the run (trace times)
     int err = RECON_OK;
     std::string err_msg;
@@ -223,7 +227,8 @@ recon_image dev_image(Run &r, Slot &sl, int p) {
     return im;
 }
 
-int gpu_compute(Run &r, Slot &sl, int op, hipStream_t s) {
+// Enqueue the GPU variant of op on stream s (nothing waits for it).
+int gpu_enqueue(Run &r, Slot &sl, int op, hipStream_t s) {
     const recon_pipe_config &c = r.cfg;
     recon_image a = dev_image(r, sl, PA);
     int rc = RECON_OK;
@@ -243,15 +248,6 @@ int gpu_compute(Run &r, Slot &sl, int op, hipStream_t s) {
             break;
     }
     if (rc) return set_err(r, rc, "GPU operation %d failed: %s", op, recon_last_error());
-    rc = sync_stream(r, s);
-    if (rc) return rc;
-    // the reconstructions (h-dome, fill-holes, the markers' regional maxima)
-    // report a launch their scheduler gave up only through its counters
-    if (op == RECON_PIPE_HDOME || op == RECON_PIPE_FILL || op == RECON_PIPE_MARKERS) {
-        recon_stats st;
-        if (recon_last_stats(r.ctx, &st) != RECON_OK)
-            return set_err(r, RECON_EDEVICE, "GPU operation %d failed: %s", op, recon_last_error());
-    }
     return RECON_OK;
 }
 
@@ -320,7 +316,10 @@ int load_slot(Run &r, int k, hipStream_t s) {
 // Queue the first operation of the loaded slots, in order (under r.mu).
 void queue_first(Run &r, const std::vector<int> &got) {
     for (int k : got) r.ready.push_back({k, RECON_PIPE_HDOME, r.seq++, r.cfg.speedup[RECON_PIPE_HDOME]});
-    if (!got.empty()) r.cv.notify_all();
+    if (!got.empty()) {
+        r.ready_gen.fetch_add(1);
+        r.cv.notify_all();
+    }
 }
 
 int admit(Run &r, hipStream_t s) {
@@ -416,7 +415,10 @@ bool complete(Run &r, int slot, int op) {
     Slot &sl = r.slots[slot];
     for (int k = 0; k < 2; ++k) {
         const int nx = kOps[op].next[k];
-        if (nx >= 0 && --sl.waiting[nx] == 0) r.ready.push_back({slot, nx, r.seq++, r.cfg.speedup[nx]});
+        if (nx >= 0 && --sl.waiting[nx] == 0) {
+            r.ready.push_back({slot, nx, r.seq++, r.cfg.speedup[nx]});
+            r.ready_gen.fetch_add(1);
+        }
     }
     return --sl.left == 0;
 }
@@ -471,75 +473,211 @@ void io_thread(Run &r, hipStream_t s) {
     }
 }
 
+// Take ready instance i for device `dev` (under r.mu): remove it from the
+// ready list, count its estimated GPU time out of the remaining work and open
+// its trace entry (returned, or -1).
+int64_t take(Run &r, int i, const Device &dev, int &slot, int &op) {
+    slot = r.ready[i].slot;
+    op = r.ready[i].op;
+    r.ready.erase(r.ready.begin() + i);
+    r.gpu_left_ms -= r.cfg.gpu_ms[op];
+    int64_t ev = -1;
+    if (r.cfg.trace && r.st.trace_n < r.cfg.trace_cap) {
+        ev = r.st.trace_n++;
+        recon_pipe_event &e = r.cfg.trace[ev];
+        e.tile = r.slots[slot].tile;
+        e.op = op;
+        e.device = dev.id;
+        e.reserved = 0;
+        e.start_ms = ms_since(r.t0);
+        e.end_ms = -1.0;
+    }
+    return ev;
+}
+
+// An instance's outputs were written on `dev`: an in-place write leaves the
+// only valid copy where it was made.
+void outputs_written(Slot &sl, int op, const Device &dev) {
+    std::lock_guard<std::mutex> xg(sl.xfer_mu);
+    for (int p = 0; p < NPLANES; ++p)
+        if (kOps[op].out_mask & (1u << p)) sl.where[p].store(dev.gpu ? ON_DEV : ON_HOST);
+}
+
+// The instance of op on the slot has finished on `dev` (computation time ms)
+// and its outputs' location is recorded: mark it done (releasing its
+// successors; the tile's last instance hands the tile to the I/O threads).
+void finish_instance(Run &r, const Device &dev, int slot, int op, int64_t ev, double ms) {
+    bool last;
+    {
+        std::lock_guard<std::mutex> g(r.mu);
+        if (ev >= 0) r.cfg.trace[ev].end_ms = ms_since(r.t0);
+        if (dev.gpu) {
+            r.st.ops_gpu[op]++;
+            r.st.busy_gpu_ms[op] += ms;
+        } else {
+            r.st.ops_cpu[op]++;
+            r.st.busy_cpu_ms[op] += ms;
+        }
+        last = complete(r, slot, op);
+        if (last) r.finished.push_back(slot);
+        r.cv.notify_all();
+    }
+}
+
 void worker(Run &r, Device dev) {
     if (r.cfg.use_gpu && hipSetDevice(r.device) != hipSuccess) {
         set_err(r, RECON_EDEVICE, "hipSetDevice failed in a pipeline thread");
         return;
     }
-    const bool basic = dev.gpu && !r.cfg.data_locality;
     while (true) {
         int slot, op;
-        int64_t ev = -1;   // this instance's trace entry
+        int64_t ev;
         {
             std::unique_lock<std::mutex> lk(r.mu);
             int i = -1;
-            r.cv.wait(lk, [&] { return r.err || r.done_tiles == r.n || (i = pick(r, dev.gpu)) >= 0; });
+            r.cv.wait(lk, [&] { return r.err || r.done_tiles == r.n || (i = pick(r, false)) >= 0; });
             if (r.err || r.done_tiles == r.n) return;
-            slot = r.ready[i].slot;
-            op = r.ready[i].op;
-            r.ready.erase(r.ready.begin() + i);
-            r.gpu_left_ms -= r.cfg.gpu_ms[op];
-            if (r.cfg.trace && r.st.trace_n < r.cfg.trace_cap) {
-                ev = r.st.trace_n++;
-                recon_pipe_event &e = r.cfg.trace[ev];
-                e.tile = r.slots[slot].tile;
-                e.op = op;
-                e.device = dev.id;
-                e.reserved = 0;
-                e.start_ms = ms_since(r.t0);
-                e.end_ms = -1.0;
-            }
+            ev = take(r, i, dev, slot, op);
         }
         Slot &sl = r.slots[slot];
-        const uint8_t in = kOps[op].in_mask, out = kOps[op].out_mask;
-        if (stage(r, sl, in, dev.gpu, dev.stream)) return;
+        if (stage(r, sl, kOps[op].in_mask, false, dev.stream)) return;
         const auto t0 = Clock::now();
-        if (dev.gpu ? gpu_compute(r, sl, op, dev.stream) : cpu_compute(r, sl, op, dev.scratch)) return;
+        if (cpu_compute(r, sl, op, dev.scratch)) return;
         const double ms = ms_since(t0);
-        {
-            // an in-place write leaves the only valid copy where it was made
-            std::lock_guard<std::mutex> xg(sl.xfer_mu);
-            for (int p = 0; p < NPLANES; ++p)
-                if (out & (1u << p)) sl.where[p].store(dev.gpu ? ON_DEV : ON_HOST);
+        outputs_written(sl, op, dev);
+        finish_instance(r, dev, slot, op, ev, ms);
+    }
+}
+
+// The GPU manager.  Instances are enqueued on the manager's stream, at most
+// cfg.gpu_inflight at once, each followed by a write of its launch's outcome
+// into pinned memory and an event; the oldest is retired once its event has
+// completed.  Inputs are staged on a separate transfer stream (waited for
+// before the instance is enqueued), so a transfer never waits behind the
+// instances already enqueued.  Its time per instance runs from the later of
+// its enqueue and the previous instance's completion to its own completion.
+void gpu_manager(Run &r, Device dev) {
+    if (hipSetDevice(r.device) != hipSuccess) {
+        set_err(r, RECON_EDEVICE, "hipSetDevice failed in a pipeline thread");
+        return;
+    }
+    const int depth = std::max(1, (int)r.cfg.gpu_inflight);
+    const bool basic = !r.cfg.data_locality;
+    struct Issued {
+        int slot, op, k;
+        int64_t ev;
+        Clock::time_point t_enq;
+    };
+    std::vector<hipEvent_t> done(depth, nullptr);
+    uint32_t *outcome = nullptr;   // pinned, one word per in-flight position
+    bool ok = hipHostMalloc((void **)&outcome, (size_t)depth * sizeof(uint32_t), hipHostMallocDefault) == hipSuccess;
+    for (int k = 0; ok && k < depth; ++k)
+        ok = hipEventCreateWithFlags(&done[k], hipEventDisableTiming) == hipSuccess;
+    std::deque<Issued> q;
+    std::vector<int> free_k;
+    for (int k = depth - 1; k >= 0; --k) free_k.push_back(k);
+    Clock::time_point last_done = Clock::now();
+    if (!ok) set_err(r, RECON_EDEVICE, "GPU manager: event or pinned allocation failed");
+
+    // retire the oldest instance (its event has completed); false on an error
+    auto retire = [&]() -> bool {
+        const Issued x = q.front();
+        q.pop_front();
+        free_k.push_back(x.k);
+        const auto now = Clock::now();
+        const double ms =
+            std::chrono::duration<double, std::milli>(now - std::max(x.t_enq, last_done)).count();
+        last_done = now;
+        if (((volatile uint32_t *)outcome)[x.k] != 0) {
+            set_err(r, RECON_EDEVICE, "GPU operation %d: the scheduler watchdog gave the launch up", x.op);
+            return false;
         }
-        // the basic mode brings every GPU assignment's outputs back to the host
-        // (and its inputs in again next time): no data stays on the device
-        if (basic && stage(r, sl, out, false, dev.stream, true)) return;
+        Slot &sl = r.slots[x.slot];
+        outputs_written(sl, x.op, dev);
         if (basic) {
+            // the basic mode brings every GPU assignment's outputs back to the
+            // host (and its inputs in again next time): no data stays on the device
+            const uint8_t in = kOps[x.op].in_mask;
+            if (stage(r, sl, kOps[x.op].out_mask, false, dev.xfer, true)) return false;
             std::lock_guard<std::mutex> xg(sl.xfer_mu);
             for (int p = 0; p < NPLANES; ++p)
                 if (in & (1u << p)) sl.where[p].store(sl.where[p].load() & (uint8_t)~ON_DEV);
         }
-        bool last;
-        {
-            std::lock_guard<std::mutex> g(r.mu);
-            if (ev >= 0) r.cfg.trace[ev].end_ms = ms_since(r.t0);
-            if (dev.gpu) {
-                r.st.ops_gpu[op]++;
-                r.st.busy_gpu_ms[op] += ms;
-            } else {
-                r.st.ops_cpu[op]++;
-                r.st.busy_cpu_ms[op] += ms;
+        finish_instance(r, dev, x.slot, x.op, x.ev, ms);
+        return true;
+    };
+
+    while (ok) {
+        if (!q.empty()) {
+            const hipError_t e = hipEventQuery(done[q.front().k]);
+            if (e == hipSuccess) {
+                if (!retire()) break;
+                continue;
             }
-            last = complete(r, slot, op);
-            r.cv.notify_all();
+            if (e != hipErrorNotReady) {
+                set_err(r, RECON_EDEVICE, "GPU manager stream failed: %s", hipGetErrorString(e));
+                break;
+            }
         }
-        if (last) {
-            std::lock_guard<std::mutex> g(r.mu);
-            r.finished.push_back(slot);
-            r.cv.notify_all();
+        // take another instance while there is room (blocking only when none is in flight)
+        int slot = -1, op = -1;
+        int64_t ev = -1;
+        const uint64_t gen = r.ready_gen.load();
+        if ((int)q.size() < depth) {
+            std::unique_lock<std::mutex> lk(r.mu);
+            int i = -1;
+            if (q.empty())
+                r.cv.wait(lk, [&] { return r.err || r.done_tiles == r.n || (i = pick(r, true)) >= 0; });
+            else if (!r.err)
+                i = pick(r, true);
+            if (r.err || (q.empty() && r.done_tiles == r.n)) break;
+            if (i >= 0) ev = take(r, i, dev, slot, op);
+        }
+        if (slot >= 0) {
+            Slot &sl = r.slots[slot];
+            const int k = free_k.back();
+            free_k.pop_back();
+            if (stage(r, sl, kOps[op].in_mask, true, dev.xfer)) break;
+            const auto t_enq = Clock::now();
+            if (gpu_enqueue(r, sl, op, dev.stream)) break;
+            // the reconstructions (h-dome, fill-holes, the markers' regional
+            // maxima) report a launch their scheduler gave up through its outcome
+            if (op == RECON_PIPE_HDOME || op == RECON_PIPE_FILL || op == RECON_PIPE_MARKERS) {
+                if (recon_enqueue_status(r.ctx, outcome + k, dev.stream) != RECON_OK) {
+                    set_err(r, RECON_EDEVICE, "GPU operation %d: %s", op, recon_last_error());
+                    break;
+                }
+            } else {
+                outcome[k] = 0;
+            }
+            if (hipEventRecord(done[k], dev.stream) != hipSuccess) {
+                set_err(r, RECON_EDEVICE, "GPU manager: event record failed");
+                break;
+            }
+            q.push_back({slot, op, k, ev, t_enq});
+            continue;
+        }
+        // wait for the oldest instance, or (with room) for newly ready ones:
+        // polled without sleeping for 2 ms, then with short sleeps, 60 s at most
+        const auto t_wait = Clock::now();
+        while (true) {
+            const hipError_t e = hipEventQuery(done[q.front().k]);
+            if (e != hipErrorNotReady) break;
+            if ((int)q.size() < depth && r.ready_gen.load() != gen) break;
+            const double w = ms_since(t_wait);
+            if (w > 60000.0) {
+                set_err(r, RECON_ETIMEDOUT, "GPU manager: an instance did not finish within 60 s");
+                ok = false;
+                break;
+            }
+            if (w > 2.0) std::this_thread::sleep_for(std::chrono::microseconds(20));
         }
     }
+    // leave nothing in flight behind: the slots' planes are freed after the run
+    for (const Issued &x : q) (void)hipEventSynchronize(done[x.k]);
+    for (hipEvent_t e : done)
+        if (e) (void)hipEventDestroy(e);
+    if (outcome) (void)hipHostFree(outcome);
 }
 
 int check_config(const recon_pipe_config *c, recon_ctx *ctx) {
@@ -548,6 +686,7 @@ int check_config(const recon_pipe_config *c, recon_ctx *ctx) {
     if (c->io_threads < 0 || c->io_threads > 64) return 1;
     if (c->trace_cap < 0 || (c->trace_cap > 0 && !c->trace)) return 1;
     if (c->prefetch < 0 || c->prefetch > 1) return 1;
+    if (c->gpu_inflight < 0 || c->gpu_inflight > 4 || c->reserved_pipe != 0) return 1;
     if (c->use_gpu && !ctx) return 1;
     if (!c->use_gpu && c->cpu_workers == 0) return 1;
     if (c->conn != 4 && c->conn != 8) return 1;
@@ -621,7 +760,9 @@ extern "C" int recon_pipeline_run(recon_ctx *ctx, const recon_pipe_tile *tiles, 
     if (rc == RECON_OK && cfg->use_gpu) {
         Device g;
         g.gpu = true;
-        if (hipStreamCreateWithFlags(&g.stream, hipStreamNonBlocking) != hipSuccess) rc = RECON_EDEVICE;
+        if (hipStreamCreateWithFlags(&g.stream, hipStreamNonBlocking) != hipSuccess ||
+            hipStreamCreateWithFlags(&g.xfer, hipStreamNonBlocking) != hipSuccess)
+            rc = RECON_EDEVICE;
         devs.push_back(g);
     }
     for (int k = 0; rc == RECON_OK && k < cfg->cpu_workers; ++k) {
@@ -645,7 +786,7 @@ extern "C" int recon_pipeline_run(recon_ctx *ctx, const recon_pipe_tile *tiles, 
         // the first tiles are admitted here, before the devices and the I/O threads start
         if (admit_first(r, io_streams) != RECON_OK) r.cv.notify_all();
         std::vector<std::thread> th;
-        for (auto &d : devs) th.emplace_back(worker, std::ref(r), d);
+        for (auto &d : devs) th.emplace_back(d.gpu ? gpu_manager : worker, std::ref(r), d);
         for (int k = 0; k < n_io; ++k) th.emplace_back(io_thread, std::ref(r), io_streams[k]);
         for (auto &t : th) t.join();
         r.st.makespan_ms = ms_since(t0);
@@ -655,6 +796,7 @@ extern "C" int recon_pipeline_run(recon_ctx *ctx, const recon_pipe_tile *tiles, 
         if (st) (void)hipStreamDestroy(st);
     for (auto &d : devs) {
         if (d.stream) (void)hipStreamDestroy(d.stream);
+        if (d.xfer) (void)hipStreamDestroy(d.xfer);
         if (d.scratch) hostops::scratch_free(d.scratch);
     }
     for (int k = 0; k < r.nslots; ++k) {

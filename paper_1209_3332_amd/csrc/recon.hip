@@ -1543,6 +1543,26 @@ int recon_last_stats(recon_ctx *ctx, recon_stats *out) {
     return RECON_OK;
 }
 
+int recon_enqueue_status(recon_ctx *ctx, uint32_t *host_flag, void *stream) {
+    if (!ctx || !host_flag) return fail(RECON_EINVAL, "null argument");
+    int rc = ensure_device(ctx);
+    if (rc) return rc;
+    // the Work records of the last launch (one per block-height group)
+    const rk::Work *w[3] = {nullptr, nullptr, nullptr};
+    int n = 0;
+    if (ctx->have_last) {
+        if (ctx->last_shapes) {
+            for (int v = 0; v < kVariants && n < 3; ++v)
+                if ((ctx->last_shapes & (1u << v)) && ctx->shape_ctx[v]) w[n++] = ctx->shape_ctx[v]->last_work;
+        } else {
+            w[n++] = ctx->last_work;
+        }
+    }
+    hipLaunchKernelGGL(rk::launch_outcome, dim3(1), dim3(64), 0, (hipStream_t)stream, w[0], w[1], w[2], host_flag);
+    HIP_TRY(hipGetLastError());
+    return RECON_OK;
+}
+
 int recon_launch_times(recon_ctx *ctx, int back, float *dense_ms, float *seed_ms, float *drain_ms,
                        float *total_ms, float *route_ms) {
     if (!ctx || !dense_ms || !seed_ms || !drain_ms || !total_ms || !route_ms)

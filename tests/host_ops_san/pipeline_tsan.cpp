@@ -18,7 +18,7 @@ int recon_fill_holes(recon_ctx *, recon_image *, int, void *) { abort(); }
 int recon_area_threshold(recon_ctx *, recon_image *, int, int64_t, int64_t, void *) { abort(); }
 int recon_pre_watershed(recon_ctx *, recon_image *, int, void *) { abort(); }
 int recon_label(recon_ctx *, const recon_image *, int32_t *, int64_t, int, int32_t *, void *) { abort(); }
-int recon_last_stats(recon_ctx *, recon_stats *) { abort(); }
+int recon_enqueue_status(recon_ctx *, uint32_t *, void *) { abort(); }
 const char *recon_last_error(void) { return ""; }
 }
 

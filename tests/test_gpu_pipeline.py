@@ -206,3 +206,58 @@ def test_many_workers_and_io_threads(lib, rc, oracle_mod):
         check(outs, want)
         seen = sorted((t, op) for t, op, _, _, _ in st["trace"])
         assert seen == sorted((t, op) for t in range(16) for op in lib.PIPE_OPS)
+
+
+@pytest.mark.parametrize("depth", [2, 3])
+@pytest.mark.parametrize("cpu_workers,policy,dl,prefetch", [(0, "pats", True, True), (0, "fcfs", False, False),
+                                                            (3, "pats", True, False), (3, "fcfs", False, True)])
+def test_gpu_inflight(lib, rc, tiles, expected, depth, cpu_workers, policy, dl, prefetch):
+    """The GPU manager with 2 or 3 instances enqueued on its stream at once,
+    alone or beside CPU workers, with and without data locality: every tile
+    equals the oracle's chain and every instance runs once."""
+    gpu_ms = {"hdome": 0.2, "fill_holes": 0.2, "area_threshold": 0.1, "markers": 0.1, "label": 0.05}
+    cfg = lib.pipe_config(policy=policy, cpu_workers=cpu_workers, use_gpu=True, window=4, data_locality=dl,
+                          conn=8, h=H, area_min=LO, area_max=HI, speedup=SPEEDUP, gpu_ms=gpu_ms,
+                          cpu_guard=cpu_workers > 0, prefetch=prefetch, gpu_inflight=depth)
+    outs, st = lib.recon_pipeline_run(rc.ctx, tiles, cfg, trace=True)
+    check(outs, expected[8])
+    assert [a + b for a, b in zip(st["ops_cpu"], st["ops_gpu"])] == [len(tiles)] * 5
+    seen = sorted((t, op) for t, op, _, _, _ in st["trace"])
+    assert seen == sorted((t, op) for t in range(len(tiles)) for op in lib.PIPE_OPS)
+    if cpu_workers == 0 and dl:
+        assert st["uploads"] == len(tiles) and st["downloads"] == 3 * len(tiles)
+
+
+def test_gpu_inflight_full_size_tiles(lib, rc, oracle_mod):
+    """Five 4096 x 4096 nuclei-like tiles with two instances in flight on the
+    GPU and prefetching, against the oracle's chain."""
+    tiles = [synth.config2_tile(seed=synth.seed_for(6, 960 + i))[1] for i in range(5)]
+    cfg = lib.pipe_config(policy="pats", cpu_workers=0, use_gpu=True, window=3, conn=8, h=H, area_min=LO,
+                          area_max=HI, speedup=SPEEDUP, prefetch=True, io_threads=4, gpu_inflight=2)
+    outs, st = lib.recon_pipeline_run(rc.ctx, tiles, cfg)
+    for img, o in zip(tiles, outs):
+        a = oracle_mod.area_threshold(oracle_mod.fill_holes(oracle_mod.hdome(img, H, 8), 8), LO, HI, 8)
+        lab, n = oracle_mod.label(a, 8)
+        assert np.array_equal(o["objects"], a) and np.array_equal(o["markers"], oracle_mod.pre_watershed(a, 8))
+        assert np.array_equal(o["labels"], lab) and o["count"] == n
+    assert st["ops_gpu"] == [5] * 5
+
+
+def test_enqueue_status(lib, torch_mod):
+    """recon_enqueue_status writes 0 after a launch that converged (and before
+    any launch), 1 after one its scheduler gave up (the context's test hook
+    makes every block claim fail), into pinned host memory, without a wait."""
+    mask = synth.gaussian_tile(100, 300, 5, seed=3)
+    flag = torch_mod.full((4,), 7, dtype=torch_mod.int32).pin_memory()
+    stream = torch_mod.cuda.current_stream()
+    for fault, want in ((0, 0), (1, 1)):
+        with lib.Recon(0, test_fault=fault) as ctx:
+            lib.recon_enqueue_status(ctx.ctx, flag.data_ptr() + 4, stream)   # no launch yet
+            m = torch_mod.from_numpy(synth.hdome_marker(mask, 30)).cuda()
+            ctx.dilate(m, torch_mod.from_numpy(mask).cuda(), 8, stream)
+            lib.recon_enqueue_status(ctx.ctx, flag.data_ptr(), stream)
+            torch_mod.cuda.synchronize()
+            assert int(flag[0]) == want and int(flag[1]) == 0, (fault, flag.tolist())
+            if fault:
+                with pytest.raises(lib.ReconError):
+                    ctx.last_stats()

@@ -184,3 +184,14 @@ def test_pipeline_writes_into_reused_output_buffers(lib, oracle_mod):
     bad[1]["labels"] = np.empty(tiles[1].shape, np.int64)
     with pytest.raises(ValueError):
         lib.recon_pipeline_run(None, tiles, cfg, outputs=bad)
+
+
+def test_pipeline_inflight_argument(lib):
+    img = [np.zeros((8, 8), np.uint8)]
+    for depth in (-1, 5):
+        with pytest.raises(lib.ReconError) as e:
+            lib.recon_pipeline_run(None, img, lib.pipe_config(use_gpu=False, cpu_workers=1, gpu_inflight=depth))
+        assert e.value.code == lib.RECON_EINVAL, depth
+    # without a GPU the depth changes nothing
+    outs, st = lib.recon_pipeline_run(None, img, lib.pipe_config(use_gpu=False, cpu_workers=1, gpu_inflight=3))
+    assert st["ops_cpu"] == [1] * 5
