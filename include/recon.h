@@ -71,6 +71,12 @@
  *   ordered on the streams they name; calls on different streams that
  *   overlap in time share the context's workspace and must not be issued
  *   concurrently.
+ * * Several contexts on one GPU may run launches at the same time (the
+ *   serving lanes run up to three).  With four to eight contexts running
+ *   4096 x 4096 reconstructions, labellings and distance transforms side by
+ *   side, a few runs had a launch given up by its scheduler watchdog or
+ *   results that differed, for a cause not found; a caller doing so should
+ *   check every launch's outcome (recon_last_stats, recon_enqueue_status).
  */
 #ifndef RECON_H
 #define RECON_H
