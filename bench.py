@@ -774,7 +774,8 @@ def pipeline(recon, torch, n_tiles, size, window, cpu_workers, workers, windows=
     memory: the GPU alone, then the GPU beside cpu_workers CPU workers under
     FCFS and PATS, without and with data locality, and PATS with the CPU workers
     kept off the operations a core would take too long on, and the GPU manager
-    keeping two instances enqueued at once, alone and beside the CPU workers.
+    keeping two instances enqueued at once and running up to 8 ready h-dome or
+    fill-holes instances in one launch, alone and beside the CPU workers.
     Speedup estimates
     come from a calibration on one tile (each operation's CPU variant against
     its GPU variant, computation only); every run's outputs are compared byte
@@ -847,7 +848,13 @@ def pipeline(recon, torch, n_tiles, size, window, cpu_workers, workers, windows=
                                                      prefetch=True, gpu_inflight=2)),
                 ("pats_dl_guard_prefetch_inflight2", dict(policy="pats", cpu_workers=cpu_workers,
                                                           data_locality=True, cpu_guard=True, prefetch=True,
-                                                          gpu_inflight=2))]
+                                                          gpu_inflight=2)),
+                # and running up to 8 ready h-dome or fill-holes instances in one launch
+                ("gpu_only_prefetch_inflight2_batch8", dict(policy="pats", cpu_workers=0, data_locality=True,
+                                                            prefetch=True, gpu_inflight=2, gpu_batch=8)),
+                ("pats_dl_guard_prefetch_inflight2_batch8", dict(policy="pats", cpu_workers=cpu_workers,
+                                                                 data_locality=True, cpu_guard=True,
+                                                                 prefetch=True, gpu_inflight=2, gpu_batch=8))]
         ref = None
         res["runs"] = {}
         for name, kw in runs:
@@ -870,7 +877,7 @@ def pipeline(recon, torch, n_tiles, size, window, cpu_workers, workers, windows=
                  "transfer_GB": (st["upload_bytes"] + st["download_bytes"]) / 1e9,
                  "transfer_ms": st["transfer_ms"], "io_ms": st["io_ms"], "policy": kw["policy"],
                  "data_locality": kw["data_locality"], "prefetch": bool(kw.get("prefetch")),
-                 "gpu_inflight": max(1, kw.get("gpu_inflight", 1))}
+                 "gpu_inflight": max(1, kw.get("gpu_inflight", 1)), "gpu_batch": max(1, kw.get("gpu_batch", 1))}
             if ref is None:
                 ref = [{k: (v.copy() if hasattr(v, "copy") else v) for k, v in o.items()} for o in outs]
                 for i in (0, n_tiles - 1):

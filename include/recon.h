@@ -453,7 +453,11 @@ typedef struct {
                                instance is chosen and enqueued while the previous one runs, which
                                hides the host's round trip between them; the choice is then made
                                among the instances ready at that earlier moment */
-    int32_t reserved_pipe;  /* 0 */
+    int32_t gpu_batch;      /* most ready instances of one reconstruction operation (h-dome or
+                               fill-holes) the GPU manager runs in one recon_batch launch, 1..8
+                               (0: 1).  With more, the instance the policy picks takes the other
+                               ready instances of its operation along (oldest first): one tile's
+                               reconstruction leaves most of the GPU idle, a batch fills it */
 } recon_pipe_config;
 
 /* One operation instance of a recon_pipeline_run, as it ran. */

@@ -118,7 +118,7 @@ class recon_pipe_config(ctypes.Structure):
                 ("cpu_guard", ctypes.c_int32), ("gpu_ms", ctypes.c_float * 5), ("prefetch", ctypes.c_int32),
                 ("trace_cap", ctypes.c_int32),
                 ("trace", ctypes.POINTER(recon_pipe_event)), ("gpu_inflight", ctypes.c_int32),
-                ("reserved_pipe", ctypes.c_int32)]
+                ("gpu_batch", ctypes.c_int32)]
 
 
 class recon_pipe_stats(ctypes.Structure):
@@ -375,7 +375,7 @@ def pipe_config(policy: str = "pats", cpu_workers: int = 0, use_gpu: bool = True
                 data_locality: bool = True, conn: int = 8, h: int = 20, area_min: int = 20, area_max: int = 1000,
                 speedup=None, transfer_impact=None, cpu_max_speedup: float = 0.0,
                 io_threads: int = 2, gpu_ms=None, cpu_guard: bool = False,
-                prefetch: bool = False, gpu_inflight: int = 1) -> recon_pipe_config:
+                prefetch: bool = False, gpu_inflight: int = 1, gpu_batch: int = 1) -> recon_pipe_config:
     """recon_pipe_config; speedup / transfer_impact: dicts or sequences over PIPE_OPS."""
     c = recon_pipe_config()
     if policy not in POLICIES:
@@ -389,6 +389,7 @@ def pipe_config(policy: str = "pats", cpu_workers: int = 0, use_gpu: bool = True
     c.cpu_guard = int(bool(cpu_guard))
     c.prefetch = int(bool(prefetch))
     c.gpu_inflight = int(gpu_inflight)
+    c.gpu_batch = int(gpu_batch)
 
     def seq(v, default):
         if v is None:

@@ -251,6 +251,22 @@ int gpu_enqueue(Run &r, Slot &sl, int op, hipStream_t s) {
     return RECON_OK;
 }
 
+// Enqueue one launch of op (h-dome or fill-holes) over the slots' A planes.
+int gpu_enqueue_batch(Run &r, const std::vector<int> &slots, int op, hipStream_t s) {
+    std::vector<recon_task> tasks(slots.size());
+    for (size_t k = 0; k < slots.size(); ++k) {
+        recon_task &t = tasks[k];
+        t = recon_task{};
+        t.op = op == RECON_PIPE_HDOME ? RECON_OP_HDOME : RECON_OP_FILL_HOLES;
+        t.conn = r.cfg.conn;
+        t.image = dev_image(r, r.slots[slots[k]], PA);
+        t.h = op == RECON_PIPE_HDOME ? r.cfg.h : 0;
+    }
+    const int rc = recon_batch(r.ctx, tasks.data(), (int32_t)tasks.size(), s);
+    if (rc) return set_err(r, rc, "GPU batch of operation %d failed: %s", op, recon_last_error());
+    return RECON_OK;
+}
+
 int cpu_compute(Run &r, Slot &sl, int op, hostops::Scratch *scr) {
     const recon_pipe_config &c = r.cfg;
     const recon_pipe_tile &t = r.tiles[sl.tile];
@@ -563,9 +579,14 @@ void gpu_manager(Run &r, Device dev) {
     }
     const int depth = std::max(1, (int)r.cfg.gpu_inflight);
     const bool basic = !r.cfg.data_locality;
-    struct Issued {
-        int slot, op, k;
+    const int batch = std::max(1, (int)r.cfg.gpu_batch);
+    struct Inst {
+        int slot;
         int64_t ev;
+    };
+    struct Issued {   // one launch: instances of one operation
+        std::vector<Inst> insts;
+        int op, k;
         Clock::time_point t_enq;
     };
     std::vector<hipEvent_t> done(depth, nullptr);
@@ -592,18 +613,21 @@ void gpu_manager(Run &r, Device dev) {
             set_err(r, RECON_EDEVICE, "GPU operation %d: the scheduler watchdog gave the launch up", x.op);
             return false;
         }
-        Slot &sl = r.slots[x.slot];
-        outputs_written(sl, x.op, dev);
-        if (basic) {
-            // the basic mode brings every GPU assignment's outputs back to the
-            // host (and its inputs in again next time): no data stays on the device
-            const uint8_t in = kOps[x.op].in_mask;
-            if (stage(r, sl, kOps[x.op].out_mask, false, dev.xfer, true)) return false;
-            std::lock_guard<std::mutex> xg(sl.xfer_mu);
-            for (int p = 0; p < NPLANES; ++p)
-                if (in & (1u << p)) sl.where[p].store(sl.where[p].load() & (uint8_t)~ON_DEV);
+        for (const Inst &in_x : x.insts) {
+            Slot &sl = r.slots[in_x.slot];
+            outputs_written(sl, x.op, dev);
+            if (basic) {
+                // the basic mode brings every GPU assignment's outputs back to the
+                // host (and its inputs in again next time): no data stays on the device
+                const uint8_t in = kOps[x.op].in_mask;
+                if (stage(r, sl, kOps[x.op].out_mask, false, dev.xfer, true)) return false;
+                std::lock_guard<std::mutex> xg(sl.xfer_mu);
+                for (int p = 0; p < NPLANES; ++p)
+                    if (in & (1u << p)) sl.where[p].store(sl.where[p].load() & (uint8_t)~ON_DEV);
+            }
+            // a launch's time is shared by its instances
+            finish_instance(r, dev, in_x.slot, x.op, in_x.ev, ms / (double)x.insts.size());
         }
-        finish_instance(r, dev, x.slot, x.op, x.ev, ms);
         return true;
     };
 
@@ -619,9 +643,11 @@ void gpu_manager(Run &r, Device dev) {
                 break;
             }
         }
-        // take another instance while there is room (blocking only when none is in flight)
+        // take another instance while there is room (blocking only when none is
+        // in flight); a reconstruction takes the other ready instances of its
+        // operation along, up to the batch size, oldest first
         int slot = -1, op = -1;
-        int64_t ev = -1;
+        std::vector<Inst> group;
         const uint64_t gen = r.ready_gen.load();
         if ((int)q.size() < depth) {
             std::unique_lock<std::mutex> lk(r.mu);
@@ -631,15 +657,44 @@ void gpu_manager(Run &r, Device dev) {
             else if (!r.err)
                 i = pick(r, true);
             if (r.err || (q.empty() && r.done_tiles == r.n)) break;
-            if (i >= 0) ev = take(r, i, dev, slot, op);
+            if (i >= 0) {
+                int64_t ev = take(r, i, dev, slot, op);
+                group.push_back({slot, ev});
+                if (batch > 1 && (op == RECON_PIPE_HDOME || op == RECON_PIPE_FILL)) {
+                    std::vector<int> more;   // indices into r.ready, oldest first
+                    for (int j = 0; j < (int)r.ready.size(); ++j)
+                        if (r.ready[j].op == op) more.push_back(j);
+                    std::sort(more.begin(), more.end(),
+                              [&](int a, int b) { return r.ready[a].seq < r.ready[b].seq; });
+                    if ((int)more.size() > batch - 1) more.resize(batch - 1);
+                    // take from the back so that the remaining indices stay valid
+                    std::sort(more.begin(), more.end(), [](int a, int b) { return a > b; });
+                    for (int j : more) {
+                        int s2, o2;
+                        const int64_t e2 = take(r, j, dev, s2, o2);
+                        group.push_back({s2, e2});
+                    }
+                }
+            }
         }
         if (slot >= 0) {
-            Slot &sl = r.slots[slot];
             const int k = free_k.back();
             free_k.pop_back();
-            if (stage(r, sl, kOps[op].in_mask, true, dev.xfer)) break;
+            bool staged = true;
+            for (const Inst &g : group)
+                if (stage(r, r.slots[g.slot], kOps[op].in_mask, true, dev.xfer)) {
+                    staged = false;
+                    break;
+                }
+            if (!staged) break;
             const auto t_enq = Clock::now();
-            if (gpu_enqueue(r, sl, op, dev.stream)) break;
+            if (group.size() == 1) {
+                if (gpu_enqueue(r, r.slots[slot], op, dev.stream)) break;
+            } else {
+                std::vector<int> slots;
+                for (const Inst &g : group) slots.push_back(g.slot);
+                if (gpu_enqueue_batch(r, slots, op, dev.stream)) break;
+            }
             // the reconstructions (h-dome, fill-holes, the markers' regional
             // maxima) report a launch their scheduler gave up through its outcome
             if (op == RECON_PIPE_HDOME || op == RECON_PIPE_FILL || op == RECON_PIPE_MARKERS) {
@@ -654,7 +709,7 @@ void gpu_manager(Run &r, Device dev) {
                 set_err(r, RECON_EDEVICE, "GPU manager: event record failed");
                 break;
             }
-            q.push_back({slot, op, k, ev, t_enq});
+            q.push_back({std::move(group), op, k, t_enq});
             continue;
         }
         // wait for the oldest instance, or (with room) for newly ready ones:
@@ -686,7 +741,7 @@ int check_config(const recon_pipe_config *c, recon_ctx *ctx) {
     if (c->io_threads < 0 || c->io_threads > 64) return 1;
     if (c->trace_cap < 0 || (c->trace_cap > 0 && !c->trace)) return 1;
     if (c->prefetch < 0 || c->prefetch > 1) return 1;
-    if (c->gpu_inflight < 0 || c->gpu_inflight > 4 || c->reserved_pipe != 0) return 1;
+    if (c->gpu_inflight < 0 || c->gpu_inflight > 4 || c->gpu_batch < 0 || c->gpu_batch > 8) return 1;
     if (c->use_gpu && !ctx) return 1;
     if (!c->use_gpu && c->cpu_workers == 0) return 1;
     if (c->conn != 4 && c->conn != 8) return 1;

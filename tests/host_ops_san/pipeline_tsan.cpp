@@ -19,6 +19,7 @@ int recon_area_threshold(recon_ctx *, recon_image *, int, int64_t, int64_t, void
 int recon_pre_watershed(recon_ctx *, recon_image *, int, void *) { abort(); }
 int recon_label(recon_ctx *, const recon_image *, int32_t *, int64_t, int, int32_t *, void *) { abort(); }
 int recon_enqueue_status(recon_ctx *, uint32_t *, void *) { abort(); }
+int recon_batch(recon_ctx *, const recon_task *, int32_t, void *) { abort(); }
 const char *recon_last_error(void) { return ""; }
 }
 

@@ -261,3 +261,42 @@ def test_enqueue_status(lib, torch_mod):
             if fault:
                 with pytest.raises(lib.ReconError):
                     ctx.last_stats()
+
+
+@pytest.mark.parametrize("batch,depth", [(4, 1), (8, 2)])
+@pytest.mark.parametrize("cpu_workers,policy,dl,prefetch", [(0, "pats", True, True), (0, "fcfs", False, False),
+                                                            (3, "pats", True, True), (3, "fcfs", True, False)])
+def test_gpu_batches(lib, rc, tiles, expected, batch, depth, cpu_workers, policy, dl, prefetch):
+    """The GPU manager running up to 4 or 8 ready h-dome or fill-holes instances
+    in one recon_batch launch (tiles of different shapes together), alone or
+    beside CPU workers: every tile equals the oracle's chain and every
+    instance runs once."""
+    gpu_ms = {"hdome": 0.2, "fill_holes": 0.2, "area_threshold": 0.1, "markers": 0.1, "label": 0.05}
+    cfg = lib.pipe_config(policy=policy, cpu_workers=cpu_workers, use_gpu=True, window=6, data_locality=dl,
+                          conn=8, h=H, area_min=LO, area_max=HI, speedup=SPEEDUP, gpu_ms=gpu_ms,
+                          cpu_guard=cpu_workers > 0, prefetch=prefetch, gpu_inflight=depth, gpu_batch=batch)
+    outs, st = lib.recon_pipeline_run(rc.ctx, tiles, cfg, trace=True)
+    check(outs, expected[8])
+    assert [a + b for a, b in zip(st["ops_cpu"], st["ops_gpu"])] == [len(tiles)] * 5
+    seen = sorted((t, op) for t, op, _, _, _ in st["trace"])
+    assert seen == sorted((t, op) for t in range(len(tiles)) for op in lib.PIPE_OPS)
+    if cpu_workers == 0:
+        # with the GPU alone the first h-domes of the window go in one launch
+        first = [e for e in st["trace"] if e[1] == "hdome"][:2]
+        assert len(first) == 2 and first[0][3] == first[1][3]
+
+
+def test_gpu_batches_full_size_and_conn4(lib, rc, oracle_mod):
+    """Six 4096 x 4096 nuclei-like tiles, 4-connectivity and another dome
+    height, in batches of up to 8 with two launches in flight, against the
+    oracle's chain."""
+    tiles = [synth.config2_tile(seed=synth.seed_for(6, 980 + i))[1] for i in range(6)]
+    cfg = lib.pipe_config(policy="pats", cpu_workers=0, use_gpu=True, window=6, conn=4, h=35, area_min=LO,
+                          area_max=HI, speedup=SPEEDUP, prefetch=True, io_threads=4, gpu_inflight=2, gpu_batch=8)
+    outs, st = lib.recon_pipeline_run(rc.ctx, tiles, cfg)
+    for img, o in zip(tiles, outs):
+        a = oracle_mod.area_threshold(oracle_mod.fill_holes(oracle_mod.hdome(img, 35, 4), 4), LO, HI, 4)
+        lab, n = oracle_mod.label(a, 4)
+        assert np.array_equal(o["objects"], a) and np.array_equal(o["markers"], oracle_mod.pre_watershed(a, 4))
+        assert np.array_equal(o["labels"], lab) and o["count"] == n
+    assert st["ops_gpu"] == [6] * 5

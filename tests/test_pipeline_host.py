@@ -188,10 +188,11 @@ def test_pipeline_writes_into_reused_output_buffers(lib, oracle_mod):
 
 def test_pipeline_inflight_argument(lib):
     img = [np.zeros((8, 8), np.uint8)]
-    for depth in (-1, 5):
+    for kw in (dict(gpu_inflight=-1), dict(gpu_inflight=5), dict(gpu_batch=-1), dict(gpu_batch=9)):
         with pytest.raises(lib.ReconError) as e:
-            lib.recon_pipeline_run(None, img, lib.pipe_config(use_gpu=False, cpu_workers=1, gpu_inflight=depth))
-        assert e.value.code == lib.RECON_EINVAL, depth
-    # without a GPU the depth changes nothing
-    outs, st = lib.recon_pipeline_run(None, img, lib.pipe_config(use_gpu=False, cpu_workers=1, gpu_inflight=3))
+            lib.recon_pipeline_run(None, img, lib.pipe_config(use_gpu=False, cpu_workers=1, **kw))
+        assert e.value.code == lib.RECON_EINVAL, kw
+    # without a GPU the depth and the batch size change nothing
+    outs, st = lib.recon_pipeline_run(None, img, lib.pipe_config(use_gpu=False, cpu_workers=1, gpu_inflight=3,
+                                                                 gpu_batch=8))
     assert st["ops_cpu"] == [1] * 5
