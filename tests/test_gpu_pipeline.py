@@ -281,9 +281,10 @@ def test_gpu_batches(lib, rc, tiles, expected, batch, depth, cpu_workers, policy
     seen = sorted((t, op) for t, op, _, _, _ in st["trace"])
     assert seen == sorted((t, op) for t in range(len(tiles)) for op in lib.PIPE_OPS)
     if cpu_workers == 0:
-        # with the GPU alone the first h-domes of the window go in one launch
+        # with the GPU alone the first h-domes of the window go in one launch:
+        # the second is taken before the first is done
         first = [e for e in st["trace"] if e[1] == "hdome"][:2]
-        assert len(first) == 2 and first[0][3] == first[1][3]
+        assert len(first) == 2 and first[1][3] < first[0][4], first
 
 
 def test_gpu_batches_full_size_and_conn4(lib, rc, oracle_mod):
