@@ -307,12 +307,23 @@ std::vector<int> reserve(Run &r) {
     return got;
 }
 
+// Copy `rows` rows of `row_bytes` between pitched planes: one copy when both
+// are contiguous (a large copy streams past the caches; row by row it would
+// read every destination line first).
+void copy_rows(void *dst, int64_t dst_pitch, const void *src, int64_t src_pitch, size_t row_bytes, int rows) {
+    if (dst_pitch == (int64_t)row_bytes && src_pitch == (int64_t)row_bytes) {
+        std::memcpy(dst, src, row_bytes * (size_t)rows);
+        return;
+    }
+    for (int y = 0; y < rows; ++y)
+        std::memcpy((uint8_t *)dst + (int64_t)y * dst_pitch, (const uint8_t *)src + (int64_t)y * src_pitch, row_bytes);
+}
+
 // Copy the tile's image into the slot's pinned plane and reset its counters.
 void load(Run &r, int k) {
     Slot &sl = r.slots[k];
     const recon_pipe_tile &t = r.tiles[sl.tile];
-    for (int y = 0; y < t.height; ++y)
-        std::memcpy(sl.h[PA] + (int64_t)y * r.pitch, t.image + (int64_t)y * t.pitch, t.width);
+    copy_rows(sl.h[PA], r.pitch, t.image, t.pitch, (size_t)t.width, t.height);
     sl.where[PA].store(ON_HOST);
     sl.where[PB].store(0);
     sl.where[PL].store(0);
@@ -448,13 +459,9 @@ int finish_tile(Run &r, int slot, hipStream_t s) {
     int rc = stage(r, sl, (1u << PA) | (1u << PB) | (1u << PL), false, s);
     if (rc) return rc;
     const recon_pipe_tile &t = r.tiles[sl.tile];
-    for (int y = 0; y < t.height; ++y) {
-        if (t.objects) std::memcpy(t.objects + (int64_t)y * t.pitch, sl.h[PA] + (int64_t)y * r.pitch, t.width);
-        if (t.markers) std::memcpy(t.markers + (int64_t)y * t.pitch, sl.h[PB] + (int64_t)y * r.pitch, t.width);
-        if (t.labels)
-            std::memcpy(t.labels + (int64_t)y * t.label_pitch, sl.h[PL] + (int64_t)y * r.lpitch * 4,
-                        (size_t)t.width * 4);
-    }
+    if (t.objects) copy_rows(t.objects, t.pitch, sl.h[PA], r.pitch, (size_t)t.width, t.height);
+    if (t.markers) copy_rows(t.markers, t.pitch, sl.h[PB], r.pitch, (size_t)t.width, t.height);
+    if (t.labels) copy_rows(t.labels, t.label_pitch * 4, sl.h[PL], r.lpitch * 4, (size_t)t.width * 4, t.height);
     if (t.count) *t.count = sl.h_count;
     {
         std::lock_guard<std::mutex> g(r.mu);
