@@ -854,7 +854,11 @@ def pipeline(recon, torch, n_tiles, size, window, cpu_workers, workers, windows=
                                                             prefetch=True, gpu_inflight=2, gpu_batch=8)),
                 ("pats_dl_guard_prefetch_inflight2_batch8", dict(policy="pats", cpu_workers=cpu_workers,
                                                                  data_locality=True, cpu_guard=True,
-                                                                 prefetch=True, gpu_inflight=2, gpu_batch=8))]
+                                                                 prefetch=True, gpu_inflight=2, gpu_batch=8)),
+                # the GPU alone needs no CPU workers: their cores copy tiles in and out instead
+                ("gpu_only_prefetch_inflight2_batch8_io8", dict(policy="pats", cpu_workers=0, data_locality=True,
+                                                                prefetch=True, gpu_inflight=2, gpu_batch=8,
+                                                                io_threads=2 * io_threads))]
         ref = None
         res["runs"] = {}
         for name, kw in runs:
@@ -867,7 +871,7 @@ def pipeline(recon, torch, n_tiles, size, window, cpu_workers, workers, windows=
                 kw = dict(policy="pats", cpu_workers=cpu_workers, data_locality=True, cpu_max_speedup=limit)
                 res["cutoff"] = {"cpu_max_speedup": limit, "cpu_ops": ok_ops}
             cfg = recon.pipe_config(window=window, speedup=speedup, transfer_impact=impact, gpu_ms=gpu_ms,
-                                    **base, **kw)
+                                    **dict(base, **kw))
             poison()
             outs, st = recon.recon_pipeline_run(ctx.ctx, tiles, cfg, outputs=bufs)
             r = {"makespan_ms": st["makespan_ms"], "tiles_s": n_tiles / (st["makespan_ms"] * 1e-3),
@@ -877,7 +881,8 @@ def pipeline(recon, torch, n_tiles, size, window, cpu_workers, workers, windows=
                  "transfer_GB": (st["upload_bytes"] + st["download_bytes"]) / 1e9,
                  "transfer_ms": st["transfer_ms"], "io_ms": st["io_ms"], "policy": kw["policy"],
                  "data_locality": kw["data_locality"], "prefetch": bool(kw.get("prefetch")),
-                 "gpu_inflight": max(1, kw.get("gpu_inflight", 1)), "gpu_batch": max(1, kw.get("gpu_batch", 1))}
+                 "gpu_inflight": max(1, kw.get("gpu_inflight", 1)), "gpu_batch": max(1, kw.get("gpu_batch", 1)),
+                 "io_threads": kw.get("io_threads", io_threads)}
             if ref is None:
                 ref = [{k: (v.copy() if hasattr(v, "copy") else v) for k, v in o.items()} for o in outs]
                 for i in (0, n_tiles - 1):
